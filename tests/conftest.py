@@ -1,0 +1,21 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: longer oracle computations")
+
+
+@pytest.fixture(scope="session")
+def lib():
+    """The HIP library binding; GPU tests only."""
+    import paper_1512_06126_amd as g
+    g.load()
+    return g

@@ -1,0 +1,169 @@
+"""Pins of the oracle's hot-path parts against what the paper and the
+mathematics fix: storage symmetry (Sect. 3.1), table size (8x claim), the
+relation between the scaled and the physical system (Sect. 2.2), the
+sigma_a = sigma_b special case, and the 1-D normal field."""
+import numpy as np
+import pytest
+
+import giem_synth as gs
+from oracle import dense, normal_field, packed
+
+
+def _small_model(seed=7, nx=5, ny=4, nz=3):
+    rng = np.random.default_rng(seed)
+    z = np.array([0.0, 100.0, 250.0, 300.0])[: nz + 1]
+    m = gs.make_model(nx, ny, nz, 50.0, 60.0, z, [0.0, 250.0, 2000.0],
+                      [0.0, 0.01, 0.1, 0.003], 1.0)
+    sa = m["sigma_a"] * 10 ** rng.uniform(0, 2, size=m["sigma_a"].shape)
+    m["sigma_a"] = sa
+    return m
+
+
+def test_pack_roundtrip_exact():
+    rng = np.random.default_rng(0)
+    t = gs.random_packed_table(rng, 4, 3, 5)
+    c = packed.split_classes(t, 5)
+    assert np.array_equal(packed.pack_classes(c, 5), t)
+    for k in ("xx", "xy", "yy", "zz"):
+        assert np.array_equal(c[k], np.swapaxes(c[k], -1, -2))
+
+
+def test_table_sizes_eight_fold():
+    # 2 Nx Ny Nz (2Nz+1) complex vs 36 Nx Ny Nz^2 (Sect. 3.1); ratio -> 9 for
+    # the 36-form and -> 8 for the 32-form as Nz grows.
+    nx, ny, nz = 128, 128, 32
+    assert gs.packed_len(nz) * nx * ny * 16 == packed.packed_table_bytes(nx, ny, nz)
+    assert packed.packed_table_bytes(nx, ny, nz) == 2 * 128 * 128 * 32 * 65 * 16
+    r32 = 32 * nx * ny * nz * nz * 16 / packed.packed_table_bytes(nx, ny, nz)
+    assert abs(r32 - 8 * 2 * nz / (2 * nz + 1)) < 1e-12 and 7.8 < r32 < 8.0
+
+
+def test_unpacked_tensor_satisfies_lemmas():
+    rng = np.random.default_rng(1)
+    nx, ny, nz = 4, 3, 3
+    t = gs.random_packed_table(rng, nx, ny, nz)
+    qf = packed.full_tensor_signed(t, nz)
+    c = lambda i, j: qf[i + ny - 1, j + nx - 1]
+    for i in range(-ny + 1, ny):
+        for j in range(-nx + 1, nx):
+            q = c(i, j)
+            # Lemma 1 / block relations
+            assert np.array_equal(q[2, 0], -q[0, 2].T)
+            assert np.array_equal(q[2, 1], -q[1, 2].T)
+            assert np.array_equal(q[1, 0], q[0, 1])
+            for a in range(3):
+                assert np.array_equal(q[a, a], q[a, a].T)
+            # Lemma 2 parities
+            qx, qy = c(i, -j), c(-i, j)
+            assert np.array_equal(qx[0, 0], q[0, 0]) and np.array_equal(qy[2, 2], q[2, 2])
+            assert np.array_equal(qx[0, 1], -q[0, 1]) and np.array_equal(qy[0, 1], -q[0, 1])
+            assert np.array_equal(qx[2, 0], -q[2, 0]) and np.array_equal(qy[2, 0], q[2, 0])
+            assert np.array_equal(qx[2, 1], q[2, 1]) and np.array_equal(qy[2, 1], -q[2, 1])
+
+
+def test_dense_B_symmetric_and_toeplitz():
+    rng = np.random.default_rng(2)
+    nx, ny, nz = 4, 3, 2
+    t = gs.random_packed_table(rng, nx, ny, nz)
+    B = packed.dense_B(t, nx, ny, nz)
+    # reciprocity: B = B^T (not B^H)
+    assert np.array_equal(B, B.T)
+    # block-Toeplitz: entry depends on the lateral offset only
+    Bv = B.reshape(3, nz, ny, nx, 3, nz, ny, nx)
+    assert np.array_equal(Bv[:, :, 1, 2, :, :, 0, 1], Bv[:, :, 2, 3, :, :, 1, 2])
+
+
+def test_scaled_system_equals_physical_system():
+    """With U = a E the scaled system of Sect. 2.2 is the cell average of the
+    integral equation: A u = s <E^N> and P E = <E^N> give the same E."""
+    m = _small_model()
+    rng = np.random.default_rng(3)
+    t = gs.random_packed_table(rng, m["nx"], m["ny"], m["nz"], scale=1e3)
+    B = dense.dense_from_packed(t, m)
+    d = dense.cie_diagonals(m)
+    A = dense.system_matrix(B, d)
+    assert np.allclose(A, dense.system_matrix_from_K(B, d), rtol=0, atol=1e-12 * np.abs(A).max())
+    en = normal_field.normal_field_cells(m)
+    b = normal_field.plane_wave_rhs(m)
+    u = dense.solve_lu(A, b)
+    E1 = u / np.tile(d["a"].reshape(-1), 3).reshape(1, 3, *d["a"].shape)
+    P = dense.physical_matrix(B, m)
+    E2 = dense.solve_lu(P, en)
+    assert np.linalg.norm(E1 - E2) <= 1e-11 * np.linalg.norm(E2)
+
+
+def test_no_anomaly_gives_normal_field():
+    m = _small_model()
+    m["sigma_a"] = np.broadcast_to(dense.cell_layer_sigma(m)[:, None, None],
+                                   m["sigma_a"].shape).copy()
+    rng = np.random.default_rng(4)
+    t = gs.random_packed_table(rng, m["nx"], m["ny"], m["nz"], scale=1e3)
+    B = dense.dense_from_packed(t, m)
+    d = dense.cie_diagonals(m)
+    assert np.all(d["gamma"] == 0)
+    A = dense.system_matrix(B, d)
+    assert np.array_equal(A, np.eye(A.shape[0]))
+
+
+def test_transpose_mode_is_bilinear_adjoint():
+    m = _small_model()
+    rng = np.random.default_rng(5)
+    t = gs.random_packed_table(rng, m["nx"], m["ny"], m["nz"])
+    B = dense.dense_from_packed(t, m)
+    d = dense.cie_diagonals(m)
+    x = gs.random_vector(rng, 1, m["nz"], m["ny"], m["nx"])
+    y = gs.random_vector(rng, 1, m["nz"], m["ny"], m["nx"])
+    Ax = dense.apply_direct(B, d, x, "A")
+    ATy = dense.apply_direct(B, d, y, "AT")
+    lhs, rhs = np.sum(Ax * y), np.sum(x * ATy)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+# ---------------------------------------------------------------- normal field
+
+def test_half_space_impedance_closed_form():
+    for sig, f in ((0.01, 1.0), (1.0, 1e-3), (1e-4, 10.0)):
+        pw = normal_field.LayeredPlaneWave([0.0], [0.0, sig], f)
+        w = 2 * np.pi * f
+        k = np.sqrt(1j * w * normal_field.MU0 * sig)
+        assert abs(pw.Zs - w * normal_field.MU0 / k) <= 1e-14 * abs(pw.Zs)
+        rho = abs(pw.Zs) ** 2 / (w * normal_field.MU0)
+        assert abs(rho * sig - 1) < 1e-12
+        # e^{-i w t}: the impedance phase is -45 degrees
+        assert abs(np.degrees(np.angle(pw.Zs)) + 45.0) < 1e-10
+        assert abs(pw.H_surface() - 1.0 / pw.Zs) <= 1e-13 * abs(pw.H_surface())
+
+
+def test_layered_field_recursion_vs_transfer_matrix():
+    d = [0.0, 1000.0, 10000.0]
+    s = [0.0, 0.01, 0.001, 0.1]
+    pw = normal_field.LayeredPlaneWave(d, s, 0.1)
+    for z in (-50.0, 0.0, 10.0, 999.0, 1001.0, 5000.0, 10500.0, 20000.0):
+        a, b = pw.E(z), normal_field.transfer_matrix_field(d, s, 0.1, z)
+        assert abs(a - b) <= 1e-12 * max(abs(a), 1e-3)
+
+
+def test_layered_field_satisfies_interface_conditions():
+    d = [0.0, 300.0, 1200.0, 4000.0]
+    s = [0.0, 0.05, 0.002, 1.0, 0.01]
+    pw = normal_field.LayeredPlaneWave(d, s, 3.0)
+    eps = 1e-7
+    for di in d[1:]:
+        assert abs(pw.E(di - eps) - pw.E(di + eps)) < 1e-8
+        assert abs(pw.dE(di - eps) - pw.dE(di + eps)) < 1e-8 * abs(pw.dE(di))
+    # ODE E'' + k^2 E = 0 inside a layer, by central differences
+    z, h = 700.0, 0.5
+    k2 = 1j * 2 * np.pi * 3.0 * normal_field.MU0 * s[2]
+    e2 = (pw.E(z + h) - 2 * pw.E(z) + pw.E(z - h)) / h ** 2
+    assert abs(e2 + k2 * pw.E(z)) < 1e-6 * abs(k2 * pw.E(z))
+
+
+def test_cell_average_vs_quadrature():
+    d = [0.0, 1000.0, 10000.0]
+    s = [0.0, 0.01, 0.001, 0.1]
+    pw = normal_field.LayeredPlaneWave(d, s, 0.1)
+    x, w = np.polynomial.legendre.leggauss(20)
+    for z1, z2 in ((0.0, 250.0), (750.0, 1000.0), (1000.0, 1100.0), (10000.0, 10100.0)):
+        zz = 0.5 * (z2 - z1) * x + 0.5 * (z1 + z2)
+        q = 0.5 * np.sum(w * np.array([pw.E(v) for v in zz]))
+        assert abs(pw.cell_average(z1, z2) - q) < 1e-13
