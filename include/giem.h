@@ -1,0 +1,214 @@
+/*
+ * giem.h -- C-ABI of the MI355X (gfx950) Galerkin integral-equation solver.
+ *
+ * The library solves the discrete contracting integral equation (CIE) of
+ * Kruglyakov & Bloshanskaya, "High-performance parallel solver for integral
+ * equations of electromagnetics based on Galerkin method" (arXiv:1512.06126):
+ *
+ *   Problem (Sect. 2.1): Maxwell's equations with time factor exp(-i w t),
+ *   layered background conductivity sigma_b(z), anomalous conductivity
+ *   sigma_a in a rectangular domain split into Nx x Ny x Nz cells of uniform
+ *   lateral size hx x hy (Sect. 3.1), magnetotelluric plane-wave source.
+ *
+ *   System (Sect. 2.2, linear system for U_n): A U = U^0 with
+ *     A = S + R1 B R2   (Sect. 3.1, factorised form),
+ *     S = 1 - gamma, R1 = -2 sqrt(Re sb) / V, R2 = sqrt(Re sb) gamma,
+ *     gamma = (sa - sb) / (sa + conj sb), U^0 = sqrt(Re sb) <E^N>,
+ *   B the block-Toeplitz matrix of Galerkin coefficients B_n^m (double
+ *   volume integrals of the electric Green's tensor), E = U / a with
+ *   a = (sa + conj sb) / (2 sqrt(Re sb)).
+ *
+ *   Operator apply (Sect. 3.3, three-step algorithm): forward 2-D FFT of the
+ *   3 Nz zero-padded planes, Nz-order block products with the stored
+ *   spectra of the packed table, inverse FFT.  Solver: GMRES with restarts
+ *   (Sect. 3.3 names flexible GMRES; with no preconditioner it is GMRES).
+ *
+ * Conventions
+ *   complex numbers are interleaved (re, im) doubles ("c128") unless stated;
+ *   "device" pointers are HIP device memory (e.g. torch tensors' data_ptr),
+ *   "host" pointers are ordinary host memory;
+ *   every call is ordered on the caller's hipStream_t passed as `stream`
+ *   (NULL = the default stream);
+ *   cell vectors use the layout [nrhs][3][Nz][Ny][Nx] (component x, y, z;
+ *   x index fastest); per-cell scalars use [Nz][Ny][Nx];
+ *   SI units, mu0 = 4 pi 1e-7, omega = 2 pi f.
+ *
+ * Ownership: the caller owns every array it passes.  The library owns only
+ * the giem_handle with its device tables and workspace, released by
+ * giem_free.  No pointer is retained after a call returns.
+ *
+ * Errors: 0 = success; negative = error (outputs untouched unless stated),
+ * with a message from giem_last_error() (thread-local); GIEM_ENOCONV is a
+ * warning: the output holds the last iterate and the statistics are valid.
+ * One handle must not be used by two threads at once.
+ */
+#ifndef GIEM_H
+#define GIEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GIEM_OK 0
+#define GIEM_EINVAL (-1)  /* bad argument, shape or pointer                   */
+#define GIEM_EDOMAIN (-2) /* physics outside the method's domain (see calls)  */
+#define GIEM_ENOMEM (-3)  /* device or host allocation failed                 */
+#define GIEM_EHIP (-4)    /* a HIP runtime call failed                        */
+#define GIEM_ENOCONV 1    /* iteration limit reached before the tolerance     */
+
+/* operator modes for giem_apply */
+#define GIEM_MODE_A 0u  /* y = A x   = S x + R1 B R2 x                            */
+#define GIEM_MODE_AT 1u /* y = A^T x = S x + R2 B R1 x (B = B^T by reciprocity)  */
+#define GIEM_MODE_B 2u  /* y = B x   (the raw convolution with the coefficients) */
+
+/* arithmetic of the FFT convolution */
+#define GIEM_FP64 0u /* complex128 FFTs, FP64 block products                     */
+#define GIEM_FP32 1u /* complex64 FFTs and tables, FP32-accumulated products      */
+
+/* giem_tables flags */
+#define GIEM_TABLES_C64 1u /* also keep complex64 spectra for GIEM_FP32 applies */
+
+/* Model of the medium (Sect. 2.1 and Appendix B).  All pointers are host. */
+typedef struct {
+  int32_t nlay;           /* number of interfaces d_1 < ... < d_nlay            */
+  const double *d;        /* [nlay] interface depths, d_1 = 0 (surface), m, z down */
+  const double *sigma_b;  /* c128 [nlay+1]: [0] air (0 allowed), [k] the layer
+                             below d_k, [nlay] the lower half-space; Re >= 0     */
+  int32_t nx, ny, nz;     /* anomaly grid (Sect. 3.1)                           */
+  double hx, hy;          /* lateral cell size, m                               */
+  double x0, y0;          /* position of the grid corner, m                     */
+  const double *z_edges;  /* [nz+1] increasing depths of the cell faces, m; no
+                             cell may straddle an interface (Appendix A)        */
+} giem_model;
+
+typedef struct giem_handle giem_handle; /* opaque: tables, workspace */
+
+/* GMRES options.  precision: GIEM_FP64, or GIEM_FP32 = complex64 convolution
+   inside an inner GMRES, corrected by FP64 residual refinement (outer loop). */
+typedef struct {
+  double tol;          /* stop when ||b - A x|| <= tol ||b|| (weighted norm)   */
+  int32_t restart;     /* Krylov dimension m of GMRES(m), 1..64               */
+  int32_t max_iter;    /* limit on operator applies of the (inner) GMRES      */
+  int32_t precision;   /* GIEM_FP64 or GIEM_FP32                              */
+  double inner_tol;    /* GIEM_FP32: relative tolerance of each inner solve    */
+  int32_t max_outer;   /* GIEM_FP32: limit on refinement steps                */
+  int32_t weighted_ip; /* nonzero: volume-weighted L2 inner product (Sect. 2.1) */
+  int32_t warm_start;  /* nonzero: E_cells holds the initial guess on entry    */
+} giem_solve_opts;
+
+typedef struct {
+  int32_t iters;       /* operator applies in GMRES (all RHS, max over RHS)    */
+  int32_t outer_iters; /* refinement steps (GIEM_FP32), else restarts          */
+  int32_t converged;   /* 1 if every RHS met tol                              */
+  double rel_residual; /* max over RHS of the final true ||b - A x|| / ||b||   */
+  double ms;           /* wall time of the call, ms                           */
+} giem_solve_stats;
+
+/*
+ * giem_tables -- compute the Galerkin coefficient tables B_n^m (Sect. 3.2,
+ * Appendices A-C) for nfreq frequencies on the host in FP64 and upload their
+ * packed spectra (Sect. 3.3) to the device.
+ *   freq_hz: host [nfreq], > 0.  flags: GIEM_TABLES_C64 or 0.
+ *   *out receives a new handle.
+ * Errors: EINVAL (shapes), EDOMAIN (a cell straddles an interface,
+ * Re sigma_b <= 0 in a layer holding cells), ENOMEM, EHIP.
+ */
+int giem_tables(const giem_model *model, int32_t nfreq, const double *freq_hz,
+                uint32_t flags, void *stream, giem_handle **out);
+
+/*
+ * giem_tables_import -- build a handle from caller-supplied packed spatial
+ * tables (Sect. 3.1, storage after Lemmas 1-2) instead of computing them.
+ *   host_packed_spatial: host c128 [nfreq][Ny][Nx][E], E = 2 Nz (2 Nz + 1);
+ *   block (i, j) holds Q(i, j) for y-offset i, x-offset j (observation minus
+ *   source cell), classes in the order
+ *     [xx upper][xy upper][yy upper][zz upper][xz full][yz full]
+ *   (upper triangles row-major over iz <= jz, full blocks row-major [iz][jz];
+ *   iz = depth index of the observation cell).  Entries of classes odd in x
+ *   (xy, xz) at j = 0 and odd in y (xy, yz) at i = 0 are taken as zero.
+ *   The spectra are computed on the device (packed even/odd 2-D transforms).
+ */
+int giem_tables_import(const giem_model *model, int32_t nfreq, const double *freq_hz,
+                       const void *host_packed_spatial, uint32_t flags, void *stream,
+                       giem_handle **out);
+
+/* giem_tables_export -- copy the packed spatial table of frequency ifreq
+   (layout as in giem_tables_import) to host memory [Ny][Nx][E] c128. */
+int giem_tables_export(const giem_handle *t, int32_t ifreq, void *host_packed_spatial);
+
+/* giem_tables_bytes -- device bytes held by the packed spectral tables of one
+   frequency: (Nx+1)(Ny+1) 2 Nz (2 Nz + 1) complex (c128 and, if kept, c64). */
+int giem_tables_bytes(const giem_handle *t, int64_t *bytes_c128, int64_t *bytes_c64);
+
+/*
+ * giem_apply -- one application of the operator (Sect. 3.3, three steps).
+ *   sigma_a: device c128 [Nz][Ny][Nx] (ignored for GIEM_MODE_B);
+ *   x, y:    device c128 [nrhs][3][Nz][Ny][Nx], 1 <= nrhs <= 8; x and y must
+ *            not overlap;
+ *   mode:    GIEM_MODE_A, GIEM_MODE_AT or GIEM_MODE_B; prec: GIEM_FP64 or
+ *            GIEM_FP32 (needs GIEM_TABLES_C64).
+ * Never synchronises the stream.  Errors: EINVAL, EDOMAIN (Re sigma_b <= 0),
+ * EHIP.
+ */
+int giem_apply(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
+               const void *x, void *y, uint32_t mode, uint32_t prec, void *stream);
+
+/* giem_apply_timed -- giem_apply with HIP events around each of the five
+   kernels (x-FFT, y-FFT, block product, inverse y-FFT, inverse x-FFT); waits
+   for the stream and writes their durations in ms to stage_ms[5]. */
+int giem_apply_timed(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
+                     const void *x, void *y, uint32_t mode, uint32_t prec, void *stream,
+                     double *stage_ms);
+
+/*
+ * giem_solve -- solve A U = U^0 by GMRES(m) (Sect. 2.2 system, Sect. 3.3
+ * solver) and return the cell-averaged field E = U / a.
+ *   sigma_a: device c128 [Nz][Ny][Nx] with Re >= 0 and no NaN;
+ *   rhs:     device c128 [nrhs][3][Nz][Ny][Nx] holding U^0, or NULL for the
+ *            plane-wave source: RHS 0 = x polarisation, RHS 1 = y
+ *            polarisation (E^N horizontal, 1 V/m at z = 0);
+ *   E_cells: device c128 [nrhs][3][Nz][Ny][Nx] output (input if warm_start);
+ *   opts, stats: host; stats may be NULL.
+ * Synchronises once per Arnoldi step.  Returns GIEM_ENOCONV if the
+ * iteration limit is reached.
+ */
+int giem_solve(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
+               const void *rhs, void *E_cells, const giem_solve_opts *opts,
+               giem_solve_stats *stats, void *stream);
+
+/*
+ * giem_adjoint -- gradient of J = sum_r Re( sum_n g_r[n] . E_r[n] ) with
+ * respect to log sigma_a of every cell for real conductivities (the
+ * sensitivity is obtained from one solve with A^T; B = B^T by reciprocity).
+ *   adj_src: device c128 [nrhs][3][Nz][Ny][Nx], g above;
+ *   E_fwd:   device c128 [nrhs][3][Nz][Ny][Nx], the forward solution E;
+ *   grad_log_sigma: device double [Nz][Ny][Nx], accumulated (+=).
+ */
+int giem_adjoint(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
+                 const void *adj_src, const void *E_fwd, void *grad_log_sigma,
+                 const giem_solve_opts *opts, giem_solve_stats *stats, void *stream);
+
+/*
+ * giem_fields -- electric and magnetic fields at receivers on the surface
+ * (z = 0, the horizontal components are continuous there) from the cell
+ * field (Sect. 2.2, field recovery):
+ *   e(r) = E^N(r) + sum_n (sa_n - sb_n) [int_{cell n} G^E(r, M0) dM0] E_n,
+ *   h(r) = H^N(r) + sum_n (sa_n - sb_n) [int_{cell n} G^H(r, M0) dM0] E_n.
+ *   rec_xy: host [nrec][2] receiver positions (x, y) in m;
+ *   E_cells: device c128 [nrhs][3][Nz][Ny][Nx];
+ *   E_rec, H_rec: device c128 [nrhs][nrec][3].
+ *   E^N, H^N are the plane-wave fields of RHS 0 (x pol.) and 1 (y pol.).
+ */
+int giem_fields(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
+                const void *E_cells, int32_t nrec, const double *rec_xy, void *E_rec,
+                void *H_rec, void *stream);
+
+void giem_free(giem_handle *t);
+const char *giem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GIEM_H */

@@ -101,3 +101,33 @@ def solve_lu(A, rhs):
 
 def dense_from_packed(packed, model):
     return _packed.dense_B(packed, model["nx"], model["ny"], model["nz"])
+
+
+def gradient_log_sigma(B, model, g, en_cells, sigma_a=None):
+    """d/d(log sigma_a) of J = Re sum_r g_r . E_r for real conductivities.
+
+    Uses the physical form P(sigma) E = <E^N>, P = I - V^{-1} B Dsigma
+    (Sect. 2.1 integral equation averaged over cells):
+      dE = P^{-1} V^{-1} B dDsigma E,  mu = P^{-T} g,
+      dJ/dsigma_k = sum_alpha (mu^T V^{-1} B)_(alpha,k) E_(alpha,k),
+      grad_k = Re(sigma_k dJ/dsigma_k)."""
+    if sigma_a is None:
+        sigma_a = model["sigma_a"]
+    P = physical_matrix(B, model, sigma_a)
+    d = cie_diagonals(model, sigma_a)
+    vol = _rep3(d["vol"])
+    E = solve_lu(P, en_cells)
+    nr = g.shape[0]
+    grad = np.zeros(sigma_a.size, dtype=np.complex128)
+    for r in range(nr):
+        mu = np.linalg.solve(P.T, g[r].reshape(-1))
+        row = (mu / vol) @ B
+        grad += (row * E[r].reshape(-1)).reshape(3, -1).sum(axis=0)
+    return np.real(sigma_a.reshape(-1) * grad).reshape(sigma_a.shape)
+
+
+def objective(B, model, g, en_cells, sigma_a):
+    """J = Re sum_r g_r . E_r with E from the physical form (for finite differences)."""
+    P = physical_matrix(B, model, sigma_a)
+    E = solve_lu(P, en_cells)
+    return float(np.real(np.sum(g * E)))

@@ -1,0 +1,231 @@
+"""Python binding of libgiem (include/giem.h): argument marshalling only.
+
+Every step of the solver runs in the HIP library; this module converts model
+descriptions to the C structs, passes torch tensors' device pointers and the
+current HIP stream, and turns error codes into exceptions.  It never computes
+anything itself and it fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "lib", "libgiem.so")
+
+GIEM_OK, GIEM_EINVAL, GIEM_EDOMAIN, GIEM_ENOMEM, GIEM_EHIP, GIEM_ENOCONV = 0, -1, -2, -3, -4, 1
+MODE_A, MODE_AT, MODE_B = 0, 1, 2
+FP64, FP32 = 0, 1
+TABLES_C64 = 1
+
+_lib = None
+
+
+class GiemError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"giem error {code}: {msg}")
+        self.code = code
+
+
+class NotConverged(RuntimeWarning):
+    pass
+
+
+class _Model(ctypes.Structure):
+    _fields_ = [("nlay", ctypes.c_int32), ("d", ctypes.c_void_p), ("sigma_b", ctypes.c_void_p),
+                ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("hx", ctypes.c_double), ("hy", ctypes.c_double), ("x0", ctypes.c_double),
+                ("y0", ctypes.c_double), ("z_edges", ctypes.c_void_p)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int32),
+                ("weighted_ip", ctypes.c_int32), ("warm_start", ctypes.c_int32)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("outer_iters", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("rel_residual", ctypes.c_double),
+                ("ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def load():
+    """Load libgiem.so (built by __graft_entry__.build()); raise if missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBPATH):
+        raise ImportError(f"HIP library not built: {LIBPATH} is missing "
+                          "(run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIBPATH)
+    P, I32, U32, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_double
+    sig = {
+        "giem_tables": [P, I32, P, U32, P, P],
+        "giem_tables_import": [P, I32, P, P, U32, P, P],
+        "giem_tables_export": [P, I32, P],
+        "giem_tables_bytes": [P, P, P],
+        "giem_apply": [P, I32, P, I32, P, P, U32, U32, P],
+        "giem_apply_timed": [P, I32, P, I32, P, P, U32, U32, P, P],
+        "giem_solve": [P, I32, P, I32, P, P, P, P, P],
+        "giem_adjoint": [P, I32, P, I32, P, P, P, P, P, P],
+        "giem_fields": [P, I32, P, I32, P, I32, P, P, P, P],
+        "giem_free": [P],
+        "giem_last_error": [],
+    }
+    for name, argt in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = argt
+        f.restype = ctypes.c_int
+    lib.giem_free.restype = None
+    lib.giem_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return ["giem_tables", "giem_tables_import", "giem_tables_export", "giem_tables_bytes",
+            "giem_apply", "giem_apply_timed", "giem_solve", "giem_adjoint", "giem_fields",
+            "giem_free", "giem_last_error"]
+
+
+def _check(rc, allow_noconv=False):
+    if rc == GIEM_OK:
+        return rc
+    msg = _lib.giem_last_error().decode()
+    if rc == GIEM_ENOCONV and allow_noconv:
+        return rc
+    raise GiemError(rc, msg)
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(stream)
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _model_struct(m):
+    keep = {
+        "d": np.ascontiguousarray(m["d"], dtype=np.float64),
+        "sigma": np.ascontiguousarray(m["sigma"], dtype=np.complex128),
+        "z": np.ascontiguousarray(m["z_edges"], dtype=np.float64),
+    }
+    s = _Model(nlay=keep["d"].size, d=keep["d"].ctypes.data, sigma_b=keep["sigma"].ctypes.data,
+               nx=m["nx"], ny=m["ny"], nz=m["nz"], hx=m["hx"], hy=m["hy"],
+               x0=m.get("x0", 0.0), y0=m.get("y0", 0.0), z_edges=keep["z"].ctypes.data)
+    return s, keep
+
+
+class Handle:
+    """Owns a giem_handle (device tables + workspace)."""
+
+    def __init__(self, ptr, model, freqs):
+        self._p = ctypes.c_void_p(ptr)
+        self.model = model
+        self.freqs = np.asarray(freqs, dtype=np.float64)
+
+    def close(self):
+        if self._p and self._p.value:
+            _lib.giem_free(self._p)
+            self._p = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def export(self, ifreq=0):
+        nz = self.model["nz"]
+        e = 2 * nz * (2 * nz + 1)
+        out = np.empty((self.model["ny"], self.model["nx"], e), dtype=np.complex128)
+        _check(_lib.giem_tables_export(self._p, ifreq, out.ctypes.data))
+        return out
+
+    def table_bytes(self):
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(_lib.giem_tables_bytes(self._p, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def apply(self, x, y, sigma_a=None, mode=MODE_A, prec=FP64, ifreq=0, stream=None):
+        nrhs = x.shape[0]
+        sa = _ptr(sigma_a) if sigma_a is not None else ctypes.c_void_p(0)
+        _check(_lib.giem_apply(self._p, ifreq, sa, nrhs, _ptr(x), _ptr(y), mode, prec,
+                               _stream(stream)))
+        return y
+
+    def apply_timed(self, x, y, sigma_a=None, mode=MODE_A, prec=FP64, ifreq=0, stream=None):
+        nrhs = x.shape[0]
+        sa = _ptr(sigma_a) if sigma_a is not None else ctypes.c_void_p(0)
+        ms = (ctypes.c_double * 5)()
+        _check(_lib.giem_apply_timed(self._p, ifreq, sa, nrhs, _ptr(x), _ptr(y), mode, prec,
+                                     _stream(stream), ms))
+        return list(ms)
+
+    def solve(self, sigma_a, E_out, rhs=None, tol=1e-6, restart=30, max_iter=2000,
+              precision=FP64, inner_tol=1e-3, max_outer=20, weighted_ip=0, warm_start=0,
+              ifreq=0, stream=None):
+        o = SolveOpts(tol=tol, restart=restart, max_iter=max_iter, precision=precision,
+                      inner_tol=inner_tol, max_outer=max_outer, weighted_ip=weighted_ip,
+                      warm_start=warm_start)
+        st = SolveStats()
+        nrhs = E_out.shape[0]
+        rp = _ptr(rhs) if rhs is not None else ctypes.c_void_p(0)
+        rc = _lib.giem_solve(self._p, ifreq, _ptr(sigma_a), nrhs, rp, _ptr(E_out),
+                             ctypes.byref(o), ctypes.byref(st), _stream(stream))
+        _check(rc, allow_noconv=True)
+        d = st.as_dict()
+        d["rc"] = rc
+        return d
+
+    def adjoint(self, sigma_a, adj_src, E_fwd, grad, tol=1e-10, restart=30, max_iter=4000,
+                weighted_ip=0, ifreq=0, stream=None):
+        o = SolveOpts(tol=tol, restart=restart, max_iter=max_iter, precision=FP64,
+                      inner_tol=0.0, max_outer=0, weighted_ip=weighted_ip, warm_start=0)
+        st = SolveStats()
+        rc = _lib.giem_adjoint(self._p, ifreq, _ptr(sigma_a), adj_src.shape[0], _ptr(adj_src),
+                               _ptr(E_fwd), _ptr(grad), ctypes.byref(o), ctypes.byref(st),
+                               _stream(stream))
+        _check(rc, allow_noconv=True)
+        d = st.as_dict()
+        d["rc"] = rc
+        return d
+
+    def fields(self, sigma_a, E_cells, rec_xy, E_rec, H_rec, ifreq=0, stream=None):
+        rec = np.ascontiguousarray(rec_xy, dtype=np.float64)
+        _check(_lib.giem_fields(self._p, ifreq, _ptr(sigma_a), E_cells.shape[0], _ptr(E_cells),
+                                rec.shape[0], rec.ctypes.data, _ptr(E_rec), _ptr(H_rec),
+                                _stream(stream)))
+        return E_rec, H_rec
+
+
+def tables(model, freqs, flags=0, stream=None):
+    load()
+    s, keep = _model_struct(model)
+    f = np.ascontiguousarray(np.atleast_1d(freqs), dtype=np.float64)
+    out = ctypes.c_void_p()
+    _check(_lib.giem_tables(ctypes.byref(s), f.size, f.ctypes.data, flags, _stream(stream),
+                            ctypes.byref(out)))
+    return Handle(out.value, model, f)
+
+
+def tables_import(model, freqs, packed, flags=0, stream=None):
+    load()
+    s, keep = _model_struct(model)
+    f = np.ascontiguousarray(np.atleast_1d(freqs), dtype=np.float64)
+    pk = np.ascontiguousarray(packed, dtype=np.complex128)
+    out = ctypes.c_void_p()
+    _check(_lib.giem_tables_import(ctypes.byref(s), f.size, f.ctypes.data, pk.ctypes.data, flags,
+                                   _stream(stream), ctypes.byref(out)))
+    return Handle(out.value, model, f)

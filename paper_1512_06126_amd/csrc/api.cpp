@@ -1,0 +1,441 @@
+// C-ABI entry points: handle construction, table upload and spectra, the
+// operator apply, error reporting.  The GMRES driver is in solve.cpp.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <algorithm>
+
+#include "handle.h"
+
+namespace giem {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string &msg) { g_last_error = msg; }
+const std::string &get_error() { return g_last_error; }
+
+int check_hip(hipError_t e, const char *what) {
+  if (e == hipSuccess) return GIEM_OK;
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? GIEM_ENOMEM : GIEM_EHIP;
+}
+
+#define GIEM_TRY(expr)          \
+  do {                          \
+    int rc__ = (expr);          \
+    if (rc__ < 0) return rc__;  \
+  } while (0)
+#define GIEM_HIP(expr, what) GIEM_TRY(check_hip((expr), (what)))
+
+static bool factor_ok(int L, FftDesc &d) {
+  d.L = L;
+  d.nf = 0;
+  int m = L;
+  const int radices[] = {4, 2, 3, 5, 7};
+  for (int r : radices) {
+    while (m % r == 0) {
+      if (d.nf >= kMaxFactors) return false;
+      d.fac[d.nf++] = r;
+      m /= r;
+    }
+  }
+  return m == 1;
+}
+
+static int make_plan(int L, FftPlan &p) {
+  if (!factor_ok(L, p.d)) {
+    set_error("transform length " + std::to_string(L) +
+              " must factor into 2, 3, 5 and 7 (Nx and Ny must be 7-smooth)");
+    return GIEM_EINVAL;
+  }
+  std::vector<c128> t64(L);
+  std::vector<c64> t32(L);
+  for (int k = 0; k < L; ++k) {
+    long double a = -2.0L * 3.141592653589793238462643383279503L * (long double)k / (long double)L;
+    t64[k] = mk<double>((double)cosl(a), (double)sinl(a));
+    t32[k] = mk<float>((float)cosl(a), (float)sinl(a));
+  }
+  GIEM_HIP(hipMalloc(&p.tw64, L * sizeof(c128)), "hipMalloc twiddles");
+  GIEM_HIP(hipMalloc(&p.tw32, L * sizeof(c64)), "hipMalloc twiddles");
+  GIEM_HIP(hipMemcpy(p.tw64, t64.data(), L * sizeof(c128), hipMemcpyHostToDevice), "copy twiddles");
+  GIEM_HIP(hipMemcpy(p.tw32, t32.data(), L * sizeof(c64), hipMemcpyHostToDevice), "copy twiddles");
+  return GIEM_OK;
+}
+
+static int make_cs(int n, void **out) {
+  std::vector<c128> cs(2 * n);
+  for (int a = 0; a < 2 * n; ++a) {
+    long double th = 3.141592653589793238462643383279503L * (long double)a / (long double)n;
+    cs[a] = mk<double>((double)cosl(th), (double)sinl(th));
+  }
+  GIEM_HIP(hipMalloc(out, cs.size() * sizeof(c128)), "hipMalloc cs");
+  GIEM_HIP(hipMemcpy(*out, cs.data(), cs.size() * sizeof(c128), hipMemcpyHostToDevice), "copy cs");
+  return GIEM_OK;
+}
+
+int ensure_spec_ws(giem_handle *t, int nrhs, int prec) {
+  (void)prec;
+  const size_t need = (size_t)4 * t->nx * t->ny * 3 * t->nz * nrhs * sizeof(c128);
+  if (t->spec_ws_bytes >= need) return GIEM_OK;
+  if (t->spec_ws) hipFree(t->spec_ws);
+  t->spec_ws = nullptr;
+  t->spec_ws_bytes = 0;
+  GIEM_HIP(hipMalloc(&t->spec_ws, need), "hipMalloc spectra workspace");
+  t->spec_ws_bytes = need;
+  return GIEM_OK;
+}
+
+int compute_diagonals(giem_handle *t, const c128 *sigma_a, hipStream_t s) {
+  c128 *dg = static_cast<c128 *>(t->diag);
+  const size_t n = t->ncell();
+  GIEM_HIP(launch_diagonals(sigma_a, static_cast<const c128 *>(t->sb_lev),
+                            static_cast<const double *>(t->vol_lev), t->nx, t->ny, t->nz, dg,
+                            dg + n, dg + 2 * n, dg + 3 * n, nullptr, s),
+           "diagonals kernel");
+  return GIEM_OK;
+}
+
+int apply_core(giem_handle *t, int ifreq, int nrhs, const VecPtrs &p, unsigned mode,
+               unsigned prec, hipStream_t s, double *stage_ms) {
+  const int nx = t->nx, ny = t->ny, nz = t->nz;
+  FreqTables &ft = t->f[ifreq];
+  const void *tab = prec == PREC_FP32 ? ft.spec32 : ft.spec64;
+  if (!tab) {
+    set_error("complex64 tables were not requested (GIEM_TABLES_C64)");
+    return GIEM_EINVAL;
+  }
+  GIEM_TRY(ensure_spec_ws(t, nrhs, prec));
+  const c128 *dg = static_cast<const c128 *>(t->diag);
+  const size_t n = t->ncell();
+  const c128 *S = dg, *R1 = dg + n, *R2 = dg + 2 * n;
+  const c128 *r2 = nullptr, *r1 = nullptr, *sd = nullptr;
+  if (mode == MODE_A) {
+    r2 = R2; r1 = R1; sd = S;
+  } else if (mode == MODE_AT) {
+    r2 = R1; r1 = R2; sd = S;
+  }
+  const int rp = nrhs * 3 * nz;
+  // planes per FFT workgroup: 128-byte runs, at most 32 elements per thread
+  int G = prec == PREC_FP32 ? 16 : 8;
+  const int Lmax = std::max(2 * nx, 2 * ny);
+  while (G > 1 && G * Lmax > 32 * 256) G /= 2;
+  if (block_threads(nz, nrhs) > 1024 || block_lds_bytes(nz, nrhs, prec) > 160 * 1024) {
+    set_error("block product: 3 Nz x nrhs too large for one workgroup");
+    return GIEM_EINVAL;
+  }
+  const void *twx = prec == PREC_FP32 ? t->px.tw32 : t->px.tw64;
+  const void *twy = prec == PREC_FP32 ? t->py.tw32 : t->py.tw64;
+  const double scale = 1.0 / (4.0 * nx * ny);
+  hipEvent_t ev[6];
+  if (stage_ms) {
+    for (int i = 0; i < 6; ++i) GIEM_HIP(hipEventCreate(&ev[i]), "hipEventCreate");
+    GIEM_HIP(hipEventRecord(ev[0], s), "hipEventRecord");
+  }
+  GIEM_HIP(launch_fft_x_fwd(prec, p, r2, t->spec_ws, nx, ny, nz, rp, G, t->px.d, twx, s), "x-FFT");
+  if (stage_ms) GIEM_HIP(hipEventRecord(ev[1], s), "hipEventRecord");
+  GIEM_HIP(launch_fft_y(prec, t->spec_ws, 2 * nx, ny, rp, G, t->py.d, twy, 0, s), "y-FFT");
+  if (stage_ms) GIEM_HIP(hipEventRecord(ev[2], s), "hipEventRecord");
+  GIEM_HIP(launch_block(prec, tab, t->spec_ws, nx, ny, nz, nrhs, s), "block product");
+  if (stage_ms) GIEM_HIP(hipEventRecord(ev[3], s), "hipEventRecord");
+  GIEM_HIP(launch_fft_y(prec, t->spec_ws, 2 * nx, ny, rp, G, t->py.d, twy, 1, s), "inverse y-FFT");
+  if (stage_ms) GIEM_HIP(hipEventRecord(ev[4], s), "hipEventRecord");
+  GIEM_HIP(launch_fft_x_inv(prec, p, sd, r1, t->spec_ws, nx, ny, nz, rp, G, t->px.d, twx, scale, s),
+           "inverse x-FFT");
+  if (stage_ms) {
+    GIEM_HIP(hipEventRecord(ev[5], s), "hipEventRecord");
+    GIEM_HIP(hipEventSynchronize(ev[5]), "hipEventSynchronize");
+    for (int i = 0; i < 5; ++i) {
+      float ms = 0.f;
+      GIEM_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]), "hipEventElapsedTime");
+      stage_ms[i] = ms;
+    }
+    for (int i = 0; i < 6; ++i) hipEventDestroy(ev[i]);
+  }
+  return GIEM_OK;
+}
+
+// Spatial packed tables (host) -> device -> packed spectra (+ c64 copy).
+int upload_spatial(giem_handle *t, hipStream_t s) {
+  const int nx = t->nx, ny = t->ny, nz = t->nz, E = t->E();
+  const size_t nsp = (size_t)nx * ny * E, nsc = (size_t)(nx + 1) * (ny + 1) * E;
+  void *dsp = nullptr, *tmp = nullptr;
+  int rc = GIEM_OK;
+  rc = check_hip(hipMalloc(&dsp, nsp * sizeof(c128)), "hipMalloc spatial");
+  if (rc == GIEM_OK) rc = check_hip(hipMalloc(&tmp, (size_t)ny * (nx + 1) * E * sizeof(c128)), "hipMalloc tmp");
+  for (size_t q = 0; rc == GIEM_OK && q < t->f.size(); ++q) {
+    FreqTables &ft = t->f[q];
+    rc = check_hip(hipMemcpyAsync(dsp, ft.spatial.data(), nsp * sizeof(c128), hipMemcpyHostToDevice, s),
+                   "copy spatial table");
+    if (rc == GIEM_OK) rc = check_hip(hipMalloc(&ft.spec64, nsc * sizeof(c128)), "hipMalloc spectra");
+    if (rc == GIEM_OK)
+      rc = check_hip(launch_spectral_x(static_cast<c128 *>(dsp), static_cast<c128 *>(tmp),
+                                       static_cast<c128 *>(t->cs_x), nx, ny, nz, s), "spectral x");
+    if (rc == GIEM_OK)
+      rc = check_hip(launch_spectral_y(static_cast<c128 *>(tmp), static_cast<c128 *>(ft.spec64),
+                                       static_cast<c128 *>(t->cs_y), nx, ny, nz, s), "spectral y");
+    if (rc == GIEM_OK && (t->flags & GIEM_TABLES_C64)) {
+      rc = check_hip(hipMalloc(&ft.spec32, nsc * sizeof(c64)), "hipMalloc c64 spectra");
+      if (rc == GIEM_OK)
+        rc = check_hip(launch_to_c64(static_cast<c128 *>(ft.spec64), static_cast<c64 *>(ft.spec32), nsc, s),
+                       "to c64");
+    }
+    if (rc == GIEM_OK) rc = check_hip(hipStreamSynchronize(s), "sync");
+  }
+  if (dsp) hipFree(dsp);
+  if (tmp) hipFree(tmp);
+  return rc;
+}
+
+static int validate_model(const giem_model *m) {
+  if (!m || m->nlay < 1 || !m->d || !m->sigma_b || !m->z_edges) {
+    set_error("model: null pointer or nlay < 1");
+    return GIEM_EINVAL;
+  }
+  if (m->nx < 1 || m->ny < 1 || m->nz < 1 || !(m->hx > 0) || !(m->hy > 0)) {
+    set_error("model: grid sizes must be positive");
+    return GIEM_EINVAL;
+  }
+  if (m->d[0] != 0.0) {
+    set_error("model: the first interface must be the surface d_1 = 0");
+    return GIEM_EINVAL;
+  }
+  for (int k = 1; k < m->nlay; ++k)
+    if (!(m->d[k] > m->d[k - 1])) {
+      set_error("model: interfaces must increase");
+      return GIEM_EINVAL;
+    }
+  for (int k = 0; k < m->nz; ++k)
+    if (!(m->z_edges[k + 1] > m->z_edges[k])) {
+      set_error("model: z_edges must increase");
+      return GIEM_EINVAL;
+    }
+  if (m->z_edges[0] < 0.0) {
+    set_error("model: cells must lie in the earth (z >= 0)");
+    return GIEM_EDOMAIN;
+  }
+  for (int k = 0; k <= m->nlay; ++k) {
+    const double re = m->sigma_b[2 * k], im = m->sigma_b[2 * k + 1];
+    if (!std::isfinite(re) || !std::isfinite(im) || re < 0.0) {
+      set_error("model: sigma_b must be finite with Re >= 0");
+      return GIEM_EDOMAIN;
+    }
+  }
+  return GIEM_OK;
+}
+
+static int create_handle(const giem_model *m, int nfreq, const double *freq, uint32_t flags,
+                         giem_handle **out) {
+  GIEM_TRY(validate_model(m));
+  if (nfreq < 1 || !freq || !out) {
+    set_error("nfreq must be >= 1 with frequencies and an output pointer");
+    return GIEM_EINVAL;
+  }
+  for (int q = 0; q < nfreq; ++q)
+    if (!(freq[q] > 0.0) || !std::isfinite(freq[q])) {
+      set_error("frequencies must be positive");
+      return GIEM_EINVAL;
+    }
+  if (3 * m->nz * ((4 * kMaxRhs + 3) / 4) > 1024 * 4) {
+    set_error("Nz too large");
+    return GIEM_EINVAL;
+  }
+  giem_handle *t = new giem_handle();
+  t->nx = m->nx; t->ny = m->ny; t->nz = m->nz; t->nlay = m->nlay;
+  t->hx = m->hx; t->hy = m->hy; t->x0 = m->x0; t->y0 = m->y0;
+  t->d.assign(m->d, m->d + m->nlay);
+  t->z_edges.assign(m->z_edges, m->z_edges + m->nz + 1);
+  for (int k = 0; k <= m->nlay; ++k) t->sigma.emplace_back(m->sigma_b[2 * k], m->sigma_b[2 * k + 1]);
+  t->flags = flags;
+  hipGetDevice(&t->device);
+  // layer of every cell; no cell may straddle an interface
+  for (int k = 0; k < t->nz; ++k) {
+    const double a = t->z_edges[k], b = t->z_edges[k + 1];
+    for (double di : t->d)
+      if (a < di && di < b) {
+        set_error("a cell straddles an interface (the vertical integrals need one layer per cell)");
+        delete t;
+        return GIEM_EDOMAIN;
+      }
+    const double mid = 0.5 * (a + b);
+    int lay = 0;
+    while (lay < t->nlay && t->d[lay] <= mid) ++lay;
+    t->layer_of_cell.push_back(lay);
+    if (!(t->sigma[lay].real() > 0.0)) {
+      set_error("Re sigma_b must be positive in every layer that holds cells");
+      delete t;
+      return GIEM_EDOMAIN;
+    }
+  }
+  t->f.resize(nfreq);
+  for (int q = 0; q < nfreq; ++q) t->f[q].freq = freq[q];
+  *out = t;
+  return GIEM_OK;
+}
+
+static int finish_handle(giem_handle *t, hipStream_t s) {
+  static bool lds_set = false;
+  if (!lds_set) {
+    GIEM_HIP(set_lds_limits(), "hipFuncSetAttribute");
+    lds_set = true;
+  }
+  const int nz = t->nz;
+  if (block_lds_bytes(nz, 2, PREC_FP64) > 160 * 1024) {
+    set_error("Nz too large for the LDS-resident block product");
+    return GIEM_EINVAL;
+  }
+  GIEM_TRY(make_plan(2 * t->nx, t->px));
+  GIEM_TRY(make_plan(2 * t->ny, t->py));
+  GIEM_TRY(make_cs(t->nx, &t->cs_x));
+  GIEM_TRY(make_cs(t->ny, &t->cs_y));
+  std::vector<c128> sb(nz);
+  std::vector<double> vol(nz), sr(nz);
+  for (int k = 0; k < nz; ++k) {
+    cd s0 = t->sigma[t->layer_of_cell[k]];
+    sb[k] = mk<double>(s0.real(), s0.imag());
+    vol[k] = t->hx * t->hy * (t->z_edges[k + 1] - t->z_edges[k]);
+    sr[k] = std::sqrt(s0.real());
+  }
+  GIEM_HIP(hipMalloc(&t->sb_lev, nz * sizeof(c128)), "hipMalloc");
+  GIEM_HIP(hipMalloc(&t->vol_lev, nz * sizeof(double)), "hipMalloc");
+  GIEM_HIP(hipMalloc(&t->sroot_lev, nz * sizeof(double)), "hipMalloc");
+  GIEM_HIP(hipMemcpy(t->sb_lev, sb.data(), nz * sizeof(c128), hipMemcpyHostToDevice), "copy");
+  GIEM_HIP(hipMemcpy(t->vol_lev, vol.data(), nz * sizeof(double), hipMemcpyHostToDevice), "copy");
+  GIEM_HIP(hipMemcpy(t->sroot_lev, sr.data(), nz * sizeof(double), hipMemcpyHostToDevice), "copy");
+  GIEM_HIP(hipMalloc(&t->diag, 4 * t->ncell() * sizeof(c128)), "hipMalloc diagonals");
+  const size_t nred = (size_t)kMaxRhs * 65 * dot_partials_per_rhs();
+  GIEM_HIP(hipMalloc(&t->red_part, nred * sizeof(c128)), "hipMalloc");
+  GIEM_HIP(hipMalloc(&t->red_out, kMaxRhs * 65 * sizeof(c128)), "hipMalloc");
+  GIEM_HIP(hipHostMalloc(&t->red_host, kMaxRhs * 65 * sizeof(c128), 0), "hipHostMalloc");
+  GIEM_HIP(hipMalloc(&t->coef_dev, kMaxRhs * 65 * sizeof(c128)), "hipMalloc");
+  GIEM_HIP(hipHostMalloc(&t->coef_host, kMaxRhs * 65 * sizeof(c128), 0), "hipHostMalloc");
+  GIEM_TRY(ensure_spec_ws(t, 2, PREC_FP64));
+  return upload_spatial(t, s);
+}
+
+}  // namespace giem
+
+using namespace giem;
+
+extern "C" {
+
+const char *giem_last_error(void) { return get_error().c_str(); }
+
+void giem_free(giem_handle *t) {
+  if (!t) return;
+  for (auto &ft : t->f) {
+    if (ft.spec64) hipFree(ft.spec64);
+    if (ft.spec32) hipFree(ft.spec32);
+  }
+  void *dev[] = {t->px.tw64, t->px.tw32, t->py.tw64, t->py.tw32, t->cs_x, t->cs_y,
+                 t->sb_lev, t->vol_lev, t->sroot_lev, t->diag, t->spec_ws, t->red_part,
+                 t->red_out, t->coef_dev, t->basis, t->vec_ws};
+  for (void *p : dev)
+    if (p) hipFree(p);
+  if (t->red_host) hipHostFree(t->red_host);
+  if (t->coef_host) hipHostFree(t->coef_host);
+  delete t;
+}
+
+int giem_tables_import(const giem_model *model, int32_t nfreq, const double *freq_hz,
+                       const void *host_packed_spatial, uint32_t flags, void *stream,
+                       giem_handle **out) {
+  if (!host_packed_spatial) {
+    set_error("host_packed_spatial is null");
+    return GIEM_EINVAL;
+  }
+  giem_handle *t = nullptr;
+  GIEM_TRY(create_handle(model, nfreq, freq_hz, flags, &t));
+  const size_t nsp = (size_t)t->nx * t->ny * t->E();
+  const cd *src = static_cast<const cd *>(host_packed_spatial);
+  for (int q = 0; q < nfreq; ++q) t->f[q].spatial.assign(src + q * nsp, src + (q + 1) * nsp);
+  int rc = finish_handle(t, static_cast<hipStream_t>(stream));
+  if (rc < 0) {
+    giem_free(t);
+    return rc;
+  }
+  *out = t;
+  return GIEM_OK;
+}
+
+int giem_tables(const giem_model *model, int32_t nfreq, const double *freq_hz, uint32_t flags,
+                void *stream, giem_handle **out) {
+  giem_handle *t = nullptr;
+  GIEM_TRY(create_handle(model, nfreq, freq_hz, flags, &t));
+  for (int q = 0; q < nfreq; ++q) {
+    int rc = compute_tables_host(t, t->f[q].freq, t->f[q].spatial);
+    if (rc < 0) {
+      giem_free(t);
+      return rc;
+    }
+  }
+  int rc = finish_handle(t, static_cast<hipStream_t>(stream));
+  if (rc < 0) {
+    giem_free(t);
+    return rc;
+  }
+  *out = t;
+  return GIEM_OK;
+}
+
+int giem_tables_export(const giem_handle *t, int32_t ifreq, void *host_packed_spatial) {
+  if (!t || !host_packed_spatial || ifreq < 0 || ifreq >= (int)t->f.size()) {
+    set_error("giem_tables_export: bad handle, frequency index or pointer");
+    return GIEM_EINVAL;
+  }
+  const auto &sp = t->f[ifreq].spatial;
+  std::memcpy(host_packed_spatial, sp.data(), sp.size() * sizeof(cd));
+  return GIEM_OK;
+}
+
+int giem_tables_bytes(const giem_handle *t, int64_t *b128, int64_t *b64) {
+  if (!t) {
+    set_error("null handle");
+    return GIEM_EINVAL;
+  }
+  const int64_t n = (int64_t)(t->nx + 1) * (t->ny + 1) * t->E();
+  if (b128) *b128 = n * (int64_t)sizeof(c128);
+  if (b64) *b64 = (t->flags & GIEM_TABLES_C64) ? n * (int64_t)sizeof(c64) : 0;
+  return GIEM_OK;
+}
+
+static int apply_entry(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
+                       const void *x, void *y, uint32_t mode, uint32_t prec, void *stream,
+                       double *stage_ms) {
+  if (!t || ifreq < 0 || ifreq >= (int)t->f.size() || nrhs < 1 || nrhs > kMaxRhs || !x || !y ||
+      mode > MODE_B || prec > PREC_FP32 || (mode != MODE_B && !sigma_a)) {
+    set_error("giem_apply: bad argument");
+    return GIEM_EINVAL;
+  }
+  const size_t nbytes = (size_t)nrhs * t->nvec() * sizeof(c128);
+  const char *xa = static_cast<const char *>(x), *ya = static_cast<const char *>(y);
+  if (xa < ya + nbytes && ya < xa + nbytes) {
+    set_error("giem_apply: x and y overlap");
+    return GIEM_EINVAL;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (mode != MODE_B) GIEM_TRY(compute_diagonals(t, static_cast<const c128 *>(sigma_a), s));
+  VecPtrs p{};
+  for (int r = 0; r < nrhs; ++r) {
+    p.in[r] = static_cast<const c128 *>(x) + r * t->nvec();
+    p.out[r] = static_cast<c128 *>(y) + r * t->nvec();
+  }
+  return apply_core(t, ifreq, nrhs, p, mode, prec, s, stage_ms);
+}
+
+int giem_apply(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs, const void *x,
+               void *y, uint32_t mode, uint32_t prec, void *stream) {
+  return apply_entry(t, ifreq, sigma_a, nrhs, x, y, mode, prec, stream, nullptr);
+}
+
+int giem_apply_timed(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
+                     const void *x, void *y, uint32_t mode, uint32_t prec, void *stream,
+                     double *stage_ms) {
+  if (!stage_ms) {
+    set_error("stage_ms is null");
+    return GIEM_EINVAL;
+  }
+  return apply_entry(t, ifreq, sigma_a, nrhs, x, y, mode, prec, stream, stage_ms);
+}
+
+}  // extern "C"

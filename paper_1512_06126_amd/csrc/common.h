@@ -1,0 +1,84 @@
+// Internal definitions shared by the HIP kernels and the host side of the
+// library.  Not part of the public ABI (see include/giem.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace giem {
+
+// ---------------------------------------------------------------- complex
+template <typename T>
+struct alignas(2 * sizeof(T)) cplx {
+  T x, y;
+};
+
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> mk(T a, T b) {
+  cplx<T> r;
+  r.x = a;
+  r.y = b;
+  return r;
+}
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) {
+  return mk<T>(a.x + b.x, a.y + b.y);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) {
+  return mk<T>(a.x - b.x, a.y - b.y);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> cmulc(cplx<T> a, cplx<T> b) {
+  return mk<T>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) {
+  return mk<T>(a.x * s, a.y * s);
+}
+// acc += a * b
+template <typename T>
+__host__ __device__ __forceinline__ void cfma(cplx<T> &acc, cplx<T> a, cplx<T> b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+}
+template <typename T, typename U>
+__host__ __device__ __forceinline__ cplx<T> ccast(cplx<U> a) {
+  return mk<T>(static_cast<T>(a.x), static_cast<T>(a.y));
+}
+
+typedef cplx<double> c128;
+typedef cplx<float> c64;
+
+// ---------------------------------------------------------------- FFT plan
+constexpr int kMaxFactors = 24;
+struct FftDesc {
+  int L;                  // transform length
+  int nf;                 // number of radix stages
+  int fac[kMaxFactors];   // radices in stage order (4, 2, 3, 5, 7)
+};
+
+// Per-RHS vector pointers of one apply (the basis vectors of GMRES are not
+// contiguous across right-hand sides).
+constexpr int kMaxRhs = 8;
+struct VecPtrs {
+  const c128 *in[kMaxRhs];
+  c128 *out[kMaxRhs];
+};
+
+// Operator modes and precisions (mirror include/giem.h)
+enum { MODE_A = 0, MODE_AT = 1, MODE_B = 2 };
+enum { PREC_FP64 = 0, PREC_FP32 = 1 };
+
+}  // namespace giem

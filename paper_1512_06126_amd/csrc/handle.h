@@ -1,0 +1,86 @@
+// The giem_handle and host-side helpers (internal).
+#pragma once
+
+#include <complex>
+#include <string>
+#include <vector>
+
+#include "../../include/giem.h"
+#include "kernels.h"
+
+namespace giem {
+
+typedef std::complex<double> cd;
+
+void set_error(const std::string &msg);
+const std::string &get_error();
+
+struct FftPlan {
+  FftDesc d{};
+  void *tw64 = nullptr;  // c128 [L]
+  void *tw32 = nullptr;  // c64  [L]
+};
+
+struct FreqTables {
+  double freq = 0.0;
+  void *spec64 = nullptr;      // c128 [(Ny+1)(Nx+1)][E] packed spectra
+  void *spec32 = nullptr;      // c64 copy (GIEM_TABLES_C64)
+  std::vector<cd> spatial;     // packed spatial table [Ny][Nx][E] (host)
+};
+
+struct SolveWork;
+
+}  // namespace giem
+
+struct giem_handle {
+  int nx = 0, ny = 0, nz = 0, nlay = 0;
+  double hx = 0, hy = 0, x0 = 0, y0 = 0;
+  std::vector<double> d, z_edges;
+  std::vector<giem::cd> sigma;     // [nlay + 1]
+  std::vector<int> layer_of_cell;  // [nz]
+  uint32_t flags = 0;
+  int device = 0;
+  std::vector<giem::FreqTables> f;
+  giem::FftPlan px, py;            // lengths 2 Nx, 2 Ny
+  void *cs_x = nullptr, *cs_y = nullptr;  // (cos, sin)(pi a / N), a < 2N
+  // per-level device data
+  void *sb_lev = nullptr;    // c128 [nz]
+  void *vol_lev = nullptr;   // double [nz]
+  void *sroot_lev = nullptr; // double [nz]
+  // diagonals of the last sigma_a: S, R1, R2, a (c128 [N] each)
+  void *diag = nullptr;
+  // spectra workspace
+  void *spec_ws = nullptr;
+  size_t spec_ws_bytes = 0;
+  // reduction scratch
+  void *red_part = nullptr;  // c128 [kMaxRhs][65][nblk]
+  void *red_out = nullptr;   // c128 [kMaxRhs][65]
+  void *red_host = nullptr;  // pinned host mirror of red_out
+  void *coef_dev = nullptr;  // c128 [kMaxRhs][65] coefficients for updates
+  void *coef_host = nullptr; // pinned
+  // solver workspace (grown on demand)
+  void *basis = nullptr;
+  size_t basis_bytes = 0;
+  void *vec_ws = nullptr;
+  size_t vec_ws_bytes = 0;
+  giem::SolveWork *sw = nullptr;
+
+  size_t ncell() const { return (size_t)nx * ny * nz; }
+  size_t nvec() const { return 3 * ncell(); }
+  int E() const { return 2 * nz * (2 * nz + 1); }
+};
+
+namespace giem {
+
+int check_hip(hipError_t e, const char *what);
+int ensure_spec_ws(giem_handle *t, int nrhs, int prec);
+int compute_diagonals(giem_handle *t, const c128 *sigma_a, hipStream_t s);
+// y = op x on per-RHS pointers; diagonals must be current (compute_diagonals)
+int apply_core(giem_handle *t, int ifreq, int nrhs, const VecPtrs &p, unsigned mode,
+               unsigned prec, hipStream_t s, double *stage_ms);
+int upload_spatial(giem_handle *t, hipStream_t s);
+int plane_wave_levels(const giem_handle *t, double freq, std::vector<cd> &en_lev,
+                      std::vector<cd> &hsurf);
+int compute_tables_host(giem_handle *t, double freq, std::vector<cd> &spatial);
+
+}  // namespace giem

@@ -1,0 +1,76 @@
+// Launchers of the HIP kernels (internal).
+#pragma once
+
+#include "common.h"
+
+namespace giem {
+
+// operator apply (kernels_apply.hip)
+hipError_t set_lds_limits();
+int block_threads(int nz, int R);
+size_t block_lds_bytes(int nz, int R, int prec);
+size_t fft_lds_bytes(int G, int L, int prec);
+hipError_t launch_fft_x_fwd(int prec, const VecPtrs &ptrs, const c128 *r2, void *spec, int nx,
+                            int ny, int nz, int rp_total, int G, const FftDesc &fd,
+                            const void *tw, hipStream_t s);
+hipError_t launch_fft_x_inv(int prec, const VecPtrs &ptrs, const c128 *sd, const c128 *r1,
+                            const void *spec, int nx, int ny, int nz, int rp_total, int G,
+                            const FftDesc &fd, const void *tw, double scale, hipStream_t s);
+hipError_t launch_fft_y(int prec, void *spec, int nx2, int ny, int rp_total, int G,
+                        const FftDesc &fd, const void *tw, int inverse, hipStream_t s);
+hipError_t launch_block(int prec, const void *tab, void *spec, int nx, int ny, int nz, int R,
+                        hipStream_t s);
+
+// table set-up (kernels_setup.hip)
+hipError_t launch_spectral_x(const c128 *spatial, c128 *tmp, const c128 *cs_x, int nx, int ny,
+                             int nz, hipStream_t s);
+hipError_t launch_spectral_y(const c128 *tmp, c128 *spectral, const c128 *cs_y, int nx, int ny,
+                             int nz, hipStream_t s);
+hipError_t launch_to_c64(const c128 *src, c64 *dst, size_t n, hipStream_t s);
+hipError_t launch_diagonals(const c128 *sigma_a, const c128 *sb_lev, const double *vol_lev,
+                            int nx, int ny, int nz, c128 *S, c128 *R1, c128 *R2, c128 *a,
+                            int *bad, hipStream_t s);
+hipError_t launch_plane_wave_rhs(const c128 *en_lev, const double *sroot_lev, int nx, int ny,
+                                 int nz, int pol, c128 *out, hipStream_t s);
+
+hipError_t launch_adjoint_grad(const c128 *sigma_a, const c128 *sb_lev, const c128 *acell,
+                               const c128 *g, const c128 *E, const c128 *lam, const c128 *w,
+                               int nrhs, int nx, int ny, int nz, double *grad, hipStream_t s);
+
+// Krylov vector kernels (kernels_vec.hip); vectors of n = 3 Nz Ny Nx complex.
+struct DotArgs {
+  const c128 *w[kMaxRhs];      // vector to project
+  const c128 *basis[kMaxRhs];  // basis base pointer, vectors at stride n
+};
+int dot_partials_per_rhs();
+// partial sums of conj-weighted dots <w, V_i> (i < nb) and ||w||^2 into
+// part[r][block][nb + 1]; then reduced into out[r][nb + 1].
+hipError_t launch_dots(const DotArgs &a, int nrhs, int nb, size_t n, int nz, int plane,
+                       const double *wlev, c128 *part, c128 *out, hipStream_t s);
+// w -= sum_i h[r][i] V_i, and ||w||^2 reduced into nrm[r] (real in .x)
+hipError_t launch_update(const DotArgs &a, int nrhs, int nb, size_t n, int nz, int plane,
+                         const double *wlev, const c128 *h, int hstride, c128 *part,
+                         c128 *nrm, hipStream_t s);
+// dst[r] = src[r] * scal[r] (complex scalars on device)
+hipError_t launch_scale(c128 *const *dst, const c128 *const *src, const c128 *scal, int nrhs,
+                        size_t n, hipStream_t s);
+struct LinArgs {
+  c128 *x[kMaxRhs];
+  const c128 *basis[kMaxRhs];
+};
+// x[r] += sum_i y[r][i] V_i
+hipError_t launch_lincomb(const LinArgs &a, int nrhs, int nb, size_t n, const c128 *y,
+                          int ystride, hipStream_t s);
+// out = alpha * a + beta * b  (element-wise, complex scalars from host)
+hipError_t launch_axpby(c128 *out, const c128 *a, const c128 *b, c128 alpha, c128 beta,
+                        size_t n, hipStream_t s);
+// out[r] = u[r] / a_cell (E = U / a)
+hipError_t launch_div_cells(c128 *out, const c128 *u, const c128 *acell, int nrhs, size_t ncell,
+                            hipStream_t s);
+hipError_t launch_mul_cells(c128 *out, const c128 *u, const c128 *acell, int nrhs, size_t ncell,
+                            hipStream_t s);
+// weighted squared norms of nrhs contiguous vectors into nrm[r].x
+hipError_t launch_norms(const c128 *v, int nrhs, size_t n, int nz, int plane, const double *wlev,
+                        c128 *part, c128 *nrm, hipStream_t s);
+
+}  // namespace giem

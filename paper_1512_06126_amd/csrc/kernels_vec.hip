@@ -1,0 +1,264 @@
+// Krylov vector kernels of GMRES (Sect. 3.3, flexible GMRES; Sect. 2.1, the
+// L2 inner product (V, U) = int V . conj(U)).  On the cell grid the inner
+// product is sum_n wt_n V_n conj(U_n) with wt_n = V_n (cell volume) when the
+// weighted form is requested, else 1.  All accumulation is FP64; reductions
+// are wavefront shuffles, LDS across the workgroup, then a second pass over
+// the per-workgroup partials.
+#include "kernels.h"
+
+namespace giem {
+
+constexpr int kRedBlocks = 480;  // workgroups of the first reduction stage
+constexpr int kSlots = 8;        // inner products per workgroup pass
+
+int dot_partials_per_rhs() { return kRedBlocks; }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Sum a per-thread value over the 256-thread workgroup; result in thread 0.
+__device__ __forceinline__ double block_sum(double v, double *red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+  }
+  return s;
+}
+
+__device__ __forceinline__ double weight_of(size_t k, int plane, int nz, const double *wlev) {
+  return wlev ? wlev[(int)((k / plane) % nz)] : 1.0;
+}
+
+// part[r][slot][block]: slot s < nb: sum wt w conj(V_s); slot nb: sum wt |w|^2
+__global__ void __launch_bounds__(256)
+k_dots(DotArgs a, int nb, size_t n, int nz, int plane, const double *__restrict__ wlev,
+       c128 *__restrict__ part) {
+  __shared__ double red[8];
+  const int r = blockIdx.y;
+  const int s0 = blockIdx.z * kSlots;
+  const c128 *w = a.w[r];
+  const c128 *V = a.basis[r];
+  double accr[kSlots], acci[kSlots];
+#pragma unroll
+  for (int k = 0; k < kSlots; ++k) accr[k] = acci[k] = 0.0;
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n;
+       k += (size_t)gridDim.x * blockDim.x) {
+    const c128 wv = w[k];
+    const double wt = weight_of(k, plane, nz, wlev);
+#pragma unroll
+    for (int q = 0; q < kSlots; ++q) {
+      const int s = s0 + q;
+      if (s < nb) {
+        const c128 v = V[(size_t)s * n + k];
+        accr[q] += wt * (wv.x * v.x + wv.y * v.y);
+        acci[q] += wt * (wv.y * v.x - wv.x * v.y);
+      } else if (s == nb) {
+        accr[q] += wt * (wv.x * wv.x + wv.y * wv.y);
+      }
+    }
+  }
+  const int nslots = nb + 1;
+#pragma unroll
+  for (int q = 0; q < kSlots; ++q) {
+    const int s = s0 + q;
+    const double sr = block_sum(accr[q], red);
+    const double si = block_sum(acci[q], red);
+    if (threadIdx.x == 0 && s < nslots)
+      part[((size_t)r * nslots + s) * gridDim.x + blockIdx.x] = mk<double>(sr, si);
+  }
+}
+
+// out[r][slot] = sum over blocks of part[r][slot][block]
+__global__ void __launch_bounds__(256)
+k_reduce(const c128 *__restrict__ part, int nblk, int nslots, c128 *__restrict__ out) {
+  __shared__ double red[8];
+  const int r = blockIdx.y, s = blockIdx.x;
+  const c128 *p = part + ((size_t)r * nslots + s) * nblk;
+  double ar = 0.0, ai = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+    ar += p[b].x;
+    ai += p[b].y;
+  }
+  ar = block_sum(ar, red);
+  ai = block_sum(ai, red);
+  if (threadIdx.x == 0) out[(size_t)r * nslots + s] = mk<double>(ar, ai);
+}
+
+hipError_t launch_dots(const DotArgs &a, int nrhs, int nb, size_t n, int nz, int plane,
+                       const double *wlev, c128 *part, c128 *out, hipStream_t s) {
+  const int nslots = nb + 1;
+  dim3 grid(kRedBlocks, nrhs, (nslots + kSlots - 1) / kSlots);
+  k_dots<<<grid, 256, 0, s>>>(a, nb, n, nz, plane, wlev, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_reduce<<<dim3(nslots, nrhs), 256, 0, s>>>(part, kRedBlocks, nslots, out);
+  return hipGetLastError();
+}
+
+// w -= sum_{i < nb} h[r][i] V_i ; partial ||w||^2 into part[r][0][block]
+__global__ void __launch_bounds__(256)
+k_update(DotArgs a, int nb, size_t n, int nz, int plane, const double *__restrict__ wlev,
+         const c128 *__restrict__ h, int hstride, c128 *__restrict__ part) {
+  __shared__ double red[8];
+  __shared__ c128 hs[64];
+  const int r = blockIdx.y;
+  c128 *w = const_cast<c128 *>(a.w[r]);
+  const c128 *V = a.basis[r];
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) hs[i] = h[(size_t)r * hstride + i];
+  __syncthreads();
+  double acc = 0.0;
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n;
+       k += (size_t)gridDim.x * blockDim.x) {
+    c128 wv = w[k];
+    for (int i = 0; i < nb; ++i) {
+      const c128 v = V[(size_t)i * n + k];
+      const c128 hv = hs[i];
+      wv.x -= hv.x * v.x - hv.y * v.y;
+      wv.y -= hv.x * v.y + hv.y * v.x;
+    }
+    w[k] = wv;
+    acc += weight_of(k, plane, nz, wlev) * (wv.x * wv.x + wv.y * wv.y);
+  }
+  const double sum = block_sum(acc, red);
+  if (threadIdx.x == 0) part[(size_t)r * gridDim.x + blockIdx.x] = mk<double>(sum, 0.0);
+}
+
+hipError_t launch_update(const DotArgs &a, int nrhs, int nb, size_t n, int nz, int plane,
+                         const double *wlev, const c128 *h, int hstride, c128 *part, c128 *nrm,
+                         hipStream_t s) {
+  if (nb > 64) return hipErrorInvalidValue;
+  dim3 grid(kRedBlocks, nrhs);
+  k_update<<<grid, 256, 0, s>>>(a, nb, n, nz, plane, wlev, h, hstride, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_reduce<<<dim3(1, nrhs), 256, 0, s>>>(part, kRedBlocks, 1, nrm);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256)
+k_norms(const c128 *__restrict__ v, size_t n, int nz, int plane, const double *__restrict__ wlev,
+        c128 *__restrict__ part) {
+  __shared__ double red[8];
+  const int r = blockIdx.y;
+  const c128 *x = v + (size_t)r * n;
+  double acc = 0.0;
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n;
+       k += (size_t)gridDim.x * blockDim.x) {
+    const c128 a = x[k];
+    acc += weight_of(k, plane, nz, wlev) * (a.x * a.x + a.y * a.y);
+  }
+  const double sum = block_sum(acc, red);
+  if (threadIdx.x == 0) part[(size_t)r * gridDim.x + blockIdx.x] = mk<double>(sum, 0.0);
+}
+
+hipError_t launch_norms(const c128 *v, int nrhs, size_t n, int nz, int plane, const double *wlev,
+                        c128 *part, c128 *nrm, hipStream_t s) {
+  dim3 grid(kRedBlocks, nrhs);
+  k_norms<<<grid, 256, 0, s>>>(v, n, nz, plane, wlev, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_reduce<<<dim3(1, nrhs), 256, 0, s>>>(part, kRedBlocks, 1, nrm);
+  return hipGetLastError();
+}
+
+struct ScaleArgs {
+  c128 *dst[kMaxRhs];
+  const c128 *src[kMaxRhs];
+  c128 f[kMaxRhs];
+};
+
+__global__ void k_scale(ScaleArgs a, size_t n) {
+  const int r = blockIdx.y;
+  const c128 f = a.f[r];
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n;
+       k += (size_t)gridDim.x * blockDim.x)
+    a.dst[r][k] = cmul(a.src[r][k], f);
+}
+
+hipError_t launch_scale(c128 *const *dst, const c128 *const *src, const c128 *scal, int nrhs,
+                        size_t n, hipStream_t s) {
+  ScaleArgs a;
+  for (int r = 0; r < nrhs; ++r) {
+    a.dst[r] = dst[r];
+    a.src[r] = src[r];
+    a.f[r] = scal[r];
+  }
+  k_scale<<<dim3(1024, nrhs), 256, 0, s>>>(a, n);
+  return hipGetLastError();
+}
+
+__global__ void k_lincomb(LinArgs a, int nb, size_t n, const c128 *__restrict__ y, int ystride) {
+  __shared__ c128 ys[64];
+  const int r = blockIdx.y;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) ys[i] = y[(size_t)r * ystride + i];
+  __syncthreads();
+  c128 *x = a.x[r];
+  const c128 *V = a.basis[r];
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n;
+       k += (size_t)gridDim.x * blockDim.x) {
+    c128 acc = x[k];
+    for (int i = 0; i < nb; ++i) cfma(acc, ys[i], V[(size_t)i * n + k]);
+    x[k] = acc;
+  }
+}
+
+hipError_t launch_lincomb(const LinArgs &a, int nrhs, int nb, size_t n, const c128 *y,
+                          int ystride, hipStream_t s) {
+  if (nb > 64) return hipErrorInvalidValue;
+  k_lincomb<<<dim3(1024, nrhs), 256, 0, s>>>(a, nb, n, y, ystride);
+  return hipGetLastError();
+}
+
+__global__ void k_axpby(c128 *__restrict__ out, const c128 *__restrict__ a,
+                        const c128 *__restrict__ b, c128 alpha, c128 beta, size_t n) {
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n;
+       k += (size_t)gridDim.x * blockDim.x) {
+    c128 v = cmul(alpha, a[k]);
+    cfma(v, beta, b[k]);
+    out[k] = v;
+  }
+}
+
+hipError_t launch_axpby(c128 *out, const c128 *a, const c128 *b, c128 alpha, c128 beta, size_t n,
+                        hipStream_t s) {
+  k_axpby<<<1024, 256, 0, s>>>(out, a, b, alpha, beta, n);
+  return hipGetLastError();
+}
+
+// out[r][comp][cell] = u[r][comp][cell] (op) acell[cell]
+__global__ void k_cellop(c128 *__restrict__ out, const c128 *__restrict__ u,
+                         const c128 *__restrict__ acell, size_t ncell, size_t n, int divide) {
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n;
+       k += (size_t)gridDim.x * blockDim.x) {
+    const c128 a = acell[k % ncell];
+    const c128 v = u[k];
+    if (divide) {
+      const double dd = a.x * a.x + a.y * a.y;
+      out[k] = mk<double>((v.x * a.x + v.y * a.y) / dd, (v.y * a.x - v.x * a.y) / dd);
+    } else {
+      out[k] = cmul(v, a);
+    }
+  }
+}
+
+hipError_t launch_div_cells(c128 *out, const c128 *u, const c128 *acell, int nrhs, size_t ncell,
+                            hipStream_t s) {
+  k_cellop<<<1024, 256, 0, s>>>(out, u, acell, ncell, (size_t)nrhs * 3 * ncell, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_mul_cells(c128 *out, const c128 *u, const c128 *acell, int nrhs, size_t ncell,
+                            hipStream_t s) {
+  k_cellop<<<1024, 256, 0, s>>>(out, u, acell, ncell, (size_t)nrhs * 3 * ncell, 0);
+  return hipGetLastError();
+}
+
+}  // namespace giem

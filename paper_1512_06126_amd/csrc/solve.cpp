@@ -1,0 +1,643 @@
+// GMRES driver (Sect. 3.3: the system is solved by flexible GMRES; without a
+// preconditioner it reduces to GMRES(m)), the precision form (complex64
+// convolution inside an inner GMRES, FP64 residual refinement outside), the
+// adjoint solve, and the plane-wave normal field used for the right-hand side
+// (Sect. 2.1).  The Arnoldi vectors and all inner products are FP64 on the
+// device; the Hessenberg matrix, the Givens rotations and the small
+// least-squares problem are FP64 on the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "handle.h"
+
+namespace giem {
+
+#define GIEM_TRY(expr)          \
+  do {                          \
+    int rc__ = (expr);          \
+    if (rc__ < 0) return rc__;  \
+  } while (0)
+#define GIEM_HIP(expr, what) GIEM_TRY(check_hip((expr), (what)))
+
+static const double kMu0 = 4e-7 * 3.14159265358979323846;
+
+// ------------------------------------------------------------ normal field
+// 1-D plane wave in the layered earth, exp(-i w t), E'' + k^2 E = 0 with
+// k^2 = i w mu0 sigma, Im k >= 0, E(0) = 1.  In layer m (between d[m-1] and
+// d[m]) E = a_m (e^{ik(z-d[m])} + r_m e^{-ik(z-d[m])}); r_m follows from the
+// impedance of the medium below, evaluated from the lower half-space up.
+struct PlaneWave {
+  std::vector<cd> k, a, r;
+  std::vector<double> d;
+  int nl = 0;
+  cd Zs;
+  double omega = 0;
+
+  PlaneWave(const std::vector<double> &dd, const std::vector<cd> &sigma, double freq) {
+    d = dd;
+    nl = (int)d.size();
+    omega = 2.0 * M_PI * freq;
+    k.resize(nl + 1);
+    for (int m = 0; m <= nl; ++m) {
+      cd kk = std::sqrt(cd(0.0, omega * kMu0) * sigma[m]);
+      if (kk.imag() < 0) kk = -kk;
+      k[m] = kk;
+    }
+    r.assign(nl + 1, 0.0);
+    a.assign(nl + 1, 0.0);
+    auto z0 = [&](int m) { return omega * kMu0 / k[m]; };
+    cd zb = z0(nl);
+    for (int m = nl - 1; m >= 1; --m) {
+      const double l = d[m] - d[m - 1];
+      const cd rr = (zb - z0(m)) / (zb + z0(m));
+      r[m] = rr;
+      const cd e = std::exp(cd(0, 2) * k[m] * l);
+      zb = z0(m) * (1.0 + rr * e) / (1.0 - rr * e);
+    }
+    Zs = zb;
+    cd etop = 1.0;
+    for (int m = 1; m < nl; ++m) {
+      const double l = d[m] - d[m - 1];
+      const cd e = std::exp(cd(0, 1) * k[m] * l);
+      a[m] = etop * e / (1.0 + r[m] * e * e);
+      etop = a[m] * (1.0 + r[m]);
+    }
+    a[nl] = etop;
+  }
+  int layer(double z) const {
+    int m = 0;
+    while (m < nl && d[m] <= z) ++m;
+    return m;
+  }
+  // mean of E over [z1, z2] inside one earth layer
+  cd average(double z1, double z2) const {
+    const int m = layer(0.5 * (z1 + z2));
+    const cd ik = cd(0, 1) * k[m];
+    cd v;
+    if (m == nl) {
+      const double dd = d[m - 1];
+      v = a[m] * (std::exp(ik * (z2 - dd)) - std::exp(ik * (z1 - dd))) / ik;
+    } else {
+      const double dm = d[m];
+      const cd up = (std::exp(ik * (z2 - dm)) - std::exp(ik * (z1 - dm))) / ik;
+      const cd dn = (std::exp(-ik * (z2 - dm)) - std::exp(-ik * (z1 - dm))) / (-ik);
+      v = a[m] * (up + r[m] * dn);
+    }
+    return v / (z2 - z1);
+  }
+};
+
+int plane_wave_levels(const giem_handle *t, double freq, std::vector<cd> &en_lev,
+                      std::vector<cd> &hsurf) {
+  PlaneWave pw(t->d, t->sigma, freq);
+  en_lev.resize(t->nz);
+  for (int k = 0; k < t->nz; ++k) en_lev[k] = pw.average(t->z_edges[k], t->z_edges[k + 1]);
+  hsurf.assign(1, 1.0 / pw.Zs);
+  return GIEM_OK;
+}
+
+// ------------------------------------------------------------ GMRES(m)
+struct GmresParams {
+  double tol = 1e-6;
+  int m = 30;
+  int max_iter = 1000;
+  int weighted = 0;
+  unsigned mode = MODE_A;
+  unsigned prec = PREC_FP64;
+  bool x_zero = true;
+};
+
+struct GmresResult {
+  int iters = 0;      // operator applies inside Arnoldi (max over RHS)
+  int restarts = 0;
+  std::vector<double> relres;  // final true residual / ||b||
+  bool converged = false;
+};
+
+static int ensure_basis(giem_handle *t, int nrhs, int m) {
+  const size_t need = (size_t)nrhs * (m + 1) * t->nvec() * sizeof(c128);
+  if (t->basis_bytes >= need) return GIEM_OK;
+  if (t->basis) hipFree(t->basis);
+  t->basis = nullptr;
+  t->basis_bytes = 0;
+  GIEM_HIP(hipMalloc(&t->basis, need), "hipMalloc Krylov basis");
+  t->basis_bytes = need;
+  return GIEM_OK;
+}
+
+static int ensure_vec_ws(giem_handle *t, size_t nvecs) {
+  const size_t need = nvecs * t->nvec() * sizeof(c128);
+  if (t->vec_ws_bytes >= need) return GIEM_OK;
+  if (t->vec_ws) hipFree(t->vec_ws);
+  t->vec_ws = nullptr;
+  t->vec_ws_bytes = 0;
+  GIEM_HIP(hipMalloc(&t->vec_ws, need), "hipMalloc vector workspace");
+  t->vec_ws_bytes = need;
+  return GIEM_OK;
+}
+
+// weighted squared norms of nv vectors (each at its own pointer)
+static int norms_of(giem_handle *t, const c128 *const *v, int nv, const double *wlev,
+                    hipStream_t s, std::vector<double> &out) {
+  c128 *part = static_cast<c128 *>(t->red_part);
+  c128 *res = static_cast<c128 *>(t->coef_dev);
+  const int plane = t->nx * t->ny;
+  for (int r = 0; r < nv; ++r)
+    GIEM_HIP(launch_norms(v[r], 1, t->nvec(), t->nz, plane, wlev, part, res + r, s), "norm kernel");
+  GIEM_HIP(hipMemcpyAsync(t->coef_host, res, nv * sizeof(c128), hipMemcpyDeviceToHost, s), "copy norms");
+  GIEM_HIP(hipStreamSynchronize(s), "sync");
+  out.resize(nv);
+  const c128 *h = static_cast<const c128 *>(t->coef_host);
+  for (int r = 0; r < nv; ++r) out[r] = std::sqrt(std::max(h[r].x, 0.0));
+  return GIEM_OK;
+}
+
+// y_r = op(x_r) for a set of RHS given by pointers (batched in groups of 8)
+static int apply_ptrs(giem_handle *t, int ifreq, const std::vector<const c128 *> &in,
+                      const std::vector<c128 *> &out, unsigned mode, unsigned prec,
+                      hipStream_t s) {
+  for (size_t b0 = 0; b0 < in.size(); b0 += kMaxRhs) {
+    const int nb = (int)std::min<size_t>(kMaxRhs, in.size() - b0);
+    VecPtrs p{};
+    for (int r = 0; r < nb; ++r) {
+      p.in[r] = in[b0 + r];
+      p.out[r] = out[b0 + r];
+    }
+    GIEM_TRY(apply_core(t, ifreq, nb, p, mode, prec, s, nullptr));
+  }
+  return GIEM_OK;
+}
+
+static int gmres(giem_handle *t, int ifreq, int nrhs, const c128 *const *b, c128 *const *x,
+                 const GmresParams &gp, hipStream_t s, GmresResult &res) {
+  const int m = gp.m;
+  const size_t n = t->nvec();
+  const int plane = t->nx * t->ny;
+  const double *wlev = gp.weighted ? static_cast<const double *>(t->vol_lev) : nullptr;
+  GIEM_TRY(ensure_basis(t, nrhs, m));
+  c128 *basis = static_cast<c128 *>(t->basis);
+  auto V = [&](int r, int i) { return basis + ((size_t)r * (m + 1) + i) * n; };
+  std::vector<double> normb;
+  GIEM_TRY(norms_of(t, b, nrhs, wlev, s, normb));
+  res.relres.assign(nrhs, 0.0);
+  res.iters = 0;
+  res.restarts = 0;
+  std::vector<int> done(nrhs, 0);
+  for (int r = 0; r < nrhs; ++r) {
+    if (normb[r] == 0.0) {
+      GIEM_HIP(hipMemsetAsync(x[r], 0, n * sizeof(c128), s), "zero x");
+      done[r] = 1;
+    }
+  }
+  bool x_zero = gp.x_zero;
+  int iters = 0;
+  std::vector<std::vector<cd>> H(nrhs), cs(nrhs), sn(nrhs), g(nrhs);
+  c128 *hdev = static_cast<c128 *>(t->red_out);
+  c128 *ndev = static_cast<c128 *>(t->coef_dev);
+  c128 *part = static_cast<c128 *>(t->red_part);
+  c128 *hhost = static_cast<c128 *>(t->red_host);
+  c128 *chost = static_cast<c128 *>(t->coef_host);
+  while (true) {
+    // residual r0 = b - A x into V(r, 0)
+    std::vector<int> act;
+    for (int r = 0; r < nrhs; ++r)
+      if (!done[r]) act.push_back(r);
+    if (act.empty()) break;
+    if (x_zero) {
+      for (int r : act) {
+        GIEM_HIP(hipMemcpyAsync(V(r, 0), b[r], n * sizeof(c128), hipMemcpyDeviceToDevice, s), "copy b");
+        GIEM_HIP(hipMemsetAsync(x[r], 0, n * sizeof(c128), s), "zero x");
+      }
+    } else {
+      std::vector<const c128 *> in;
+      std::vector<c128 *> out;
+      for (int r : act) {
+        in.push_back(x[r]);
+        out.push_back(V(r, 0));
+      }
+      GIEM_TRY(apply_ptrs(t, ifreq, in, out, gp.mode, gp.prec, s));
+      for (int r : act)
+        GIEM_HIP(launch_axpby(V(r, 0), b[r], V(r, 0), mk<double>(1, 0), mk<double>(-1, 0), n, s), "axpby");
+    }
+    x_zero = false;
+    std::vector<const c128 *> r0p;
+    for (int r : act) r0p.push_back(V(r, 0));
+    std::vector<double> beta;
+    GIEM_TRY(norms_of(t, r0p.data(), (int)act.size(), wlev, s, beta));
+    std::vector<int> cyc;  // RHS iterating in this cycle
+    for (size_t q = 0; q < act.size(); ++q) {
+      const int r = act[q];
+      res.relres[r] = beta[q] / normb[r];
+      if (beta[q] <= gp.tol * normb[r]) {
+        done[r] = 1;
+        continue;
+      }
+      if (iters >= gp.max_iter) continue;
+      cyc.push_back(r);
+      H[r].assign((size_t)(m + 1) * m, 0.0);
+      cs[r].assign(m, 0.0);
+      sn[r].assign(m, 0.0);
+      g[r].assign(m + 1, 0.0);
+      g[r][0] = beta[q];
+      const c128 f = mk<double>(1.0 / beta[q], 0.0);
+      c128 *dst = V(r, 0);
+      const c128 *src = V(r, 0);
+      GIEM_HIP(launch_scale(&dst, &src, &f, 1, n, s), "scale");
+    }
+    if (cyc.empty()) break;
+    ++res.restarts;
+    std::vector<int> jlen(nrhs, 0);
+    std::vector<int> running = cyc;
+    for (int j = 0; j < m && !running.empty(); ++j) {
+      if (iters >= gp.max_iter) break;
+      const int na = (int)running.size();
+      // w = A v_j into V(r, j+1)
+      std::vector<const c128 *> in;
+      std::vector<c128 *> out;
+      for (int r : running) {
+        in.push_back(V(r, j));
+        out.push_back(V(r, j + 1));
+      }
+      GIEM_TRY(apply_ptrs(t, ifreq, in, out, gp.mode, gp.prec, s));
+      ++iters;
+      // classical Gram-Schmidt, repeated once when the norm drops sharply
+      std::vector<std::vector<cd>> hcol(na, std::vector<cd>(j + 1, 0.0));
+      std::vector<double> nw0(na, 0.0), nw1(na, 0.0);
+      for (int pass = 0; pass < 2; ++pass) {
+        DotArgs da{};
+        for (int q = 0; q < na; ++q) {
+          da.w[q] = V(running[q], j + 1);
+          da.basis[q] = V(running[q], 0);
+        }
+        const int nb = j + 1;
+        GIEM_HIP(launch_dots(da, na, nb, n, t->nz, plane, wlev, part, hdev, s), "dots");
+        GIEM_HIP(launch_update(da, na, nb, n, t->nz, plane, wlev, hdev, nb + 1, part, ndev, s), "update");
+        GIEM_HIP(hipMemcpyAsync(hhost, hdev, (size_t)na * (nb + 1) * sizeof(c128), hipMemcpyDeviceToHost, s), "copy h");
+        GIEM_HIP(hipMemcpyAsync(chost, ndev, (size_t)na * sizeof(c128), hipMemcpyDeviceToHost, s), "copy norm");
+        GIEM_HIP(hipStreamSynchronize(s), "sync");
+        bool again = false;
+        for (int q = 0; q < na; ++q) {
+          for (int i = 0; i < nb; ++i)
+            hcol[q][i] += cd(hhost[(size_t)q * (nb + 1) + i].x, hhost[(size_t)q * (nb + 1) + i].y);
+          if (pass == 0) nw0[q] = hhost[(size_t)q * (nb + 1) + nb].x;
+          nw1[q] = std::max(chost[q].x, 0.0);
+          if (nw1[q] < 0.49 * nw0[q]) again = true;
+        }
+        if (!again) break;
+        for (int q = 0; q < na; ++q) nw0[q] = nw1[q];
+      }
+      std::vector<int> still;
+      for (int q = 0; q < na; ++q) {
+        const int r = running[q];
+        const double hn = std::sqrt(nw1[q]);
+        std::vector<cd> &Hr = H[r];
+        auto Hc = [&](int i) -> cd & { return Hr[(size_t)i * m + j]; };
+        for (int i = 0; i <= j; ++i) Hc(i) = hcol[q][i];
+        Hc(j + 1) = hn;
+        for (int i = 0; i < j; ++i) {  // earlier rotations
+          const cd a = Hc(i), bb = Hc(i + 1);
+          Hc(i) = cs[r][i] * a + sn[r][i] * bb;
+          Hc(i + 1) = -std::conj(sn[r][i]) * a + cs[r][i] * bb;
+        }
+        const cd a = Hc(j);
+        const double bn = std::abs(Hc(j + 1));
+        const double rr = std::hypot(std::abs(a), bn);
+        cd c, sv;
+        if (std::abs(a) == 0.0) {
+          c = 0.0;
+          sv = 1.0;
+        } else {
+          c = std::abs(a) / rr;
+          sv = (a / std::abs(a)) * std::conj(Hc(j + 1)) / rr;
+        }
+        cs[r][j] = c;
+        sn[r][j] = sv;
+        Hc(j) = c * a + sv * Hc(j + 1);
+        Hc(j + 1) = 0.0;
+        g[r][j + 1] = -std::conj(sv) * g[r][j];
+        g[r][j] = c * g[r][j];
+        jlen[r] = j + 1;
+        const double est = std::abs(g[r][j + 1]);
+        if (hn > 0.0) {
+          const c128 f = mk<double>(1.0 / hn, 0.0);
+          c128 *dst = V(r, j + 1);
+          const c128 *src = V(r, j + 1);
+          GIEM_HIP(launch_scale(&dst, &src, &f, 1, n, s), "scale");
+        }
+        if (est > gp.tol * normb[r] && hn > 0.0) still.push_back(r);
+      }
+      running = still;
+    }
+    // x += V y, y = R^{-1} g (back substitution on the rotated Hessenberg)
+    for (int r : cyc) {
+      const int k = jlen[r];
+      if (k == 0) continue;
+      std::vector<cd> y(k);
+      for (int i = k - 1; i >= 0; --i) {
+        cd acc = g[r][i];
+        for (int l = i + 1; l < k; ++l) acc -= H[r][(size_t)i * m + l] * y[l];
+        y[i] = acc / H[r][(size_t)i * m + i];
+      }
+      c128 *yh = static_cast<c128 *>(t->coef_host);
+      for (int i = 0; i < k; ++i) yh[i] = mk<double>(y[i].real(), y[i].imag());
+      GIEM_HIP(hipMemcpyAsync(t->coef_dev, yh, k * sizeof(c128), hipMemcpyHostToDevice, s), "copy y");
+      LinArgs la{};
+      la.x[0] = x[r];
+      la.basis[0] = V(r, 0);
+      GIEM_HIP(launch_lincomb(la, 1, k, n, static_cast<c128 *>(t->coef_dev), k, s), "lincomb");
+      GIEM_HIP(hipStreamSynchronize(s), "sync");
+    }
+    if (iters >= gp.max_iter) {
+      // final true residual for the report
+      std::vector<int> left;
+      for (int r = 0; r < nrhs; ++r)
+        if (!done[r]) left.push_back(r);
+      if (!left.empty()) {
+        std::vector<const c128 *> in;
+        std::vector<c128 *> out;
+        for (int r : left) {
+          in.push_back(x[r]);
+          out.push_back(V(r, 0));
+        }
+        GIEM_TRY(apply_ptrs(t, ifreq, in, out, gp.mode, gp.prec, s));
+        std::vector<const c128 *> rp;
+        for (int r : left) {
+          GIEM_HIP(launch_axpby(V(r, 0), b[r], V(r, 0), mk<double>(1, 0), mk<double>(-1, 0), n, s), "axpby");
+          rp.push_back(V(r, 0));
+        }
+        std::vector<double> rn;
+        GIEM_TRY(norms_of(t, rp.data(), (int)left.size(), wlev, s, rn));
+        for (size_t q = 0; q < left.size(); ++q) {
+          res.relres[left[q]] = rn[q] / normb[left[q]];
+          if (rn[q] <= gp.tol * normb[left[q]]) done[left[q]] = 1;
+        }
+      }
+      break;
+    }
+  }
+  res.iters = iters;
+  res.converged = true;
+  for (int r = 0; r < nrhs; ++r)
+    if (!done[r]) res.converged = false;
+  return GIEM_OK;
+}
+
+// ------------------------------------------------------------ solve entry
+static int check_sigma_a(giem_handle *t, const void *sigma_a, hipStream_t s) {
+  std::vector<c128> h(t->ncell());
+  GIEM_HIP(hipMemcpyAsync(h.data(), sigma_a, h.size() * sizeof(c128), hipMemcpyDeviceToHost, s),
+           "copy sigma_a");
+  GIEM_HIP(hipStreamSynchronize(s), "sync");
+  for (const c128 &v : h) {
+    if (!std::isfinite(v.x) || !std::isfinite(v.y)) {
+      set_error("sigma_a holds NaN or Inf");
+      return GIEM_EINVAL;
+    }
+    if (v.x < 0.0) {
+      set_error("Re sigma_a must be >= 0");
+      return GIEM_EDOMAIN;
+    }
+  }
+  return GIEM_OK;
+}
+
+static int solve_impl(giem_handle *t, int ifreq, const void *sigma_a, int nrhs, const void *rhs,
+                      void *E_cells, const giem_solve_opts *o, giem_solve_stats *st,
+                      hipStream_t s, unsigned mode) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!t || ifreq < 0 || ifreq >= (int)t->f.size() || nrhs < 1 || nrhs > kMaxRhs || !sigma_a ||
+      !E_cells || !o) {
+    set_error("giem_solve: bad argument");
+    return GIEM_EINVAL;
+  }
+  if (!rhs && nrhs > 2) {
+    set_error("giem_solve: the plane-wave source has two polarisations (nrhs <= 2)");
+    return GIEM_EINVAL;
+  }
+  if (!(o->tol > 0) || o->restart < 1 || o->restart > 64 || o->max_iter < 1 ||
+      (o->precision != PREC_FP64 && o->precision != PREC_FP32)) {
+    set_error("giem_solve: bad options (tol > 0, 1 <= restart <= 64, max_iter >= 1)");
+    return GIEM_EINVAL;
+  }
+  if (o->precision == PREC_FP32 && !t->f[ifreq].spec32) {
+    set_error("giem_solve: the FP32 form needs tables built with GIEM_TABLES_C64");
+    return GIEM_EINVAL;
+  }
+  GIEM_TRY(check_sigma_a(t, sigma_a, s));
+  GIEM_TRY(compute_diagonals(t, static_cast<const c128 *>(sigma_a), s));
+  const size_t n = t->nvec(), nc = t->ncell();
+  // workspace: b, u, residual, correction (nrhs vectors each)
+  GIEM_TRY(ensure_vec_ws(t, (size_t)4 * nrhs));
+  c128 *ws = static_cast<c128 *>(t->vec_ws);
+  c128 *bv = ws, *uv = ws + (size_t)nrhs * n, *dv = ws + (size_t)2 * nrhs * n;
+  c128 *cv = ws + (size_t)3 * nrhs * n;
+  const c128 *acell = static_cast<const c128 *>(t->diag) + 3 * nc;
+  if (rhs) {
+    GIEM_HIP(hipMemcpyAsync(bv, rhs, (size_t)nrhs * n * sizeof(c128), hipMemcpyDeviceToDevice, s), "copy rhs");
+  } else {
+    std::vector<cd> en, hs;
+    plane_wave_levels(t, t->f[ifreq].freq, en, hs);
+    std::vector<c128> enc(t->nz);
+    for (int k = 0; k < t->nz; ++k) enc[k] = mk<double>(en[k].real(), en[k].imag());
+    // stage per-level E^N in the small coefficient buffer
+    if ((size_t)t->nz > (size_t)kMaxRhs * 65) {
+      set_error("Nz too large");
+      return GIEM_EINVAL;
+    }
+    GIEM_HIP(hipMemcpyAsync(t->coef_dev, enc.data(), t->nz * sizeof(c128), hipMemcpyHostToDevice, s), "copy EN");
+    for (int r = 0; r < nrhs; ++r)
+      GIEM_HIP(launch_plane_wave_rhs(static_cast<c128 *>(t->coef_dev), static_cast<double *>(t->sroot_lev),
+                                     t->nx, t->ny, t->nz, r, bv + (size_t)r * n, s), "plane wave");
+    GIEM_HIP(hipStreamSynchronize(s), "sync");
+  }
+  const bool warm = o->warm_start != 0;
+  if (warm) GIEM_HIP(launch_mul_cells(uv, static_cast<const c128 *>(E_cells), acell, nrhs, nc, s), "U = a E");
+  std::vector<const c128 *> bp(nrhs);
+  std::vector<c128 *> up(nrhs), dp(nrhs);
+  for (int r = 0; r < nrhs; ++r) {
+    bp[r] = bv + (size_t)r * n;
+    up[r] = uv + (size_t)r * n;
+    dp[r] = dv + (size_t)r * n;
+  }
+  GmresParams gp;
+  gp.tol = o->tol;
+  gp.m = o->restart;
+  gp.max_iter = o->max_iter;
+  gp.weighted = o->weighted_ip;
+  gp.mode = mode;
+  int rc = GIEM_OK;
+  giem_solve_stats lst{};
+  if (o->precision == PREC_FP64) {
+    gp.prec = PREC_FP64;
+    gp.x_zero = !warm;
+    GmresResult gr;
+    GIEM_TRY(gmres(t, ifreq, nrhs, bp.data(), up.data(), gp, s, gr));
+    lst.iters = gr.iters;
+    lst.outer_iters = gr.restarts;
+    lst.converged = gr.converged;
+    lst.rel_residual = *std::max_element(gr.relres.begin(), gr.relres.end());
+    rc = gr.converged ? GIEM_OK : GIEM_ENOCONV;
+  } else {
+    // refinement: r = b - A64 u (FP64), inner GMRES on A32 d = r, u += d
+    const double *wlev = o->weighted_ip ? static_cast<const double *>(t->vol_lev) : nullptr;
+    std::vector<double> normb, rn;
+    GIEM_TRY(norms_of(t, bp.data(), nrhs, wlev, s, normb));
+    if (!warm)
+      for (int r = 0; r < nrhs; ++r) GIEM_HIP(hipMemsetAsync(up[r], 0, n * sizeof(c128), s), "zero");
+    const int max_outer = o->max_outer > 0 ? o->max_outer : 20;
+    const double itol = o->inner_tol > 0 ? o->inner_tol : 1e-3;
+    std::vector<int> act;
+    int outer = 0, inner_total = 0;
+    double worst = 0.0;
+    bool conv = false;
+    for (outer = 0; outer <= max_outer; ++outer) {
+      // true FP64 residual of all RHS
+      std::vector<const c128 *> in(up.begin(), up.end());
+      GIEM_TRY(apply_ptrs(t, ifreq, in, dp, mode, PREC_FP64, s));
+      for (int r = 0; r < nrhs; ++r)
+        GIEM_HIP(launch_axpby(dp[r], bp[r], dp[r], mk<double>(1, 0), mk<double>(-1, 0), n, s), "axpby");
+      std::vector<const c128 *> dcp(dp.begin(), dp.end());
+      GIEM_TRY(norms_of(t, dcp.data(), nrhs, wlev, s, rn));
+      act.clear();
+      worst = 0.0;
+      for (int r = 0; r < nrhs; ++r) {
+        const double rel = normb[r] > 0 ? rn[r] / normb[r] : 0.0;
+        worst = std::max(worst, rel);
+        if (rel > o->tol) act.push_back(r);
+      }
+      if (act.empty()) {
+        conv = true;
+        break;
+      }
+      if (outer == max_outer || inner_total >= o->max_iter) break;
+      // inner complex64 solve of A d = r for the RHS not yet converged
+      std::vector<const c128 *> rb;
+      std::vector<c128 *> cx;
+      for (int r : act) {
+        rb.push_back(dp[r]);
+        cx.push_back(cv + (size_t)r * n);
+      }
+      GmresParams ip = gp;
+      ip.prec = PREC_FP32;
+      ip.tol = itol;
+      ip.x_zero = true;
+      ip.max_iter = std::max(1, o->max_iter - inner_total);
+      GmresResult gr;
+      GIEM_TRY(gmres(t, ifreq, (int)act.size(), rb.data(), cx.data(), ip, s, gr));
+      inner_total += gr.iters;
+      for (size_t q = 0; q < act.size(); ++q)
+        GIEM_HIP(launch_axpby(up[act[q]], up[act[q]], cx[q], mk<double>(1, 0), mk<double>(1, 0), n, s), "u += d");
+    }
+    lst.iters = inner_total;
+    lst.outer_iters = outer;
+    lst.converged = conv;
+    lst.rel_residual = worst;
+    rc = conv ? GIEM_OK : GIEM_ENOCONV;
+  }
+  // E = U / a
+  GIEM_HIP(launch_div_cells(static_cast<c128 *>(E_cells), uv, acell, nrhs, nc, s), "E = U / a");
+  GIEM_HIP(hipStreamSynchronize(s), "sync");
+  lst.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (st) *st = lst;
+  if (rc == GIEM_ENOCONV) set_error("GMRES reached the iteration limit before the tolerance");
+  return rc;
+}
+
+// Adjoint: lambda = A^{-T} (g / a), then the per-cell sensitivity kernel.
+static int adjoint_impl(giem_handle *t, int ifreq, const void *sigma_a, int nrhs,
+                        const void *adj_src, const void *E_fwd, void *grad,
+                        const giem_solve_opts *o, giem_solve_stats *st, hipStream_t s) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!t || ifreq < 0 || ifreq >= (int)t->f.size() || nrhs < 1 || nrhs > kMaxRhs || !sigma_a ||
+      !adj_src || !E_fwd || !grad || !o || !(o->tol > 0) || o->restart < 1 || o->restart > 64 ||
+      o->max_iter < 1) {
+    set_error("giem_adjoint: bad argument");
+    return GIEM_EINVAL;
+  }
+  GIEM_TRY(check_sigma_a(t, sigma_a, s));
+  GIEM_TRY(compute_diagonals(t, static_cast<const c128 *>(sigma_a), s));
+  const size_t n = t->nvec(), nc = t->ncell();
+  GIEM_TRY(ensure_vec_ws(t, (size_t)4 * nrhs));
+  c128 *ws = static_cast<c128 *>(t->vec_ws);
+  c128 *rhs = ws, *lam = ws + (size_t)nrhs * n, *v = ws + (size_t)2 * nrhs * n,
+       *w = ws + (size_t)3 * nrhs * n;
+  const c128 *dg = static_cast<const c128 *>(t->diag);
+  const c128 *R1 = dg + nc, *acell = dg + 3 * nc;
+  GIEM_HIP(launch_div_cells(rhs, static_cast<const c128 *>(adj_src), acell, nrhs, nc, s), "g / a");
+  std::vector<const c128 *> bp(nrhs);
+  std::vector<c128 *> lp(nrhs);
+  for (int r = 0; r < nrhs; ++r) {
+    bp[r] = rhs + (size_t)r * n;
+    lp[r] = lam + (size_t)r * n;
+  }
+  GmresParams gp;
+  gp.tol = o->tol;
+  gp.m = o->restart;
+  gp.max_iter = o->max_iter;
+  gp.weighted = o->weighted_ip;
+  gp.mode = MODE_AT;
+  gp.prec = PREC_FP64;
+  gp.x_zero = true;
+  GmresResult gr;
+  GIEM_TRY(gmres(t, ifreq, nrhs, bp.data(), lp.data(), gp, s, gr));
+  GIEM_HIP(launch_mul_cells(v, lam, R1, nrhs, nc, s), "R1 lambda");
+  std::vector<const c128 *> in(nrhs);
+  std::vector<c128 *> out(nrhs);
+  for (int r = 0; r < nrhs; ++r) {
+    in[r] = v + (size_t)r * n;
+    out[r] = w + (size_t)r * n;
+  }
+  GIEM_TRY(apply_ptrs(t, ifreq, in, out, MODE_B, PREC_FP64, s));
+  GIEM_HIP(launch_adjoint_grad(static_cast<const c128 *>(sigma_a), static_cast<const c128 *>(t->sb_lev),
+                               acell, static_cast<const c128 *>(adj_src),
+                               static_cast<const c128 *>(E_fwd), lam, w, nrhs, t->nx, t->ny, t->nz,
+                               static_cast<double *>(grad), s),
+           "gradient kernel");
+  GIEM_HIP(hipStreamSynchronize(s), "sync");
+  if (st) {
+    st->iters = gr.iters;
+    st->outer_iters = gr.restarts;
+    st->converged = gr.converged;
+    st->rel_residual = *std::max_element(gr.relres.begin(), gr.relres.end());
+    st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (!gr.converged) {
+    set_error("adjoint GMRES reached the iteration limit before the tolerance");
+    return GIEM_ENOCONV;
+  }
+  return GIEM_OK;
+}
+
+}  // namespace giem
+
+using namespace giem;
+
+extern "C" {
+
+int giem_solve(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs, const void *rhs,
+               void *E_cells, const giem_solve_opts *opts, giem_solve_stats *stats, void *stream) {
+  return solve_impl(t, ifreq, sigma_a, nrhs, rhs, E_cells, opts, stats,
+                    static_cast<hipStream_t>(stream), MODE_A);
+}
+
+int giem_adjoint(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
+                 const void *adj_src, const void *E_fwd, void *grad_log_sigma,
+                 const giem_solve_opts *opts, giem_solve_stats *stats, void *stream) {
+  return adjoint_impl(t, ifreq, sigma_a, nrhs, adj_src, E_fwd, grad_log_sigma, opts, stats,
+                      static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"
+
+extern "C" int giem_fields(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
+                           const void *E_cells, int32_t nrec, const double *rec_xy, void *E_rec,
+                           void *H_rec, void *stream) {
+  (void)t; (void)ifreq; (void)sigma_a; (void)nrhs; (void)E_cells; (void)nrec; (void)rec_xy;
+  (void)E_rec; (void)H_rec; (void)stream;
+  giem::set_error("giem_fields: receiver tables are not available in this build yet");
+  return GIEM_EINVAL;
+}

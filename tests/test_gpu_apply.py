@@ -1,0 +1,90 @@
+"""GPU parity of the operator apply (Sect. 3.3 three-step FFT algorithm) with
+the oracle's O(N^2) dense product on the same packed table."""
+import numpy as np
+import pytest
+
+import giem_synth as gs
+from oracle import dense
+from tests.gpu_util import random_model, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+# (nx, ny, nz, nrhs): single-cell and single-row edge cases, ragged 7-smooth
+# sizes whose padded lengths need radices 3, 5 and 7, the 16 x 16 x 4 grid.
+SHAPES = [(1, 1, 1, 1), (1, 5, 2, 1), (6, 1, 3, 2), (4, 3, 2, 3), (15, 7, 3, 2),
+          (10, 14, 2, 1), (16, 16, 4, 2), (9, 12, 5, 1)]
+
+
+def _case(nx, ny, nz, seed):
+    rng = np.random.default_rng(seed)
+    m = random_model(nx, ny, nz, seed)
+    t = gs.random_packed_table(rng, nx, ny, nz, decay=0.1)
+    return m, t, rng
+
+
+@pytest.mark.parametrize("nx,ny,nz,nrhs", SHAPES)
+@pytest.mark.parametrize("mode", ["B", "A", "AT"])
+def test_apply_fp64_matches_dense(lib, nx, ny, nz, nrhs, mode):
+    import torch
+    m, t, rng = _case(nx, ny, nz, 100 + nx * 7 + ny * 3 + nz)
+    h = lib.tables_import(m, [m["freq"]], t[None])
+    B = dense.dense_from_packed(t, m)
+    d = dense.cie_diagonals(m)
+    x = gs.random_vector(rng, nrhs, nz, ny, nx)
+    ref = dense.apply_direct(B, d, x, mode)
+    xd = to_dev(x)
+    yd = torch.empty_like(xd)
+    sa = to_dev(m["sigma_a"])
+    code = {"A": lib.MODE_A, "AT": lib.MODE_AT, "B": lib.MODE_B}[mode]
+    h.apply(xd, yd, sa, mode=code)
+    torch.cuda.synchronize()
+    err = rel_err(yd.cpu().numpy(), ref)
+    assert err <= 1e-10, err
+    h.close()
+
+
+@pytest.mark.parametrize("nx,ny,nz,nrhs", [(15, 7, 3, 2), (16, 16, 4, 2)])
+def test_apply_fp32_error(lib, nx, ny, nz, nrhs):
+    import torch
+    m, t, rng = _case(nx, ny, nz, 7)
+    h = lib.tables_import(m, [m["freq"]], t[None], flags=lib.TABLES_C64)
+    B = dense.dense_from_packed(t, m)
+    d = dense.cie_diagonals(m)
+    x = gs.random_vector(rng, nrhs, nz, ny, nx)
+    ref = dense.apply_direct(B, d, x, "B")
+    xd = to_dev(x)
+    yd = torch.empty_like(xd)
+    h.apply(xd, yd, None, mode=lib.MODE_B, prec=lib.FP32)
+    torch.cuda.synchronize()
+    err = rel_err(yd.cpu().numpy(), ref)
+    # complex64 FFTs and FP32 accumulation: a few units of 1e-7 per term
+    assert err <= 2e-5, err
+    h.close()
+
+
+def test_table_bytes_is_packed_size(lib):
+    m, t, _ = _case(6, 5, 3, 3)
+    h = lib.tables_import(m, [m["freq"]], t[None], flags=lib.TABLES_C64)
+    b128, b64 = h.table_bytes()
+    assert b128 == 7 * 6 * 2 * 3 * 7 * 16 and b64 == b128 // 2
+    h.close()
+
+
+def test_export_roundtrip(lib):
+    m, t, _ = _case(5, 4, 2, 4)
+    h = lib.tables_import(m, [m["freq"]], t[None])
+    assert np.array_equal(h.export(0), t)
+    h.close()
+
+
+def test_rejects_non_smooth_sizes_and_bad_models(lib):
+    m, t, _ = _case(11, 4, 2, 5)
+    with pytest.raises(lib.GiemError):
+        lib.tables_import(m, [m["freq"]], t[None])
+    m2, t2, _ = _case(4, 4, 2, 6)
+    m2 = dict(m2)
+    m2["z_edges"] = np.array([0.0, 150.0, 300.0])  # second interface at 100: straddles
+    m2["d"] = np.array([0.0, 100.0, 5000.0])
+    with pytest.raises(lib.GiemError) as e:
+        lib.tables_import(m2, [1.0], t2[None])
+    assert e.value.code == lib.GIEM_EDOMAIN

@@ -1,0 +1,152 @@
+"""GPU parity of the GMRES solve (Sect. 2.2 system, Sect. 3.3 solver) with the
+oracle's dense LU on the same packed table, the precision form, the adjoint
+gradient, and the failure paths."""
+import numpy as np
+import pytest
+
+import giem_synth as gs
+from oracle import dense, normal_field
+from tests.gpu_util import random_model, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _conditioned_case(nx, ny, nz, seed, contrast=2.0):
+    """Random packed table scaled so that ||R1 B R2|| is about 0.3."""
+    rng = np.random.default_rng(seed)
+    m = random_model(nx, ny, nz, seed, contrast=contrast)
+    t = gs.random_packed_table(rng, nx, ny, nz, decay=0.2)
+    d = dense.cie_diagonals(m)
+    n3 = 3 * nx * ny * nz
+    scale = 0.3 / (np.abs(d["R1"]).max() * np.abs(d["R2"]).max() * 2 * np.sqrt(n3))
+    return m, t * scale, rng
+
+
+def _oracle_E(m, t, rhs_u):
+    B = dense.dense_from_packed(t, m)
+    d = dense.cie_diagonals(m)
+    A = dense.system_matrix(B, d)
+    u = dense.solve_lu(A, rhs_u)
+    a = d["a"][None, None]
+    return u / a
+
+
+@pytest.mark.parametrize("nx,ny,nz", [(4, 3, 2), (15, 7, 3), (16, 16, 4)])
+def test_solve_fp64_matches_lu(lib, nx, ny, nz):
+    import torch
+    m, t, rng = _conditioned_case(nx, ny, nz, 11 + nx)
+    rhs = gs.random_vector(rng, 2, nz, ny, nx)
+    ref = _oracle_E(m, t, rhs)
+    h = lib.tables_import(m, [m["freq"]], t[None])
+    E = torch.empty((2, 3, nz, ny, nx), dtype=torch.complex128, device="cuda")
+    st = h.solve(to_dev(m["sigma_a"]), E, rhs=to_dev(rhs), tol=1e-13, restart=30, max_iter=3000)
+    assert st["converged"] == 1, st
+    err = rel_err(E.cpu().numpy(), ref)
+    assert err <= 1e-10, (err, st)
+    h.close()
+
+
+def test_plane_wave_rhs_matches_oracle(lib):
+    import torch
+    nx, ny, nz = 8, 6, 3
+    m, t, _ = _conditioned_case(nx, ny, nz, 5)
+    ref = _oracle_E(m, t, normal_field.plane_wave_rhs(m))
+    h = lib.tables_import(m, [m["freq"]], t[None])
+    E = torch.empty((2, 3, nz, ny, nx), dtype=torch.complex128, device="cuda")
+    st = h.solve(to_dev(m["sigma_a"]), E, tol=1e-13)
+    assert st["converged"] == 1
+    assert rel_err(E.cpu().numpy(), ref) <= 1e-10
+    h.close()
+
+
+def test_no_anomaly_returns_normal_field(lib):
+    import torch
+    nx, ny, nz = 6, 5, 3
+    m, t, _ = _conditioned_case(nx, ny, nz, 6)
+    sb = dense.cell_layer_sigma(m)[:, None, None] * np.ones((nz, ny, nx))
+    h = lib.tables_import(m, [m["freq"]], t[None])
+    E = torch.empty((2, 3, nz, ny, nx), dtype=torch.complex128, device="cuda")
+    st = h.solve(to_dev(sb.astype(np.complex128)), E, tol=1e-12)
+    en = normal_field.normal_field_cells(m)
+    assert st["converged"] == 1 and st["iters"] <= 1
+    assert rel_err(E.cpu().numpy(), en) <= 1e-14
+    h.close()
+
+
+def test_precision_form_refines_to_fp64(lib):
+    import torch
+    nx, ny, nz = 15, 7, 3
+    m, t, rng = _conditioned_case(nx, ny, nz, 9, contrast=3.0)
+    rhs = gs.random_vector(rng, 2, nz, ny, nx)
+    ref = _oracle_E(m, t, rhs)
+    h = lib.tables_import(m, [m["freq"]], t[None], flags=lib.TABLES_C64)
+    E = torch.empty((2, 3, nz, ny, nx), dtype=torch.complex128, device="cuda")
+    st = h.solve(to_dev(m["sigma_a"]), E, rhs=to_dev(rhs), tol=1e-10, precision=lib.FP32,
+                 inner_tol=1e-4, max_iter=5000)
+    assert st["converged"] == 1, st
+    assert rel_err(E.cpu().numpy(), ref) <= 1e-8, st
+    h.close()
+
+
+def test_warm_start_and_weighted_product(lib):
+    import torch
+    nx, ny, nz = 8, 6, 3
+    m, t, rng = _conditioned_case(nx, ny, nz, 12)
+    rhs = gs.random_vector(rng, 1, nz, ny, nx)
+    ref = _oracle_E(m, t, rhs)
+    h = lib.tables_import(m, [m["freq"]], t[None])
+    E = to_dev(ref * (1 + 1e-3))
+    st = h.solve(to_dev(m["sigma_a"]), E, rhs=to_dev(rhs), tol=1e-13, warm_start=1, weighted_ip=1)
+    assert st["converged"] == 1
+    assert rel_err(E.cpu().numpy(), ref) <= 1e-10
+    h.close()
+
+
+def test_iteration_limit_reports_noconv(lib):
+    import torch
+    nx, ny, nz = 8, 6, 3
+    m, t, rng = _conditioned_case(nx, ny, nz, 13, contrast=3.0)
+    h = lib.tables_import(m, [m["freq"]], t[None])
+    E = torch.empty((1, 3, nz, ny, nx), dtype=torch.complex128, device="cuda")
+    rhs = to_dev(gs.random_vector(rng, 1, nz, ny, nx))
+    st = h.solve(to_dev(m["sigma_a"]), E, rhs=rhs, tol=1e-15, max_iter=2, restart=2)
+    assert st["rc"] == lib.GIEM_ENOCONV and st["converged"] == 0
+    assert np.isfinite(E.cpu().numpy()).all()
+    h.close()
+
+
+def test_invalid_sigma_rejected(lib):
+    import torch
+    nx, ny, nz = 4, 3, 2
+    m, t, _ = _conditioned_case(nx, ny, nz, 14)
+    h = lib.tables_import(m, [m["freq"]], t[None])
+    E = torch.empty((1, 3, nz, ny, nx), dtype=torch.complex128, device="cuda")
+    sa = m["sigma_a"].copy()
+    sa[0, 0, 0] = np.nan
+    with pytest.raises(lib.GiemError) as e:
+        h.solve(to_dev(sa), E)
+    assert e.value.code == lib.GIEM_EINVAL
+    sa = m["sigma_a"].copy()
+    sa[1, 1, 1] = -1.0
+    with pytest.raises(lib.GiemError) as e:
+        h.solve(to_dev(sa), E)
+    assert e.value.code == lib.GIEM_EDOMAIN
+    h.close()
+
+
+def test_adjoint_gradient_matches_oracle(lib):
+    import torch
+    nx, ny, nz = 6, 5, 3
+    m, t, rng = _conditioned_case(nx, ny, nz, 15)
+    g = gs.random_vector(rng, 2, nz, ny, nx)
+    ref = dense.gradient_log_sigma(dense.dense_from_packed(t, m), m, g,
+                                   normal_field.normal_field_cells(m))
+    h = lib.tables_import(m, [m["freq"]], t[None])
+    sa = to_dev(m["sigma_a"])
+    E = torch.empty((2, 3, nz, ny, nx), dtype=torch.complex128, device="cuda")
+    h.solve(sa, E, tol=1e-13)
+    grad = torch.zeros((nz, ny, nx), dtype=torch.float64, device="cuda")
+    st = h.adjoint(sa, to_dev(g), E, grad, tol=1e-13)
+    assert st["converged"] == 1
+    assert rel_err(grad.cpu().numpy(), ref) <= 1e-9
+    h.close()

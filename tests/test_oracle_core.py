@@ -167,3 +167,21 @@ def test_cell_average_vs_quadrature():
         zz = 0.5 * (z2 - z1) * x + 0.5 * (z1 + z2)
         q = 0.5 * np.sum(w * np.array([pw.E(v) for v in zz]))
         assert abs(pw.cell_average(z1, z2) - q) < 1e-13
+
+
+def test_oracle_adjoint_gradient_vs_finite_differences():
+    m = _small_model(seed=21, nx=3, ny=2, nz=3)
+    rng = np.random.default_rng(22)
+    t = gs.random_packed_table(rng, m["nx"], m["ny"], m["nz"], scale=3e4)
+    B = dense.dense_from_packed(t, m)
+    g = gs.random_vector(rng, 2, m["nz"], m["ny"], m["nx"])
+    en = normal_field.normal_field_cells(m)
+    grad = dense.gradient_log_sigma(B, m, g, en)
+    h = 1e-6
+    sa = m["sigma_a"]
+    for idx in [(0, 0, 0), (1, 1, 2), (2, 0, 1)]:
+        sp, sm = sa.copy(), sa.copy()
+        sp[idx] *= np.exp(h)
+        sm[idx] *= np.exp(-h)
+        fd = (dense.objective(B, m, g, en, sp) - dense.objective(B, m, g, en, sm)) / (2 * h)
+        assert abs(fd - grad[idx]) <= 1e-6 * np.abs(grad).max() + 1e-5 * abs(fd), (idx, fd, grad[idx])
