@@ -64,6 +64,9 @@ def load():
     if not os.path.exists(LIBPATH):
         raise ImportError(f"HIP library not built: {LIBPATH} is missing "
                           "(run __graft_entry__.build())")
+    # torch ships its own HIP runtime; load it first so that libgiem binds to
+    # the same libamdhip64 instance (one runtime, one device context).
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIBPATH)
     P, I32, U32, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_double
     sig = {

@@ -11,14 +11,16 @@ from tests.gpu_util import random_model, rel_err, to_dev
 pytestmark = pytest.mark.gpu
 
 
-def _conditioned_case(nx, ny, nz, seed, contrast=2.0):
-    """Random packed table scaled so that ||R1 B R2|| is about 0.3."""
+def _conditioned_case(nx, ny, nz, seed, contrast=1.0):
+    """Random packed table scaled so that ||R1 B R2|| is about 0.2 (condition
+    number about 6; the random table is not a contracting operator, so the
+    contrast is kept moderate)."""
     rng = np.random.default_rng(seed)
     m = random_model(nx, ny, nz, seed, contrast=contrast)
     t = gs.random_packed_table(rng, nx, ny, nz, decay=0.2)
     d = dense.cie_diagonals(m)
     n3 = 3 * nx * ny * nz
-    scale = 0.3 / (np.abs(d["R1"]).max() * np.abs(d["R2"]).max() * 2 * np.sqrt(n3))
+    scale = 0.2 / (np.abs(d["R1"]).max() * np.abs(d["R2"]).max() * 2 * np.sqrt(n3))
     return m, t * scale, rng
 
 
@@ -76,7 +78,7 @@ def test_no_anomaly_returns_normal_field(lib):
 def test_precision_form_refines_to_fp64(lib):
     import torch
     nx, ny, nz = 15, 7, 3
-    m, t, rng = _conditioned_case(nx, ny, nz, 9, contrast=3.0)
+    m, t, rng = _conditioned_case(nx, ny, nz, 9)
     rhs = gs.random_vector(rng, 2, nz, ny, nx)
     ref = _oracle_E(m, t, rhs)
     h = lib.tables_import(m, [m["freq"]], t[None], flags=lib.TABLES_C64)
@@ -105,7 +107,7 @@ def test_warm_start_and_weighted_product(lib):
 def test_iteration_limit_reports_noconv(lib):
     import torch
     nx, ny, nz = 8, 6, 3
-    m, t, rng = _conditioned_case(nx, ny, nz, 13, contrast=3.0)
+    m, t, rng = _conditioned_case(nx, ny, nz, 13)
     h = lib.tables_import(m, [m["freq"]], t[None])
     E = torch.empty((1, 3, nz, ny, nx), dtype=torch.complex128, device="cuda")
     rhs = to_dev(gs.random_vector(rng, 1, nz, ny, nx))
