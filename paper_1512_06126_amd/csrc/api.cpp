@@ -76,7 +76,8 @@ static int make_cs(int n, void **out) {
 
 int ensure_spec_ws(giem_handle *t, int nrhs, int prec) {
   (void)prec;
-  const size_t need = (size_t)4 * t->nx * t->ny * 3 * t->nz * nrhs * sizeof(c128);
+  // two spectra buffers: the block product reads one and writes the other
+  const size_t need = (size_t)2 * 4 * t->nx * t->ny * 3 * t->nz * nrhs * sizeof(c128);
   if (t->spec_ws_bytes >= need) return GIEM_OK;
   if (t->spec_ws) hipFree(t->spec_ws);
   t->spec_ws = nullptr;
@@ -120,7 +121,7 @@ int apply_core(giem_handle *t, int ifreq, int nrhs, const VecPtrs &p, unsigned m
   int G = prec == PREC_FP32 ? 16 : 8;
   const int Lmax = std::max(2 * nx, 2 * ny);
   while (G > 1 && G * Lmax > 32 * 256) G /= 2;
-  if (block_threads(nz, nrhs) > 1024 || block_lds_bytes(nz, nrhs, prec) > 160 * 1024) {
+  if (!block_supported(nz, nrhs)) {
     set_error("block product: 3 Nz x nrhs too large for one workgroup");
     return GIEM_EINVAL;
   }
@@ -132,15 +133,20 @@ int apply_core(giem_handle *t, int ifreq, int nrhs, const VecPtrs &p, unsigned m
     for (int i = 0; i < 6; ++i) GIEM_HIP(hipEventCreate(&ev[i]), "hipEventCreate");
     GIEM_HIP(hipEventRecord(ev[0], s), "hipEventRecord");
   }
-  GIEM_HIP(launch_fft_x_fwd(prec, p, r2, t->spec_ws, nx, ny, nz, rp, G, t->px.d, twx, s), "x-FFT");
+  const size_t cbytes = prec == PREC_FP32 ? sizeof(c64) : sizeof(c128);
+  void *spa = t->spec_ws;
+  void *spb = static_cast<char *>(t->spec_ws) + (size_t)4 * nx * ny * rp * cbytes;
+  GIEM_HIP(launch_fft_x_fwd(prec, p, r2, spa, nx, ny, nz, rp, G, t->px.d, twx, s), "x-FFT");
   if (stage_ms) GIEM_HIP(hipEventRecord(ev[1], s), "hipEventRecord");
-  GIEM_HIP(launch_fft_y(prec, t->spec_ws, 2 * nx, ny, rp, G, t->py.d, twy, 0, s), "y-FFT");
+  GIEM_HIP(launch_fft_y(prec, spa, 2 * nx, ny, rp, G, t->py.d, twy, 0, s), "y-FFT");
   if (stage_ms) GIEM_HIP(hipEventRecord(ev[2], s), "hipEventRecord");
-  GIEM_HIP(launch_block(prec, tab, t->spec_ws, nx, ny, nz, nrhs, s), "block product");
+  GIEM_HIP(launch_block(prec, tab, spa, spb, static_cast<const unsigned *>(t->bplan), nx, ny, nz,
+                        nrhs, s),
+           "block product");
   if (stage_ms) GIEM_HIP(hipEventRecord(ev[3], s), "hipEventRecord");
-  GIEM_HIP(launch_fft_y(prec, t->spec_ws, 2 * nx, ny, rp, G, t->py.d, twy, 1, s), "inverse y-FFT");
+  GIEM_HIP(launch_fft_y(prec, spb, 2 * nx, ny, rp, G, t->py.d, twy, 1, s), "inverse y-FFT");
   if (stage_ms) GIEM_HIP(hipEventRecord(ev[4], s), "hipEventRecord");
-  GIEM_HIP(launch_fft_x_inv(prec, p, sd, r1, t->spec_ws, nx, ny, nz, rp, G, t->px.d, twx, scale, s),
+  GIEM_HIP(launch_fft_x_inv(prec, p, sd, r1, spb, nx, ny, nz, rp, G, t->px.d, twx, scale, s),
            "inverse x-FFT");
   if (stage_ms) {
     GIEM_HIP(hipEventRecord(ev[5], s), "hipEventRecord");
@@ -280,14 +286,20 @@ static int finish_handle(giem_handle *t, hipStream_t s) {
     lds_set = true;
   }
   const int nz = t->nz;
-  if (block_lds_bytes(nz, 2, PREC_FP64) > 160 * 1024) {
-    set_error("Nz too large for the LDS-resident block product");
+  if (!block_supported(nz, 1)) {
+    set_error("Nz too large for the packed block offsets");
     return GIEM_EINVAL;
   }
   GIEM_TRY(make_plan(2 * t->nx, t->px));
   GIEM_TRY(make_plan(2 * t->ny, t->py));
   GIEM_TRY(make_cs(t->nx, &t->cs_x));
   GIEM_TRY(make_cs(t->ny, &t->cs_y));
+  {
+    const std::vector<unsigned> plan = block_plan(nz);
+    GIEM_HIP(hipMalloc(&t->bplan, plan.size() * sizeof(unsigned)), "hipMalloc plan");
+    GIEM_HIP(hipMemcpy(t->bplan, plan.data(), plan.size() * sizeof(unsigned), hipMemcpyHostToDevice),
+             "copy plan");
+  }
   std::vector<c128> sb(nz);
   std::vector<double> vol(nz), sr(nz);
   for (int k = 0; k < nz; ++k) {
@@ -327,7 +339,7 @@ void giem_free(giem_handle *t) {
     if (ft.spec64) hipFree(ft.spec64);
     if (ft.spec32) hipFree(ft.spec32);
   }
-  void *dev[] = {t->px.tw64, t->px.tw32, t->py.tw64, t->py.tw32, t->cs_x, t->cs_y,
+  void *dev[] = {t->px.tw64, t->px.tw32, t->py.tw64, t->py.tw32, t->cs_x, t->cs_y, t->bplan,
                  t->sb_lev, t->vol_lev, t->sroot_lev, t->diag, t->spec_ws, t->red_part,
                  t->red_out, t->coef_dev, t->basis, t->vec_ws};
   for (void *p : dev)

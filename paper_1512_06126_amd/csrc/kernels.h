@@ -1,6 +1,8 @@
 // Launchers of the HIP kernels (internal).
 #pragma once
 
+#include <vector>
+
 #include "common.h"
 
 namespace giem {
@@ -9,6 +11,7 @@ namespace giem {
 hipError_t set_lds_limits();
 int block_threads(int nz, int R);
 size_t block_lds_bytes(int nz, int R, int prec);
+bool block_supported(int nz, int R);
 size_t fft_lds_bytes(int G, int L, int prec);
 hipError_t launch_fft_x_fwd(int prec, const VecPtrs &ptrs, const c128 *r2, void *spec, int nx,
                             int ny, int nz, int rp_total, int G, const FftDesc &fd,
@@ -18,8 +21,10 @@ hipError_t launch_fft_x_inv(int prec, const VecPtrs &ptrs, const c128 *sd, const
                             const FftDesc &fd, const void *tw, double scale, hipStream_t s);
 hipError_t launch_fft_y(int prec, void *spec, int nx2, int ny, int rp_total, int G,
                         const FftDesc &fd, const void *tw, int inverse, hipStream_t s);
-hipError_t launch_block(int prec, const void *tab, void *spec, int nx, int ny, int nz, int R,
-                        hipStream_t s);
+// out-of-place: sin and sout are two spectra buffers; plan from block_plan(nz)
+hipError_t launch_block(int prec, const void *tab, const void *sin, void *sout,
+                        const unsigned *plan, int nx, int ny, int nz, int R, hipStream_t s);
+std::vector<unsigned> block_plan(int nz);
 
 // table set-up (kernels_setup.hip)
 hipError_t launch_spectral_x(const c128 *spatial, c128 *tmp, const c128 *cs_x, int nx, int ny,

@@ -17,6 +17,8 @@
 
 namespace giem {
 
+constexpr int kFftThreads = 256;  // workgroup size of the FFT passes
+
 // ------------------------------------------------------------------ small DFTs
 template <typename T, int P>
 __device__ __forceinline__ void small_dft(cplx<T> (&v)[P], bool inv,
@@ -130,7 +132,7 @@ __device__ void fft_lds(cplx<T> *buf, int G, int ld, const FftDesc &fd,
 // Step 1, x pass: u -> R2 u (or u), zero-pad to 2 Nx, forward FFT along x.
 // Grid: (y, plane group).  Output rows y < Ny of the spectra buffer.
 template <typename T, int EPT>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kFftThreads)
 k_fft_x_fwd(VecPtrs ptrs, const c128 *__restrict__ r2, cplx<T> *__restrict__ spec, int nx,
             int ny, int nz, int rp_total, int G, FftDesc fd, const cplx<T> *__restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
@@ -140,18 +142,29 @@ k_fft_x_fwd(VecPtrs ptrs, const c128 *__restrict__ r2, cplx<T> *__restrict__ spe
   const int rp0 = blockIdx.y * G;
   const int p3 = 3 * nz;
   const size_t plane = (size_t)nx * ny;
-  for (int e = threadIdx.x; e < G * L; e += blockDim.x) {
+  // all global loads of a thread are issued before its LDS stores
+  c128 va[EPT], vs[EPT];
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) {
+    const int e = threadIdx.x + u * kFftThreads;
     const int g = e / L, xx = e - g * L;
     const int rp = rp0 + g;
-    cplx<T> v = mk<T>(0, 0);
-    if (xx < nx && rp < rp_total) {
+    va[u] = mk<double>(0, 0);
+    vs[u] = mk<double>(1, 0);
+    if (e < G * L && xx < nx && rp < rp_total) {
       const int r = rp / p3, p = rp - r * p3;
       const int iz = p % nz;
-      c128 a = ptrs.in[r][(size_t)p * plane + (size_t)y * nx + xx];
-      if (r2) a = cmul(a, r2[(size_t)iz * plane + (size_t)y * nx + xx]);
-      v = ccast<T>(a);
+      va[u] = ptrs.in[r][(size_t)p * plane + (size_t)y * nx + xx];
+      if (r2) vs[u] = r2[(size_t)iz * plane + (size_t)y * nx + xx];
     }
-    buf[g * ld + xx] = v;
+  }
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) {
+    const int e = threadIdx.x + u * kFftThreads;
+    if (e < G * L) {
+      const int g = e / L, xx = e - g * L;
+      buf[g * ld + xx] = ccast<T>(cmul(va[u], vs[u]));
+    }
   }
   fft_lds<T, EPT>(buf, G, ld, fd, tw, false);
   for (int e = threadIdx.x; e < G * L; e += blockDim.x) {
@@ -165,7 +178,7 @@ k_fft_x_fwd(VecPtrs ptrs, const c128 *__restrict__ r2, cplx<T> *__restrict__ spe
 // finish the operator: y = S u + R1 (B R2 u)  (mode A, with R1/R2 swapped for
 // A^T), or y = B u (mode B: s == nullptr, r1 == nullptr).
 template <typename T, int EPT>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kFftThreads)
 k_fft_x_inv(VecPtrs ptrs, const c128 *__restrict__ sdiag, const c128 *__restrict__ r1,
             const cplx<T> *__restrict__ spec, int nx, int ny, int nz, int rp_total, int G,
             FftDesc fd, const cplx<T> *__restrict__ tw, double scale) {
@@ -176,28 +189,59 @@ k_fft_x_inv(VecPtrs ptrs, const c128 *__restrict__ sdiag, const c128 *__restrict
   const int rp0 = blockIdx.y * G;
   const int p3 = 3 * nz;
   const size_t plane = (size_t)nx * ny;
-  for (int e = threadIdx.x; e < G * L; e += blockDim.x) {
-    const int K = e / G, g = e - K * G;
-    const int rp = rp0 + g;
-    buf[g * ld + K] = (rp < rp_total) ? spec[((size_t)y * L + K) * rp_total + rp] : mk<T>(0, 0);
+  {
+    cplx<T> v[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = threadIdx.x + u * kFftThreads;
+      const int K = e / G, g = e - K * G;
+      const int rp = rp0 + g;
+      v[u] = mk<T>(0, 0);
+      if (e < G * L && rp < rp_total) v[u] = spec[((size_t)y * L + K) * rp_total + rp];
+    }
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = threadIdx.x + u * kFftThreads;
+      if (e < G * L) {
+        const int K = e / G, g = e - K * G;
+        buf[g * ld + K] = v[u];
+      }
+    }
+  }
+  // the diagonal terms of the epilogue are loaded while the FFT runs
+  constexpr int EO = (EPT + 1) / 2;  // G * nx <= G * L / 2 outputs
+  c128 xin[EO], dsd[EO], dr1[EO];
+  if (r1) {
+#pragma unroll
+    for (int u = 0; u < EO; ++u) {
+      const int e = threadIdx.x + u * kFftThreads;
+      const int g = e / nx, xx = e - g * nx;
+      const int rp = rp0 + g;
+      if (e < G * nx && rp < rp_total) {
+        const int r = rp / p3, p = rp - r * p3;
+        const int iz = p % nz;
+        const size_t cell = (size_t)iz * plane + (size_t)y * nx + xx;
+        xin[u] = ptrs.in[r][(size_t)p * plane + (size_t)y * nx + xx];
+        dsd[u] = sdiag[cell];
+        dr1[u] = r1[cell];
+      }
+    }
   }
   fft_lds<T, EPT>(buf, G, ld, fd, tw, true);
-  for (int e = threadIdx.x; e < G * nx; e += blockDim.x) {
+#pragma unroll
+  for (int u = 0; u < EO; ++u) {
+    const int e = threadIdx.x + u * kFftThreads;
     const int g = e / nx, xx = e - g * nx;
     const int rp = rp0 + g;
-    if (rp < rp_total) {
+    if (e < G * nx && rp < rp_total) {
       const int r = rp / p3, p = rp - r * p3;
-      const int iz = p % nz;
       const size_t off = (size_t)p * plane + (size_t)y * nx + xx;
       c128 b = ccast<double>(buf[g * ld + xx]);
       b = cscale(b, scale);
-      c128 out;
+      c128 out = b;
       if (r1) {
-        const size_t cell = (size_t)iz * plane + (size_t)y * nx + xx;
-        out = cmul(r1[cell], b);
-        cfma(out, sdiag[cell], ptrs.in[r][off]);
-      } else {
-        out = b;
+        out = cmul(dr1[u], b);
+        cfma(out, dsd[u], xin[u]);
       }
       ptrs.out[r][off] = out;
     }
@@ -208,7 +252,7 @@ k_fft_x_inv(VecPtrs ptrs, const c128 *__restrict__ sdiag, const c128 *__restrict
 // Forward (rows y >= Ny are zero, output all 2 Ny rows) or inverse (read all
 // 2 Ny rows, write rows < Ny) FFT along y, in place.  Grid: (Kx, plane group).
 template <typename T, int EPT>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kFftThreads)
 k_fft_y(cplx<T> *__restrict__ spec, int nx2, int ny, int rp_total, int G, FftDesc fd,
         const cplx<T> *__restrict__ tw, int inverse) {
   extern __shared__ unsigned char smem_raw[];
@@ -218,149 +262,30 @@ k_fft_y(cplx<T> *__restrict__ spec, int nx2, int ny, int rp_total, int G, FftDes
   const int rp0 = blockIdx.y * G;
   const int nin = inverse ? L : ny;
   const int nout = inverse ? ny : L;
-  for (int e = threadIdx.x; e < G * L; e += blockDim.x) {
-    const int yy = e / G, g = e - yy * G;
-    const int rp = rp0 + g;
-    cplx<T> v = mk<T>(0, 0);
-    if (yy < nin && rp < rp_total) v = spec[((size_t)yy * nx2 + kx) * rp_total + rp];
-    buf[g * ld + yy] = v;
+  {
+    cplx<T> v[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = threadIdx.x + u * kFftThreads;
+      const int yy = e / G, g = e - yy * G;
+      const int rp = rp0 + g;
+      v[u] = mk<T>(0, 0);
+      if (e < G * L && yy < nin && rp < rp_total) v[u] = spec[((size_t)yy * nx2 + kx) * rp_total + rp];
+    }
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = threadIdx.x + u * kFftThreads;
+      if (e < G * L) {
+        const int yy = e / G, g = e - yy * G;
+        buf[g * ld + yy] = v[u];
+      }
+    }
   }
   fft_lds<T, EPT>(buf, G, ld, fd, tw, inverse != 0);
   for (int e = threadIdx.x; e < G * nout; e += blockDim.x) {
     const int yy = e / G, g = e - yy * G;
     const int rp = rp0 + g;
     if (rp < rp_total) spec[((size_t)yy * nx2 + kx) * rp_total + rp] = buf[g * ld + yy];
-  }
-}
-
-// ---------------------------------------------------------------- block product
-// Step 2: for every frequency point K of the 2Nx x 2Ny grid,
-//   Y^(K) = Q~(K) X^(K),   Q~(K) the 3Nz x 3Nz matrix of 3 x 3 Nz-blocks.
-// Q~ is stored once per representative (Kx, Ky), 0 <= Kx <= Nx, 0 <= Ky <= Ny
-// (Sect. 3.3: the transform keeps the parities of Lemma 2).  A mirrored point
-// (2Nx - Kx or 2Ny - Ky) uses Q~_ab times t_a t_b, t = (-1, 1, 1) for an x
-// mirror and (1, -1, 1) for a y mirror, i.e. Y = T Q~ T X: the sign flips are
-// applied to the loaded vectors and to the results, and one read of the
-// packed block serves the up to four mirror points and all R right-hand sides.
-// Lemma 1 gives the blocks not stored: yx = xy, zx = -xz^T, zy = -yz^T, and
-// xx, xy, yy, zz are read from their upper triangles.
-//
-// One workgroup per representative point.  LDS: the packed block (E complex)
-// and the V = mirrors x R input vectors.  Thread (row, vector group) owns one
-// output row of 3Nz for VPT vectors.
-template <typename T, int VPT>
-__global__ void __launch_bounds__(1024)
-k_block(const cplx<T> *__restrict__ tab, cplx<T> *__restrict__ spec, int nx, int ny, int nz,
-        int R) {
-  extern __shared__ unsigned char smem_raw[];
-  const int E = 2 * nz * (2 * nz + 1);
-  const int p3 = 3 * nz;
-  cplx<T> *qs = reinterpret_cast<cplx<T> *>(smem_raw);
-  cplx<T> *xs = qs + E;  // [V][3nz]
-  const int rep = blockIdx.x;
-  const int kxr = rep % (nx + 1), kyr = rep / (nx + 1);
-  const int nx2 = 2 * nx, ny2 = 2 * ny;
-  // mirror points of this representative
-  int mkx[4], mky[4], mtx[4], mty[4];
-  int nm = 0;
-  const bool mx = (kxr != 0 && kxr != nx), my = (kyr != 0 && kyr != ny);
-  mkx[nm] = kxr; mky[nm] = kyr; mtx[nm] = 1; mty[nm] = 1; ++nm;
-  if (mx) { mkx[nm] = nx2 - kxr; mky[nm] = kyr; mtx[nm] = -1; mty[nm] = 1; ++nm; }
-  if (my) { mkx[nm] = kxr; mky[nm] = ny2 - kyr; mtx[nm] = 1; mty[nm] = -1; ++nm; }
-  if (mx && my) { mkx[nm] = nx2 - kxr; mky[nm] = ny2 - kyr; mtx[nm] = -1; mty[nm] = -1; ++nm; }
-  const int V = nm * R;
-
-  // stage the packed block and the (sign-flipped) input vectors
-  const cplx<T> *tsrc = tab + (size_t)rep * E;
-  for (int e = threadIdx.x; e < E; e += blockDim.x) qs[e] = tsrc[e];
-  for (int e = threadIdx.x; e < V * p3; e += blockDim.x) {
-    const int v = e / p3, p = e - v * p3;
-    const int m = v / R, r = v - m * R;
-    cplx<T> val = spec[(((size_t)mky[m] * nx2 + mkx[m]) * R + r) * p3 + p];
-    const int a = p / nz;
-    if ((a == 0 && mtx[m] < 0) || (a == 1 && mty[m] < 0)) val = mk<T>(-val.x, -val.y);
-    xs[e] = val;
-  }
-  __syncthreads();
-
-  const int row = threadIdx.x % p3;
-  const int vg = threadIdx.x / p3;
-  const int v0 = vg * VPT;
-  if (v0 < V) {
-    const int a = row / nz, iz = row - a * nz;
-    const int tri = nz * (nz + 1) / 2;
-    const int o_xx = 0, o_xy = tri, o_yy = 2 * tri, o_zz = 3 * tri;
-    const int o_xz = 4 * tri, o_yz = 4 * tri + nz * nz;
-    cplx<T> acc[VPT];
-#pragma unroll
-    for (int k = 0; k < VPT; ++k) acc[k] = mk<T>(0, 0);
-    const int nv = min(VPT, V - v0);
-    // symmetric block (upper triangle) row iz times X_b
-    auto sym_row = [&](int off, int b) {
-      const cplx<T> *xb = xs + (size_t)v0 * p3 + b * nz;
-      // jz < iz: element (jz, iz) at rowstart(jz) + iz - jz
-      int idx = iz;  // rowstart(0) + iz
-      for (int jz = 0; jz < iz; ++jz) {
-        const cplx<T> q = qs[off + idx];
-#pragma unroll
-        for (int k = 0; k < VPT; ++k)
-          if (k < nv) cfma(acc[k], q, xb[k * p3 + jz]);
-        idx += nz - jz - 1;
-      }
-      // jz >= iz: element (iz, jz) at rowstart(iz) + jz - iz
-      const int rs = iz * nz - (iz * (iz - 1)) / 2;
-      for (int jz = iz; jz < nz; ++jz) {
-        const cplx<T> q = qs[off + rs + jz - iz];
-#pragma unroll
-        for (int k = 0; k < VPT; ++k)
-          if (k < nv) cfma(acc[k], q, xb[k * p3 + jz]);
-      }
-    };
-    // full block row iz times X_b
-    auto full_row = [&](int off, int b) {
-      const cplx<T> *xb = xs + (size_t)v0 * p3 + b * nz;
-      const cplx<T> *qr = qs + off + iz * nz;
-      for (int jz = 0; jz < nz; ++jz) {
-        const cplx<T> q = qr[jz];
-#pragma unroll
-        for (int k = 0; k < VPT; ++k)
-          if (k < nv) cfma(acc[k], q, xb[k * p3 + jz]);
-      }
-    };
-    // minus transposed full block: row iz of -F^T is -column iz of F
-    auto negcol = [&](int off, int b) {
-      const cplx<T> *xb = xs + (size_t)v0 * p3 + b * nz;
-      for (int jz = 0; jz < nz; ++jz) {
-        const cplx<T> q = qs[off + jz * nz + iz];
-        const cplx<T> nq = mk<T>(-q.x, -q.y);
-#pragma unroll
-        for (int k = 0; k < VPT; ++k)
-          if (k < nv) cfma(acc[k], nq, xb[k * p3 + jz]);
-      }
-    };
-    if (a == 0) {
-      sym_row(o_xx, 0);
-      sym_row(o_xy, 1);
-      full_row(o_xz, 2);
-    } else if (a == 1) {
-      sym_row(o_xy, 0);
-      sym_row(o_yy, 1);
-      full_row(o_yz, 2);
-    } else {
-      negcol(o_xz, 0);
-      negcol(o_yz, 1);
-      sym_row(o_zz, 2);
-    }
-#pragma unroll
-    for (int k = 0; k < VPT; ++k) {
-      if (k < nv) {
-        const int v = v0 + k;
-        const int m = v / R, r = v - m * R;
-        cplx<T> o = acc[k];
-        if ((a == 0 && mtx[m] < 0) || (a == 1 && mty[m] < 0)) o = mk<T>(-o.x, -o.y);
-        spec[(((size_t)mky[m] * nx2 + mkx[m]) * R + r) * p3 + row] = o;
-      }
-    }
   }
 }
 
@@ -427,31 +352,6 @@ static hipError_t launch_fft_y_t(void *spec, int nx2, int ny, int rp_total, int 
   return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t launch_block_t(const void *tab, void *spec, int nx, int ny, int nz, int R,
-                                 hipStream_t s) {
-  constexpr int VPT = 4;
-  const int E = 2 * nz * (2 * nz + 1);
-  const int p3 = 3 * nz;
-  const int vg = (4 * R + VPT - 1) / VPT;
-  int nthr = p3 * vg;
-  nthr = ((nthr + 63) / 64) * 64;
-  size_t lds = ((size_t)E + (size_t)4 * R * p3) * sizeof(cplx<T>);
-  dim3 grid((nx + 1) * (ny + 1));
-  k_block<T, VPT><<<grid, nthr, lds, s>>>(static_cast<const cplx<T> *>(tab),
-                                          static_cast<cplx<T> *>(spec), nx, ny, nz, R);
-  return hipGetLastError();
-}
-
-int block_threads(int nz, int R) {
-  const int vg = (4 * R + 3) / 4;
-  int nthr = 3 * nz * vg;
-  return ((nthr + 63) / 64) * 64;
-}
-size_t block_lds_bytes(int nz, int R, int prec) {
-  const size_t c = prec == PREC_FP32 ? sizeof(c64) : sizeof(c128);
-  return ((size_t)2 * nz * (2 * nz + 1) + (size_t)4 * R * 3 * nz) * c;
-}
 size_t fft_lds_bytes(int G, int L, int prec) {
   const size_t c = prec == PREC_FP32 ? sizeof(c64) : sizeof(c128);
   return (size_t)G * (L + 1) * c;
@@ -463,8 +363,6 @@ hipError_t set_lds_limits() {
   hipError_t e = hipSuccess;
 #define GIEM_SET(k) \
   if (e == hipSuccess) e = hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize, lim)
-  GIEM_SET((k_block<double, 4>));
-  GIEM_SET((k_block<float, 4>));
   GIEM_SET((k_fft_x_fwd<double, 4>)); GIEM_SET((k_fft_x_fwd<double, 8>)); GIEM_SET((k_fft_x_fwd<double, 16>)); GIEM_SET((k_fft_x_fwd<double, 32>));
   GIEM_SET((k_fft_x_fwd<float, 4>)); GIEM_SET((k_fft_x_fwd<float, 8>)); GIEM_SET((k_fft_x_fwd<float, 16>)); GIEM_SET((k_fft_x_fwd<float, 32>));
   GIEM_SET((k_fft_x_inv<double, 4>)); GIEM_SET((k_fft_x_inv<double, 8>)); GIEM_SET((k_fft_x_inv<double, 16>)); GIEM_SET((k_fft_x_inv<double, 32>));
@@ -494,10 +392,4 @@ hipError_t launch_fft_y(int prec, void *spec, int nx2, int ny, int rp_total, int
   return prec == PREC_FP32 ? launch_fft_y_t<float>(spec, nx2, ny, rp_total, G, fd, tw, inverse, s)
                            : launch_fft_y_t<double>(spec, nx2, ny, rp_total, G, fd, tw, inverse, s);
 }
-hipError_t launch_block(int prec, const void *tab, void *spec, int nx, int ny, int nz, int R,
-                        hipStream_t s) {
-  return prec == PREC_FP32 ? launch_block_t<float>(tab, spec, nx, ny, nz, R, s)
-                           : launch_block_t<double>(tab, spec, nx, ny, nz, R, s);
-}
-
 }  // namespace giem
