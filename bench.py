@@ -1,0 +1,281 @@
+#!/usr/bin/env python3
+"""Throughput of the contracting-IE hot path on one GPU.
+
+One step = one GMRES(30) solve to a relative residual of 1e-6 of the
+128 x 128 x 32 layered-earth workload (200 x 200 x 100 m cells, 5 earth
+layers, 3 blocks of contrast up to 1e4, f = 0.01 Hz) for both plane-wave
+polarisations at once (2 right-hand sides), with the tables and all vectors
+resident in HBM.  Every operator apply inside the solve runs the five HIP
+kernels (x-FFT, y-FFT, packed block product, inverse y-FFT, inverse x-FFT).
+
+value = RHS operator applies per second of solve wall time (whole solve,
+orthogonalisation included).  Also reported: the apply alone, the solve time
+of the FP32-refined form and its field error against a tight FP64 solve,
+the roofline of the dominant kernel (HIP events around every launch in the
+timed region) and the oracle's direct summation timed on the host cores.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--table synthetic|physical]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+HBM_PEAK_GBS = 8000.0
+COUNTERS_FILE = os.path.join(HERE, "profiles", "block_product_128x128x32_r2_fp64_counters.md")
+BLOCK_SOURCE = os.path.join(HERE, "paper_1512_06126_amd", "csrc", "kernels_block.hip")
+STAGES = ("fft_x", "fft_y", "block_product", "ifft_y", "ifft_x")
+
+
+def stage_bytes(nx, ny, nz, R, c):
+    """Algorithmic HBM bytes of one launch of each kernel (R right-hand sides,
+    c bytes per complex of the spectra; vectors are always complex128)."""
+    n = nx * ny * nz
+    P = 3 * nz
+    half = R * P * 2 * nx * ny * c          # x-transformed planes, Ny rows
+    full = R * P * 4 * nx * ny * c          # padded 2-D spectra
+    T = (nx + 1) * (ny + 1) * 2 * nz * (2 * nz + 1) * c
+    return {
+        "fft_x": R * 3 * n * 16 + n * 16 + half,
+        "fft_y": half + full,
+        "block_product": T + 2 * full,
+        "ifft_y": full + half,
+        "ifft_x": half + 2 * R * 3 * n * 16 + 2 * n * 16,
+    }
+
+
+def m3_bytes(nx, ny, nz, R, c):
+    """Three-step model: table once + 78 N c per right-hand side."""
+    T = (nx + 1) * (ny + 1) * 2 * nz * (2 * nz + 1) * c
+    return T + R * 78 * nx * ny * nz * c
+
+
+def read_traffic():
+    """HBM bytes per launch of the block product from the committed counter
+    summary, or None when absent or taken on another version of the kernel."""
+    if not os.path.exists(COUNTERS_FILE):
+        return None
+    kv = {}
+    for line in open(COUNTERS_FILE):
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            kv[k.strip()] = v.strip().strip("`")
+    with open(BLOCK_SOURCE, "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()
+    if kv.get("kernel_source_sha256") != sha:
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def synthetic_table(model, seed=20):
+    """Random packed table with the storage symmetries, scaled so that the
+    system stays well conditioned (stand-in until tables are computed)."""
+    import giem_synth as gs
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = model["nx"], model["ny"], model["nz"]
+    t = gs.random_packed_table(rng, nx, ny, nz, decay=0.2)
+    # |R1| <= 2 sqrt(Re sb) / V and |R2| <= sqrt(Re sb) since |gamma| < 1
+    sb = np.asarray(model["sigma"])[model["layer_of_cell"]].real
+    vol = model["hx"] * model["hy"] * np.diff(model["z_edges"])
+    bound = (2 * np.sqrt(sb) / vol).max() * np.sqrt(sb).max() * 2 * np.sqrt(3 * nx * ny * nz)
+    return t * (0.2 / bound)
+
+
+def cpu_baseline(model, table, budget_s=15.0, seed=30):
+    """The oracle's direct summation (eq. bcyl, O(N) per output cell) timed
+    on a bounded sample of output cells of the same workload."""
+    from oracle import dense, packed
+    import giem_synth as gs
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        cores = 1
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = model["nx"], model["ny"], model["nz"]
+    x = gs.random_vector(rng, 2, nz, ny, nx)
+    qnn = packed.full_tensor_nonneg(table, nz)
+    done = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        c = (int(rng.integers(nz)), int(rng.integers(ny)), int(rng.integers(nx)))
+        dense.apply_cells(qnn, model, x, [c], "A")
+        done += 1
+    dt = time.perf_counter() - t0
+    ncell = nx * ny * nz
+    rhs_applies_per_s = 2 * done / dt / ncell
+    return {"value": rhs_applies_per_s, "unit": "RHS-applies/s", "cores": cores, "kind": "oracle",
+            "sample": f"direct summation of {done} output cells (all 3 components, 2 RHS) of "
+                      f"the {nx}x{ny}x{nz} apply in {dt:.1f} s, scaled by {ncell} cells per apply"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--table", choices=("synthetic", "physical"), default="synthetic")
+    ap.add_argument("--apply-reps", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--counter-run", action="store_true",
+                    help="only a 1 GiB device copy (counter calibration) and 3 FP64 applies, "
+                         "for hardware-counter passes")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
+              "(independent frequencies and models shard across GPUs without communication, "
+              "which is not part of this benchmark)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import giem_synth as gs
+    import paper_1512_06126_amd as g
+    g.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    model = gs.config_baseline()
+    nx, ny, nz = model["nx"], model["ny"], model["nz"]
+    R = 2
+    f = model["freq"]
+    t_tab = time.perf_counter()
+    if args.table == "physical":
+        h = g.tables(model, [f], flags=g.TABLES_C64)
+        table = None
+    else:
+        table = synthetic_table(model)
+        h = g.tables_import(model, [f], table[None], flags=g.TABLES_C64)
+    torch.cuda.synchronize()
+    table_s = time.perf_counter() - t_tab
+    sa = torch.from_numpy(np.ascontiguousarray(model["sigma_a"])).to(dev)
+    E = torch.zeros((R, 3, nz, ny, nx), dtype=torch.complex128, device=dev)
+
+    if args.counter_run:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        x = torch.randn((R, 3, nz, ny, nx), dtype=torch.complex128, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            h.apply(x, y, sa, prec=g.FP64)
+        torch.cuda.synchronize()
+        print("counter run done: copy 1073741824 B, 3 FP64 applies", flush=True)
+        h.close()
+        return
+
+    def solve(prec, tol, out=E):
+        return h.solve(sa, out, tol=tol, restart=30, max_iter=3000, precision=prec,
+                       inner_tol=1e-3, max_outer=30)
+
+    for _ in range(args.warmup):
+        solve(g.FP64, 1e-6)
+    torch.cuda.synchronize()
+    h.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [solve(g.FP64, 1e-6) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = h.profile_read()
+    h.profile(False)
+    p64 = prof["fp64"]
+    rhs_applies = p64["rhs"]
+    ms_per_step = 1e3 * wall / args.steps
+    value = rhs_applies / wall
+
+    # roofline of the dominant kernel, from the events of the timed region
+    dom = int(np.argmax(p64["stage_ms"]))
+    name = STAGES[dom]
+    avg_ms = p64["stage_ms"][dom] / max(p64["applies"], 1)
+    avg_rhs = p64["rhs"] / max(p64["applies"], 1)
+    bytes_launch = stage_bytes(nx, ny, nz, avg_rhs, 16)[name]
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    traffic = read_traffic() if name == "block_product" else None
+    roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "bytes_per_launch": bytes_launch,
+                "avg_launch_ms": round(avg_ms, 5), "launches": p64["applies"]}
+
+    # the apply alone, both precisions
+    x = torch.randn((R, 3, nz, ny, nx), dtype=torch.complex128, device=dev)
+    y = torch.empty_like(x)
+    apply = {}
+    for prec, key, c in ((g.FP64, "fp64", 16), (g.FP32, "fp32", 8)):
+        for _ in range(3):
+            h.apply(x, y, sa, prec=prec)
+        torch.cuda.synchronize()
+        st = np.array([h.apply_timed(x, y, sa, prec=prec) for _ in range(args.apply_reps)])
+        med = np.median(st, axis=0)
+        tot = float(med.sum())
+        m3 = m3_bytes(nx, ny, nz, R, c)
+        apply[key] = {"ms_per_apply": round(tot, 4), "rhs_applies_per_s": round(R / tot * 1e3, 1),
+                      "stage_ms": [round(v, 4) for v in med], "m3_bytes": m3,
+                      "hbm_frac_m3": round(m3 / (tot * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                      "min_ms": round(float(st.sum(1).min()), 4),
+                      "max_ms": round(float(st.sum(1).max()), 4)}
+
+    # FP32-refined solve vs FP64, and both against a tight FP64 reference
+    Eref = torch.zeros_like(E)
+    sref = solve(g.FP64, 1e-12, Eref)
+    E32 = torch.zeros_like(E)
+    solve(g.FP32, 1e-6, E32)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s32 = [solve(g.FP32, 1e-6, E32) for _ in range(max(1, args.steps // 2))]
+    torch.cuda.synchronize()
+    ms32 = 1e3 * (time.perf_counter() - t1) / len(s32)
+
+    def relerr(a, b):
+        return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+    solve_info = {
+        "fp64_ms": round(ms_per_step, 3), "fp64_iters": stats[-1]["iters"],
+        "fp64_rel_residual": stats[-1]["rel_residual"],
+        "fp64_field_err": relerr(E, Eref),
+        "fp32_refined_ms": round(ms32, 3), "fp32_refined_inner_iters": s32[-1]["iters"],
+        "fp32_refined_outer": s32[-1]["outer_iters"],
+        "fp32_refined_field_err": relerr(E32, Eref),
+        "speedup_fp32_refined": round(ms_per_step / ms32, 3),
+        "reference_iters": sref["iters"], "table_build_s": round(table_s, 3),
+    }
+
+    cpu = None
+    if not args.no_cpu:
+        if table is None:
+            table = h.export(0)
+        cpu = cpu_baseline(model, table, args.cpu_seconds)
+
+    line = {
+        "metric": "IE operator applies/s + GMRES solve time to 1e-6, FP32-refined vs FP64, HBM %",
+        "value": round(value, 2), "unit": "RHS-applies/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": "128x128x32 cells of 200x200x100 m, 5-layer earth, 3 blocks "
+                               "contrast <= 1e4, f = 0.01 Hz, 2 plane-wave RHS, GMRES(30) "
+                               "to 1e-6, FP64",
+                   "table": args.table, "rhs": R},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "apply": apply,
+        "solve": solve_info,
+    }
+    h.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

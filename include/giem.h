@@ -162,6 +162,21 @@ int giem_apply_timed(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t
                      const void *x, void *y, uint32_t mode, uint32_t prec, void *stream,
                      double *stage_ms);
 
+/* giem_profile -- switch per-kernel event recording on (enable != 0) or off
+   for every later operator apply on this handle, including those inside
+   giem_solve and giem_adjoint, and discard what was recorded.  Recording adds
+   six hipEventRecord calls per apply and never synchronises.  Errors: EINVAL
+   (null handle). */
+int giem_profile(giem_handle *t, int32_t enable);
+
+/* giem_profile_read -- wait for the last recorded apply and report what was
+   recorded since giem_profile or the previous read, then clear it:
+     stage_ms[2][5]: summed kernel durations (ms) per precision (0 = FP64,
+                     1 = FP32) and per kernel in the order of giem_apply_timed;
+     applies[2], rhs[2]: number of applies and of right-hand sides in them.
+   All pointers are host memory owned by the caller.  Errors: EINVAL, EHIP. */
+int giem_profile_read(giem_handle *t, double *stage_ms, int64_t *applies, int64_t *rhs);
+
 /*
  * giem_solve -- solve A U = U^0 by GMRES(m) (Sect. 2.2 system, Sect. 3.3
  * solver) and return the cell-averaged field E = U / a.

@@ -131,3 +131,48 @@ def objective(B, model, g, en_cells, sigma_a):
     P = physical_matrix(B, model, sigma_a)
     E = solve_lu(P, en_cells)
     return float(np.real(np.sum(g * E)))
+
+
+def offset_blocks(qnn, dy, dx):
+    """Q(dy, dx) for arrays of signed offsets from a non-negative tensor
+    qnn[Ny][Nx][3][3][...] (packed.full_tensor_nonneg, or a slice of it over
+    the trailing depth indices): Lemma 2 mirror signs, with the odd
+    components zero on the axis they are odd in."""
+    dy = np.asarray(dy)
+    dx = np.asarray(dx)
+    q = qnn[np.abs(dy), np.abs(dx)]                       # [..., 3, 3, *rest]
+    sx = np.where((dx < 0)[..., None, None], _packed.SIGN_X, 1.0)
+    sy = np.where((dy < 0)[..., None, None], _packed.SIGN_Y, 1.0)
+    zx = np.where((dx == 0)[..., None, None] & (_packed.SIGN_X < 0), 0.0, 1.0)
+    zy = np.where((dy == 0)[..., None, None] & (_packed.SIGN_Y < 0), 0.0, 1.0)
+    sgn = sx * sy * zx * zy
+    return q * sgn.reshape(sgn.shape + (1,) * (q.ndim - sgn.ndim))
+
+
+def apply_cells(qnn, model, x, cells, mode="A", sigma_a=None):
+    """Selected rows of y = A x (mode "A"), A^T x ("AT") or B x ("B"), each
+    by direct summation over every source cell of eq. (bcyl), with no FFT:
+      (B x)_(a, n) = sum_m sum_b Q_ab(y_n - y_m, x_n - x_m)[iz_n, iz_m] x_(b, m).
+    qnn from packed.full_tensor_nonneg; x [R][3][Nz][Ny][Nx]; cells is a list
+    of (iz, iy, ix).  Returns [R][len(cells)][3].  A^T uses B = B^T
+    (reciprocity), so A^T = S + R2 B R1."""
+    nz, ny, nx = model["nz"], model["ny"], model["nx"]
+    d = cie_diagonals(model, sigma_a) if mode != "B" else None
+    xs = x
+    if mode == "A":
+        xs = x * d["R2"][None, None]
+    elif mode == "AT":
+        xs = x * d["R1"][None, None]
+    ym = np.arange(ny)
+    xm = np.arange(nx)
+    out = np.zeros((x.shape[0], len(cells), 3), dtype=np.complex128)
+    for k, (iz, iy, ix) in enumerate(cells):
+        row = offset_blocks(qnn[:, :, :, :, iz, :], (iy - ym)[:, None],
+                            (ix - xm)[None, :])                          # [ny,nx,a,b,jz]
+        bx = np.einsum("yxabj,rbjyx->ra", row, xs, optimize=True)
+        if mode == "B":
+            out[:, k] = bx
+        else:
+            left = d["R1"] if mode == "A" else d["R2"]
+            out[:, k] = d["S"][iz, iy, ix] * x[:, :, iz, iy, ix] + left[iz, iy, ix] * bx
+    return out

@@ -79,6 +79,8 @@ def load():
         "giem_solve": [P, I32, P, I32, P, P, P, P, P],
         "giem_adjoint": [P, I32, P, I32, P, P, P, P, P, P],
         "giem_fields": [P, I32, P, I32, P, I32, P, P, P, P],
+        "giem_profile": [P, I32],
+        "giem_profile_read": [P, P, P, P],
         "giem_free": [P],
         "giem_last_error": [],
     }
@@ -94,8 +96,8 @@ def load():
 
 def exported_symbols():
     return ["giem_tables", "giem_tables_import", "giem_tables_export", "giem_tables_bytes",
-            "giem_apply", "giem_apply_timed", "giem_solve", "giem_adjoint", "giem_fields",
-            "giem_free", "giem_last_error"]
+            "giem_apply", "giem_apply_timed", "giem_profile", "giem_profile_read", "giem_solve",
+            "giem_adjoint", "giem_fields", "giem_free", "giem_last_error"]
 
 
 def _check(rc, allow_noconv=False):
@@ -175,6 +177,19 @@ class Handle:
         _check(_lib.giem_apply_timed(self._p, ifreq, sa, nrhs, _ptr(x), _ptr(y), mode, prec,
                                      _stream(stream), ms))
         return list(ms)
+
+    def profile(self, enable=True):
+        _check(_lib.giem_profile(self._p, 1 if enable else 0))
+
+    def profile_read(self):
+        """Summed kernel times per precision since the last read:
+        {"fp64"|"fp32": {"stage_ms": [5], "applies": n, "rhs": n}}."""
+        ms = (ctypes.c_double * 10)()
+        ap = (ctypes.c_int64 * 2)()
+        rh = (ctypes.c_int64 * 2)()
+        _check(_lib.giem_profile_read(self._p, ms, ap, rh))
+        return {k: {"stage_ms": list(ms[5 * i:5 * i + 5]), "applies": ap[i], "rhs": rh[i]}
+                for i, k in enumerate(("fp64", "fp32"))}
 
     def solve(self, sigma_a, E_out, rhs=None, tol=1e-6, restart=30, max_iter=2000,
               precision=FP64, inner_tol=1e-3, max_outer=20, weighted_ip=0, warm_start=0,

@@ -128,35 +128,53 @@ int apply_core(giem_handle *t, int ifreq, int nrhs, const VecPtrs &p, unsigned m
   const void *twx = prec == PREC_FP32 ? t->px.tw32 : t->px.tw64;
   const void *twy = prec == PREC_FP32 ? t->py.tw32 : t->py.tw64;
   const double scale = 1.0 / (4.0 * nx * ny);
-  hipEvent_t ev[6];
+  // Events around the five kernels: private ones for giem_apply_timed, pooled
+  // ones (read back later by giem_profile_read) while profiling is on.
+  hipEvent_t own[6];
+  hipEvent_t *ev = nullptr;
   if (stage_ms) {
-    for (int i = 0; i < 6; ++i) GIEM_HIP(hipEventCreate(&ev[i]), "hipEventCreate");
-    GIEM_HIP(hipEventRecord(ev[0], s), "hipEventRecord");
+    for (int i = 0; i < 6; ++i) GIEM_HIP(hipEventCreate(&own[i]), "hipEventCreate");
+    ev = own;
+  } else if (t->prof) {
+    while (t->prof_ev.size() < t->prof_used + 6) {
+      hipEvent_t e;
+      GIEM_HIP(hipEventCreate(&e), "hipEventCreate");
+      t->prof_ev.push_back(e);
+    }
+    ev = t->prof_ev.data() + t->prof_used;
+    t->prof_used += 6;
+    t->prof_meta.push_back((int)prec);
+    t->prof_meta.push_back(nrhs);
   }
+  auto mark = [&](int i) -> int {
+    if (ev) GIEM_HIP(hipEventRecord(ev[i], s), "hipEventRecord");
+    return GIEM_OK;
+  };
   const size_t cbytes = prec == PREC_FP32 ? sizeof(c64) : sizeof(c128);
   void *spa = t->spec_ws;
   void *spb = static_cast<char *>(t->spec_ws) + (size_t)4 * nx * ny * rp * cbytes;
+  GIEM_TRY(mark(0));
   GIEM_HIP(launch_fft_x_fwd(prec, p, r2, spa, nx, ny, nz, rp, G, t->px.d, twx, s), "x-FFT");
-  if (stage_ms) GIEM_HIP(hipEventRecord(ev[1], s), "hipEventRecord");
+  GIEM_TRY(mark(1));
   GIEM_HIP(launch_fft_y(prec, spa, 2 * nx, ny, rp, G, t->py.d, twy, 0, s), "y-FFT");
-  if (stage_ms) GIEM_HIP(hipEventRecord(ev[2], s), "hipEventRecord");
+  GIEM_TRY(mark(2));
   GIEM_HIP(launch_block(prec, tab, spa, spb, static_cast<const unsigned *>(t->bplan), nx, ny, nz,
                         nrhs, s),
            "block product");
-  if (stage_ms) GIEM_HIP(hipEventRecord(ev[3], s), "hipEventRecord");
+  GIEM_TRY(mark(3));
   GIEM_HIP(launch_fft_y(prec, spb, 2 * nx, ny, rp, G, t->py.d, twy, 1, s), "inverse y-FFT");
-  if (stage_ms) GIEM_HIP(hipEventRecord(ev[4], s), "hipEventRecord");
+  GIEM_TRY(mark(4));
   GIEM_HIP(launch_fft_x_inv(prec, p, sd, r1, spb, nx, ny, nz, rp, G, t->px.d, twx, scale, s),
            "inverse x-FFT");
+  GIEM_TRY(mark(5));
   if (stage_ms) {
-    GIEM_HIP(hipEventRecord(ev[5], s), "hipEventRecord");
     GIEM_HIP(hipEventSynchronize(ev[5]), "hipEventSynchronize");
     for (int i = 0; i < 5; ++i) {
       float ms = 0.f;
       GIEM_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]), "hipEventElapsedTime");
       stage_ms[i] = ms;
     }
-    for (int i = 0; i < 6; ++i) hipEventDestroy(ev[i]);
+    for (int i = 0; i < 6; ++i) hipEventDestroy(own[i]);
   }
   return GIEM_OK;
 }
@@ -346,6 +364,7 @@ void giem_free(giem_handle *t) {
     if (p) hipFree(p);
   if (t->red_host) hipHostFree(t->red_host);
   if (t->coef_host) hipHostFree(t->coef_host);
+  for (hipEvent_t e : t->prof_ev) hipEventDestroy(e);
   delete t;
 }
 
@@ -448,6 +467,42 @@ int giem_apply_timed(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t
     return GIEM_EINVAL;
   }
   return apply_entry(t, ifreq, sigma_a, nrhs, x, y, mode, prec, stream, stage_ms);
+}
+
+int giem_profile(giem_handle *t, int32_t enable) {
+  if (!t) {
+    set_error("null handle");
+    return GIEM_EINVAL;
+  }
+  t->prof = enable != 0;
+  t->prof_used = 0;
+  t->prof_meta.clear();
+  return GIEM_OK;
+}
+
+int giem_profile_read(giem_handle *t, double *stage_ms, int64_t *applies, int64_t *rhs) {
+  if (!t || !stage_ms || !applies || !rhs) {
+    set_error("giem_profile_read: null argument");
+    return GIEM_EINVAL;
+  }
+  for (int i = 0; i < 10; ++i) stage_ms[i] = 0.0;
+  for (int i = 0; i < 2; ++i) applies[i] = rhs[i] = 0;
+  const size_t napp = t->prof_used / 6;
+  if (napp) GIEM_HIP(hipEventSynchronize(t->prof_ev[t->prof_used - 1]), "hipEventSynchronize");
+  for (size_t a = 0; a < napp; ++a) {
+    const int pr = t->prof_meta[2 * a] == PREC_FP32 ? 1 : 0;
+    const hipEvent_t *ev = t->prof_ev.data() + 6 * a;
+    for (int i = 0; i < 5; ++i) {
+      float ms = 0.f;
+      GIEM_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]), "hipEventElapsedTime");
+      stage_ms[5 * pr + i] += ms;
+    }
+    applies[pr] += 1;
+    rhs[pr] += t->prof_meta[2 * a + 1];
+  }
+  t->prof_used = 0;
+  t->prof_meta.clear();
+  return GIEM_OK;
 }
 
 }  // extern "C"

@@ -65,6 +65,11 @@ struct giem_handle {
   void *vec_ws = nullptr;
   size_t vec_ws_bytes = 0;
   giem::SolveWork *sw = nullptr;
+  // stage profiling (giem_profile): 6 events per recorded apply
+  bool prof = false;
+  std::vector<hipEvent_t> prof_ev;
+  std::vector<int> prof_meta;  // per recorded apply: precision, nrhs
+  size_t prof_used = 0;
 
   size_t ncell() const { return (size_t)nx * ny * nz; }
   size_t nvec() const { return 3 * ncell(); }

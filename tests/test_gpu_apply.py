@@ -88,3 +88,45 @@ def test_rejects_non_smooth_sizes_and_bad_models(lib):
     with pytest.raises(lib.GiemError) as e:
         lib.tables_import(m2, [1.0], t2[None])
     assert e.value.code == lib.GIEM_EDOMAIN
+
+
+@pytest.fixture(scope="module")
+def full_case():
+    """The 128 x 128 x 32 layered workload (2 RHS) with a random table."""
+    from oracle import packed
+    m = gs.config_baseline()
+    rng = np.random.default_rng(77)
+    t = gs.random_packed_table(rng, m["nx"], m["ny"], m["nz"], decay=0.2)
+    d = dense.cie_diagonals(m)
+    t = t / (np.abs(d["R1"]).max() * np.abs(d["R2"]).max() * 1e3)
+    x = gs.random_vector(rng, 2, m["nz"], m["ny"], m["nx"])
+    qnn = packed.full_tensor_nonneg(t, m["nz"])
+    nz, ny, nx = m["nz"], m["ny"], m["nx"]
+    cells = [(0, 0, 0), (nz - 1, ny - 1, nx - 1), (0, ny - 1, 0), (nz - 1, 0, nx - 1),
+             (nz // 2, ny // 2, nx // 2)]
+    cells += [(int(rng.integers(nz)), int(rng.integers(ny)), int(rng.integers(nx)))
+              for _ in range(5)]
+    return m, t, x, qnn, cells
+
+
+@pytest.mark.parametrize("mode,prec,tol", [("A", 0, 1e-10), ("B", 0, 1e-10), ("AT", 0, 1e-10),
+                                           ("B", 1, 1e-4)])
+def test_apply_full_size_sampled(lib, full_case, mode, prec, tol):
+    # The launch configuration the benchmark times (128 x 128 x 32, 2 RHS),
+    # checked at sampled output cells against the oracle's direct sum.
+    import torch
+    m, t, x, qnn, cells = full_case
+    print(f"full-size apply mode={mode} prec={prec}", flush=True)
+    h = lib.tables_import(m, [m["freq"]], t[None], flags=lib.TABLES_C64)
+    xd = to_dev(x)
+    yd = torch.empty_like(xd)
+    code = {"A": lib.MODE_A, "AT": lib.MODE_AT, "B": lib.MODE_B}[mode]
+    h.apply(xd, yd, to_dev(m["sigma_a"]), mode=code, prec=prec)
+    torch.cuda.synchronize()
+    y = yd.cpu().numpy()
+    h.close()
+    got = np.stack([y[:, :, iz, iy, ix] for (iz, iy, ix) in cells], 1)
+    ref = dense.apply_cells(qnn, m, x, cells, mode)
+    err = rel_err(got, ref)
+    print(f"  sampled rel err {err:.3e}", flush=True)
+    assert err <= tol, err

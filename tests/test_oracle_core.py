@@ -185,3 +185,23 @@ def test_oracle_adjoint_gradient_vs_finite_differences():
         sm[idx] *= np.exp(-h)
         fd = (dense.objective(B, m, g, en, sp) - dense.objective(B, m, g, en, sm)) / (2 * h)
         assert abs(fd - grad[idx]) <= 1e-6 * np.abs(grad).max() + 1e-5 * abs(fd), (idx, fd, grad[idx])
+
+
+@pytest.mark.parametrize("mode", ["A", "AT", "B"])
+def test_row_evaluator_matches_dense_apply(mode):
+    # The per-cell direct sum (used at sizes where no dense matrix fits)
+    # against the dense matrix-vector product; the table is scaled so that
+    # R1 B R2 is of order one and the B part decides the result.
+    m = _small_model(seed=9)
+    rng = np.random.default_rng(4)
+    t = gs.random_packed_table(rng, m["nx"], m["ny"], m["nz"])
+    d = dense.cie_diagonals(m)
+    t = t / (np.abs(d["R1"]).max() * np.abs(d["R2"]).max())
+    B = dense.dense_from_packed(t, m)
+    x = gs.random_vector(rng, 2, m["nz"], m["ny"], m["nx"])
+    y = dense.apply_direct(B, d, x, mode)
+    cells = [(iz, iy, ix) for iz in range(m["nz"]) for iy in range(m["ny"])
+             for ix in range(m["nx"])]
+    yc = dense.apply_cells(packed.full_tensor_nonneg(t, m["nz"]), m, x, cells, mode)
+    ref = np.stack([y[:, :, iz, iy, ix] for (iz, iy, ix) in cells], 1)
+    assert np.abs(yc - ref).max() <= 1e-13 * np.abs(ref).max()

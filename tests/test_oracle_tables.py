@@ -1,0 +1,158 @@
+"""Pins of the oracle's fundamental functions (Appendix B problem) and of its
+Galerkin tables (Sect. 3.1, Appendix A) against what the mathematics fixes:
+the whole-space closed form, the jump and interface conditions, reciprocity
+and the storage symmetries of Lemma 1 and Lemma 2."""
+import numpy as np
+import pytest
+
+from oracle import fundamental, tables, vertical, wholespace
+from oracle.packed import SIGN_X, SIGN_Y
+
+LAM = np.array([1e-5, 3e-4, 2e-3, 0.05, 1.0])
+D = np.array([0.0, 120.0, 400.0])
+SIG = np.array([0.0, 0.03, 0.002, 0.2], dtype=complex)
+F = 0.5
+
+
+def test_fundamental_whole_space_closed_form():
+    # equal conductivity everywhere: U = exp(-eta |z - z*|) / eta
+    sig = np.full(4, 0.01, dtype=complex)
+    eta = fundamental.eta_of(LAM, sig, F)[:, 0]
+    for kind in ("1", "sigma"):
+        for z, z0 in ((10.0, 250.0), (300.0, 300.0), (500.0, 130.0)):
+            u = fundamental.U_point(LAM, D, sig, F, kind, z, z0)
+            ref = np.exp(-eta * abs(z - z0)) / eta
+            assert np.allclose(u, ref, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("kind", ["1", "sigma"])
+def test_fundamental_jump_and_interface_conditions(kind):
+    z0 = 250.0
+    p = fundamental.Profile(LAM, D, SIG, F, kind, ("point", z0, 2))
+    eps = 1e-4
+    eta = fundamental.eta_of(LAM, SIG, F)
+
+    def deriv(z, side):
+        # one-sided derivative from the exponential basis: finite difference
+        # of the continuous function on the chosen side, second order
+        h = eps * side
+        return (-3 * p.value(z, np.sign(side)) + 4 * p.value(z + h) - p.value(z + 2 * h)) / (2 * h)
+
+    # [U'] = -2 at the source
+    jump = deriv(z0, +1) - deriv(z0, -1)
+    assert np.allclose(jump, -2.0, rtol=2e-5)
+    # continuity of U and of U' / gamma at the interfaces 120 m and 400 m
+    for di, (lo, hi) in ((120.0, (1, 2)), (400.0, (2, 3))):
+        assert np.allclose(p.value(di - 1e-9), p.value(di + 1e-9), rtol=1e-7)
+        g_lo = SIG[lo] if kind == "sigma" else 1.0
+        g_hi = SIG[hi] if kind == "sigma" else 1.0
+        assert np.allclose(deriv(di, -1) / g_lo, deriv(di, +1) / g_hi, rtol=2e-5)
+    # the ODE inside a layer: U'' = eta^2 U
+    z = 320.0
+    h = 0.05
+    d2 = (p.value(z + h) - 2 * p.value(z) + p.value(z - h)) / h ** 2
+    assert np.allclose(d2, eta[:, 2] ** 2 * p.value(z), rtol=1e-4, atol=1e-12)
+
+
+def test_fundamental_reciprocity():
+    # U_1(z, z*) = U_1(z*, z); sigma_s U_sigma(z, z*) = sigma_r U_sigma(z*, z)
+    z, zs = 60.0, 700.0            # layers 1 and 3
+    u1 = fundamental.U_point(LAM, D, SIG, F, "1", z, zs)
+    u1r = fundamental.U_point(LAM, D, SIG, F, "1", zs, z)
+    assert np.allclose(u1, u1r, rtol=1e-11)
+    us = fundamental.U_point(LAM, D, SIG, F, "sigma", z, zs)
+    usr = fundamental.U_point(LAM, D, SIG, F, "sigma", zs, z)
+    assert np.allclose(SIG[3] * us, SIG[1] * usr, rtol=1e-11)
+
+
+def _ws_model(sig=0.01, freq=1.0):
+    return dict(nx=4, ny=3, nz=2, hx=100.0, hy=120.0, z_edges=np.array([0.0, 60.0, 100.0]),
+                d=np.array([0.0]), sigma=np.array([sig, sig], complex), freq=freq)
+
+
+_SEPARATED = [(0, 2), (0, 3), (2, 0), (1, 2), (2, 3), (-2, -1), (2, -3), (0, -2)]
+
+
+def _ws_errors(B, m):
+    ny, nx = m["ny"], m["nx"]
+    ze = m["z_edges"]
+    worst = 0.0
+    for (i, j) in _SEPARATED:
+        for iz in range(m["nz"]):
+            for jz in range(m["nz"]):
+                lo_n = [j * m["hx"], i * m["hy"], ze[iz]]
+                hi_n = [(j + 1) * m["hx"], (i + 1) * m["hy"], ze[iz + 1]]
+                lo_m = [0.0, 0.0, ze[jz]]
+                hi_m = [m["hx"], m["hy"], ze[jz + 1]]
+                ref = wholespace.cell_pair(lo_n, hi_n, lo_m, hi_m, m["sigma"][0].real,
+                                           m["freq"], q=10)
+                got = B[i + ny - 1, j + nx - 1, :, :, iz, jz]
+                worst = max(worst, np.abs(got - ref).max() / np.abs(ref).max())
+    return worst
+
+
+@pytest.fixture(scope="module")
+def ws_tables():
+    m = _ws_model()
+    return m, tables.build_tables(m)
+
+
+def test_tables_whole_space_closed_form(ws_tables):
+    # all nine components, same and different depths, separated cells
+    m, B = ws_tables
+    assert _ws_errors(B, m) <= 1e-9
+
+
+def test_tables_other_v3_reading_fails_whole_space(monkeypatch):
+    # Planted mistake: keep the 2 delta term in the vertical integral behind
+    # V3 (the reading that differentiates outside the z* integral).  The
+    # whole-space pin must reject it, which decides that reading.
+    orig = vertical.vertical_functions
+
+    def planted(lam, d, sigma, freq, z_edges):
+        A = orig(lam, d, sigma, freq, z_edges)
+        A["A3"] = A["A3"] + 2.0 * np.diag(np.diff(np.asarray(z_edges, float)))[None]
+        return A
+
+    monkeypatch.setattr(vertical, "vertical_functions", planted)
+    m = _ws_model()
+    assert _ws_errors(tables.build_tables(m), m) > 1e-3
+
+
+@pytest.fixture(scope="module")
+def layered_tables():
+    # cells in two earth layers under air, unequal vertical sizes
+    m = dict(nx=3, ny=3, nz=3, hx=80.0, hy=110.0, z_edges=np.array([0.0, 40.0, 100.0, 130.0]),
+             d=np.array([0.0, 100.0]), sigma=np.array([0.0, 0.02, 0.1], complex), freq=2.0)
+    return m, tables.build_tables(m)
+
+
+def test_tables_lemma2_mirror_parity(layered_tables):
+    m, B = layered_tables
+    ny, nx = m["ny"], m["nx"]
+    scale = np.abs(B).max()
+    for i in range(ny):
+        for j in range(nx):
+            q = B[ny - 1 + i, nx - 1 + j]
+            sx = SIGN_X[:, :, None, None]
+            sy = SIGN_Y[:, :, None, None]
+            assert np.abs(B[ny - 1 + i, nx - 1 - j] - sx * q).max() <= 1e-11 * scale
+            assert np.abs(B[ny - 1 - i, nx - 1 + j] - sy * q).max() <= 1e-11 * scale
+    # odd components vanish on their axis
+    b0 = B[ny - 1, nx - 1]
+    assert np.abs(b0[0, 1]).max() <= 1e-11 * scale
+    assert np.abs(b0[0, 2]).max() <= 1e-11 * scale
+    assert np.abs(b0[1, 2]).max() <= 1e-11 * scale
+
+
+def test_tables_lemma1_and_reciprocity(layered_tables):
+    m, B = layered_tables
+    ny, nx = m["ny"], m["nx"]
+    scale = np.abs(B).max()
+    # Lemma 1: yx = xy, zx = -xz^T, zy = -yz^T at every offset
+    assert np.abs(B[:, :, 1, 0] - B[:, :, 0, 1]).max() <= 1e-11 * scale
+    assert np.abs(B[:, :, 2, 0] + np.swapaxes(B[:, :, 0, 2], -1, -2)).max() <= 1e-11 * scale
+    assert np.abs(B[:, :, 2, 1] + np.swapaxes(B[:, :, 1, 2], -1, -2)).max() <= 1e-11 * scale
+    # reciprocity of the full matrix: B[(a, iz), (b, jz)](D) = B[(b, jz), (a, iz)](-D)
+    Bm = B[::-1, ::-1]
+    assert np.abs(B - np.transpose(Bm, (0, 1, 3, 2, 5, 4))).max() <= 1e-11 * scale
