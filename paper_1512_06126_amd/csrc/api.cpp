@@ -285,6 +285,11 @@ static int create_handle(const giem_model *m, int nfreq, const double *freq, uin
     int lay = 0;
     while (lay < t->nlay && t->d[lay] <= mid) ++lay;
     t->layer_of_cell.push_back(lay);
+    if (lay == 0) {
+      set_error("cells must lie below the surface d[0] (the anomaly domain is in the earth)");
+      delete t;
+      return GIEM_EDOMAIN;
+    }
     if (!(t->sigma[lay].real() > 0.0)) {
       set_error("Re sigma_b must be positive in every layer that holds cells");
       delete t;
@@ -393,14 +398,12 @@ int giem_tables(const giem_model *model, int32_t nfreq, const double *freq_hz, u
                 void *stream, giem_handle **out) {
   giem_handle *t = nullptr;
   GIEM_TRY(create_handle(model, nfreq, freq_hz, flags, &t));
-  for (int q = 0; q < nfreq; ++q) {
-    int rc = compute_tables_host(t, t->f[q].freq, t->f[q].spatial);
-    if (rc < 0) {
-      giem_free(t);
-      return rc;
-    }
+  int rc = compute_tables(t, static_cast<hipStream_t>(stream));
+  if (rc < 0) {
+    giem_free(t);
+    return rc;
   }
-  int rc = finish_handle(t, static_cast<hipStream_t>(stream));
+  rc = finish_handle(t, static_cast<hipStream_t>(stream));
   if (rc < 0) {
     giem_free(t);
     return rc;

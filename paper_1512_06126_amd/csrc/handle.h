@@ -87,6 +87,7 @@ int apply_core(giem_handle *t, int ifreq, int nrhs, const VecPtrs &p, unsigned m
 int upload_spatial(giem_handle *t, hipStream_t s);
 int plane_wave_levels(const giem_handle *t, double freq, std::vector<cd> &en_lev,
                       std::vector<cd> &hsurf);
-int compute_tables_host(giem_handle *t, double freq, std::vector<cd> &spatial);
+// packed spatial tables of every frequency of the handle (t->f[q].spatial)
+int compute_tables(giem_handle *t, hipStream_t s);
 
 }  // namespace giem

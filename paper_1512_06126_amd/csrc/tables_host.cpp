@@ -1,9 +1,702 @@
-// placeholder, replaced below
+// Coefficient tables B_n^m of eq. (bcyl) for a layered background
+// (Sect. 3.1; Appendix A for the Green's tensor, Appendix B for the vertical
+// integration, Appendix C for the horizontal integration).
+//
+// Structure of the computation, per frequency:
+//  1. vertical integrals over every pair of depth cells, for lambda on a
+//     logarithmic Chebyshev grid, from the p/q recursions of Appendix B and
+//     the factorisation of the fundamental function U_gamma into a solution
+//     F that satisfies the conditions above and G that satisfies those below
+//     (U(z, z*) ~ F(z_<) G(z_>)); every exponential is evaluated with a
+//     non-positive real part;
+//  2. zero-order Hankel transforms h(rho) = int J0(lambda rho) g(lambda)
+//     dlambda of the five lambda functions, on a logarithmic Chebyshev grid
+//     in rho: a geometry-only weight matrix (Gauss-Legendre panels between
+//     the zeros of J0, tail summed by repeated averaging) contracted with the
+//     lambda samples on the GPU;
+//  3. horizontal Galerkin integration: the product of the two cells'
+//     footprints becomes their autocorrelation phi (a product of triangles),
+//     and the tensor components are convolutions of h with phi, d phi or
+//     d^2 phi, evaluated with quadrature rules whose nodes are graded towards
+//     the singular vertex (Duffy); folded onto the rho grid they form a
+//     second geometry-only matrix, contracted on the GPU;
+//  4. the nine components are formed and packed (upper triangles of xx, xy,
+//     yy, zz; full xz, yz).
+// The lambda-functions, with sigma_n the conductivity of the observation
+// cell and P = -i w mu0 A1 + A3 / sigma_n:
+//   A1 = int int U_1;  A3 = int int (d_z d_z* U_sigma - 2 delta) (regular
+//   part);  A4 = int int d_z U_sigma;  A6 = int int (lambda^2 U_sigma - 2
+//   delta);  A2 = int int U_sigma.
+//   xx = [i w mu0 phi*h(A1 lambda) + (-d_xx phi)*h(P / lambda)] / 4pi
+//   yy likewise with d_yy;  xy = (-d_xy phi)*h(P / lambda) / 4pi
+//   xz = (d_x phi)*h(lambda A4 / sigma_n) / 4pi;  yz with d_y
+//   zz = phi*h(lambda A6 / sigma_n) / 4pi.
+// h(P / lambda) diverges logarithmically at lambda -> 0; it is regularised by
+// J0 -> J0 - 1 below a small lambda_a, which shifts it by a constant that the
+// zero-mean weights d_xx phi, d_yy phi, d_xy phi annihilate.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <functional>
+#include <thread>
+#include <vector>
+
 #include "handle.h"
+
 namespace giem {
-int compute_tables_host(giem_handle *t, double freq, std::vector<cd> &spatial) {
-  (void)t; (void)freq; (void)spatial;
-  set_error("giem_tables: coefficient computation not available in this build");
-  return GIEM_EINVAL;
+
+hipError_t launch_gemm_tn(const double *At, int64_t lda, const double *B, int64_t ldb, double *C,
+                          int64_t ldc, int m, int n, int k, hipStream_t s);
+hipError_t launch_assemble(const c128 *c0, const c128 *c1, const c128 *c2, c128 *out, int nx,
+                           int ny, int nz, double omega_mu0, hipStream_t s);
+
+namespace {
+
+const double kPi = 3.14159265358979323846;
+const double kMu0 = 4e-7 * kPi;
+
+// ---------------------------------------------------------------- quadrature
+struct Rule {
+  std::vector<double> x, w;  // on [-1, 1]
+};
+
+Rule gauss_legendre(int n) {
+  Rule r;
+  r.x.resize(n);
+  r.w.resize(n);
+  for (int i = 0; i < n; ++i) {
+    double x = std::cos(kPi * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (x * p1 - p0) / (x * x - 1.0);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = x;
+    for (int k = 2; k <= n; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (x * p1 - p0) / (x * x - 1.0);
+    r.x[n - 1 - i] = x;
+    r.w[n - 1 - i] = 2.0 / ((1.0 - x * x) * dp * dp);
+  }
+  return r;
 }
+
+// Chebyshev-Lobatto panels of equal width in u = ln x; barycentric
+// interpolation inside a panel.
+struct LogGrid {
+  std::vector<double> edges, node, bw, x;
+  int n = 0;
+  void init(double lo, double hi, double width, int npp) {
+    n = npp;
+    const double u0 = std::log(lo), u1 = std::log(hi);
+    const int np = std::max(1, (int)std::ceil((u1 - u0) / width));
+    edges.resize(np + 1);
+    for (int i = 0; i <= np; ++i) edges[i] = u0 + (u1 - u0) * i / np;
+    node.resize(n);
+    bw.resize(n);
+    for (int j = 0; j < n; ++j) {
+      node[j] = -std::cos(kPi * j / (n - 1));
+      bw[j] = (j & 1) ? -1.0 : 1.0;
+      if (j == 0 || j == n - 1) bw[j] *= 0.5;
+    }
+    x.resize((size_t)np * n);
+    for (int p = 0; p < np; ++p)
+      for (int j = 0; j < n; ++j)
+        x[(size_t)p * n + j] =
+            std::exp(0.5 * (edges[p] + edges[p + 1]) + 0.5 * (edges[p + 1] - edges[p]) * node[j]);
+  }
+  size_t size() const { return x.size(); }
+  // f(xq) ~ sum_j w[j] f(x[col0 + j]); returns col0
+  size_t interp(double xq, double *w) const {
+    const double u = std::log(xq);
+    const int np = (int)edges.size() - 1;
+    int p = (int)(std::upper_bound(edges.begin(), edges.end(), u) - edges.begin()) - 1;
+    p = std::min(std::max(p, 0), np - 1);
+    const double s = (2.0 * u - (edges[p] + edges[p + 1])) / (edges[p + 1] - edges[p]);
+    double tot = 0.0;
+    int hit = -1;
+    for (int j = 0; j < n; ++j) {
+      const double d = s - node[j];
+      if (std::fabs(d) < 1e-14) hit = j;
+      w[j] = hit >= 0 ? 0.0 : bw[j] / d;
+      tot += w[j];
+    }
+    if (hit >= 0) {
+      for (int j = 0; j < n; ++j) w[j] = (j == hit) ? 1.0 : 0.0;
+    } else {
+      for (int j = 0; j < n; ++j) w[j] /= tot;
+    }
+    return (size_t)p * n;
+  }
+};
+
+void parallel_for(int n, const std::function<void(int)> &f) {
+  int nt = (int)std::thread::hardware_concurrency();
+  nt = std::max(1, std::min(nt, 32));
+  nt = std::min(nt, n);
+  if (nt <= 1) {
+    for (int i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t)
+    th.emplace_back([&, t] {
+      for (int i = t; i < n; i += nt) f(i);
+    });
+  for (auto &x : th) x.join();
 }
+
+// ------------------------------------------------------------ Bessel zeros
+std::vector<double> j0_zeros(int count) {
+  std::vector<double> z(count);
+  for (int s = 1; s <= count; ++s) {
+    const double b = (s - 0.25) * kPi;
+    double x = b + 1.0 / (8.0 * b) - 124.0 / (3.0 * std::pow(8.0 * b, 3));
+    for (int it = 0; it < 20; ++it) {
+      const double dx = std::cyl_bessel_j(0.0, x) / (-std::cyl_bessel_j(1.0, x));
+      x -= dx;
+      if (std::fabs(dx) < 1e-15 * x) break;
+    }
+    z[s - 1] = x;
+  }
+  return z;
+}
+
+// -------------------------------------------------------- grid parameters
+struct Grids {
+  LogGrid lam, rho;
+  double lam_lo, lam_a, lam_asym, rho_min;
+  int ntail = 30, levels = 14, ngl_main = 16, ngl_first = 12;
+};
+
+Grids make_grids(const giem_handle *t) {
+  Grids g;
+  double hmin = 1e300;
+  for (int l = 0; l < t->nz; ++l) hmin = std::min(hmin, t->z_edges[l + 1] - t->z_edges[l]);
+  const double href = std::min(t->hx, t->hy);
+  g.rho_min = 1e-7 * href;
+  const double rho_max = 1.05 * std::hypot((t->nx + 1) * t->hx, (t->ny + 1) * t->hy);
+  const double zmax = t->z_edges[t->nz];
+  const double scale = std::max(rho_max, zmax);
+  g.lam_asym = 40.0 / hmin;
+  g.lam_lo = 1e-9 / scale;
+  g.lam_a = 1e-3 / scale;
+  const double lam_hi = 1.1 * (g.lam_asym + (g.ntail + 3) * kPi / g.rho_min);
+  g.lam.init(0.5 * g.lam_lo, lam_hi, 0.5, 16);
+  g.rho.init(g.rho_min, rho_max, 0.5, 12);
+  return g;
+}
+
+// Hankel weights: rows Wt[lam][rho] (transposed for the GEMM) for the plain
+// transform and for the regularised one.
+void hankel_weights(const Grids &g, std::vector<double> &Wt, std::vector<double> &Wt_reg) {
+  const size_t nl = g.lam.size(), nr = g.rho.size();
+  Wt.assign(nl * nr, 0.0);
+  Wt_reg.assign(nl * nr, 0.0);
+  const double rho_max = g.rho.x.back();
+  const int kmax = (int)std::ceil(g.lam_asym * rho_max / kPi) + 1;
+  const std::vector<double> zeros = j0_zeros(kmax + g.ntail + 2);
+  const Rule r1 = gauss_legendre(g.ngl_first), r2 = gauss_legendre(g.ngl_main);
+  // averaged limit of the last partial sums: weight of the tail panel i
+  const int nt = g.ntail, lv = std::min(g.levels, nt - 1);
+  std::vector<double> c(nt, 0.0), beta(nt, 0.0);
+  {
+    std::vector<double> binom(lv + 1, 1.0);
+    for (int i = 1; i <= lv; ++i) binom[i] = binom[i - 1] * (lv - i + 1) / i;
+    for (int i = 0; i <= lv; ++i) c[nt - 1 - lv + i] = binom[i] / std::ldexp(1.0, lv);
+    double acc = 0.0;
+    for (int i = nt - 1; i >= 0; --i) {
+      acc += c[i];
+      beta[i] = acc;
+    }
+  }
+  parallel_for((int)nr, [&](int ir) {
+    const double rho = g.rho.x[ir];
+    std::vector<double> row(nl, 0.0), row_reg(nl, 0.0);
+    double wi[32];
+    auto add = [&](double lam, double w, bool reg_part) {
+      const double j = std::cyl_bessel_j(0.0, lam * rho);
+      const size_t c0 = g.lam.interp(lam, wi);
+      for (int q = 0; q < g.lam.n; ++q) {
+        row[c0 + q] += w * j * wi[q];
+        row_reg[c0 + q] += w * (reg_part ? j - 1.0 : j) * wi[q];
+      }
+    };
+    const int K = (int)std::ceil(g.lam_asym * rho / kPi) + 1;
+    const double l1 = zeros[0] / rho;
+    // [lam_lo, l1] in halving subpanels, with lam_a as a breakpoint
+    std::vector<double> brk{l1};
+    while (brk.back() / 2.0 > g.lam_lo) brk.push_back(brk.back() / 2.0);
+    brk.push_back(g.lam_lo);
+    if (g.lam_a > g.lam_lo && g.lam_a < l1) brk.push_back(g.lam_a);
+    std::sort(brk.begin(), brk.end());
+    brk.erase(std::unique(brk.begin(), brk.end()), brk.end());
+    for (size_t p = 0; p + 1 < brk.size(); ++p) {
+      const double a = brk[p], b = brk[p + 1];
+      for (int q = 0; q < g.ngl_first; ++q) {
+        const double lam = 0.5 * (a + b) + 0.5 * (b - a) * r1.x[q];
+        add(lam, 0.5 * (b - a) * r1.w[q], lam < g.lam_a);
+      }
+    }
+    // panels between consecutive zeros up to the K-th zero, then the tail
+    auto panel = [&](double a, double b, double scale) {
+      for (int q = 0; q < g.ngl_main; ++q) {
+        const double lam = 0.5 * (a + b) + 0.5 * (b - a) * r2.x[q];
+        add(lam, scale * 0.5 * (b - a) * r2.w[q], lam < g.lam_a);
+      }
+    };
+    for (int k = 1; k < K; ++k) panel(zeros[k - 1] / rho, zeros[k] / rho, 1.0);
+    for (int i = 0; i < nt; ++i) panel(zeros[K - 1 + i] / rho, zeros[K + i] / rho, beta[i]);
+    for (size_t l = 0; l < nl; ++l) {
+      Wt[l * nr + ir] = row[l];
+      Wt_reg[l * nr + ir] = row_reg[l];
+    }
+  });
+}
+
+// ----------------------------------------------------- horizontal rules
+enum { K_W0 = 0, K_XX, K_YY, K_XY, K_X, K_Y, K_COUNT };
+
+struct RulePts {
+  std::vector<double> rho, w;
+  void add(double r, double wt) {
+    rho.push_back(r);
+    w.push_back(wt);
+  }
+};
+
+inline double weight_fn(int kind, double u, double v, double su, double sv, double hx, double hy) {
+  switch (kind) {
+    case K_W0: return (hx - std::fabs(u)) * (hy - std::fabs(v));
+    case K_X: return -su * (hy - std::fabs(v));
+    case K_Y: return -sv * (hx - std::fabs(u));
+    default: return -su * sv;  // K_XY
+  }
+}
+
+// int over the quadrant [x0,x1]x[y0,y1] of weight * h(|D - r'|); the
+// integrand is singular only when D is a vertex of the quadrant.
+void quadrant_rule(int kind, double dx, double dy, double x0, double x1, double y0, double y1,
+                   double su, double sv, double hx, double hy, const Rule &gs, const Rule &g14,
+                   const Rule &g8, RulePts &out) {
+  const double tx = 1e-9 * hx, ty = 1e-9 * hy;
+  int sing = -1;
+  const double vx[2] = {x0, x1}, vy[2] = {y0, y1};
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      if (std::fabs(vx[a] - dx) < tx && std::fabs(vy[b] - dy) < ty) sing = 2 * a + b;
+  auto emit = [&](double u, double v, double wq) {
+    const double wk = weight_fn(kind, u, v, su, sv, hx, hy);
+    out.add(std::hypot(dx - u, dy - v), wq * wk);
+  };
+  if (sing >= 0) {
+    // two triangles from the singular vertex P, radial variable r = s^2
+    const double px = vx[sing >> 1], py = vy[sing & 1];
+    const double ox = vx[1 - (sing >> 1)], oy = vy[1 - (sing & 1)];
+    const double ax[2] = {ox, px}, ay[2] = {py, oy};  // the two adjacent corners
+    const int n = (int)gs.x.size();
+    for (int tri = 0; tri < 2; ++tri) {
+      const double e1x = ax[tri] - px, e1y = ay[tri] - py;
+      const double e2x = ox - ax[tri], e2y = oy - ay[tri];
+      const double det = std::fabs(e1x * e2y - e1y * e2x);
+      for (int i = 0; i < n; ++i) {
+        const double s = 0.5 * (gs.x[i] + 1.0), ws = 0.5 * gs.w[i];
+        const double r = s * s, wr = ws * 2.0 * s;
+        for (int j = 0; j < n; ++j) {
+          const double tt = 0.5 * (gs.x[j] + 1.0), wt = 0.5 * gs.w[j];
+          const double u = px + r * (e1x + tt * e2x), v = py + r * (e1y + tt * e2y);
+          emit(u, v, wr * wt * r * det);
+        }
+      }
+    }
+    return;
+  }
+  const double ddx = std::max({x0 - dx, 0.0, dx - x1}), ddy = std::max({y0 - dy, 0.0, dy - y1});
+  const double dist = std::hypot(ddx, ddy), hm = std::min(hx, hy);
+  const Rule &rr = dist < 2.0 * hm ? g14 : g8;
+  const int split = dist < 0.5 * hm ? 2 : 1;
+  const int n = (int)rr.x.size();
+  for (int a = 0; a < split; ++a)
+    for (int b = 0; b < split; ++b) {
+      const double xa = x0 + (x1 - x0) * a / split, xb = x0 + (x1 - x0) * (a + 1) / split;
+      const double ya = y0 + (y1 - y0) * b / split, yb = y0 + (y1 - y0) * (b + 1) / split;
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+          const double u = 0.5 * (xa + xb) + 0.5 * (xb - xa) * rr.x[i];
+          const double v = 0.5 * (ya + yb) + 0.5 * (yb - ya) * rr.x[j];
+          emit(u, v, 0.25 * (xb - xa) * (yb - ya) * rr.w[i] * rr.w[j]);
+        }
+    }
+}
+
+void area_rule(int kind, double dx, double dy, double hx, double hy, const Rule &gs,
+               const Rule &g14, const Rule &g8, RulePts &out) {
+  for (int sx = -1; sx <= 1; sx += 2)
+    for (int sy = -1; sy <= 1; sy += 2) {
+      const double x0 = std::min(0.0, sx * hx), x1 = std::max(0.0, sx * hx);
+      const double y0 = std::min(0.0, sy * hy), y1 = std::max(0.0, sy * hy);
+      quadrant_rule(kind, dx, dy, x0, x1, y0, y1, sx, sy, hx, hy, gs, g14, g8, out);
+    }
+}
+
+// -d_xx phi = -(delta(u + hx) - 2 delta(u) + delta(u - hx)) (hy - |v|) and
+// the same with x and y exchanged: line integrals along v.
+void line_rule(int kind, double dx, double dy, double hx, double hy, const Rule &gl,
+               RulePts &out) {
+  const int n = (int)gl.x.size();
+  const double dfix = kind == K_XX ? dx : dy, drun = kind == K_XX ? dy : dx;
+  const double hfix = kind == K_XX ? hx : hy, hrun = kind == K_XX ? hy : hx;
+  for (int c = -1; c <= 1; ++c) {
+    const double wc = c == 0 ? 2.0 : -1.0;
+    const double off = dfix - c * hfix;
+    std::vector<double> cuts{-hrun, 0.0, hrun};
+    if (drun > -hrun && drun < hrun) cuts.push_back(drun);
+    std::sort(cuts.begin(), cuts.end());
+    cuts.erase(std::unique(cuts.begin(), cuts.end()), cuts.end());
+    for (size_t p = 0; p + 1 < cuts.size(); ++p) {
+      const double a = cuts[p], b = cuts[p + 1];
+      const bool on_line = std::fabs(off) < 1e-12 * hfix;
+      const bool sa = on_line && std::fabs(a - drun) < 1e-12 * hrun;
+      const bool sb = on_line && std::fabs(b - drun) < 1e-12 * hrun;
+      for (int i = 0; i < n; ++i) {
+        double v, wv;
+        const double s = 0.5 * (gl.x[i] + 1.0), ws = 0.5 * gl.w[i];
+        if (sa) {
+          v = a + (b - a) * s * s;
+          wv = (b - a) * ws * 2.0 * s;
+        } else if (sb) {
+          v = b - (b - a) * s * s;
+          wv = (b - a) * ws * 2.0 * s;
+        } else {
+          v = 0.5 * (a + b) + 0.5 * (b - a) * gl.x[i];
+          wv = 0.5 * (b - a) * gl.w[i];
+        }
+        out.add(std::hypot(off, drun - v), wc * wv * (hrun - std::fabs(v)));
+      }
+    }
+  }
+}
+
+// Spatial fold matrices Mt[rho][kind * noff + (i Nx + j)] for i, j >= 0.
+void spatial_matrix(const giem_handle *t, const Grids &g, std::vector<double> &Mt) {
+  const int nx = t->nx, ny = t->ny;
+  const size_t noff = (size_t)nx * ny, nr = g.rho.size(), ncol = K_COUNT * noff;
+  Mt.assign(nr * ncol, 0.0);
+  const Rule gs = gauss_legendre(24), g14 = gauss_legendre(14), g8 = gauss_legendre(8);
+  const Rule gline = gauss_legendre(24);
+  parallel_for((int)noff, [&](int o) {
+    const int i = o / nx, j = o % nx;
+    const double dx = j * t->hx, dy = i * t->hy;
+    double wi[32];
+    for (int kind = 0; kind < K_COUNT; ++kind) {
+      RulePts pts;
+      if (kind == K_XX || kind == K_YY)
+        line_rule(kind, dx, dy, t->hx, t->hy, gline, pts);
+      else
+        area_rule(kind, dx, dy, t->hx, t->hy, gs, g14, g8, pts);
+      const size_t col = kind * noff + o;
+      for (size_t q = 0; q < pts.rho.size(); ++q) {
+        const size_t c0 = g.rho.interp(std::max(pts.rho[q], g.rho_min), wi);
+        for (int k = 0; k < g.rho.n; ++k) Mt[(c0 + k) * ncol + col] += pts.w[q] * wi[k];
+      }
+    }
+  });
+}
+
+// ----------------------------------------------------- vertical functions
+typedef std::complex<double> cx;
+
+// Functions of x = eta h (Re x >= 0) that cancel for small |x|, by their
+// power series there:
+//   eps(x) = (1 - e^-x) / x       = sum_m (-x)^m / (m+1)!
+//   phi(x) = (x - 1 + e^-x) / x^2 = sum_m (-x)^m / (m+2)!
+//   psi(x) = (e^x - 1 - x) / x^2  = sum_m   x^m / (m+2)!
+inline cx series(cx x, int shift, bool alternate) {
+  cx s = 0.0, term = 1.0;
+  double fact = 1.0;
+  for (int q = 2; q <= shift; ++q) fact *= q;
+  for (int m = 0; m < 24; ++m) {
+    s += term / fact;
+    term *= alternate ? -x : x;
+    fact *= (m + 1 + shift);
+  }
+  return s;
+}
+inline cx f_eps(cx x) { return std::abs(x) < 0.5 ? series(x, 1, true) : (1.0 - std::exp(-x)) / x; }
+inline cx f_phi(cx x) {
+  return std::abs(x) < 0.5 ? series(x, 2, true) : (x - 1.0 + std::exp(-x)) / (x * x);
+}
+// damp psi(x) and damp (e^x - 1) with damp = e^{-2 eta L}, L >= h (no
+// overflow for large x: damp e^x = e^{x - 2 eta L})
+inline cx f_psi_damped(cx x, cx damp, cx e_x_damped) {
+  if (std::abs(x) < 0.5) return damp * series(x, 2, false);
+  return (e_x_damped - damp * (1.0 + x)) / (x * x);
+}
+inline cx f_expm1_damped(cx x, cx damp, cx e_x_damped) {
+  if (std::abs(x) < 0.5) return damp * x * series(x, 1, false);
+  return e_x_damped - damp;
+}
+
+struct Layering {
+  int nlay;                   // number of interfaces
+  std::vector<double> d;      // [nlay]
+  std::vector<cx> sigma;      // [nlay + 1]
+};
+
+// Per-lambda vertical functions written into the four column groups of one
+// row of G: [P / lambda (T) | lambda A1 (T) | lambda A6 / sigma (T) |
+// lambda A4 / sigma (nz^2)].
+struct Vertical {
+  const giem_handle *t;
+  double omega;
+  int nz;
+  std::vector<int> lay;          // layer of each cell
+  std::vector<double> ta, tb;    // local coordinates of the cell edges
+  void init(const giem_handle *h, double freq) {
+    t = h;
+    nz = h->nz;
+    omega = 2 * kPi * freq;
+    lay.resize(nz);
+    ta.resize(nz);
+    tb.resize(nz);
+    for (int l = 0; l < nz; ++l) {
+      const int n = h->layer_of_cell[l];
+      lay[l] = n;
+      const double top = h->d[n - 1];
+      ta[l] = h->z_edges[l] - top;
+      tb[l] = h->z_edges[l + 1] - top;
+    }
+  }
+
+  void row(double lam, cx *out) const {
+    const int nl = t->nlay;
+    const int nlayers = nl + 1;
+    std::vector<cx> eta(nlayers), gam(nlayers);
+    std::vector<double> L(nlayers);
+    for (int n = 0; n < nlayers; ++n) {
+      cx e = std::sqrt(cx(lam * lam, 0.0) - cx(0.0, omega * kMu0) * t->sigma[n]);
+      if (e.real() < 0) e = -e;
+      eta[n] = e;
+      L[n] = (n >= 1 && n < nl) ? t->d[n] - t->d[n - 1] : INFINITY;
+    }
+    const int T = nz * (nz + 1) / 2;
+    // both kinds: k = 0 (gamma = 1), k = 1 (gamma = sigma)
+    std::vector<cx> p[2], q[2];
+    for (int k = 0; k < 2; ++k) {
+      p[k].assign(nlayers, 0.0);
+      q[k].assign(nlayers, 0.0);
+      auto g = [&](int n) { return k == 0 ? cx(1.0) : t->sigma[n]; };
+      // downward: p_n from the admittance of everything above layer n
+      for (int n = 1; n < nlayers; ++n) {
+        const cx Pm = (n - 1 >= 1) ? p[k][n - 1] * std::exp(-2.0 * eta[n - 1] * L[n - 1]) : 0.0;
+        const cx a = g(n - 1) * (1.0 + Pm) * eta[n], b = g(n) * eta[n - 1] * (1.0 - Pm);
+        p[k][n] = (a - b) / (a + b);
+      }
+      // upward: q_n from the admittance of everything below layer n
+      for (int n = nlayers - 2; n >= 1; --n) {
+        const cx Qp = (n + 1 < nl) ? q[k][n + 1] * std::exp(-2.0 * eta[n + 1] * L[n + 1]) : 0.0;
+        const cx a = g(n + 1) * eta[n] * (1.0 + Qp), b = g(n) * eta[n + 1] * (1.0 - Qp);
+        q[k][n] = (a - b) / (a + b);
+      }
+    }
+    // per-cell factors for both kinds
+    struct Cell {
+      cx theta, FI, FD, GI, GD, diagA, diagA4, diagA3, diagA6;
+    };
+    std::vector<Cell> cell[2];
+    for (int k = 0; k < 2; ++k) {
+      cell[k].resize(nz);
+      for (int l = 0; l < nz; ++l) {
+        const int n = lay[l];
+        const cx e = eta[n];
+        const double h = tb[l] - ta[l];
+        const cx P = p[k][n], Q = q[k][n];
+        const bool half = !std::isfinite(L[n]);
+        const cx eh = std::exp(-e * h);
+        const cx x = e * h;
+        const cx E1 = h * f_eps(x);
+        const cx ea = std::exp(-2.0 * e * ta[l]), eb = std::exp(-2.0 * e * tb[l]);
+        const cx fa = 1.0 + P * ea, fb = 1.0 + P * eb;
+        const cx qa = half ? cx(0.0) : Q * std::exp(-2.0 * e * (L[n] - ta[l]));
+        const cx qb = half ? cx(0.0) : Q * std::exp(-2.0 * e * (L[n] - tb[l]));
+        const cx ga = 1.0 + qa, gb = 1.0 + qb;
+        const cx damp = half ? cx(0.0) : std::exp(-2.0 * e * L[n]);
+        const cx pqd = P * Q * damp;
+        const cx D = 1.0 - pqd;
+        Cell &c = cell[k][l];
+        c.theta = eh * fa / fb;
+        c.FI = E1 * (1.0 + P * std::exp(-e * (ta[l] + tb[l]))) / fb;
+        c.FD = 1.0 - c.theta;
+        const cx qm = half ? cx(0.0) : Q * std::exp(-e * (2.0 * L[n] - ta[l] - tb[l]));
+        c.GI = fa * E1 * (1.0 + qm) / (e * D);
+        c.GD = fa * (eh * gb - ga) / (e * D);
+        // same cell
+        const cx Sp = ea * E1 * E1;
+        const cx Sq = half ? cx(0.0) : std::exp(-2.0 * e * (L[n] - tb[l])) * E1 * E1;
+        const cx psi = half ? cx(0.0) : f_psi_damped(x, damp, std::exp(x - 2.0 * e * L[n]));
+        const cx phix = f_phi(x);
+        c.diagA = (2.0 * h * h * phix + P * Sp + Q * Sq + P * Q * 2.0 * h * h * psi) / (e * D);
+        c.diagA4 = E1 * E1 * (qb - P * ea) / D;
+        {
+          // U(b,b) + U(a,a) - 2 U(a,b) - 2h, with the free part written
+          // stably: (2/(eta D))(1 - e^{-x}) - 2h = 2h (pqd - x phi(x)) / D
+          const cx em = std::exp(-e * ta[l]) - std::exp(-e * tb[l]);
+          const cx qq = half ? cx(0.0)
+                             : std::exp(-e * (L[n] - tb[l])) - std::exp(-e * (L[n] - ta[l]));
+          const cx pq_term =
+              half ? cx(0.0) : -2.0 * P * Q * f_expm1_damped(x, damp, std::exp(x - 2.0 * e * L[n]));
+          c.diagA3 = 2.0 * h * (pqd - x * phix) / D + (P * em * em + Q * qq * qq + pq_term) / (e * D);
+        }
+        {
+          // lambda^2 A2 - 2h = eta^2 A2 - 2h + k^2 A2 (stable for large lambda)
+          const cx ep = f_eps(x);
+          const cx kk2 = cx(0.0, omega * kMu0) * t->sigma[n];
+          const cx eta2A2m2h =
+              (2.0 * h * (pqd - ep) + e * (P * Sp + Q * Sq + P * Q * 2.0 * h * h * psi)) / D;
+          c.diagA6 = eta2A2m2h + kk2 * c.diagA;
+        }
+      }
+    }
+    const cx iwm(0.0, omega * kMu0);
+    const double lam2 = lam * lam;
+    // upper pairs iz <= jz: P / lambda, lambda A1, lambda A6 / sigma
+    int u = 0;
+    for (int i = 0; i < nz; ++i) {
+      const cx si = t->sigma[lay[i]];
+      cx R1 = 1.0, Rs = 1.0;  // products of theta over cells strictly between
+      for (int j = i; j < nz; ++j) {
+        cx A1, A2, A3;
+        if (j == i) {
+          A1 = cell[0][i].diagA;
+          A2 = cell[1][i].diagA;
+          A3 = cell[1][i].diagA3;
+        } else {
+          if (j > i + 1) {
+            R1 *= cell[0][j - 1].theta;
+            Rs *= cell[1][j - 1].theta;
+          }
+          A1 = cell[0][i].FI * R1 * cell[0][j].GI;
+          A2 = cell[1][i].FI * Rs * cell[1][j].GI;
+          A3 = cell[1][i].FD * Rs * cell[1][j].GD;
+        }
+        const cx Pv = -iwm * A1 + A3 / si;
+        out[u] = Pv / lam;
+        out[T + u] = lam * A1;
+        const cx A6 = (j == i) ? cell[1][i].diagA6 : lam2 * A2;
+        out[2 * T + u] = lam * A6 / si;
+        ++u;
+      }
+    }
+    // A4 / sigma_obs, full [iz][jz]
+    cx *a4 = out + 3 * T;
+    for (int i = 0; i < nz; ++i) {
+      const cx si = t->sigma[lay[i]];
+      a4[i * nz + i] = lam * cell[1][i].diagA4 / si;
+      cx R = 1.0;
+      for (int j = i + 1; j < nz; ++j) {
+        if (j > i + 1) R *= cell[1][j - 1].theta;
+        // observation i above source j
+        a4[i * nz + j] = lam * cell[1][i].FD * R * cell[1][j].GI / si;
+        // observation j below source i: (sigma_j / sigma_i) FI_i R GD_j / sigma_j
+        a4[j * nz + i] = lam * cell[1][i].FI * R * cell[1][j].GD / si;
+      }
+    }
+  }
+};
+
+struct DevBuf {
+  void *p = nullptr;
+  ~DevBuf() {
+    if (p) hipFree(p);
+  }
+  hipError_t alloc(size_t bytes) { return hipMalloc(&p, bytes); }
+  double *d() { return static_cast<double *>(p); }
+  c128 *c() { return static_cast<c128 *>(p); }
+};
+
+}  // namespace
+
+int compute_tables(giem_handle *t, hipStream_t s) {
+  const int nx = t->nx, ny = t->ny, nz = t->nz;
+  const int T = nz * (nz + 1) / 2, nz2 = nz * nz;
+  const int ncolc = 3 * T + nz2;  // complex columns of G and H
+  const size_t noff = (size_t)nx * ny;
+  if (noff * K_COUNT > (size_t)64 * 65535 * 1024) {
+    set_error("giem_tables: grid too large for the table build");
+    return GIEM_EINVAL;
+  }
+  const Grids g = make_grids(t);
+  const size_t nl = g.lam.size(), nr = g.rho.size();
+  std::vector<double> Wt, Wt_reg, Mt;
+  hankel_weights(g, Wt, Wt_reg);
+  spatial_matrix(t, g, Mt);
+  DevBuf dW, dWr, dM, dG, dH, dc0, dc1, dc2, dout;
+  if (dW.alloc(Wt.size() * 8) != hipSuccess || dWr.alloc(Wt_reg.size() * 8) != hipSuccess ||
+      dM.alloc(Mt.size() * 8) != hipSuccess || dG.alloc(nl * ncolc * 16) != hipSuccess ||
+      dH.alloc(nr * ncolc * 16) != hipSuccess || dc0.alloc(noff * 2 * T * 16) != hipSuccess ||
+      dc1.alloc(3 * noff * T * 16) != hipSuccess || dc2.alloc(2 * noff * nz2 * 16) != hipSuccess ||
+      dout.alloc(noff * t->E() * 16) != hipSuccess) {
+    set_error("giem_tables: out of device memory");
+    return GIEM_ENOMEM;
+  }
+  if (check_hip(hipMemcpyAsync(dW.p, Wt.data(), Wt.size() * 8, hipMemcpyHostToDevice, s),
+                "upload Hankel weights") ||
+      check_hip(hipMemcpyAsync(dWr.p, Wt_reg.data(), Wt_reg.size() * 8, hipMemcpyHostToDevice, s),
+                "upload Hankel weights") ||
+      check_hip(hipMemcpyAsync(dM.p, Mt.data(), Mt.size() * 8, hipMemcpyHostToDevice, s),
+                "upload spatial weights"))
+    return GIEM_EHIP;
+  std::vector<cx> G(nl * ncolc);
+  for (size_t q = 0; q < t->f.size(); ++q) {
+    Vertical v;
+    v.init(t, t->f[q].freq);
+    parallel_for((int)nl, [&](int l) { v.row(g.lam.x[l], G.data() + (size_t)l * ncolc); });
+    if (check_hip(hipMemcpyAsync(dG.p, G.data(), G.size() * 16, hipMemcpyHostToDevice, s),
+                  "upload vertical functions"))
+      return GIEM_EHIP;
+    const int64_t ldg = 2 * (int64_t)ncolc;  // doubles per row of G and H
+    // H[:, P] = W_reg G[:, P];  H[:, rest] = W G[:, rest]
+    if (check_hip(launch_gemm_tn(dWr.d(), nr, dG.d(), ldg, dH.d(), ldg, (int)nr, 2 * T, (int)nl, s),
+                  "Hankel contraction") ||
+        check_hip(launch_gemm_tn(dW.d(), nr, dG.d() + 2 * T, ldg, dH.d() + 2 * T, ldg, (int)nr,
+                                 2 * (2 * T + nz2), (int)nl, s),
+                  "Hankel contraction"))
+      return GIEM_EHIP;
+    const int64_t ldm = (int64_t)K_COUNT * noff;
+    // c0 = M_W0 [A1 | A6];  c1 = M_{XX,YY,XY} P;  c2 = M_{X,Y} A4
+    if (check_hip(launch_gemm_tn(dM.d(), ldm, dH.d() + 2 * T, ldg, dc0.d(), 4 * T, (int)noff, 4 * T,
+                                 (int)nr, s),
+                  "spatial contraction") ||
+        check_hip(launch_gemm_tn(dM.d() + K_XX * noff, ldm, dH.d(), ldg, dc1.d(), 2 * T,
+                                 (int)(3 * noff), 2 * T, (int)nr, s),
+                  "spatial contraction") ||
+        check_hip(launch_gemm_tn(dM.d() + K_X * noff, ldm, dH.d() + 6 * T, ldg, dc2.d(), 2 * nz2,
+                                 (int)(2 * noff), 2 * nz2, (int)nr, s),
+                  "spatial contraction") ||
+        check_hip(launch_assemble(dc0.c(), dc1.c(), dc2.c(), dout.c(), nx, ny, nz, t->f[q].freq * 2 * kPi * kMu0, s),
+                  "table assembly"))
+      return GIEM_EHIP;
+    t->f[q].spatial.resize(noff * t->E());
+    if (check_hip(hipMemcpyAsync(t->f[q].spatial.data(), dout.p, noff * t->E() * 16,
+                                 hipMemcpyDeviceToHost, s),
+                  "download table") ||
+        check_hip(hipStreamSynchronize(s), "table build"))
+      return GIEM_EHIP;
+  }
+  return GIEM_OK;
+}
+
+}  // namespace giem

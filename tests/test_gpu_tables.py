@@ -1,0 +1,90 @@
+"""The library's coefficient tables (giem_tables: Appendix B recursions,
+Hankel transforms and horizontal quadratures, contracted on the GPU) against
+the oracle's independent construction, and the whole physical chain (tables,
+plane-wave source, GMRES) against a dense LU solve."""
+import numpy as np
+import pytest
+
+import giem_synth as gs
+from oracle import dense, normal_field, tables
+from tests.gpu_util import rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+# table accuracy bound, relative to the largest entry of each stored class
+TAU_TAB = 1e-9
+
+MODELS = {
+    "whole_space": dict(nx=4, ny=3, nz=2, hx=100.0, hy=120.0, z_edges=np.array([0.0, 60.0, 100.0]),
+                        d=np.array([0.0]), sigma=np.array([0.01, 0.01], complex), freq=1.0),
+    "layered_air": dict(nx=3, ny=3, nz=3, hx=80.0, hy=110.0,
+                        z_edges=np.array([0.0, 40.0, 100.0, 130.0]), d=np.array([0.0, 100.0]),
+                        sigma=np.array([0.0, 0.02, 0.1], complex), freq=2.0),
+    "contrast_1e4": dict(nx=3, ny=2, nz=3, hx=100.0, hy=100.0,
+                         z_edges=np.array([0.0, 50.0, 100.0, 150.0]), d=np.array([0.0, 50.0]),
+                         sigma=np.array([0.0, 1e-4, 1.0], complex), freq=0.01),
+}
+
+
+def _lib_model(m):
+    return gs.make_model(m["nx"], m["ny"], m["nz"], m["hx"], m["hy"], m["z_edges"], m["d"],
+                         m["sigma"], m["freq"])
+
+
+def _class_errors(lib_t, ref_t, nz):
+    T = nz * (nz + 1) // 2
+    cuts = {"xx": (0, T), "xy": (T, 2 * T), "yy": (2 * T, 3 * T), "zz": (3 * T, 4 * T),
+            "xz": (4 * T, 4 * T + nz * nz), "yz": (4 * T + nz * nz, 4 * T + 2 * nz * nz)}
+    return {k: float(np.abs(lib_t[..., a:b] - ref_t[..., a:b]).max() / np.abs(ref_t[..., a:b]).max())
+            for k, (a, b) in cuts.items()}
+
+
+@pytest.mark.parametrize("name", list(MODELS))
+def test_tables_match_oracle(lib, name):
+    m = MODELS[name]
+    print(f"tables {name}", flush=True)
+    h = lib.tables(_lib_model(m), [m["freq"]])
+    got = h.export(0)
+    h.close()
+    ref = tables.pack(tables.build_tables(m), m["nx"], m["ny"], m["nz"])
+    errs = _class_errors(got, ref, m["nz"])
+    print("  per-class errors", errs, flush=True)
+    assert max(errs.values()) <= TAU_TAB, errs
+
+
+def test_tables_air_limit(lib):
+    # sigma_0 = 0 (the limit p = -1) against a tiny air conductivity
+    m = dict(MODELS["layered_air"])
+    h0 = lib.tables(_lib_model(m), [m["freq"]])
+    t0 = h0.export(0)
+    h0.close()
+    m["sigma"] = np.array([1e-12, 0.02, 0.1], complex)
+    h1 = lib.tables(_lib_model(m), [m["freq"]])
+    t1 = h1.export(0)
+    h1.close()
+    errs = _class_errors(t1, t0, m["nz"])
+    assert max(errs.values()) <= 1e-8, errs
+
+
+def test_physical_solve_matches_lu(lib):
+    # 16 x 16 x 4 model of contrast up to 1e3, plane-wave source: the library's
+    # tables, exported and solved densely by LU, against giem_solve
+    import torch
+    m = gs.config_small()
+    nx, ny, nz = m["nx"], m["ny"], m["nz"]
+    print("physical solve 16x16x4", flush=True)
+    h = lib.tables(m, [m["freq"]])
+    t = h.export(0)
+    B = dense.dense_from_packed(t, m)
+    d = dense.cie_diagonals(m)
+    A = dense.system_matrix(B, d)
+    rhs = normal_field.plane_wave_rhs(m)
+    ref = dense.solve_lu(A, rhs) / d["a"][None, None]
+    E = torch.zeros((2, 3, nz, ny, nx), dtype=torch.complex128, device="cuda")
+    st = h.solve(to_dev(m["sigma_a"]), E, tol=1e-13, restart=30, max_iter=4000)
+    h.close()
+    print("  stats", st, flush=True)
+    assert st["converged"] == 1
+    err = rel_err(E.cpu().numpy(), ref)
+    print(f"  field rel err {err:.3e}", flush=True)
+    assert err <= 1e-10

@@ -156,3 +156,29 @@ def test_tables_lemma1_and_reciprocity(layered_tables):
     # reciprocity of the full matrix: B[(a, iz), (b, jz)](D) = B[(b, jz), (a, iz)](-D)
     Bm = B[::-1, ::-1]
     assert np.abs(B - np.transpose(Bm, (0, 1, 3, 2, 5, 4))).max() <= 1e-11 * scale
+
+
+@pytest.mark.parametrize("which", ["layered", "contrast"])
+def test_modified_operator_is_contraction(layered_tables, which):
+    # The modified Green's operator I + 2 D^-1/2 S_b B S_b D^-1/2 (D the cell
+    # volumes, S_b = sqrt(Re sigma_b)) has 2-norm at most one (Sect. 2.2),
+    # whatever the layering; a wrong sign or term in B breaks it.
+    import giem_synth as gs
+    from oracle import dense
+    if which == "layered":
+        m, B = layered_tables
+    else:
+        m = dict(nx=4, ny=4, nz=6, hx=200.0, hy=200.0, z_edges=np.arange(7) * 100.0,
+                 d=np.array([0.0, 300.0, 500.0]), sigma=np.array([0, 0.02, 1e-4, 0.5], complex),
+                 freq=0.01)
+        B = tables.build_tables(m)
+    t = tables.pack(B, m["nx"], m["ny"], m["nz"])
+    mm = gs.make_model(m["nx"], m["ny"], m["nz"], m["hx"], m["hy"], m["z_edges"], m["d"],
+                       m["sigma"], m["freq"])
+    Bd = dense.dense_from_packed(t, mm)
+    dg = dense.cie_diagonals(mm)
+    w = np.tile((dg["s"] / np.sqrt(dg["vol"])).reshape(-1), 3)
+    Tt = np.eye(w.size) + 2 * w[:, None] * Bd * w[None, :]
+    smax = np.linalg.svd(Tt, compute_uv=False).max()
+    assert smax <= 1.0 + 1e-8, smax
+    assert smax > 0.9   # and it is not trivially small
