@@ -9,6 +9,7 @@ namespace giem {
 
 // operator apply (kernels_apply.hip)
 hipError_t set_lds_limits();
+hipError_t set_block_lds_limits();
 int block_threads(int nz, int R);
 size_t block_lds_bytes(int nz, int R, int prec);
 bool block_supported(int nz, int R);

@@ -370,6 +370,7 @@ hipError_t set_lds_limits() {
   GIEM_SET((k_fft_y<double, 4>)); GIEM_SET((k_fft_y<double, 8>)); GIEM_SET((k_fft_y<double, 16>)); GIEM_SET((k_fft_y<double, 32>));
   GIEM_SET((k_fft_y<float, 4>)); GIEM_SET((k_fft_y<float, 8>)); GIEM_SET((k_fft_y<float, 16>)); GIEM_SET((k_fft_y<float, 32>));
 #undef GIEM_SET
+  if (e == hipSuccess) e = set_block_lds_limits();
   return e;
 }
 

@@ -15,13 +15,17 @@
 // The product at one representative point is a dense contraction
 //   [Yr | Yi] (3Nz x 16) = [Qr | Qi] (3Nz x 6Nz) [[Xr | Xi]; [-Xi | Xr]]
 // over up to 8 complex vectors (mirrors x RHS) per pass, done with 16x16x4
-// MFMA tiles (FP64 or FP32): one wavefront per 16 output rows, separate
-// accumulators for the real and the imaginary part of Q.
+// MFMA tiles (FP64 or FP32), two accumulators (real and imaginary part of Q).
 //
-// One workgroup per representative point.  The vectors are staged in LDS;
-// the MFMA A fragments are gathered straight from the packed block in global
-// memory (a symmetric entry serves two rows, its second read hits the L2), so
-// that the small LDS footprint lets many workgroups share a CU.
+// k_block_pipe (Nz <= 32): one persistent workgroup per CU stages a point's
+// packed row (2Nz(2Nz+1) complex, 66.5 KB for Nz = 32 in FP64) in LDS with
+// coalesced loads, so every table byte crosses HBM once, while the next
+// point's row is in flight into registers; 12 wavefronts (two per 16-row
+// tile, each half of the contraction) run the MFMAs from LDS.
+//
+// k_block (fallback for larger Nz or many RHS): one wavefront per (point,
+// 16-row tile), fragments gathered straight from global memory through a
+// host-built plan.
 #include <algorithm>
 #include <vector>
 
@@ -108,7 +112,7 @@ __host__ __device__ inline unsigned plan_word(int nz, int r, int c) {
 // and its B fragments from the input spectra (with the mirror sign flips), and
 // writes its rows of the output spectra, which live in a second buffer.
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 k_block(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
         cplx<T> *__restrict__ sout, const unsigned *__restrict__ plan, int nx, int ny, int nz,
         int R) {
@@ -185,6 +189,240 @@ k_block(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
   }
 }
 
+
+// LDS offset and sign of Q[row][col] (row = alpha Nz + iz, col = beta Nz +
+// jz).  The staged row keeps the storage of Sect. 3.1 (upper triangles of
+// xx, xy, yy, zz, then xz and yz), but the rows of the two full blocks are
+// padded to Nz + 1 entries so that the 16 lanes of a fragment, which read 16
+// consecutive rows of one column, fall into different LDS banks.  Lemma 1
+// gives yx = xy, zx = -xz^T, zy = -yz^T.
+__device__ __forceinline__ int staged_index(int a, int iz, int b, int jz, int nz, int tri,
+                                            bool &neg) {
+  const bool full = (a == 2) != (b == 2);
+  const int lo = iz < jz ? iz : jz, hi = iz < jz ? jz : iz;
+  const int sbase = (a == 2) ? 3 * tri : (a + b == 0) ? 0 : (a + b == 1) ? tri : 2 * tri;
+  const int sidx = sbase + lo * nz - (lo * (lo - 1)) / 2 + (hi - lo);
+  const int frow = (a == 2) ? jz : iz, fcol = (a == 2) ? iz : jz;
+  const int fblk = (a == 1 || b == 1) ? nz : 0;
+  const int fidx = 4 * tri + (fblk + frow) * (nz + 1) + fcol;
+  neg = full && a == 2;
+  return full ? fidx : sidx;
+}
+
+__device__ __forceinline__ int staged_of_packed(int e, int nz, int tri) {
+  if (e < 4 * tri) return e;
+  const int f = e - 4 * tri, r = f / nz;
+  return 4 * tri + r * (nz + 1) + (f - r * nz);
+}
+
+// entries of the packed row and of the input vectors that a thread carries
+// ahead in registers (the next point's data, loaded during the MFMAs)
+constexpr int kStageRegs = 6;
+constexpr int kXRegs = 2;
+// k-steps of 4 columns per wavefront (half of 3 Nz, rounded up)
+constexpr int kMaxHalfSteps = 16;
+
+__device__ __forceinline__ double flip_sign(double x, unsigned m) {
+  return __hiloint2double(__double2hiint(x) ^ (int)m, __double2loint(x));
+}
+__device__ __forceinline__ float flip_sign(float x, unsigned m) {
+  return __int_as_float(__float_as_int(x) ^ (int)m);
+}
+
+// Software-pipelined block product.  One persistent workgroup per CU takes
+// the representative points g, g + grid, ...; it holds one point's packed
+// row and input vectors in LDS while the next point's are in flight into
+// registers.  Two wavefronts per 16-row output tile split the contraction
+// into halves (split-k) and are added through LDS, so 2 x ceil(3Nz/16)
+// wavefronts (12 for Nz = 32) keep the four SIMDs' matrix cores busy.  The
+// LDS offsets of a lane's A fragments and the Lemma 1 signs (bit 15 of each
+// 16-bit entry) do not depend on the point and are computed once.  The
+// input vectors are staged as real B fragments: row c holds
+// [Re X_0..7 | Im X_0..7]; the second operand [-Im | Re] is the same row read
+// with its halves swapped and the sign of the first half flipped.
+template <typename T, int NS>
+__global__ void __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(3, 3)))
+k_block_pipe(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
+             cplx<T> *__restrict__ sout, int nx, int ny, int nz, int R, int nct) {
+  typedef Mfma<T> M;
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  constexpr int HS = NS / 2;  // k-steps per half
+  constexpr int kpad = 4 * NS;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int E = 2 * nz * (2 * nz + 1);
+  const int Es = E + 2 * nz;  // padded rows of the full blocks; entry Es is zero
+  const int p3 = 3 * nz, tri = nz * (nz + 1) / 2;
+  const int nrt = (p3 + 15) >> 4;
+  v2 *Qv = reinterpret_cast<v2 *>(lds_raw);
+  T *Bs = reinterpret_cast<T *>(Qv + Es + 2);          // [nct][kpad][16]
+  T *Red = Bs + (size_t)nct * kpad * 16;                 // [nrt][4][64] partial sums
+  const int npts = (nx + 1) * (ny + 1);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int kk0 = lane >> 4, j = lane & 15, part = j >> 3;
+  const int rt = wave % nrt, kh = wave / nrt;  // output tile, contraction half
+  const unsigned bmask = part ? 0u : 0x80000000u;
+  unsigned aoff[(HS + 1) / 2];
+  {
+    const int row = rt * 16 + (lane & 15);
+    const bool rowok = row < p3;
+    const int a = rowok ? row / nz : 0, iz = rowok ? row - a * nz : 0;
+#pragma unroll
+    for (int u = 0; u < HS; ++u) {
+      const int c = 4 * (kh * HS + u) + kk0;
+      unsigned w = (unsigned)Es;
+      if (rowok && c < p3) {
+        const int b = c / nz, jz = c - b * nz;
+        bool neg;
+        w = (unsigned)staged_index(a, iz, b, jz, nz, tri, neg) | (neg ? 0x8000u : 0u);
+      }
+      if (u & 1)
+        aoff[u >> 1] |= w << 16;
+      else
+        aoff[u >> 1] = w;
+    }
+  }
+  if (tid == 0) Qv[Es] = v2{(T)0, (T)0};
+  const int nxe = nct * 8 * kpad;  // input-vector elements (c, v)
+  v2 pre[kStageRegs];
+  cplx<T> xpre[kXRegs];
+  // loads of one point's row and input vectors into the prefetch registers
+  auto prefetch = [&](int rep_) __attribute__((always_inline)) {
+    const v2 *src = reinterpret_cast<const v2 *>(tab) + (size_t)rep_ * E;
+#pragma unroll
+    for (int u = 0; u < kStageRegs; ++u) {
+      const int e = tid + u * nthr;
+      if (e < E) pre[u] = src[e];
+    }
+    const MirrorSet m = mirror_set(rep_, nx, ny);
+    const int V = m.n * R;
+#pragma unroll
+    for (int u = 0; u < kXRegs; ++u) {
+      const int idx = u * nthr + tid;
+      const int v = idx / kpad, c = idx - v * kpad;
+      xpre[u] = cplx<T>{(T)0, (T)0};
+      if (idx < nxe && v < V && c < p3) {
+        const int mi = v / R, r = v - mi * R;
+        int pt;
+        bool fx, fy;
+        mirror_of(m, mi, nx, ny, pt, fx, fy);
+        xpre[u] = sin[((size_t)pt * R + r) * p3 + c];
+        const int b = c / nz;
+        if ((b == 0 && fx) || (b == 1 && fy)) {
+          xpre[u].x = -xpre[u].x;
+          xpre[u].y = -xpre[u].y;
+        }
+      }
+    }
+  };
+  int rep = blockIdx.x;
+  if (rep < npts) prefetch(rep);
+  for (; rep < npts; rep += gridDim.x) {
+    __syncthreads();  // every wavefront is done with the previous point
+#pragma unroll
+    for (int u = 0; u < kStageRegs; ++u) {
+      const int e = tid + u * nthr;
+      if (e < E) Qv[staged_of_packed(e, nz, tri)] = pre[u];
+    }
+#pragma unroll
+    for (int u = 0; u < kXRegs; ++u) {
+      const int idx = u * nthr + tid;
+      if (idx < nxe) {
+        const int v = idx / kpad, c = idx - v * kpad;
+        T *brow = Bs + ((size_t)(v >> 3) * kpad + c) * 16 + (v & 7);
+        brow[0] = xpre[u].x;
+        brow[8] = xpre[u].y;
+      }
+    }
+    const MirrorSet m = mirror_set(rep, nx, ny);
+    const int V = m.n * R;
+    if (rep + (int)gridDim.x < npts) prefetch(rep + gridDim.x);
+    __syncthreads();
+    for (int ct = 0; ct * 8 < V; ++ct) {
+      typename M::acc_t accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+      const int kb = kh * HS * 4 + kk0;  // first B row of this half
+      const T *b1p = Bs + ((size_t)ct * kpad + kb) * 16 + j;
+      const T *b2p = Bs + ((size_t)ct * kpad + kb) * 16 + (j ^ 8);
+#pragma unroll
+      for (int u = 0; u < HS; ++u) {
+        const unsigned w = (u & 1) ? (aoff[u >> 1] >> 16) : (aoff[u >> 1] & 0xffffu);
+        const v2 q = Qv[w & 0x7fffu];
+        const unsigned qm = (w & 0x8000u) << 16;
+        const T b1 = b1p[u * 64];
+        const T b2 = flip_sign(b2p[u * 64], bmask);
+        accr = M::mma(flip_sign(q.x, qm), b1, accr);
+        acci = M::mma(flip_sign(q.y, qm), b2, acci);
+      }
+      if (kh == 1) {
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) Red[(rt * 4 + qq) * 64 + lane] = accr[qq] + acci[qq];
+      }
+      __syncthreads();
+      if (kh == 0) {
+        const int v = ct * 8 + (j & 7);
+        if (v < V) {
+          const int mi = v / R, r = v - mi * R;
+          int pt;
+          bool fx, fy;
+          mirror_of(m, mi, nx, ny, pt, fx, fy);
+          T *ob = reinterpret_cast<T *>(sout + ((size_t)pt * R + r) * p3);
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq) {
+            const int orow = rt * 16 + M::row(lane, qq);
+            if (orow < p3) {
+              const int oa = orow / nz;
+              const T sg = ((oa == 0 && fx) || (oa == 1 && fy)) ? (T)-1 : (T)1;
+              ob[2 * orow + part] = sg * (accr[qq] + acci[qq] + Red[(rt * 4 + qq) * 64 + lane]);
+            }
+          }
+        }
+      }
+      __syncthreads();  // Red is reused by the next column tile
+    }
+  }
+}
+
+static int lds_nct(int R) { return (4 * R + 7) / 8; }
+
+// k-steps rounded up to a multiple of 4 (the compiled variants)
+static int lds_ns(int nz) { return 4 * (((3 * nz + 3) / 4 + 3) / 4); }
+
+static size_t lds_bytes_t(int nz, int R, size_t csize) {
+  const size_t Es = 2 * (size_t)nz * (2 * nz + 1) + 2 * nz;
+  const size_t kpad = 4 * (size_t)lds_ns(nz);
+  const size_t nrt = (3 * (size_t)nz + 15) / 16;
+  return (Es + 2) * csize + (size_t)lds_nct(R) * kpad * 16 * (csize / 2) + nrt * 256 * (csize / 2);
+}
+
+static const size_t kLdsLimit = 160 * 1024;
+
+// two wavefronts (contraction halves) per 16-row tile
+static int lds_waves(int nz) { return 2 * ((3 * nz + 15) / 16); }
+
+static bool lds_fits(int nz, int R, size_t csize) {
+  const long long E = 2LL * nz * (2 * nz + 1);
+  const int nthr = 64 * lds_waves(nz);
+  const long long nxe = (long long)lds_nct(R) * 8 * 4 * lds_ns(nz);
+  return lds_bytes_t(nz, R, csize) <= kLdsLimit && lds_ns(nz) / 2 <= kMaxHalfSteps &&
+         nthr <= 768 && E <= (long long)kStageRegs * nthr && nxe <= (long long)kXRegs * nthr &&
+         E + 2 * nz + 1 < 0x8000;
+}
+
+#define GIEM_BLOCK_VARIANTS(X, T) \
+  X(T, 4) X(T, 8) X(T, 12) X(T, 16) X(T, 20) X(T, 24) X(T, 28) X(T, 32)
+
+hipError_t set_block_lds_limits() {
+  hipError_t e = hipSuccess;
+#define GIEM_SET_ATTR(T, NS)                                                               \
+  if (e == hipSuccess)                                                                     \
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_block_pipe<T, NS>),            \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
+  GIEM_BLOCK_VARIANTS(GIEM_SET_ATTR, double)
+  GIEM_BLOCK_VARIANTS(GIEM_SET_ATTR, float)
+#undef GIEM_SET_ATTR
+  return e;
+}
+
 int block_threads(int nz, int R) {
   (void)nz;
   (void)R;
@@ -214,6 +452,23 @@ template <typename T>
 static hipError_t launch_block_t(const void *tab, const void *sin, void *sout,
                                  const unsigned *plan, int nx, int ny, int nz, int R,
                                  hipStream_t s) {
+  const size_t lds = lds_bytes_t(nz, R, sizeof(cplx<T>));
+  const int nthr = 64 * lds_waves(nz);
+  if (lds_fits(nz, R, sizeof(cplx<T>))) {
+    const long long npts = (long long)(nx + 1) * (ny + 1);
+    // persistent grid: one workgroup per CU
+    const long long grid = npts < 256 ? npts : 256;
+    const int ns = lds_ns(nz);
+#define GIEM_LAUNCH(TT, NS)                                                             \
+  if (ns == NS) {                                                                       \
+    k_block_pipe<TT, NS><<<(unsigned)grid, nthr, lds, s>>>(                              \
+        static_cast<const cplx<TT> *>(tab), static_cast<const cplx<TT> *>(sin),         \
+        static_cast<cplx<TT> *>(sout), nx, ny, nz, R, lds_nct(R));                      \
+    return hipGetLastError();                                                           \
+  }
+    GIEM_BLOCK_VARIANTS(GIEM_LAUNCH, T)
+#undef GIEM_LAUNCH
+  }
   const int ntiles = (3 * nz + 15) / 16;
   const long long waves = (long long)(nx + 1) * (ny + 1) * ntiles;
   const int per_block = 4;
