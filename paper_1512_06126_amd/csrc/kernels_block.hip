@@ -222,6 +222,14 @@ constexpr int kXRegs = 2;
 // k-steps of 4 columns per wavefront (half of 3 Nz, rounded up)
 constexpr int kMaxHalfSteps = 16;
 
+// Workgroup barrier that waits only for this wave's LDS operations: the
+// prefetch loads into registers stay in flight across it (__syncthreads()
+// would also wait for them).  Global memory is not shared between the
+// wavefronts here, so LDS ordering is all the barrier has to provide.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 __device__ __forceinline__ double flip_sign(double x, unsigned m) {
   return __hiloint2double(__double2hiint(x) ^ (int)m, __double2loint(x));
 }
@@ -284,60 +292,98 @@ k_block_pipe(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
   }
   if (tid == 0) Qv[Es] = v2{(T)0, (T)0};
   const int nxe = nct * 8 * kpad;  // input-vector elements (c, v)
+  // point-independent staging maps of this thread: LDS slot of each packed
+  // entry it carries; column v, row c (component b) and RHS of each input
+  // element, and its place in the B rows
+  int tdst[kStageRegs];
+#pragma unroll
+  for (int u = 0; u < kStageRegs; ++u) {
+    const int e = tid + u * nthr;
+    tdst[u] = e < E ? staged_of_packed(e, nz, tri) : -1;
+  }
+  int xv_[kXRegs], xc_[kXRegs], xmi_[kXRegs], xr_[kXRegs], xb_[kXRegs], xdst_[kXRegs];
+#pragma unroll
+  for (int u = 0; u < kXRegs; ++u) {
+    const int idx = u * nthr + tid;
+    const int v = idx < nxe ? idx / kpad : 1 << 20, c = idx < nxe ? idx - v * kpad : 0;
+    xv_[u] = v;
+    xc_[u] = c < p3 ? c : 0;
+    xmi_[u] = idx < nxe ? v / R : 0;
+    xr_[u] = idx < nxe ? v - (v / R) * R : 0;
+    xb_[u] = c < p3 ? c / nz : 3;  // 3: padding row
+    xdst_[u] = idx < nxe ? ((v >> 3) * kpad + c) * 16 + (v & 7) : -1;
+  }
   v2 pre[kStageRegs];
   cplx<T> xpre[kXRegs];
+  unsigned xneg = 0;  // mirror sign of each prefetched input element
+  unsigned xval = 0;  // which prefetched input elements are real (else zero)
   // loads of one point's row and input vectors into the prefetch registers
   auto prefetch = [&](int rep_) __attribute__((always_inline)) {
     const v2 *src = reinterpret_cast<const v2 *>(tab) + (size_t)rep_ * E;
 #pragma unroll
-    for (int u = 0; u < kStageRegs; ++u) {
-      const int e = tid + u * nthr;
-      if (e < E) pre[u] = src[e];
-    }
+    for (int u = 0; u < kStageRegs; ++u)
+      if (tdst[u] >= 0) pre[u] = src[tid + u * nthr];
     const MirrorSet m = mirror_set(rep_, nx, ny);
     const int V = m.n * R;
+    // the sign is applied when the element is written to LDS, so that no
+    // instruction here waits for the loads
+    // (every element is loaded, from a clamped address when it is padding,
+    // so that no register is written between the loads and their use)
+    xneg = 0;
+    xval = 0;
 #pragma unroll
     for (int u = 0; u < kXRegs; ++u) {
-      const int idx = u * nthr + tid;
-      const int v = idx / kpad, c = idx - v * kpad;
-      xpre[u] = cplx<T>{(T)0, (T)0};
-      if (idx < nxe && v < V && c < p3) {
-        const int mi = v / R, r = v - mi * R;
-        int pt;
-        bool fx, fy;
-        mirror_of(m, mi, nx, ny, pt, fx, fy);
-        xpre[u] = sin[((size_t)pt * R + r) * p3 + c];
-        const int b = c / nz;
-        if ((b == 0 && fx) || (b == 1 && fy)) {
-          xpre[u].x = -xpre[u].x;
-          xpre[u].y = -xpre[u].y;
-        }
-      }
+      const bool ok = xv_[u] < V && xb_[u] < 3;
+      int pt;
+      bool fx, fy;
+      mirror_of(m, ok ? xmi_[u] : 0, nx, ny, pt, fx, fy);
+      xpre[u] = sin[((size_t)pt * R + (ok ? xr_[u] : 0)) * p3 + xc_[u]];
+      if (ok && ((xb_[u] == 0 && fx) || (xb_[u] == 1 && fy))) xneg |= 1u << u;
+      if (ok) xval |= 1u << u;
     }
   };
   int rep = blockIdx.x;
   if (rep < npts) prefetch(rep);
   for (; rep < npts; rep += gridDim.x) {
-    __syncthreads();  // every wavefront is done with the previous point
+    lds_barrier();  // every wavefront is done with the previous point
 #pragma unroll
-    for (int u = 0; u < kStageRegs; ++u) {
-      const int e = tid + u * nthr;
-      if (e < E) Qv[staged_of_packed(e, nz, tri)] = pre[u];
-    }
+    for (int u = 0; u < kStageRegs; ++u)
+      if (tdst[u] >= 0) Qv[tdst[u]] = pre[u];
 #pragma unroll
     for (int u = 0; u < kXRegs; ++u) {
-      const int idx = u * nthr + tid;
-      if (idx < nxe) {
-        const int v = idx / kpad, c = idx - v * kpad;
-        T *brow = Bs + ((size_t)(v >> 3) * kpad + c) * 16 + (v & 7);
-        brow[0] = xpre[u].x;
-        brow[8] = xpre[u].y;
+      if (xdst_[u] >= 0) {
+        T *brow = Bs + xdst_[u];
+        const unsigned sm = ((xneg >> u) & 1u) ? 0x80000000u : 0u;
+        const bool ok = (xval >> u) & 1u;
+        brow[0] = ok ? flip_sign(xpre[u].x, sm) : (T)0;
+        brow[8] = ok ? flip_sign(xpre[u].y, sm) : (T)0;
       }
     }
     const MirrorSet m = mirror_set(rep, nx, ny);
     const int V = m.n * R;
-    if (rep + (int)gridDim.x < npts) prefetch(rep + gridDim.x);
-    __syncthreads();
+    // the next point's loads are issued one per k-step of the first column
+    // tile below, so that waiting for queue space overlaps the MFMAs
+    const int nrep = rep + (int)gridDim.x;
+    const bool more = nrep < npts;
+    const v2 *nsrc = reinterpret_cast<const v2 *>(tab) + (size_t)(more ? nrep : rep) * E;
+    int xaddr[kXRegs];
+    {
+      const MirrorSet mn = mirror_set(more ? nrep : rep, nx, ny);
+      const int Vn = mn.n * R;
+      xneg = 0;
+      xval = 0;
+#pragma unroll
+      for (int u = 0; u < kXRegs; ++u) {
+        const bool ok = xv_[u] < Vn && xb_[u] < 3;
+        int pt;
+        bool fx, fy;
+        mirror_of(mn, ok ? xmi_[u] : 0, nx, ny, pt, fx, fy);
+        xaddr[u] = (pt * R + (ok ? xr_[u] : 0)) * p3 + xc_[u];
+        if (ok && ((xb_[u] == 0 && fx) || (xb_[u] == 1 && fy))) xneg |= 1u << u;
+        if (ok) xval |= 1u << u;
+      }
+    }
+    lds_barrier();
     for (int ct = 0; ct * 8 < V; ++ct) {
       typename M::acc_t accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
       const int kb = kh * HS * 4 + kk0;  // first B row of this half
@@ -345,6 +391,14 @@ k_block_pipe(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
       const T *b2p = Bs + ((size_t)ct * kpad + kb) * 16 + (j ^ 8);
 #pragma unroll
       for (int u = 0; u < HS; ++u) {
+        if (ct == 0 && more) {
+          // prefetch slot u: packed entries first, then input elements
+          if (u < kStageRegs) {
+            if (tdst[u] >= 0) pre[u] = nsrc[tid + u * nthr];
+          } else if (u - kStageRegs < kXRegs) {
+            xpre[u - kStageRegs] = sin[xaddr[u - kStageRegs]];
+          }
+        }
         const unsigned w = (u & 1) ? (aoff[u >> 1] >> 16) : (aoff[u >> 1] & 0xffffu);
         const v2 q = Qv[w & 0x7fffu];
         const unsigned qm = (w & 0x8000u) << 16;
@@ -353,11 +407,21 @@ k_block_pipe(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
         accr = M::mma(flip_sign(q.x, qm), b1, accr);
         acci = M::mma(flip_sign(q.y, qm), b2, acci);
       }
+      if (ct == 0 && more) {
+#pragma unroll
+        for (int u = HS; u < kStageRegs + kXRegs; ++u) {
+          if (u < kStageRegs) {
+            if (tdst[u] >= 0) pre[u] = nsrc[tid + u * nthr];
+          } else {
+            xpre[u - kStageRegs] = sin[xaddr[u - kStageRegs]];
+          }
+        }
+      }
       if (kh == 1) {
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) Red[(rt * 4 + qq) * 64 + lane] = accr[qq] + acci[qq];
       }
-      __syncthreads();
+      lds_barrier();
       if (kh == 0) {
         const int v = ct * 8 + (j & 7);
         if (v < V) {
@@ -377,7 +441,7 @@ k_block_pipe(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
           }
         }
       }
-      __syncthreads();  // Red is reused by the next column tile
+      lds_barrier();  // Red is reused by the next column tile
     }
   }
 }
