@@ -163,6 +163,21 @@ class Profile:
             v = self.coef[:, o] * np.exp(-e * (z - zl)) + self.coef[:, o + 1] * np.exp(-e * (zr - z))
         return v + self.part[:, k]
 
+    def deriv(self, z, side=0):
+        """d/dz Psi(z) on the interval chosen by side (one-sided at a
+        breakpoint: -1 left, +1 right)."""
+        k = self._interval(z, side)
+        o = self.offs[k]
+        e = self.eta[:, k]
+        nb = self.B.size
+        if k == 0:
+            return e * self.coef[:, o] * np.exp(-e * (self.B[0] - z))
+        if k == nb:
+            return -e * self.coef[:, o] * np.exp(-e * (z - self.B[-1]))
+        zl, zr = self.B[k - 1], self.B[k]
+        return (-e * self.coef[:, o] * np.exp(-e * (z - zl))
+                + e * self.coef[:, o + 1] * np.exp(-e * (zr - z)))
+
     def integral(self, a, b):
         """int_a^b Psi(z) dz, a < b, splitting at breakpoints."""
         cuts = [a] + [x for x in self.B if a < x < b] + [b]

@@ -1,10 +1,12 @@
-"""Zero-order Hankel transforms used by the coefficient tables (Appendix A:
-the horizontal integrals of J0(lambda rho) against functions of lambda).
+"""Hankel transforms used by the coefficient tables and the receiver kernels
+(Appendix A: the horizontal integrals of J0(lambda rho) against functions of
+lambda; J1 gives their radial derivatives for the fields at receivers).
 
-  h(rho) = int_0^inf J0(lambda rho) g(lambda) dlambda
+  h(rho) = int_0^inf J0(lambda rho) g(lambda) dlambda   (order 0)
+  h1(rho) = int_0^inf J1(lambda rho) g(lambda) dlambda  (order 1)
 
 computed the plain way: Gauss-Legendre panels between consecutive zeros of
-J0(lambda rho) (a geometric subdivision of the first panel resolves the
+J0 (or J1) (a geometric subdivision of the first panel resolves the
 structure of g at small lambda), and the oscillating algebraic tail beyond
 the last panels summed by repeated pairwise averaging of the partial sums
 (Euler's transform of an alternating series).
@@ -83,15 +85,16 @@ def _averaged_limit(S, levels=14):
     return T[-1]
 
 
-def transform_weights(lp, rho, lam_a, lam_lo, lam_asym, ntail=30, n_gl=16):
+def transform_weights(lp, rho, lam_a, lam_lo, lam_asym, ntail=30, n_gl=16, order=0):
     """Weights over the samples of lp (LogPanels in lambda) such that
-      main @ g  = int over [lam_lo, lambda_K] of J0(lambda rho) g
+      main @ g  = int over [lam_lo, lambda_K] of J_order(lambda rho) g
       tail[k] @ g = integral over the k-th panel after lambda_K,
       corr @ g  = int over [lam_lo, lam_a] of g (for the regularised kind).
-    lambda_K is the first J0 zero beyond lam_asym."""
+    lambda_K is the first zero of J_order beyond lam_asym."""
     ncols = lp.size
+    jn = special.j0 if order == 0 else special.j1
     K = int(np.ceil(lam_asym * rho / np.pi)) + 1
-    zeros = special.jn_zeros(0, K + ntail + 1) / rho
+    zeros = special.jn_zeros(order, K + ntail + 1) / rho
     l1 = zeros[0]
     # geometric subpanels of [lam_lo, l1], with lam_a as a breakpoint
     brk = [l1]
@@ -115,7 +118,7 @@ def transform_weights(lp, rho, lam_a, lam_lo, lam_asym, ntail=30, n_gl=16):
         nod1 = np.zeros(0)
         w1 = np.zeros(0)
     nodes = np.concatenate([nod0, nod1])
-    wts = np.concatenate([w0, w1]) * special.j0(nodes * rho)
+    wts = np.concatenate([w0, w1]) * jn(nodes * rho)
     main = np.zeros(ncols)
     cols, iw = lp.interp_rows(nodes)
     np.add.at(main, cols.ravel(), (wts[:, None] * iw).ravel())
@@ -130,21 +133,23 @@ def transform_weights(lp, rho, lam_a, lam_lo, lam_asym, ntail=30, n_gl=16):
     for k in range(ntail):
         a, b = zeros[K - 1 + k], zeros[K + k]
         nd = 0.5 * (a + b) + 0.5 * (b - a) * xg2
-        ww = 0.5 * (b - a) * wg2 * special.j0(nd * rho)
+        ww = 0.5 * (b - a) * wg2 * jn(nd * rho)
         c3, i3 = lp.interp_rows(nd)
         np.add.at(tail[k], c3.ravel(), (ww[:, None] * i3).ravel())
     return main, tail, corr
 
 
-def hankel_on_grid(G, lp, rhos, reg, lam_a, lam_lo, lam_asym, ntail=30):
-    """h[rho, f] = int J0(lambda rho) G[lambda, f] dlambda, with the
-    regularisation applied to the functions where reg[f] is True.  G holds the
-    samples of g on lp's nodes, shape [lp.size, F]."""
+def hankel_on_grid(G, lp, rhos, reg, lam_a, lam_lo, lam_asym, ntail=30, order=0):
+    """h[rho, f] = int J_order(lambda rho) G[lambda, f] dlambda, with the
+    regularisation (order 0 only) applied to the functions where reg[f] is
+    True.  G holds the samples of g on lp's nodes, shape [lp.size, F]."""
     G = np.asarray(G)
     out = np.zeros((len(rhos), G.shape[1]), dtype=np.complex128)
     corr_val = None
+    if order != 0:
+        reg = np.zeros(G.shape[1], bool)
     for ir, rho in enumerate(rhos):
-        main, tail, corr = transform_weights(lp, rho, lam_a, lam_lo, lam_asym, ntail)
+        main, tail, corr = transform_weights(lp, rho, lam_a, lam_lo, lam_asym, ntail, order=order)
         if corr_val is None:
             corr_val = corr @ G
         s0 = main @ G

@@ -65,3 +65,31 @@ def cell_pair(lo_n, hi_n, lo_m, hi_m, sigma, freq, q=8):
         G = greens_e(r, sigma, freq)
         out += np.einsum("i,j,ijab->ab", wn[i:i + 64], wm, G)
     return out
+
+
+def greens_h(r, sigma, freq):
+    """G^H = curl_r G^E / (i w mu0) at separation vectors r [..., 3]:
+    G^H_ab = eps_acb d_c g (the field of a unit current element)."""
+    k = wavenumber(sigma, freq)
+    R = np.linalg.norm(r, axis=-1)
+    g1 = np.exp(1j * k * R) / (4 * np.pi * R) * (1j * k - 1.0 / R)   # dg/dR
+    grad = r / R[..., None] * g1[..., None]                          # d_c g
+    out = np.zeros(r.shape[:-1] + (3, 3), complex)
+    gx, gy, gz = grad[..., 0], grad[..., 1], grad[..., 2]
+    out[..., 0, 1] = -gz
+    out[..., 0, 2] = gy
+    out[..., 1, 0] = gz
+    out[..., 1, 2] = -gx
+    out[..., 2, 0] = -gy
+    out[..., 2, 1] = gx
+    return out
+
+
+def point_box(p, lo, hi, sigma, freq, q=12):
+    """int over the box [lo, hi] of G^E(p - r') and G^H(p - r') for a point p
+    outside the box: tensor Gauss-Legendre, ([3, 3], [3, 3])."""
+    lo, hi, p = map(np.asarray, (lo, hi, p))
+    pm, wm = _box_nodes(lo, hi, q)
+    r = p[None, :] - pm
+    return (np.einsum("i,iab->ab", wm, greens_e(r, sigma, freq)),
+            np.einsum("i,iab->ab", wm, greens_h(r, sigma, freq)))
