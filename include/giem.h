@@ -206,15 +206,25 @@ int giem_adjoint(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrh
                  const giem_solve_opts *opts, giem_solve_stats *stats, void *stream);
 
 /*
- * giem_fields -- electric and magnetic fields at receivers on the surface
- * (z = 0, the horizontal components are continuous there) from the cell
- * field (Sect. 2.2, field recovery):
+ * giem_fields -- electric and magnetic fields at receivers on the earth's
+ * surface from the cell field (Sect. 2.2, the representation of the fields
+ * through G^E and G^H integrated over the cells; Appendix A):
  *   e(r) = E^N(r) + sum_n (sa_n - sb_n) [int_{cell n} G^E(r, M0) dM0] E_n,
- *   h(r) = H^N(r) + sum_n (sa_n - sb_n) [int_{cell n} G^H(r, M0) dM0] E_n.
- *   rec_xy: host [nrec][2] receiver positions (x, y) in m;
- *   E_cells: device c128 [nrhs][3][Nz][Ny][Nx];
- *   E_rec, H_rec: device c128 [nrhs][nrec][3].
- *   E^N, H^N are the plane-wave fields of RHS 0 (x pol.) and 1 (y pol.).
+ *   h(r) = H^N(r) + sum_n (sa_n - sb_n) [int_{cell n} G^H(r, M0) dM0] E_n,
+ * with G^H = curl G^E / (i w mu0).  The horizontal E and all of H are
+ * continuous across the surface; E_z is the value at the surface on the
+ * earth side when the air is insulating (there sigma E_z + j_z = 0).
+ *   sigma_a: device c128 [Nz][Ny][Nx];
+ *   E_cells: device c128 [nrhs][3][Nz][Ny][Nx] (E = U / a, as from giem_solve);
+ *   rec_xy:  host [nrec][2] receiver positions (x, y) in m; every receiver
+ *            must lie above the centre of a cell of the grid;
+ *   E_rec, H_rec: device c128 [nrhs][nrec][3] outputs.
+ * E^N, H^N (1 V/m plane wave) are added for RHS 0 (x polarisation) and RHS 1
+ * (y polarisation); further RHS get the anomalous fields only.  The cell
+ * integrals for every receiver offset are computed on the first call for a
+ * frequency and kept on the handle.  Synchronises the stream.
+ * Errors: EINVAL, EDOMAIN (receiver not above a cell centre, or the grid does
+ * not start at the surface d[0]), ENOMEM, EHIP.
  */
 int giem_fields(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
                 const void *E_cells, int32_t nrec, const double *rec_xy, void *E_rec,

@@ -361,6 +361,7 @@ void giem_free(giem_handle *t) {
   for (auto &ft : t->f) {
     if (ft.spec64) hipFree(ft.spec64);
     if (ft.spec32) hipFree(ft.spec32);
+    if (ft.rec_kernel) hipFree(ft.rec_kernel);
   }
   void *dev[] = {t->px.tw64, t->px.tw32, t->py.tw64, t->py.tw32, t->cs_x, t->cs_y, t->bplan,
                  t->sb_lev, t->vol_lev, t->sroot_lev, t->diag, t->spec_ws, t->red_part,

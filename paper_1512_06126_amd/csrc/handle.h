@@ -26,6 +26,7 @@ struct FreqTables {
   void *spec64 = nullptr;      // c128 [(Ny+1)(Nx+1)][E] packed spectra
   void *spec32 = nullptr;      // c64 copy (GIEM_TABLES_C64)
   std::vector<cd> spatial;     // packed spatial table [Ny][Nx][E] (host)
+  void *rec_kernel = nullptr;  // receiver kernels (giem_fields), built on first use
 };
 
 struct SolveWork;
@@ -89,5 +90,7 @@ int plane_wave_levels(const giem_handle *t, double freq, std::vector<cd> &en_lev
                       std::vector<cd> &hsurf);
 // packed spatial tables of every frequency of the handle (t->f[q].spatial)
 int compute_tables(giem_handle *t, hipStream_t s);
+// receiver kernels of frequency ifreq (device, owned by the caller)
+int compute_receiver_kernels(giem_handle *t, int ifreq, void **out, hipStream_t s);
 
 }  // namespace giem

@@ -43,6 +43,11 @@ hipError_t launch_adjoint_grad(const c128 *sigma_a, const c128 *sb_lev, const c1
                                const c128 *g, const c128 *E, const c128 *lam, const c128 *w,
                                int nrhs, int nx, int ny, int nz, double *grad, hipStream_t s);
 
+// fields at receivers above cell centres (kernels_tables.hip)
+hipError_t launch_fields(const c128 *K, const c128 *E, const c128 *sa, const c128 *sb_lev,
+                         const int *rec, int nrec, int nrhs, int nx, int ny, int nz,
+                         const c128 *en_hn, c128 *Erec, c128 *Hrec, hipStream_t s);
+
 // Krylov vector kernels (kernels_vec.hip); vectors of n = 3 Nz Ny Nx complex.
 struct DotArgs {
   const c128 *w[kMaxRhs];      // vector to project

@@ -102,7 +102,118 @@ __global__ void k_assemble(const c128 *__restrict__ c0, const c128 *__restrict__
   out[idx] = v;
 }
 
+// Receiver kernels: c[kind][off][f nz + jz] (kinds B0, BX, BY, BXX, BYY, BXY;
+// functions A1, A2, dA1, A4/s, A5/s, A6/s, P, Q) -> out[off][jz][18], G^E then
+// G^H row-major (row = field component at the receiver):
+//   4pi E: xx = i w mu0 B0 A1 + BXX P, yy = i w mu0 B0 A1 + BYY P,
+//          xy = yx = BXY P, xz = BX A4, yz = BY A4, zx = -BX A5,
+//          zy = -BY A5, zz = B0 A6
+//   4pi H: xx = BXY Q, yx = B0 dA1 - BXX Q, zx = -BY A1, xy = BYY Q - B0 dA1,
+//          yy = -BXY Q, zy = BX A1, xz = BY A2, yz = -BX A2, zz = 0
+__global__ void k_assemble_rec(const c128 *__restrict__ c, c128 *__restrict__ out, int noff,
+                               int nz, double omega_mu0) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)noff * nz) return;
+  const int o = (int)(idx / nz), jz = (int)(idx - (int64_t)o * nz);
+  const int nf = 8 * nz;
+  auto at = [&](int kind, int f) { return c[((int64_t)kind * noff + o) * nf + f * nz + jz]; };
+  const double q = 0.25 / 3.14159265358979323846;
+  auto sc = [&](c128 v, double f) { return mk<double>(q * f * v.x, q * f * v.y); };
+  auto add = [&](c128 a, c128 b) { return mk<double>(a.x + b.x, a.y + b.y); };
+  auto sub = [&](c128 a, c128 b) { return mk<double>(a.x - b.x, a.y - b.y); };
+  auto iw = [&](c128 v) { return mk<double>(-omega_mu0 * v.y, omega_mu0 * v.x); };
+  enum { B0 = 0, BX, BY, BXX, BYY, BXY };
+  enum { A1 = 0, A2, DA1, A4, A5, A6, P, Q };
+  c128 *r = out + idx * 18;
+  const c128 zero = mk<double>(0.0, 0.0);
+  r[0] = sc(add(iw(at(B0, A1)), at(BXX, P)), 1.0);
+  r[1] = sc(at(BXY, P), 1.0);
+  r[2] = sc(at(BX, A4), 1.0);
+  r[3] = sc(at(BXY, P), 1.0);
+  r[4] = sc(add(iw(at(B0, A1)), at(BYY, P)), 1.0);
+  r[5] = sc(at(BY, A4), 1.0);
+  r[6] = sc(at(BX, A5), -1.0);
+  r[7] = sc(at(BY, A5), -1.0);
+  r[8] = sc(at(B0, A6), 1.0);
+  r[9] = sc(at(BXY, Q), 1.0);
+  r[10] = sc(sub(at(BYY, Q), at(B0, DA1)), 1.0);
+  r[11] = sc(at(BY, A2), 1.0);
+  r[12] = sc(sub(at(B0, DA1), at(BXX, Q)), 1.0);
+  r[13] = sc(at(BXY, Q), -1.0);
+  r[14] = sc(at(BX, A2), -1.0);
+  r[15] = sc(at(BY, A1), -1.0);
+  r[16] = sc(at(BX, A1), 1.0);
+  r[17] = zero;
+}
+
+// Fields at receivers above cell centres: one workgroup per (receiver, RHS);
+// every thread sums the kernels against the currents (sa - sb) E of a
+// stride of cells, then the workgroup reduces.
+__global__ void __launch_bounds__(256)
+k_fields(const c128 *__restrict__ K, const c128 *__restrict__ E, const c128 *__restrict__ sa,
+         const c128 *__restrict__ sb_lev, const int *__restrict__ rec, int nrec, int nx, int ny,
+         int nz, const c128 *__restrict__ en_hn, c128 *__restrict__ Erec, c128 *__restrict__ Hrec) {
+  const int q = blockIdx.x, r = blockIdx.y;
+  const int ir = rec[2 * q], jr = rec[2 * q + 1];
+  const size_t plane = (size_t)nx * ny, N = plane * nz;
+  const c128 *Er = E + (size_t)r * 3 * N;
+  double acc[12];
+  for (int i = 0; i < 12; ++i) acc[i] = 0.0;
+  for (size_t n = threadIdx.x; n < N; n += blockDim.x) {
+    const int iz = (int)(n / plane);
+    const size_t rem = n - (size_t)iz * plane;
+    const int iy = (int)(rem / nx), ix = (int)(rem - (size_t)iy * nx);
+    const c128 ds = csub(sa[n], sb_lev[iz]);
+    const c128 cu[3] = {cmul(ds, Er[n]), cmul(ds, Er[N + n]), cmul(ds, Er[2 * N + n])};
+    const size_t off = (size_t)(jr - iy + ny - 1) * (2 * nx - 1) + (ir - ix + nx - 1);
+    const c128 *k = K + (off * nz + iz) * 18;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      c128 s = mk<double>(0.0, 0.0);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) cfma(s, k[3 * a + b], cu[b]);
+      acc[2 * a] += s.x;
+      acc[2 * a + 1] += s.y;
+    }
+  }
+  __shared__ double red[256][13];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) red[threadIdx.x][i] = acc[i];
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int i = 0; i < 12; ++i) red[threadIdx.x][i] += red[threadIdx.x + w][i];
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) {
+    const int a = threadIdx.x;
+    const c128 nf = en_hn[r * 6 + a];
+    const c128 v = mk<double>(red[0][2 * a] + nf.x, red[0][2 * a + 1] + nf.y);
+    if (a < 3)
+      Erec[((size_t)r * nrec + q) * 3 + a] = v;
+    else
+      Hrec[((size_t)r * nrec + q) * 3 + (a - 3)] = v;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_assemble_rec(const c128 *c, c128 *out, int noff, int nz, double omega_mu0,
+                               hipStream_t s) {
+  const int64_t total = (int64_t)noff * nz;
+  hipLaunchKernelGGL(k_assemble_rec, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, c,
+                     out, noff, nz, omega_mu0);
+  return hipGetLastError();
+}
+
+hipError_t launch_fields(const c128 *K, const c128 *E, const c128 *sa, const c128 *sb_lev,
+                         const int *rec, int nrec, int nrhs, int nx, int ny, int nz,
+                         const c128 *en_hn, c128 *Erec, c128 *Hrec, hipStream_t s) {
+  if (nrec <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fields, dim3(nrec, nrhs), dim3(256), 0, s, K, E, sa, sb_lev, rec, nrec, nx,
+                     ny, nz, en_hn, Erec, Hrec);
+  return hipGetLastError();
+}
 
 hipError_t launch_gemm_tn(const double *At, int64_t lda, const double *B, int64_t ldb, double *C,
                           int64_t ldc, int m, int n, int k, hipStream_t s) {

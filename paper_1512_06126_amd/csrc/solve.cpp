@@ -644,8 +644,64 @@ int giem_adjoint(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrh
 extern "C" int giem_fields(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
                            const void *E_cells, int32_t nrec, const double *rec_xy, void *E_rec,
                            void *H_rec, void *stream) {
-  (void)t; (void)ifreq; (void)sigma_a; (void)nrhs; (void)E_cells; (void)nrec; (void)rec_xy;
-  (void)E_rec; (void)H_rec; (void)stream;
-  giem::set_error("giem_fields: receiver tables are not available in this build yet");
-  return GIEM_EINVAL;
+  using namespace giem;
+  if (!t || ifreq < 0 || ifreq >= (int)t->f.size() || !sigma_a || nrhs < 1 || !E_cells ||
+      nrec < 0 || (nrec > 0 && (!rec_xy || !E_rec || !H_rec))) {
+    set_error("giem_fields: bad argument");
+    return GIEM_EINVAL;
+  }
+  if (nrec == 0) return GIEM_OK;
+  if (std::fabs(t->z_edges[0] - t->d[0]) > 1e-9 * (t->z_edges[t->nz] - t->z_edges[0])) {
+    set_error("giem_fields: the anomaly grid must start at the earth's surface d[0]");
+    return GIEM_EDOMAIN;
+  }
+  // receivers above cell centres: lattice indices
+  std::vector<int> idx(2 * (size_t)nrec);
+  for (int q = 0; q < nrec; ++q) {
+    const double fx = (rec_xy[2 * q] - t->x0) / t->hx - 0.5;
+    const double fy = (rec_xy[2 * q + 1] - t->y0) / t->hy - 0.5;
+    const double ix = std::round(fx), iy = std::round(fy);
+    if (std::fabs(fx - ix) > 1e-9 || std::fabs(fy - iy) > 1e-9 || ix < 0 || ix >= t->nx ||
+        iy < 0 || iy >= t->ny) {
+      set_error("giem_fields: receivers must lie above cell centres of the grid");
+      return GIEM_EDOMAIN;
+    }
+    idx[2 * q] = (int)ix;
+    idx[2 * q + 1] = (int)iy;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  FreqTables &ft = t->f[ifreq];
+  if (!ft.rec_kernel) GIEM_TRY(compute_receiver_kernels(t, ifreq, &ft.rec_kernel, s));
+  // normal fields at the surface: RHS 0 x polarisation, RHS 1 y polarisation
+  std::vector<cd> en_lev, hsurf;
+  GIEM_TRY(plane_wave_levels(t, ft.freq, en_lev, hsurf));
+  const cd hy = hsurf[0];
+  std::vector<c128> nf((size_t)nrhs * 6, mk<double>(0.0, 0.0));
+  if (nrhs >= 1) {
+    nf[0] = mk<double>(1.0, 0.0);
+    nf[4] = mk<double>(hy.real(), hy.imag());
+  }
+  if (nrhs >= 2) {
+    nf[6 + 1] = mk<double>(1.0, 0.0);
+    nf[6 + 3] = mk<double>(-hy.real(), -hy.imag());
+  }
+  void *drec = nullptr, *dnf = nullptr;
+  int rc = GIEM_OK;
+  if (check_hip(hipMalloc(&drec, idx.size() * sizeof(int)), "hipMalloc receivers") ||
+      check_hip(hipMalloc(&dnf, nf.size() * sizeof(c128)), "hipMalloc normal fields") ||
+      check_hip(hipMemcpyAsync(drec, idx.data(), idx.size() * sizeof(int), hipMemcpyHostToDevice, s),
+                "copy receivers") ||
+      check_hip(hipMemcpyAsync(dnf, nf.data(), nf.size() * sizeof(c128), hipMemcpyHostToDevice, s),
+                "copy normal fields") ||
+      check_hip(launch_fields(static_cast<const c128 *>(ft.rec_kernel),
+                              static_cast<const c128 *>(E_cells), static_cast<const c128 *>(sigma_a),
+                              static_cast<const c128 *>(t->sb_lev), static_cast<const int *>(drec),
+                              nrec, nrhs, t->nx, t->ny, t->nz, static_cast<const c128 *>(dnf),
+                              static_cast<c128 *>(E_rec), static_cast<c128 *>(H_rec), s),
+                "fields kernel") ||
+      check_hip(hipStreamSynchronize(s), "fields"))
+    rc = GIEM_EHIP;
+  if (drec) hipFree(drec);
+  if (dnf) hipFree(dnf);
+  return rc;
 }

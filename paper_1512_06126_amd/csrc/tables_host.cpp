@@ -51,6 +51,8 @@ hipError_t launch_gemm_tn(const double *At, int64_t lda, const double *B, int64_
                           int64_t ldc, int m, int n, int k, hipStream_t s);
 hipError_t launch_assemble(const c128 *c0, const c128 *c1, const c128 *c2, c128 *out, int nx,
                            int ny, int nz, double omega_mu0, hipStream_t s);
+hipError_t launch_assemble_rec(const c128 *c, c128 *out, int noff, int nz, double omega_mu0,
+                               hipStream_t s);
 
 namespace {
 
@@ -139,6 +141,43 @@ struct LogGrid {
     } else {
       for (int j = 0; j < n; ++j) w[j] /= tot;
     }
+    return (size_t)p * n;
+  }
+  // d f / d x at xq: weights over the same n nodes (derivative of the panel's
+  // interpolating polynomial in u = ln x, divided by x)
+  size_t interp_deriv(double xq, double *w) const {
+    const double u = std::log(xq);
+    const int np = (int)edges.size() - 1;
+    int p = (int)(std::upper_bound(edges.begin(), edges.end(), u) - edges.begin()) - 1;
+    p = std::min(std::max(p, 0), np - 1);
+    const double width = edges[p + 1] - edges[p];
+    const double s = (2.0 * u - (edges[p] + edges[p + 1])) / width;
+    const double scale = 2.0 / width / xq;  // ds/du * du/dx
+    int hit = -1;
+    for (int j = 0; j < n; ++j)
+      if (std::fabs(s - node[j]) < 1e-14) hit = j;
+    if (hit >= 0) {
+      // row of the barycentric differentiation matrix
+      double diag = 0.0;
+      for (int j = 0; j < n; ++j) {
+        if (j == hit) continue;
+        w[j] = (bw[j] / bw[hit]) / (node[hit] - node[j]);
+        diag -= w[j];
+      }
+      w[hit] = diag;
+    } else {
+      double D = 0.0, Dd = 0.0;
+      double a[32], ad[32];
+      for (int j = 0; j < n; ++j) {
+        const double d = s - node[j];
+        a[j] = bw[j] / d;
+        ad[j] = -bw[j] / (d * d);
+        D += a[j];
+        Dd += ad[j];
+      }
+      for (int j = 0; j < n; ++j) w[j] = ad[j] / D - a[j] * Dd / (D * D);
+    }
+    for (int j = 0; j < n; ++j) w[j] *= scale;
     return (size_t)p * n;
   }
 };
@@ -416,6 +455,129 @@ void spatial_matrix(const giem_handle *t, const Grids &g, std::vector<double> &M
   });
 }
 
+// ------------------------------------------- receiver (point) rules
+// A receiver above the centre of a cell at lateral offset (dx, dy) from the
+// centre of the source cell sees the source footprint B = [-hx/2, hx/2] x
+// [-hy/2, hy/2]: the plain terms need int_B h(|D - r'|) d^2 r', the i kx /
+// i ky terms the line measures d_x B (faces x = -hx/2 with +1, x = +hx/2
+// with -1) and d_y B, and the kx^2, ky^2, kx ky terms the same faces against
+// -d h / d x or -d h / d y (derivative weights).
+enum { R_B0 = 0, R_BX, R_BY, R_BXX, R_BYY, R_BXY, R_COUNT };
+
+struct RulePtsD {
+  std::vector<double> rho, w;
+  std::vector<char> deriv;
+  void add(double r, double wt, bool d) {
+    rho.push_back(r);
+    w.push_back(wt);
+    deriv.push_back(d ? 1 : 0);
+  }
+};
+
+// int over [x0,x1] x [y0,y1] of h(|D - r'|); singular only at a vertex
+static void box_piece(double dx, double dy, double x0, double x1, double y0, double y1, double h,
+                      const Rule &gs, const Rule &g14, const Rule &g8, RulePtsD &out) {
+  const double tol = 1e-9 * h;
+  int sing = -1;
+  const double vx[2] = {x0, x1}, vy[2] = {y0, y1};
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      if (std::fabs(vx[a] - dx) < tol && std::fabs(vy[b] - dy) < tol) sing = 2 * a + b;
+  if (sing >= 0) {
+    const double px = vx[sing >> 1], py = vy[sing & 1];
+    const double ox = vx[1 - (sing >> 1)], oy = vy[1 - (sing & 1)];
+    const double ax[2] = {ox, px}, ay[2] = {py, oy};
+    const int n = (int)gs.x.size();
+    for (int tri = 0; tri < 2; ++tri) {
+      const double e1x = ax[tri] - px, e1y = ay[tri] - py;
+      const double e2x = ox - ax[tri], e2y = oy - ay[tri];
+      const double det = std::fabs(e1x * e2y - e1y * e2x);
+      for (int i = 0; i < n; ++i) {
+        const double sv = 0.5 * (gs.x[i] + 1.0), ws = 0.5 * gs.w[i];
+        const double r = sv * sv, wr = ws * 2.0 * sv;
+        for (int j = 0; j < n; ++j) {
+          const double tt = 0.5 * (gs.x[j] + 1.0), wt = 0.5 * gs.w[j];
+          const double u = px + r * (e1x + tt * e2x), v = py + r * (e1y + tt * e2y);
+          out.add(std::hypot(dx - u, dy - v), wr * wt * r * det, false);
+        }
+      }
+    }
+    return;
+  }
+  const double dist = std::hypot(std::max({x0 - dx, 0.0, dx - x1}), std::max({y0 - dy, 0.0, dy - y1}));
+  const Rule &rr = dist < 2.0 * h ? g14 : g8;
+  const int split = dist < 0.5 * h ? 3 : 1;
+  const int n = (int)rr.x.size();
+  for (int a = 0; a < split; ++a)
+    for (int b = 0; b < split; ++b) {
+      const double xa = x0 + (x1 - x0) * a / split, xb = x0 + (x1 - x0) * (a + 1) / split;
+      const double ya = y0 + (y1 - y0) * b / split, yb = y0 + (y1 - y0) * (b + 1) / split;
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+          const double u = 0.5 * (xa + xb) + 0.5 * (xb - xa) * rr.x[i];
+          const double v = 0.5 * (ya + yb) + 0.5 * (yb - ya) * rr.x[j];
+          out.add(std::hypot(dx - u, dy - v), 0.25 * (xb - xa) * (yb - ya) * rr.w[i] * rr.w[j],
+                  false);
+        }
+    }
+}
+
+static void receiver_rule(int kind, double dx, double dy, double hx, double hy, const Rule &gs,
+                          const Rule &g14, const Rule &g8, const Rule &gl, RulePtsD &out) {
+  if (kind == R_B0) {
+    // split the footprint at the receiver's projection
+    double xs[3] = {-hx / 2, 0, hx / 2}, ys[3] = {-hy / 2, 0, hy / 2};
+    int nxs = 2, nys = 2;
+    xs[1] = hx / 2;
+    ys[1] = hy / 2;
+    if (dx > -hx / 2 && dx < hx / 2) {
+      xs[1] = dx;
+      xs[2] = hx / 2;
+      nxs = 3;
+    }
+    if (dy > -hy / 2 && dy < hy / 2) {
+      ys[1] = dy;
+      ys[2] = hy / 2;
+      nys = 3;
+    }
+    for (int a = 0; a + 1 < nxs; ++a)
+      for (int b = 0; b + 1 < nys; ++b)
+        box_piece(dx, dy, xs[a], xs[a + 1], ys[b], ys[b + 1], std::min(hx, hy), gs, g14, g8, out);
+    return;
+  }
+  const bool xface = kind == R_BX || kind == R_BXX || kind == R_BXY;
+  const int n = (int)gl.x.size();
+  for (int side = 0; side < 2; ++side) {
+    const double sgn = side == 0 ? 1.0 : -1.0;
+    const double fpos = (side == 0 ? -0.5 : 0.5) * (xface ? hx : hy);
+    const double half = 0.5 * (xface ? hy : hx);
+    const double dn = xface ? dx : dy;  // normal coordinate of the receiver
+    const double dt = xface ? dy : dx;  // running coordinate
+    double cuts[3] = {-half, half, half};
+    int nc = 2;
+    if (dt > -half && dt < half) {
+      cuts[1] = dt;
+      cuts[2] = half;
+      nc = 3;
+    }
+    for (int piece = 0; piece + 1 < nc; ++piece) {
+      const double a = cuts[piece], b = cuts[piece + 1];
+      for (int i = 0; i < n; ++i) {
+        const double t = 0.5 * (a + b) + 0.5 * (b - a) * gl.x[i];
+        const double w = sgn * 0.5 * (b - a) * gl.w[i];
+        const double rho = std::hypot(dn - fpos, dt - t);
+        if (kind == R_BX || kind == R_BY) {
+          out.add(rho, w, false);
+        } else if (kind == R_BXX || kind == R_BYY) {
+          out.add(rho, -w * (dn - fpos) / rho, true);  // -dh/drho (normal) / rho
+        } else {
+          out.add(rho, -w * (dt - t) / rho, true);     // kx ky: running direction
+        }
+      }
+    }
+  }
+}
+
 // ----------------------------------------------------- vertical functions
 typedef std::complex<double> cx;
 
@@ -481,10 +643,18 @@ struct Vertical {
     }
   }
 
-  void row(double lam, cx *out) const {
+  // per-cell factors of both kinds (k = 0: gamma = 1, k = 1: gamma = sigma)
+  struct Cell {
+    cx theta, FI, FD, GI, GD, diagA, diagA4, diagA3, diagA6;
+    cx thetad;  // F'(top) / F(bottom): the top cell's ratio differentiated at its top
+    cx GId;     // d/dz of int_cell U(z, z*) dz* at the cell's top edge
+    cx GDd;     // d/dz of U(z, bottom) - U(z, top) at the top edge (regular part)
+  };
+
+  void factors(double lam, std::vector<Cell> (&cell)[2]) const {
     const int nl = t->nlay;
     const int nlayers = nl + 1;
-    std::vector<cx> eta(nlayers), gam(nlayers);
+    std::vector<cx> eta(nlayers);
     std::vector<double> L(nlayers);
     for (int n = 0; n < nlayers; ++n) {
       cx e = std::sqrt(cx(lam * lam, 0.0) - cx(0.0, omega * kMu0) * t->sigma[n]);
@@ -492,8 +662,6 @@ struct Vertical {
       eta[n] = e;
       L[n] = (n >= 1 && n < nl) ? t->d[n] - t->d[n - 1] : INFINITY;
     }
-    const int T = nz * (nz + 1) / 2;
-    // both kinds: k = 0 (gamma = 1), k = 1 (gamma = sigma)
     std::vector<cx> p[2], q[2];
     for (int k = 0; k < 2; ++k) {
       p[k].assign(nlayers, 0.0);
@@ -512,11 +680,6 @@ struct Vertical {
         q[k][n] = (a - b) / (a + b);
       }
     }
-    // per-cell factors for both kinds
-    struct Cell {
-      cx theta, FI, FD, GI, GD, diagA, diagA4, diagA3, diagA6;
-    };
-    std::vector<Cell> cell[2];
     for (int k = 0; k < 2; ++k) {
       cell[k].resize(nz);
       for (int l = 0; l < nz; ++l) {
@@ -530,6 +693,7 @@ struct Vertical {
         const cx E1 = h * f_eps(x);
         const cx ea = std::exp(-2.0 * e * ta[l]), eb = std::exp(-2.0 * e * tb[l]);
         const cx fa = 1.0 + P * ea, fb = 1.0 + P * eb;
+        const cx fta = 1.0 - P * ea;  // F'(t_a) / (eta e^{eta t_a})
         const cx qa = half ? cx(0.0) : Q * std::exp(-2.0 * e * (L[n] - ta[l]));
         const cx qb = half ? cx(0.0) : Q * std::exp(-2.0 * e * (L[n] - tb[l]));
         const cx ga = 1.0 + qa, gb = 1.0 + qb;
@@ -538,11 +702,14 @@ struct Vertical {
         const cx D = 1.0 - pqd;
         Cell &c = cell[k][l];
         c.theta = eh * fa / fb;
+        c.thetad = e * eh * fta / fb;
         c.FI = E1 * (1.0 + P * std::exp(-e * (ta[l] + tb[l]))) / fb;
         c.FD = 1.0 - c.theta;
         const cx qm = half ? cx(0.0) : Q * std::exp(-e * (2.0 * L[n] - ta[l] - tb[l]));
         c.GI = fa * E1 * (1.0 + qm) / (e * D);
         c.GD = fa * (eh * gb - ga) / (e * D);
+        c.GId = fta * E1 * (1.0 + qm) / D;
+        c.GDd = fta * (eh * gb - ga) / D;
         // same cell
         const cx Sp = ea * E1 * E1;
         const cx Sq = half ? cx(0.0) : std::exp(-2.0 * e * (L[n] - tb[l])) * E1 * E1;
@@ -570,6 +737,12 @@ struct Vertical {
         }
       }
     }
+  }
+
+  void row(double lam, cx *out) const {
+    const int T = nz * (nz + 1) / 2;
+    std::vector<Cell> cell[2];
+    factors(lam, cell);
     const cx iwm(0.0, omega * kMu0);
     const double lam2 = lam * lam;
     // upper pairs iz <= jz: P / lambda, lambda A1, lambda A6 / sigma
@@ -612,6 +785,71 @@ struct Vertical {
         a4[i * nz + j] = lam * cell[1][i].FD * R * cell[1][j].GI / si;
         // observation j below source i: (sigma_j / sigma_i) FI_i R GD_j / sigma_j
         a4[j * nz + i] = lam * cell[1][i].FI * R * cell[1][j].GD / si;
+      }
+    }
+  }
+
+  // Point observer at the top of the first cell (the earth's surface), on
+  // the earth side; the eight lambda-functions of every source level jz,
+  // written as out[f * nz + jz]:
+  //   0 lambda A1, 1 lambda A2, 2 lambda dA1, 3 lambda A4 / s, 4 lambda A5 / s,
+  //   5 lambda A6 / s, 6 P / lambda, 7 Q / lambda   (s: surface layer)
+  // with A1 = int U_1, A2 = int U_s, dA1 = d/dz A1, A4 = d/dz A2,
+  // A5 = U_s(z, bottom) - U_s(z, top), A3 = d/dz A5 (regular part),
+  // A6 = lambda^2 A2 - 2 [observer in the cell], P = -i w mu0 A1 + A3 / s,
+  // Q = dA1 + A5.  U(z0, z*) = F(z0) G(z*) / ..., so for the cell jz below
+  // the observer the z0-dependence is the product of the top-to-bottom
+  // ratios of the cells above it; the cell the observer sits on uses the
+  // derivative at its own top edge.
+  // large-lambda limit of lambda^2 A2 - 2 for the observer's own cell: every
+  // eta tends to lambda, so p_1 -> (s0 - s1) / (s0 + s1) and lambda^2 A2 ->
+  // 1 + p_1
+  cx a6_inf() const {
+    const cx s0 = t->sigma[0], s1 = t->sigma[lay[0]];
+    return (s0 - s1) / (s0 + s1) - 1.0;
+  }
+
+  void point_row(double lam, cx *out) const {
+    std::vector<Cell> cell[2];
+    factors(lam, cell);
+    const cx iwm(0.0, omega * kMu0);
+    const cx so = t->sigma[lay[0]];
+    cx R[2] = {1.0, 1.0}, Rd[2] = {0.0, 0.0};
+    for (int jz = 0; jz < nz; ++jz) {
+      cx A1, A2, dA1, A4, A5, A3;
+      if (jz == 0) {
+        A1 = cell[0][0].GI;
+        A2 = cell[1][0].GI;
+        dA1 = cell[0][0].GId;
+        A4 = cell[1][0].GId;
+        A5 = cell[1][0].GD;
+        A3 = cell[1][0].GDd;
+      } else {
+        A1 = R[0] * cell[0][jz].GI;
+        A2 = R[1] * cell[1][jz].GI;
+        dA1 = Rd[0] * cell[0][jz].GI;
+        A4 = Rd[1] * cell[1][jz].GI;
+        A5 = R[1] * cell[1][jz].GD;
+        A3 = Rd[1] * cell[1][jz].GD;
+      }
+      // the observer's own cell: A6 tends to the constant a6_inf, whose
+      // transform is a delta at the observer; it is taken out here and added
+      // exactly to the own cell's G_zz (see compute_receiver_kernels)
+      const cx A6 = lam * lam * A2 - (jz == 0 ? 2.0 + a6_inf() : 0.0);
+      const cx Pv = -iwm * A1 + A3 / so;
+      const cx Qv = dA1 + A5;
+      out[0 * nz + jz] = lam * A1;
+      out[1 * nz + jz] = lam * A2;
+      out[2 * nz + jz] = lam * dA1;
+      out[3 * nz + jz] = lam * A4 / so;
+      out[4 * nz + jz] = lam * A5 / so;
+      out[5 * nz + jz] = lam * A6 / so;
+      out[6 * nz + jz] = Pv / lam;
+      out[7 * nz + jz] = Qv / lam;
+      // ratios from the observer to the top of the next cell
+      for (int k = 0; k < 2; ++k) {
+        Rd[k] = (jz == 0) ? cell[k][0].thetad : Rd[k] * cell[k][jz].theta;
+        R[k] *= cell[k][jz].theta;
       }
     }
   }
@@ -696,6 +934,95 @@ int compute_tables(giem_handle *t, hipStream_t s) {
         check_hip(hipStreamSynchronize(s), "table build"))
       return GIEM_EHIP;
   }
+  return GIEM_OK;
+}
+
+// Receiver kernels of every frequency: for receivers above cell centres at
+// lateral offset (di hx, dj hy) from a source cell of level jz, the cell
+// integrals of G^E and G^H, out[((dj + Ny - 1)(2 Nx - 1) + di + Nx - 1) nz +
+// jz][18] (E row-major, then H).  Receivers are at the earth's surface, the
+// top of the first cell.
+int compute_receiver_kernels(giem_handle *t, int ifreq, void **out, hipStream_t s) {
+  const int nx = t->nx, ny = t->ny, nz = t->nz;
+  const int nxo = 2 * nx - 1, nyo = 2 * ny - 1;
+  const size_t noff = (size_t)nxo * nyo;
+  const int nf = 8 * nz;  // complex functions per lambda
+  const Grids g = make_grids(t);
+  const size_t nl = g.lam.size(), nr = g.rho.size();
+  std::vector<double> Wt, Wt_reg, Mt(nr * R_COUNT * noff, 0.0);
+  hankel_weights(g, Wt, Wt_reg);
+  {
+    const Rule gs = gauss_legendre(24), g14 = gauss_legendre(14), g8 = gauss_legendre(8);
+    const Rule gl = gauss_legendre(24);
+    const size_t ncol = R_COUNT * noff;
+    parallel_for((int)noff, [&](int o) {
+      const int dj = o / nxo - (ny - 1), di = o % nxo - (nx - 1);
+      double wi[32];
+      for (int kind = 0; kind < R_COUNT; ++kind) {
+        RulePtsD pts;
+        receiver_rule(kind, di * t->hx, dj * t->hy, t->hx, t->hy, gs, g14, g8, gl, pts);
+        const size_t col = kind * noff + o;
+        for (size_t q = 0; q < pts.rho.size(); ++q) {
+          const double r = std::max(pts.rho[q], g.rho_min);
+          const size_t c0 = pts.deriv[q] ? g.rho.interp_deriv(r, wi) : g.rho.interp(r, wi);
+          for (int k = 0; k < g.rho.n; ++k) Mt[(c0 + k) * ncol + col] += pts.w[q] * wi[k];
+        }
+      }
+    });
+  }
+  Vertical v;
+  v.init(t, t->f[ifreq].freq);
+  std::vector<cx> G(nl * nf);
+  parallel_for((int)nl, [&](int l) { v.point_row(g.lam.x[l], G.data() + (size_t)l * nf); });
+  DevBuf dW, dWr, dM, dG, dH, dC;
+  void *dK = nullptr;
+  if (dW.alloc(Wt.size() * 8) != hipSuccess || dWr.alloc(Wt_reg.size() * 8) != hipSuccess ||
+      dM.alloc(Mt.size() * 8) != hipSuccess || dG.alloc(G.size() * 16) != hipSuccess ||
+      dH.alloc(nr * nf * 16) != hipSuccess || dC.alloc((size_t)R_COUNT * noff * nf * 16) != hipSuccess ||
+      hipMalloc(&dK, noff * nz * 18 * sizeof(c128)) != hipSuccess) {
+    if (dK) hipFree(dK);
+    set_error("giem_fields: out of device memory for the receiver kernels");
+    return GIEM_ENOMEM;
+  }
+  const int64_t ldg = 2 * (int64_t)nf;
+  const int64_t ldm = (int64_t)R_COUNT * noff;
+  int rc = GIEM_OK;
+  if (check_hip(hipMemcpyAsync(dW.p, Wt.data(), Wt.size() * 8, hipMemcpyHostToDevice, s), "upload") ||
+      check_hip(hipMemcpyAsync(dWr.p, Wt_reg.data(), Wt_reg.size() * 8, hipMemcpyHostToDevice, s), "upload") ||
+      check_hip(hipMemcpyAsync(dM.p, Mt.data(), Mt.size() * 8, hipMemcpyHostToDevice, s), "upload") ||
+      check_hip(hipMemcpyAsync(dG.p, G.data(), G.size() * 16, hipMemcpyHostToDevice, s), "upload") ||
+      // plain functions 0..5, regularised 6..7
+      check_hip(launch_gemm_tn(dW.d(), nr, dG.d(), ldg, dH.d(), ldg, (int)nr, 2 * 6 * nz, (int)nl, s),
+                "receiver Hankel contraction") ||
+      check_hip(launch_gemm_tn(dWr.d(), nr, dG.d() + 2 * 6 * nz, ldg, dH.d() + 2 * 6 * nz, ldg,
+                               (int)nr, 2 * 2 * nz, (int)nl, s),
+                "receiver Hankel contraction") ||
+      check_hip(launch_gemm_tn(dM.d(), ldm, dH.d(), ldg, dC.d(), ldg, (int)(R_COUNT * noff), 2 * nf,
+                               (int)nr, s),
+                "receiver spatial contraction") ||
+      check_hip(launch_assemble_rec(dC.c(), static_cast<c128 *>(dK), (int)noff, nz,
+                                    2 * kPi * t->f[ifreq].freq * kMu0, s),
+                "receiver kernel assembly") ||
+      check_hip(hipStreamSynchronize(s), "receiver kernels"))
+    rc = GIEM_EHIP;
+  if (rc == GIEM_OK) {
+    // delta part of G_zz for the own cell (offset 0, level 0): the constant
+    // a6_inf / s transforms to 2 pi a6_inf / s times the footprint's
+    // indicator, i.e. a6_inf / (2 s) after the 1 / 4pi
+    const cx add = v.a6_inf() / (2.0 * t->sigma[t->layer_of_cell[0]]);
+    const size_t o0 = (size_t)(ny - 1) * nxo + (nx - 1);
+    c128 *kzz = static_cast<c128 *>(dK) + (o0 * nz + 0) * 18 + 8;
+    c128 val;
+    if (check_hip(hipMemcpy(&val, kzz, sizeof(c128), hipMemcpyDeviceToHost), "read kernel") ||
+        (val = mk<double>(val.x + add.real(), val.y + add.imag()),
+         check_hip(hipMemcpy(kzz, &val, sizeof(c128), hipMemcpyHostToDevice), "write kernel")))
+      rc = GIEM_EHIP;
+  }
+  if (rc != GIEM_OK) {
+    hipFree(dK);
+    return rc;
+  }
+  *out = dK;
   return GIEM_OK;
 }
 
