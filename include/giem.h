@@ -108,8 +108,10 @@ typedef struct {
 
 /*
  * giem_tables -- compute the Galerkin coefficient tables B_n^m (Sect. 3.2,
- * Appendices A-C) for nfreq frequencies on the host in FP64 and upload their
- * packed spectra (Sect. 3.3) to the device.
+ * Appendices A-C) for nfreq frequencies in FP64 and keep their packed spectra
+ * (Sect. 3.3) on the device.  The vertical functions and the geometry-only
+ * quadrature matrices are built on the host; the Hankel and horizontal
+ * contractions run as FP64 GEMMs on the device.  Synchronises the stream.
  *   freq_hz: host [nfreq], > 0.  flags: GIEM_TABLES_C64 or 0.
  *   *out receives a new handle.
  * Errors: EINVAL (shapes), EDOMAIN (a cell straddles an interface,
@@ -229,6 +231,51 @@ int giem_adjoint(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrh
 int giem_fields(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
                 const void *E_cells, int32_t nrec, const double *rec_xy, void *E_rec,
                 void *H_rec, void *stream);
+
+/*
+ * giem_impedance -- impedance tensor at every receiver from the fields of the
+ * x and the y polarisation (Sect. 4, the apparent resistivity of the
+ * benchmark is computed from it): with Eh[c][p] = e_c of polarisation p and
+ * Hh[c][p] = h_c of polarisation p (c, p in {x, y}), Z = Eh Hh^-1.
+ *   E_rec, H_rec: device c128 [2][nrec][3] (as written by giem_fields with
+ *                 nrhs = 2: RHS 0 = x, RHS 1 = y polarisation);
+ *   Z:            device c128 [nrec][2][2] output, row-major (Zxx Zxy Zyx Zyy).
+ * Asynchronous on the stream.  A receiver whose Hh is singular gets inf/NaN.
+ * Errors: EINVAL, EHIP.
+ */
+int giem_impedance(int32_t nrec, const void *E_rec, const void *H_rec, void *Z, void *stream);
+
+/*
+ * giem_impedance_adjoint -- reverse mode of giem_impedance.  gZ holds the
+ * gradient of a real function L with respect to Z in the convention
+ * dL = Re sum conj(gZ) dZ (the gradient torch stores for complex tensors).
+ * Writes wE, wH such that dL = Re sum_{p,q,c} (wE[p][q][c] de + wH[p][q][c] dh)
+ * for perturbations de, dh of E_rec, H_rec.
+ *   E_rec, H_rec: device c128 [2][nrec][3];  gZ: device c128 [nrec][2][2];
+ *   wE, wH:       device c128 [2][nrec][3] outputs (z components zero).
+ * Asynchronous on the stream.  Errors: EINVAL, EHIP.
+ */
+int giem_impedance_adjoint(int32_t nrec, const void *E_rec, const void *H_rec, const void *gZ,
+                           void *wE, void *wH, void *stream);
+
+/*
+ * giem_fields_adjoint -- transpose of giem_fields (Sect. 2.2 field
+ * representation).  For weights wE, wH on the receiver fields,
+ * dL = Re sum (wE . de + wH . dh), it writes the source of the adjoint solve
+ * and adds the explicit part of the gradient:
+ *   v_n      = sum_q wE_q^T [int_{cell n} G^E(r_q, M0) dM0]
+ *            + wH_q^T [int_{cell n} G^H(r_q, M0) dM0]          (per RHS),
+ *   adj_src  = (sa_n - sb_n) v_n            (device c128 [nrhs][3][Nz][Ny][Nx]),
+ *   grad_log_sigma[n] += Re sum_r sa_n v_n . E_n  (device double [Nz][Ny][Nx]).
+ * Passing adj_src and E_cells to giem_adjoint then adds the part of the
+ * gradient that flows through the cell field, so that grad_log_sigma ends as
+ * dL / d log sa for real conductivities.  Receivers, E_cells and the kernel
+ * cache are as in giem_fields; nrec = 0 gives adj_src = 0.  Synchronises.
+ * Errors: EINVAL, EDOMAIN, ENOMEM, EHIP.
+ */
+int giem_fields_adjoint(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
+                        const void *E_cells, int32_t nrec, const double *rec_xy, const void *wE,
+                        const void *wH, void *adj_src, void *grad_log_sigma, void *stream);
 
 void giem_free(giem_handle *t);
 const char *giem_last_error(void);

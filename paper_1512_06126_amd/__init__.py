@@ -79,6 +79,9 @@ def load():
         "giem_solve": [P, I32, P, I32, P, P, P, P, P],
         "giem_adjoint": [P, I32, P, I32, P, P, P, P, P, P],
         "giem_fields": [P, I32, P, I32, P, I32, P, P, P, P],
+        "giem_fields_adjoint": [P, I32, P, I32, P, I32, P, P, P, P, P, P],
+        "giem_impedance": [I32, P, P, P, P],
+        "giem_impedance_adjoint": [I32, P, P, P, P, P, P],
         "giem_profile": [P, I32],
         "giem_profile_read": [P, P, P, P],
         "giem_free": [P],
@@ -97,7 +100,8 @@ def load():
 def exported_symbols():
     return ["giem_tables", "giem_tables_import", "giem_tables_export", "giem_tables_bytes",
             "giem_apply", "giem_apply_timed", "giem_profile", "giem_profile_read", "giem_solve",
-            "giem_adjoint", "giem_fields", "giem_free", "giem_last_error"]
+            "giem_adjoint", "giem_fields", "giem_fields_adjoint", "giem_impedance",
+            "giem_impedance_adjoint", "giem_free", "giem_last_error"]
 
 
 def _check(rc, allow_noconv=False):
@@ -226,6 +230,30 @@ class Handle:
                                 rec.shape[0], rec.ctypes.data, _ptr(E_rec), _ptr(H_rec),
                                 _stream(stream)))
         return E_rec, H_rec
+
+    def fields_adjoint(self, sigma_a, E_cells, rec_xy, wE, wH, adj_src, grad, ifreq=0,
+                       stream=None):
+        rec = np.ascontiguousarray(rec_xy, dtype=np.float64).reshape(-1, 2)
+        _check(_lib.giem_fields_adjoint(self._p, ifreq, _ptr(sigma_a), E_cells.shape[0],
+                                        _ptr(E_cells), rec.shape[0], rec.ctypes.data, _ptr(wE),
+                                        _ptr(wH), _ptr(adj_src), _ptr(grad), _stream(stream)))
+        return adj_src, grad
+
+
+def impedance(E_rec, H_rec, Z, stream=None):
+    """Z [nrec][2][2] = Eh Hh^-1 from the fields of the two polarisations."""
+    load()
+    _check(_lib.giem_impedance(E_rec.shape[1], _ptr(E_rec), _ptr(H_rec), _ptr(Z),
+                               _stream(stream)))
+    return Z
+
+
+def impedance_adjoint(E_rec, H_rec, gZ, wE, wH, stream=None):
+    """Weights on the receiver fields from the gradient with respect to Z."""
+    load()
+    _check(_lib.giem_impedance_adjoint(E_rec.shape[1], _ptr(E_rec), _ptr(H_rec), _ptr(gZ),
+                                       _ptr(wE), _ptr(wH), _stream(stream)))
+    return wE, wH
 
 
 def tables(model, freqs, flags=0, stream=None):

@@ -48,6 +48,14 @@ hipError_t launch_fields(const c128 *K, const c128 *E, const c128 *sa, const c12
                          const int *rec, int nrec, int nrhs, int nx, int ny, int nz,
                          const c128 *en_hn, c128 *Erec, c128 *Hrec, hipStream_t s);
 
+hipError_t launch_impedance(const c128 *E, const c128 *H, int nrec, c128 *Z, hipStream_t s);
+hipError_t launch_impedance_adjoint(const c128 *E, const c128 *H, int nrec, const c128 *G, c128 *wE,
+                                    c128 *wH, hipStream_t s);
+hipError_t launch_fields_adjoint(const c128 *K, const c128 *E, const c128 *sa, const c128 *sb_lev,
+                                 const int *rec, int nrec, int nrhs, int nx, int ny, int nz,
+                                 const c128 *wE, const c128 *wH, c128 *g, double *grad,
+                                 hipStream_t s);
+
 // Krylov vector kernels (kernels_vec.hip); vectors of n = 3 Nz Ny Nx complex.
 struct DotArgs {
   const c128 *w[kMaxRhs];      // vector to project

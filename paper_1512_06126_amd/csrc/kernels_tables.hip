@@ -196,7 +196,153 @@ k_fields(const c128 *__restrict__ K, const c128 *__restrict__ E, const c128 *__r
   }
 }
 
+// Impedance tensor at one receiver per thread: with Eh[c][p] = e_c of
+// polarisation p and Hh likewise (c, p in {x, y}; RHS 0 / 1 = x / y
+// polarisation), Z = Eh Hh^-1.  E, H: [2][nrec][3]; Z: [nrec][2][2].
+__device__ inline void imp_load(const c128 *__restrict__ E, const c128 *__restrict__ H, int nrec,
+                                int q, c128 (&Eh)[2][2], c128 (&Hi)[2][2]) {
+  c128 Hh[2][2];
+  for (int c = 0; c < 2; ++c)
+    for (int p = 0; p < 2; ++p) {
+      Eh[c][p] = E[((size_t)p * nrec + q) * 3 + c];
+      Hh[c][p] = H[((size_t)p * nrec + q) * 3 + c];
+    }
+  const c128 det = csub(cmul(Hh[0][0], Hh[1][1]), cmul(Hh[0][1], Hh[1][0]));
+  const double dn = det.x * det.x + det.y * det.y;
+  const c128 id = mk<double>(det.x / dn, -det.y / dn);
+  const c128 m1 = mk<double>(-1.0, 0.0);
+  Hi[0][0] = cmul(Hh[1][1], id);
+  Hi[0][1] = cmul(cmul(Hh[0][1], m1), id);
+  Hi[1][0] = cmul(cmul(Hh[1][0], m1), id);
+  Hi[1][1] = cmul(Hh[0][0], id);
+}
+
+__global__ void k_impedance(const c128 *__restrict__ E, const c128 *__restrict__ H, int nrec,
+                            c128 *__restrict__ Z) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nrec) return;
+  c128 Eh[2][2], Hi[2][2];
+  imp_load(E, H, nrec, q, Eh, Hi);
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      c128 z = mk<double>(0.0, 0.0);
+      for (int k = 0; k < 2; ++k) cfma(z, Eh[i][k], Hi[k][j]);
+      Z[(size_t)q * 4 + i * 2 + j] = z;
+    }
+}
+
+// Reverse mode of k_impedance.  G holds the gradient of a real L with respect
+// to Z in the convention dL = Re sum conj(G_ij) dZ_ij.  Since
+// dZ = (dEh - Z dHh) Hh^-1, with W = Hh^-1 G^H,
+//   dL = Re sum_{p,c} ( W[p][c] dEh[c][p] - (W Z)[p][c] dHh[c][p] ),
+// so the weights on the receiver fields are wE[p][q][c] = W[p][c] and
+// wH[p][q][c] = -(W Z)[p][c] for c in {x, y}, and zero for c = z.
+__global__ void k_impedance_adjoint(const c128 *__restrict__ E, const c128 *__restrict__ H, int nrec,
+                                    const c128 *__restrict__ G, c128 *__restrict__ wE,
+                                    c128 *__restrict__ wH) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nrec) return;
+  c128 Eh[2][2], Hi[2][2], Z[2][2], W[2][2];
+  imp_load(E, H, nrec, q, Eh, Hi);
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      c128 z = mk<double>(0.0, 0.0), w = mk<double>(0.0, 0.0);
+      for (int k = 0; k < 2; ++k) {
+        cfma(z, Eh[i][k], Hi[k][j]);
+        const c128 g = G[(size_t)q * 4 + j * 2 + k];
+        cfma(w, Hi[i][k], mk<double>(g.x, -g.y));
+      }
+      Z[i][j] = z;
+      W[i][j] = w;
+    }
+  for (int p = 0; p < 2; ++p) {
+    for (int c = 0; c < 2; ++c) {
+      c128 wz = mk<double>(0.0, 0.0);
+      for (int k = 0; k < 2; ++k) cfma(wz, W[p][k], Z[k][c]);
+      wE[((size_t)p * nrec + q) * 3 + c] = W[p][c];
+      wH[((size_t)p * nrec + q) * 3 + c] = mk<double>(-wz.x, -wz.y);
+    }
+    wE[((size_t)p * nrec + q) * 3 + 2] = mk<double>(0.0, 0.0);
+    wH[((size_t)p * nrec + q) * 3 + 2] = mk<double>(0.0, 0.0);
+  }
+}
+
+// Transpose of k_fields.  For dL = Re sum_{r,q,a} (wE[r][q][a] de_a + wH[r][q][a] dh_a)
+// and the anomalous fields e = sum_n (sa_n - sb_n) KE(q, n) E_n (h likewise),
+// per cell n and RHS r
+//   v[b] = sum_q sum_a wE[r][q][a] KE(q, n)[a][b] + wH[r][q][a] KH(q, n)[a][b],
+// the source of the adjoint solve is g[r][b][n] = (sa_n - sb_n) v[b] (the
+// dependence through E) and, for real sa, the explicit dependence on log sa is
+// grad[n] += Re sum_{r,b} sa_n v[b] E[r][b][n].  Threads run over depth first
+// so that neighbouring threads read neighbouring entries of the kernel table
+// [offset][Nz][18].
+__global__ void __launch_bounds__(256)
+k_fields_adjoint(const c128 *__restrict__ K, const c128 *__restrict__ E,
+                 const c128 *__restrict__ sa, const c128 *__restrict__ sb_lev,
+                 const int *__restrict__ rec, int nrec, int nrhs, int nx, int ny, int nz,
+                 const c128 *__restrict__ wE, const c128 *__restrict__ wH, c128 *__restrict__ g,
+                 double *__restrict__ grad) {
+  const size_t plane = (size_t)nx * ny, N = plane * nz;
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  const int iz = (int)(t % nz);
+  const size_t col = t / nz;
+  const int ix = (int)(col % nx), iy = (int)(col / nx);
+  const size_t n = (size_t)iz * plane + (size_t)iy * nx + ix;
+  const c128 s = sa[n];
+  const c128 ds = csub(s, sb_lev[iz]);
+  double gsum = 0.0;
+  for (int r = 0; r < nrhs; ++r) {
+    c128 v[3] = {mk<double>(0.0, 0.0), mk<double>(0.0, 0.0), mk<double>(0.0, 0.0)};
+    for (int q = 0; q < nrec; ++q) {
+      const size_t off =
+          (size_t)(rec[2 * q + 1] - iy + ny - 1) * (2 * nx - 1) + (rec[2 * q] - ix + nx - 1);
+      const c128 *k = K + (off * nz + iz) * 18;
+      const c128 *we = wE + ((size_t)r * nrec + q) * 3;
+      const c128 *wh = wH + ((size_t)r * nrec + q) * 3;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const c128 ea = we[a], ha = wh[a];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          cfma(v[b], ea, k[3 * a + b]);
+          cfma(v[b], ha, k[9 + 3 * a + b]);
+        }
+      }
+    }
+    for (int b = 0; b < 3; ++b) {
+      g[((size_t)r * 3 + b) * N + n] = cmul(ds, v[b]);
+      gsum += cmul(cmul(s, v[b]), E[((size_t)r * 3 + b) * N + n]).x;
+    }
+  }
+  grad[n] += gsum;
+}
+
 }  // namespace
+
+hipError_t launch_impedance(const c128 *E, const c128 *H, int nrec, c128 *Z, hipStream_t s) {
+  if (nrec <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_impedance, dim3((nrec + 127) / 128), dim3(128), 0, s, E, H, nrec, Z);
+  return hipGetLastError();
+}
+
+hipError_t launch_impedance_adjoint(const c128 *E, const c128 *H, int nrec, const c128 *G, c128 *wE,
+                                    c128 *wH, hipStream_t s) {
+  if (nrec <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_impedance_adjoint, dim3((nrec + 127) / 128), dim3(128), 0, s, E, H, nrec, G,
+                     wE, wH);
+  return hipGetLastError();
+}
+
+hipError_t launch_fields_adjoint(const c128 *K, const c128 *E, const c128 *sa, const c128 *sb_lev,
+                                 const int *rec, int nrec, int nrhs, int nx, int ny, int nz,
+                                 const c128 *wE, const c128 *wH, c128 *g, double *grad,
+                                 hipStream_t s) {
+  const size_t N = (size_t)nx * ny * nz;
+  hipLaunchKernelGGL(k_fields_adjoint, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, K, E,
+                     sa, sb_lev, rec, nrec, nrhs, nx, ny, nz, wE, wH, g, grad);
+  return hipGetLastError();
+}
 
 hipError_t launch_assemble_rec(const c128 *c, c128 *out, int noff, int nz, double omega_mu0,
                                hipStream_t s) {

@@ -641,6 +641,48 @@ int giem_adjoint(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrh
 
 }  // extern "C"
 
+namespace giem {
+
+// Lattice indices of receivers that lie above cell centres; EDOMAIN otherwise
+// or when the anomaly grid does not start at the surface d[0].
+static int receiver_indices(const giem_handle *t, int nrec, const double *rec_xy,
+                            std::vector<int> &idx, const char *who) {
+  if (std::fabs(t->z_edges[0] - t->d[0]) > 1e-9 * (t->z_edges[t->nz] - t->z_edges[0])) {
+    set_error(std::string(who) + ": the anomaly grid must start at the earth's surface d[0]");
+    return GIEM_EDOMAIN;
+  }
+  idx.assign(2 * (size_t)nrec, 0);
+  for (int q = 0; q < nrec; ++q) {
+    const double fx = (rec_xy[2 * q] - t->x0) / t->hx - 0.5;
+    const double fy = (rec_xy[2 * q + 1] - t->y0) / t->hy - 0.5;
+    const double ix = std::round(fx), iy = std::round(fy);
+    if (!(std::fabs(fx - ix) <= 1e-9) || !(std::fabs(fy - iy) <= 1e-9) || ix < 0 ||
+        ix >= t->nx || iy < 0 || iy >= t->ny) {
+      set_error(std::string(who) + ": receivers must lie above cell centres of the grid");
+      return GIEM_EDOMAIN;
+    }
+    idx[2 * q] = (int)ix;
+    idx[2 * q + 1] = (int)iy;
+  }
+  return GIEM_OK;
+}
+
+// Device copy of a small host array, freed on scope exit.
+struct DevCopy {
+  void *p = nullptr;
+  ~DevCopy() {
+    if (p) hipFree(p);
+  }
+  int put(const void *h, size_t bytes, hipStream_t s, const char *what) {
+    if (check_hip(hipMalloc(&p, bytes), what) ||
+        check_hip(hipMemcpyAsync(p, h, bytes, hipMemcpyHostToDevice, s), what))
+      return GIEM_EHIP;
+    return GIEM_OK;
+  }
+};
+
+}  // namespace giem
+
 extern "C" int giem_fields(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
                            const void *E_cells, int32_t nrec, const double *rec_xy, void *E_rec,
                            void *H_rec, void *stream) {
@@ -651,24 +693,8 @@ extern "C" int giem_fields(giem_handle *t, int32_t ifreq, const void *sigma_a, i
     return GIEM_EINVAL;
   }
   if (nrec == 0) return GIEM_OK;
-  if (std::fabs(t->z_edges[0] - t->d[0]) > 1e-9 * (t->z_edges[t->nz] - t->z_edges[0])) {
-    set_error("giem_fields: the anomaly grid must start at the earth's surface d[0]");
-    return GIEM_EDOMAIN;
-  }
-  // receivers above cell centres: lattice indices
-  std::vector<int> idx(2 * (size_t)nrec);
-  for (int q = 0; q < nrec; ++q) {
-    const double fx = (rec_xy[2 * q] - t->x0) / t->hx - 0.5;
-    const double fy = (rec_xy[2 * q + 1] - t->y0) / t->hy - 0.5;
-    const double ix = std::round(fx), iy = std::round(fy);
-    if (std::fabs(fx - ix) > 1e-9 || std::fabs(fy - iy) > 1e-9 || ix < 0 || ix >= t->nx ||
-        iy < 0 || iy >= t->ny) {
-      set_error("giem_fields: receivers must lie above cell centres of the grid");
-      return GIEM_EDOMAIN;
-    }
-    idx[2 * q] = (int)ix;
-    idx[2 * q + 1] = (int)iy;
-  }
+  std::vector<int> idx;
+  GIEM_TRY(receiver_indices(t, nrec, rec_xy, idx, "giem_fields"));
   hipStream_t s = static_cast<hipStream_t>(stream);
   FreqTables &ft = t->f[ifreq];
   if (!ft.rec_kernel) GIEM_TRY(compute_receiver_kernels(t, ifreq, &ft.rec_kernel, s));
@@ -685,23 +711,74 @@ extern "C" int giem_fields(giem_handle *t, int32_t ifreq, const void *sigma_a, i
     nf[6 + 1] = mk<double>(1.0, 0.0);
     nf[6 + 3] = mk<double>(-hy.real(), -hy.imag());
   }
-  void *drec = nullptr, *dnf = nullptr;
-  int rc = GIEM_OK;
-  if (check_hip(hipMalloc(&drec, idx.size() * sizeof(int)), "hipMalloc receivers") ||
-      check_hip(hipMalloc(&dnf, nf.size() * sizeof(c128)), "hipMalloc normal fields") ||
-      check_hip(hipMemcpyAsync(drec, idx.data(), idx.size() * sizeof(int), hipMemcpyHostToDevice, s),
-                "copy receivers") ||
-      check_hip(hipMemcpyAsync(dnf, nf.data(), nf.size() * sizeof(c128), hipMemcpyHostToDevice, s),
-                "copy normal fields") ||
-      check_hip(launch_fields(static_cast<const c128 *>(ft.rec_kernel),
-                              static_cast<const c128 *>(E_cells), static_cast<const c128 *>(sigma_a),
-                              static_cast<const c128 *>(t->sb_lev), static_cast<const int *>(drec),
-                              nrec, nrhs, t->nx, t->ny, t->nz, static_cast<const c128 *>(dnf),
-                              static_cast<c128 *>(E_rec), static_cast<c128 *>(H_rec), s),
-                "fields kernel") ||
-      check_hip(hipStreamSynchronize(s), "fields"))
-    rc = GIEM_EHIP;
-  if (drec) hipFree(drec);
-  if (dnf) hipFree(dnf);
-  return rc;
+  DevCopy drec, dnf;
+  GIEM_TRY(drec.put(idx.data(), idx.size() * sizeof(int), s, "receivers"));
+  GIEM_TRY(dnf.put(nf.data(), nf.size() * sizeof(c128), s, "normal fields"));
+  GIEM_HIP(launch_fields(static_cast<const c128 *>(ft.rec_kernel), static_cast<const c128 *>(E_cells),
+                         static_cast<const c128 *>(sigma_a), static_cast<const c128 *>(t->sb_lev),
+                         static_cast<const int *>(drec.p), nrec, nrhs, t->nx, t->ny, t->nz,
+                         static_cast<const c128 *>(dnf.p), static_cast<c128 *>(E_rec),
+                         static_cast<c128 *>(H_rec), s),
+           "fields kernel");
+  GIEM_HIP(hipStreamSynchronize(s), "fields");
+  return GIEM_OK;
+}
+
+extern "C" int giem_fields_adjoint(giem_handle *t, int32_t ifreq, const void *sigma_a,
+                                   int32_t nrhs, const void *E_cells, int32_t nrec,
+                                   const double *rec_xy, const void *wE, const void *wH,
+                                   void *adj_src, void *grad_log_sigma, void *stream) {
+  using namespace giem;
+  if (!t || ifreq < 0 || ifreq >= (int)t->f.size() || !sigma_a || nrhs < 1 || !E_cells ||
+      nrec < 0 || (nrec > 0 && (!rec_xy || !wE || !wH)) || !adj_src || !grad_log_sigma) {
+    set_error("giem_fields_adjoint: bad argument");
+    return GIEM_EINVAL;
+  }
+  std::vector<int> idx;
+  if (nrec > 0) GIEM_TRY(receiver_indices(t, nrec, rec_xy, idx, "giem_fields_adjoint"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  GIEM_TRY(check_sigma_a(t, sigma_a, s));
+  FreqTables &ft = t->f[ifreq];
+  if (nrec > 0 && !ft.rec_kernel) GIEM_TRY(compute_receiver_kernels(t, ifreq, &ft.rec_kernel, s));
+  DevCopy drec;
+  if (nrec > 0) GIEM_TRY(drec.put(idx.data(), idx.size() * sizeof(int), s, "receivers"));
+  GIEM_HIP(launch_fields_adjoint(static_cast<const c128 *>(ft.rec_kernel),
+                                 static_cast<const c128 *>(E_cells),
+                                 static_cast<const c128 *>(sigma_a),
+                                 static_cast<const c128 *>(t->sb_lev),
+                                 static_cast<const int *>(drec.p), nrec, nrhs, t->nx, t->ny, t->nz,
+                                 static_cast<const c128 *>(wE), static_cast<const c128 *>(wH),
+                                 static_cast<c128 *>(adj_src), static_cast<double *>(grad_log_sigma),
+                                 s),
+           "fields adjoint kernel");
+  GIEM_HIP(hipStreamSynchronize(s), "fields adjoint");
+  return GIEM_OK;
+}
+
+extern "C" int giem_impedance(int32_t nrec, const void *E_rec, const void *H_rec, void *Z,
+                              void *stream) {
+  using namespace giem;
+  if (nrec < 0 || (nrec > 0 && (!E_rec || !H_rec || !Z))) {
+    set_error("giem_impedance: bad argument");
+    return GIEM_EINVAL;
+  }
+  GIEM_HIP(launch_impedance(static_cast<const c128 *>(E_rec), static_cast<const c128 *>(H_rec), nrec,
+                            static_cast<c128 *>(Z), static_cast<hipStream_t>(stream)),
+           "impedance kernel");
+  return GIEM_OK;
+}
+
+extern "C" int giem_impedance_adjoint(int32_t nrec, const void *E_rec, const void *H_rec,
+                                      const void *gZ, void *wE, void *wH, void *stream) {
+  using namespace giem;
+  if (nrec < 0 || (nrec > 0 && (!E_rec || !H_rec || !gZ || !wE || !wH))) {
+    set_error("giem_impedance_adjoint: bad argument");
+    return GIEM_EINVAL;
+  }
+  GIEM_HIP(launch_impedance_adjoint(static_cast<const c128 *>(E_rec),
+                                    static_cast<const c128 *>(H_rec), nrec,
+                                    static_cast<const c128 *>(gZ), static_cast<c128 *>(wE),
+                                    static_cast<c128 *>(wH), static_cast<hipStream_t>(stream)),
+           "impedance adjoint kernel");
+  return GIEM_OK;
 }
