@@ -171,6 +171,31 @@ int giem_apply_timed(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t
    (null handle). */
 int giem_profile(giem_handle *t, int32_t enable);
 
+/* giem_tune -- choose the launch shape of the four FFT passes of the apply
+   (Sect. 3.3 steps 1 and 3: x forward, y forward, y inverse, x inverse) for
+   this handle by timing: for each precision whose tables exist, every
+   instantiated (sequences per workgroup, threads per workgroup) pair that
+   fits the local data share is run on nrhs right-hand sides of frequency
+   ifreq, and the fastest median per pass is kept on the handle for all later
+   applies (results do not depend on the choice beyond rounding order, which
+   is the same: each transform runs on one workgroup either way).
+     sigma_a: device c128 [Nz][Ny][Nx] (the diagonals of mode A are used);
+     chosen:  host int32 [2][4][2] or NULL: (sequences, threads) per
+              precision (0 = FP64, 1 = FP32) and pass, as now in effect.
+   Allocates and frees two vectors of nrhs right-hand sides; synchronises.
+   Errors: EINVAL, ENOMEM, EHIP. */
+int giem_tune(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs, void *stream,
+              int32_t *chosen);
+
+/* giem_set_fft_shape -- set the FFT launch shape of one precision (0 = FP64,
+   1 = FP32) directly, e.g. to reuse a result of giem_tune on another handle
+   of the same grid.  shape: host int32 [4][2], (sequences per workgroup,
+   threads per workgroup) for x forward, y forward, y inverse, x inverse;
+   threads must be 256 or 512 and the pass must fit the local data share and
+   at most 16 elements per thread.  NULL restores the built-in choice.
+   Errors: EINVAL (nothing is changed). */
+int giem_set_fft_shape(giem_handle *t, uint32_t prec, const int32_t *shape);
+
 /* giem_profile_read -- wait for the last recorded apply and report what was
    recorded since giem_profile or the previous read, then clear it:
      stage_ms[2][5]: summed kernel durations (ms) per precision (0 = FP64,

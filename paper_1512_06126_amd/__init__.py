@@ -83,6 +83,8 @@ def load():
         "giem_impedance": [I32, P, P, P, P],
         "giem_impedance_adjoint": [I32, P, P, P, P, P, P],
         "giem_profile": [P, I32],
+        "giem_tune": [P, I32, P, I32, P, P],
+        "giem_set_fft_shape": [P, U32, P],
         "giem_profile_read": [P, P, P, P],
         "giem_free": [P],
         "giem_last_error": [],
@@ -99,7 +101,7 @@ def load():
 
 def exported_symbols():
     return ["giem_tables", "giem_tables_import", "giem_tables_export", "giem_tables_bytes",
-            "giem_apply", "giem_apply_timed", "giem_profile", "giem_profile_read", "giem_solve",
+            "giem_apply", "giem_apply_timed", "giem_tune", "giem_set_fft_shape", "giem_profile", "giem_profile_read", "giem_solve",
             "giem_adjoint", "giem_fields", "giem_fields_adjoint", "giem_impedance",
             "giem_impedance_adjoint", "giem_free", "giem_last_error"]
 
@@ -181,6 +183,22 @@ class Handle:
         _check(_lib.giem_apply_timed(self._p, ifreq, sa, nrhs, _ptr(x), _ptr(y), mode, prec,
                                      _stream(stream), ms))
         return list(ms)
+
+    def tune(self, sigma_a, nrhs=2, ifreq=0, stream=None):
+        """Time the FFT launch shapes on this handle and keep the fastest;
+        returns {"fp64"|"fp32": [(sequences, threads) per pass]}."""
+        ch = (ctypes.c_int32 * 16)()
+        _check(_lib.giem_tune(self._p, ifreq, _ptr(sigma_a), nrhs, _stream(stream), ch))
+        return {k: [(ch[(i * 4 + j) * 2], ch[(i * 4 + j) * 2 + 1]) for j in range(4)]
+                for i, k in enumerate(("fp64", "fp32"))}
+
+    def set_fft_shape(self, prec, shape=None):
+        """shape: four (sequences, threads) pairs, or None for the built-in choice."""
+        if shape is None:
+            _check(_lib.giem_set_fft_shape(self._p, prec, None))
+            return
+        arr = (ctypes.c_int32 * 8)(*[int(v) for pair in shape for v in pair])
+        _check(_lib.giem_set_fft_shape(self._p, prec, arr))
 
     def profile(self, enable=True):
         _check(_lib.giem_profile(self._p, 1 if enable else 0))

@@ -32,7 +32,7 @@ static bool factor_ok(int L, FftDesc &d) {
   d.L = L;
   d.nf = 0;
   int m = L;
-  const int radices[] = {4, 2, 3, 5, 7};
+  const int radices[] = {16, 8, 4, 2, 3, 5, 7};
   for (int r : radices) {
     while (m % r == 0) {
       if (d.nf >= kMaxFactors) return false;
@@ -97,6 +97,30 @@ int compute_diagonals(giem_handle *t, const c128 *sigma_a, hipStream_t s) {
   return GIEM_OK;
 }
 
+// Whether G sequences of length L on nthr threads can be launched.
+static bool fft_shape_ok(int G, int nthr, int L, unsigned prec) {
+  return G >= 1 && fft_ept(G, L, nthr, (int)prec) > 0 && fft_lds_bytes(G, L, (int)prec) <= 160 * 1024;
+}
+
+// Launch shape of the four FFT passes: the tuned one where set and valid,
+// else 128-byte runs of planes (8 c128 or 16 c64) on 256 threads, halved
+// until the sequences fit the per-thread register budget.
+static void fft_shape(const giem_handle *t, unsigned prec, int G[4], int NT[4]) {
+  const int pi = prec == PREC_FP32 ? 1 : 0;
+  const int L[4] = {2 * t->nx, 2 * t->ny, 2 * t->ny, 2 * t->nx};
+  for (int k = 0; k < 4; ++k) {
+    if (t->fft_g[pi][k] > 0 && fft_shape_ok(t->fft_g[pi][k], t->fft_nt[pi][k], L[k], prec)) {
+      G[k] = t->fft_g[pi][k];
+      NT[k] = t->fft_nt[pi][k];
+      continue;
+    }
+    int g = prec == PREC_FP32 ? 16 : 8;
+    while (g > 1 && !fft_shape_ok(g, 256, L[k], prec)) g /= 2;
+    G[k] = g;
+    NT[k] = 256;
+  }
+}
+
 int apply_core(giem_handle *t, int ifreq, int nrhs, const VecPtrs &p, unsigned mode,
                unsigned prec, hipStream_t s, double *stage_ms) {
   const int nx = t->nx, ny = t->ny, nz = t->nz;
@@ -117,10 +141,8 @@ int apply_core(giem_handle *t, int ifreq, int nrhs, const VecPtrs &p, unsigned m
     r2 = R1; r1 = R2; sd = S;
   }
   const int rp = nrhs * 3 * nz;
-  // planes per FFT workgroup: 128-byte runs, at most 32 elements per thread
-  int G = prec == PREC_FP32 ? 16 : 8;
-  const int Lmax = std::max(2 * nx, 2 * ny);
-  while (G > 1 && G * Lmax > 32 * 256) G /= 2;
+  int G[4], NT[4];
+  fft_shape(t, prec, G, NT);
   if (!block_supported(nz, nrhs)) {
     set_error("block product: 3 Nz x nrhs too large for one workgroup");
     return GIEM_EINVAL;
@@ -154,17 +176,20 @@ int apply_core(giem_handle *t, int ifreq, int nrhs, const VecPtrs &p, unsigned m
   void *spa = t->spec_ws;
   void *spb = static_cast<char *>(t->spec_ws) + (size_t)4 * nx * ny * rp * cbytes;
   GIEM_TRY(mark(0));
-  GIEM_HIP(launch_fft_x_fwd(prec, p, r2, spa, nx, ny, nz, rp, G, t->px.d, twx, s), "x-FFT");
+  GIEM_HIP(launch_fft_x_fwd(prec, p, r2, spa, nx, ny, nz, rp, G[0], NT[0], t->px.d, twx, s),
+           "x-FFT");
   GIEM_TRY(mark(1));
-  GIEM_HIP(launch_fft_y(prec, spa, 2 * nx, ny, rp, G, t->py.d, twy, 0, s), "y-FFT");
+  GIEM_HIP(launch_fft_y(prec, spa, 2 * nx, ny, rp, G[1], NT[1], t->py.d, twy, 0, s), "y-FFT");
   GIEM_TRY(mark(2));
   GIEM_HIP(launch_block(prec, tab, spa, spb, static_cast<const unsigned *>(t->bplan), nx, ny, nz,
                         nrhs, s),
            "block product");
   GIEM_TRY(mark(3));
-  GIEM_HIP(launch_fft_y(prec, spb, 2 * nx, ny, rp, G, t->py.d, twy, 1, s), "inverse y-FFT");
+  GIEM_HIP(launch_fft_y(prec, spb, 2 * nx, ny, rp, G[2], NT[2], t->py.d, twy, 1, s),
+           "inverse y-FFT");
   GIEM_TRY(mark(4));
-  GIEM_HIP(launch_fft_x_inv(prec, p, sd, r1, spb, nx, ny, nz, rp, G, t->px.d, twx, scale, s),
+  GIEM_HIP(launch_fft_x_inv(prec, p, sd, r1, spb, nx, ny, nz, rp, G[3], NT[3], t->px.d, twx, scale,
+                            s),
            "inverse x-FFT");
   GIEM_TRY(mark(5));
   if (stage_ms) {
@@ -262,6 +287,10 @@ static int create_handle(const giem_model *m, int nfreq, const double *freq, uin
     }
   if (3 * m->nz * ((4 * kMaxRhs + 3) / 4) > 1024 * 4) {
     set_error("Nz too large");
+    return GIEM_EINVAL;
+  }
+  if (m->nx > 2048 || m->ny > 2048) {
+    set_error("Nx and Ny must not exceed 2048 (transform lengths up to 4096)");
     return GIEM_EINVAL;
   }
   giem_handle *t = new giem_handle();
@@ -471,6 +500,111 @@ int giem_apply_timed(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t
     return GIEM_EINVAL;
   }
   return apply_entry(t, ifreq, sigma_a, nrhs, x, y, mode, prec, stream, stage_ms);
+}
+
+int giem_tune(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs, void *stream,
+              int32_t *chosen) {
+  if (!t || ifreq < 0 || ifreq >= (int)t->f.size() || nrhs < 1 || nrhs > kMaxRhs || !sigma_a) {
+    set_error("giem_tune: bad argument");
+    return GIEM_EINVAL;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  GIEM_TRY(compute_diagonals(t, static_cast<const c128 *>(sigma_a), s));
+  const size_t nbytes = (size_t)nrhs * t->nvec() * sizeof(c128);
+  void *x = nullptr, *y = nullptr;
+  struct Free {
+    void **a, **b;
+    ~Free() {
+      if (*a) hipFree(*a);
+      if (*b) hipFree(*b);
+    }
+  } fr{&x, &y};
+  GIEM_HIP(hipMalloc(&x, nbytes), "hipMalloc tuning input");
+  GIEM_HIP(hipMalloc(&y, nbytes), "hipMalloc tuning output");
+  GIEM_HIP(hipMemsetAsync(x, 0x3f, nbytes, s), "fill tuning input");  // doubles of order 1e-4
+  VecPtrs p{};
+  for (int r = 0; r < nrhs; ++r) {
+    p.in[r] = static_cast<const c128 *>(x) + r * t->nvec();
+    p.out[r] = static_cast<c128 *>(y) + r * t->nvec();
+  }
+  const int L[4] = {2 * t->nx, 2 * t->ny, 2 * t->ny, 2 * t->nx};
+  const int stage_of_pass[4] = {0, 1, 3, 4};
+  for (int pi = 0; pi < 2; ++pi) {
+    const unsigned prec = pi ? PREC_FP32 : PREC_FP64;
+    const bool have = pi ? t->f[ifreq].spec32 != nullptr : t->f[ifreq].spec64 != nullptr;
+    if (!have) {
+      for (int k = 0; k < 4; ++k) t->fft_g[pi][k] = t->fft_nt[pi][k] = 0;
+      continue;
+    }
+    double best[4] = {1e30, 1e30, 1e30, 1e30};
+    int bg[4] = {0, 0, 0, 0}, bt[4] = {0, 0, 0, 0};
+    for (int nt : {256, 512})
+      for (int g = 1; g <= 64; g *= 2) {
+        bool any = false;
+        for (int k = 0; k < 4; ++k) {
+          t->fft_g[pi][k] = g;
+          t->fft_nt[pi][k] = nt;
+          any = any || fft_shape_ok(g, nt, L[k], prec);
+        }
+        if (!any) continue;
+        double st[5];
+        for (int w = 0; w < 2; ++w) GIEM_TRY(apply_core(t, ifreq, nrhs, p, MODE_A, prec, s, st));
+        std::vector<double> ms[4];
+        for (int rep = 0; rep < 5; ++rep) {
+          GIEM_TRY(apply_core(t, ifreq, nrhs, p, MODE_A, prec, s, st));
+          for (int k = 0; k < 4; ++k) ms[k].push_back(st[stage_of_pass[k]]);
+        }
+        for (int k = 0; k < 4; ++k) {
+          if (!fft_shape_ok(g, nt, L[k], prec)) continue;
+          std::sort(ms[k].begin(), ms[k].end());
+          if (ms[k][2] < best[k]) {
+            best[k] = ms[k][2];
+            bg[k] = g;
+            bt[k] = nt;
+          }
+        }
+      }
+    for (int k = 0; k < 4; ++k) {
+      t->fft_g[pi][k] = bg[k];
+      t->fft_nt[pi][k] = bt[k];
+    }
+  }
+  if (chosen) {
+    for (int pi = 0; pi < 2; ++pi) {
+      int G[4], NT[4];
+      fft_shape(t, pi ? PREC_FP32 : PREC_FP64, G, NT);
+      for (int k = 0; k < 4; ++k) {
+        chosen[(pi * 4 + k) * 2] = G[k];
+        chosen[(pi * 4 + k) * 2 + 1] = NT[k];
+      }
+    }
+  }
+  return GIEM_OK;
+}
+
+int giem_set_fft_shape(giem_handle *t, uint32_t prec, const int32_t *shape) {
+  if (!t || prec > PREC_FP32) {
+    set_error("giem_set_fft_shape: bad argument");
+    return GIEM_EINVAL;
+  }
+  const int pi = prec == PREC_FP32 ? 1 : 0;
+  if (!shape) {
+    for (int k = 0; k < 4; ++k) t->fft_g[pi][k] = t->fft_nt[pi][k] = 0;
+    return GIEM_OK;
+  }
+  const int L[4] = {2 * t->nx, 2 * t->ny, 2 * t->ny, 2 * t->nx};
+  for (int k = 0; k < 4; ++k)
+    if (!fft_shape_ok(shape[2 * k], shape[2 * k + 1], L[k], prec)) {
+      set_error("giem_set_fft_shape: pass " + std::to_string(k) + " cannot run " +
+                std::to_string(shape[2 * k]) + " sequences on " + std::to_string(shape[2 * k + 1]) +
+                " threads");
+      return GIEM_EINVAL;
+    }
+  for (int k = 0; k < 4; ++k) {
+    t->fft_g[pi][k] = shape[2 * k];
+    t->fft_nt[pi][k] = shape[2 * k + 1];
+  }
+  return GIEM_OK;
 }
 
 int giem_profile(giem_handle *t, int32_t enable) {

@@ -66,6 +66,10 @@ struct giem_handle {
   void *vec_ws = nullptr;
   size_t vec_ws_bytes = 0;
   giem::SolveWork *sw = nullptr;
+  // FFT launch shape per precision (0 = FP64, 1 = FP32) and pass (x forward,
+  // y forward, y inverse, x inverse): sequences per workgroup and threads per
+  // workgroup, set by giem_tune; 0 selects the built-in choice
+  int fft_g[2][4] = {}, fft_nt[2][4] = {};
   // stage profiling (giem_profile): 6 events per recorded apply
   bool prof = false;
   std::vector<hipEvent_t> prof_ev;

@@ -14,13 +14,17 @@ int block_threads(int nz, int R);
 size_t block_lds_bytes(int nz, int R, int prec);
 bool block_supported(int nz, int R);
 size_t fft_lds_bytes(int G, int L, int prec);
+// elements per thread for G sequences of length L on nthr threads; 0 when no
+// kernel is instantiated for it (nthr in {256, 512})
+int fft_ept(int G, int L, int nthr, int prec);
 hipError_t launch_fft_x_fwd(int prec, const VecPtrs &ptrs, const c128 *r2, void *spec, int nx,
-                            int ny, int nz, int rp_total, int G, const FftDesc &fd,
+                            int ny, int nz, int rp_total, int G, int nthr, const FftDesc &fd,
                             const void *tw, hipStream_t s);
 hipError_t launch_fft_x_inv(int prec, const VecPtrs &ptrs, const c128 *sd, const c128 *r1,
                             const void *spec, int nx, int ny, int nz, int rp_total, int G,
-                            const FftDesc &fd, const void *tw, double scale, hipStream_t s);
-hipError_t launch_fft_y(int prec, void *spec, int nx2, int ny, int rp_total, int G,
+                            int nthr, const FftDesc &fd, const void *tw, double scale,
+                            hipStream_t s);
+hipError_t launch_fft_y(int prec, void *spec, int nx2, int ny, int rp_total, int G, int nthr,
                         const FftDesc &fd, const void *tw, int inverse, hipStream_t s);
 // out-of-place: sin and sout are two spectra buffers; plan from block_plan(nz)
 hipError_t launch_block(int prec, const void *tab, const void *sin, void *sout,

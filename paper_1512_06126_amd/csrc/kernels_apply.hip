@@ -11,15 +11,49 @@
 // frequency point as one contiguous run and the FFT passes move G adjacent
 // planes (128-byte runs) per frequency point.
 //
-// FFTs are mixed-radix (4, 2, 3, 5, 7) Stockham passes done in LDS, G
-// sequences per workgroup, twiddles from a per-length table.
+// FFTs are mixed-radix (16, 8, 4, 2, 3, 5, 7) Stockham passes done in LDS,
+// G sequences per workgroup; radix 16 and 8 are nested length-4 transforms in
+// registers, so a 256-point transform takes two passes through LDS.  Twiddles
+// between passes come from a per-length table.
 #include "kernels.h"
 
 namespace giem {
 
-constexpr int kFftThreads = 256;  // workgroup size of the FFT passes
-
 // ------------------------------------------------------------------ small DFTs
+// The LDS copy of a sequence is padded by one element after every 16, so
+// that the strided Stockham writes of radix 16, 8, 4 and 2 spread over all
+// banks (element offsets 17, 8.5, 4.25, 2.125 per lane are distinct mod 16).
+__host__ __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
+__host__ __device__ __forceinline__ int fft_ld(int L) { return L + (L >> 4) + 1; }
+
+// cos and sin of 2 pi m / 16
+__device__ constexpr double kC16[16] = {1.0, 0.92387953251128674, 0.70710678118654752, 0.38268343236508977,
+                                        0.0, -0.38268343236508977, -0.70710678118654752, -0.92387953251128674,
+                                        -1.0, -0.92387953251128674, -0.70710678118654752, -0.38268343236508977,
+                                        0.0, 0.38268343236508977, 0.70710678118654752, 0.92387953251128674};
+__device__ constexpr double kS16[16] = {0.0, 0.38268343236508977, 0.70710678118654752, 0.92387953251128674,
+                                        1.0, 0.92387953251128674, 0.70710678118654752, 0.38268343236508977,
+                                        0.0, -0.38268343236508977, -0.70710678118654752, -0.92387953251128674,
+                                        -1.0, -0.92387953251128674, -0.70710678118654752, -0.38268343236508977};
+
+// v * exp(-+ 2 pi i m / 16) (minus for the forward transform)
+template <typename T>
+__device__ __forceinline__ cplx<T> rot16(cplx<T> v, int m, bool inv) {
+  const T c = (T)kC16[m & 15], sn = inv ? (T)kS16[m & 15] : -(T)kS16[m & 15];
+  return mk<T>(v.x * c - v.y * sn, v.x * sn + v.y * c);
+}
+
+template <typename T>
+__device__ __forceinline__ void dft4(cplx<T> &a0, cplx<T> &a1, cplx<T> &a2, cplx<T> &a3, bool inv) {
+  const cplx<T> t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), t3 = csub(a1, a3);
+  const cplx<T> mit3 = mk<T>(t3.y, -t3.x);  // -i t3
+  a0 = cadd(t0, t2);
+  a2 = csub(t0, t2);
+  // forward: y1 = t1 - i t3, y3 = t1 + i t3; the inverse swaps them
+  a1 = inv ? csub(t1, mit3) : cadd(t1, mit3);
+  a3 = inv ? cadd(t1, mit3) : csub(t1, mit3);
+}
+
 template <typename T, int P>
 __device__ __forceinline__ void small_dft(cplx<T> (&v)[P], bool inv,
                                           const cplx<T> *__restrict__ tw, int L) {
@@ -29,19 +63,45 @@ __device__ __forceinline__ void small_dft(cplx<T> (&v)[P], bool inv,
     v[0] = a;
     v[1] = b;
   } else if constexpr (P == 4) {
-    cplx<T> t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
-    cplx<T> t2 = cadd(v[1], v[3]), t3 = csub(v[1], v[3]);
-    // forward: y1 = t1 - i t3, y3 = t1 + i t3; inverse swaps them
-    cplx<T> mit3 = mk<T>(t3.y, -t3.x);  // -i t3
-    v[0] = cadd(t0, t2);
-    v[2] = csub(t0, t2);
-    if (!inv) {
-      v[1] = cadd(t1, mit3);
-      v[3] = csub(t1, mit3);
-    } else {
-      v[1] = csub(t1, mit3);
-      v[3] = cadd(t1, mit3);
+    dft4(v[0], v[1], v[2], v[3], inv);
+  } else if constexpr (P == 8) {
+    // n = n1 + 2 n2, k = k2 + 4 k1: length-4 DFTs over n2, twiddles
+    // W8^(n1 k2), length-2 DFTs over n1
+    dft4(v[0], v[2], v[4], v[6], inv);
+    dft4(v[1], v[3], v[5], v[7], inv);
+    cplx<T> b[4];
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) b[k2] = rot16(v[2 * k2 + 1], 2 * k2, inv);
+    cplx<T> out[8];
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) {
+      out[k2] = cadd(v[2 * k2], b[k2]);
+      out[k2 + 4] = csub(v[2 * k2], b[k2]);
     }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = out[k];
+  } else if constexpr (P == 16) {
+    // n = n1 + 4 n2, k = k2 + 4 k1: length-4 DFTs over n2, twiddles
+    // W16^(n1 k2), length-4 DFTs over n1
+#pragma unroll
+    for (int n1 = 0; n1 < 4; ++n1) dft4(v[n1], v[n1 + 4], v[n1 + 8], v[n1 + 12], inv);
+#pragma unroll
+    for (int n1 = 1; n1 < 4; ++n1)
+#pragma unroll
+      for (int k2 = 1; k2 < 4; ++k2) v[n1 + 4 * k2] = rot16(v[n1 + 4 * k2], n1 * k2, inv);
+    // now v[n1 + 4 k2] holds the twiddled inner results
+    cplx<T> out[16];
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) {
+      cplx<T> a0 = v[4 * k2], a1 = v[4 * k2 + 1], a2 = v[4 * k2 + 2], a3 = v[4 * k2 + 3];
+      dft4(a0, a1, a2, a3, inv);
+      out[k2] = a0;
+      out[k2 + 4] = a1;
+      out[k2 + 8] = a2;
+      out[k2 + 12] = a3;
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = out[k];
   } else {
     // generic odd radix: y_t = sum_s x_s W^(s t mod P), W = exp(-+ 2 pi i / P)
     cplx<T> out[P];
@@ -82,7 +142,7 @@ __device__ __forceinline__ void fft_pass(cplx<T> *buf, int G, int ld, int L, int
     if (b < nb) {
       const int g = b / lp, j = b - g * lp;
 #pragma unroll
-      for (int q = 0; q < P; ++q) v[i][q] = buf[g * ld + j + q * lp];
+      for (int q = 0; q < P; ++q) v[i][q] = buf[g * ld + lds_pad(j + q * lp)];
     }
   }
   __syncthreads();
@@ -94,35 +154,63 @@ __device__ __forceinline__ void fft_pass(cplx<T> *buf, int G, int ld, int L, int
       const int g = b / lp, j = b - g * lp;
       const int k = j % ns;
       if (k != 0) {
+        if constexpr (P >= 8) {
+          // W^q by a running product from one table entry (at most P - 1
+          // products deep: a few units of rounding), instead of P - 1 loads
+          // held in registers
+          cplx<T> w1 = tw[k * tstride];
+          if (inv) w1.y = -w1.y;
+          cplx<T> w = w1;
 #pragma unroll
-        for (int q = 1; q < P; ++q) {
-          cplx<T> w = tw[q * k * tstride];
-          if (inv) w.y = -w.y;
-          v[i][q] = cmul(v[i][q], w);
+          for (int q = 1; q < P; ++q) {
+            v[i][q] = cmul(v[i][q], w);
+            if (q + 1 < P) w = cmul(w, w1);
+          }
+        } else {
+#pragma unroll
+          for (int q = 1; q < P; ++q) {
+            cplx<T> w = tw[q * k * tstride];
+            if (inv) w.y = -w.y;
+            v[i][q] = cmul(v[i][q], w);
+          }
         }
       }
       small_dft<T, P>(v[i], inv, tw, L);
-      const int base = g * ld + (j / ns) * ns * P + k;
+      const int base = (j / ns) * ns * P + k;
 #pragma unroll
-      for (int q = 0; q < P; ++q) buf[base + q * ns] = v[i][q];
+      for (int q = 0; q < P; ++q) buf[g * ld + lds_pad(base + q * ns)] = v[i][q];
     }
   }
   __syncthreads();
 }
 
-template <typename T, int EPT>
+// All passes of one transform.  POW2 instantiations (lengths 2^k) carry
+// only the radix 16, 8, 4 and 2 passes: register allocation takes the
+// largest path of the switch, and the odd-radix passes would cost occupancy.
+template <typename T, int EPT, bool POW2>
 __device__ void fft_lds(cplx<T> *buf, int G, int ld, const FftDesc &fd,
                         const cplx<T> *__restrict__ tw, bool inv) {
   __syncthreads();
   int ns = 1;
   for (int s = 0; s < fd.nf; ++s) {
     const int p = fd.fac[s];
-    switch (p) {
-      case 4: fft_pass<T, 4, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
-      case 2: fft_pass<T, 2, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
-      case 3: fft_pass<T, 3, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
-      case 5: fft_pass<T, 5, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
-      default: fft_pass<T, 7, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
+    if constexpr (POW2) {
+      switch (p) {
+        case 16: fft_pass<T, 16, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
+        case 8: fft_pass<T, 8, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
+        case 4: fft_pass<T, 4, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
+        default: fft_pass<T, 2, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
+      }
+    } else {
+      switch (p) {
+        case 16: fft_pass<T, 16, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
+        case 8: fft_pass<T, 8, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
+        case 4: fft_pass<T, 4, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
+        case 2: fft_pass<T, 2, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
+        case 3: fft_pass<T, 3, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
+        case 5: fft_pass<T, 5, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
+        default: fft_pass<T, 7, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
+      }
     }
     ns *= p;
   }
@@ -131,13 +219,13 @@ __device__ void fft_lds(cplx<T> *buf, int G, int ld, const FftDesc &fd,
 // ---------------------------------------------------------------- x passes
 // Step 1, x pass: u -> R2 u (or u), zero-pad to 2 Nx, forward FFT along x.
 // Grid: (y, plane group).  Output rows y < Ny of the spectra buffer.
-template <typename T, int EPT>
-__global__ void __launch_bounds__(kFftThreads)
+template <typename T, int EPT, int NT, bool POW2>
+__global__ void __launch_bounds__(NT)
 k_fft_x_fwd(VecPtrs ptrs, const c128 *__restrict__ r2, cplx<T> *__restrict__ spec, int nx,
             int ny, int nz, int rp_total, int G, FftDesc fd, const cplx<T> *__restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T> *buf = reinterpret_cast<cplx<T> *>(smem_raw);
-  const int L = fd.L, ld = L + 1;
+  const int L = fd.L, ld = fft_ld(L);
   const int y = blockIdx.x;
   const int rp0 = blockIdx.y * G;
   const int p3 = 3 * nz;
@@ -146,7 +234,7 @@ k_fft_x_fwd(VecPtrs ptrs, const c128 *__restrict__ r2, cplx<T> *__restrict__ spe
   c128 va[EPT], vs[EPT];
 #pragma unroll
   for (int u = 0; u < EPT; ++u) {
-    const int e = threadIdx.x + u * kFftThreads;
+    const int e = threadIdx.x + u * NT;
     const int g = e / L, xx = e - g * L;
     const int rp = rp0 + g;
     va[u] = mk<double>(0, 0);
@@ -160,31 +248,31 @@ k_fft_x_fwd(VecPtrs ptrs, const c128 *__restrict__ r2, cplx<T> *__restrict__ spe
   }
 #pragma unroll
   for (int u = 0; u < EPT; ++u) {
-    const int e = threadIdx.x + u * kFftThreads;
+    const int e = threadIdx.x + u * NT;
     if (e < G * L) {
       const int g = e / L, xx = e - g * L;
-      buf[g * ld + xx] = ccast<T>(cmul(va[u], vs[u]));
+      buf[g * ld + lds_pad(xx)] = ccast<T>(cmul(va[u], vs[u]));
     }
   }
-  fft_lds<T, EPT>(buf, G, ld, fd, tw, false);
+  fft_lds<T, EPT, POW2>(buf, G, ld, fd, tw, false);
   for (int e = threadIdx.x; e < G * L; e += blockDim.x) {
     const int K = e / G, g = e - K * G;
     const int rp = rp0 + g;
-    if (rp < rp_total) spec[((size_t)y * L + K) * rp_total + rp] = buf[g * ld + K];
+    if (rp < rp_total) spec[((size_t)y * L + K) * rp_total + rp] = buf[g * ld + lds_pad(K)];
   }
 }
 
 // Step 3, x pass: inverse FFT along x, keep x < Nx, scale by 1/(4 Nx Ny) and
 // finish the operator: y = S u + R1 (B R2 u)  (mode A, with R1/R2 swapped for
 // A^T), or y = B u (mode B: s == nullptr, r1 == nullptr).
-template <typename T, int EPT>
-__global__ void __launch_bounds__(kFftThreads)
+template <typename T, int EPT, int NT, bool POW2>
+__global__ void __launch_bounds__(NT)
 k_fft_x_inv(VecPtrs ptrs, const c128 *__restrict__ sdiag, const c128 *__restrict__ r1,
             const cplx<T> *__restrict__ spec, int nx, int ny, int nz, int rp_total, int G,
             FftDesc fd, const cplx<T> *__restrict__ tw, double scale) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T> *buf = reinterpret_cast<cplx<T> *>(smem_raw);
-  const int L = fd.L, ld = L + 1;
+  const int L = fd.L, ld = fft_ld(L);
   const int y = blockIdx.x;
   const int rp0 = blockIdx.y * G;
   const int p3 = 3 * nz;
@@ -193,7 +281,7 @@ k_fft_x_inv(VecPtrs ptrs, const c128 *__restrict__ sdiag, const c128 *__restrict
     cplx<T> v[EPT];
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
-      const int e = threadIdx.x + u * kFftThreads;
+      const int e = threadIdx.x + u * NT;
       const int K = e / G, g = e - K * G;
       const int rp = rp0 + g;
       v[u] = mk<T>(0, 0);
@@ -201,47 +289,33 @@ k_fft_x_inv(VecPtrs ptrs, const c128 *__restrict__ sdiag, const c128 *__restrict
     }
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
-      const int e = threadIdx.x + u * kFftThreads;
+      const int e = threadIdx.x + u * NT;
       if (e < G * L) {
         const int K = e / G, g = e - K * G;
-        buf[g * ld + K] = v[u];
+        buf[g * ld + lds_pad(K)] = v[u];
       }
     }
   }
-  // the diagonal terms of the epilogue are loaded while the FFT runs
+  fft_lds<T, EPT, POW2>(buf, G, ld, fd, tw, true);
+  // epilogue: the diagonal terms are loaded after the transform, so that
+  // they do not hold registers across it
   constexpr int EO = (EPT + 1) / 2;  // G * nx <= G * L / 2 outputs
-  c128 xin[EO], dsd[EO], dr1[EO];
-  if (r1) {
-#pragma unroll
-    for (int u = 0; u < EO; ++u) {
-      const int e = threadIdx.x + u * kFftThreads;
-      const int g = e / nx, xx = e - g * nx;
-      const int rp = rp0 + g;
-      if (e < G * nx && rp < rp_total) {
-        const int r = rp / p3, p = rp - r * p3;
-        const int iz = p % nz;
-        const size_t cell = (size_t)iz * plane + (size_t)y * nx + xx;
-        xin[u] = ptrs.in[r][(size_t)p * plane + (size_t)y * nx + xx];
-        dsd[u] = sdiag[cell];
-        dr1[u] = r1[cell];
-      }
-    }
-  }
-  fft_lds<T, EPT>(buf, G, ld, fd, tw, true);
 #pragma unroll
   for (int u = 0; u < EO; ++u) {
-    const int e = threadIdx.x + u * kFftThreads;
+    const int e = threadIdx.x + u * NT;
     const int g = e / nx, xx = e - g * nx;
     const int rp = rp0 + g;
     if (e < G * nx && rp < rp_total) {
       const int r = rp / p3, p = rp - r * p3;
       const size_t off = (size_t)p * plane + (size_t)y * nx + xx;
-      c128 b = ccast<double>(buf[g * ld + xx]);
+      c128 b = ccast<double>(buf[g * ld + lds_pad(xx)]);
       b = cscale(b, scale);
       c128 out = b;
       if (r1) {
-        out = cmul(dr1[u], b);
-        cfma(out, dsd[u], xin[u]);
+        const int iz = p % nz;
+        const size_t cell = (size_t)iz * plane + (size_t)y * nx + xx;
+        out = cmul(r1[cell], b);
+        cfma(out, sdiag[cell], ptrs.in[r][off]);
       }
       ptrs.out[r][off] = out;
     }
@@ -251,13 +325,13 @@ k_fft_x_inv(VecPtrs ptrs, const c128 *__restrict__ sdiag, const c128 *__restrict
 // ---------------------------------------------------------------- y passes
 // Forward (rows y >= Ny are zero, output all 2 Ny rows) or inverse (read all
 // 2 Ny rows, write rows < Ny) FFT along y, in place.  Grid: (Kx, plane group).
-template <typename T, int EPT>
-__global__ void __launch_bounds__(kFftThreads)
+template <typename T, int EPT, int NT, bool POW2>
+__global__ void __launch_bounds__(NT)
 k_fft_y(cplx<T> *__restrict__ spec, int nx2, int ny, int rp_total, int G, FftDesc fd,
         const cplx<T> *__restrict__ tw, int inverse) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T> *buf = reinterpret_cast<cplx<T> *>(smem_raw);
-  const int L = fd.L, ld = L + 1;
+  const int L = fd.L, ld = fft_ld(L);
   const int kx = blockIdx.x;
   const int rp0 = blockIdx.y * G;
   const int nin = inverse ? L : ny;
@@ -266,7 +340,7 @@ k_fft_y(cplx<T> *__restrict__ spec, int nx2, int ny, int rp_total, int G, FftDes
     cplx<T> v[EPT];
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
-      const int e = threadIdx.x + u * kFftThreads;
+      const int e = threadIdx.x + u * NT;
       const int yy = e / G, g = e - yy * G;
       const int rp = rp0 + g;
       v[u] = mk<T>(0, 0);
@@ -274,87 +348,99 @@ k_fft_y(cplx<T> *__restrict__ spec, int nx2, int ny, int rp_total, int G, FftDes
     }
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
-      const int e = threadIdx.x + u * kFftThreads;
+      const int e = threadIdx.x + u * NT;
       if (e < G * L) {
         const int yy = e / G, g = e - yy * G;
-        buf[g * ld + yy] = v[u];
+        buf[g * ld + lds_pad(yy)] = v[u];
       }
     }
   }
-  fft_lds<T, EPT>(buf, G, ld, fd, tw, inverse != 0);
+  fft_lds<T, EPT, POW2>(buf, G, ld, fd, tw, inverse != 0);
   for (int e = threadIdx.x; e < G * nout; e += blockDim.x) {
     const int yy = e / G, g = e - yy * G;
     const int rp = rp0 + g;
-    if (rp < rp_total) spec[((size_t)yy * nx2 + kx) * rp_total + rp] = buf[g * ld + yy];
+    if (rp < rp_total) spec[((size_t)yy * nx2 + kx) * rp_total + rp] = buf[g * ld + lds_pad(yy)];
   }
 }
 
 // ---------------------------------------------------------------- launchers
-static int ept_for(int G, int L, int nthr) {
+// Elements per thread of a pass over G sequences of length L with nthr
+// threads (0 if the configuration is not instantiated).  At most 16: the x
+// passes stage c128 input in registers, and 32 per thread spills.
+int fft_ept(int G, int L, int nthr, int prec) {
+  (void)prec;
+  if (nthr != 256 && nthr != 512) return 0;
   const int need = (G * L + nthr - 1) / nthr;
-  if (need <= 4) return 4;
-  if (need <= 8) return 8;
-  if (need <= 16) return 16;
-  return 32;
+  for (int e = 4; e <= 16; e *= 2)
+    if (need <= e) return e;
+  return 0;
 }
+
+#define GIEM_FFT_CASES(KERNEL, NTV, P2, ...)                                                 \
+  switch (ept) {                                                                              \
+    case 4: KERNEL<T, 4, NTV, P2><<<grid, NTV, lds, s>>>(__VA_ARGS__); break;                 \
+    case 8: KERNEL<T, 8, NTV, P2><<<grid, NTV, lds, s>>>(__VA_ARGS__); break;                 \
+    case 16: KERNEL<T, 16, NTV, P2><<<grid, NTV, lds, s>>>(__VA_ARGS__); break;               \
+    default: return hipErrorInvalidConfiguration;                                             \
+  }
+#define GIEM_FFT_DISPATCH(KERNEL, ...)                                                        \
+  do {                                                                                        \
+    const int ept = fft_ept(G, fd.L, nthr, sizeof(T) == 4 ? PREC_FP32 : PREC_FP64);          \
+    const bool pow2 = (fd.L & (fd.L - 1)) == 0;                                              \
+    if (nthr == 512 && pow2) {                                                                \
+      GIEM_FFT_CASES(KERNEL, 512, true, __VA_ARGS__)                                          \
+    } else if (nthr == 512) {                                                                 \
+      GIEM_FFT_CASES(KERNEL, 512, false, __VA_ARGS__)                                         \
+    } else if (nthr == 256 && pow2) {                                                         \
+      GIEM_FFT_CASES(KERNEL, 256, true, __VA_ARGS__)                                          \
+    } else if (nthr == 256) {                                                                 \
+      GIEM_FFT_CASES(KERNEL, 256, false, __VA_ARGS__)                                         \
+    } else {                                                                                  \
+      return hipErrorInvalidConfiguration;                                                    \
+    }                                                                                         \
+  } while (0)
 
 template <typename T>
 static hipError_t launch_fft_x_fwd_t(const VecPtrs &ptrs, const c128 *r2, void *spec, int nx,
-                                     int ny, int nz, int rp_total, int G, const FftDesc &fd,
-                                     const void *tw, hipStream_t s) {
-  const int nthr = 256;
+                                     int ny, int nz, int rp_total, int G, int nthr,
+                                     const FftDesc &fd, const void *tw, hipStream_t s) {
   dim3 grid(ny, (rp_total + G - 1) / G);
-  size_t lds = (size_t)G * (fd.L + 1) * sizeof(cplx<T>);
+  size_t lds = (size_t)G * fft_ld(fd.L) * sizeof(cplx<T>);
   const cplx<T> *twp = static_cast<const cplx<T> *>(tw);
   cplx<T> *sp = static_cast<cplx<T> *>(spec);
-  switch (ept_for(G, fd.L, nthr)) {
-    case 4: k_fft_x_fwd<T, 4><<<grid, nthr, lds, s>>>(ptrs, r2, sp, nx, ny, nz, rp_total, G, fd, twp); break;
-    case 8: k_fft_x_fwd<T, 8><<<grid, nthr, lds, s>>>(ptrs, r2, sp, nx, ny, nz, rp_total, G, fd, twp); break;
-    case 16: k_fft_x_fwd<T, 16><<<grid, nthr, lds, s>>>(ptrs, r2, sp, nx, ny, nz, rp_total, G, fd, twp); break;
-    default: k_fft_x_fwd<T, 32><<<grid, nthr, lds, s>>>(ptrs, r2, sp, nx, ny, nz, rp_total, G, fd, twp); break;
-  }
+  GIEM_FFT_DISPATCH(k_fft_x_fwd, ptrs, r2, sp, nx, ny, nz, rp_total, G, fd, twp);
   return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t launch_fft_x_inv_t(const VecPtrs &ptrs, const c128 *sd, const c128 *r1,
                                      const void *spec, int nx, int ny, int nz, int rp_total,
-                                     int G, const FftDesc &fd, const void *tw, double scale,
-                                     hipStream_t s) {
-  const int nthr = 256;
+                                     int G, int nthr, const FftDesc &fd, const void *tw,
+                                     double scale, hipStream_t s) {
   dim3 grid(ny, (rp_total + G - 1) / G);
-  size_t lds = (size_t)G * (fd.L + 1) * sizeof(cplx<T>);
+  size_t lds = (size_t)G * fft_ld(fd.L) * sizeof(cplx<T>);
   const cplx<T> *twp = static_cast<const cplx<T> *>(tw);
   const cplx<T> *sp = static_cast<const cplx<T> *>(spec);
-  switch (ept_for(G, fd.L, nthr)) {
-    case 4: k_fft_x_inv<T, 4><<<grid, nthr, lds, s>>>(ptrs, sd, r1, sp, nx, ny, nz, rp_total, G, fd, twp, scale); break;
-    case 8: k_fft_x_inv<T, 8><<<grid, nthr, lds, s>>>(ptrs, sd, r1, sp, nx, ny, nz, rp_total, G, fd, twp, scale); break;
-    case 16: k_fft_x_inv<T, 16><<<grid, nthr, lds, s>>>(ptrs, sd, r1, sp, nx, ny, nz, rp_total, G, fd, twp, scale); break;
-    default: k_fft_x_inv<T, 32><<<grid, nthr, lds, s>>>(ptrs, sd, r1, sp, nx, ny, nz, rp_total, G, fd, twp, scale); break;
-  }
+  GIEM_FFT_DISPATCH(k_fft_x_inv, ptrs, sd, r1, sp, nx, ny, nz, rp_total, G, fd, twp, scale);
   return hipGetLastError();
 }
 
 template <typename T>
-static hipError_t launch_fft_y_t(void *spec, int nx2, int ny, int rp_total, int G,
+static hipError_t launch_fft_y_t(void *spec, int nx2, int ny, int rp_total, int G, int nthr,
                                  const FftDesc &fd, const void *tw, int inverse, hipStream_t s) {
-  const int nthr = 256;
   dim3 grid(nx2, (rp_total + G - 1) / G);
-  size_t lds = (size_t)G * (fd.L + 1) * sizeof(cplx<T>);
+  size_t lds = (size_t)G * fft_ld(fd.L) * sizeof(cplx<T>);
   const cplx<T> *twp = static_cast<const cplx<T> *>(tw);
   cplx<T> *sp = static_cast<cplx<T> *>(spec);
-  switch (ept_for(G, fd.L, nthr)) {
-    case 4: k_fft_y<T, 4><<<grid, nthr, lds, s>>>(sp, nx2, ny, rp_total, G, fd, twp, inverse); break;
-    case 8: k_fft_y<T, 8><<<grid, nthr, lds, s>>>(sp, nx2, ny, rp_total, G, fd, twp, inverse); break;
-    case 16: k_fft_y<T, 16><<<grid, nthr, lds, s>>>(sp, nx2, ny, rp_total, G, fd, twp, inverse); break;
-    default: k_fft_y<T, 32><<<grid, nthr, lds, s>>>(sp, nx2, ny, rp_total, G, fd, twp, inverse); break;
-  }
+  GIEM_FFT_DISPATCH(k_fft_y, sp, nx2, ny, rp_total, G, fd, twp, inverse);
   return hipGetLastError();
 }
+#undef GIEM_FFT_DISPATCH
+#undef GIEM_FFT_CASES
 
 size_t fft_lds_bytes(int G, int L, int prec) {
   const size_t c = prec == PREC_FP32 ? sizeof(c64) : sizeof(c128);
-  return (size_t)G * (L + 1) * c;
+  return (size_t)G * fft_ld(L) * c;
 }
 
 hipError_t set_lds_limits() {
@@ -363,34 +449,41 @@ hipError_t set_lds_limits() {
   hipError_t e = hipSuccess;
 #define GIEM_SET(k) \
   if (e == hipSuccess) e = hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize, lim)
-  GIEM_SET((k_fft_x_fwd<double, 4>)); GIEM_SET((k_fft_x_fwd<double, 8>)); GIEM_SET((k_fft_x_fwd<double, 16>)); GIEM_SET((k_fft_x_fwd<double, 32>));
-  GIEM_SET((k_fft_x_fwd<float, 4>)); GIEM_SET((k_fft_x_fwd<float, 8>)); GIEM_SET((k_fft_x_fwd<float, 16>)); GIEM_SET((k_fft_x_fwd<float, 32>));
-  GIEM_SET((k_fft_x_inv<double, 4>)); GIEM_SET((k_fft_x_inv<double, 8>)); GIEM_SET((k_fft_x_inv<double, 16>)); GIEM_SET((k_fft_x_inv<double, 32>));
-  GIEM_SET((k_fft_x_inv<float, 4>)); GIEM_SET((k_fft_x_inv<float, 8>)); GIEM_SET((k_fft_x_inv<float, 16>)); GIEM_SET((k_fft_x_inv<float, 32>));
-  GIEM_SET((k_fft_y<double, 4>)); GIEM_SET((k_fft_y<double, 8>)); GIEM_SET((k_fft_y<double, 16>)); GIEM_SET((k_fft_y<double, 32>));
-  GIEM_SET((k_fft_y<float, 4>)); GIEM_SET((k_fft_y<float, 8>)); GIEM_SET((k_fft_y<float, 16>)); GIEM_SET((k_fft_y<float, 32>));
+#define GIEM_SET_NT(K, T, P2)                                                               \
+  GIEM_SET((K<T, 4, 256, P2>)); GIEM_SET((K<T, 8, 256, P2>)); GIEM_SET((K<T, 16, 256, P2>));  \
+  GIEM_SET((K<T, 4, 512, P2>)); GIEM_SET((K<T, 8, 512, P2>)); GIEM_SET((K<T, 16, 512, P2>))
+#define GIEM_SET_ALL(K)                                                                     \
+  GIEM_SET_NT(K, double, true); GIEM_SET_NT(K, double, false);                              \
+  GIEM_SET_NT(K, float, true); GIEM_SET_NT(K, float, false)
+  GIEM_SET_ALL(k_fft_x_fwd);
+  GIEM_SET_ALL(k_fft_x_inv);
+  GIEM_SET_ALL(k_fft_y);
+#undef GIEM_SET_ALL
+#undef GIEM_SET_NT
 #undef GIEM_SET
   if (e == hipSuccess) e = set_block_lds_limits();
   return e;
 }
 
 hipError_t launch_fft_x_fwd(int prec, const VecPtrs &ptrs, const c128 *r2, void *spec, int nx,
-                            int ny, int nz, int rp_total, int G, const FftDesc &fd,
+                            int ny, int nz, int rp_total, int G, int nthr, const FftDesc &fd,
                             const void *tw, hipStream_t s) {
   return prec == PREC_FP32
-             ? launch_fft_x_fwd_t<float>(ptrs, r2, spec, nx, ny, nz, rp_total, G, fd, tw, s)
-             : launch_fft_x_fwd_t<double>(ptrs, r2, spec, nx, ny, nz, rp_total, G, fd, tw, s);
+             ? launch_fft_x_fwd_t<float>(ptrs, r2, spec, nx, ny, nz, rp_total, G, nthr, fd, tw, s)
+             : launch_fft_x_fwd_t<double>(ptrs, r2, spec, nx, ny, nz, rp_total, G, nthr, fd, tw, s);
 }
 hipError_t launch_fft_x_inv(int prec, const VecPtrs &ptrs, const c128 *sd, const c128 *r1,
                             const void *spec, int nx, int ny, int nz, int rp_total, int G,
-                            const FftDesc &fd, const void *tw, double scale, hipStream_t s) {
+                            int nthr, const FftDesc &fd, const void *tw, double scale,
+                            hipStream_t s) {
   return prec == PREC_FP32
-             ? launch_fft_x_inv_t<float>(ptrs, sd, r1, spec, nx, ny, nz, rp_total, G, fd, tw, scale, s)
-             : launch_fft_x_inv_t<double>(ptrs, sd, r1, spec, nx, ny, nz, rp_total, G, fd, tw, scale, s);
+             ? launch_fft_x_inv_t<float>(ptrs, sd, r1, spec, nx, ny, nz, rp_total, G, nthr, fd, tw, scale, s)
+             : launch_fft_x_inv_t<double>(ptrs, sd, r1, spec, nx, ny, nz, rp_total, G, nthr, fd, tw, scale, s);
 }
-hipError_t launch_fft_y(int prec, void *spec, int nx2, int ny, int rp_total, int G,
+hipError_t launch_fft_y(int prec, void *spec, int nx2, int ny, int rp_total, int G, int nthr,
                         const FftDesc &fd, const void *tw, int inverse, hipStream_t s) {
-  return prec == PREC_FP32 ? launch_fft_y_t<float>(spec, nx2, ny, rp_total, G, fd, tw, inverse, s)
-                           : launch_fft_y_t<double>(spec, nx2, ny, rp_total, G, fd, tw, inverse, s);
+  return prec == PREC_FP32
+             ? launch_fft_y_t<float>(spec, nx2, ny, rp_total, G, nthr, fd, tw, inverse, s)
+             : launch_fft_y_t<double>(spec, nx2, ny, rp_total, G, nthr, fd, tw, inverse, s);
 }
 }  // namespace giem

@@ -130,3 +130,41 @@ def test_apply_full_size_sampled(lib, full_case, mode, prec, tol):
     err = rel_err(got, ref)
     print(f"  sampled rel err {err:.3e}", flush=True)
     assert err <= tol, err
+
+
+@pytest.mark.parametrize("nx,ny,nz,nrhs", [(15, 7, 3, 2), (16, 16, 4, 2), (48, 40, 2, 1)])
+def test_every_fft_shape_matches_dense(lib, nx, ny, nz, nrhs):
+    # every (sequences, threads) launch shape of the four FFT passes gives the
+    # dense product; giem_tune then keeps one of them per pass
+    import torch
+    m, t, rng = _case(nx, ny, nz, 300 + nx + ny + nz)
+    h = lib.tables_import(m, [m["freq"]], t[None], flags=lib.TABLES_C64)
+    B = dense.dense_from_packed(t, m)
+    d = dense.cie_diagonals(m)
+    x = gs.random_vector(rng, nrhs, nz, ny, nx)
+    ref = dense.apply_direct(B, d, x, "A")
+    xd, sa = to_dev(x), to_dev(m["sigma_a"])
+    yd = torch.empty_like(xd)
+    tried = 0
+    for prec, tol in ((lib.FP64, 1e-10), (lib.FP32, 2e-5)):
+        for nt in (256, 512):
+            for g in (1, 2, 4, 8, 16, 32, 64):
+                try:
+                    h.set_fft_shape(prec, [(g, nt)] * 4)
+                except lib.GiemError:
+                    continue
+                h.apply(xd, yd, sa, mode=lib.MODE_A, prec=prec)
+                torch.cuda.synchronize()
+                err = rel_err(yd.cpu().numpy(), ref)
+                assert err <= tol, (prec, g, nt, err)
+                tried += 1
+        h.set_fft_shape(prec, None)
+    with pytest.raises(lib.GiemError):
+        h.set_fft_shape(lib.FP64, [(8, 384)] * 4)
+    chosen = h.tune(sa, nrhs=nrhs)
+    h.apply(xd, yd, sa, mode=lib.MODE_A)
+    torch.cuda.synchronize()
+    assert rel_err(yd.cpu().numpy(), ref) <= 1e-10
+    assert all(nt in (256, 512) and g >= 1 for g, nt in chosen["fp64"] + chosen["fp32"])
+    print(f"{nx}x{ny}x{nz}: {tried} shapes; tuned {chosen}", flush=True)
+    h.close()
