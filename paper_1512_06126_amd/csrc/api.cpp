@@ -121,8 +121,9 @@ static void fft_shape(const giem_handle *t, unsigned prec, int G[4], int NT[4]) 
   }
 }
 
-int apply_core(giem_handle *t, int ifreq, int nrhs, const VecPtrs &p, unsigned mode,
-               unsigned prec, hipStream_t s, double *stage_ms) {
+template <typename VT>
+static int apply_core_t(giem_handle *t, int ifreq, int nrhs, const VecPtrsT<VT> &p, unsigned mode,
+                        unsigned prec, hipStream_t s, double *stage_ms) {
   const int nx = t->nx, ny = t->ny, nz = t->nz;
   FreqTables &ft = t->f[ifreq];
   const void *tab = prec == PREC_FP32 ? ft.spec32 : ft.spec64;
@@ -202,6 +203,20 @@ int apply_core(giem_handle *t, int ifreq, int nrhs, const VecPtrs &p, unsigned m
     for (int i = 0; i < 6; ++i) hipEventDestroy(own[i]);
   }
   return GIEM_OK;
+}
+
+int apply_core(giem_handle *t, int ifreq, int nrhs, const VecPtrs &p, unsigned mode,
+               unsigned prec, hipStream_t s, double *stage_ms) {
+  return apply_core_t(t, ifreq, nrhs, p, mode, prec, s, stage_ms);
+}
+
+int apply_core(giem_handle *t, int ifreq, int nrhs, const VecPtrs32 &p, unsigned mode,
+               unsigned prec, hipStream_t s, double *stage_ms) {
+  if (prec != PREC_FP32) {
+    set_error("complex64 vectors need the FP32 operator");
+    return GIEM_EINVAL;
+  }
+  return apply_core_t(t, ifreq, nrhs, p, mode, prec, s, stage_ms);
 }
 
 // Spatial packed tables (host) -> device -> packed spectra (+ c64 copy).

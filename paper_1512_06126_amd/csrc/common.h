@@ -70,12 +70,16 @@ struct FftDesc {
 };
 
 // Per-RHS vector pointers of one apply (the basis vectors of GMRES are not
-// contiguous across right-hand sides).
+// contiguous across right-hand sides); complex128 vectors, or complex64 ones
+// for the inner solve of the precision form.
 constexpr int kMaxRhs = 8;
-struct VecPtrs {
-  const c128 *in[kMaxRhs];
-  c128 *out[kMaxRhs];
+template <typename VT>
+struct VecPtrsT {
+  const VT *in[kMaxRhs];
+  VT *out[kMaxRhs];
 };
+using VecPtrs = VecPtrsT<c128>;
+using VecPtrs32 = VecPtrsT<c64>;
 
 // Operator modes and precisions (mirror include/giem.h)
 enum { MODE_A = 0, MODE_AT = 1, MODE_B = 2 };

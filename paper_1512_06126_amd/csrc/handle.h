@@ -89,6 +89,9 @@ int compute_diagonals(giem_handle *t, const c128 *sigma_a, hipStream_t s);
 // y = op x on per-RHS pointers; diagonals must be current (compute_diagonals)
 int apply_core(giem_handle *t, int ifreq, int nrhs, const VecPtrs &p, unsigned mode,
                unsigned prec, hipStream_t s, double *stage_ms);
+// the same on complex64 vectors (FP32 operator only)
+int apply_core(giem_handle *t, int ifreq, int nrhs, const VecPtrs32 &p, unsigned mode,
+               unsigned prec, hipStream_t s, double *stage_ms);
 int upload_spatial(giem_handle *t, hipStream_t s);
 int plane_wave_levels(const giem_handle *t, double freq, std::vector<cd> &en_lev,
                       std::vector<cd> &hsurf);

@@ -26,6 +26,14 @@ hipError_t launch_fft_x_inv(int prec, const VecPtrs &ptrs, const c128 *sd, const
                             hipStream_t s);
 hipError_t launch_fft_y(int prec, void *spec, int nx2, int ny, int rp_total, int G, int nthr,
                         const FftDesc &fd, const void *tw, int inverse, hipStream_t s);
+// complex64 vectors (FP32 transforms only)
+hipError_t launch_fft_x_fwd(int prec, const VecPtrs32 &ptrs, const c128 *r2, void *spec, int nx,
+                            int ny, int nz, int rp_total, int G, int nthr, const FftDesc &fd,
+                            const void *tw, hipStream_t s);
+hipError_t launch_fft_x_inv(int prec, const VecPtrs32 &ptrs, const c128 *sd, const c128 *r1,
+                            const void *spec, int nx, int ny, int nz, int rp_total, int G,
+                            int nthr, const FftDesc &fd, const void *tw, double scale,
+                            hipStream_t s);
 // out-of-place: sin and sout are two spectra buffers; plan from block_plan(nz)
 hipError_t launch_block(int prec, const void *tab, const void *sin, void *sout,
                         const unsigned *plan, int nx, int ny, int nz, int R, hipStream_t s);
@@ -61,31 +69,54 @@ hipError_t launch_fields_adjoint(const c128 *K, const c128 *E, const c128 *sa, c
                                  hipStream_t s);
 
 // Krylov vector kernels (kernels_vec.hip); vectors of n = 3 Nz Ny Nx complex.
-struct DotArgs {
-  const c128 *w[kMaxRhs];      // vector to project
-  const c128 *basis[kMaxRhs];  // basis base pointer, vectors at stride n
+// Krylov vectors are complex128, or complex64 in the inner solve of the
+// precision form (suffix 32); arithmetic and accumulation are FP64 for both.
+template <typename VT>
+struct DotArgsT {
+  const VT *w[kMaxRhs];      // vector to project
+  const VT *basis[kMaxRhs];  // basis base pointer, vectors at stride n
 };
+using DotArgs = DotArgsT<c128>;
+using DotArgs32 = DotArgsT<c64>;
 int dot_partials_per_rhs();
 // partial sums of conj-weighted dots <w, V_i> (i < nb) and ||w||^2 into
 // part[r][block][nb + 1]; then reduced into out[r][nb + 1].
 hipError_t launch_dots(const DotArgs &a, int nrhs, int nb, size_t n, int nz, int plane,
                        const double *wlev, c128 *part, c128 *out, hipStream_t s);
+hipError_t launch_dots(const DotArgs32 &a, int nrhs, int nb, size_t n, int nz, int plane,
+                       const double *wlev, c128 *part, c128 *out, hipStream_t s);
 // w -= sum_i h[r][i] V_i, and ||w||^2 reduced into nrm[r] (real in .x)
 hipError_t launch_update(const DotArgs &a, int nrhs, int nb, size_t n, int nz, int plane,
                          const double *wlev, const c128 *h, int hstride, c128 *part,
                          c128 *nrm, hipStream_t s);
-// dst[r] = src[r] * scal[r] (complex scalars on device)
+hipError_t launch_update(const DotArgs32 &a, int nrhs, int nb, size_t n, int nz, int plane,
+                         const double *wlev, const c128 *h, int hstride, c128 *part,
+                         c128 *nrm, hipStream_t s);
+// dst[r] = src[r] * scal[r] (complex scalars from the host)
 hipError_t launch_scale(c128 *const *dst, const c128 *const *src, const c128 *scal, int nrhs,
                         size_t n, hipStream_t s);
-struct LinArgs {
-  c128 *x[kMaxRhs];
-  const c128 *basis[kMaxRhs];
+hipError_t launch_scale(c64 *const *dst, const c64 *const *src, const c128 *scal, int nrhs,
+                        size_t n, hipStream_t s);
+hipError_t launch_scale(c64 *const *dst, const c128 *const *src, const c128 *scal, int nrhs,
+                        size_t n, hipStream_t s);
+template <typename VT>
+struct LinArgsT {
+  VT *x[kMaxRhs];
+  const VT *basis[kMaxRhs];
 };
+using LinArgs = LinArgsT<c128>;
+using LinArgs32 = LinArgsT<c64>;
 // x[r] += sum_i y[r][i] V_i
 hipError_t launch_lincomb(const LinArgs &a, int nrhs, int nb, size_t n, const c128 *y,
                           int ystride, hipStream_t s);
+hipError_t launch_lincomb(const LinArgs32 &a, int nrhs, int nb, size_t n, const c128 *y,
+                          int ystride, hipStream_t s);
 // out = alpha * a + beta * b  (element-wise, complex scalars from host)
 hipError_t launch_axpby(c128 *out, const c128 *a, const c128 *b, c128 alpha, c128 beta,
+                        size_t n, hipStream_t s);
+hipError_t launch_axpby(c64 *out, const c64 *a, const c64 *b, c128 alpha, c128 beta, size_t n,
+                        hipStream_t s);
+hipError_t launch_axpby(c128 *out, const c128 *a, const c64 *b, c128 alpha, c128 beta,
                         size_t n, hipStream_t s);
 // out[r] = u[r] / a_cell (E = U / a)
 hipError_t launch_div_cells(c128 *out, const c128 *u, const c128 *acell, int nrhs, size_t ncell,
@@ -94,6 +125,8 @@ hipError_t launch_mul_cells(c128 *out, const c128 *u, const c128 *acell, int nrh
                             hipStream_t s);
 // weighted squared norms of nrhs contiguous vectors into nrm[r].x
 hipError_t launch_norms(const c128 *v, int nrhs, size_t n, int nz, int plane, const double *wlev,
+                        c128 *part, c128 *nrm, hipStream_t s);
+hipError_t launch_norms(const c64 *v, int nrhs, size_t n, int nz, int plane, const double *wlev,
                         c128 *part, c128 *nrm, hipStream_t s);
 
 }  // namespace giem

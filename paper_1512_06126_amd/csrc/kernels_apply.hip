@@ -19,6 +19,17 @@
 
 namespace giem {
 
+template <typename VT>
+struct VTraits;
+template <>
+struct VTraits<c128> {
+  using elem = double;
+};
+template <>
+struct VTraits<c64> {
+  using elem = float;
+};
+
 // ------------------------------------------------------------------ small DFTs
 // The LDS copy of a sequence is padded by one element after every 16, so
 // that the strided Stockham writes of radix 16, 8, 4 and 2 spread over all
@@ -219,9 +230,9 @@ __device__ void fft_lds(cplx<T> *buf, int G, int ld, const FftDesc &fd,
 // ---------------------------------------------------------------- x passes
 // Step 1, x pass: u -> R2 u (or u), zero-pad to 2 Nx, forward FFT along x.
 // Grid: (y, plane group).  Output rows y < Ny of the spectra buffer.
-template <typename T, int EPT, int NT, bool POW2>
+template <typename T, int EPT, int NT, bool POW2, typename VT>
 __global__ void __launch_bounds__(NT)
-k_fft_x_fwd(VecPtrs ptrs, const c128 *__restrict__ r2, cplx<T> *__restrict__ spec, int nx,
+k_fft_x_fwd(VecPtrsT<VT> ptrs, const c128 *__restrict__ r2, cplx<T> *__restrict__ spec, int nx,
             int ny, int nz, int rp_total, int G, FftDesc fd, const cplx<T> *__restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T> *buf = reinterpret_cast<cplx<T> *>(smem_raw);
@@ -242,7 +253,7 @@ k_fft_x_fwd(VecPtrs ptrs, const c128 *__restrict__ r2, cplx<T> *__restrict__ spe
     if (e < G * L && xx < nx && rp < rp_total) {
       const int r = rp / p3, p = rp - r * p3;
       const int iz = p % nz;
-      va[u] = ptrs.in[r][(size_t)p * plane + (size_t)y * nx + xx];
+      va[u] = ccast<double>(ptrs.in[r][(size_t)p * plane + (size_t)y * nx + xx]);
       if (r2) vs[u] = r2[(size_t)iz * plane + (size_t)y * nx + xx];
     }
   }
@@ -265,9 +276,9 @@ k_fft_x_fwd(VecPtrs ptrs, const c128 *__restrict__ r2, cplx<T> *__restrict__ spe
 // Step 3, x pass: inverse FFT along x, keep x < Nx, scale by 1/(4 Nx Ny) and
 // finish the operator: y = S u + R1 (B R2 u)  (mode A, with R1/R2 swapped for
 // A^T), or y = B u (mode B: s == nullptr, r1 == nullptr).
-template <typename T, int EPT, int NT, bool POW2>
+template <typename T, int EPT, int NT, bool POW2, typename VT>
 __global__ void __launch_bounds__(NT)
-k_fft_x_inv(VecPtrs ptrs, const c128 *__restrict__ sdiag, const c128 *__restrict__ r1,
+k_fft_x_inv(VecPtrsT<VT> ptrs, const c128 *__restrict__ sdiag, const c128 *__restrict__ r1,
             const cplx<T> *__restrict__ spec, int nx, int ny, int nz, int rp_total, int G,
             FftDesc fd, const cplx<T> *__restrict__ tw, double scale) {
   extern __shared__ unsigned char smem_raw[];
@@ -315,9 +326,9 @@ k_fft_x_inv(VecPtrs ptrs, const c128 *__restrict__ sdiag, const c128 *__restrict
         const int iz = p % nz;
         const size_t cell = (size_t)iz * plane + (size_t)y * nx + xx;
         out = cmul(r1[cell], b);
-        cfma(out, sdiag[cell], ptrs.in[r][off]);
+        cfma(out, sdiag[cell], ccast<double>(ptrs.in[r][off]));
       }
-      ptrs.out[r][off] = out;
+      ptrs.out[r][off] = ccast<typename VTraits<VT>::elem>(out);
     }
   }
 }
@@ -378,9 +389,9 @@ int fft_ept(int G, int L, int nthr, int prec) {
 
 #define GIEM_FFT_CASES(KERNEL, NTV, P2, ...)                                                 \
   switch (ept) {                                                                              \
-    case 4: KERNEL<T, 4, NTV, P2><<<grid, NTV, lds, s>>>(__VA_ARGS__); break;                 \
-    case 8: KERNEL<T, 8, NTV, P2><<<grid, NTV, lds, s>>>(__VA_ARGS__); break;                 \
-    case 16: KERNEL<T, 16, NTV, P2><<<grid, NTV, lds, s>>>(__VA_ARGS__); break;               \
+    case 4: KERNEL<T, 4, NTV, P2 KX><<<grid, NTV, lds, s>>>(__VA_ARGS__); break;              \
+    case 8: KERNEL<T, 8, NTV, P2 KX><<<grid, NTV, lds, s>>>(__VA_ARGS__); break;              \
+    case 16: KERNEL<T, 16, NTV, P2 KX><<<grid, NTV, lds, s>>>(__VA_ARGS__); break;            \
     default: return hipErrorInvalidConfiguration;                                             \
   }
 #define GIEM_FFT_DISPATCH(KERNEL, ...)                                                        \
@@ -400,8 +411,9 @@ int fft_ept(int G, int L, int nthr, int prec) {
     }                                                                                         \
   } while (0)
 
-template <typename T>
-static hipError_t launch_fft_x_fwd_t(const VecPtrs &ptrs, const c128 *r2, void *spec, int nx,
+#define KX , VT
+template <typename T, typename VT>
+static hipError_t launch_fft_x_fwd_t(const VecPtrsT<VT> &ptrs, const c128 *r2, void *spec, int nx,
                                      int ny, int nz, int rp_total, int G, int nthr,
                                      const FftDesc &fd, const void *tw, hipStream_t s) {
   dim3 grid(ny, (rp_total + G - 1) / G);
@@ -412,8 +424,8 @@ static hipError_t launch_fft_x_fwd_t(const VecPtrs &ptrs, const c128 *r2, void *
   return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t launch_fft_x_inv_t(const VecPtrs &ptrs, const c128 *sd, const c128 *r1,
+template <typename T, typename VT>
+static hipError_t launch_fft_x_inv_t(const VecPtrsT<VT> &ptrs, const c128 *sd, const c128 *r1,
                                      const void *spec, int nx, int ny, int nz, int rp_total,
                                      int G, int nthr, const FftDesc &fd, const void *tw,
                                      double scale, hipStream_t s) {
@@ -424,6 +436,8 @@ static hipError_t launch_fft_x_inv_t(const VecPtrs &ptrs, const c128 *sd, const 
   GIEM_FFT_DISPATCH(k_fft_x_inv, ptrs, sd, r1, sp, nx, ny, nz, rp_total, G, fd, twp, scale);
   return hipGetLastError();
 }
+#undef KX
+#define KX
 
 template <typename T>
 static hipError_t launch_fft_y_t(void *spec, int nx2, int ny, int rp_total, int G, int nthr,
@@ -435,6 +449,7 @@ static hipError_t launch_fft_y_t(void *spec, int nx2, int ny, int rp_total, int 
   GIEM_FFT_DISPATCH(k_fft_y, sp, nx2, ny, rp_total, G, fd, twp, inverse);
   return hipGetLastError();
 }
+#undef KX
 #undef GIEM_FFT_DISPATCH
 #undef GIEM_FFT_CASES
 
@@ -443,24 +458,48 @@ size_t fft_lds_bytes(int G, int L, int prec) {
   return (size_t)G * fft_ld(L) * c;
 }
 
+// gfx950 has 160 KB of LDS per CU; allow the large dynamic allocations.
+static hipError_t allow_lds(const void *k) {
+  return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+template <typename T, bool P2, typename VT>
+static hipError_t allow_lds_x() {
+  const void *ks[] = {(const void *)k_fft_x_fwd<T, 4, 256, P2, VT>, (const void *)k_fft_x_fwd<T, 8, 256, P2, VT>,
+                      (const void *)k_fft_x_fwd<T, 16, 256, P2, VT>, (const void *)k_fft_x_fwd<T, 4, 512, P2, VT>,
+                      (const void *)k_fft_x_fwd<T, 8, 512, P2, VT>, (const void *)k_fft_x_fwd<T, 16, 512, P2, VT>,
+                      (const void *)k_fft_x_inv<T, 4, 256, P2, VT>, (const void *)k_fft_x_inv<T, 8, 256, P2, VT>,
+                      (const void *)k_fft_x_inv<T, 16, 256, P2, VT>, (const void *)k_fft_x_inv<T, 4, 512, P2, VT>,
+                      (const void *)k_fft_x_inv<T, 8, 512, P2, VT>, (const void *)k_fft_x_inv<T, 16, 512, P2, VT>};
+  for (const void *k : ks) {
+    const hipError_t e = allow_lds(k);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+template <typename T, bool P2>
+static hipError_t allow_lds_y() {
+  const void *ks[] = {(const void *)k_fft_y<T, 4, 256, P2>, (const void *)k_fft_y<T, 8, 256, P2>,
+                      (const void *)k_fft_y<T, 16, 256, P2>, (const void *)k_fft_y<T, 4, 512, P2>,
+                      (const void *)k_fft_y<T, 8, 512, P2>, (const void *)k_fft_y<T, 16, 512, P2>};
+  for (const void *k : ks) {
+    const hipError_t e = allow_lds(k);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t set_lds_limits() {
-  // gfx950 has 160 KB of LDS per CU; allow the large dynamic allocations.
-  const int lim = 160 * 1024;
   hipError_t e = hipSuccess;
-#define GIEM_SET(k) \
-  if (e == hipSuccess) e = hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize, lim)
-#define GIEM_SET_NT(K, T, P2)                                                               \
-  GIEM_SET((K<T, 4, 256, P2>)); GIEM_SET((K<T, 8, 256, P2>)); GIEM_SET((K<T, 16, 256, P2>));  \
-  GIEM_SET((K<T, 4, 512, P2>)); GIEM_SET((K<T, 8, 512, P2>)); GIEM_SET((K<T, 16, 512, P2>))
-#define GIEM_SET_ALL(K)                                                                     \
-  GIEM_SET_NT(K, double, true); GIEM_SET_NT(K, double, false);                              \
-  GIEM_SET_NT(K, float, true); GIEM_SET_NT(K, float, false)
-  GIEM_SET_ALL(k_fft_x_fwd);
-  GIEM_SET_ALL(k_fft_x_inv);
-  GIEM_SET_ALL(k_fft_y);
-#undef GIEM_SET_ALL
-#undef GIEM_SET_NT
-#undef GIEM_SET
+  if (e == hipSuccess) e = allow_lds_x<double, true, c128>();
+  if (e == hipSuccess) e = allow_lds_x<double, false, c128>();
+  if (e == hipSuccess) e = allow_lds_x<float, true, c128>();
+  if (e == hipSuccess) e = allow_lds_x<float, false, c128>();
+  if (e == hipSuccess) e = allow_lds_x<float, true, c64>();
+  if (e == hipSuccess) e = allow_lds_x<float, false, c64>();
+  if (e == hipSuccess) e = allow_lds_y<double, true>();
+  if (e == hipSuccess) e = allow_lds_y<double, false>();
+  if (e == hipSuccess) e = allow_lds_y<float, true>();
+  if (e == hipSuccess) e = allow_lds_y<float, false>();
   if (e == hipSuccess) e = set_block_lds_limits();
   return e;
 }
@@ -479,6 +518,19 @@ hipError_t launch_fft_x_inv(int prec, const VecPtrs &ptrs, const c128 *sd, const
   return prec == PREC_FP32
              ? launch_fft_x_inv_t<float>(ptrs, sd, r1, spec, nx, ny, nz, rp_total, G, nthr, fd, tw, scale, s)
              : launch_fft_x_inv_t<double>(ptrs, sd, r1, spec, nx, ny, nz, rp_total, G, nthr, fd, tw, scale, s);
+}
+hipError_t launch_fft_x_fwd(int prec, const VecPtrs32 &ptrs, const c128 *r2, void *spec, int nx,
+                            int ny, int nz, int rp_total, int G, int nthr, const FftDesc &fd,
+                            const void *tw, hipStream_t s) {
+  if (prec != PREC_FP32) return hipErrorInvalidValue;
+  return launch_fft_x_fwd_t<float>(ptrs, r2, spec, nx, ny, nz, rp_total, G, nthr, fd, tw, s);
+}
+hipError_t launch_fft_x_inv(int prec, const VecPtrs32 &ptrs, const c128 *sd, const c128 *r1,
+                            const void *spec, int nx, int ny, int nz, int rp_total, int G,
+                            int nthr, const FftDesc &fd, const void *tw, double scale,
+                            hipStream_t s) {
+  if (prec != PREC_FP32) return hipErrorInvalidValue;
+  return launch_fft_x_inv_t<float>(ptrs, sd, r1, spec, nx, ny, nz, rp_total, G, nthr, fd, tw, scale, s);
 }
 hipError_t launch_fft_y(int prec, void *spec, int nx2, int ny, int rp_total, int G, int nthr,
                         const FftDesc &fd, const void *tw, int inverse, hipStream_t s) {

@@ -1,9 +1,10 @@
 // Krylov vector kernels of GMRES (Sect. 3.3, flexible GMRES; Sect. 2.1, the
 // L2 inner product (V, U) = int V . conj(U)).  On the cell grid the inner
 // product is sum_n wt_n V_n conj(U_n) with wt_n = V_n (cell volume) when the
-// weighted form is requested, else 1.  All accumulation is FP64; reductions
-// are wavefront shuffles, LDS across the workgroup, then a second pass over
-// the per-workgroup partials.
+// weighted form is requested, else 1.  Vectors are stored as complex128, or
+// as complex64 for the inner solve of the precision form; all arithmetic and
+// accumulation is FP64.  Reductions are wavefront shuffles, LDS across the
+// workgroup, then a second pass over the per-workgroup partials.
 #include "kernels.h"
 
 namespace giem {
@@ -33,31 +34,41 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
   return s;
 }
 
+template <typename VT>
+__device__ __forceinline__ c128 wide(VT v) {
+  return ccast<double>(v);
+}
+template <typename VT>
+__device__ __forceinline__ VT store_as(c128 v) {
+  return ccast<decltype(VT::x)>(v);
+}
+
 __device__ __forceinline__ double weight_of(size_t k, int plane, int nz, const double *wlev) {
   return wlev ? wlev[(int)((k / plane) % nz)] : 1.0;
 }
 
 // part[r][slot][block]: slot s < nb: sum wt w conj(V_s); slot nb: sum wt |w|^2
+template <typename VT>
 __global__ void __launch_bounds__(256)
-k_dots(DotArgs a, int nb, size_t n, int nz, int plane, const double *__restrict__ wlev,
+k_dots(DotArgsT<VT> a, int nb, size_t n, int nz, int plane, const double *__restrict__ wlev,
        c128 *__restrict__ part) {
   __shared__ double red[8];
   const int r = blockIdx.y;
   const int s0 = blockIdx.z * kSlots;
-  const c128 *w = a.w[r];
-  const c128 *V = a.basis[r];
+  const VT *w = a.w[r];
+  const VT *V = a.basis[r];
   double accr[kSlots], acci[kSlots];
 #pragma unroll
   for (int k = 0; k < kSlots; ++k) accr[k] = acci[k] = 0.0;
   for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n;
        k += (size_t)gridDim.x * blockDim.x) {
-    const c128 wv = w[k];
+    const c128 wv = wide(w[k]);
     const double wt = weight_of(k, plane, nz, wlev);
 #pragma unroll
     for (int q = 0; q < kSlots; ++q) {
       const int s = s0 + q;
       if (s < nb) {
-        const c128 v = V[(size_t)s * n + k];
+        const c128 v = wide(V[(size_t)s * n + k]);
         accr[q] += wt * (wv.x * v.x + wv.y * v.y);
         acci[q] += wt * (wv.y * v.x - wv.x * v.y);
       } else if (s == nb) {
@@ -92,142 +103,209 @@ k_reduce(const c128 *__restrict__ part, int nblk, int nslots, c128 *__restrict__
   if (threadIdx.x == 0) out[(size_t)r * nslots + s] = mk<double>(ar, ai);
 }
 
-hipError_t launch_dots(const DotArgs &a, int nrhs, int nb, size_t n, int nz, int plane,
-                       const double *wlev, c128 *part, c128 *out, hipStream_t s) {
+template <typename VT>
+static hipError_t launch_dots_t(const DotArgsT<VT> &a, int nrhs, int nb, size_t n, int nz,
+                                int plane, const double *wlev, c128 *part, c128 *out,
+                                hipStream_t s) {
   const int nslots = nb + 1;
   dim3 grid(kRedBlocks, nrhs, (nslots + kSlots - 1) / kSlots);
-  k_dots<<<grid, 256, 0, s>>>(a, nb, n, nz, plane, wlev, part);
+  k_dots<VT><<<grid, 256, 0, s>>>(a, nb, n, nz, plane, wlev, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_reduce<<<dim3(nslots, nrhs), 256, 0, s>>>(part, kRedBlocks, nslots, out);
   return hipGetLastError();
 }
+hipError_t launch_dots(const DotArgs &a, int nrhs, int nb, size_t n, int nz, int plane,
+                       const double *wlev, c128 *part, c128 *out, hipStream_t s) {
+  return launch_dots_t(a, nrhs, nb, n, nz, plane, wlev, part, out, s);
+}
+hipError_t launch_dots(const DotArgs32 &a, int nrhs, int nb, size_t n, int nz, int plane,
+                       const double *wlev, c128 *part, c128 *out, hipStream_t s) {
+  return launch_dots_t(a, nrhs, nb, n, nz, plane, wlev, part, out, s);
+}
 
 // w -= sum_{i < nb} h[r][i] V_i ; partial ||w||^2 into part[r][0][block]
+template <typename VT>
 __global__ void __launch_bounds__(256)
-k_update(DotArgs a, int nb, size_t n, int nz, int plane, const double *__restrict__ wlev,
+k_update(DotArgsT<VT> a, int nb, size_t n, int nz, int plane, const double *__restrict__ wlev,
          const c128 *__restrict__ h, int hstride, c128 *__restrict__ part) {
   __shared__ double red[8];
   __shared__ c128 hs[64];
   const int r = blockIdx.y;
-  c128 *w = const_cast<c128 *>(a.w[r]);
-  const c128 *V = a.basis[r];
+  VT *w = const_cast<VT *>(a.w[r]);
+  const VT *V = a.basis[r];
   for (int i = threadIdx.x; i < nb; i += blockDim.x) hs[i] = h[(size_t)r * hstride + i];
   __syncthreads();
   double acc = 0.0;
   for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n;
        k += (size_t)gridDim.x * blockDim.x) {
-    c128 wv = w[k];
+    c128 wv = wide(w[k]);
     for (int i = 0; i < nb; ++i) {
-      const c128 v = V[(size_t)i * n + k];
+      const c128 v = wide(V[(size_t)i * n + k]);
       const c128 hv = hs[i];
       wv.x -= hv.x * v.x - hv.y * v.y;
       wv.y -= hv.x * v.y + hv.y * v.x;
     }
-    w[k] = wv;
+    w[k] = store_as<VT>(wv);
     acc += weight_of(k, plane, nz, wlev) * (wv.x * wv.x + wv.y * wv.y);
   }
   const double sum = block_sum(acc, red);
   if (threadIdx.x == 0) part[(size_t)r * gridDim.x + blockIdx.x] = mk<double>(sum, 0.0);
 }
 
-hipError_t launch_update(const DotArgs &a, int nrhs, int nb, size_t n, int nz, int plane,
-                         const double *wlev, const c128 *h, int hstride, c128 *part, c128 *nrm,
-                         hipStream_t s) {
+template <typename VT>
+static hipError_t launch_update_t(const DotArgsT<VT> &a, int nrhs, int nb, size_t n, int nz,
+                                  int plane, const double *wlev, const c128 *h, int hstride,
+                                  c128 *part, c128 *nrm, hipStream_t s) {
   if (nb > 64) return hipErrorInvalidValue;
   dim3 grid(kRedBlocks, nrhs);
-  k_update<<<grid, 256, 0, s>>>(a, nb, n, nz, plane, wlev, h, hstride, part);
+  k_update<VT><<<grid, 256, 0, s>>>(a, nb, n, nz, plane, wlev, h, hstride, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_reduce<<<dim3(1, nrhs), 256, 0, s>>>(part, kRedBlocks, 1, nrm);
   return hipGetLastError();
 }
+hipError_t launch_update(const DotArgs &a, int nrhs, int nb, size_t n, int nz, int plane,
+                         const double *wlev, const c128 *h, int hstride, c128 *part, c128 *nrm,
+                         hipStream_t s) {
+  return launch_update_t(a, nrhs, nb, n, nz, plane, wlev, h, hstride, part, nrm, s);
+}
+hipError_t launch_update(const DotArgs32 &a, int nrhs, int nb, size_t n, int nz, int plane,
+                         const double *wlev, const c128 *h, int hstride, c128 *part, c128 *nrm,
+                         hipStream_t s) {
+  return launch_update_t(a, nrhs, nb, n, nz, plane, wlev, h, hstride, part, nrm, s);
+}
 
+template <typename VT>
 __global__ void __launch_bounds__(256)
-k_norms(const c128 *__restrict__ v, size_t n, int nz, int plane, const double *__restrict__ wlev,
+k_norms(const VT *__restrict__ v, size_t n, int nz, int plane, const double *__restrict__ wlev,
         c128 *__restrict__ part) {
   __shared__ double red[8];
   const int r = blockIdx.y;
-  const c128 *x = v + (size_t)r * n;
+  const VT *x = v + (size_t)r * n;
   double acc = 0.0;
   for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n;
        k += (size_t)gridDim.x * blockDim.x) {
-    const c128 a = x[k];
+    const c128 a = wide(x[k]);
     acc += weight_of(k, plane, nz, wlev) * (a.x * a.x + a.y * a.y);
   }
   const double sum = block_sum(acc, red);
   if (threadIdx.x == 0) part[(size_t)r * gridDim.x + blockIdx.x] = mk<double>(sum, 0.0);
 }
 
-hipError_t launch_norms(const c128 *v, int nrhs, size_t n, int nz, int plane, const double *wlev,
-                        c128 *part, c128 *nrm, hipStream_t s) {
+template <typename VT>
+static hipError_t launch_norms_t(const VT *v, int nrhs, size_t n, int nz, int plane,
+                                 const double *wlev, c128 *part, c128 *nrm, hipStream_t s) {
   dim3 grid(kRedBlocks, nrhs);
-  k_norms<<<grid, 256, 0, s>>>(v, n, nz, plane, wlev, part);
+  k_norms<VT><<<grid, 256, 0, s>>>(v, n, nz, plane, wlev, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_reduce<<<dim3(1, nrhs), 256, 0, s>>>(part, kRedBlocks, 1, nrm);
   return hipGetLastError();
 }
+hipError_t launch_norms(const c128 *v, int nrhs, size_t n, int nz, int plane, const double *wlev,
+                        c128 *part, c128 *nrm, hipStream_t s) {
+  return launch_norms_t(v, nrhs, n, nz, plane, wlev, part, nrm, s);
+}
+hipError_t launch_norms(const c64 *v, int nrhs, size_t n, int nz, int plane, const double *wlev,
+                        c128 *part, c128 *nrm, hipStream_t s) {
+  return launch_norms_t(v, nrhs, n, nz, plane, wlev, part, nrm, s);
+}
 
+template <typename VD, typename VS>
 struct ScaleArgs {
-  c128 *dst[kMaxRhs];
-  const c128 *src[kMaxRhs];
+  VD *dst[kMaxRhs];
+  const VS *src[kMaxRhs];
   c128 f[kMaxRhs];
 };
 
-__global__ void k_scale(ScaleArgs a, size_t n) {
+template <typename VD, typename VS>
+__global__ void k_scale(ScaleArgs<VD, VS> a, size_t n) {
   const int r = blockIdx.y;
   const c128 f = a.f[r];
   for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n;
        k += (size_t)gridDim.x * blockDim.x)
-    a.dst[r][k] = cmul(a.src[r][k], f);
+    a.dst[r][k] = store_as<VD>(cmul(wide(a.src[r][k]), f));
 }
 
-hipError_t launch_scale(c128 *const *dst, const c128 *const *src, const c128 *scal, int nrhs,
-                        size_t n, hipStream_t s) {
-  ScaleArgs a;
+template <typename VD, typename VS>
+static hipError_t launch_scale_t(VD *const *dst, const VS *const *src, const c128 *scal, int nrhs,
+                                 size_t n, hipStream_t s) {
+  ScaleArgs<VD, VS> a;
   for (int r = 0; r < nrhs; ++r) {
     a.dst[r] = dst[r];
     a.src[r] = src[r];
     a.f[r] = scal[r];
   }
-  k_scale<<<dim3(1024, nrhs), 256, 0, s>>>(a, n);
+  k_scale<VD, VS><<<dim3(1024, nrhs), 256, 0, s>>>(a, n);
   return hipGetLastError();
 }
+hipError_t launch_scale(c128 *const *dst, const c128 *const *src, const c128 *scal, int nrhs,
+                        size_t n, hipStream_t s) {
+  return launch_scale_t(dst, src, scal, nrhs, n, s);
+}
+hipError_t launch_scale(c64 *const *dst, const c64 *const *src, const c128 *scal, int nrhs,
+                        size_t n, hipStream_t s) {
+  return launch_scale_t(dst, src, scal, nrhs, n, s);
+}
+hipError_t launch_scale(c64 *const *dst, const c128 *const *src, const c128 *scal, int nrhs,
+                        size_t n, hipStream_t s) {
+  return launch_scale_t(dst, src, scal, nrhs, n, s);
+}
 
-__global__ void k_lincomb(LinArgs a, int nb, size_t n, const c128 *__restrict__ y, int ystride) {
+template <typename VT>
+__global__ void k_lincomb(LinArgsT<VT> a, int nb, size_t n, const c128 *__restrict__ y,
+                          int ystride) {
   __shared__ c128 ys[64];
   const int r = blockIdx.y;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) ys[i] = y[(size_t)r * ystride + i];
   __syncthreads();
-  c128 *x = a.x[r];
-  const c128 *V = a.basis[r];
+  VT *x = a.x[r];
+  const VT *V = a.basis[r];
   for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n;
        k += (size_t)gridDim.x * blockDim.x) {
-    c128 acc = x[k];
-    for (int i = 0; i < nb; ++i) cfma(acc, ys[i], V[(size_t)i * n + k]);
-    x[k] = acc;
+    c128 acc = wide(x[k]);
+    for (int i = 0; i < nb; ++i) cfma(acc, ys[i], wide(V[(size_t)i * n + k]));
+    x[k] = store_as<VT>(acc);
   }
 }
 
 hipError_t launch_lincomb(const LinArgs &a, int nrhs, int nb, size_t n, const c128 *y,
                           int ystride, hipStream_t s) {
   if (nb > 64) return hipErrorInvalidValue;
-  k_lincomb<<<dim3(1024, nrhs), 256, 0, s>>>(a, nb, n, y, ystride);
+  k_lincomb<c128><<<dim3(1024, nrhs), 256, 0, s>>>(a, nb, n, y, ystride);
+  return hipGetLastError();
+}
+hipError_t launch_lincomb(const LinArgs32 &a, int nrhs, int nb, size_t n, const c128 *y,
+                          int ystride, hipStream_t s) {
+  if (nb > 64) return hipErrorInvalidValue;
+  k_lincomb<c64><<<dim3(1024, nrhs), 256, 0, s>>>(a, nb, n, y, ystride);
   return hipGetLastError();
 }
 
-__global__ void k_axpby(c128 *__restrict__ out, const c128 *__restrict__ a,
-                        const c128 *__restrict__ b, c128 alpha, c128 beta, size_t n) {
+// out = alpha a + beta b in FP64, stored as the type of out
+template <typename VO, typename VA, typename VB>
+__global__ void k_axpby(VO *__restrict__ out, const VA *__restrict__ a, const VB *__restrict__ b,
+                        c128 alpha, c128 beta, size_t n) {
   for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n;
        k += (size_t)gridDim.x * blockDim.x) {
-    c128 v = cmul(alpha, a[k]);
-    cfma(v, beta, b[k]);
-    out[k] = v;
+    c128 v = cmul(alpha, wide(a[k]));
+    cfma(v, beta, wide(b[k]));
+    out[k] = store_as<VO>(v);
   }
 }
 
 hipError_t launch_axpby(c128 *out, const c128 *a, const c128 *b, c128 alpha, c128 beta, size_t n,
+                        hipStream_t s) {
+  k_axpby<<<1024, 256, 0, s>>>(out, a, b, alpha, beta, n);
+  return hipGetLastError();
+}
+hipError_t launch_axpby(c64 *out, const c64 *a, const c64 *b, c128 alpha, c128 beta, size_t n,
+                        hipStream_t s) {
+  k_axpby<<<1024, 256, 0, s>>>(out, a, b, alpha, beta, n);
+  return hipGetLastError();
+}
+hipError_t launch_axpby(c128 *out, const c128 *a, const c64 *b, c128 alpha, c128 beta, size_t n,
                         hipStream_t s) {
   k_axpby<<<1024, 256, 0, s>>>(out, a, b, alpha, beta, n);
   return hipGetLastError();

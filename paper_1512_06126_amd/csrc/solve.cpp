@@ -2,8 +2,9 @@
 // preconditioner it reduces to GMRES(m)), the precision form (complex64
 // convolution inside an inner GMRES, FP64 residual refinement outside), the
 // adjoint solve, and the plane-wave normal field used for the right-hand side
-// (Sect. 2.1).  The Arnoldi vectors and all inner products are FP64 on the
-// device; the Hessenberg matrix, the Givens rotations and the small
+// (Sect. 2.1).  The Arnoldi vectors are complex128 (complex64 in the inner
+// solve of the precision form) and all inner products are accumulated in FP64
+// on the device; the Hessenberg matrix, the Givens rotations and the small
 // least-squares problem are FP64 on the host.
 #include <hip/hip_runtime.h>
 
@@ -141,7 +142,8 @@ static int ensure_vec_ws(giem_handle *t, size_t nvecs) {
 }
 
 // weighted squared norms of nv vectors (each at its own pointer)
-static int norms_of(giem_handle *t, const c128 *const *v, int nv, const double *wlev,
+template <typename VT>
+static int norms_of(giem_handle *t, const VT *const *v, int nv, const double *wlev,
                     hipStream_t s, std::vector<double> &out) {
   c128 *part = static_cast<c128 *>(t->red_part);
   c128 *res = static_cast<c128 *>(t->coef_dev);
@@ -157,12 +159,13 @@ static int norms_of(giem_handle *t, const c128 *const *v, int nv, const double *
 }
 
 // y_r = op(x_r) for a set of RHS given by pointers (batched in groups of 8)
-static int apply_ptrs(giem_handle *t, int ifreq, const std::vector<const c128 *> &in,
-                      const std::vector<c128 *> &out, unsigned mode, unsigned prec,
+template <typename VT>
+static int apply_ptrs(giem_handle *t, int ifreq, const std::vector<const VT *> &in,
+                      const std::vector<VT *> &out, unsigned mode, unsigned prec,
                       hipStream_t s) {
   for (size_t b0 = 0; b0 < in.size(); b0 += kMaxRhs) {
     const int nb = (int)std::min<size_t>(kMaxRhs, in.size() - b0);
-    VecPtrs p{};
+    VecPtrsT<VT> p{};
     for (int r = 0; r < nb; ++r) {
       p.in[r] = in[b0 + r];
       p.out[r] = out[b0 + r];
@@ -179,14 +182,17 @@ static int apply_ptrs(giem_handle *t, int ifreq, const std::vector<const c128 *>
 // second passes over the basis.
 constexpr double kReorthDrop = 0.01;
 
-static int gmres(giem_handle *t, int ifreq, int nrhs, const c128 *const *b, c128 *const *x,
+// VT: storage of the Krylov vectors, x and b (complex128; complex64 for the
+// inner solve of the precision form, which runs the FP32 operator).
+template <typename VT>
+static int gmres(giem_handle *t, int ifreq, int nrhs, const VT *const *b, VT *const *x,
                  const GmresParams &gp, hipStream_t s, GmresResult &res) {
   const int m = gp.m;
   const size_t n = t->nvec();
   const int plane = t->nx * t->ny;
   const double *wlev = gp.weighted ? static_cast<const double *>(t->vol_lev) : nullptr;
   GIEM_TRY(ensure_basis(t, nrhs, m));
-  c128 *basis = static_cast<c128 *>(t->basis);
+  VT *basis = static_cast<VT *>(t->basis);
   auto V = [&](int r, int i) { return basis + ((size_t)r * (m + 1) + i) * n; };
   std::vector<double> normb;
   GIEM_TRY(norms_of(t, b, nrhs, wlev, s, normb));
@@ -196,7 +202,7 @@ static int gmres(giem_handle *t, int ifreq, int nrhs, const c128 *const *b, c128
   std::vector<int> done(nrhs, 0);
   for (int r = 0; r < nrhs; ++r) {
     if (normb[r] == 0.0) {
-      GIEM_HIP(hipMemsetAsync(x[r], 0, n * sizeof(c128), s), "zero x");
+      GIEM_HIP(hipMemsetAsync(x[r], 0, n * sizeof(VT), s), "zero x");
       done[r] = 1;
     }
   }
@@ -216,12 +222,12 @@ static int gmres(giem_handle *t, int ifreq, int nrhs, const c128 *const *b, c128
     if (act.empty()) break;
     if (x_zero) {
       for (int r : act) {
-        GIEM_HIP(hipMemcpyAsync(V(r, 0), b[r], n * sizeof(c128), hipMemcpyDeviceToDevice, s), "copy b");
-        GIEM_HIP(hipMemsetAsync(x[r], 0, n * sizeof(c128), s), "zero x");
+        GIEM_HIP(hipMemcpyAsync(V(r, 0), b[r], n * sizeof(VT), hipMemcpyDeviceToDevice, s), "copy b");
+        GIEM_HIP(hipMemsetAsync(x[r], 0, n * sizeof(VT), s), "zero x");
       }
     } else {
-      std::vector<const c128 *> in;
-      std::vector<c128 *> out;
+      std::vector<const VT *> in;
+      std::vector<VT *> out;
       for (int r : act) {
         in.push_back(x[r]);
         out.push_back(V(r, 0));
@@ -231,7 +237,7 @@ static int gmres(giem_handle *t, int ifreq, int nrhs, const c128 *const *b, c128
         GIEM_HIP(launch_axpby(V(r, 0), b[r], V(r, 0), mk<double>(1, 0), mk<double>(-1, 0), n, s), "axpby");
     }
     x_zero = false;
-    std::vector<const c128 *> r0p;
+    std::vector<const VT *> r0p;
     for (int r : act) r0p.push_back(V(r, 0));
     std::vector<double> beta;
     GIEM_TRY(norms_of(t, r0p.data(), (int)act.size(), wlev, s, beta));
@@ -251,8 +257,8 @@ static int gmres(giem_handle *t, int ifreq, int nrhs, const c128 *const *b, c128
       g[r].assign(m + 1, 0.0);
       g[r][0] = beta[q];
       const c128 f = mk<double>(1.0 / beta[q], 0.0);
-      c128 *dst = V(r, 0);
-      const c128 *src = V(r, 0);
+      VT *dst = V(r, 0);
+      const VT *src = V(r, 0);
       GIEM_HIP(launch_scale(&dst, &src, &f, 1, n, s), "scale");
     }
     if (cyc.empty()) break;
@@ -263,8 +269,8 @@ static int gmres(giem_handle *t, int ifreq, int nrhs, const c128 *const *b, c128
       if (iters >= gp.max_iter) break;
       const int na = (int)running.size();
       // w = A v_j into V(r, j+1)
-      std::vector<const c128 *> in;
-      std::vector<c128 *> out;
+      std::vector<const VT *> in;
+      std::vector<VT *> out;
       for (int r : running) {
         in.push_back(V(r, j));
         out.push_back(V(r, j + 1));
@@ -276,7 +282,7 @@ static int gmres(giem_handle *t, int ifreq, int nrhs, const c128 *const *b, c128
       std::vector<std::vector<cd>> hcol(na, std::vector<cd>(j + 1, 0.0));
       std::vector<double> nw0(na, 0.0), nw1(na, 0.0);
       for (int pass = 0; pass < 2; ++pass) {
-        DotArgs da{};
+        DotArgsT<VT> da{};
         for (int q = 0; q < na; ++q) {
           da.w[q] = V(running[q], j + 1);
           da.basis[q] = V(running[q], 0);
@@ -332,8 +338,8 @@ static int gmres(giem_handle *t, int ifreq, int nrhs, const c128 *const *b, c128
         const double est = std::abs(g[r][j + 1]);
         if (hn > 0.0) {
           const c128 f = mk<double>(1.0 / hn, 0.0);
-          c128 *dst = V(r, j + 1);
-          const c128 *src = V(r, j + 1);
+          VT *dst = V(r, j + 1);
+          const VT *src = V(r, j + 1);
           GIEM_HIP(launch_scale(&dst, &src, &f, 1, n, s), "scale");
         }
         if (est > gp.tol * normb[r] && hn > 0.0) still.push_back(r);
@@ -353,7 +359,7 @@ static int gmres(giem_handle *t, int ifreq, int nrhs, const c128 *const *b, c128
       c128 *yh = static_cast<c128 *>(t->coef_host);
       for (int i = 0; i < k; ++i) yh[i] = mk<double>(y[i].real(), y[i].imag());
       GIEM_HIP(hipMemcpyAsync(t->coef_dev, yh, k * sizeof(c128), hipMemcpyHostToDevice, s), "copy y");
-      LinArgs la{};
+      LinArgsT<VT> la{};
       la.x[0] = x[r];
       la.basis[0] = V(r, 0);
       GIEM_HIP(launch_lincomb(la, 1, k, n, static_cast<c128 *>(t->coef_dev), k, s), "lincomb");
@@ -365,14 +371,14 @@ static int gmres(giem_handle *t, int ifreq, int nrhs, const c128 *const *b, c128
       for (int r = 0; r < nrhs; ++r)
         if (!done[r]) left.push_back(r);
       if (!left.empty()) {
-        std::vector<const c128 *> in;
-        std::vector<c128 *> out;
+        std::vector<const VT *> in;
+        std::vector<VT *> out;
         for (int r : left) {
           in.push_back(x[r]);
           out.push_back(V(r, 0));
         }
         GIEM_TRY(apply_ptrs(t, ifreq, in, out, gp.mode, gp.prec, s));
-        std::vector<const c128 *> rp;
+        std::vector<const VT *> rp;
         for (int r : left) {
           GIEM_HIP(launch_axpby(V(r, 0), b[r], V(r, 0), mk<double>(1, 0), mk<double>(-1, 0), n, s), "axpby");
           rp.push_back(V(r, 0));
@@ -522,12 +528,19 @@ static int solve_impl(giem_handle *t, int ifreq, const void *sigma_a, int nrhs, 
         break;
       }
       if (outer == max_outer || inner_total >= o->max_iter) break;
-      // inner complex64 solve of A d = r for the RHS not yet converged
-      std::vector<const c128 *> rb;
-      std::vector<c128 *> cx;
+      // inner solve of A d = r for the RHS not yet converged, entirely in
+      // complex64 (vectors, basis and operator; FP64 accumulation), in the
+      // space of the correction buffer: r32 and d32 per RHS
+      std::vector<const c64 *> rb;
+      std::vector<c64 *> cx;
       for (int r : act) {
-        rb.push_back(dp[r]);
-        cx.push_back(cv + (size_t)r * n);
+        c64 *r32 = reinterpret_cast<c64 *>(cv + (size_t)r * n);
+        c64 *dst[1] = {r32};
+        const c128 *src[1] = {dp[r]};
+        const c128 one = mk<double>(1, 0);
+        GIEM_HIP(launch_scale(dst, src, &one, 1, n, s), "r -> complex64");
+        rb.push_back(r32);
+        cx.push_back(r32 + n);
       }
       GmresParams ip = gp;
       ip.prec = PREC_FP32;
