@@ -153,9 +153,10 @@ def apply_cells(qnn, model, x, cells, mode="A", sigma_a=None):
     """Selected rows of y = A x (mode "A"), A^T x ("AT") or B x ("B"), each
     by direct summation over every source cell of eq. (bcyl), with no FFT:
       (B x)_(a, n) = sum_m sum_b Q_ab(y_n - y_m, x_n - x_m)[iz_n, iz_m] x_(b, m).
-    qnn from packed.full_tensor_nonneg; x [R][3][Nz][Ny][Nx]; cells is a list
-    of (iz, iy, ix).  Returns [R][len(cells)][3].  A^T uses B = B^T
-    (reciprocity), so A^T = S + R2 B R1."""
+    qnn from packed.full_tensor_nonneg, or a function iz -> its row
+    (packed.tensor_row) for grids where the whole tensor is too large;
+    x [R][3][Nz][Ny][Nx]; cells is a list of (iz, iy, ix).  Returns
+    [R][len(cells)][3].  A^T uses B = B^T (reciprocity), so A^T = S + R2 B R1."""
     nz, ny, nx = model["nz"], model["ny"], model["nx"]
     d = cie_diagonals(model, sigma_a) if mode != "B" else None
     xs = x
@@ -167,8 +168,8 @@ def apply_cells(qnn, model, x, cells, mode="A", sigma_a=None):
     xm = np.arange(nx)
     out = np.zeros((x.shape[0], len(cells), 3), dtype=np.complex128)
     for k, (iz, iy, ix) in enumerate(cells):
-        row = offset_blocks(qnn[:, :, :, :, iz, :], (iy - ym)[:, None],
-                            (ix - xm)[None, :])                          # [ny,nx,a,b,jz]
+        qrow = qnn(iz) if callable(qnn) else qnn[:, :, :, :, iz, :]
+        row = offset_blocks(qrow, (iy - ym)[:, None], (ix - xm)[None, :])  # [ny,nx,a,b,jz]
         bx = np.einsum("yxabj,rbjyx->ra", row, xs, optimize=True)
         if mode == "B":
             out[:, k] = bx

@@ -46,6 +46,32 @@ def split_classes(packed, nz):
     return out
 
 
+def tensor_row(packed, nz, iz):
+    """Q(i, j)[..., iz, :] for i, j >= 0, the row of observation depth iz:
+    shape [Ny][Nx][3][3][Nz].  The same numbers as full_tensor_nonneg
+    restricted to one row, read straight from the stored classes (Lemma 1)
+    so that large grids need not form the whole tensor."""
+    t = nz * (nz + 1) // 2
+    iu = np.triu_indices(nz)
+    pos = np.zeros((nz, nz), dtype=int)
+    pos[iu[0], iu[1]] = np.arange(t)
+    pos[iu[1], iu[0]] = np.arange(t)
+    up = pos[iz]                                  # upper-triangle slot of (iz, jz)
+    base = 4 * t
+    jz = np.arange(nz)
+    q = np.zeros(packed.shape[:2] + (3, 3, nz), dtype=np.complex128)
+    q[:, :, 0, 0] = packed[..., up]
+    q[:, :, 0, 1] = packed[..., t + up]
+    q[:, :, 1, 0] = packed[..., t + up]
+    q[:, :, 1, 1] = packed[..., 2 * t + up]
+    q[:, :, 2, 2] = packed[..., 3 * t + up]
+    q[:, :, 0, 2] = packed[..., base + iz * nz + jz]                 # xz[iz][jz]
+    q[:, :, 1, 2] = packed[..., base + nz * nz + iz * nz + jz]       # yz[iz][jz]
+    q[:, :, 2, 0] = -packed[..., base + jz * nz + iz]                # zx = -xz^T
+    q[:, :, 2, 1] = -packed[..., base + nz * nz + jz * nz + iz]      # zy = -yz^T
+    return q
+
+
 def pack_classes(blocks, nz):
     """Inverse of split_classes for tables built from full blocks."""
     iu = np.triu_indices(nz)

@@ -205,3 +205,13 @@ def test_row_evaluator_matches_dense_apply(mode):
     yc = dense.apply_cells(packed.full_tensor_nonneg(t, m["nz"]), m, x, cells, mode)
     ref = np.stack([y[:, :, iz, iy, ix] for (iz, iy, ix) in cells], 1)
     assert np.abs(yc - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_tensor_row_is_a_row_of_the_full_tensor():
+    from oracle import packed
+    rng = np.random.default_rng(41)
+    nz = 5
+    t = gs.random_packed_table(rng, 4, 3, nz)
+    full = packed.full_tensor_nonneg(t, nz)
+    for iz in range(nz):
+        assert np.array_equal(packed.tensor_row(t, nz, iz), full[:, :, :, :, iz, :])
