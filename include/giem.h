@@ -221,6 +221,28 @@ int giem_solve(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
                giem_solve_stats *stats, void *stream);
 
 /*
+ * giem_solve_batch -- giem_solve for nf frequencies of one model at once.
+ * The operators of one model at several frequencies share sigma_a and the
+ * diagonal scalings of Sect. 3.1 and differ only in their tables, so the
+ * nf x nrhs systems run GMRES (Sect. 3.4) in lockstep: one host
+ * synchronisation per Arnoldi step for all of them, applies grouped per
+ * frequency.  Each system follows its own Krylov process, so the results are
+ * those of nf separate giem_solve calls up to rounding.
+ *   ifreqs:  host int32 [nf], frequency indices of the handle;
+ *   rhs:     host [nf] device pointers to [nrhs][3][Nz][Ny][Nx] c128, or
+ *            NULL (or NULL entries) for the plane-wave source;
+ *   E_cells: host [nf] device pointers to [nrhs][3][Nz][Ny][Nx] c128 outputs
+ *            (inputs if warm_start);
+ *   stats:   host [nf] or NULL; iters and outer_iters count the whole batch,
+ *            ms is the wall time of the call.
+ * nf * nrhs <= 96.  Returns GIEM_ENOCONV if any system stops at the
+ * iteration limit.  Errors as giem_solve.
+ */
+int giem_solve_batch(giem_handle *t, int32_t nf, const int32_t *ifreqs, const void *sigma_a,
+                     int32_t nrhs, const void *const *rhs, void *const *E_cells,
+                     const giem_solve_opts *opts, giem_solve_stats *stats, void *stream);
+
+/*
  * giem_adjoint -- gradient of J = sum_r Re( sum_n g_r[n] . E_r[n] ) with
  * respect to log sigma_a of every cell for real conductivities (the
  * sensitivity is obtained from one solve with A^T; B = B^T by reciprocity).

@@ -77,6 +77,7 @@ def load():
         "giem_apply": [P, I32, P, I32, P, P, U32, U32, P],
         "giem_apply_timed": [P, I32, P, I32, P, P, U32, U32, P, P],
         "giem_solve": [P, I32, P, I32, P, P, P, P, P],
+        "giem_solve_batch": [P, I32, P, P, I32, P, P, P, P, P],
         "giem_adjoint": [P, I32, P, I32, P, P, P, P, P, P],
         "giem_fields": [P, I32, P, I32, P, I32, P, P, P, P],
         "giem_fields_adjoint": [P, I32, P, I32, P, I32, P, P, P, P, P, P],
@@ -101,7 +102,7 @@ def load():
 
 def exported_symbols():
     return ["giem_tables", "giem_tables_import", "giem_tables_export", "giem_tables_bytes",
-            "giem_apply", "giem_apply_timed", "giem_tune", "giem_set_fft_shape", "giem_profile", "giem_profile_read", "giem_solve",
+            "giem_apply", "giem_apply_timed", "giem_tune", "giem_set_fft_shape", "giem_profile", "giem_profile_read", "giem_solve", "giem_solve_batch",
             "giem_adjoint", "giem_fields", "giem_fields_adjoint", "giem_impedance",
             "giem_impedance_adjoint", "giem_free", "giem_last_error"]
 
@@ -228,6 +229,35 @@ class Handle:
         d = st.as_dict()
         d["rc"] = rc
         return d
+
+    def solve_batch(self, sigma_a, E_outs, ifreqs=None, rhs=None, tol=1e-6, restart=30,
+                    max_iter=2000, precision=FP64, inner_tol=1e-3, max_outer=20, weighted_ip=0,
+                    warm_start=0, stream=None):
+        """Solve at several frequencies at once: E_outs[f] receives the
+        solution at frequency ifreqs[f] (all frequencies by default); rhs is
+        None (plane waves) or a list of tensors.  Returns one stats dict per
+        frequency."""
+        nf = len(E_outs)
+        if ifreqs is None:
+            ifreqs = list(range(nf))
+        fi = (ctypes.c_int32 * nf)(*ifreqs)
+        ep = (ctypes.c_void_p * nf)(*[e.data_ptr() for e in E_outs])
+        rp = None
+        if rhs is not None:
+            rp = (ctypes.c_void_p * nf)(*[(r.data_ptr() if r is not None else None) for r in rhs])
+        o = SolveOpts(tol=tol, restart=restart, max_iter=max_iter, precision=precision,
+                      inner_tol=inner_tol, max_outer=max_outer, weighted_ip=weighted_ip,
+                      warm_start=warm_start)
+        st = (SolveStats * nf)()
+        rc = _lib.giem_solve_batch(self._p, nf, fi, _ptr(sigma_a), E_outs[0].shape[0], rp, ep,
+                                   ctypes.byref(o), st, _stream(stream))
+        _check(rc, allow_noconv=True)
+        out = []
+        for k in range(nf):
+            d = st[k].as_dict()
+            d["rc"] = rc
+            out.append(d)
+        return out
 
     def adjoint(self, sigma_a, adj_src, E_fwd, grad, tol=1e-10, restart=30, max_iter=4000,
                 weighted_ip=0, ifreq=0, stream=None):

@@ -384,10 +384,10 @@ static int finish_handle(giem_handle *t, hipStream_t s) {
   GIEM_HIP(hipMalloc(&t->diag, 4 * t->ncell() * sizeof(c128)), "hipMalloc diagonals");
   const size_t nred = (size_t)kMaxRhs * 65 * dot_partials_per_rhs();
   GIEM_HIP(hipMalloc(&t->red_part, nred * sizeof(c128)), "hipMalloc");
-  GIEM_HIP(hipMalloc(&t->red_out, kMaxRhs * 65 * sizeof(c128)), "hipMalloc");
-  GIEM_HIP(hipHostMalloc(&t->red_host, kMaxRhs * 65 * sizeof(c128), 0), "hipHostMalloc");
-  GIEM_HIP(hipMalloc(&t->coef_dev, kMaxRhs * 65 * sizeof(c128)), "hipMalloc");
-  GIEM_HIP(hipHostMalloc(&t->coef_host, kMaxRhs * 65 * sizeof(c128), 0), "hipHostMalloc");
+  GIEM_HIP(hipMalloc(&t->red_out, kMaxSys * 65 * sizeof(c128)), "hipMalloc");
+  GIEM_HIP(hipHostMalloc(&t->red_host, kMaxSys * 65 * sizeof(c128), 0), "hipHostMalloc");
+  GIEM_HIP(hipMalloc(&t->coef_dev, kMaxSys * 65 * sizeof(c128)), "hipMalloc");
+  GIEM_HIP(hipHostMalloc(&t->coef_host, kMaxSys * 65 * sizeof(c128), 0), "hipHostMalloc");
   GIEM_TRY(ensure_spec_ws(t, 2, PREC_FP64));
   return upload_spatial(t, s);
 }

@@ -80,6 +80,8 @@ struct VecPtrsT {
 };
 using VecPtrs = VecPtrsT<c128>;
 using VecPtrs32 = VecPtrsT<c64>;
+// linear systems (frequencies x right-hand sides) of one batched solve
+constexpr int kMaxSys = 96;
 
 // Operator modes and precisions (mirror include/giem.h)
 enum { MODE_A = 0, MODE_AT = 1, MODE_B = 2 };

@@ -56,9 +56,9 @@ struct giem_handle {
   size_t spec_ws_bytes = 0;
   // reduction scratch
   void *red_part = nullptr;  // c128 [kMaxRhs][65][nblk]
-  void *red_out = nullptr;   // c128 [kMaxRhs][65]
+  void *red_out = nullptr;   // c128 [kMaxSys][65]
   void *red_host = nullptr;  // pinned host mirror of red_out
-  void *coef_dev = nullptr;  // c128 [kMaxRhs][65] coefficients for updates
+  void *coef_dev = nullptr;  // c128 [kMaxSys][65] coefficients for updates
   void *coef_host = nullptr; // pinned
   // solver workspace (grown on demand)
   void *basis = nullptr;

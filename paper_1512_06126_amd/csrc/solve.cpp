@@ -175,6 +175,30 @@ static int apply_ptrs(giem_handle *t, int ifreq, const std::vector<const VT *> &
   return GIEM_OK;
 }
 
+// y = op x for systems of several frequencies: in[i], out[i] belong to system
+// sys[i], whose operator is frequency fq[sys[i]]; one batched apply per
+// frequency.
+template <typename VT>
+static int apply_sys(giem_handle *t, const std::vector<int> &fq, const std::vector<int> &sys,
+                     const std::vector<const VT *> &in, const std::vector<VT *> &out,
+                     unsigned mode, unsigned prec, hipStream_t s) {
+  std::vector<char> used(in.size(), 0);
+  for (size_t i = 0; i < in.size(); ++i) {
+    if (used[i]) continue;
+    const int f = fq[sys[i]];
+    std::vector<const VT *> gi;
+    std::vector<VT *> go;
+    for (size_t k = i; k < in.size(); ++k)
+      if (!used[k] && fq[sys[k]] == f) {
+        gi.push_back(in[k]);
+        go.push_back(out[k]);
+        used[k] = 1;
+      }
+    GIEM_TRY(apply_ptrs(t, f, gi, go, mode, prec, s));
+  }
+  return GIEM_OK;
+}
+
 // Squared norm ratio below which a Gram-Schmidt pass is repeated: a second
 // pass only when the projection removed more than 90% of the norm (severe
 // cancellation).  On the layered-earth workloads this never changes the
@@ -184,9 +208,16 @@ constexpr double kReorthDrop = 0.01;
 
 // VT: storage of the Krylov vectors, x and b (complex128; complex64 for the
 // inner solve of the precision form, which runs the FP32 operator).
+// System r has right-hand side b[r], solution x[r] and operator fq[r] (the
+// frequency index); systems of different frequencies advance in lockstep,
+// with one host synchronisation per Arnoldi step for all of them.
 template <typename VT>
-static int gmres(giem_handle *t, int ifreq, int nrhs, const VT *const *b, VT *const *x,
-                 const GmresParams &gp, hipStream_t s, GmresResult &res) {
+static int gmres(giem_handle *t, const std::vector<int> &fq, int nrhs, const VT *const *b,
+                 VT *const *x, const GmresParams &gp, hipStream_t s, GmresResult &res) {
+  if (nrhs > kMaxSys || (int)fq.size() < nrhs) {
+    set_error("too many linear systems in one solve");
+    return GIEM_EINVAL;
+  }
   const int m = gp.m;
   const size_t n = t->nvec();
   const int plane = t->nx * t->ny;
@@ -232,7 +263,7 @@ static int gmres(giem_handle *t, int ifreq, int nrhs, const VT *const *b, VT *co
         in.push_back(x[r]);
         out.push_back(V(r, 0));
       }
-      GIEM_TRY(apply_ptrs(t, ifreq, in, out, gp.mode, gp.prec, s));
+      GIEM_TRY(apply_sys(t, fq, act, in, out, gp.mode, gp.prec, s));
       for (int r : act)
         GIEM_HIP(launch_axpby(V(r, 0), b[r], V(r, 0), mk<double>(1, 0), mk<double>(-1, 0), n, s), "axpby");
     }
@@ -275,21 +306,26 @@ static int gmres(giem_handle *t, int ifreq, int nrhs, const VT *const *b, VT *co
         in.push_back(V(r, j));
         out.push_back(V(r, j + 1));
       }
-      GIEM_TRY(apply_ptrs(t, ifreq, in, out, gp.mode, gp.prec, s));
+      GIEM_TRY(apply_sys(t, fq, running, in, out, gp.mode, gp.prec, s));
       ++iters;
       // classical Gram-Schmidt, repeated once when the norm drops sharply
       // (cancellation of more than a factor 10)
       std::vector<std::vector<cd>> hcol(na, std::vector<cd>(j + 1, 0.0));
       std::vector<double> nw0(na, 0.0), nw1(na, 0.0);
       for (int pass = 0; pass < 2; ++pass) {
-        DotArgsT<VT> da{};
-        for (int q = 0; q < na; ++q) {
-          da.w[q] = V(running[q], j + 1);
-          da.basis[q] = V(running[q], 0);
-        }
         const int nb = j + 1;
-        GIEM_HIP(launch_dots(da, na, nb, n, t->nz, plane, wlev, part, hdev, s), "dots");
-        GIEM_HIP(launch_update(da, na, nb, n, t->nz, plane, wlev, hdev, nb + 1, part, ndev, s), "update");
+        for (int q0 = 0; q0 < na; q0 += kMaxRhs) {
+          const int nq = std::min(kMaxRhs, na - q0);
+          DotArgsT<VT> da{};
+          for (int q = 0; q < nq; ++q) {
+            da.w[q] = V(running[q0 + q], j + 1);
+            da.basis[q] = V(running[q0 + q], 0);
+          }
+          c128 *hq = hdev + (size_t)q0 * (nb + 1);
+          GIEM_HIP(launch_dots(da, nq, nb, n, t->nz, plane, wlev, part, hq, s), "dots");
+          GIEM_HIP(launch_update(da, nq, nb, n, t->nz, plane, wlev, hq, nb + 1, part, ndev + q0, s),
+                   "update");
+        }
         GIEM_HIP(hipMemcpyAsync(hhost, hdev, (size_t)na * (nb + 1) * sizeof(c128), hipMemcpyDeviceToHost, s), "copy h");
         GIEM_HIP(hipMemcpyAsync(chost, ndev, (size_t)na * sizeof(c128), hipMemcpyDeviceToHost, s), "copy norm");
         GIEM_HIP(hipStreamSynchronize(s), "sync");
@@ -377,7 +413,7 @@ static int gmres(giem_handle *t, int ifreq, int nrhs, const VT *const *b, VT *co
           in.push_back(x[r]);
           out.push_back(V(r, 0));
         }
-        GIEM_TRY(apply_ptrs(t, ifreq, in, out, gp.mode, gp.prec, s));
+        GIEM_TRY(apply_sys(t, fq, left, in, out, gp.mode, gp.prec, s));
         std::vector<const VT *> rp;
         for (int r : left) {
           GIEM_HIP(launch_axpby(V(r, 0), b[r], V(r, 0), mk<double>(1, 0), mk<double>(-1, 0), n, s), "axpby");
@@ -419,63 +455,93 @@ static int check_sigma_a(giem_handle *t, const void *sigma_a, hipStream_t s) {
   return GIEM_OK;
 }
 
-static int solve_impl(giem_handle *t, int ifreq, const void *sigma_a, int nrhs, const void *rhs,
-                      void *E_cells, const giem_solve_opts *o, giem_solve_stats *st,
-                      hipStream_t s, unsigned mode) {
+// Solve for nf frequencies of the handle at once (nf = 1 for giem_solve).
+// System (f, r) = frequency ifreqs[f], right-hand side r; all systems share
+// sigma_a and therefore the diagonals S, R1, R2, a.  rhs[f] (or NULL for the
+// plane-wave source) and E_cells[f] are [nrhs][3][N] device arrays; st has nf
+// entries (or is NULL).
+static int solve_batch_impl(giem_handle *t, int nf, const int *ifreqs, const void *sigma_a,
+                            int nrhs, const void *const *rhs, void *const *E_cells,
+                            const giem_solve_opts *o, giem_solve_stats *st, hipStream_t s,
+                            unsigned mode) {
   auto t0 = std::chrono::steady_clock::now();
-  if (!t || ifreq < 0 || ifreq >= (int)t->f.size() || nrhs < 1 || nrhs > kMaxRhs || !sigma_a ||
-      !E_cells || !o) {
+  if (!t || nf < 1 || !ifreqs || nrhs < 1 || nrhs > kMaxRhs || !sigma_a || !E_cells || !o) {
     set_error("giem_solve: bad argument");
     return GIEM_EINVAL;
   }
-  if (!rhs && nrhs > 2) {
-    set_error("giem_solve: the plane-wave source has two polarisations (nrhs <= 2)");
+  if (nf * nrhs > kMaxSys) {
+    set_error("giem_solve_batch: more than " + std::to_string(kMaxSys) +
+              " systems (frequencies x right-hand sides)");
     return GIEM_EINVAL;
+  }
+  for (int f = 0; f < nf; ++f) {
+    if (ifreqs[f] < 0 || ifreqs[f] >= (int)t->f.size() || !E_cells[f]) {
+      set_error("giem_solve: bad frequency index or output");
+      return GIEM_EINVAL;
+    }
+    if (!(rhs && rhs[f]) && nrhs > 2) {
+      set_error("giem_solve: the plane-wave source has two polarisations (nrhs <= 2)");
+      return GIEM_EINVAL;
+    }
+    if (o->precision == PREC_FP32 && !t->f[ifreqs[f]].spec32) {
+      set_error("giem_solve: the FP32 form needs tables built with GIEM_TABLES_C64");
+      return GIEM_EINVAL;
+    }
   }
   if (!(o->tol > 0) || o->restart < 1 || o->restart > 64 || o->max_iter < 1 ||
       (o->precision != PREC_FP64 && o->precision != PREC_FP32)) {
     set_error("giem_solve: bad options (tol > 0, 1 <= restart <= 64, max_iter >= 1)");
     return GIEM_EINVAL;
   }
-  if (o->precision == PREC_FP32 && !t->f[ifreq].spec32) {
-    set_error("giem_solve: the FP32 form needs tables built with GIEM_TABLES_C64");
-    return GIEM_EINVAL;
-  }
   GIEM_TRY(check_sigma_a(t, sigma_a, s));
   GIEM_TRY(compute_diagonals(t, static_cast<const c128 *>(sigma_a), s));
   const size_t n = t->nvec(), nc = t->ncell();
-  // workspace: b, u, residual, correction (nrhs vectors each)
-  GIEM_TRY(ensure_vec_ws(t, (size_t)4 * nrhs));
+  const int ns = nf * nrhs;  // systems, index f * nrhs + r
+  // workspace: b, u, residual, correction (ns vectors each)
+  GIEM_TRY(ensure_vec_ws(t, (size_t)4 * ns));
   c128 *ws = static_cast<c128 *>(t->vec_ws);
-  c128 *bv = ws, *uv = ws + (size_t)nrhs * n, *dv = ws + (size_t)2 * nrhs * n;
-  c128 *cv = ws + (size_t)3 * nrhs * n;
+  c128 *bv = ws, *uv = ws + (size_t)ns * n, *dv = ws + (size_t)2 * ns * n;
+  c128 *cv = ws + (size_t)3 * ns * n;
   const c128 *acell = static_cast<const c128 *>(t->diag) + 3 * nc;
-  if (rhs) {
-    GIEM_HIP(hipMemcpyAsync(bv, rhs, (size_t)nrhs * n * sizeof(c128), hipMemcpyDeviceToDevice, s), "copy rhs");
-  } else {
-    std::vector<cd> en, hs;
-    plane_wave_levels(t, t->f[ifreq].freq, en, hs);
-    std::vector<c128> enc(t->nz);
-    for (int k = 0; k < t->nz; ++k) enc[k] = mk<double>(en[k].real(), en[k].imag());
-    // stage per-level E^N in the small coefficient buffer
-    if ((size_t)t->nz > (size_t)kMaxRhs * 65) {
-      set_error("Nz too large");
-      return GIEM_EINVAL;
+  for (int f = 0; f < nf; ++f) {
+    c128 *bf = bv + (size_t)f * nrhs * n;
+    if (rhs && rhs[f]) {
+      GIEM_HIP(hipMemcpyAsync(bf, rhs[f], (size_t)nrhs * n * sizeof(c128), hipMemcpyDeviceToDevice, s),
+               "copy rhs");
+    } else {
+      std::vector<cd> en, hs;
+      plane_wave_levels(t, t->f[ifreqs[f]].freq, en, hs);
+      std::vector<c128> enc(t->nz);
+      for (int k = 0; k < t->nz; ++k) enc[k] = mk<double>(en[k].real(), en[k].imag());
+      // stage per-level E^N in the small coefficient buffer
+      if ((size_t)t->nz > (size_t)kMaxSys * 65) {
+        set_error("Nz too large");
+        return GIEM_EINVAL;
+      }
+      GIEM_HIP(hipMemcpyAsync(t->coef_dev, enc.data(), t->nz * sizeof(c128), hipMemcpyHostToDevice, s),
+               "copy EN");
+      for (int r = 0; r < nrhs; ++r)
+        GIEM_HIP(launch_plane_wave_rhs(static_cast<c128 *>(t->coef_dev),
+                                       static_cast<double *>(t->sroot_lev), t->nx, t->ny, t->nz, r,
+                                       bf + (size_t)r * n, s),
+                 "plane wave");
+      GIEM_HIP(hipStreamSynchronize(s), "sync");
     }
-    GIEM_HIP(hipMemcpyAsync(t->coef_dev, enc.data(), t->nz * sizeof(c128), hipMemcpyHostToDevice, s), "copy EN");
-    for (int r = 0; r < nrhs; ++r)
-      GIEM_HIP(launch_plane_wave_rhs(static_cast<c128 *>(t->coef_dev), static_cast<double *>(t->sroot_lev),
-                                     t->nx, t->ny, t->nz, r, bv + (size_t)r * n, s), "plane wave");
-    GIEM_HIP(hipStreamSynchronize(s), "sync");
   }
   const bool warm = o->warm_start != 0;
-  if (warm) GIEM_HIP(launch_mul_cells(uv, static_cast<const c128 *>(E_cells), acell, nrhs, nc, s), "U = a E");
-  std::vector<const c128 *> bp(nrhs);
-  std::vector<c128 *> up(nrhs), dp(nrhs);
-  for (int r = 0; r < nrhs; ++r) {
-    bp[r] = bv + (size_t)r * n;
-    up[r] = uv + (size_t)r * n;
-    dp[r] = dv + (size_t)r * n;
+  if (warm)
+    for (int f = 0; f < nf; ++f)
+      GIEM_HIP(launch_mul_cells(uv + (size_t)f * nrhs * n, static_cast<const c128 *>(E_cells[f]),
+                                acell, nrhs, nc, s),
+               "U = a E");
+  std::vector<const c128 *> bp(ns);
+  std::vector<c128 *> up(ns), dp(ns);
+  std::vector<int> fq(ns);
+  for (int q = 0; q < ns; ++q) {
+    bp[q] = bv + (size_t)q * n;
+    up[q] = uv + (size_t)q * n;
+    dp[q] = dv + (size_t)q * n;
+    fq[q] = ifreqs[q / nrhs];
   }
   GmresParams gp;
   gp.tol = o->tol;
@@ -484,63 +550,63 @@ static int solve_impl(giem_handle *t, int ifreq, const void *sigma_a, int nrhs, 
   gp.weighted = o->weighted_ip;
   gp.mode = mode;
   int rc = GIEM_OK;
-  giem_solve_stats lst{};
+  int iters_total = 0, outer_total = 0;
+  std::vector<double> relres(ns, 0.0);
+  std::vector<char> sys_conv(ns, 0);
   if (o->precision == PREC_FP64) {
     gp.prec = PREC_FP64;
     gp.x_zero = !warm;
     GmresResult gr;
-    GIEM_TRY(gmres(t, ifreq, nrhs, bp.data(), up.data(), gp, s, gr));
-    lst.iters = gr.iters;
-    lst.outer_iters = gr.restarts;
-    lst.converged = gr.converged;
-    lst.rel_residual = *std::max_element(gr.relres.begin(), gr.relres.end());
-    rc = gr.converged ? GIEM_OK : GIEM_ENOCONV;
+    GIEM_TRY(gmres(t, fq, ns, bp.data(), up.data(), gp, s, gr));
+    iters_total = gr.iters;
+    outer_total = gr.restarts;
+    for (int q = 0; q < ns; ++q) {
+      relres[q] = gr.relres[q];
+      sys_conv[q] = gr.relres[q] <= o->tol;
+    }
   } else {
     // refinement: r = b - A64 u (FP64), inner GMRES on A32 d = r, u += d
     const double *wlev = o->weighted_ip ? static_cast<const double *>(t->vol_lev) : nullptr;
     std::vector<double> normb, rn;
-    GIEM_TRY(norms_of(t, bp.data(), nrhs, wlev, s, normb));
+    GIEM_TRY(norms_of(t, bp.data(), ns, wlev, s, normb));
     if (!warm)
-      for (int r = 0; r < nrhs; ++r) GIEM_HIP(hipMemsetAsync(up[r], 0, n * sizeof(c128), s), "zero");
+      for (int q = 0; q < ns; ++q) GIEM_HIP(hipMemsetAsync(up[q], 0, n * sizeof(c128), s), "zero");
     const int max_outer = o->max_outer > 0 ? o->max_outer : 20;
     const double itol = o->inner_tol > 0 ? o->inner_tol : 1e-3;
-    std::vector<int> act;
+    std::vector<int> all(ns), act;
+    for (int q = 0; q < ns; ++q) all[q] = q;
     int outer = 0, inner_total = 0;
-    double worst = 0.0;
-    bool conv = false;
     for (outer = 0; outer <= max_outer; ++outer) {
-      // true FP64 residual of all RHS
+      // true FP64 residual of every system
       std::vector<const c128 *> in(up.begin(), up.end());
-      GIEM_TRY(apply_ptrs(t, ifreq, in, dp, mode, PREC_FP64, s));
-      for (int r = 0; r < nrhs; ++r)
-        GIEM_HIP(launch_axpby(dp[r], bp[r], dp[r], mk<double>(1, 0), mk<double>(-1, 0), n, s), "axpby");
+      GIEM_TRY(apply_sys(t, fq, all, in, dp, mode, PREC_FP64, s));
+      for (int q = 0; q < ns; ++q)
+        GIEM_HIP(launch_axpby(dp[q], bp[q], dp[q], mk<double>(1, 0), mk<double>(-1, 0), n, s), "axpby");
       std::vector<const c128 *> dcp(dp.begin(), dp.end());
-      GIEM_TRY(norms_of(t, dcp.data(), nrhs, wlev, s, rn));
+      GIEM_TRY(norms_of(t, dcp.data(), ns, wlev, s, rn));
       act.clear();
-      worst = 0.0;
-      for (int r = 0; r < nrhs; ++r) {
-        const double rel = normb[r] > 0 ? rn[r] / normb[r] : 0.0;
-        worst = std::max(worst, rel);
-        if (rel > o->tol) act.push_back(r);
+      for (int q = 0; q < ns; ++q) {
+        relres[q] = normb[q] > 0 ? rn[q] / normb[q] : 0.0;
+        sys_conv[q] = relres[q] <= o->tol;
+        if (!sys_conv[q]) act.push_back(q);
       }
-      if (act.empty()) {
-        conv = true;
-        break;
-      }
+      if (act.empty()) break;
       if (outer == max_outer || inner_total >= o->max_iter) break;
-      // inner solve of A d = r for the RHS not yet converged, entirely in
+      // inner solve of A d = r for the systems not yet converged, entirely in
       // complex64 (vectors, basis and operator; FP64 accumulation), in the
-      // space of the correction buffer: r32 and d32 per RHS
+      // space of the correction buffer: r32 and d32 per system
       std::vector<const c64 *> rb;
       std::vector<c64 *> cx;
-      for (int r : act) {
-        c64 *r32 = reinterpret_cast<c64 *>(cv + (size_t)r * n);
+      std::vector<int> afq;
+      for (int q : act) {
+        c64 *r32 = reinterpret_cast<c64 *>(cv + (size_t)q * n);
         c64 *dst[1] = {r32};
-        const c128 *src[1] = {dp[r]};
+        const c128 *src[1] = {dp[q]};
         const c128 one = mk<double>(1, 0);
         GIEM_HIP(launch_scale(dst, src, &one, 1, n, s), "r -> complex64");
         rb.push_back(r32);
         cx.push_back(r32 + n);
+        afq.push_back(fq[q]);
       }
       GmresParams ip = gp;
       ip.prec = PREC_FP32;
@@ -548,24 +614,51 @@ static int solve_impl(giem_handle *t, int ifreq, const void *sigma_a, int nrhs, 
       ip.x_zero = true;
       ip.max_iter = std::max(1, o->max_iter - inner_total);
       GmresResult gr;
-      GIEM_TRY(gmres(t, ifreq, (int)act.size(), rb.data(), cx.data(), ip, s, gr));
+      GIEM_TRY(gmres(t, afq, (int)act.size(), rb.data(), cx.data(), ip, s, gr));
       inner_total += gr.iters;
-      for (size_t q = 0; q < act.size(); ++q)
-        GIEM_HIP(launch_axpby(up[act[q]], up[act[q]], cx[q], mk<double>(1, 0), mk<double>(1, 0), n, s), "u += d");
+      for (size_t k = 0; k < act.size(); ++k)
+        GIEM_HIP(launch_axpby(up[act[k]], up[act[k]], cx[k], mk<double>(1, 0), mk<double>(1, 0), n, s),
+                 "u += d");
     }
-    lst.iters = inner_total;
-    lst.outer_iters = outer;
-    lst.converged = conv;
-    lst.rel_residual = worst;
-    rc = conv ? GIEM_OK : GIEM_ENOCONV;
+    iters_total = inner_total;
+    outer_total = outer;
   }
   // E = U / a
-  GIEM_HIP(launch_div_cells(static_cast<c128 *>(E_cells), uv, acell, nrhs, nc, s), "E = U / a");
+  bool all_conv = true;
+  for (int f = 0; f < nf; ++f)
+    GIEM_HIP(launch_div_cells(static_cast<c128 *>(E_cells[f]), uv + (size_t)f * nrhs * n, acell,
+                              nrhs, nc, s),
+             "E = U / a");
   GIEM_HIP(hipStreamSynchronize(s), "sync");
-  lst.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  if (st) *st = lst;
-  if (rc == GIEM_ENOCONV) set_error("GMRES reached the iteration limit before the tolerance");
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  for (int f = 0; f < nf; ++f) {
+    giem_solve_stats lst{};
+    lst.iters = iters_total;
+    lst.outer_iters = outer_total;
+    lst.converged = 1;
+    lst.rel_residual = 0.0;
+    for (int r = 0; r < nrhs; ++r) {
+      const int q = f * nrhs + r;
+      lst.rel_residual = std::max(lst.rel_residual, relres[q]);
+      if (!sys_conv[q]) lst.converged = 0;
+    }
+    if (!lst.converged) all_conv = false;
+    lst.ms = ms;
+    if (st) st[f] = lst;
+  }
+  if (!all_conv) {
+    rc = GIEM_ENOCONV;
+    set_error("GMRES reached the iteration limit before the tolerance");
+  }
   return rc;
+}
+
+static int solve_impl(giem_handle *t, int ifreq, const void *sigma_a, int nrhs, const void *rhs,
+                      void *E_cells, const giem_solve_opts *o, giem_solve_stats *st,
+                      hipStream_t s, unsigned mode) {
+  const void *rp[1] = {rhs};
+  void *ep[1] = {E_cells};
+  return solve_batch_impl(t, 1, &ifreq, sigma_a, nrhs, rp, ep, o, st, s, mode);
 }
 
 // Adjoint: lambda = A^{-T} (g / a), then the per-cell sensitivity kernel.
@@ -604,7 +697,7 @@ static int adjoint_impl(giem_handle *t, int ifreq, const void *sigma_a, int nrhs
   gp.prec = PREC_FP64;
   gp.x_zero = true;
   GmresResult gr;
-  GIEM_TRY(gmres(t, ifreq, nrhs, bp.data(), lp.data(), gp, s, gr));
+  GIEM_TRY(gmres(t, std::vector<int>(nrhs, ifreq), nrhs, bp.data(), lp.data(), gp, s, gr));
   GIEM_HIP(launch_mul_cells(v, lam, R1, nrhs, nc, s), "R1 lambda");
   std::vector<const c128 *> in(nrhs);
   std::vector<c128 *> out(nrhs);
@@ -643,6 +736,18 @@ int giem_solve(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
                void *E_cells, const giem_solve_opts *opts, giem_solve_stats *stats, void *stream) {
   return solve_impl(t, ifreq, sigma_a, nrhs, rhs, E_cells, opts, stats,
                     static_cast<hipStream_t>(stream), MODE_A);
+}
+
+int giem_solve_batch(giem_handle *t, int32_t nf, const int32_t *ifreqs, const void *sigma_a,
+                     int32_t nrhs, const void *const *rhs, void *const *E_cells,
+                     const giem_solve_opts *opts, giem_solve_stats *stats, void *stream) {
+  if (!t || nf < 1 || !ifreqs) {
+    set_error("giem_solve_batch: bad argument");
+    return GIEM_EINVAL;
+  }
+  std::vector<int> fi(ifreqs, ifreqs + nf);
+  return solve_batch_impl(t, nf, fi.data(), sigma_a, nrhs, rhs, E_cells, opts, stats,
+                          static_cast<hipStream_t>(stream), MODE_A);
 }
 
 int giem_adjoint(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,

@@ -87,3 +87,68 @@ def test_batched_models_and_frequencies(lib, which):
         assert max(errs) <= 1e-6, (freqs[q], errs)
     h.close()
     print(f"  worst {worst:.2e}", flush=True)
+
+
+def test_batched_solve_matches_oracle(lib):
+    # three frequencies of a small model solved together, each against the
+    # oracle's LU on its exported table
+    import torch
+    from oracle import normal_field
+    rng = np.random.default_rng(404)
+    m = gs.make_model(6, 5, 3, 100.0, 120.0, np.arange(4) * 50.0, [0.0, 100.0, 900.0],
+                      [0.0, 0.02, 0.2, 0.004], 1.0)
+    m["sigma_a"] = m["sigma_a"] * 10 ** rng.uniform(0, 2, m["sigma_a"].shape)
+    freqs = [0.1, 1.0, 10.0]
+    h = lib.tables(m, freqs, flags=lib.TABLES_C64)
+    sa = to_dev(m["sigma_a"])
+    Es = [torch.zeros((2, 3, 3, 5, 6), dtype=torch.complex128, device="cuda") for _ in freqs]
+    st = h.solve_batch(sa, Es, tol=1e-13, max_iter=4000)
+    E32 = [torch.zeros_like(e) for e in Es]
+    st32 = h.solve_batch(sa, E32, ifreqs=[2, 0, 1], tol=1e-12, precision=lib.FP32,
+                         max_iter=8000, max_outer=60)
+    torch.cuda.synchronize()
+    for q, f in enumerate(freqs):
+        assert st[q]["converged"] == 1 and st32[q]["converged"] == 1
+        mf = dict(m, freq=f)
+        d = dense.cie_diagonals(mf)
+        A = dense.system_matrix(dense.dense_from_packed(h.export(q), mf), d)
+        ref = dense.solve_lu(A, normal_field.plane_wave_rhs(mf)) / d["a"][None, None]
+        e64 = rel_err(Es[q].cpu().numpy(), ref)
+        e32 = rel_err(E32[[1, 2, 0][q]].cpu().numpy(), ref)
+        print(f"  f = {f} Hz: batched FP64 {e64:.2e}, batched FP32-refined {e32:.2e}", flush=True)
+        assert e64 <= 1e-10 and e32 <= 1e-9
+    h.close()
+
+
+def test_batched_solve_equals_separate_solves(lib):
+    # the 64 x 64 x 16 model at its twelve frequencies: one lockstep solve
+    # against twelve separate ones, and the wall time of both
+    import torch
+    models, freqs = gs.config_batched()
+    m = models[0]
+    shape = (2, 3, m["nz"], m["ny"], m["nx"])
+    h = lib.tables(m, freqs, flags=lib.TABLES_C64)
+    sa = to_dev(m["sigma_a"])
+    h.tune(sa)
+    for prec, name in ((lib.FP64, "FP64"), (lib.FP32, "FP32-refined")):
+        sep = [torch.zeros(shape, dtype=torch.complex128, device="cuda") for _ in freqs]
+        bat = [torch.zeros_like(e) for e in sep]
+        kw = dict(tol=1e-8, max_iter=20000, precision=prec, max_outer=40)
+        h.solve(sa, sep[0], ifreq=0, **kw)                 # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for q in range(len(freqs)):
+            h.solve(sa, sep[q], ifreq=q, **kw)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = h.solve_batch(sa, bat, **kw)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        assert all(s["converged"] == 1 for s in st)
+        err = max(float(torch.linalg.vector_norm(b - a) / torch.linalg.vector_norm(a))
+                  for a, b in zip(sep, bat))
+        print(f"  {name}: 12 separate solves {1e3 * (t1 - t0):.0f} ms, one batched solve "
+              f"{1e3 * (t2 - t1):.0f} ms ({(t1 - t0) / (t2 - t1):.2f}x); max difference {err:.1e}",
+              flush=True)
+        assert err <= 1e-7
+    h.close()
