@@ -59,9 +59,10 @@ def m3_bytes(nx, ny, nz, R, c):
     return T + R * 78 * nx * ny * nz * c
 
 
-def read_traffic():
+def read_traffic(block_buffers):
     """HBM bytes per launch of the block product from the committed counter
-    summary, or None when absent or taken on another version of the kernel."""
+    summary, or None when absent, taken on another version of the kernel, or
+    on the other prefetch depth than the one in use."""
     if not os.path.exists(COUNTERS_FILE):
         return None
     kv = {}
@@ -71,7 +72,7 @@ def read_traffic():
             kv[k.strip()] = v.strip().strip("`")
     with open(BLOCK_SOURCE, "rb") as fh:
         sha = hashlib.sha256(fh.read()).hexdigest()
-    if kv.get("kernel_source_sha256") != sha:
+    if kv.get("kernel_source_sha256") != sha or kv.get("block_buffers") != str(block_buffers):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -133,6 +134,9 @@ def main():
     ap.add_argument("--counter-run", action="store_true",
                     help="only a 1 GiB device copy (counter calibration) and 3 FP64 applies, "
                          "for hardware-counter passes")
+    ap.add_argument("--block-buffers", type=int, default=2,
+                    help="prefetch sets of the block product in --counter-run (the depth "
+                         "giem_tune chooses for FP64 on this workload)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
@@ -169,10 +173,12 @@ def main():
         dst.copy_(src)
         x = torch.randn((R, 3, nz, ny, nx), dtype=torch.complex128, device=dev)
         y = torch.empty_like(x)
+        h.set_block_buffers(g.FP64, args.block_buffers)
         for _ in range(3):
             h.apply(x, y, sa, prec=g.FP64)
         torch.cuda.synchronize()
-        print("counter run done: copy 1073741824 B, 3 FP64 applies", flush=True)
+        print(f"counter run done: copy 1073741824 B, 3 FP64 applies "
+              f"(block product with {args.block_buffers} prefetch sets)", flush=True)
         h.close()
         return
 
@@ -209,7 +215,7 @@ def main():
     avg_rhs = p64["rhs"] / max(p64["applies"], 1)
     bytes_launch = stage_bytes(nx, ny, nz, avg_rhs, 16)[name]
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-    traffic = read_traffic() if name == "block_product" else None
+    traffic = read_traffic(fft_shape["block_buffers"]["fp64"]) if name == "block_product" else None
     roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "bytes_per_launch": bytes_launch,

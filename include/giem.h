@@ -171,17 +171,19 @@ int giem_apply_timed(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t
    (null handle). */
 int giem_profile(giem_handle *t, int32_t enable);
 
-/* giem_tune -- choose the launch shape of the four FFT passes of the apply
-   (Sect. 3.3 steps 1 and 3: x forward, y forward, y inverse, x inverse) for
-   this handle by timing: for each precision whose tables exist, every
-   instantiated (sequences per workgroup, threads per workgroup) pair that
-   fits the local data share is run on nrhs right-hand sides of frequency
-   ifreq, and the fastest median per pass is kept on the handle for all later
-   applies (results do not depend on the choice beyond rounding order, which
-   is the same: each transform runs on one workgroup either way).
+/* giem_tune -- choose launch shapes of the apply for this handle by timing
+   (Sect. 3.3): for the four FFT passes (x forward, y forward, y inverse, x
+   inverse) every instantiated (sequences per workgroup, threads per
+   workgroup) pair that fits the local data share, and for the block product
+   one or two register sets of prefetched points; each candidate is run on
+   nrhs right-hand sides of frequency ifreq for every precision whose tables
+   exist, and the fastest median is kept on the handle for all later applies.
+   Results do not depend on the choice: every transform and every block
+   product is computed the same way whichever workgroup runs it.
      sigma_a: device c128 [Nz][Ny][Nx] (the diagonals of mode A are used);
-     chosen:  host int32 [2][4][2] or NULL: (sequences, threads) per
-              precision (0 = FP64, 1 = FP32) and pass, as now in effect.
+     chosen:  host int32 [2][5][2] or NULL: per precision (0 = FP64,
+              1 = FP32) the (sequences, threads) of the four passes, then
+              (register sets, 0) of the block product, as now in effect.
    Allocates and frees two vectors of nrhs right-hand sides; synchronises.
    Errors: EINVAL, ENOMEM, EHIP. */
 int giem_tune(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs, void *stream,
@@ -195,6 +197,12 @@ int giem_tune(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs, 
    at most 16 elements per thread.  NULL restores the built-in choice.
    Errors: EINVAL (nothing is changed). */
 int giem_set_fft_shape(giem_handle *t, uint32_t prec, const int32_t *shape);
+
+/* giem_set_block_buffers -- register sets of prefetched points in the block
+   product (Sect. 3.3 step 2) for one precision (0 = FP64, 1 = FP32): 1 or 2
+   (2 keeps the next point's loads in flight while a point is staged into
+   local memory), 0 for the built-in choice (1).  Errors: EINVAL. */
+int giem_set_block_buffers(giem_handle *t, uint32_t prec, int32_t nbuf);
 
 /* giem_profile_read -- wait for the last recorded apply and report what was
    recorded since giem_profile or the previous read, then clear it:

@@ -86,6 +86,7 @@ def load():
         "giem_profile": [P, I32],
         "giem_tune": [P, I32, P, I32, P, P],
         "giem_set_fft_shape": [P, U32, P],
+        "giem_set_block_buffers": [P, U32, I32],
         "giem_profile_read": [P, P, P, P],
         "giem_free": [P],
         "giem_last_error": [],
@@ -102,7 +103,7 @@ def load():
 
 def exported_symbols():
     return ["giem_tables", "giem_tables_import", "giem_tables_export", "giem_tables_bytes",
-            "giem_apply", "giem_apply_timed", "giem_tune", "giem_set_fft_shape", "giem_profile", "giem_profile_read", "giem_solve", "giem_solve_batch",
+            "giem_apply", "giem_apply_timed", "giem_tune", "giem_set_fft_shape", "giem_set_block_buffers", "giem_profile", "giem_profile_read", "giem_solve", "giem_solve_batch",
             "giem_adjoint", "giem_fields", "giem_fields_adjoint", "giem_impedance",
             "giem_impedance_adjoint", "giem_free", "giem_last_error"]
 
@@ -186,12 +187,15 @@ class Handle:
         return list(ms)
 
     def tune(self, sigma_a, nrhs=2, ifreq=0, stream=None):
-        """Time the FFT launch shapes on this handle and keep the fastest;
-        returns {"fp64"|"fp32": [(sequences, threads) per pass]}."""
-        ch = (ctypes.c_int32 * 16)()
+        """Time the FFT launch shapes and the block-product prefetch depth on
+        this handle and keep the fastest; returns {"fp64"|"fp32": [(sequences,
+        threads) per pass], "block_buffers": {"fp64"|"fp32": 1 or 2}}."""
+        ch = (ctypes.c_int32 * 20)()
         _check(_lib.giem_tune(self._p, ifreq, _ptr(sigma_a), nrhs, _stream(stream), ch))
-        return {k: [(ch[(i * 4 + j) * 2], ch[(i * 4 + j) * 2 + 1]) for j in range(4)]
-                for i, k in enumerate(("fp64", "fp32"))}
+        out = {k: [(ch[(i * 5 + j) * 2], ch[(i * 5 + j) * 2 + 1]) for j in range(4)]
+               for i, k in enumerate(("fp64", "fp32"))}
+        out["block_buffers"] = {k: ch[(i * 5 + 4) * 2] for i, k in enumerate(("fp64", "fp32"))}
+        return out
 
     def set_fft_shape(self, prec, shape=None):
         """shape: four (sequences, threads) pairs, or None for the built-in choice."""
@@ -200,6 +204,10 @@ class Handle:
             return
         arr = (ctypes.c_int32 * 8)(*[int(v) for pair in shape for v in pair])
         _check(_lib.giem_set_fft_shape(self._p, prec, arr))
+
+    def set_block_buffers(self, prec, nbuf):
+        """Prefetch depth of the block product (1 or 2; 0 = built-in)."""
+        _check(_lib.giem_set_block_buffers(self._p, prec, nbuf))
 
     def profile(self, enable=True):
         _check(_lib.giem_profile(self._p, 1 if enable else 0))

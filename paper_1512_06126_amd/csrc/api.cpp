@@ -2,6 +2,7 @@
 // operator apply, error reporting.  The GMRES driver is in solve.cpp.
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -182,8 +183,9 @@ static int apply_core_t(giem_handle *t, int ifreq, int nrhs, const VecPtrsT<VT> 
   GIEM_TRY(mark(1));
   GIEM_HIP(launch_fft_y(prec, spa, 2 * nx, ny, rp, G[1], NT[1], t->py.d, twy, 0, s), "y-FFT");
   GIEM_TRY(mark(2));
+  const int nbuf = t->block_nbuf[prec == PREC_FP32 ? 1 : 0] == 2 ? 2 : 1;
   GIEM_HIP(launch_block(prec, tab, spa, spb, static_cast<const unsigned *>(t->bplan), nx, ny, nz,
-                        nrhs, s),
+                        nrhs, nbuf, s),
            "block product");
   GIEM_TRY(mark(3));
   GIEM_HIP(launch_fft_y(prec, spb, 2 * nx, ny, rp, G[2], NT[2], t->py.d, twy, 1, s),
@@ -551,47 +553,80 @@ int giem_tune(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs, 
       for (int k = 0; k < 4; ++k) t->fft_g[pi][k] = t->fft_nt[pi][k] = 0;
       continue;
     }
-    double best[4] = {1e30, 1e30, 1e30, 1e30};
-    int bg[4] = {0, 0, 0, 0}, bt[4] = {0, 0, 0, 0};
+    // candidates: FFT shapes (applied to all four passes at once) and the
+    // block-product prefetch depth; two interleaved rounds of seven timed
+    // applies each, the best median per candidate counts
+    struct Cand {
+      int g, nt, nbuf;
+    };
+    std::vector<Cand> cands;
     for (int nt : {256, 512})
       for (int g = 1; g <= 64; g *= 2) {
         bool any = false;
+        for (int k = 0; k < 4; ++k) any = any || fft_shape_ok(g, nt, L[k], prec);
+        if (any) cands.push_back({g, nt, 0});
+      }
+    cands.push_back({0, 0, 1});
+    cands.push_back({0, 0, 2});
+    std::vector<std::array<double, 5>> med(cands.size());
+    for (auto &m : med) m.fill(1e30);
+    for (int round = 0; round < 2; ++round)
+      for (size_t c = 0; c < cands.size(); ++c) {
+        const Cand &cd = cands[c];
         for (int k = 0; k < 4; ++k) {
-          t->fft_g[pi][k] = g;
-          t->fft_nt[pi][k] = nt;
-          any = any || fft_shape_ok(g, nt, L[k], prec);
+          t->fft_g[pi][k] = cd.g;
+          t->fft_nt[pi][k] = cd.nt;
         }
-        if (!any) continue;
+        t->block_nbuf[pi] = cd.nbuf;
         double st[5];
         for (int w = 0; w < 2; ++w) GIEM_TRY(apply_core(t, ifreq, nrhs, p, MODE_A, prec, s, st));
-        std::vector<double> ms[4];
-        for (int rep = 0; rep < 5; ++rep) {
+        std::vector<double> ms[5];
+        for (int rep = 0; rep < 7; ++rep) {
           GIEM_TRY(apply_core(t, ifreq, nrhs, p, MODE_A, prec, s, st));
-          for (int k = 0; k < 4; ++k) ms[k].push_back(st[stage_of_pass[k]]);
+          for (int k = 0; k < 5; ++k) ms[k].push_back(st[k]);
         }
-        for (int k = 0; k < 4; ++k) {
-          if (!fft_shape_ok(g, nt, L[k], prec)) continue;
+        for (int k = 0; k < 5; ++k) {
           std::sort(ms[k].begin(), ms[k].end());
-          if (ms[k][2] < best[k]) {
-            best[k] = ms[k][2];
-            bg[k] = g;
-            bt[k] = nt;
-          }
+          med[c][k] = std::min(med[c][k], ms[k][3]);
         }
       }
+    double best[4] = {1e30, 1e30, 1e30, 1e30};
+    int bg[4] = {0, 0, 0, 0}, bt[4] = {0, 0, 0, 0};
+    double bbest = 1e30;
+    int bnb = 1;
+    for (size_t c = 0; c < cands.size(); ++c) {
+      const Cand &cd = cands[c];
+      if (cd.g > 0) {
+        for (int k = 0; k < 4; ++k) {
+          if (!fft_shape_ok(cd.g, cd.nt, L[k], prec)) continue;
+          const double v = med[c][stage_of_pass[k]];
+          if (v < best[k]) {
+            best[k] = v;
+            bg[k] = cd.g;
+            bt[k] = cd.nt;
+          }
+        }
+      } else if (med[c][2] < bbest) {
+        bbest = med[c][2];
+        bnb = cd.nbuf;
+      }
+    }
     for (int k = 0; k < 4; ++k) {
       t->fft_g[pi][k] = bg[k];
       t->fft_nt[pi][k] = bt[k];
     }
+    t->block_nbuf[pi] = bnb;
   }
   if (chosen) {
     for (int pi = 0; pi < 2; ++pi) {
       int G[4], NT[4];
       fft_shape(t, pi ? PREC_FP32 : PREC_FP64, G, NT);
       for (int k = 0; k < 4; ++k) {
-        chosen[(pi * 4 + k) * 2] = G[k];
-        chosen[(pi * 4 + k) * 2 + 1] = NT[k];
+        chosen[(pi * 5 + k) * 2] = G[k];
+        chosen[(pi * 5 + k) * 2 + 1] = NT[k];
       }
+      chosen[(pi * 5 + 4) * 2] = t->block_nbuf[pi] == 2 ? 2 : 1;
+      chosen[(pi * 5 + 4) * 2 + 1] = 0;
     }
   }
   return GIEM_OK;
@@ -619,6 +654,15 @@ int giem_set_fft_shape(giem_handle *t, uint32_t prec, const int32_t *shape) {
     t->fft_g[pi][k] = shape[2 * k];
     t->fft_nt[pi][k] = shape[2 * k + 1];
   }
+  return GIEM_OK;
+}
+
+int giem_set_block_buffers(giem_handle *t, uint32_t prec, int32_t nbuf) {
+  if (!t || prec > PREC_FP32 || nbuf < 0 || nbuf > 2) {
+    set_error("giem_set_block_buffers: bad argument (nbuf 0, 1 or 2)");
+    return GIEM_EINVAL;
+  }
+  t->block_nbuf[prec == PREC_FP32 ? 1 : 0] = nbuf;
   return GIEM_OK;
 }
 

@@ -70,6 +70,9 @@ struct giem_handle {
   // y forward, y inverse, x inverse): sequences per workgroup and threads per
   // workgroup, set by giem_tune; 0 selects the built-in choice
   int fft_g[2][4] = {}, fft_nt[2][4] = {};
+  // register sets of prefetched points in the block product per precision
+  // (1 or 2), set by giem_tune; 0 selects the built-in choice
+  int block_nbuf[2] = {};
   // stage profiling (giem_profile): 6 events per recorded apply
   bool prof = false;
   std::vector<hipEvent_t> prof_ev;

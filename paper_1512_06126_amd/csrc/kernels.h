@@ -35,8 +35,10 @@ hipError_t launch_fft_x_inv(int prec, const VecPtrs32 &ptrs, const c128 *sd, con
                             int nthr, const FftDesc &fd, const void *tw, double scale,
                             hipStream_t s);
 // out-of-place: sin and sout are two spectra buffers; plan from block_plan(nz)
+// nbuf: register sets of prefetched points in the pipelined kernel (1 or 2)
 hipError_t launch_block(int prec, const void *tab, const void *sin, void *sout,
-                        const unsigned *plan, int nx, int ny, int nz, int R, hipStream_t s);
+                        const unsigned *plan, int nx, int ny, int nz, int R, int nbuf,
+                        hipStream_t s);
 std::vector<unsigned> block_plan(int nz);
 
 // table set-up (kernels_setup.hip)

@@ -250,7 +250,7 @@ __device__ __forceinline__ float flip_sign(float x, unsigned m) {
 // with its halves swapped and the sign of the first half flipped.
 template <typename T, int NS>
 __global__ void __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(3, 3)))
-k_block_pipe(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
+k_block_pipe1(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
              cplx<T> *__restrict__ sout, int nx, int ny, int nz, int R, int nct) {
   typedef Mfma<T> M;
   typedef T v2 __attribute__((ext_vector_type(2)));
@@ -446,6 +446,220 @@ k_block_pipe(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
   }
 }
 
+
+// The same with NB register sets of prefetched points (used with NB = 2):
+// the loads of point p + 2 grid are in flight while point p + grid is staged
+// into LDS, so the memory pipe does not idle during staging.  It takes more
+// registers, so the one-set kernel above is kept and the faster of the two
+// is chosen per handle and precision (giem_tune).
+template <typename T, int NS, int NB>
+__global__ void __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(3, 3)))
+k_block_pipe(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
+             cplx<T> *__restrict__ sout, int nx, int ny, int nz, int R, int nct) {
+  typedef Mfma<T> M;
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  constexpr int HS = NS / 2;  // k-steps per half
+  constexpr int kpad = 4 * NS;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int E = 2 * nz * (2 * nz + 1);
+  const int Es = E + 2 * nz;  // padded rows of the full blocks; entry Es is zero
+  const int p3 = 3 * nz, tri = nz * (nz + 1) / 2;
+  const int nrt = (p3 + 15) >> 4;
+  v2 *Qv = reinterpret_cast<v2 *>(lds_raw);
+  T *Bs = reinterpret_cast<T *>(Qv + Es + 2);          // [nct][kpad][16]
+  T *Red = Bs + (size_t)nct * kpad * 16;                 // [nrt][4][64] partial sums
+  const int npts = (nx + 1) * (ny + 1);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int kk0 = lane >> 4, j = lane & 15, part = j >> 3;
+  const int rt = wave % nrt, kh = wave / nrt;  // output tile, contraction half
+  const unsigned bmask = part ? 0u : 0x80000000u;
+  unsigned aoff[(HS + 1) / 2];
+  {
+    const int row = rt * 16 + (lane & 15);
+    const bool rowok = row < p3;
+    const int a = rowok ? row / nz : 0, iz = rowok ? row - a * nz : 0;
+#pragma unroll
+    for (int u = 0; u < HS; ++u) {
+      const int c = 4 * (kh * HS + u) + kk0;
+      unsigned w = (unsigned)Es;
+      if (rowok && c < p3) {
+        const int b = c / nz, jz = c - b * nz;
+        bool neg;
+        w = (unsigned)staged_index(a, iz, b, jz, nz, tri, neg) | (neg ? 0x8000u : 0u);
+      }
+      if (u & 1)
+        aoff[u >> 1] |= w << 16;
+      else
+        aoff[u >> 1] = w;
+    }
+  }
+  if (tid == 0) Qv[Es] = v2{(T)0, (T)0};
+  const int nxe = nct * 8 * kpad;  // input-vector elements (c, v)
+  // point-independent staging maps of this thread: LDS slot of each packed
+  // entry it carries; column v, row c (component b) and RHS of each input
+  // element, and its place in the B rows
+  int tdst[kStageRegs];
+#pragma unroll
+  for (int u = 0; u < kStageRegs; ++u) {
+    const int e = tid + u * nthr;
+    tdst[u] = e < E ? staged_of_packed(e, nz, tri) : -1;
+  }
+  int xv_[kXRegs], xc_[kXRegs], xmi_[kXRegs], xr_[kXRegs], xb_[kXRegs], xdst_[kXRegs];
+#pragma unroll
+  for (int u = 0; u < kXRegs; ++u) {
+    const int idx = u * nthr + tid;
+    const int v = idx < nxe ? idx / kpad : 1 << 20, c = idx < nxe ? idx - v * kpad : 0;
+    xv_[u] = v;
+    xc_[u] = c < p3 ? c : 0;
+    xmi_[u] = idx < nxe ? v / R : 0;
+    xr_[u] = idx < nxe ? v - (v / R) * R : 0;
+    xb_[u] = c < p3 ? c / nz : 3;  // 3: padding row
+    xdst_[u] = idx < nxe ? ((v >> 3) * kpad + c) * 16 + (v & 7) : -1;
+  }
+  v2 pre[NB][kStageRegs];
+  cplx<T> xpre[NB][kXRegs];
+  unsigned xneg[NB], xval[NB];  // mirror sign / presence of each prefetched input element
+  // loads of one point's row and input vectors into prefetch set b
+  auto prefetch = [&](int rep_, int b) __attribute__((always_inline)) {
+    const v2 *src = reinterpret_cast<const v2 *>(tab) + (size_t)rep_ * E;
+#pragma unroll
+    for (int u = 0; u < kStageRegs; ++u)
+      if (tdst[u] >= 0) pre[b][u] = src[tid + u * nthr];
+    const MirrorSet m = mirror_set(rep_, nx, ny);
+    const int V = m.n * R;
+    // the sign is applied when the element is written to LDS, so that no
+    // instruction here waits for the loads
+    // (every element is loaded, from a clamped address when it is padding,
+    // so that no register is written between the loads and their use)
+    xneg[b] = 0;
+    xval[b] = 0;
+#pragma unroll
+    for (int u = 0; u < kXRegs; ++u) {
+      const bool ok = xv_[u] < V && xb_[u] < 3;
+      int pt;
+      bool fx, fy;
+      mirror_of(m, ok ? xmi_[u] : 0, nx, ny, pt, fx, fy);
+      xpre[b][u] = sin[((size_t)pt * R + (ok ? xr_[u] : 0)) * p3 + xc_[u]];
+      if (ok && ((xb_[u] == 0 && fx) || (xb_[u] == 1 && fy))) xneg[b] |= 1u << u;
+      if (ok) xval[b] |= 1u << u;
+    }
+  };
+  const int stride = NB * (int)gridDim.x;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int r0 = (int)blockIdx.x + b * (int)gridDim.x;
+    prefetch(r0 < npts ? r0 : npts - 1, b);
+  }
+  for (int rep0 = blockIdx.x; rep0 < npts; rep0 += stride) {
+#pragma unroll
+  for (int hb = 0; hb < NB; ++hb) {
+    const int rep = rep0 + hb * (int)gridDim.x;
+    if (rep >= npts) break;
+    lds_barrier();  // every wavefront is done with the previous point
+#pragma unroll
+    for (int u = 0; u < kStageRegs; ++u)
+      if (tdst[u] >= 0) Qv[tdst[u]] = pre[hb][u];
+#pragma unroll
+    for (int u = 0; u < kXRegs; ++u) {
+      if (xdst_[u] >= 0) {
+        T *brow = Bs + xdst_[u];
+        const unsigned sm = ((xneg[hb] >> u) & 1u) ? 0x80000000u : 0u;
+        const bool ok = (xval[hb] >> u) & 1u;
+        brow[0] = ok ? flip_sign(xpre[hb][u].x, sm) : (T)0;
+        brow[8] = ok ? flip_sign(xpre[hb][u].y, sm) : (T)0;
+      }
+    }
+    const MirrorSet m = mirror_set(rep, nx, ny);
+    const int V = m.n * R;
+    // the loads of the point NB steps ahead go into the set just staged; they
+    // are issued one per k-step of the first column tile below, so that
+    // waiting for queue space overlaps the MFMAs (a clamped address past the
+    // last point: the loads are always issued)
+    const int nrep = rep + stride;
+    const bool more = nrep < npts;
+    const v2 *nsrc = reinterpret_cast<const v2 *>(tab) + (size_t)(more ? nrep : rep) * E;
+    int xaddr[kXRegs];
+    {
+      const MirrorSet mn = mirror_set(more ? nrep : rep, nx, ny);
+      const int Vn = mn.n * R;
+      xneg[hb] = 0;
+      xval[hb] = 0;
+#pragma unroll
+      for (int u = 0; u < kXRegs; ++u) {
+        const bool ok = xv_[u] < Vn && xb_[u] < 3;
+        int pt;
+        bool fx, fy;
+        mirror_of(mn, ok ? xmi_[u] : 0, nx, ny, pt, fx, fy);
+        xaddr[u] = (pt * R + (ok ? xr_[u] : 0)) * p3 + xc_[u];
+        if (ok && ((xb_[u] == 0 && fx) || (xb_[u] == 1 && fy))) xneg[hb] |= 1u << u;
+        if (ok) xval[hb] |= 1u << u;
+      }
+    }
+    lds_barrier();
+    for (int ct = 0; ct * 8 < V; ++ct) {
+      typename M::acc_t accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+      const int kb = kh * HS * 4 + kk0;  // first B row of this half
+      const T *b1p = Bs + ((size_t)ct * kpad + kb) * 16 + j;
+      const T *b2p = Bs + ((size_t)ct * kpad + kb) * 16 + (j ^ 8);
+#pragma unroll
+      for (int u = 0; u < HS; ++u) {
+        if (ct == 0 && (NB > 1 || more)) {
+          // prefetch slot u: packed entries first, then input elements
+          if (u < kStageRegs) {
+            if (tdst[u] >= 0) pre[hb][u] = nsrc[tid + u * nthr];
+          } else if (u - kStageRegs < kXRegs) {
+            xpre[hb][u - kStageRegs] = sin[xaddr[u - kStageRegs]];
+          }
+        }
+        const unsigned w = (u & 1) ? (aoff[u >> 1] >> 16) : (aoff[u >> 1] & 0xffffu);
+        const v2 q = Qv[w & 0x7fffu];
+        const unsigned qm = (w & 0x8000u) << 16;
+        const T b1 = b1p[u * 64];
+        const T b2 = flip_sign(b2p[u * 64], bmask);
+        accr = M::mma(flip_sign(q.x, qm), b1, accr);
+        acci = M::mma(flip_sign(q.y, qm), b2, acci);
+      }
+      if (ct == 0 && (NB > 1 || more)) {
+#pragma unroll
+        for (int u = HS; u < kStageRegs + kXRegs; ++u) {
+          if (u < kStageRegs) {
+            if (tdst[u] >= 0) pre[hb][u] = nsrc[tid + u * nthr];
+          } else {
+            xpre[hb][u - kStageRegs] = sin[xaddr[u - kStageRegs]];
+          }
+        }
+      }
+      if (kh == 1) {
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) Red[(rt * 4 + qq) * 64 + lane] = accr[qq] + acci[qq];
+      }
+      lds_barrier();
+      if (kh == 0) {
+        const int v = ct * 8 + (j & 7);
+        if (v < V) {
+          const int mi = v / R, r = v - mi * R;
+          int pt;
+          bool fx, fy;
+          mirror_of(m, mi, nx, ny, pt, fx, fy);
+          T *ob = reinterpret_cast<T *>(sout + ((size_t)pt * R + r) * p3);
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq) {
+            const int orow = rt * 16 + M::row(lane, qq);
+            if (orow < p3) {
+              const int oa = orow / nz;
+              const T sg = ((oa == 0 && fx) || (oa == 1 && fy)) ? (T)-1 : (T)1;
+              ob[2 * orow + part] = sg * (accr[qq] + acci[qq] + Red[(rt * 4 + qq) * 64 + lane]);
+            }
+          }
+        }
+      }
+      lds_barrier();  // Red is reused by the next column tile
+    }
+  }
+  }
+}
+
 static int lds_nct(int R) { return (4 * R + 7) / 8; }
 
 // k-steps rounded up to a multiple of 4 (the compiled variants)
@@ -479,7 +693,10 @@ hipError_t set_block_lds_limits() {
   hipError_t e = hipSuccess;
 #define GIEM_SET_ATTR(T, NS)                                                               \
   if (e == hipSuccess)                                                                     \
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_block_pipe<T, NS>),            \
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_block_pipe1<T, NS>),           \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);  \
+  if (e == hipSuccess)                                                                     \
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_block_pipe<T, NS, 2>),         \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
   GIEM_BLOCK_VARIANTS(GIEM_SET_ATTR, double)
   GIEM_BLOCK_VARIANTS(GIEM_SET_ATTR, float)
@@ -514,7 +731,7 @@ std::vector<unsigned> block_plan(int nz) {
 
 template <typename T>
 static hipError_t launch_block_t(const void *tab, const void *sin, void *sout,
-                                 const unsigned *plan, int nx, int ny, int nz, int R,
+                                 const unsigned *plan, int nx, int ny, int nz, int R, int nbuf,
                                  hipStream_t s) {
   const size_t lds = lds_bytes_t(nz, R, sizeof(cplx<T>));
   const int nthr = 64 * lds_waves(nz);
@@ -525,9 +742,14 @@ static hipError_t launch_block_t(const void *tab, const void *sin, void *sout,
     const int ns = lds_ns(nz);
 #define GIEM_LAUNCH(TT, NS)                                                             \
   if (ns == NS) {                                                                       \
-    k_block_pipe<TT, NS><<<(unsigned)grid, nthr, lds, s>>>(                              \
-        static_cast<const cplx<TT> *>(tab), static_cast<const cplx<TT> *>(sin),         \
-        static_cast<cplx<TT> *>(sout), nx, ny, nz, R, lds_nct(R));                      \
+    if (nbuf == 2)                                                                      \
+      k_block_pipe<TT, NS, 2><<<(unsigned)grid, nthr, lds, s>>>(                         \
+          static_cast<const cplx<TT> *>(tab), static_cast<const cplx<TT> *>(sin),       \
+          static_cast<cplx<TT> *>(sout), nx, ny, nz, R, lds_nct(R));                    \
+    else                                                                                \
+      k_block_pipe1<TT, NS><<<(unsigned)grid, nthr, lds, s>>>(                           \
+          static_cast<const cplx<TT> *>(tab), static_cast<const cplx<TT> *>(sin),       \
+          static_cast<cplx<TT> *>(sout), nx, ny, nz, R, lds_nct(R));                    \
     return hipGetLastError();                                                           \
   }
     GIEM_BLOCK_VARIANTS(GIEM_LAUNCH, T)
@@ -544,9 +766,10 @@ static hipError_t launch_block_t(const void *tab, const void *sin, void *sout,
 }
 
 hipError_t launch_block(int prec, const void *tab, const void *sin, void *sout,
-                        const unsigned *plan, int nx, int ny, int nz, int R, hipStream_t s) {
-  return prec == PREC_FP32 ? launch_block_t<float>(tab, sin, sout, plan, nx, ny, nz, R, s)
-                           : launch_block_t<double>(tab, sin, sout, plan, nx, ny, nz, R, s);
+                        const unsigned *plan, int nx, int ny, int nz, int R, int nbuf,
+                        hipStream_t s) {
+  return prec == PREC_FP32 ? launch_block_t<float>(tab, sin, sout, plan, nx, ny, nz, R, nbuf, s)
+                           : launch_block_t<double>(tab, sin, sout, plan, nx, ny, nz, R, nbuf, s);
 }
 
 }  // namespace giem

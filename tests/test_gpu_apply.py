@@ -109,15 +109,18 @@ def full_case():
     return m, t, x, qnn, cells
 
 
+@pytest.mark.parametrize("nbuf", [1, 2])
 @pytest.mark.parametrize("mode,prec,tol", [("A", 0, 1e-10), ("B", 0, 1e-10), ("AT", 0, 1e-10),
                                            ("B", 1, 1e-4)])
-def test_apply_full_size_sampled(lib, full_case, mode, prec, tol):
+def test_apply_full_size_sampled(lib, full_case, mode, prec, tol, nbuf):
     # The launch configuration the benchmark times (128 x 128 x 32, 2 RHS),
-    # checked at sampled output cells against the oracle's direct sum.
+    # checked at sampled output cells against the oracle's direct sum, with
+    # one and two prefetch sets in the block product.
     import torch
     m, t, x, qnn, cells = full_case
-    print(f"full-size apply mode={mode} prec={prec}", flush=True)
+    print(f"full-size apply mode={mode} prec={prec} block buffers={nbuf}", flush=True)
     h = lib.tables_import(m, [m["freq"]], t[None], flags=lib.TABLES_C64)
+    h.set_block_buffers(prec, nbuf)
     xd = to_dev(x)
     yd = torch.empty_like(xd)
     code = {"A": lib.MODE_A, "AT": lib.MODE_AT, "B": lib.MODE_B}[mode]
@@ -159,6 +162,11 @@ def test_every_fft_shape_matches_dense(lib, nx, ny, nz, nrhs):
                 assert err <= tol, (prec, g, nt, err)
                 tried += 1
         h.set_fft_shape(prec, None)
+        for nbuf in (2, 1):
+            h.set_block_buffers(prec, nbuf)
+            h.apply(xd, yd, sa, mode=lib.MODE_A, prec=prec)
+            torch.cuda.synchronize()
+            assert rel_err(yd.cpu().numpy(), ref) <= tol, (prec, nbuf)
     with pytest.raises(lib.GiemError):
         h.set_fft_shape(lib.FP64, [(8, 384)] * 4)
     chosen = h.tune(sa, nrhs=nrhs)
