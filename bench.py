@@ -95,31 +95,38 @@ def synthetic_table(model, seed=20):
 
 
 def cpu_baseline(model, table, budget_s=15.0, seed=30):
-    """The oracle's direct summation (eq. bcyl, O(N) per output cell) timed
-    on a bounded sample of output cells of the same workload."""
-    from oracle import dense, packed
+    """The oracle's three-step FFT apply (Sect. 3.3 on the CPU: scipy.fft
+    with every host core, one batched matrix product per frequency) timed on
+    whole applies of the same workload, 2 RHS, for about budget_s seconds; the
+    set-up of its unpacked spectral table is not counted (as the GPU table
+    build is not)."""
+    from oracle import dense, fft_apply
     import giem_synth as gs
     try:
         from threadpoolctl import threadpool_info
-        cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+        blas = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
     except Exception:
-        cores = 1
+        blas = 1
+    cores = max(blas, os.cpu_count() or 1)
     rng = np.random.default_rng(seed)
     nx, ny, nz = model["nx"], model["ny"], model["nz"]
     x = gs.random_vector(rng, 2, nz, ny, nx)
-    qnn = packed.full_tensor_nonneg(table, nz)
+    t_set = time.perf_counter()
+    qhat = fft_apply.spectral_blocks(table, nz)
+    d = dense.cie_diagonals(model)
+    setup_s = time.perf_counter() - t_set
     done = 0
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
-        c = (int(rng.integers(nz)), int(rng.integers(ny)), int(rng.integers(nx)))
-        dense.apply_cells(qnn, model, x, [c], "A")
+    while done == 0 or time.perf_counter() - t0 < budget_s:
+        fft_apply.apply(qhat, d, x, "A")
         done += 1
     dt = time.perf_counter() - t0
-    ncell = nx * ny * nz
-    rhs_applies_per_s = 2 * done / dt / ncell
-    return {"value": rhs_applies_per_s, "unit": "RHS-applies/s", "cores": cores, "kind": "oracle",
-            "sample": f"direct summation of {done} output cells (all 3 components, 2 RHS) of "
-                      f"the {nx}x{ny}x{nz} apply in {dt:.1f} s, scaled by {ncell} cells per apply"}
+    del qhat
+    return {"value": 2 * done / dt, "unit": "RHS-applies/s", "cores": cores, "kind": "oracle",
+            "sample": f"{done} whole applies of the {nx}x{ny}x{nz} operator to 2 RHS by the "
+                      f"oracle's three-step FFT path (scipy.fft and batched products, "
+                      f"{os.cpu_count()} host threads) in {dt:.1f} s; its spectral table "
+                      f"set-up ({setup_s:.1f} s) not counted"}
 
 
 def main():

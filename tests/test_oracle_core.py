@@ -215,3 +215,20 @@ def test_tensor_row_is_a_row_of_the_full_tensor():
     full = packed.full_tensor_nonneg(t, nz)
     for iz in range(nz):
         assert np.array_equal(packed.tensor_row(t, nz, iz), full[:, :, :, :, iz, :])
+
+
+@pytest.mark.parametrize("nx,ny,nz,R", [(1, 1, 1, 1), (5, 4, 3, 2), (7, 3, 2, 1), (6, 9, 2, 2)])
+@pytest.mark.parametrize("mode", ["A", "AT", "B"])
+def test_fft_apply_equals_dense_product(nx, ny, nz, R, mode):
+    # the three-step FFT apply (Sect. 3.3) is the dense block-Toeplitz
+    # product (eq. bcyl) up to rounding
+    from oracle import fft_apply
+    m = _small_model(seed=50 + nx + ny, nx=nx, ny=ny, nz=nz)
+    rng = np.random.default_rng(51)
+    t = gs.random_packed_table(rng, nx, ny, nz, decay=0.1)
+    B = dense.dense_from_packed(t, m)
+    d = dense.cie_diagonals(m)
+    x = gs.random_vector(rng, R, nz, ny, nx)
+    ref = dense.apply_direct(B, d, x, mode)
+    got = fft_apply.apply(fft_apply.spectral_blocks(t, nz), d, x, mode)
+    assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
