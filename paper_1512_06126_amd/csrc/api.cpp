@@ -390,6 +390,8 @@ static int finish_handle(giem_handle *t, hipStream_t s) {
   GIEM_HIP(hipHostMalloc(&t->red_host, kMaxSys * 65 * sizeof(c128), 0), "hipHostMalloc");
   GIEM_HIP(hipMalloc(&t->coef_dev, kMaxSys * 65 * sizeof(c128)), "hipMalloc");
   GIEM_HIP(hipHostMalloc(&t->coef_host, kMaxSys * 65 * sizeof(c128), 0), "hipHostMalloc");
+  GIEM_HIP(hipMalloc(&t->gs_scale_dev, kMaxSys * 65 * sizeof(double)), "hipMalloc");
+  GIEM_HIP(hipHostMalloc(&t->gs_scale_host, kMaxSys * 65 * sizeof(double), 0), "hipHostMalloc");
   GIEM_TRY(ensure_spec_ws(t, 2, PREC_FP64));
   return upload_spatial(t, s);
 }
@@ -411,11 +413,12 @@ void giem_free(giem_handle *t) {
   }
   void *dev[] = {t->px.tw64, t->px.tw32, t->py.tw64, t->py.tw32, t->cs_x, t->cs_y, t->bplan,
                  t->sb_lev, t->vol_lev, t->sroot_lev, t->diag, t->spec_ws, t->red_part,
-                 t->red_out, t->coef_dev, t->basis, t->vec_ws};
+                 t->red_out, t->coef_dev, t->basis, t->vec_ws, t->gs_scale_dev};
   for (void *p : dev)
     if (p) hipFree(p);
   if (t->red_host) hipHostFree(t->red_host);
   if (t->coef_host) hipHostFree(t->coef_host);
+  if (t->gs_scale_host) hipHostFree(t->gs_scale_host);
   for (hipEvent_t e : t->prof_ev) hipEventDestroy(e);
   delete t;
 }

@@ -60,6 +60,8 @@ struct giem_handle {
   void *red_host = nullptr;  // pinned host mirror of red_out
   void *coef_dev = nullptr;  // c128 [kMaxSys][65] coefficients for updates
   void *coef_host = nullptr; // pinned
+  void *gs_scale_dev = nullptr;   // double [kMaxSys][65]: 1 / |V_i|^2 of the basis
+  void *gs_scale_host = nullptr;  // pinned mirror
   // solver workspace (grown on demand)
   void *basis = nullptr;
   size_t basis_bytes = 0;

@@ -87,13 +87,14 @@ hipError_t launch_dots(const DotArgs &a, int nrhs, int nb, size_t n, int nz, int
                        const double *wlev, c128 *part, c128 *out, hipStream_t s);
 hipError_t launch_dots(const DotArgs32 &a, int nrhs, int nb, size_t n, int nz, int plane,
                        const double *wlev, c128 *part, c128 *out, hipStream_t s);
-// w -= sum_i h[r][i] V_i, and ||w||^2 reduced into nrm[r] (real in .x)
+// w -= sum_i f[r][i] h[r][i] V_i (f = hscale[r * sstride + i], or 1 when
+// hscale is null), and ||w||^2 reduced into nrm[r] (real in .x)
 hipError_t launch_update(const DotArgs &a, int nrhs, int nb, size_t n, int nz, int plane,
-                         const double *wlev, const c128 *h, int hstride, c128 *part,
-                         c128 *nrm, hipStream_t s);
+                         const double *wlev, const c128 *h, int hstride, const double *hscale,
+                         int sstride, c128 *part, c128 *nrm, hipStream_t s);
 hipError_t launch_update(const DotArgs32 &a, int nrhs, int nb, size_t n, int nz, int plane,
-                         const double *wlev, const c128 *h, int hstride, c128 *part,
-                         c128 *nrm, hipStream_t s);
+                         const double *wlev, const c128 *h, int hstride, const double *hscale,
+                         int sstride, c128 *part, c128 *nrm, hipStream_t s);
 // dst[r] = src[r] * scal[r] (complex scalars from the host)
 hipError_t launch_scale(c128 *const *dst, const c128 *const *src, const c128 *scal, int nrhs,
                         size_t n, hipStream_t s);

@@ -10,7 +10,6 @@
 namespace giem {
 
 constexpr int kRedBlocks = 480;  // workgroups of the first reduction stage
-constexpr int kSlots = 8;        // inner products per workgroup pass
 
 int dot_partials_per_rhs() { return kRedBlocks; }
 
@@ -48,10 +47,16 @@ __device__ __forceinline__ double weight_of(size_t k, int plane, int nz, const d
 }
 
 // part[r][slot][block]: slot s < nb: sum wt w conj(V_s); slot nb: sum wt |w|^2
-template <typename VT>
+// SLOTS inner products per workgroup pass (blockIdx.z selects the group).
+// Eight: w is re-read once per group of eight basis vectors, but wider groups
+// need more registers, and the lower occupancy cost more than the re-reads
+// (measured on the 128 x 128 x 32 solve).
+constexpr int kSlots = 8;
+template <typename VT, int SLOTS>
 __global__ void __launch_bounds__(256)
 k_dots(DotArgsT<VT> a, int nb, size_t n, int nz, int plane, const double *__restrict__ wlev,
        c128 *__restrict__ part) {
+  constexpr int kSlots = SLOTS;
   __shared__ double red[8];
   const int r = blockIdx.y;
   const int s0 = blockIdx.z * kSlots;
@@ -108,8 +113,8 @@ static hipError_t launch_dots_t(const DotArgsT<VT> &a, int nrhs, int nb, size_t 
                                 int plane, const double *wlev, c128 *part, c128 *out,
                                 hipStream_t s) {
   const int nslots = nb + 1;
-  dim3 grid(kRedBlocks, nrhs, (nslots + kSlots - 1) / kSlots);
-  k_dots<VT><<<grid, 256, 0, s>>>(a, nb, n, nz, plane, wlev, part);
+  k_dots<VT, kSlots><<<dim3(kRedBlocks, nrhs, (nslots + kSlots - 1) / kSlots), 256, 0, s>>>(
+      a, nb, n, nz, plane, wlev, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_reduce<<<dim3(nslots, nrhs), 256, 0, s>>>(part, kRedBlocks, nslots, out);
@@ -128,13 +133,18 @@ hipError_t launch_dots(const DotArgs32 &a, int nrhs, int nb, size_t n, int nz, i
 template <typename VT>
 __global__ void __launch_bounds__(256)
 k_update(DotArgsT<VT> a, int nb, size_t n, int nz, int plane, const double *__restrict__ wlev,
-         const c128 *__restrict__ h, int hstride, c128 *__restrict__ part) {
+         const c128 *__restrict__ h, int hstride, const double *__restrict__ hscale,
+         int sstride, c128 *__restrict__ part) {
   __shared__ double red[8];
   __shared__ c128 hs[64];
   const int r = blockIdx.y;
   VT *w = const_cast<VT *>(a.w[r]);
   const VT *V = a.basis[r];
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) hs[i] = h[(size_t)r * hstride + i];
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    const c128 hv = h[(size_t)r * hstride + i];
+    const double f = hscale ? hscale[(size_t)r * sstride + i] : 1.0;
+    hs[i] = mk<double>(hv.x * f, hv.y * f);
+  }
   __syncthreads();
   double acc = 0.0;
   for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n;
@@ -156,24 +166,27 @@ k_update(DotArgsT<VT> a, int nb, size_t n, int nz, int plane, const double *__re
 template <typename VT>
 static hipError_t launch_update_t(const DotArgsT<VT> &a, int nrhs, int nb, size_t n, int nz,
                                   int plane, const double *wlev, const c128 *h, int hstride,
-                                  c128 *part, c128 *nrm, hipStream_t s) {
+                                  const double *hscale, int sstride, c128 *part, c128 *nrm,
+                                  hipStream_t s) {
   if (nb > 64) return hipErrorInvalidValue;
   dim3 grid(kRedBlocks, nrhs);
-  k_update<VT><<<grid, 256, 0, s>>>(a, nb, n, nz, plane, wlev, h, hstride, part);
+  k_update<VT><<<grid, 256, 0, s>>>(a, nb, n, nz, plane, wlev, h, hstride, hscale, sstride, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_reduce<<<dim3(1, nrhs), 256, 0, s>>>(part, kRedBlocks, 1, nrm);
   return hipGetLastError();
 }
 hipError_t launch_update(const DotArgs &a, int nrhs, int nb, size_t n, int nz, int plane,
-                         const double *wlev, const c128 *h, int hstride, c128 *part, c128 *nrm,
-                         hipStream_t s) {
-  return launch_update_t(a, nrhs, nb, n, nz, plane, wlev, h, hstride, part, nrm, s);
+                         const double *wlev, const c128 *h, int hstride, const double *hscale,
+                         int sstride, c128 *part, c128 *nrm, hipStream_t s) {
+  return launch_update_t(a, nrhs, nb, n, nz, plane, wlev, h, hstride, hscale, sstride, part, nrm,
+                         s);
 }
 hipError_t launch_update(const DotArgs32 &a, int nrhs, int nb, size_t n, int nz, int plane,
-                         const double *wlev, const c128 *h, int hstride, c128 *part, c128 *nrm,
-                         hipStream_t s) {
-  return launch_update_t(a, nrhs, nb, n, nz, plane, wlev, h, hstride, part, nrm, s);
+                         const double *wlev, const c128 *h, int hstride, const double *hscale,
+                         int sstride, c128 *part, c128 *nrm, hipStream_t s) {
+  return launch_update_t(a, nrhs, nb, n, nz, plane, wlev, h, hstride, hscale, sstride, part, nrm,
+                         s);
 }
 
 template <typename VT>

@@ -240,6 +240,14 @@ static int gmres(giem_handle *t, const std::vector<int> &fq, int nrhs, const VT 
   bool x_zero = gp.x_zero;
   int iters = 0;
   std::vector<std::vector<cd>> H(nrhs), cs(nrhs), sn(nrhs), g(nrhs);
+  // The basis vectors are stored unnormalised, V_i = |V_i| v_i, with the
+  // norms kept here: h_ij = <V_i, A V_j> / (|V_i| |V_j|), the update
+  // subtracts (<V_i, w> / |V_i|^2) V_i, and x += sum (y_i / |V_i|) V_i.  This
+  // saves a scaling pass over every new basis vector.
+  std::vector<std::vector<double>> vn(nrhs);
+  double *sdev = static_cast<double *>(t->gs_scale_dev);
+  double *shost = static_cast<double *>(t->gs_scale_host);
+  constexpr int kSStride = 65;
   c128 *hdev = static_cast<c128 *>(t->red_out);
   c128 *ndev = static_cast<c128 *>(t->coef_dev);
   c128 *part = static_cast<c128 *>(t->red_part);
@@ -287,10 +295,8 @@ static int gmres(giem_handle *t, const std::vector<int> &fq, int nrhs, const VT 
       sn[r].assign(m, 0.0);
       g[r].assign(m + 1, 0.0);
       g[r][0] = beta[q];
-      const c128 f = mk<double>(1.0 / beta[q], 0.0);
-      VT *dst = V(r, 0);
-      const VT *src = V(r, 0);
-      GIEM_HIP(launch_scale(&dst, &src, &f, 1, n, s), "scale");
+      vn[r].assign(m + 1, 0.0);
+      vn[r][0] = beta[q];
     }
     if (cyc.empty()) break;
     ++res.restarts;
@@ -312,6 +318,12 @@ static int gmres(giem_handle *t, const std::vector<int> &fq, int nrhs, const VT 
       // (cancellation of more than a factor 10)
       std::vector<std::vector<cd>> hcol(na, std::vector<cd>(j + 1, 0.0));
       std::vector<double> nw0(na, 0.0), nw1(na, 0.0);
+      for (int q = 0; q < na; ++q)
+        for (int i = 0; i <= j; ++i)
+          shost[(size_t)q * kSStride + i] = 1.0 / (vn[running[q]][i] * vn[running[q]][i]);
+      GIEM_HIP(hipMemcpyAsync(sdev, shost, (size_t)na * kSStride * sizeof(double),
+                              hipMemcpyHostToDevice, s),
+               "copy basis scales");
       for (int pass = 0; pass < 2; ++pass) {
         const int nb = j + 1;
         for (int q0 = 0; q0 < na; q0 += kMaxRhs) {
@@ -323,7 +335,8 @@ static int gmres(giem_handle *t, const std::vector<int> &fq, int nrhs, const VT 
           }
           c128 *hq = hdev + (size_t)q0 * (nb + 1);
           GIEM_HIP(launch_dots(da, nq, nb, n, t->nz, plane, wlev, part, hq, s), "dots");
-          GIEM_HIP(launch_update(da, nq, nb, n, t->nz, plane, wlev, hq, nb + 1, part, ndev + q0, s),
+          GIEM_HIP(launch_update(da, nq, nb, n, t->nz, plane, wlev, hq, nb + 1,
+                                 sdev + (size_t)q0 * kSStride, kSStride, part, ndev + q0, s),
                    "update");
         }
         GIEM_HIP(hipMemcpyAsync(hhost, hdev, (size_t)na * (nb + 1) * sizeof(c128), hipMemcpyDeviceToHost, s), "copy h");
@@ -331,8 +344,10 @@ static int gmres(giem_handle *t, const std::vector<int> &fq, int nrhs, const VT 
         GIEM_HIP(hipStreamSynchronize(s), "sync");
         bool again = false;
         for (int q = 0; q < na; ++q) {
+          const std::vector<double> &nq_ = vn[running[q]];
           for (int i = 0; i < nb; ++i)
-            hcol[q][i] += cd(hhost[(size_t)q * (nb + 1) + i].x, hhost[(size_t)q * (nb + 1) + i].y);
+            hcol[q][i] += cd(hhost[(size_t)q * (nb + 1) + i].x, hhost[(size_t)q * (nb + 1) + i].y) /
+                          (nq_[i] * nq_[j]);
           if (pass == 0) nw0[q] = hhost[(size_t)q * (nb + 1) + nb].x;
           nw1[q] = std::max(chost[q].x, 0.0);
           if (nw1[q] < kReorthDrop * nw0[q]) again = true;
@@ -343,7 +358,9 @@ static int gmres(giem_handle *t, const std::vector<int> &fq, int nrhs, const VT 
       std::vector<int> still;
       for (int q = 0; q < na; ++q) {
         const int r = running[q];
-        const double hn = std::sqrt(nw1[q]);
+        const double wn = std::sqrt(nw1[q]);  // |V_{j+1}|
+        const double hn = wn / vn[r][j];
+        vn[r][j + 1] = wn;
         std::vector<cd> &Hr = H[r];
         auto Hc = [&](int i) -> cd & { return Hr[(size_t)i * m + j]; };
         for (int i = 0; i <= j; ++i) Hc(i) = hcol[q][i];
@@ -372,12 +389,6 @@ static int gmres(giem_handle *t, const std::vector<int> &fq, int nrhs, const VT 
         g[r][j] = c * g[r][j];
         jlen[r] = j + 1;
         const double est = std::abs(g[r][j + 1]);
-        if (hn > 0.0) {
-          const c128 f = mk<double>(1.0 / hn, 0.0);
-          VT *dst = V(r, j + 1);
-          const VT *src = V(r, j + 1);
-          GIEM_HIP(launch_scale(&dst, &src, &f, 1, n, s), "scale");
-        }
         if (est > gp.tol * normb[r] && hn > 0.0) still.push_back(r);
       }
       running = still;
@@ -393,7 +404,10 @@ static int gmres(giem_handle *t, const std::vector<int> &fq, int nrhs, const VT 
         y[i] = acc / H[r][(size_t)i * m + i];
       }
       c128 *yh = static_cast<c128 *>(t->coef_host);
-      for (int i = 0; i < k; ++i) yh[i] = mk<double>(y[i].real(), y[i].imag());
+      for (int i = 0; i < k; ++i) {
+        const cd yi = y[i] / vn[r][i];
+        yh[i] = mk<double>(yi.real(), yi.imag());
+      }
       GIEM_HIP(hipMemcpyAsync(t->coef_dev, yh, k * sizeof(c128), hipMemcpyHostToDevice, s), "copy y");
       LinArgsT<VT> la{};
       la.x[0] = x[r];
