@@ -176,3 +176,25 @@ def test_every_fft_shape_matches_dense(lib, nx, ny, nz, nrhs):
     assert all(nt in (256, 512) and g >= 1 for g, nt in chosen["fp64"] + chosen["fp32"])
     print(f"{nx}x{ny}x{nz}: {tried} shapes; tuned {chosen}", flush=True)
     h.close()
+
+
+@pytest.mark.parametrize("nx,ny,nz,nrhs", [(4, 3, 40, 2), (3, 2, 32, 8), (2, 3, 33, 1)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 2e-5)])
+def test_apply_gather_block_product(lib, nx, ny, nz, nrhs, prec, tol):
+    # shapes whose packed row and input fragments do not fit the pipelined
+    # kernel (more than 32 layers, or 8 right-hand sides at 32 layers) take
+    # the gather kernel; same bar against the dense product
+    import torch
+    m, t, rng = _case(nx, ny, nz, 500 + nz + nrhs)
+    h = lib.tables_import(m, [m["freq"]], t[None], flags=lib.TABLES_C64)
+    B = dense.dense_from_packed(t, m)
+    d = dense.cie_diagonals(m)
+    x = gs.random_vector(rng, nrhs, nz, ny, nx)
+    ref = dense.apply_direct(B, d, x, "A")
+    xd = to_dev(x)
+    yd = torch.empty_like(xd)
+    h.apply(xd, yd, to_dev(m["sigma_a"]), mode=lib.MODE_A, prec=prec)
+    torch.cuda.synchronize()
+    err = rel_err(yd.cpu().numpy(), ref)
+    h.close()
+    assert err <= tol, err
