@@ -184,6 +184,8 @@ int giem_profile(giem_handle *t, int32_t enable);
      chosen:  host int32 [2][5][2] or NULL: per precision (0 = FP64,
               1 = FP32) the (sequences, threads) of the four passes, then
               (register sets, 0) of the block product, as now in effect.
+   The choice is also kept for the process and given to handles created
+   later for the same grid (Nx, Ny, Nz) on the same device.
    Allocates and frees two vectors of nrhs right-hand sides; synchronises.
    Errors: EINVAL, ENOMEM, EHIP. */
 int giem_tune(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs, void *stream,

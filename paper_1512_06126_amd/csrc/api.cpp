@@ -6,6 +6,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <algorithm>
 
 #include "handle.h"
@@ -348,6 +350,36 @@ static int create_handle(const giem_model *m, int nfreq, const double *freq, uin
   return GIEM_OK;
 }
 
+// Launch shapes chosen by giem_tune, kept for the process and given to
+// handles created later for the same grid on the same device.
+struct TunedShapes {
+  int fft_g[2][4], fft_nt[2][4], block_nbuf[2];
+};
+static std::mutex g_tuned_mu;
+static std::map<std::array<int, 4>, TunedShapes> g_tuned;
+
+static std::array<int, 4> tuned_key(const giem_handle *t) {
+  return {t->device, t->nx, t->ny, t->nz};
+}
+
+static void remember_tuned(const giem_handle *t) {
+  TunedShapes e;
+  std::memcpy(e.fft_g, t->fft_g, sizeof(e.fft_g));
+  std::memcpy(e.fft_nt, t->fft_nt, sizeof(e.fft_nt));
+  std::memcpy(e.block_nbuf, t->block_nbuf, sizeof(e.block_nbuf));
+  std::lock_guard<std::mutex> lk(g_tuned_mu);
+  g_tuned[tuned_key(t)] = e;
+}
+
+static void recall_tuned(giem_handle *t) {
+  std::lock_guard<std::mutex> lk(g_tuned_mu);
+  auto it = g_tuned.find(tuned_key(t));
+  if (it == g_tuned.end()) return;
+  std::memcpy(t->fft_g, it->second.fft_g, sizeof(t->fft_g));
+  std::memcpy(t->fft_nt, it->second.fft_nt, sizeof(t->fft_nt));
+  std::memcpy(t->block_nbuf, it->second.block_nbuf, sizeof(t->block_nbuf));
+}
+
 static int finish_handle(giem_handle *t, hipStream_t s) {
   static bool lds_set = false;
   if (!lds_set) {
@@ -359,6 +391,7 @@ static int finish_handle(giem_handle *t, hipStream_t s) {
     set_error("Nz too large for the packed block offsets");
     return GIEM_EINVAL;
   }
+  recall_tuned(t);
   GIEM_TRY(make_plan(2 * t->nx, t->px));
   GIEM_TRY(make_plan(2 * t->ny, t->py));
   GIEM_TRY(make_cs(t->nx, &t->cs_x));
@@ -620,6 +653,7 @@ int giem_tune(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs, 
     }
     t->block_nbuf[pi] = bnb;
   }
+  remember_tuned(t);
   if (chosen) {
     for (int pi = 0; pi < 2; ++pi) {
       int G[4], NT[4];
