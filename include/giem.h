@@ -109,9 +109,11 @@ typedef struct {
 /*
  * giem_tables -- compute the Galerkin coefficient tables B_n^m (Sect. 3.2,
  * Appendices A-C) for nfreq frequencies in FP64 and keep their packed spectra
- * (Sect. 3.3) on the device.  The vertical functions and the geometry-only
- * quadrature matrices are built on the host; the Hankel and horizontal
- * contractions run as FP64 GEMMs on the device.  Synchronises the stream.
+ * (Sect. 3.3) on the device, together with the packed spatial tables
+ * (Nx Ny 2Nz(2Nz+1) complex128 per frequency, read by giem_tables_export).
+ * The vertical functions and the geometry-only quadrature matrices are built
+ * on the host; the Hankel and horizontal contractions run as FP64 GEMMs on
+ * the device.  Synchronises the stream.
  *   freq_hz: host [nfreq], > 0.  flags: GIEM_TABLES_C64 or 0.
  *   *out receives a new handle.
  * Errors: EINVAL (shapes), EDOMAIN (a cell straddles an interface,

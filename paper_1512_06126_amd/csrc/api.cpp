@@ -223,21 +223,19 @@ int apply_core(giem_handle *t, int ifreq, int nrhs, const VecPtrs32 &p, unsigned
   return apply_core_t(t, ifreq, nrhs, p, mode, prec, s, stage_ms);
 }
 
-// Spatial packed tables (host) -> device -> packed spectra (+ c64 copy).
+// Packed spatial tables (device, kept for giem_tables_export) -> packed
+// spectra (+ c64 copy).
 int upload_spatial(giem_handle *t, hipStream_t s) {
   const int nx = t->nx, ny = t->ny, nz = t->nz, E = t->E();
-  const size_t nsp = (size_t)nx * ny * E, nsc = (size_t)(nx + 1) * (ny + 1) * E;
-  void *dsp = nullptr, *tmp = nullptr;
+  const size_t nsc = (size_t)(nx + 1) * (ny + 1) * E;
+  void *tmp = nullptr;
   int rc = GIEM_OK;
-  rc = check_hip(hipMalloc(&dsp, nsp * sizeof(c128)), "hipMalloc spatial");
-  if (rc == GIEM_OK) rc = check_hip(hipMalloc(&tmp, (size_t)ny * (nx + 1) * E * sizeof(c128)), "hipMalloc tmp");
+  rc = check_hip(hipMalloc(&tmp, (size_t)ny * (nx + 1) * E * sizeof(c128)), "hipMalloc tmp");
   for (size_t q = 0; rc == GIEM_OK && q < t->f.size(); ++q) {
     FreqTables &ft = t->f[q];
-    rc = check_hip(hipMemcpyAsync(dsp, ft.spatial.data(), nsp * sizeof(c128), hipMemcpyHostToDevice, s),
-                   "copy spatial table");
     if (rc == GIEM_OK) rc = check_hip(hipMalloc(&ft.spec64, nsc * sizeof(c128)), "hipMalloc spectra");
     if (rc == GIEM_OK)
-      rc = check_hip(launch_spectral_x(static_cast<c128 *>(dsp), static_cast<c128 *>(tmp),
+      rc = check_hip(launch_spectral_x(static_cast<const c128 *>(ft.spatial), static_cast<c128 *>(tmp),
                                        static_cast<c128 *>(t->cs_x), nx, ny, nz, s), "spectral x");
     if (rc == GIEM_OK)
       rc = check_hip(launch_spectral_y(static_cast<c128 *>(tmp), static_cast<c128 *>(ft.spec64),
@@ -250,7 +248,6 @@ int upload_spatial(giem_handle *t, hipStream_t s) {
     }
     if (rc == GIEM_OK) rc = check_hip(hipStreamSynchronize(s), "sync");
   }
-  if (dsp) hipFree(dsp);
   if (tmp) hipFree(tmp);
   return rc;
 }
@@ -440,6 +437,7 @@ const char *giem_last_error(void) { return get_error().c_str(); }
 void giem_free(giem_handle *t) {
   if (!t) return;
   for (auto &ft : t->f) {
+    if (ft.spatial) hipFree(ft.spatial);
     if (ft.spec64) hipFree(ft.spec64);
     if (ft.spec32) hipFree(ft.spec32);
     if (ft.rec_kernel) hipFree(ft.rec_kernel);
@@ -467,8 +465,18 @@ int giem_tables_import(const giem_model *model, int32_t nfreq, const double *fre
   GIEM_TRY(create_handle(model, nfreq, freq_hz, flags, &t));
   const size_t nsp = (size_t)t->nx * t->ny * t->E();
   const cd *src = static_cast<const cd *>(host_packed_spatial);
-  for (int q = 0; q < nfreq; ++q) t->f[q].spatial.assign(src + q * nsp, src + (q + 1) * nsp);
-  int rc = finish_handle(t, static_cast<hipStream_t>(stream));
+  int rc = GIEM_OK;
+  for (int q = 0; q < nfreq && rc == GIEM_OK; ++q) {
+    rc = check_hip(hipMalloc(&t->f[q].spatial, nsp * sizeof(c128)), "hipMalloc spatial table");
+    if (rc == GIEM_OK)
+      rc = check_hip(hipMemcpy(t->f[q].spatial, src + q * nsp, nsp * sizeof(c128), hipMemcpyHostToDevice),
+                     "copy spatial table");
+  }
+  if (rc < 0) {
+    giem_free(t);
+    return rc;
+  }
+  rc = finish_handle(t, static_cast<hipStream_t>(stream));
   if (rc < 0) {
     giem_free(t);
     return rc;
@@ -500,8 +508,11 @@ int giem_tables_export(const giem_handle *t, int32_t ifreq, void *host_packed_sp
     set_error("giem_tables_export: bad handle, frequency index or pointer");
     return GIEM_EINVAL;
   }
-  const auto &sp = t->f[ifreq].spatial;
-  std::memcpy(host_packed_spatial, sp.data(), sp.size() * sizeof(cd));
+  const size_t nsp = (size_t)t->nx * t->ny * t->E();
+  if (check_hip(hipMemcpy(host_packed_spatial, t->f[ifreq].spatial, nsp * sizeof(c128),
+                          hipMemcpyDeviceToHost),
+                "copy spatial table"))
+    return GIEM_EHIP;
   return GIEM_OK;
 }
 

@@ -25,7 +25,7 @@ struct FreqTables {
   double freq = 0.0;
   void *spec64 = nullptr;      // c128 [(Ny+1)(Nx+1)][E] packed spectra
   void *spec32 = nullptr;      // c64 copy (GIEM_TABLES_C64)
-  std::vector<cd> spatial;     // packed spatial table [Ny][Nx][E] (host)
+  void *spatial = nullptr;     // c128 [Ny][Nx][E] packed spatial table (device)
   void *rec_kernel = nullptr;  // receiver kernels (giem_fields), built on first use
 };
 
@@ -100,7 +100,7 @@ int apply_core(giem_handle *t, int ifreq, int nrhs, const VecPtrs32 &p, unsigned
 int upload_spatial(giem_handle *t, hipStream_t s);
 int plane_wave_levels(const giem_handle *t, double freq, std::vector<cd> &en_lev,
                       std::vector<cd> &hsurf);
-// packed spatial tables of every frequency of the handle (t->f[q].spatial)
+// packed spatial tables of every frequency of the handle (t->f[q].spatial, device)
 int compute_tables(giem_handle *t, hipStream_t s);
 // receiver kernels of frequency ifreq (device, owned by the caller)
 int compute_receiver_kernels(giem_handle *t, int ifreq, void **out, hipStream_t s);

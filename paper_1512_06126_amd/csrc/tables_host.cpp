@@ -881,12 +881,11 @@ int compute_tables(giem_handle *t, hipStream_t s) {
   std::vector<double> Wt, Wt_reg, Mt;
   hankel_weights(g, Wt, Wt_reg);
   spatial_matrix(t, g, Mt);
-  DevBuf dW, dWr, dM, dG, dH, dc0, dc1, dc2, dout;
+  DevBuf dW, dWr, dM, dG, dH, dc0, dc1, dc2;
   if (dW.alloc(Wt.size() * 8) != hipSuccess || dWr.alloc(Wt_reg.size() * 8) != hipSuccess ||
       dM.alloc(Mt.size() * 8) != hipSuccess || dG.alloc(nl * ncolc * 16) != hipSuccess ||
       dH.alloc(nr * ncolc * 16) != hipSuccess || dc0.alloc(noff * 2 * T * 16) != hipSuccess ||
-      dc1.alloc(3 * noff * T * 16) != hipSuccess || dc2.alloc(2 * noff * nz2 * 16) != hipSuccess ||
-      dout.alloc(noff * t->E() * 16) != hipSuccess) {
+      dc1.alloc(3 * noff * T * 16) != hipSuccess || dc2.alloc(2 * noff * nz2 * 16) != hipSuccess) {
     set_error("giem_tables: out of device memory");
     return GIEM_ENOMEM;
   }
@@ -924,13 +923,10 @@ int compute_tables(giem_handle *t, hipStream_t s) {
         check_hip(launch_gemm_tn(dM.d() + K_X * noff, ldm, dH.d() + 6 * T, ldg, dc2.d(), 2 * nz2,
                                  (int)(2 * noff), 2 * nz2, (int)nr, s),
                   "spatial contraction") ||
-        check_hip(launch_assemble(dc0.c(), dc1.c(), dc2.c(), dout.c(), nx, ny, nz, t->f[q].freq * 2 * kPi * kMu0, s),
-                  "table assembly"))
-      return GIEM_EHIP;
-    t->f[q].spatial.resize(noff * t->E());
-    if (check_hip(hipMemcpyAsync(t->f[q].spatial.data(), dout.p, noff * t->E() * 16,
-                                 hipMemcpyDeviceToHost, s),
-                  "download table") ||
+        check_hip(hipMalloc(&t->f[q].spatial, noff * t->E() * 16), "hipMalloc spatial table") ||
+        check_hip(launch_assemble(dc0.c(), dc1.c(), dc2.c(), static_cast<c128 *>(t->f[q].spatial),
+                                  nx, ny, nz, t->f[q].freq * 2 * kPi * kMu0, s),
+                  "table assembly") ||
         check_hip(hipStreamSynchronize(s), "table build"))
       return GIEM_EHIP;
   }
