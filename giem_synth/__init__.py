@@ -171,6 +171,16 @@ def config_batched():
     return models, freqs
 
 
+def config_large(seed=7, freq=10.0):
+    """A grid of the size of the paper's scalability workload (Sect. 4: cubes
+    of 25 m, 118 layers of cells; 175 x 224 columns here, since 2 x 176 has
+    the prime factor 11): three-layer earth, seven blocks with conductivity
+    factors up to 3.3e4."""
+    return config_layered(175, 224, 118, 25.0, 25.0, 25.0, seed, freq, n_earth_layers=3,
+                          n_boxes=7, side_xy=(10, 60), side_z=(8, 40),
+                          max_log_contrast=float(np.log10(3.3e4)), interface_step=25.0)
+
+
 def config_gradient(seed=5):
     """64 x 64 x 16 cells of 200 x 200 x 100 m, four frequencies, a 32 x 32
     receiver lattice at the surface over every second cell centre."""
