@@ -159,6 +159,26 @@ int giem_tables_bytes(const giem_handle *t, int64_t *bytes_c128, int64_t *bytes_
 int giem_apply(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
                const void *x, void *y, uint32_t mode, uint32_t prec, void *stream);
 
+/*
+ * giem_apply_batch -- giem_apply for several frequencies of the handle at
+ * once, one launch per kernel for all of them: y[f][r] = op_{ifreqs[f]}
+ * x[f][r].  The frequencies share sigma_a (the diagonal scalings of
+ * Sect. 3.1 do not depend on frequency); the spectra of all vectors are
+ * transformed together and the block product runs over (frequency, point)
+ * pairs, each with its own table.
+ *   ifreqs:  host int32 [nf], 1 <= nf <= 16, indices of the handle's
+ *            frequencies (repeats allowed);
+ *   x, y:    device c128 [nf][nrhs][3][Nz][Ny][Nx], 1 <= nrhs <= 8,
+ *            nf * nrhs <= 32; x and y must not overlap;
+ *   sigma_a, mode, prec: as for giem_apply.
+ * The result equals nf separate giem_apply calls.  The spectra workspace
+ * grows to 2 x 4 Nx Ny x 3 Nz x 16 bytes per vector of the batch.  Never
+ * synchronises the stream.  Errors: EINVAL, EDOMAIN, ENOMEM, EHIP.
+ */
+int giem_apply_batch(giem_handle *t, int32_t nf, const int32_t *ifreqs, const void *sigma_a,
+                     int32_t nrhs, const void *x, void *y, uint32_t mode, uint32_t prec,
+                     void *stream);
+
 /* giem_apply_timed -- giem_apply with HIP events around each of the five
    kernels (x-FFT, y-FFT, block product, inverse y-FFT, inverse x-FFT); waits
    for the stream and writes their durations in ms to stage_ms[5]. */

@@ -76,6 +76,7 @@ def load():
         "giem_tables_bytes": [P, P, P],
         "giem_apply": [P, I32, P, I32, P, P, U32, U32, P],
         "giem_apply_timed": [P, I32, P, I32, P, P, U32, U32, P, P],
+        "giem_apply_batch": [P, I32, P, P, I32, P, P, U32, U32, P],
         "giem_solve": [P, I32, P, I32, P, P, P, P, P],
         "giem_solve_batch": [P, I32, P, P, I32, P, P, P, P, P],
         "giem_adjoint": [P, I32, P, I32, P, P, P, P, P, P],
@@ -103,7 +104,7 @@ def load():
 
 def exported_symbols():
     return ["giem_tables", "giem_tables_import", "giem_tables_export", "giem_tables_bytes",
-            "giem_apply", "giem_apply_timed", "giem_tune", "giem_set_fft_shape", "giem_set_block_buffers", "giem_profile", "giem_profile_read", "giem_solve", "giem_solve_batch",
+            "giem_apply", "giem_apply_timed", "giem_apply_batch", "giem_tune", "giem_set_fft_shape", "giem_set_block_buffers", "giem_profile", "giem_profile_read", "giem_solve", "giem_solve_batch",
             "giem_adjoint", "giem_fields", "giem_fields_adjoint", "giem_impedance",
             "giem_impedance_adjoint", "giem_free", "giem_last_error"]
 
@@ -176,6 +177,20 @@ class Handle:
         sa = _ptr(sigma_a) if sigma_a is not None else ctypes.c_void_p(0)
         _check(_lib.giem_apply(self._p, ifreq, sa, nrhs, _ptr(x), _ptr(y), mode, prec,
                                _stream(stream)))
+        return y
+
+    def apply_batch(self, x, y, sigma_a=None, ifreqs=None, mode=MODE_A, prec=FP64, stream=None):
+        """y[f] = op_{ifreqs[f]} x[f] for x, y of shape [nf][nrhs][3][Nz][Ny][Nx]
+        (complex128, on the device), one launch per kernel for all nf
+        frequencies; ifreqs defaults to 0 .. nf - 1."""
+        nf, nrhs = x.shape[0], x.shape[1]
+        ifr = list(range(nf)) if ifreqs is None else [int(q) for q in ifreqs]
+        if len(ifr) != nf:
+            raise ValueError("one frequency index per leading slice of x")
+        arr = (ctypes.c_int32 * nf)(*ifr)
+        sa = _ptr(sigma_a) if sigma_a is not None else ctypes.c_void_p(0)
+        _check(_lib.giem_apply_batch(self._p, nf, arr, sa, nrhs, _ptr(x), _ptr(y), mode, prec,
+                                     _stream(stream)))
         return y
 
     def apply_timed(self, x, y, sigma_a=None, mode=MODE_A, prec=FP64, ifreq=0, stream=None):

@@ -125,16 +125,29 @@ static void fft_shape(const giem_handle *t, unsigned prec, int G[4], int NT[4]) 
 }
 
 template <typename VT>
-static int apply_core_t(giem_handle *t, int ifreq, int nrhs, const VecPtrsT<VT> &p, unsigned mode,
-                        unsigned prec, hipStream_t s, double *stage_ms) {
+static int apply_core_t(giem_handle *t, int nf, const int *ifreqs, int nrhs,
+                        const VecPtrsT<VT> &p, unsigned mode, unsigned prec, hipStream_t s,
+                        double *stage_ms) {
   const int nx = t->nx, ny = t->ny, nz = t->nz;
-  FreqTables &ft = t->f[ifreq];
-  const void *tab = prec == PREC_FP32 ? ft.spec32 : ft.spec64;
-  if (!tab) {
-    set_error("complex64 tables were not requested (GIEM_TABLES_C64)");
+  if (nf < 1 || nf > kMaxFreqBatch || nrhs < 1 || nrhs > kMaxRhs || nf * nrhs > kMaxVec) {
+    set_error("apply: too many frequencies or vectors in one batched apply");
     return GIEM_EINVAL;
   }
-  GIEM_TRY(ensure_spec_ws(t, nrhs, prec));
+  TabSet tabs{};
+  for (int f = 0; f < nf; ++f) {
+    if (ifreqs[f] < 0 || ifreqs[f] >= (int)t->f.size()) {
+      set_error("apply: frequency index out of range");
+      return GIEM_EINVAL;
+    }
+    const FreqTables &ft = t->f[ifreqs[f]];
+    tabs.tab[f] = prec == PREC_FP32 ? ft.spec32 : ft.spec64;
+    if (!tabs.tab[f]) {
+      set_error("complex64 tables were not requested (GIEM_TABLES_C64)");
+      return GIEM_EINVAL;
+    }
+  }
+  const int nv = nf * nrhs;  // vectors of this apply, frequency-major
+  GIEM_TRY(ensure_spec_ws(t, nv, prec));
   const c128 *dg = static_cast<const c128 *>(t->diag);
   const size_t n = t->ncell();
   const c128 *S = dg, *R1 = dg + n, *R2 = dg + 2 * n;
@@ -144,7 +157,7 @@ static int apply_core_t(giem_handle *t, int ifreq, int nrhs, const VecPtrsT<VT> 
   } else if (mode == MODE_AT) {
     r2 = R1; r1 = R2; sd = S;
   }
-  const int rp = nrhs * 3 * nz;
+  const int rp = nv * 3 * nz;
   int G[4], NT[4];
   fft_shape(t, prec, G, NT);
   if (!block_supported(nz, nrhs)) {
@@ -170,7 +183,7 @@ static int apply_core_t(giem_handle *t, int ifreq, int nrhs, const VecPtrsT<VT> 
     ev = t->prof_ev.data() + t->prof_used;
     t->prof_used += 6;
     t->prof_meta.push_back((int)prec);
-    t->prof_meta.push_back(nrhs);
+    t->prof_meta.push_back(nv);
   }
   auto mark = [&](int i) -> int {
     if (ev) GIEM_HIP(hipEventRecord(ev[i], s), "hipEventRecord");
@@ -186,8 +199,8 @@ static int apply_core_t(giem_handle *t, int ifreq, int nrhs, const VecPtrsT<VT> 
   GIEM_HIP(launch_fft_y(prec, spa, 2 * nx, ny, rp, G[1], NT[1], t->py.d, twy, 0, s), "y-FFT");
   GIEM_TRY(mark(2));
   const int nbuf = t->block_nbuf[prec == PREC_FP32 ? 1 : 0] == 2 ? 2 : 1;
-  GIEM_HIP(launch_block(prec, tab, spa, spb, static_cast<const unsigned *>(t->bplan), nx, ny, nz,
-                        nrhs, nbuf, s),
+  GIEM_HIP(launch_block(prec, tabs, nf, spa, spb, static_cast<const unsigned *>(t->bplan), nx,
+                        ny, nz, nrhs, nbuf, s),
            "block product");
   GIEM_TRY(mark(3));
   GIEM_HIP(launch_fft_y(prec, spb, 2 * nx, ny, rp, G[2], NT[2], t->py.d, twy, 1, s),
@@ -211,7 +224,7 @@ static int apply_core_t(giem_handle *t, int ifreq, int nrhs, const VecPtrsT<VT> 
 
 int apply_core(giem_handle *t, int ifreq, int nrhs, const VecPtrs &p, unsigned mode,
                unsigned prec, hipStream_t s, double *stage_ms) {
-  return apply_core_t(t, ifreq, nrhs, p, mode, prec, s, stage_ms);
+  return apply_core_t(t, 1, &ifreq, nrhs, p, mode, prec, s, stage_ms);
 }
 
 int apply_core(giem_handle *t, int ifreq, int nrhs, const VecPtrs32 &p, unsigned mode,
@@ -220,7 +233,21 @@ int apply_core(giem_handle *t, int ifreq, int nrhs, const VecPtrs32 &p, unsigned
     set_error("complex64 vectors need the FP32 operator");
     return GIEM_EINVAL;
   }
-  return apply_core_t(t, ifreq, nrhs, p, mode, prec, s, stage_ms);
+  return apply_core_t(t, 1, &ifreq, nrhs, p, mode, prec, s, stage_ms);
+}
+
+int apply_multi(giem_handle *t, int nf, const int *ifreqs, int nrhs, const VecPtrs &p,
+                unsigned mode, unsigned prec, hipStream_t s) {
+  return apply_core_t(t, nf, ifreqs, nrhs, p, mode, prec, s, nullptr);
+}
+
+int apply_multi(giem_handle *t, int nf, const int *ifreqs, int nrhs, const VecPtrs32 &p,
+                unsigned mode, unsigned prec, hipStream_t s) {
+  if (prec != PREC_FP32) {
+    set_error("complex64 vectors need the FP32 operator");
+    return GIEM_EINVAL;
+  }
+  return apply_core_t(t, nf, ifreqs, nrhs, p, mode, prec, s, nullptr);
 }
 
 // Packed spatial tables (device, kept for giem_tables_export) -> packed
@@ -554,6 +581,40 @@ static int apply_entry(giem_handle *t, int32_t ifreq, const void *sigma_a, int32
 int giem_apply(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs, const void *x,
                void *y, uint32_t mode, uint32_t prec, void *stream) {
   return apply_entry(t, ifreq, sigma_a, nrhs, x, y, mode, prec, stream, nullptr);
+}
+
+int giem_apply_batch(giem_handle *t, int32_t nf, const int32_t *ifreqs, const void *sigma_a,
+                     int32_t nrhs, const void *x, void *y, uint32_t mode, uint32_t prec,
+                     void *stream) {
+  if (!t || nf < 1 || nf > kMaxFreqBatch || !ifreqs || nrhs < 1 || nrhs > kMaxRhs ||
+      nf * nrhs > kMaxVec || !x || !y || mode > MODE_B || prec > PREC_FP32 ||
+      (mode != MODE_B && !sigma_a)) {
+    set_error("giem_apply_batch: bad argument");
+    return GIEM_EINVAL;
+  }
+  int ifr[kMaxFreqBatch];
+  for (int f = 0; f < nf; ++f) {
+    if (ifreqs[f] < 0 || ifreqs[f] >= (int)t->f.size()) {
+      set_error("giem_apply_batch: frequency index out of range");
+      return GIEM_EINVAL;
+    }
+    ifr[f] = ifreqs[f];
+  }
+  const int nv = nf * nrhs;
+  const size_t nbytes = (size_t)nv * t->nvec() * sizeof(c128);
+  const char *xa = static_cast<const char *>(x), *ya = static_cast<const char *>(y);
+  if (xa < ya + nbytes && ya < xa + nbytes) {
+    set_error("giem_apply_batch: x and y overlap");
+    return GIEM_EINVAL;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (mode != MODE_B) GIEM_TRY(compute_diagonals(t, static_cast<const c128 *>(sigma_a), s));
+  VecPtrs p{};
+  for (int v = 0; v < nv; ++v) {
+    p.in[v] = static_cast<const c128 *>(x) + (size_t)v * t->nvec();
+    p.out[v] = static_cast<c128 *>(y) + (size_t)v * t->nvec();
+  }
+  return apply_multi(t, nf, ifr, nrhs, p, mode, prec, s);
 }
 
 int giem_apply_timed(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,

@@ -71,15 +71,22 @@ struct FftDesc {
 
 // Per-RHS vector pointers of one apply (the basis vectors of GMRES are not
 // contiguous across right-hand sides); complex128 vectors, or complex64 ones
-// for the inner solve of the precision form.
+// for the inner solve of the precision form.  One apply takes up to kMaxRhs
+// vectors per frequency and kMaxVec vectors over all its frequencies.
 constexpr int kMaxRhs = 8;
+constexpr int kMaxVec = 32;
 template <typename VT>
 struct VecPtrsT {
-  const VT *in[kMaxRhs];
-  VT *out[kMaxRhs];
+  const VT *in[kMaxVec];
+  VT *out[kMaxVec];
 };
 using VecPtrs = VecPtrsT<c128>;
 using VecPtrs32 = VecPtrsT<c64>;
+// packed spectral tables of the frequencies of one batched apply
+constexpr int kMaxFreqBatch = 16;
+struct TabSet {
+  const void *tab[kMaxFreqBatch];
+};
 // linear systems (frequencies x right-hand sides) of one batched solve
 constexpr int kMaxSys = 96;
 

@@ -97,6 +97,12 @@ int apply_core(giem_handle *t, int ifreq, int nrhs, const VecPtrs &p, unsigned m
 // the same on complex64 vectors (FP32 operator only)
 int apply_core(giem_handle *t, int ifreq, int nrhs, const VecPtrs32 &p, unsigned mode,
                unsigned prec, hipStream_t s, double *stage_ms);
+// one apply over nf frequencies ifreqs[0..nf) with nrhs vectors each: p.in[f
+// nrhs + r] is vector r of frequency ifreqs[f] (one launch per kernel for all)
+int apply_multi(giem_handle *t, int nf, const int *ifreqs, int nrhs, const VecPtrs &p,
+                unsigned mode, unsigned prec, hipStream_t s);
+int apply_multi(giem_handle *t, int nf, const int *ifreqs, int nrhs, const VecPtrs32 &p,
+                unsigned mode, unsigned prec, hipStream_t s);
 int upload_spatial(giem_handle *t, hipStream_t s);
 int plane_wave_levels(const giem_handle *t, double freq, std::vector<cd> &en_lev,
                       std::vector<cd> &hsurf);

@@ -34,9 +34,11 @@ hipError_t launch_fft_x_inv(int prec, const VecPtrs32 &ptrs, const c128 *sd, con
                             const void *spec, int nx, int ny, int nz, int rp_total, int G,
                             int nthr, const FftDesc &fd, const void *tw, double scale,
                             hipStream_t s);
-// out-of-place: sin and sout are two spectra buffers; plan from block_plan(nz)
+// out-of-place: sin and sout are two spectra buffers; plan from block_plan(nz).
+// nf frequencies (tables tabs.tab[0..nf)) with R vectors each: a point's
+// record of the spectra holds nf R vectors, frequency f's at f R .. f R + R - 1.
 // nbuf: register sets of prefetched points in the pipelined kernel (1 or 2)
-hipError_t launch_block(int prec, const void *tab, const void *sin, void *sout,
+hipError_t launch_block(int prec, const TabSet &tabs, int nf, const void *sin, void *sout,
                         const unsigned *plan, int nx, int ny, int nz, int R, int nbuf,
                         hipStream_t s);
 std::vector<unsigned> block_plan(int nz);

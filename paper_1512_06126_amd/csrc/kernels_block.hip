@@ -26,6 +26,11 @@
 // k_block (fallback for larger Nz or many RHS): one wavefront per (point,
 // 16-row tile), fragments gathered straight from global memory through a
 // host-built plan.
+//
+// Several frequencies can share one launch: the spectra of all their vectors
+// are transformed together, a point's record holds nf R vectors (frequency
+// f's at f R .. f R + R - 1) and each (frequency, point) pair reads its own
+// table.
 #include <algorithm>
 #include <vector>
 
@@ -107,15 +112,15 @@ __host__ __device__ inline unsigned plan_word(int nz, int r, int c) {
   return (unsigned)idx | (trans ? (1u << 24) : 0u) | (1u << 25) | ((unsigned)b << 26);
 }
 
-// One wavefront per (representative point, 16-row tile of the output); no
-// LDS and no barriers: the wave gathers its A fragments from the packed block
-// and its B fragments from the input spectra (with the mirror sign flips), and
-// writes its rows of the output spectra, which live in a second buffer.
+// One wavefront per (frequency, representative point, 16-row tile of the
+// output); no LDS and no barriers: the wave gathers its A fragments from the
+// packed block and its B fragments from the input spectra (with the mirror
+// sign flips), and writes its rows of the output spectra, which live in a
+// second buffer.
 template <typename T>
 __global__ void __launch_bounds__(512)
-k_block(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
-        cplx<T> *__restrict__ sout, const unsigned *__restrict__ plan, int nx, int ny, int nz,
-        int R) {
+k_block(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict__ sout,
+        const unsigned *__restrict__ plan, int nx, int ny, int nz, int R, int nf) {
   typedef Mfma<T> M;
   const int E = 2 * nz * (2 * nz + 1);
   const int p3 = 3 * nz;
@@ -123,12 +128,14 @@ k_block(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
   const int ntiles = (p3 + 15) >> 4;
   const int npts = (nx + 1) * (ny + 1);
   const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);  // global wave
-  const int rep = gw / ntiles, tile = gw - rep * ntiles;
-  if (rep >= npts) return;  // whole wave exits together
+  const int task = gw / ntiles, tile = gw - task * ntiles;
+  if (task >= nf * npts) return;  // whole wave exits together
+  const int f = task / npts, rep = task - f * npts;
+  const int rtot = nf * R;  // vectors per point record of the spectra
   const int lane = threadIdx.x & 63;
   const MirrorSet m = mirror_set(rep, nx, ny);
   const int V = m.n * R;
-  const cplx<T> *tq = tab + (size_t)rep * E;
+  const cplx<T> *tq = static_cast<const cplx<T> *>(tabs.tab[f]) + (size_t)rep * E;
   const unsigned *pl = plan + (size_t)tile * nsteps * 64 + lane;
   const int kk = lane >> 4;
   const int j = lane & 15;
@@ -140,7 +147,7 @@ k_block(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
     bool fx = false, fy = false;
     const int mi = vvalid ? v / R : 0, rr = vvalid ? v - mi * R : 0;
     mirror_of(m, mi, nx, ny, pt, fx, fy);
-    const cplx<T> *xb = sin + ((size_t)pt * R + rr) * p3;
+    const cplx<T> *xb = sin + ((size_t)pt * rtot + f * R + rr) * p3;
     typename M::acc_t accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
     constexpr int U = 8;  // k-steps whose operands are requested ahead
     for (int s0 = 0; s0 < nsteps; s0 += U) {
@@ -175,7 +182,7 @@ k_block(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
       }
     }
     if (vvalid) {
-      T *ob = reinterpret_cast<T *>(sout + ((size_t)pt * R + rr) * p3);
+      T *ob = reinterpret_cast<T *>(sout + ((size_t)pt * rtot + f * R + rr) * p3);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int row = tile * 16 + M::row(lane, q);
@@ -238,9 +245,9 @@ __device__ __forceinline__ float flip_sign(float x, unsigned m) {
 }
 
 // Software-pipelined block product.  One persistent workgroup per CU takes
-// the representative points g, g + grid, ...; it holds one point's packed
-// row and input vectors in LDS while the next point's are in flight into
-// registers.  Two wavefronts per 16-row output tile split the contraction
+// the tasks g, g + grid, ... of the nf x (Nx + 1)(Ny + 1) (frequency,
+// representative point) pairs; it holds one task's packed row and input
+// vectors in LDS while the next task's are in flight into registers.  Two wavefronts per 16-row output tile split the contraction
 // into halves (split-k) and are added through LDS, so 2 x ceil(3Nz/16)
 // wavefronts (12 for Nz = 32) keep the four SIMDs' matrix cores busy.  The
 // LDS offsets of a lane's A fragments and the Lemma 1 signs (bit 15 of each
@@ -250,8 +257,8 @@ __device__ __forceinline__ float flip_sign(float x, unsigned m) {
 // with its halves swapped and the sign of the first half flipped.
 template <typename T, int NS>
 __global__ void __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(3, 3)))
-k_block_pipe1(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
-             cplx<T> *__restrict__ sout, int nx, int ny, int nz, int R, int nct) {
+k_block_pipe1(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict__ sout, int nx,
+              int ny, int nz, int R, int nct, int nf) {
   typedef Mfma<T> M;
   typedef T v2 __attribute__((ext_vector_type(2)));
   constexpr int HS = NS / 2;  // k-steps per half
@@ -265,6 +272,8 @@ k_block_pipe1(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
   T *Bs = reinterpret_cast<T *>(Qv + Es + 2);          // [nct][kpad][16]
   T *Red = Bs + (size_t)nct * kpad * 16;                 // [nrt][4][64] partial sums
   const int npts = (nx + 1) * (ny + 1);
+  const int ntask = nf * npts;  // (frequency, representative point) pairs
+  const int rtot = nf * R;      // vectors per point record of the spectra
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int kk0 = lane >> 4, j = lane & 15, part = j >> 3;
@@ -318,8 +327,9 @@ k_block_pipe1(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
   unsigned xneg = 0;  // mirror sign of each prefetched input element
   unsigned xval = 0;  // which prefetched input elements are real (else zero)
   // loads of one point's row and input vectors into the prefetch registers
-  auto prefetch = [&](int rep_) __attribute__((always_inline)) {
-    const v2 *src = reinterpret_cast<const v2 *>(tab) + (size_t)rep_ * E;
+  auto prefetch = [&](int task_) __attribute__((always_inline)) {
+    const int f_ = task_ / npts, rep_ = task_ - f_ * npts;
+    const v2 *src = reinterpret_cast<const v2 *>(tabs.tab[f_]) + (size_t)rep_ * E;
 #pragma unroll
     for (int u = 0; u < kStageRegs; ++u)
       if (tdst[u] >= 0) pre[u] = src[tid + u * nthr];
@@ -337,14 +347,15 @@ k_block_pipe1(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
       int pt;
       bool fx, fy;
       mirror_of(m, ok ? xmi_[u] : 0, nx, ny, pt, fx, fy);
-      xpre[u] = sin[((size_t)pt * R + (ok ? xr_[u] : 0)) * p3 + xc_[u]];
+      xpre[u] = sin[((size_t)pt * rtot + f_ * R + (ok ? xr_[u] : 0)) * p3 + xc_[u]];
       if (ok && ((xb_[u] == 0 && fx) || (xb_[u] == 1 && fy))) xneg |= 1u << u;
       if (ok) xval |= 1u << u;
     }
   };
-  int rep = blockIdx.x;
-  if (rep < npts) prefetch(rep);
-  for (; rep < npts; rep += gridDim.x) {
+  int task = blockIdx.x;
+  if (task < ntask) prefetch(task);
+  for (; task < ntask; task += gridDim.x) {
+    const int f = task / npts, rep = task - f * npts;
     lds_barrier();  // every wavefront is done with the previous point
 #pragma unroll
     for (int u = 0; u < kStageRegs; ++u)
@@ -363,12 +374,13 @@ k_block_pipe1(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
     const int V = m.n * R;
     // the next point's loads are issued one per k-step of the first column
     // tile below, so that waiting for queue space overlaps the MFMAs
-    const int nrep = rep + (int)gridDim.x;
-    const bool more = nrep < npts;
-    const v2 *nsrc = reinterpret_cast<const v2 *>(tab) + (size_t)(more ? nrep : rep) * E;
+    const int ntk = task + (int)gridDim.x;
+    const bool more = ntk < ntask;
+    const int fnx = (more ? ntk : task) / npts, nrep = (more ? ntk : task) - fnx * npts;
+    const v2 *nsrc = reinterpret_cast<const v2 *>(tabs.tab[fnx]) + (size_t)nrep * E;
     int xaddr[kXRegs];
     {
-      const MirrorSet mn = mirror_set(more ? nrep : rep, nx, ny);
+      const MirrorSet mn = mirror_set(nrep, nx, ny);
       const int Vn = mn.n * R;
       xneg = 0;
       xval = 0;
@@ -378,7 +390,7 @@ k_block_pipe1(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
         int pt;
         bool fx, fy;
         mirror_of(mn, ok ? xmi_[u] : 0, nx, ny, pt, fx, fy);
-        xaddr[u] = (pt * R + (ok ? xr_[u] : 0)) * p3 + xc_[u];
+        xaddr[u] = (pt * rtot + fnx * R + (ok ? xr_[u] : 0)) * p3 + xc_[u];
         if (ok && ((xb_[u] == 0 && fx) || (xb_[u] == 1 && fy))) xneg |= 1u << u;
         if (ok) xval |= 1u << u;
       }
@@ -429,7 +441,7 @@ k_block_pipe1(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
           int pt;
           bool fx, fy;
           mirror_of(m, mi, nx, ny, pt, fx, fy);
-          T *ob = reinterpret_cast<T *>(sout + ((size_t)pt * R + r) * p3);
+          T *ob = reinterpret_cast<T *>(sout + ((size_t)pt * rtot + f * R + r) * p3);
 #pragma unroll
           for (int qq = 0; qq < 4; ++qq) {
             const int orow = rt * 16 + M::row(lane, qq);
@@ -454,8 +466,8 @@ k_block_pipe1(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
 // is chosen per handle and precision (giem_tune).
 template <typename T, int NS, int NB>
 __global__ void __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(3, 3)))
-k_block_pipe(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
-             cplx<T> *__restrict__ sout, int nx, int ny, int nz, int R, int nct) {
+k_block_pipe(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict__ sout, int nx,
+             int ny, int nz, int R, int nct, int nf) {
   typedef Mfma<T> M;
   typedef T v2 __attribute__((ext_vector_type(2)));
   constexpr int HS = NS / 2;  // k-steps per half
@@ -469,6 +481,8 @@ k_block_pipe(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
   T *Bs = reinterpret_cast<T *>(Qv + Es + 2);          // [nct][kpad][16]
   T *Red = Bs + (size_t)nct * kpad * 16;                 // [nrt][4][64] partial sums
   const int npts = (nx + 1) * (ny + 1);
+  const int ntask = nf * npts;  // (frequency, representative point) pairs
+  const int rtot = nf * R;      // vectors per point record of the spectra
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int kk0 = lane >> 4, j = lane & 15, part = j >> 3;
@@ -521,8 +535,9 @@ k_block_pipe(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
   cplx<T> xpre[NB][kXRegs];
   unsigned xneg[NB], xval[NB];  // mirror sign / presence of each prefetched input element
   // loads of one point's row and input vectors into prefetch set b
-  auto prefetch = [&](int rep_, int b) __attribute__((always_inline)) {
-    const v2 *src = reinterpret_cast<const v2 *>(tab) + (size_t)rep_ * E;
+  auto prefetch = [&](int task_, int b) __attribute__((always_inline)) {
+    const int f_ = task_ / npts, rep_ = task_ - f_ * npts;
+    const v2 *src = reinterpret_cast<const v2 *>(tabs.tab[f_]) + (size_t)rep_ * E;
 #pragma unroll
     for (int u = 0; u < kStageRegs; ++u)
       if (tdst[u] >= 0) pre[b][u] = src[tid + u * nthr];
@@ -540,7 +555,7 @@ k_block_pipe(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
       int pt;
       bool fx, fy;
       mirror_of(m, ok ? xmi_[u] : 0, nx, ny, pt, fx, fy);
-      xpre[b][u] = sin[((size_t)pt * R + (ok ? xr_[u] : 0)) * p3 + xc_[u]];
+      xpre[b][u] = sin[((size_t)pt * rtot + f_ * R + (ok ? xr_[u] : 0)) * p3 + xc_[u]];
       if (ok && ((xb_[u] == 0 && fx) || (xb_[u] == 1 && fy))) xneg[b] |= 1u << u;
       if (ok) xval[b] |= 1u << u;
     }
@@ -548,14 +563,15 @@ k_block_pipe(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
   const int stride = NB * (int)gridDim.x;
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    const int r0 = (int)blockIdx.x + b * (int)gridDim.x;
-    prefetch(r0 < npts ? r0 : npts - 1, b);
+    const int t0 = (int)blockIdx.x + b * (int)gridDim.x;
+    prefetch(t0 < ntask ? t0 : ntask - 1, b);
   }
-  for (int rep0 = blockIdx.x; rep0 < npts; rep0 += stride) {
+  for (int task0 = blockIdx.x; task0 < ntask; task0 += stride) {
 #pragma unroll
   for (int hb = 0; hb < NB; ++hb) {
-    const int rep = rep0 + hb * (int)gridDim.x;
-    if (rep >= npts) break;
+    const int task = task0 + hb * (int)gridDim.x;
+    if (task >= ntask) break;
+    const int f = task / npts, rep = task - f * npts;
     lds_barrier();  // every wavefront is done with the previous point
 #pragma unroll
     for (int u = 0; u < kStageRegs; ++u)
@@ -576,12 +592,13 @@ k_block_pipe(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
     // are issued one per k-step of the first column tile below, so that
     // waiting for queue space overlaps the MFMAs (a clamped address past the
     // last point: the loads are always issued)
-    const int nrep = rep + stride;
-    const bool more = nrep < npts;
-    const v2 *nsrc = reinterpret_cast<const v2 *>(tab) + (size_t)(more ? nrep : rep) * E;
+    const int ntk = task + stride;
+    const bool more = ntk < ntask;
+    const int fnx = (more ? ntk : task) / npts, nrep = (more ? ntk : task) - fnx * npts;
+    const v2 *nsrc = reinterpret_cast<const v2 *>(tabs.tab[fnx]) + (size_t)nrep * E;
     int xaddr[kXRegs];
     {
-      const MirrorSet mn = mirror_set(more ? nrep : rep, nx, ny);
+      const MirrorSet mn = mirror_set(nrep, nx, ny);
       const int Vn = mn.n * R;
       xneg[hb] = 0;
       xval[hb] = 0;
@@ -591,7 +608,7 @@ k_block_pipe(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
         int pt;
         bool fx, fy;
         mirror_of(mn, ok ? xmi_[u] : 0, nx, ny, pt, fx, fy);
-        xaddr[u] = (pt * R + (ok ? xr_[u] : 0)) * p3 + xc_[u];
+        xaddr[u] = (pt * rtot + fnx * R + (ok ? xr_[u] : 0)) * p3 + xc_[u];
         if (ok && ((xb_[u] == 0 && fx) || (xb_[u] == 1 && fy))) xneg[hb] |= 1u << u;
         if (ok) xval[hb] |= 1u << u;
       }
@@ -642,7 +659,7 @@ k_block_pipe(const cplx<T> *__restrict__ tab, const cplx<T> *__restrict__ sin,
           int pt;
           bool fx, fy;
           mirror_of(m, mi, nx, ny, pt, fx, fy);
-          T *ob = reinterpret_cast<T *>(sout + ((size_t)pt * R + r) * p3);
+          T *ob = reinterpret_cast<T *>(sout + ((size_t)pt * rtot + f * R + r) * p3);
 #pragma unroll
           for (int qq = 0; qq < 4; ++qq) {
             const int orow = rt * 16 + M::row(lane, qq);
@@ -730,46 +747,50 @@ std::vector<unsigned> block_plan(int nz) {
 }
 
 template <typename T>
-static hipError_t launch_block_t(const void *tab, const void *sin, void *sout,
+static hipError_t launch_block_t(const TabSet &tabs, int nf, const void *sin, void *sout,
                                  const unsigned *plan, int nx, int ny, int nz, int R, int nbuf,
                                  hipStream_t s) {
   const size_t lds = lds_bytes_t(nz, R, sizeof(cplx<T>));
   const int nthr = 64 * lds_waves(nz);
-  if (lds_fits(nz, R, sizeof(cplx<T>))) {
-    const long long npts = (long long)(nx + 1) * (ny + 1);
+  const long long ntask = (long long)nf * (nx + 1) * (ny + 1);
+  // the pipelined kernels form spectra element offsets in 32-bit integers
+  const bool off32 = 4LL * nx * ny * nf * R * 3 * nz < (1LL << 31);
+  if (lds_fits(nz, R, sizeof(cplx<T>)) && off32) {
     // persistent grid: one workgroup per CU
-    const long long grid = npts < 256 ? npts : 256;
+    const long long grid = ntask < 256 ? ntask : 256;
     const int ns = lds_ns(nz);
-#define GIEM_LAUNCH(TT, NS)                                                             \
-  if (ns == NS) {                                                                       \
-    if (nbuf == 2)                                                                      \
-      k_block_pipe<TT, NS, 2><<<(unsigned)grid, nthr, lds, s>>>(                         \
-          static_cast<const cplx<TT> *>(tab), static_cast<const cplx<TT> *>(sin),       \
-          static_cast<cplx<TT> *>(sout), nx, ny, nz, R, lds_nct(R));                    \
-    else                                                                                \
-      k_block_pipe1<TT, NS><<<(unsigned)grid, nthr, lds, s>>>(                           \
-          static_cast<const cplx<TT> *>(tab), static_cast<const cplx<TT> *>(sin),       \
-          static_cast<cplx<TT> *>(sout), nx, ny, nz, R, lds_nct(R));                    \
-    return hipGetLastError();                                                           \
+#define GIEM_LAUNCH(TT, NS)                                                               \
+  if (ns == NS) {                                                                         \
+    if (nbuf == 2)                                                                        \
+      k_block_pipe<TT, NS, 2><<<(unsigned)grid, nthr, lds, s>>>(                           \
+          tabs, static_cast<const cplx<TT> *>(sin), static_cast<cplx<TT> *>(sout), nx, ny, \
+          nz, R, lds_nct(R), nf);                                                         \
+    else                                                                                  \
+      k_block_pipe1<TT, NS><<<(unsigned)grid, nthr, lds, s>>>(                             \
+          tabs, static_cast<const cplx<TT> *>(sin), static_cast<cplx<TT> *>(sout), nx, ny, \
+          nz, R, lds_nct(R), nf);                                                         \
+    return hipGetLastError();                                                             \
   }
     GIEM_BLOCK_VARIANTS(GIEM_LAUNCH, T)
 #undef GIEM_LAUNCH
   }
   const int ntiles = (3 * nz + 15) / 16;
-  const long long waves = (long long)(nx + 1) * (ny + 1) * ntiles;
+  const long long waves = ntask * ntiles;
   const int per_block = 4;
   const long long grid = (waves + per_block - 1) / per_block;
-  k_block<T><<<(unsigned)grid, 64 * per_block, 0, s>>>(
-      static_cast<const cplx<T> *>(tab), static_cast<const cplx<T> *>(sin),
-      static_cast<cplx<T> *>(sout), plan, nx, ny, nz, R);
+  k_block<T><<<(unsigned)grid, 64 * per_block, 0, s>>>(tabs, static_cast<const cplx<T> *>(sin),
+                                                      static_cast<cplx<T> *>(sout), plan, nx, ny,
+                                                      nz, R, nf);
   return hipGetLastError();
 }
 
-hipError_t launch_block(int prec, const void *tab, const void *sin, void *sout,
+hipError_t launch_block(int prec, const TabSet &tabs, int nf, const void *sin, void *sout,
                         const unsigned *plan, int nx, int ny, int nz, int R, int nbuf,
                         hipStream_t s) {
-  return prec == PREC_FP32 ? launch_block_t<float>(tab, sin, sout, plan, nx, ny, nz, R, nbuf, s)
-                           : launch_block_t<double>(tab, sin, sout, plan, nx, ny, nz, R, nbuf, s);
+  if (nf < 1 || nf > kMaxFreqBatch) return hipErrorInvalidValue;
+  return prec == PREC_FP32
+             ? launch_block_t<float>(tabs, nf, sin, sout, plan, nx, ny, nz, R, nbuf, s)
+             : launch_block_t<double>(tabs, nf, sin, sout, plan, nx, ny, nz, R, nbuf, s);
 }
 
 }  // namespace giem

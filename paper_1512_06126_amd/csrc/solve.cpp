@@ -176,25 +176,60 @@ static int apply_ptrs(giem_handle *t, int ifreq, const std::vector<const VT *> &
 }
 
 // y = op x for systems of several frequencies: in[i], out[i] belong to system
-// sys[i], whose operator is frequency fq[sys[i]]; one batched apply per
-// frequency.
+// sys[i], whose operator is frequency fq[sys[i]].  The vectors of each
+// frequency are cut into chunks of at most kMaxRhs; chunks of equal size are
+// applied together, one launch per kernel for up to kMaxFreqBatch
+// frequencies (kMaxVec vectors, and spectra workspace of at most 8 GiB unless
+// one chunk alone needs more).
 template <typename VT>
 static int apply_sys(giem_handle *t, const std::vector<int> &fq, const std::vector<int> &sys,
                      const std::vector<const VT *> &in, const std::vector<VT *> &out,
                      unsigned mode, unsigned prec, hipStream_t s) {
+  struct Chunk {
+    int f;
+    std::vector<size_t> idx;
+  };
+  std::vector<Chunk> chunks;
   std::vector<char> used(in.size(), 0);
   for (size_t i = 0; i < in.size(); ++i) {
     if (used[i]) continue;
     const int f = fq[sys[i]];
-    std::vector<const VT *> gi;
-    std::vector<VT *> go;
+    std::vector<size_t> all;
     for (size_t k = i; k < in.size(); ++k)
       if (!used[k] && fq[sys[k]] == f) {
-        gi.push_back(in[k]);
-        go.push_back(out[k]);
+        all.push_back(k);
         used[k] = 1;
       }
-    GIEM_TRY(apply_ptrs(t, f, gi, go, mode, prec, s));
+    for (size_t c0 = 0; c0 < all.size(); c0 += kMaxRhs) {
+      const size_t c1 = std::min(all.size(), c0 + (size_t)kMaxRhs);
+      chunks.push_back(Chunk{f, std::vector<size_t>(all.begin() + c0, all.begin() + c1)});
+    }
+  }
+  const size_t per_vec = (size_t)2 * 4 * t->nx * t->ny * 3 * t->nz * sizeof(c128);
+  const size_t budget = (size_t)8 << 30;
+  std::vector<char> done(chunks.size(), 0);
+  for (size_t i = 0; i < chunks.size(); ++i) {
+    if (done[i]) continue;
+    const int R = (int)chunks[i].idx.size();
+    const int cap_vec = std::max(R, (int)std::min<size_t>(kMaxVec, budget / per_vec));
+    const int cap_f = std::max(1, std::min(kMaxFreqBatch, cap_vec / R));
+    std::vector<size_t> group;
+    for (size_t k = i; k < chunks.size() && (int)group.size() < cap_f; ++k)
+      if (!done[k] && (int)chunks[k].idx.size() == R) {
+        group.push_back(k);
+        done[k] = 1;
+      }
+    VecPtrsT<VT> p{};
+    int ifr[kMaxFreqBatch];
+    for (size_t g = 0; g < group.size(); ++g) {
+      const Chunk &c = chunks[group[g]];
+      ifr[g] = c.f;
+      for (int r = 0; r < R; ++r) {
+        p.in[g * R + r] = in[c.idx[r]];
+        p.out[g * R + r] = out[c.idx[r]];
+      }
+    }
+    GIEM_TRY(apply_multi(t, (int)group.size(), ifr, R, p, mode, prec, s));
   }
   return GIEM_OK;
 }
