@@ -255,7 +255,7 @@ __device__ __forceinline__ float flip_sign(float x, unsigned m) {
 // input vectors are staged as real B fragments: row c holds
 // [Re X_0..7 | Im X_0..7]; the second operand [-Im | Re] is the same row read
 // with its halves swapped and the sign of the first half flipped.
-template <typename T, int NS>
+template <typename T, int NS, bool MF>
 __global__ void __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(3, 3)))
 k_block_pipe1(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict__ sout, int nx,
               int ny, int nz, int R, int nct, int nf) {
@@ -272,8 +272,12 @@ k_block_pipe1(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict_
   T *Bs = reinterpret_cast<T *>(Qv + Es + 2);          // [nct][kpad][16]
   T *Red = Bs + (size_t)nct * kpad * 16;                 // [nrt][4][64] partial sums
   const int npts = (nx + 1) * (ny + 1);
-  const int ntask = nf * npts;  // (frequency, representative point) pairs
-  const int rtot = nf * R;      // vectors per point record of the spectra
+  // tasks: (frequency, representative point) pairs when the launch serves
+  // several frequencies (MF), else the points of the one table, whose
+  // pointer is then read once
+  const int ntask = MF ? nf * npts : npts;
+  const int rtot = MF ? nf * R : R;  // vectors per point record of the spectra
+  const v2 *tab0 = reinterpret_cast<const v2 *>(tabs.tab[0]);
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int kk0 = lane >> 4, j = lane & 15, part = j >> 3;
@@ -328,8 +332,8 @@ k_block_pipe1(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict_
   unsigned xval = 0;  // which prefetched input elements are real (else zero)
   // loads of one point's row and input vectors into the prefetch registers
   auto prefetch = [&](int task_) __attribute__((always_inline)) {
-    const int f_ = task_ / npts, rep_ = task_ - f_ * npts;
-    const v2 *src = reinterpret_cast<const v2 *>(tabs.tab[f_]) + (size_t)rep_ * E;
+    const int f_ = MF ? task_ / npts : 0, rep_ = task_ - f_ * npts;
+    const v2 *src = (MF ? reinterpret_cast<const v2 *>(tabs.tab[f_]) : tab0) + (size_t)rep_ * E;
 #pragma unroll
     for (int u = 0; u < kStageRegs; ++u)
       if (tdst[u] >= 0) pre[u] = src[tid + u * nthr];
@@ -355,7 +359,7 @@ k_block_pipe1(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict_
   int task = blockIdx.x;
   if (task < ntask) prefetch(task);
   for (; task < ntask; task += gridDim.x) {
-    const int f = task / npts, rep = task - f * npts;
+    const int f = MF ? task / npts : 0, rep = task - f * npts;
     lds_barrier();  // every wavefront is done with the previous point
 #pragma unroll
     for (int u = 0; u < kStageRegs; ++u)
@@ -376,8 +380,9 @@ k_block_pipe1(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict_
     // tile below, so that waiting for queue space overlaps the MFMAs
     const int ntk = task + (int)gridDim.x;
     const bool more = ntk < ntask;
-    const int fnx = (more ? ntk : task) / npts, nrep = (more ? ntk : task) - fnx * npts;
-    const v2 *nsrc = reinterpret_cast<const v2 *>(tabs.tab[fnx]) + (size_t)nrep * E;
+    const int fnx = MF ? (more ? ntk : task) / npts : 0;
+    const int nrep = (more ? ntk : task) - fnx * npts;
+    const v2 *nsrc = (MF ? reinterpret_cast<const v2 *>(tabs.tab[fnx]) : tab0) + (size_t)nrep * E;
     int xaddr[kXRegs];
     {
       const MirrorSet mn = mirror_set(nrep, nx, ny);
@@ -464,7 +469,7 @@ k_block_pipe1(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict_
 // into LDS, so the memory pipe does not idle during staging.  It takes more
 // registers, so the one-set kernel above is kept and the faster of the two
 // is chosen per handle and precision (giem_tune).
-template <typename T, int NS, int NB>
+template <typename T, int NS, int NB, bool MF>
 __global__ void __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(3, 3)))
 k_block_pipe(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict__ sout, int nx,
              int ny, int nz, int R, int nct, int nf) {
@@ -481,8 +486,12 @@ k_block_pipe(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict__
   T *Bs = reinterpret_cast<T *>(Qv + Es + 2);          // [nct][kpad][16]
   T *Red = Bs + (size_t)nct * kpad * 16;                 // [nrt][4][64] partial sums
   const int npts = (nx + 1) * (ny + 1);
-  const int ntask = nf * npts;  // (frequency, representative point) pairs
-  const int rtot = nf * R;      // vectors per point record of the spectra
+  // tasks: (frequency, representative point) pairs when the launch serves
+  // several frequencies (MF), else the points of the one table, whose
+  // pointer is then read once
+  const int ntask = MF ? nf * npts : npts;
+  const int rtot = MF ? nf * R : R;  // vectors per point record of the spectra
+  const v2 *tab0 = reinterpret_cast<const v2 *>(tabs.tab[0]);
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int kk0 = lane >> 4, j = lane & 15, part = j >> 3;
@@ -536,8 +545,8 @@ k_block_pipe(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict__
   unsigned xneg[NB], xval[NB];  // mirror sign / presence of each prefetched input element
   // loads of one point's row and input vectors into prefetch set b
   auto prefetch = [&](int task_, int b) __attribute__((always_inline)) {
-    const int f_ = task_ / npts, rep_ = task_ - f_ * npts;
-    const v2 *src = reinterpret_cast<const v2 *>(tabs.tab[f_]) + (size_t)rep_ * E;
+    const int f_ = MF ? task_ / npts : 0, rep_ = task_ - f_ * npts;
+    const v2 *src = (MF ? reinterpret_cast<const v2 *>(tabs.tab[f_]) : tab0) + (size_t)rep_ * E;
 #pragma unroll
     for (int u = 0; u < kStageRegs; ++u)
       if (tdst[u] >= 0) pre[b][u] = src[tid + u * nthr];
@@ -571,7 +580,7 @@ k_block_pipe(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict__
   for (int hb = 0; hb < NB; ++hb) {
     const int task = task0 + hb * (int)gridDim.x;
     if (task >= ntask) break;
-    const int f = task / npts, rep = task - f * npts;
+    const int f = MF ? task / npts : 0, rep = task - f * npts;
     lds_barrier();  // every wavefront is done with the previous point
 #pragma unroll
     for (int u = 0; u < kStageRegs; ++u)
@@ -594,8 +603,9 @@ k_block_pipe(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict__
     // last point: the loads are always issued)
     const int ntk = task + stride;
     const bool more = ntk < ntask;
-    const int fnx = (more ? ntk : task) / npts, nrep = (more ? ntk : task) - fnx * npts;
-    const v2 *nsrc = reinterpret_cast<const v2 *>(tabs.tab[fnx]) + (size_t)nrep * E;
+    const int fnx = MF ? (more ? ntk : task) / npts : 0;
+    const int nrep = (more ? ntk : task) - fnx * npts;
+    const v2 *nsrc = (MF ? reinterpret_cast<const v2 *>(tabs.tab[fnx]) : tab0) + (size_t)nrep * E;
     int xaddr[kXRegs];
     {
       const MirrorSet mn = mirror_set(nrep, nx, ny);
@@ -710,10 +720,16 @@ hipError_t set_block_lds_limits() {
   hipError_t e = hipSuccess;
 #define GIEM_SET_ATTR(T, NS)                                                               \
   if (e == hipSuccess)                                                                     \
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_block_pipe1<T, NS>),           \
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_block_pipe1<T, NS, false>),    \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);  \
   if (e == hipSuccess)                                                                     \
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_block_pipe<T, NS, 2>),         \
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_block_pipe1<T, NS, true>),     \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);  \
+  if (e == hipSuccess)                                                                     \
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_block_pipe<T, NS, 2, false>),  \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);  \
+  if (e == hipSuccess)                                                                     \
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_block_pipe<T, NS, 2, true>),   \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
   GIEM_BLOCK_VARIANTS(GIEM_SET_ATTR, double)
   GIEM_BLOCK_VARIANTS(GIEM_SET_ATTR, float)
@@ -759,20 +775,27 @@ static hipError_t launch_block_t(const TabSet &tabs, int nf, const void *sin, vo
     // persistent grid: one workgroup per CU
     const long long grid = ntask < 256 ? ntask : 256;
     const int ns = lds_ns(nz);
+#define GIEM_LAUNCH_MF(TT, NS, MF)                                                        \
+  if (nbuf == 2)                                                                          \
+    k_block_pipe<TT, NS, 2, MF><<<(unsigned)grid, nthr, lds, s>>>(                         \
+        tabs, static_cast<const cplx<TT> *>(sin), static_cast<cplx<TT> *>(sout), nx, ny,   \
+        nz, R, lds_nct(R), nf);                                                           \
+  else                                                                                    \
+    k_block_pipe1<TT, NS, MF><<<(unsigned)grid, nthr, lds, s>>>(                           \
+        tabs, static_cast<const cplx<TT> *>(sin), static_cast<cplx<TT> *>(sout), nx, ny,   \
+        nz, R, lds_nct(R), nf);
 #define GIEM_LAUNCH(TT, NS)                                                               \
   if (ns == NS) {                                                                         \
-    if (nbuf == 2)                                                                        \
-      k_block_pipe<TT, NS, 2><<<(unsigned)grid, nthr, lds, s>>>(                           \
-          tabs, static_cast<const cplx<TT> *>(sin), static_cast<cplx<TT> *>(sout), nx, ny, \
-          nz, R, lds_nct(R), nf);                                                         \
-    else                                                                                  \
-      k_block_pipe1<TT, NS><<<(unsigned)grid, nthr, lds, s>>>(                             \
-          tabs, static_cast<const cplx<TT> *>(sin), static_cast<cplx<TT> *>(sout), nx, ny, \
-          nz, R, lds_nct(R), nf);                                                         \
+    if (nf > 1) {                                                                         \
+      GIEM_LAUNCH_MF(TT, NS, true)                                                        \
+    } else {                                                                              \
+      GIEM_LAUNCH_MF(TT, NS, false)                                                       \
+    }                                                                                     \
     return hipGetLastError();                                                             \
   }
     GIEM_BLOCK_VARIANTS(GIEM_LAUNCH, T)
 #undef GIEM_LAUNCH
+#undef GIEM_LAUNCH_MF
   }
   const int ntiles = (3 * nz + 15) / 16;
   const long long waves = ntask * ntiles;
