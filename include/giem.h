@@ -197,15 +197,16 @@ int giem_profile(giem_handle *t, int32_t enable);
    (Sect. 3.3): for the four FFT passes (x forward, y forward, y inverse, x
    inverse) every instantiated (sequences per workgroup, threads per
    workgroup) pair that fits the local data share, and for the block product
-   one or two register sets of prefetched points; each candidate is run on
+   the variants of giem_set_block_buffers; each candidate is run on
    nrhs right-hand sides of frequency ifreq for every precision whose tables
    exist, and the fastest median is kept on the handle for all later applies.
-   Results do not depend on the choice: every transform and every block
-   product is computed the same way whichever workgroup runs it.
+   The FFT shapes and block variants 1 and 2 do not change any result bit;
+   variant 3 sums each contraction in another order (rounding-level
+   differences).
      sigma_a: device c128 [Nz][Ny][Nx] (the diagonals of mode A are used);
      chosen:  host int32 [2][5][2] or NULL: per precision (0 = FP64,
               1 = FP32) the (sequences, threads) of the four passes, then
-              (register sets, 0) of the block product, as now in effect.
+              (block-product variant, 0), as now in effect.
    The choice is also kept for the process and given to handles created
    later for the same grid (Nx, Ny, Nz) on the same device.
    Allocates and frees two vectors of nrhs right-hand sides; synchronises.
@@ -222,10 +223,14 @@ int giem_tune(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs, 
    Errors: EINVAL (nothing is changed). */
 int giem_set_fft_shape(giem_handle *t, uint32_t prec, const int32_t *shape);
 
-/* giem_set_block_buffers -- register sets of prefetched points in the block
-   product (Sect. 3.3 step 2) for one precision (0 = FP64, 1 = FP32): 1 or 2
-   (2 keeps the next point's loads in flight while a point is staged into
-   local memory), 0 for the built-in choice (1).  Errors: EINVAL. */
+/* giem_set_block_buffers -- variant of the block product (Sect. 3.3 step 2)
+   for one precision (0 = FP64, 1 = FP32): 1 or 2 register sets of prefetched
+   points in one workgroup per CU (2 keeps the next point's loads in flight
+   while a point is staged into local memory), 3 = two workgroups per CU,
+   each wavefront doing a whole 16-row contraction (one workgroup's matrix
+   products overlap the other's staging; where two do not fit the local data
+   share, 1 is used), 0 for the built-in choice (1).  Results agree to
+   rounding whichever variant runs.  Errors: EINVAL. */
 int giem_set_block_buffers(giem_handle *t, uint32_t prec, int32_t nbuf);
 
 /* giem_profile_read -- wait for the last recorded apply and report what was

@@ -221,7 +221,8 @@ class Handle:
         _check(_lib.giem_set_fft_shape(self._p, prec, arr))
 
     def set_block_buffers(self, prec, nbuf):
-        """Prefetch depth of the block product (1 or 2; 0 = built-in)."""
+        """Variant of the block product: 1 or 2 prefetch sets in one
+        workgroup per CU, 3 = two workgroups per CU (0 = built-in, 1)."""
         _check(_lib.giem_set_block_buffers(self._p, prec, nbuf))
 
     def profile(self, enable=True):

@@ -37,11 +37,14 @@ hipError_t launch_fft_x_inv(int prec, const VecPtrs32 &ptrs, const c128 *sd, con
 // out-of-place: sin and sout are two spectra buffers; plan from block_plan(nz).
 // nf frequencies (tables tabs.tab[0..nf)) with R vectors each: a point's
 // record of the spectra holds nf R vectors, frequency f's at f R .. f R + R - 1.
-// nbuf: register sets of prefetched points in the pipelined kernel (1 or 2)
+// nbuf: variant of the pipelined kernel: 1 or 2 register sets of prefetched
+// points (one workgroup per CU), 3: two workgroups per CU with one set each
+// (falls back to 1 where it does not fit, see block_two_per_cu)
 hipError_t launch_block(int prec, const TabSet &tabs, int nf, const void *sin, void *sout,
                         const unsigned *plan, int nx, int ny, int nz, int R, int nbuf,
                         hipStream_t s);
 std::vector<unsigned> block_plan(int nz);
+bool block_two_per_cu(int nz, int R, int prec);
 
 // table set-up (kernels_setup.hip)
 hipError_t launch_spectral_x(const c128 *spatial, c128 *tmp, const c128 *cs_x, int nx, int ny,

@@ -224,7 +224,8 @@ __device__ __forceinline__ int staged_of_packed(int e, int nz, int tri) {
 
 // entries of the packed row and of the input vectors that a thread carries
 // ahead in registers (the next point's data, loaded during the MFMAs)
-constexpr int kStageRegs = 6;
+constexpr int kStageRegs = 6;   // 12 wavefronts (KS = 2)
+constexpr int kStageRegs1 = 11; // 6 wavefronts (KS = 1)
 constexpr int kXRegs = 2;
 // k-steps of 4 columns per wavefront (half of 3 Nz, rounded up)
 constexpr int kMaxHalfSteps = 16;
@@ -244,24 +245,30 @@ __device__ __forceinline__ float flip_sign(float x, unsigned m) {
   return __int_as_float(__float_as_int(x) ^ (int)m);
 }
 
-// Software-pipelined block product.  One persistent workgroup per CU takes
-// the tasks g, g + grid, ... of the nf x (Nx + 1)(Ny + 1) (frequency,
+// Software-pipelined block product.  Each persistent workgroup takes the
+// tasks g, g + grid, ... of the nf x (Nx + 1)(Ny + 1) (frequency,
 // representative point) pairs; it holds one task's packed row and input
-// vectors in LDS while the next task's are in flight into registers.  Two wavefronts per 16-row output tile split the contraction
-// into halves (split-k) and are added through LDS, so 2 x ceil(3Nz/16)
-// wavefronts (12 for Nz = 32) keep the four SIMDs' matrix cores busy.  The
-// LDS offsets of a lane's A fragments and the Lemma 1 signs (bit 15 of each
-// 16-bit entry) do not depend on the point and are computed once.  The
+// vectors in LDS while the next task's are in flight into registers.
+//   KS = 2: one workgroup per CU; two wavefronts per 16-row output tile split
+//   the contraction into halves (split-k) and add them through LDS, so
+//   2 x ceil(3Nz/16) wavefronts (12 for Nz = 32) keep the four SIMDs' matrix
+//   cores busy.
+//   KS = 1: two workgroups per CU, one wavefront per tile doing the whole
+//   contraction (no reduction buffer, no barrier between column tiles), so
+//   that one workgroup's MFMAs overlap the other's staging and stores.
+// The LDS offsets of a lane's A fragments and the Lemma 1 signs (bit 15 of
+// each 16-bit entry) do not depend on the point and are computed once.  The
 // input vectors are staged as real B fragments: row c holds
 // [Re X_0..7 | Im X_0..7]; the second operand [-Im | Re] is the same row read
 // with its halves swapped and the sign of the first half flipped.
-template <typename T, int NS, bool MF>
+template <typename T, int NS, bool MF, int KS>
 __global__ void __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(3, 3)))
 k_block_pipe1(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict__ sout, int nx,
               int ny, int nz, int R, int nct, int nf) {
   typedef Mfma<T> M;
   typedef T v2 __attribute__((ext_vector_type(2)));
-  constexpr int HS = NS / 2;  // k-steps per half
+  constexpr int HS = NS / KS;  // k-steps per wavefront
+  constexpr int SR = KS == 2 ? kStageRegs : kStageRegs1;  // packed entries per thread
   constexpr int kpad = 4 * NS;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int E = 2 * nz * (2 * nz + 1);
@@ -270,7 +277,7 @@ k_block_pipe1(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict_
   const int nrt = (p3 + 15) >> 4;
   v2 *Qv = reinterpret_cast<v2 *>(lds_raw);
   T *Bs = reinterpret_cast<T *>(Qv + Es + 2);          // [nct][kpad][16]
-  T *Red = Bs + (size_t)nct * kpad * 16;                 // [nrt][4][64] partial sums
+  T *Red = Bs + (size_t)nct * kpad * 16;  // [nrt][4][64] partial sums (KS = 2)
   const int npts = (nx + 1) * (ny + 1);
   // tasks: (frequency, representative point) pairs when the launch serves
   // several frequencies (MF), else the points of the one table, whose
@@ -281,7 +288,7 @@ k_block_pipe1(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict_
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int kk0 = lane >> 4, j = lane & 15, part = j >> 3;
-  const int rt = wave % nrt, kh = wave / nrt;  // output tile, contraction half
+  const int rt = wave % nrt, kh = KS == 2 ? wave / nrt : 0;  // output tile, contraction half
   const unsigned bmask = part ? 0u : 0x80000000u;
   unsigned aoff[(HS + 1) / 2];
   {
@@ -308,9 +315,9 @@ k_block_pipe1(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict_
   // point-independent staging maps of this thread: LDS slot of each packed
   // entry it carries; column v, row c (component b) and RHS of each input
   // element, and its place in the B rows
-  int tdst[kStageRegs];
+  int tdst[SR];
 #pragma unroll
-  for (int u = 0; u < kStageRegs; ++u) {
+  for (int u = 0; u < SR; ++u) {
     const int e = tid + u * nthr;
     tdst[u] = e < E ? staged_of_packed(e, nz, tri) : -1;
   }
@@ -326,7 +333,7 @@ k_block_pipe1(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict_
     xb_[u] = c < p3 ? c / nz : 3;  // 3: padding row
     xdst_[u] = idx < nxe ? ((v >> 3) * kpad + c) * 16 + (v & 7) : -1;
   }
-  v2 pre[kStageRegs];
+  v2 pre[SR];
   cplx<T> xpre[kXRegs];
   unsigned xneg = 0;  // mirror sign of each prefetched input element
   unsigned xval = 0;  // which prefetched input elements are real (else zero)
@@ -335,7 +342,7 @@ k_block_pipe1(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict_
     const int f_ = MF ? task_ / npts : 0, rep_ = task_ - f_ * npts;
     const v2 *src = (MF ? reinterpret_cast<const v2 *>(tabs.tab[f_]) : tab0) + (size_t)rep_ * E;
 #pragma unroll
-    for (int u = 0; u < kStageRegs; ++u)
+    for (int u = 0; u < SR; ++u)
       if (tdst[u] >= 0) pre[u] = src[tid + u * nthr];
     const MirrorSet m = mirror_set(rep_, nx, ny);
     const int V = m.n * R;
@@ -362,7 +369,7 @@ k_block_pipe1(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict_
     const int f = MF ? task / npts : 0, rep = task - f * npts;
     lds_barrier();  // every wavefront is done with the previous point
 #pragma unroll
-    for (int u = 0; u < kStageRegs; ++u)
+    for (int u = 0; u < SR; ++u)
       if (tdst[u] >= 0) Qv[tdst[u]] = pre[u];
 #pragma unroll
     for (int u = 0; u < kXRegs; ++u) {
@@ -410,13 +417,17 @@ k_block_pipe1(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict_
       for (int u = 0; u < HS; ++u) {
         if (ct == 0 && more) {
           // prefetch slot u: packed entries first, then input elements
-          if (u < kStageRegs) {
+          if (u < SR) {
             if (tdst[u] >= 0) pre[u] = nsrc[tid + u * nthr];
-          } else if (u - kStageRegs < kXRegs) {
-            xpre[u - kStageRegs] = sin[xaddr[u - kStageRegs]];
+          } else if (u - SR < kXRegs) {
+            xpre[u - SR] = sin[xaddr[u - SR]];
           }
         }
-        const unsigned w = (u & 1) ? (aoff[u >> 1] >> 16) : (aoff[u >> 1] & 0xffffu);
+        unsigned pw = aoff[u >> 1];
+        // KS = 1: decode at the use (an opaque copy), so that the decoded
+        // offsets and signs of all HS k-steps are not held in registers
+        if constexpr (KS == 1) asm volatile("" : "+v"(pw));
+        const unsigned w = (u & 1) ? (pw >> 16) : (pw & 0xffffu);
         const v2 q = Qv[w & 0x7fffu];
         const unsigned qm = (w & 0x8000u) << 16;
         const T b1 = b1p[u * 64];
@@ -426,19 +437,21 @@ k_block_pipe1(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict_
       }
       if (ct == 0 && more) {
 #pragma unroll
-        for (int u = HS; u < kStageRegs + kXRegs; ++u) {
-          if (u < kStageRegs) {
+        for (int u = HS; u < SR + kXRegs; ++u) {
+          if (u < SR) {
             if (tdst[u] >= 0) pre[u] = nsrc[tid + u * nthr];
           } else {
-            xpre[u - kStageRegs] = sin[xaddr[u - kStageRegs]];
+            xpre[u - SR] = sin[xaddr[u - SR]];
           }
         }
       }
-      if (kh == 1) {
+      if (KS == 2) {
+        if (kh == 1) {
 #pragma unroll
-        for (int qq = 0; qq < 4; ++qq) Red[(rt * 4 + qq) * 64 + lane] = accr[qq] + acci[qq];
+          for (int qq = 0; qq < 4; ++qq) Red[(rt * 4 + qq) * 64 + lane] = accr[qq] + acci[qq];
+        }
+        lds_barrier();
       }
-      lds_barrier();
       if (kh == 0) {
         const int v = ct * 8 + (j & 7);
         if (v < V) {
@@ -453,12 +466,13 @@ k_block_pipe1(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict_
             if (orow < p3) {
               const int oa = orow / nz;
               const T sg = ((oa == 0 && fx) || (oa == 1 && fy)) ? (T)-1 : (T)1;
-              ob[2 * orow + part] = sg * (accr[qq] + acci[qq] + Red[(rt * 4 + qq) * 64 + lane]);
+              const T red = KS == 2 ? Red[(rt * 4 + qq) * 64 + lane] : (T)0;
+              ob[2 * orow + part] = sg * (accr[qq] + acci[qq] + red);
             }
           }
         }
       }
-      lds_barrier();  // Red is reused by the next column tile
+      if (KS == 2) lds_barrier();  // Red is reused by the next column tile
     }
   }
 }
@@ -692,24 +706,30 @@ static int lds_nct(int R) { return (4 * R + 7) / 8; }
 // k-steps rounded up to a multiple of 4 (the compiled variants)
 static int lds_ns(int nz) { return 4 * (((3 * nz + 3) / 4 + 3) / 4); }
 
-static size_t lds_bytes_t(int nz, int R, size_t csize) {
+// LDS of one workgroup: staged row, B rows and (KS = 2) the reduction buffer
+static size_t lds_bytes_t(int nz, int R, size_t csize, int ks) {
   const size_t Es = 2 * (size_t)nz * (2 * nz + 1) + 2 * nz;
   const size_t kpad = 4 * (size_t)lds_ns(nz);
   const size_t nrt = (3 * (size_t)nz + 15) / 16;
-  return (Es + 2) * csize + (size_t)lds_nct(R) * kpad * 16 * (csize / 2) + nrt * 256 * (csize / 2);
+  return (Es + 2) * csize + (size_t)lds_nct(R) * kpad * 16 * (csize / 2) +
+         (ks == 2 ? nrt * 256 * (csize / 2) : 0);
 }
 
 static const size_t kLdsLimit = 160 * 1024;
 
-// two wavefronts (contraction halves) per 16-row tile
-static int lds_waves(int nz) { return 2 * ((3 * nz + 15) / 16); }
+// ks wavefronts (contraction parts) per 16-row tile
+static int lds_waves(int nz, int ks) { return ks * ((3 * nz + 15) / 16); }
 
-static bool lds_fits(int nz, int R, size_t csize) {
+// whether the pipelined kernel with contraction split ks runs this shape (for
+// ks = 1, with two workgroups per CU)
+static bool lds_fits(int nz, int R, size_t csize, int ks) {
   const long long E = 2LL * nz * (2 * nz + 1);
-  const int nthr = 64 * lds_waves(nz);
+  const int nthr = 64 * lds_waves(nz, ks);
   const long long nxe = (long long)lds_nct(R) * 8 * 4 * lds_ns(nz);
-  return lds_bytes_t(nz, R, csize) <= kLdsLimit && lds_ns(nz) / 2 <= kMaxHalfSteps &&
-         nthr <= 768 && E <= (long long)kStageRegs * nthr && nxe <= (long long)kXRegs * nthr &&
+  const size_t lim = ks == 2 ? kLdsLimit : kLdsLimit / 2;
+  const int sr = ks == 2 ? kStageRegs : kStageRegs1;
+  return lds_bytes_t(nz, R, csize, ks) <= lim && lds_ns(nz) / ks <= kMaxHalfSteps * (3 - ks) &&
+         nthr <= 768 && E <= (long long)sr * nthr && nxe <= (long long)kXRegs * nthr &&
          E + 2 * nz + 1 < 0x8000;
 }
 
@@ -720,10 +740,16 @@ hipError_t set_block_lds_limits() {
   hipError_t e = hipSuccess;
 #define GIEM_SET_ATTR(T, NS)                                                               \
   if (e == hipSuccess)                                                                     \
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_block_pipe1<T, NS, false>),    \
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_block_pipe1<T, NS, false, 2>), \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);  \
   if (e == hipSuccess)                                                                     \
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_block_pipe1<T, NS, true>),     \
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_block_pipe1<T, NS, true, 2>),  \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);  \
+  if (e == hipSuccess)                                                                     \
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_block_pipe1<T, NS, false, 1>), \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);  \
+  if (e == hipSuccess)                                                                     \
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_block_pipe1<T, NS, true, 1>),  \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);  \
   if (e == hipSuccess)                                                                     \
     e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_block_pipe<T, NS, 2, false>),  \
@@ -766,22 +792,31 @@ template <typename T>
 static hipError_t launch_block_t(const TabSet &tabs, int nf, const void *sin, void *sout,
                                  const unsigned *plan, int nx, int ny, int nz, int R, int nbuf,
                                  hipStream_t s) {
-  const size_t lds = lds_bytes_t(nz, R, sizeof(cplx<T>));
-  const int nthr = 64 * lds_waves(nz);
   const long long ntask = (long long)nf * (nx + 1) * (ny + 1);
   // the pipelined kernels form spectra element offsets in 32-bit integers
   const bool off32 = 4LL * nx * ny * nf * R * 3 * nz < (1LL << 31);
-  if (lds_fits(nz, R, sizeof(cplx<T>)) && off32) {
-    // persistent grid: one workgroup per CU
-    const long long grid = ntask < 256 ? ntask : 256;
+  const size_t cs = sizeof(cplx<T>);
+  if (nbuf == 3 && !lds_fits(nz, R, cs, 1)) nbuf = 1;
+  const int ks = nbuf == 3 ? 1 : 2;
+  if (lds_fits(nz, R, cs, ks) && off32) {
+    const size_t lds = lds_bytes_t(nz, R, cs, ks);
+    const int nthr = 64 * lds_waves(nz, ks);
+    // persistent grid: one workgroup per CU (two for ks = 1); more
+    // workgroups per CU at small Nz measured slower (a larger tail round)
+    const long long cap = ks == 1 ? 512 : 256;
+    const long long grid = ntask < cap ? ntask : cap;
     const int ns = lds_ns(nz);
 #define GIEM_LAUNCH_MF(TT, NS, MF)                                                        \
   if (nbuf == 2)                                                                          \
     k_block_pipe<TT, NS, 2, MF><<<(unsigned)grid, nthr, lds, s>>>(                         \
         tabs, static_cast<const cplx<TT> *>(sin), static_cast<cplx<TT> *>(sout), nx, ny,   \
         nz, R, lds_nct(R), nf);                                                           \
+  else if (nbuf == 3)                                                                     \
+    k_block_pipe1<TT, NS, MF, 1><<<(unsigned)grid, nthr, lds, s>>>(                        \
+        tabs, static_cast<const cplx<TT> *>(sin), static_cast<cplx<TT> *>(sout), nx, ny,   \
+        nz, R, lds_nct(R), nf);                                                           \
   else                                                                                    \
-    k_block_pipe1<TT, NS, MF><<<(unsigned)grid, nthr, lds, s>>>(                           \
+    k_block_pipe1<TT, NS, MF, 2><<<(unsigned)grid, nthr, lds, s>>>(                        \
         tabs, static_cast<const cplx<TT> *>(sin), static_cast<cplx<TT> *>(sout), nx, ny,   \
         nz, R, lds_nct(R), nf);
 #define GIEM_LAUNCH(TT, NS)                                                               \
@@ -805,6 +840,10 @@ static hipError_t launch_block_t(const TabSet &tabs, int nf, const void *sin, vo
                                                       static_cast<cplx<T> *>(sout), plan, nx, ny,
                                                       nz, R, nf);
   return hipGetLastError();
+}
+
+bool block_two_per_cu(int nz, int R, int prec) {
+  return lds_fits(nz, R, prec == PREC_FP32 ? sizeof(c64) : sizeof(c128), 1);
 }
 
 hipError_t launch_block(int prec, const TabSet &tabs, int nf, const void *sin, void *sout,

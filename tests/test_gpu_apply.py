@@ -109,13 +109,14 @@ def full_case():
     return m, t, x, qnn, cells
 
 
-@pytest.mark.parametrize("nbuf", [1, 2])
+@pytest.mark.parametrize("nbuf", [1, 2, 3])
 @pytest.mark.parametrize("mode,prec,tol", [("A", 0, 1e-10), ("B", 0, 1e-10), ("AT", 0, 1e-10),
                                            ("B", 1, 1e-4)])
 def test_apply_full_size_sampled(lib, full_case, mode, prec, tol, nbuf):
     # The launch configuration the benchmark times (128 x 128 x 32, 2 RHS),
     # checked at sampled output cells against the oracle's direct sum, with
-    # one and two prefetch sets in the block product.
+    # each block-product variant: one or two prefetch sets in one workgroup
+    # per CU, or two workgroups per CU.
     import torch
     m, t, x, qnn, cells = full_case
     print(f"full-size apply mode={mode} prec={prec} block buffers={nbuf}", flush=True)
@@ -162,7 +163,7 @@ def test_every_fft_shape_matches_dense(lib, nx, ny, nz, nrhs):
                 assert err <= tol, (prec, g, nt, err)
                 tried += 1
         h.set_fft_shape(prec, None)
-        for nbuf in (2, 1):
+        for nbuf in (3, 2, 1):
             h.set_block_buffers(prec, nbuf)
             h.apply(xd, yd, sa, mode=lib.MODE_A, prec=prec)
             torch.cuda.synchronize()

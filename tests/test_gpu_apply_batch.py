@@ -69,14 +69,16 @@ def test_apply_batch_equals_separate(lib, prec):
     x = np.stack([gs.random_vector(rng, nrhs, nz, ny, nx) for _ in ifreqs])
     xd = to_dev(x)
     sa = to_dev(m["sigma_a"])
-    for mode in (lib.MODE_A, lib.MODE_AT, lib.MODE_B):
-        yb = torch.empty_like(xd)
-        h.apply_batch(xd, yb, sa, ifreqs=ifreqs, mode=mode, prec=p)
-        ys = torch.empty_like(xd)
-        for f, q in enumerate(ifreqs):
-            h.apply(xd[f], ys[f], sa, mode=mode, prec=p, ifreq=q)
-        torch.cuda.synchronize()
-        assert torch.equal(yb, ys), (mode, float((yb - ys).abs().max()))
+    for nbuf in (1, 2, 3):
+        h.set_block_buffers(p, nbuf)
+        for mode in (lib.MODE_A, lib.MODE_AT, lib.MODE_B):
+            yb = torch.empty_like(xd)
+            h.apply_batch(xd, yb, sa, ifreqs=ifreqs, mode=mode, prec=p)
+            ys = torch.empty_like(xd)
+            for f, q in enumerate(ifreqs):
+                h.apply(xd[f], ys[f], sa, mode=mode, prec=p, ifreq=q)
+            torch.cuda.synchronize()
+            assert torch.equal(yb, ys), (nbuf, mode, float((yb - ys).abs().max()))
     h.close()
 
 
