@@ -52,7 +52,10 @@ __device__ __forceinline__ double weight_of(size_t k, int plane, int nz, const d
 // need more registers, and the lower occupancy cost more than the re-reads
 // (measured on the 128 x 128 x 32 solve).
 constexpr int kSlots = 8;
-template <typename VT, int SLOTS>
+// P2 (complex64 vectors, n even, 16-byte aligned vectors): each thread takes
+// two neighbouring elements per 16-byte load, which doubles the bytes in
+// flight per load instruction.
+template <typename VT, int SLOTS, bool P2>
 __global__ void __launch_bounds__(256)
 k_dots(DotArgsT<VT> a, int nb, size_t n, int nz, int plane, const double *__restrict__ wlev,
        c128 *__restrict__ part) {
@@ -65,19 +68,46 @@ k_dots(DotArgsT<VT> a, int nb, size_t n, int nz, int plane, const double *__rest
   double accr[kSlots], acci[kSlots];
 #pragma unroll
   for (int k = 0; k < kSlots; ++k) accr[k] = acci[k] = 0.0;
-  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n;
-       k += (size_t)gridDim.x * blockDim.x) {
-    const c128 wv = wide(w[k]);
-    const double wt = weight_of(k, plane, nz, wlev);
+  if constexpr (P2) {
+    const size_t n2 = n >> 1;
+    const float4 *w2 = reinterpret_cast<const float4 *>(w);
+    const float4 *V2 = reinterpret_cast<const float4 *>(V);
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n2;
+         k += (size_t)gridDim.x * blockDim.x) {
+      const float4 wq = w2[k];
+      const c128 wa = mk<double>(wq.x, wq.y), wb = mk<double>(wq.z, wq.w);
+      const double ta = weight_of(2 * k, plane, nz, wlev), tb = weight_of(2 * k + 1, plane, nz, wlev);
 #pragma unroll
-    for (int q = 0; q < kSlots; ++q) {
-      const int s = s0 + q;
-      if (s < nb) {
-        const c128 v = wide(V[(size_t)s * n + k]);
-        accr[q] += wt * (wv.x * v.x + wv.y * v.y);
-        acci[q] += wt * (wv.y * v.x - wv.x * v.y);
-      } else if (s == nb) {
-        accr[q] += wt * (wv.x * wv.x + wv.y * wv.y);
+      for (int q = 0; q < kSlots; ++q) {
+        const int s = s0 + q;
+        if (s < nb) {
+          const float4 vq = V2[(size_t)s * n2 + k];
+          const c128 va = mk<double>(vq.x, vq.y), vb = mk<double>(vq.z, vq.w);
+          accr[q] += ta * (wa.x * va.x + wa.y * va.y);
+          acci[q] += ta * (wa.y * va.x - wa.x * va.y);
+          accr[q] += tb * (wb.x * vb.x + wb.y * vb.y);
+          acci[q] += tb * (wb.y * vb.x - wb.x * vb.y);
+        } else if (s == nb) {
+          accr[q] += ta * (wa.x * wa.x + wa.y * wa.y);
+          accr[q] += tb * (wb.x * wb.x + wb.y * wb.y);
+        }
+      }
+    }
+  } else {
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n;
+         k += (size_t)gridDim.x * blockDim.x) {
+      const c128 wv = wide(w[k]);
+      const double wt = weight_of(k, plane, nz, wlev);
+#pragma unroll
+      for (int q = 0; q < kSlots; ++q) {
+        const int s = s0 + q;
+        if (s < nb) {
+          const c128 v = wide(V[(size_t)s * n + k]);
+          accr[q] += wt * (wv.x * v.x + wv.y * v.y);
+          acci[q] += wt * (wv.y * v.x - wv.x * v.y);
+        } else if (s == nb) {
+          accr[q] += wt * (wv.x * wv.x + wv.y * wv.y);
+        }
       }
     }
   }
@@ -108,13 +138,27 @@ k_reduce(const c128 *__restrict__ part, int nblk, int nslots, c128 *__restrict__
   if (threadIdx.x == 0) out[(size_t)r * nslots + s] = mk<double>(ar, ai);
 }
 
+// whether complex64 vectors can be read in 16-byte pairs: n even and every
+// vector (w and basis bases, basis vectors at stride n) 16-byte aligned
+template <typename VT>
+static bool pairs_ok(const DotArgsT<VT> &a, int nrhs, size_t n) {
+  if (sizeof(VT) != 8 || (n & 1)) return false;
+  for (int r = 0; r < nrhs; ++r)
+    if ((reinterpret_cast<uintptr_t>(a.w[r]) | reinterpret_cast<uintptr_t>(a.basis[r])) & 15)
+      return false;
+  return true;
+}
+
 template <typename VT>
 static hipError_t launch_dots_t(const DotArgsT<VT> &a, int nrhs, int nb, size_t n, int nz,
                                 int plane, const double *wlev, c128 *part, c128 *out,
                                 hipStream_t s) {
   const int nslots = nb + 1;
-  k_dots<VT, kSlots><<<dim3(kRedBlocks, nrhs, (nslots + kSlots - 1) / kSlots), 256, 0, s>>>(
-      a, nb, n, nz, plane, wlev, part);
+  const dim3 grid(kRedBlocks, nrhs, (nslots + kSlots - 1) / kSlots);
+  if (pairs_ok(a, nrhs, n))
+    k_dots<VT, kSlots, true><<<grid, 256, 0, s>>>(a, nb, n, nz, plane, wlev, part);
+  else
+    k_dots<VT, kSlots, false><<<grid, 256, 0, s>>>(a, nb, n, nz, plane, wlev, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_reduce<<<dim3(nslots, nrhs), 256, 0, s>>>(part, kRedBlocks, nslots, out);
@@ -130,7 +174,7 @@ hipError_t launch_dots(const DotArgs32 &a, int nrhs, int nb, size_t n, int nz, i
 }
 
 // w -= sum_{i < nb} h[r][i] V_i ; partial ||w||^2 into part[r][0][block]
-template <typename VT>
+template <typename VT, bool P2>
 __global__ void __launch_bounds__(256)
 k_update(DotArgsT<VT> a, int nb, size_t n, int nz, int plane, const double *__restrict__ wlev,
          const c128 *__restrict__ h, int hstride, const double *__restrict__ hscale,
@@ -147,17 +191,39 @@ k_update(DotArgsT<VT> a, int nb, size_t n, int nz, int plane, const double *__re
   }
   __syncthreads();
   double acc = 0.0;
-  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n;
-       k += (size_t)gridDim.x * blockDim.x) {
-    c128 wv = wide(w[k]);
-    for (int i = 0; i < nb; ++i) {
-      const c128 v = wide(V[(size_t)i * n + k]);
-      const c128 hv = hs[i];
-      wv.x -= hv.x * v.x - hv.y * v.y;
-      wv.y -= hv.x * v.y + hv.y * v.x;
+  if constexpr (P2) {
+    const size_t n2 = n >> 1;
+    float4 *w2 = reinterpret_cast<float4 *>(w);
+    const float4 *V2 = reinterpret_cast<const float4 *>(V);
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n2;
+         k += (size_t)gridDim.x * blockDim.x) {
+      const float4 wq = w2[k];
+      c128 wa = mk<double>(wq.x, wq.y), wb = mk<double>(wq.z, wq.w);
+      for (int i = 0; i < nb; ++i) {
+        const float4 vq = V2[(size_t)i * n2 + k];
+        const c128 hv = hs[i];
+        wa.x -= hv.x * (double)vq.x - hv.y * (double)vq.y;
+        wa.y -= hv.x * (double)vq.y + hv.y * (double)vq.x;
+        wb.x -= hv.x * (double)vq.z - hv.y * (double)vq.w;
+        wb.y -= hv.x * (double)vq.w + hv.y * (double)vq.z;
+      }
+      w2[k] = make_float4((float)wa.x, (float)wa.y, (float)wb.x, (float)wb.y);
+      acc += weight_of(2 * k, plane, nz, wlev) * (wa.x * wa.x + wa.y * wa.y);
+      acc += weight_of(2 * k + 1, plane, nz, wlev) * (wb.x * wb.x + wb.y * wb.y);
     }
-    w[k] = store_as<VT>(wv);
-    acc += weight_of(k, plane, nz, wlev) * (wv.x * wv.x + wv.y * wv.y);
+  } else {
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n;
+         k += (size_t)gridDim.x * blockDim.x) {
+      c128 wv = wide(w[k]);
+      for (int i = 0; i < nb; ++i) {
+        const c128 v = wide(V[(size_t)i * n + k]);
+        const c128 hv = hs[i];
+        wv.x -= hv.x * v.x - hv.y * v.y;
+        wv.y -= hv.x * v.y + hv.y * v.x;
+      }
+      w[k] = store_as<VT>(wv);
+      acc += weight_of(k, plane, nz, wlev) * (wv.x * wv.x + wv.y * wv.y);
+    }
   }
   const double sum = block_sum(acc, red);
   if (threadIdx.x == 0) part[(size_t)r * gridDim.x + blockIdx.x] = mk<double>(sum, 0.0);
@@ -170,7 +236,12 @@ static hipError_t launch_update_t(const DotArgsT<VT> &a, int nrhs, int nb, size_
                                   hipStream_t s) {
   if (nb > 64) return hipErrorInvalidValue;
   dim3 grid(kRedBlocks, nrhs);
-  k_update<VT><<<grid, 256, 0, s>>>(a, nb, n, nz, plane, wlev, h, hstride, hscale, sstride, part);
+  if (pairs_ok(a, nrhs, n))
+    k_update<VT, true><<<grid, 256, 0, s>>>(a, nb, n, nz, plane, wlev, h, hstride, hscale,
+                                             sstride, part);
+  else
+    k_update<VT, false><<<grid, 256, 0, s>>>(a, nb, n, nz, plane, wlev, h, hstride, hscale,
+                                              sstride, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_reduce<<<dim3(1, nrhs), 256, 0, s>>>(part, kRedBlocks, 1, nrm);
