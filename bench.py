@@ -142,8 +142,8 @@ def main():
                     help="only a 1 GiB device copy (counter calibration) and 3 FP64 applies, "
                          "for hardware-counter passes")
     ap.add_argument("--block-buffers", type=int, default=2,
-                    help="prefetch sets of the block product in --counter-run (the depth "
-                         "giem_tune chooses for FP64 on this workload)")
+                    help="block-product variant in --counter-run (1 or 2 prefetch sets, 3 = two "
+                         "workgroups per CU; giem_tune chooses 2 for FP64 on this workload)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
@@ -185,7 +185,7 @@ def main():
             h.apply(x, y, sa, prec=g.FP64)
         torch.cuda.synchronize()
         print(f"counter run done: copy 1073741824 B, 3 FP64 applies "
-              f"(block product with {args.block_buffers} prefetch sets)", flush=True)
+              f"(block-product variant {args.block_buffers})", flush=True)
         h.close()
         return
 

@@ -202,9 +202,10 @@ class Handle:
         return list(ms)
 
     def tune(self, sigma_a, nrhs=2, ifreq=0, stream=None):
-        """Time the FFT launch shapes and the block-product prefetch depth on
-        this handle and keep the fastest; returns {"fp64"|"fp32": [(sequences,
-        threads) per pass], "block_buffers": {"fp64"|"fp32": 1 or 2}}."""
+        """Time the FFT launch shapes and the block-product variants on this
+        handle and keep the fastest; returns {"fp64"|"fp32": [(sequences,
+        threads) per pass], "block_buffers": {"fp64"|"fp32": 1, 2 or 3}}
+        (see set_block_buffers)."""
         ch = (ctypes.c_int32 * 20)()
         _check(_lib.giem_tune(self._p, ifreq, _ptr(sigma_a), nrhs, _stream(stream), ch))
         out = {k: [(ch[(i * 5 + j) * 2], ch[(i * 5 + j) * 2 + 1]) for j in range(4)]
