@@ -186,11 +186,14 @@ int giem_apply_timed(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t
                      const void *x, void *y, uint32_t mode, uint32_t prec, void *stream,
                      double *stage_ms);
 
-/* giem_profile -- switch per-kernel event recording on (enable != 0) or off
-   for every later operator apply on this handle, including those inside
-   giem_solve and giem_adjoint, and discard what was recorded.  Recording adds
-   six hipEventRecord calls per apply and never synchronises.  Errors: EINVAL
-   (null handle). */
+/* giem_profile -- switch per-kernel event recording on or off for every
+   later operator apply on this handle, including those inside giem_solve and
+   giem_adjoint, and discard what was recorded.  enable: 0 off; 1 all five
+   kernels (six hipEventRecord calls per apply); 2 + k, k = 0 .. 4, only
+   kernel k in the order of giem_apply_timed (two calls per apply, which
+   perturbs a solve less: the six events cost about 2% of a GMRES solve on a
+   128 x 128 x 32 grid).  Never synchronises.  Errors: EINVAL (null handle or
+   enable outside 0 .. 6). */
 int giem_profile(giem_handle *t, int32_t enable);
 
 /* giem_tune -- choose launch shapes of the apply for this handle by timing
@@ -236,7 +239,8 @@ int giem_set_block_buffers(giem_handle *t, uint32_t prec, int32_t nbuf);
 /* giem_profile_read -- wait for the last recorded apply and report what was
    recorded since giem_profile or the previous read, then clear it:
      stage_ms[2][5]: summed kernel durations (ms) per precision (0 = FP64,
-                     1 = FP32) and per kernel in the order of giem_apply_timed;
+                     1 = FP32) and per kernel in the order of giem_apply_timed
+                     (zero for kernels that were not bracketed);
      applies[2], rhs[2]: number of applies and of right-hand sides in them.
    All pointers are host memory owned by the caller.  Errors: EINVAL, EHIP. */
 int giem_profile_read(giem_handle *t, double *stage_ms, int64_t *applies, int64_t *rhs);

@@ -226,8 +226,12 @@ class Handle:
         workgroup per CU, 3 = two workgroups per CU (0 = built-in, 1)."""
         _check(_lib.giem_set_block_buffers(self._p, prec, nbuf))
 
-    def profile(self, enable=True):
-        _check(_lib.giem_profile(self._p, 1 if enable else 0))
+    def profile(self, enable=True, stage=None):
+        """Record HIP events around the kernels of every later apply: all
+        five (stage None) or only kernel `stage` (0 .. 4, the order of
+        apply_timed), which adds two events per apply instead of six."""
+        code = 0 if not enable else (1 if stage is None else 2 + int(stage))
+        _check(_lib.giem_profile(self._p, code))
 
     def profile_read(self):
         """Summed kernel times per precision since the last read:

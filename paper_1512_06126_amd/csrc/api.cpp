@@ -171,22 +171,32 @@ static int apply_core_t(giem_handle *t, int nf, const int *ifreqs, int nrhs,
   // ones (read back later by giem_profile_read) while profiling is on.
   hipEvent_t own[6];
   hipEvent_t *ev = nullptr;
+  int only = -1;
   if (stage_ms) {
     for (int i = 0; i < 6; ++i) GIEM_HIP(hipEventCreate(&own[i]), "hipEventCreate");
     ev = own;
   } else if (t->prof) {
-    while (t->prof_ev.size() < t->prof_used + 6) {
+    const size_t need = t->prof_stage < 0 ? 6 : 2;
+    while (t->prof_ev.size() < t->prof_used + need) {
       hipEvent_t e;
       GIEM_HIP(hipEventCreate(&e), "hipEventCreate");
       t->prof_ev.push_back(e);
     }
     ev = t->prof_ev.data() + t->prof_used;
-    t->prof_used += 6;
+    t->prof_used += need;
     t->prof_meta.push_back((int)prec);
     t->prof_meta.push_back(nv);
+    t->prof_meta.push_back(t->prof_stage);
+    only = t->prof_stage;
   }
+  // event i is recorded before kernel i (and i = 5 after the last); with one
+  // kernel bracketed only its two events are recorded
   auto mark = [&](int i) -> int {
-    if (ev) GIEM_HIP(hipEventRecord(ev[i], s), "hipEventRecord");
+    if (!ev) return GIEM_OK;
+    if (only < 0)
+      GIEM_HIP(hipEventRecord(ev[i], s), "hipEventRecord");
+    else if (i == only || i == only + 1)
+      GIEM_HIP(hipEventRecord(ev[i - only], s), "hipEventRecord");
     return GIEM_OK;
   };
   const size_t cbytes = prec == PREC_FP32 ? sizeof(c64) : sizeof(c128);
@@ -779,11 +789,12 @@ int giem_set_block_buffers(giem_handle *t, uint32_t prec, int32_t nbuf) {
 }
 
 int giem_profile(giem_handle *t, int32_t enable) {
-  if (!t) {
-    set_error("null handle");
+  if (!t || enable < 0 || enable > 6) {
+    set_error("giem_profile: null handle or enable outside 0 .. 6");
     return GIEM_EINVAL;
   }
   t->prof = enable != 0;
+  t->prof_stage = enable >= 2 ? enable - 2 : -1;
   t->prof_used = 0;
   t->prof_meta.clear();
   return GIEM_OK;
@@ -796,18 +807,28 @@ int giem_profile_read(giem_handle *t, double *stage_ms, int64_t *applies, int64_
   }
   for (int i = 0; i < 10; ++i) stage_ms[i] = 0.0;
   for (int i = 0; i < 2; ++i) applies[i] = rhs[i] = 0;
-  const size_t napp = t->prof_used / 6;
+  const size_t napp = t->prof_meta.size() / 3;
   if (napp) GIEM_HIP(hipEventSynchronize(t->prof_ev[t->prof_used - 1]), "hipEventSynchronize");
+  size_t off = 0;
   for (size_t a = 0; a < napp; ++a) {
-    const int pr = t->prof_meta[2 * a] == PREC_FP32 ? 1 : 0;
-    const hipEvent_t *ev = t->prof_ev.data() + 6 * a;
-    for (int i = 0; i < 5; ++i) {
+    const int pr = t->prof_meta[3 * a] == PREC_FP32 ? 1 : 0;
+    const int only = t->prof_meta[3 * a + 2];
+    const hipEvent_t *ev = t->prof_ev.data() + off;
+    if (only < 0) {
+      for (int i = 0; i < 5; ++i) {
+        float ms = 0.f;
+        GIEM_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]), "hipEventElapsedTime");
+        stage_ms[5 * pr + i] += ms;
+      }
+      off += 6;
+    } else {
       float ms = 0.f;
-      GIEM_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]), "hipEventElapsedTime");
-      stage_ms[5 * pr + i] += ms;
+      GIEM_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]), "hipEventElapsedTime");
+      stage_ms[5 * pr + only] += ms;
+      off += 2;
     }
     applies[pr] += 1;
-    rhs[pr] += t->prof_meta[2 * a + 1];
+    rhs[pr] += t->prof_meta[3 * a + 1];
   }
   t->prof_used = 0;
   t->prof_meta.clear();

@@ -75,10 +75,12 @@ struct giem_handle {
   // register sets of prefetched points in the block product per precision
   // (1 or 2), set by giem_tune; 0 selects the built-in choice
   int block_nbuf[2] = {};
-  // stage profiling (giem_profile): 6 events per recorded apply
+  // stage profiling (giem_profile): 6 events per recorded apply, or 2 when
+  // only one kernel (prof_stage >= 0) is bracketed
   bool prof = false;
+  int prof_stage = -1;
   std::vector<hipEvent_t> prof_ev;
-  std::vector<int> prof_meta;  // per recorded apply: precision, nrhs
+  std::vector<int> prof_meta;  // per recorded apply: precision, nrhs, stage (-1: all)
   size_t prof_used = 0;
 
   size_t ncell() const { return (size_t)nx * ny * nz; }

@@ -199,3 +199,29 @@ def test_apply_gather_block_product(lib, nx, ny, nz, nrhs, prec, tol):
     err = rel_err(yd.cpu().numpy(), ref)
     h.close()
     assert err <= tol, err
+
+
+def test_profile_modes(lib):
+    # all five kernels bracketed, then only the block product: the same number
+    # of applies and RHS, only stage 2 filled in the second mode
+    import torch
+    m, t, rng = _case(16, 16, 4, 8)
+    h = lib.tables_import(m, [m["freq"]], t[None])
+    x = to_dev(gs.random_vector(rng, 2, 4, 16, 16))
+    y = torch.empty_like(x)
+    sa = to_dev(m["sigma_a"])
+    h.profile(True)
+    for _ in range(3):
+        h.apply(x, y, sa)
+    p_all = h.profile_read()["fp64"]
+    h.profile(True, stage=2)
+    for _ in range(3):
+        h.apply(x, y, sa)
+    p_one = h.profile_read()["fp64"]
+    h.profile(False)
+    assert p_all["applies"] == p_one["applies"] == 3 and p_all["rhs"] == p_one["rhs"] == 6
+    assert all(v > 0 for v in p_all["stage_ms"])
+    assert p_one["stage_ms"][2] > 0 and all(p_one["stage_ms"][k] == 0 for k in (0, 1, 3, 4))
+    with pytest.raises(lib.GiemError):
+        h.profile(True, stage=5)
+    h.close()
