@@ -241,27 +241,34 @@ k_fft_x_fwd(VecPtrsT<VT> ptrs, const c128 *__restrict__ r2, cplx<T> *__restrict_
   const int rp0 = blockIdx.y * G;
   const int p3 = 3 * nz;
   const size_t plane = (size_t)nx * ny;
-  // all global loads of a thread are issued before its LDS stores
-  c128 va[EPT], vs[EPT];
+  // only the first nx of the L = 2 nx entries of a sequence are nonzero: the
+  // G nx loads are spread over all threads, the padding is zero-filled
+  constexpr int EH = (EPT + 1) / 2;
+  c128 va[EH], vs[EH];
 #pragma unroll
-  for (int u = 0; u < EPT; ++u) {
+  for (int u = 0; u < EH; ++u) {
     const int e = threadIdx.x + u * NT;
-    const int g = e / L, xx = e - g * L;
+    const int g = e / nx, xx = e - g * nx;
     const int rp = rp0 + g;
     va[u] = mk<double>(0, 0);
     vs[u] = mk<double>(1, 0);
-    if (e < G * L && xx < nx && rp < rp_total) {
+    if (e < G * nx && rp < rp_total) {
       const int r = rp / p3, p = rp - r * p3;
       const int iz = p % nz;
       va[u] = ccast<double>(ptrs.in[r][(size_t)p * plane + (size_t)y * nx + xx]);
       if (r2) vs[u] = r2[(size_t)iz * plane + (size_t)y * nx + xx];
     }
   }
+  const int npad = L - nx;
+  for (int e = threadIdx.x; e < G * npad; e += NT) {
+    const int g = e / npad, xx = nx + (e - g * npad);
+    buf[g * ld + lds_pad(xx)] = mk<T>(0, 0);
+  }
 #pragma unroll
-  for (int u = 0; u < EPT; ++u) {
+  for (int u = 0; u < EH; ++u) {
     const int e = threadIdx.x + u * NT;
-    if (e < G * L) {
-      const int g = e / L, xx = e - g * L;
+    if (e < G * nx) {
+      const int g = e / nx, xx = e - g * nx;
       buf[g * ld + lds_pad(xx)] = ccast<T>(cmul(va[u], vs[u]));
     }
   }
