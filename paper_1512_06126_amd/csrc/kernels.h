@@ -10,8 +10,6 @@ namespace giem {
 // operator apply (kernels_apply.hip)
 hipError_t set_lds_limits();
 hipError_t set_block_lds_limits();
-int block_threads(int nz, int R);
-size_t block_lds_bytes(int nz, int R, int prec);
 bool block_supported(int nz, int R);
 size_t fft_lds_bytes(int G, int L, int prec);
 // elements per thread for G sequences of length L on nthr threads; 0 when no

@@ -763,19 +763,6 @@ hipError_t set_block_lds_limits() {
   return e;
 }
 
-int block_threads(int nz, int R) {
-  (void)nz;
-  (void)R;
-  return 256;
-}
-
-size_t block_lds_bytes(int nz, int R, int prec) {
-  (void)nz;
-  (void)R;
-  (void)prec;
-  return 0;
-}
-
 bool block_supported(int nz, int R) { return nz >= 1 && 2 * nz * (2 * nz + 1) < (1 << 24) && R >= 1 && R <= kMaxRhs; }
 
 std::vector<unsigned> block_plan(int nz) {
