@@ -316,26 +316,44 @@ k_fft_x_inv(VecPtrsT<VT> ptrs, const c128 *__restrict__ sdiag, const c128 *__res
   }
   fft_lds<T, EPT, POW2>(buf, G, ld, fd, tw, true);
   // epilogue: the diagonal terms are loaded after the transform, so that
-  // they do not hold registers across it
+  // they do not hold registers across it; every load of a thread is issued
+  // before any of them is used (from a clamped address where an output is
+  // outside the grid), and only the stores are conditional
   constexpr int EO = (EPT + 1) / 2;  // G * nx <= G * L / 2 outputs
+  c128 dr[EO], ds[EO], xin[EO];
+  size_t offs[EO];
+  int rr[EO];
+  bool okk[EO];
 #pragma unroll
   for (int u = 0; u < EO; ++u) {
     const int e = threadIdx.x + u * NT;
     const int g = e / nx, xx = e - g * nx;
     const int rp = rp0 + g;
-    if (e < G * nx && rp < rp_total) {
-      const int r = rp / p3, p = rp - r * p3;
-      const size_t off = (size_t)p * plane + (size_t)y * nx + xx;
+    okk[u] = e < G * nx && rp < rp_total;
+    const int rpc = okk[u] ? rp : 0, xc = okk[u] ? xx : 0;
+    const int r = rpc / p3, p = rpc - r * p3;
+    rr[u] = r;
+    offs[u] = (size_t)p * plane + (size_t)y * nx + xc;
+    if (r1) {
+      const size_t cell = (size_t)(p % nz) * plane + (size_t)y * nx + xc;
+      dr[u] = r1[cell];
+      ds[u] = sdiag[cell];
+      xin[u] = ccast<double>(ptrs.in[r][offs[u]]);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < EO; ++u) {
+    const int e = threadIdx.x + u * NT;
+    if (okk[u]) {
+      const int g = e / nx, xx = e - g * nx;
       c128 b = ccast<double>(buf[g * ld + lds_pad(xx)]);
       b = cscale(b, scale);
       c128 out = b;
       if (r1) {
-        const int iz = p % nz;
-        const size_t cell = (size_t)iz * plane + (size_t)y * nx + xx;
-        out = cmul(r1[cell], b);
-        cfma(out, sdiag[cell], ccast<double>(ptrs.in[r][off]));
+        out = cmul(dr[u], b);
+        cfma(out, ds[u], xin[u]);
       }
-      ptrs.out[r][off] = ccast<typename VTraits<VT>::elem>(out);
+      ptrs.out[rr[u]][offs[u]] = ccast<typename VTraits<VT>::elem>(out);
     }
   }
 }
