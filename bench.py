@@ -160,7 +160,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
-    model = gs.config_baseline()
+    model = gs.config_128x128x32()
     nx, ny, nz = model["nx"], model["ny"], model["nz"]
     R = 2
     f = model["freq"]

@@ -152,7 +152,7 @@ def config_layered(nx, ny, nz, hx, hy, hz, seed, freq, n_earth_layers=5,
     return m
 
 
-def config_baseline(seed=2):
+def config_128x128x32(seed=2):
     """128 x 128 x 32 cells of 200 x 200 x 100 m, f = 0.01 Hz."""
     return config_layered(128, 128, 32, 200.0, 200.0, 100.0, seed, 0.01)
 

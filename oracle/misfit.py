@@ -1,7 +1,7 @@
 """Impedance tensor, misfit and its gradient with respect to log sigma_a.
 Test infrastructure.
 
-The benchmark of Sect. 4 is judged through the impedance of the x and y
+The benchmark of Sect. 4 is compared through the impedance of the x and y
 plane-wave polarisations (apparent resistivity is |Z|^2 / (w mu0)).  An
 inversion built on the solver needs the misfit
     phi = sum_f sum_q sum_ij |Z_ij(f, q) - Zobs_ij(f, q)|^2

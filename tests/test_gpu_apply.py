@@ -94,7 +94,7 @@ def test_rejects_non_smooth_sizes_and_bad_models(lib):
 def full_case():
     """The 128 x 128 x 32 layered workload (2 RHS) with a random table."""
     from oracle import packed
-    m = gs.config_baseline()
+    m = gs.config_128x128x32()
     rng = np.random.default_rng(77)
     t = gs.random_packed_table(rng, m["nx"], m["ny"], m["nz"], decay=0.2)
     d = dense.cie_diagonals(m)
