@@ -152,3 +152,29 @@ def test_batched_solve_equals_separate_solves(lib):
               flush=True)
         assert err <= 1e-7
     h.close()
+
+
+def test_batched_solve_more_frequencies_than_one_launch(lib):
+    # 18 frequencies: the applies of a step need two launches per kernel (at
+    # most 16 frequencies share one); the batch must equal separate solves
+    import torch
+    rng = np.random.default_rng(405)
+    m = gs.make_model(6, 5, 3, 100.0, 120.0, np.arange(4) * 50.0, [0.0, 100.0, 900.0],
+                      [0.0, 0.02, 0.2, 0.004], 1.0)
+    m["sigma_a"] = m["sigma_a"] * 10 ** rng.uniform(0, 2, m["sigma_a"].shape)
+    freqs = list(np.logspace(-2, 1, 18))
+    h = lib.tables(m, freqs)
+    sa = to_dev(m["sigma_a"])
+    shape = (2, 3, 3, 5, 6)
+    bat = [torch.zeros(shape, dtype=torch.complex128, device="cuda") for _ in freqs]
+    st = h.solve_batch(sa, bat, tol=1e-12, max_iter=4000)
+    assert all(s["converged"] == 1 for s in st)
+    worst = 0.0
+    for q in range(len(freqs)):
+        sep = torch.zeros(shape, dtype=torch.complex128, device="cuda")
+        s1 = h.solve(sa, sep, tol=1e-12, max_iter=4000, ifreq=q)
+        assert s1["converged"] == 1
+        worst = max(worst, float(torch.linalg.vector_norm(bat[q] - sep) / torch.linalg.vector_norm(sep)))
+    h.close()
+    print(f"  18 frequencies: batched vs separate, worst {worst:.1e}", flush=True)
+    assert worst <= 1e-12
