@@ -1,7 +1,7 @@
 """Pins of the oracle's fundamental functions (Appendix B problem) and of its
 Galerkin tables (Sect. 3.1, Appendix A) against what the mathematics fixes:
-the whole-space closed form, the jump and interface conditions, reciprocity
-and the storage symmetries of Lemma 1 and Lemma 2."""
+the whole-space closed form, the whole-space sum rule, the jump and interface
+conditions, reciprocity and the storage symmetries of Lemma 1 and Lemma 2."""
 import numpy as np
 import pytest
 
@@ -117,6 +117,43 @@ def test_tables_other_v3_reading_fails_whole_space(monkeypatch):
     monkeypatch.setattr(vertical, "vertical_functions", planted)
     m = _ws_model()
     assert _ws_errors(tables.build_tables(m), m) > 1e-3
+
+
+# Whole space with cells much larger than the skin depth: the Green's tensor
+# integrates to -I / sigma over all of space (a uniform current j drives the
+# constant field E = -j / sigma: curl curl E - k^2 E = i w mu0 j with
+# k^2 = i w mu0 sigma), so summing B(n, m) over every source cell m of a
+# lattice that tiles space gives -V_n I / sigma.  The window of +-K cells
+# around n leaves out terms that decay like exp(-L / delta), L / delta > 20
+# here.  Self and touching pairs carry most of the sum: these are the pairs
+# the separated-cell closed form cannot reach.
+_SUM_K = 4
+_SUM_HZ = np.array([90.0, 110.0, 95.0, 120.0, 100.0, 85.0, 115.0, 105.0, 92.0])
+
+
+def _sum_rule_deviation():
+    hx, hy, sig = 100.0, 130.0, 0.5
+    delta = min(hx, hy, _SUM_HZ.min()) / 5.0            # skin depth
+    freq = 2.0 / (delta ** 2 * wholespace.MU0 * sig) / (2 * np.pi)
+    m = dict(nx=_SUM_K + 1, ny=_SUM_K + 1, nz=_SUM_HZ.size, hx=hx, hy=hy,
+             z_edges=np.concatenate([[0.0], np.cumsum(_SUM_HZ)]), d=np.array([0.0]),
+             sigma=np.array([sig, sig], complex), freq=freq)
+    B = tables.build_tables(m)
+    S = B[:, :, :, :, _SUM_K, :].sum(axis=(0, 1, 4))     # observation cell in the middle
+    return np.abs(S / (-hx * hy * _SUM_HZ[_SUM_K] / sig) - np.eye(3)).max()
+
+
+def test_tables_whole_space_sum_rule():
+    assert _sum_rule_deviation() <= 1e-7          # seen 3.2e-9
+
+
+def test_tables_unresolved_singularity_fails_sum_rule(monkeypatch):
+    # Planted mistake: treat the lateral integrand as smooth at the vertex
+    # where it is singular (plain tensor Gauss instead of the graded rule).
+    # Only self and touching pairs change; the sum rule must see it.
+    monkeypatch.setattr(tables, "_duffy_rect",
+                        lambda x0, x1, y0, y1, px, py, n: tables._tensor_rect(x0, x1, y0, y1, 14))
+    assert _sum_rule_deviation() > 1e-5           # seen 4.6e-4
 
 
 @pytest.fixture(scope="module")
