@@ -77,6 +77,47 @@ def test_export_roundtrip(lib):
     h.close()
 
 
+def test_apply_argument_errors_leave_output_untouched(lib):
+    # empty and out-of-range arguments are refused on the host before any
+    # kernel writes y; a valid call afterwards still matches the oracle
+    import ctypes
+    import torch
+    nx, ny, nz = 5, 4, 2
+    m, t, rng = _case(nx, ny, nz, 8)
+    h = lib.tables_import(m, [m["freq"]], t[None])       # no complex64 tables
+    raw = lib.load()
+    x = to_dev(gs.random_vector(rng, 2, nz, ny, nx))
+    sentinel = torch.full((2, 3, nz, ny, nx), 7.0 + 1.0j, dtype=torch.complex128, device="cuda")
+    y = sentinel.clone()
+    sa = to_dev(m["sigma_a"])
+
+    def call(ifreq=0, nrhs=2, xp=x, yp=y, sap=sa, mode=lib.MODE_A, prec=lib.FP64):
+        ptr = lambda v: None if v is None else ctypes.c_void_p(v.data_ptr())
+        return raw.giem_apply(h._p, ifreq, ptr(sap), nrhs, ptr(xp), ptr(yp), mode, prec, None)
+
+    assert call(nrhs=0) == lib.GIEM_EINVAL                 # no right-hand side
+    assert call(nrhs=-1) == lib.GIEM_EINVAL
+    assert call(nrhs=9) == lib.GIEM_EINVAL                 # more than 8
+    assert call(ifreq=1) == lib.GIEM_EINVAL                # one frequency only
+    assert call(ifreq=-1) == lib.GIEM_EINVAL
+    assert call(mode=3) == lib.GIEM_EINVAL
+    assert call(prec=2) == lib.GIEM_EINVAL
+    assert call(xp=None) == lib.GIEM_EINVAL
+    assert call(yp=None) == lib.GIEM_EINVAL
+    assert call(sap=None) == lib.GIEM_EINVAL               # mode A needs sigma_a
+    assert call(yp=x) == lib.GIEM_EINVAL                   # x and y overlap
+    assert call(prec=lib.FP32) == lib.GIEM_EINVAL          # complex64 tables absent
+    torch.cuda.synchronize()
+    assert torch.equal(y, sentinel)
+    assert call(sap=None, mode=lib.MODE_B) == lib.GIEM_OK  # mode B ignores sigma_a
+    assert call() == lib.GIEM_OK
+    torch.cuda.synchronize()
+    ref = dense.apply_direct(dense.dense_from_packed(t, m), dense.cie_diagonals(m),
+                             x.cpu().numpy(), "A")
+    assert rel_err(y.cpu().numpy(), ref) <= 1e-10
+    h.close()
+
+
 def test_rejects_non_smooth_sizes_and_bad_models(lib):
     m, t, _ = _case(11, 4, 2, 5)
     with pytest.raises(lib.GiemError):

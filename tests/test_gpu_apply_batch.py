@@ -160,6 +160,8 @@ def test_apply_batch_errors(lib):
     assert call(2, [0, -1], 1, x, y) == lib.GIEM_EINVAL
     assert call(2, [0, 1], 9, x, y) == lib.GIEM_EINVAL           # more than 8 RHS
     assert call(2, [0, 1], 1, x, x) == lib.GIEM_EINVAL           # x and y overlap
+    assert call(0, [], 1, x, y) == lib.GIEM_EINVAL               # no frequency
+    assert call(2, [0, 1], 0, x, y) == lib.GIEM_EINVAL           # no right-hand side
     assert call(2, [0, 1], 1, x, y) == lib.GIEM_OK
     torch.cuda.synchronize()
     h.close()
