@@ -2,6 +2,8 @@
 mathematics fix: storage symmetry (Sect. 3.1), table size (8x claim), the
 relation between the scaled and the physical system (Sect. 2.2), the
 sigma_a = sigma_b special case, and the 1-D normal field."""
+import os
+
 import numpy as np
 import pytest
 
@@ -36,6 +38,45 @@ def test_table_sizes_eight_fold():
     assert packed.packed_table_bytes(nx, ny, nz) == 2 * 128 * 128 * 32 * 65 * 16
     r32 = 32 * nx * ny * nz * nz * 16 / packed.packed_table_bytes(nx, ny, nz)
     assert abs(r32 - 8 * 2 * nz / (2 * nz + 1)) < 1e-12 and 7.8 < r32 < 8.0
+
+
+def _storage_golden():
+    path = os.path.join(os.path.dirname(__file__), "golden", "storage_bytes.txt")
+    forms = {}
+    with open(path) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                tok = line.split()
+                forms[tok[0]] = tuple(int(v) for v in tok[1:3]) if tok[0] != "factor" else int(tok[1])
+    return forms
+
+
+def _golden_bytes(form, nx, ny, nz):
+    a, b = form
+    return 16 * nx * ny * (a * nz * nz + b * nz)
+
+
+@pytest.mark.parametrize("nx,ny,nz", [(3, 2, 1), (5, 4, 3), (6, 3, 4)])
+def test_storage_matches_paper_figures(nx, ny, nz):
+    # the counts printed in Sect. 3.1 against what the oracle actually holds:
+    # its unpacked spectral blocks (4 Nx Ny offsets of the cyclic embedding,
+    # 9 Nz x Nz blocks), the same with the yx block dropped (it equals xy,
+    # Lemma 1) and the packed table (Lemmas 1 and 2), which unpacks and packs
+    # back unchanged
+    from oracle import fft_apply, tables
+    g = _storage_golden()
+    t = gs.random_packed_table(np.random.default_rng(nx + ny + nz), nx, ny, nz)
+    qhat = fft_apply.spectral_blocks(t, nz).reshape(2 * ny, 2 * nx, 3, nz, 3, nz)
+    assert qhat.size * 16 == _golden_bytes(g["unpacked"], nx, ny, nz)
+    assert np.allclose(qhat[:, :, 1, :, 0], qhat[:, :, 0, :, 1], rtol=0, atol=1e-12 * np.abs(qhat).max())
+    assert 8 * (qhat.size // 9) * 16 == _golden_bytes(g["symmetric"], nx, ny, nz)
+    assert np.array_equal(tables.pack(packed.full_tensor_signed(t, nz), nx, ny, nz), t)
+    assert t.size * 16 == _golden_bytes(g["packed"], nx, ny, nz)
+    # the reduction approaches the printed factor from below as Nz grows
+    ratios = [_golden_bytes(g["symmetric"], 1, 1, k) / _golden_bytes(g["packed"], 1, 1, k)
+              for k in (1, 4, 32, 10 ** 4)]
+    assert all(r < g["factor"] for r in ratios) and ratios == sorted(ratios)
+    assert abs(ratios[-1] - g["factor"]) < 1e-3
 
 
 def test_unpacked_tensor_satisfies_lemmas():
