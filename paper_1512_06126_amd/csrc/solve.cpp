@@ -288,6 +288,12 @@ static int gmres(giem_handle *t, const std::vector<int> &fq, int nrhs, const VT 
   c128 *part = static_cast<c128 *>(t->red_part);
   c128 *hhost = static_cast<c128 *>(t->red_host);
   c128 *chost = static_cast<c128 *>(t->coef_host);
+  hipEvent_t step_ev = nullptr;
+  GIEM_HIP(hipEventCreateWithFlags(&step_ev, hipEventDisableTiming), "hipEventCreate");
+  struct EvFree {
+    hipEvent_t e;
+    ~EvFree() { hipEventDestroy(e); }
+  } ev_free{step_ev};
   while (true) {
     // residual r0 = b - A x into V(r, 0)
     std::vector<int> act;
@@ -337,17 +343,22 @@ static int gmres(giem_handle *t, const std::vector<int> &fq, int nrhs, const VT 
     ++res.restarts;
     std::vector<int> jlen(nrhs, 0);
     std::vector<int> running = cyc;
-    for (int j = 0; j < m && !running.empty(); ++j) {
-      if (iters >= gp.max_iter) break;
-      const int na = (int)running.size();
-      // w = A v_j into V(r, j+1)
+    // w = A v_j into V(r, j+1) for the systems in `running`
+    auto apply_step = [&](int j) -> int {
       std::vector<const VT *> in;
       std::vector<VT *> out;
       for (int r : running) {
         in.push_back(V(r, j));
         out.push_back(V(r, j + 1));
       }
-      GIEM_TRY(apply_sys(t, fq, running, in, out, gp.mode, gp.prec, s));
+      return apply_sys(t, fq, running, in, out, gp.mode, gp.prec, s);
+    };
+    bool ahead = false;  // the apply of step j is already on the stream
+    for (int j = 0; j < m && !running.empty(); ++j) {
+      if (iters >= gp.max_iter) break;
+      const int na = (int)running.size();
+      if (!ahead) GIEM_TRY(apply_step(j));
+      ahead = false;
       ++iters;
       // classical Gram-Schmidt, repeated once when the norm drops sharply
       // (cancellation of more than a factor 10)
@@ -376,7 +387,20 @@ static int gmres(giem_handle *t, const std::vector<int> &fq, int nrhs, const VT 
         }
         GIEM_HIP(hipMemcpyAsync(hhost, hdev, (size_t)na * (nb + 1) * sizeof(c128), hipMemcpyDeviceToHost, s), "copy h");
         GIEM_HIP(hipMemcpyAsync(chost, ndev, (size_t)na * sizeof(c128), hipMemcpyDeviceToHost, s), "copy norm");
-        GIEM_HIP(hipStreamSynchronize(s), "sync");
+        if (pass == 0 && j + 1 < m && iters < gp.max_iter) {
+          // The next step's apply needs only the new (unnormalised) basis
+          // vector, which is final unless a second pass follows: queue it
+          // behind the copies and wait for the copies alone, so the GPU
+          // works while the host updates the Hessenberg column.  It is
+          // wasted for a system that stops here, and redone after a second
+          // pass.
+          GIEM_HIP(hipEventRecord(step_ev, s), "hipEventRecord");
+          GIEM_TRY(apply_step(j + 1));
+          ahead = true;
+          GIEM_HIP(hipEventSynchronize(step_ev), "sync");
+        } else {
+          GIEM_HIP(hipStreamSynchronize(s), "sync");
+        }
         bool again = false;
         for (int q = 0; q < na; ++q) {
           const std::vector<double> &nq_ = vn[running[q]];
@@ -388,6 +412,7 @@ static int gmres(giem_handle *t, const std::vector<int> &fq, int nrhs, const VT 
           if (nw1[q] < kReorthDrop * nw0[q]) again = true;
         }
         if (!again) break;
+        ahead = false;  // the second pass changes the vector the apply read
         for (int q = 0; q < na; ++q) nw0[q] = nw1[q];
       }
       std::vector<int> still;
