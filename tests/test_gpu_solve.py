@@ -48,6 +48,44 @@ def test_solve_fp64_matches_lu(lib, nx, ny, nz):
     h.close()
 
 
+def test_second_gram_schmidt_pass(lib):
+    # sigma_a = 3 sigma_b in every cell makes S = I/2, and the table is
+    # scaled so that R1 B R2 is a few percent of it: each new Krylov vector
+    # is nearly parallel to the last, the projection removes more than 99.9%
+    # of its squared norm (checked below on the oracle's matrix), and every
+    # Arnoldi step takes the second Gram-Schmidt pass, which discards the
+    # apply already queued for the next step and redoes it.
+    import torch
+    nx, ny, nz = 6, 5, 3
+    rng = np.random.default_rng(321)
+    m = random_model(nx, ny, nz, 321, contrast=0.0)
+    m["sigma_a"] = 3.0 * m["sigma_a"]
+    t = gs.random_packed_table(rng, nx, ny, nz, decay=0.2)
+    d = dense.cie_diagonals(m)
+    assert np.allclose(d["S"], 0.5)
+    n3 = 3 * nx * ny * nz
+    t = t * (0.04 / (np.abs(d["R1"]).max() * np.abs(d["R2"]).max() * 2 * np.sqrt(n3)))
+    rhs = gs.random_vector(rng, 2, nz, ny, nx)
+    A = dense.system_matrix(dense.dense_from_packed(t, m), d)
+    for r in range(2):
+        V = [rhs[r].reshape(-1) / np.linalg.norm(rhs[r])]
+        for _ in range(4):
+            w = A @ V[-1]
+            Q = np.stack(V, 1)
+            res = w - Q @ (Q.conj().T @ w)
+            assert np.vdot(res, res).real < 1e-3 * np.vdot(w, w).real
+            V.append(res / np.linalg.norm(res))
+    ref = _oracle_E(m, t, rhs)
+    h = lib.tables_import(m, [m["freq"]], t[None])
+    E = torch.empty((2, 3, nz, ny, nx), dtype=torch.complex128, device="cuda")
+    st = h.solve(to_dev(m["sigma_a"]), E, rhs=to_dev(rhs), tol=1e-13, restart=30, max_iter=100)
+    assert st["converged"] == 1, st
+    assert st["iters"] >= 5, st
+    err = rel_err(E.cpu().numpy(), ref)
+    assert err <= 1e-10, (err, st)
+    h.close()
+
+
 def test_plane_wave_rhs_matches_oracle(lib):
     import torch
     nx, ny, nz = 8, 6, 3
