@@ -52,6 +52,31 @@ def test_tables_match_oracle(lib, name):
     assert max(errs.values()) <= TAU_TAB, errs
 
 
+def test_tables_whole_space_sum_rule(lib):
+    # the library's tables alone, no oracle table: in a whole space whose
+    # cells are five skin depths across, the coefficients of one observation
+    # cell summed over all source cells give -V_n I / sigma (the Green's
+    # tensor integrates to -I / sigma); the +-4-cell window leaves out terms
+    # of order exp(-22).  Self and touching pairs carry most of the sum.
+    from oracle import packed
+    K = 4
+    hz = np.array([90.0, 110.0, 95.0, 120.0, 100.0, 85.0, 115.0, 105.0, 92.0])
+    hx, hy, sig = 100.0, 130.0, 0.5
+    delta = min(hx, hy, hz.min()) / 5.0
+    freq = 2.0 / (delta ** 2 * 4e-7 * np.pi * sig) / (2 * np.pi)
+    m = dict(nx=K + 1, ny=K + 1, nz=hz.size, hx=hx, hy=hy,
+             z_edges=np.concatenate([[0.0], np.cumsum(hz)]), d=np.array([0.0]),
+             sigma=np.array([sig, sig], complex), freq=freq)
+    h = lib.tables(_lib_model(m), [freq])
+    t = h.export(0)
+    h.close()
+    B = packed.full_tensor_signed(t, m["nz"])           # [2Ny-1][2Nx-1][3][3][Nz][Nz]
+    S = B[:, :, :, :, K, :].sum(axis=(0, 1, 4))
+    dev = float(np.abs(S / (-hx * hy * hz[K] / sig) - np.eye(3)).max())
+    print(f"  sum-rule deviation {dev:.3e}", flush=True)
+    assert dev <= 1e-7, dev
+
+
 def test_tables_air_limit(lib):
     # sigma_0 = 0 (the limit p = -1) against a tiny air conductivity
     m = dict(MODELS["layered_air"])
