@@ -220,6 +220,35 @@ def test_every_fft_shape_matches_dense(lib, nx, ny, nz, nrhs):
     h.close()
 
 
+@pytest.mark.parametrize("nz", [31, 32])
+def test_block_product_every_rhs_count_at_deepest_grids(lib, nz):
+    # the deepest grids the pipelined block product stages, with every
+    # right-hand-side count up to the maximum of 8: the row and the input
+    # fragments outgrow the LDS somewhere in between and the launcher falls
+    # back (two workgroups per CU -> one, pipelined -> gather); every variant
+    # on both sides of that boundary matches the dense product
+    import torch
+    nx, ny = 2, 3
+    m, t, rng = _case(nx, ny, nz, 600 + nz)
+    h = lib.tables_import(m, [m["freq"]], t[None], flags=lib.TABLES_C64)
+    B = dense.dense_from_packed(t, m)
+    d = dense.cie_diagonals(m)
+    sa = to_dev(m["sigma_a"])
+    x = gs.random_vector(rng, 8, nz, ny, nx)
+    ref = dense.apply_direct(B, d, x, "A")
+    for nrhs in range(1, 9):
+        xd = to_dev(x[:nrhs])
+        yd = torch.empty_like(xd)
+        for prec, tol in ((lib.FP64, 1e-10), (lib.FP32, 2e-5)):
+            for nbuf in (1, 2, 3):
+                h.set_block_buffers(prec, nbuf)
+                h.apply(xd, yd, sa, mode=lib.MODE_A, prec=prec)
+                torch.cuda.synchronize()
+                err = rel_err(yd.cpu().numpy(), ref[:nrhs])
+                assert err <= tol, (nrhs, prec, nbuf, err)
+    h.close()
+
+
 @pytest.mark.parametrize("nx,ny,nz,nrhs", [(4, 3, 40, 2), (3, 2, 32, 8), (2, 3, 33, 1)])
 @pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 2e-5)])
 def test_apply_gather_block_product(lib, nx, ny, nz, nrhs, prec, tol):
