@@ -48,7 +48,8 @@ def test_solve_fp64_matches_lu(lib, nx, ny, nz):
     h.close()
 
 
-def test_second_gram_schmidt_pass(lib):
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_second_gram_schmidt_pass(lib, prec):
     # sigma_a = 3 sigma_b in every cell makes S = I/2, and the table is
     # scaled so that R1 B R2 is a few percent of it: each new Krylov vector
     # is nearly parallel to the last, the projection removes more than 99.9%
@@ -76,13 +77,22 @@ def test_second_gram_schmidt_pass(lib):
             assert np.vdot(res, res).real < 1e-3 * np.vdot(w, w).real
             V.append(res / np.linalg.norm(res))
     ref = _oracle_E(m, t, rhs)
-    h = lib.tables_import(m, [m["freq"]], t[None])
+    h = lib.tables_import(m, [m["freq"]], t[None], flags=lib.TABLES_C64)
     E = torch.empty((2, 3, nz, ny, nx), dtype=torch.complex128, device="cuda")
-    st = h.solve(to_dev(m["sigma_a"]), E, rhs=to_dev(rhs), tol=1e-13, restart=30, max_iter=100)
+    if prec == "fp64":
+        st = h.solve(to_dev(m["sigma_a"]), E, rhs=to_dev(rhs), tol=1e-13, restart=30,
+                     max_iter=100)
+        assert st["iters"] >= 5, st
+        bar = 1e-10
+    else:
+        # the complex64 inner solves of the precision form take the same
+        # second passes
+        st = h.solve(to_dev(m["sigma_a"]), E, rhs=to_dev(rhs), tol=1e-10, precision=lib.FP32,
+                     inner_tol=1e-4, max_iter=200)
+        bar = 1e-8
     assert st["converged"] == 1, st
-    assert st["iters"] >= 5, st
     err = rel_err(E.cpu().numpy(), ref)
-    assert err <= 1e-10, (err, st)
+    assert err <= bar, (err, st)
     h.close()
 
 
