@@ -192,7 +192,8 @@ int giem_apply_timed(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t
    kernels (six hipEventRecord calls per apply); 2 + k, k = 0 .. 4, only
    kernel k in the order of giem_apply_timed (two calls per apply, which
    perturbs a solve less: the six events cost about 2% of a GMRES solve on a
-   128 x 128 x 32 grid).  Never synchronises.  Errors: EINVAL (null handle or
+   128 x 128 x 32 grid).  The events only time: they are recorded without a
+   system-scope fence.  Never synchronises.  Errors: EINVAL (null handle or
    enable outside 0 .. 6). */
 int giem_profile(giem_handle *t, int32_t enable);
 

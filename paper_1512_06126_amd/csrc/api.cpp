@@ -178,8 +178,10 @@ static int apply_core_t(giem_handle *t, int nf, const int *ifreqs, int nrhs,
   } else if (t->prof) {
     const size_t need = t->prof_stage < 0 ? 6 : 2;
     while (t->prof_ev.size() < t->prof_used + need) {
+      // timing only: no system-scope fence (a full L2 write-back) when the
+      // event is recorded, which would stall the kernels around it
       hipEvent_t e;
-      GIEM_HIP(hipEventCreate(&e), "hipEventCreate");
+      GIEM_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence), "hipEventCreate");
       t->prof_ev.push_back(e);
     }
     ev = t->prof_ev.data() + t->prof_used;
