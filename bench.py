@@ -226,6 +226,8 @@ def main():
     # roofline of the dominant kernel, from the events of the timed region
     name = STAGES[dom]
     avg_ms = p64["stage_ms"][dom] / max(p64["applies"], 1)
+    # right-hand sides used per launch: the few vectors GMRES queued ahead
+    # and discarded are not counted, so the byte figure errs low
     avg_rhs = p64["rhs"] / max(p64["applies"], 1)
     bytes_launch = stage_bytes(nx, ny, nz, avg_rhs, 16)[name]
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9

@@ -242,7 +242,12 @@ int giem_set_block_buffers(giem_handle *t, uint32_t prec, int32_t nbuf);
      stage_ms[2][5]: summed kernel durations (ms) per precision (0 = FP64,
                      1 = FP32) and per kernel in the order of giem_apply_timed
                      (zero for kernels that were not bracketed);
-     applies[2], rhs[2]: number of applies and of right-hand sides in them.
+     applies[2]: number of applies (all launched ones);
+     rhs[2]:     right-hand sides in them whose results were used: GMRES
+                 queues each step's apply before the host has finished the
+                 previous step, and the vectors of a system that stops at
+                 that step, or of a step whose Gram-Schmidt pass is repeated,
+                 are discarded and not counted here.
    All pointers are host memory owned by the caller.  Errors: EINVAL, EHIP. */
 int giem_profile_read(giem_handle *t, double *stage_ms, int64_t *applies, int64_t *rhs);
 

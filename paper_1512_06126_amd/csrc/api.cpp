@@ -799,6 +799,7 @@ int giem_profile(giem_handle *t, int32_t enable) {
   t->prof_stage = enable >= 2 ? enable - 2 : -1;
   t->prof_used = 0;
   t->prof_meta.clear();
+  t->prof_discarded[0] = t->prof_discarded[1] = 0;
   return GIEM_OK;
 }
 
@@ -832,8 +833,10 @@ int giem_profile_read(giem_handle *t, double *stage_ms, int64_t *applies, int64_
     applies[pr] += 1;
     rhs[pr] += t->prof_meta[3 * a + 1];
   }
+  for (int i = 0; i < 2; ++i) rhs[i] = std::max<int64_t>(0, rhs[i] - t->prof_discarded[i]);
   t->prof_used = 0;
   t->prof_meta.clear();
+  t->prof_discarded[0] = t->prof_discarded[1] = 0;
   return GIEM_OK;
 }
 

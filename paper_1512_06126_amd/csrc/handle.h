@@ -82,6 +82,10 @@ struct giem_handle {
   std::vector<hipEvent_t> prof_ev;
   std::vector<int> prof_meta;  // per recorded apply: precision, nrhs, stage (-1: all)
   size_t prof_used = 0;
+  // right-hand sides of recorded applies whose results GMRES discarded (an
+  // apply queued ahead for a system that then stopped, or before a second
+  // Gram-Schmidt pass), per precision (FP64, FP32)
+  int64_t prof_discarded[2] = {0, 0};
 
   size_t ncell() const { return (size_t)nx * ny * nz; }
   size_t nvec() const { return 3 * ncell(); }

@@ -412,6 +412,7 @@ static int gmres(giem_handle *t, const std::vector<int> &fq, int nrhs, const VT 
           if (nw1[q] < kReorthDrop * nw0[q]) again = true;
         }
         if (!again) break;
+        if (ahead && t->prof) t->prof_discarded[gp.prec == PREC_FP32 ? 1 : 0] += na;
         ahead = false;  // the second pass changes the vector the apply read
         for (int q = 0; q < na; ++q) nw0[q] = nw1[q];
       }
@@ -451,6 +452,8 @@ static int gmres(giem_handle *t, const std::vector<int> &fq, int nrhs, const VT 
         const double est = std::abs(g[r][j + 1]);
         if (est > gp.tol * normb[r] && hn > 0.0) still.push_back(r);
       }
+      // the applies queued ahead for the systems that stop here are wasted
+      if (ahead && t->prof) t->prof_discarded[gp.prec == PREC_FP32 ? 1 : 0] += na - (int)still.size();
       running = still;
     }
     // x += V y, y = R^{-1} g (back substitution on the rotated Hessenberg)

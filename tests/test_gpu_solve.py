@@ -96,6 +96,44 @@ def test_second_gram_schmidt_pass(lib, prec):
     h.close()
 
 
+def _second_pass_case():
+    nx, ny, nz = 6, 5, 3
+    rng = np.random.default_rng(321)
+    m = random_model(nx, ny, nz, 321, contrast=0.0)
+    m["sigma_a"] = 3.0 * m["sigma_a"]
+    t = gs.random_packed_table(rng, nx, ny, nz, decay=0.2)
+    d = dense.cie_diagonals(m)
+    n3 = 3 * nx * ny * nz
+    t = t * (0.04 / (np.abs(d["R1"]).max() * np.abs(d["R2"]).max() * 2 * np.sqrt(n3)))
+    return m, t, rng
+
+
+@pytest.mark.parametrize("case", ["plain", "second_pass"])
+def test_profile_counts_only_used_applies(lib, case):
+    # GMRES queues each step's apply before the host has finished the step
+    # before; the profile counts every launch in "applies" but in "rhs" only
+    # the right-hand sides whose results were used: one per Arnoldi step and
+    # one residual per cycle (the first cycle starts from x = 0)
+    import torch
+    if case == "plain":
+        m, t, rng = _conditioned_case(8, 6, 3, 17)
+    else:
+        m, t, rng = _second_pass_case()
+    nz, ny, nx = m["sigma_a"].shape
+    rhs = gs.random_vector(rng, 1, nz, ny, nx)
+    h = lib.tables_import(m, [m["freq"]], t[None])
+    E = torch.empty((1, 3, nz, ny, nx), dtype=torch.complex128, device="cuda")
+    h.profile(True)
+    st = h.solve(to_dev(m["sigma_a"]), E, rhs=to_dev(rhs), tol=1e-12, restart=30, max_iter=500)
+    p = h.profile_read()["fp64"]
+    h.profile(False)
+    assert st["converged"] == 1, st
+    assert p["rhs"] == st["iters"] + st["outer_iters"], (p, st)
+    assert p["applies"] > p["rhs"], (p, st)     # at least the apply queued at convergence
+    assert rel_err(E.cpu().numpy(), _oracle_E(m, t, rhs)) <= 1e-10
+    h.close()
+
+
 def test_plane_wave_rhs_matches_oracle(lib):
     import torch
     nx, ny, nz = 8, 6, 3
