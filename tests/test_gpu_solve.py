@@ -48,6 +48,20 @@ def test_solve_fp64_matches_lu(lib, nx, ny, nz):
     h.close()
 
 
+def _second_pass_case():
+    """sigma_a = 3 sigma_b in every cell (S = I/2) and a table scaled to a few
+    percent of S: every Arnoldi step repeats the Gram-Schmidt pass."""
+    nx, ny, nz = 6, 5, 3
+    rng = np.random.default_rng(321)
+    m = random_model(nx, ny, nz, 321, contrast=0.0)
+    m["sigma_a"] = 3.0 * m["sigma_a"]
+    t = gs.random_packed_table(rng, nx, ny, nz, decay=0.2)
+    d = dense.cie_diagonals(m)
+    n3 = 3 * nx * ny * nz
+    t = t * (0.04 / (np.abs(d["R1"]).max() * np.abs(d["R2"]).max() * 2 * np.sqrt(n3)))
+    return m, t, rng
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_second_gram_schmidt_pass(lib, prec):
     # sigma_a = 3 sigma_b in every cell makes S = I/2, and the table is
@@ -57,15 +71,10 @@ def test_second_gram_schmidt_pass(lib, prec):
     # Arnoldi step takes the second Gram-Schmidt pass, which discards the
     # apply already queued for the next step and redoes it.
     import torch
-    nx, ny, nz = 6, 5, 3
-    rng = np.random.default_rng(321)
-    m = random_model(nx, ny, nz, 321, contrast=0.0)
-    m["sigma_a"] = 3.0 * m["sigma_a"]
-    t = gs.random_packed_table(rng, nx, ny, nz, decay=0.2)
+    m, t, rng = _second_pass_case()
+    nz, ny, nx = m["sigma_a"].shape
     d = dense.cie_diagonals(m)
     assert np.allclose(d["S"], 0.5)
-    n3 = 3 * nx * ny * nz
-    t = t * (0.04 / (np.abs(d["R1"]).max() * np.abs(d["R2"]).max() * 2 * np.sqrt(n3)))
     rhs = gs.random_vector(rng, 2, nz, ny, nx)
     A = dense.system_matrix(dense.dense_from_packed(t, m), d)
     for r in range(2):
@@ -94,18 +103,6 @@ def test_second_gram_schmidt_pass(lib, prec):
     err = rel_err(E.cpu().numpy(), ref)
     assert err <= bar, (err, st)
     h.close()
-
-
-def _second_pass_case():
-    nx, ny, nz = 6, 5, 3
-    rng = np.random.default_rng(321)
-    m = random_model(nx, ny, nz, 321, contrast=0.0)
-    m["sigma_a"] = 3.0 * m["sigma_a"]
-    t = gs.random_packed_table(rng, nx, ny, nz, decay=0.2)
-    d = dense.cie_diagonals(m)
-    n3 = 3 * nx * ny * nz
-    t = t * (0.04 / (np.abs(d["R1"]).max() * np.abs(d["R2"]).max() * 2 * np.sqrt(n3)))
-    return m, t, rng
 
 
 @pytest.mark.parametrize("case", ["plain", "second_pass"])
