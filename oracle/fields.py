@@ -152,7 +152,9 @@ def receiver_kernels(model, offsets, freq=None, z0=0.0, n_lam_panel=16, lam_asym
     nz = ze.size - 1
     offsets = np.atleast_2d(np.asarray(offsets, float))
     hmin = float(np.min(np.diff(ze)))
-    rho_min = 1e-7 * min(hx, hy)
+    # the radial functions of the receiver's own cell grow like 1 / rho; the
+    # clamp below rho_min costs a relative ~rho_min / h
+    rho_min = 1e-13 * min(hx, hy)
     rho_max = 1.05 * (np.max(np.hypot(np.abs(offsets[:, 0]) + hx, np.abs(offsets[:, 1]) + hy)))
     lam_asym = lam_asym_rel / hmin
     lam_lo = 1e-9 / max(rho_max, ze[-1])

@@ -21,6 +21,8 @@ samples.  Radial results are likewise sampled on Chebyshev panels in ln(rho).
 """
 from __future__ import annotations
 
+import functools
+
 import numpy as np
 from scipy import special
 
@@ -62,7 +64,7 @@ class LogPanels:
         hit = np.abs(d) < 1e-14
         with np.errstate(divide="ignore", invalid="ignore"):
             t = self.bw[None, :] / d
-        w = t / t.sum(axis=1, keepdims=True)
+            w = t / t.sum(axis=1, keepdims=True)
         rows_hit = hit.any(axis=1)
         if rows_hit.any():
             w[rows_hit] = hit[rows_hit].astype(float)
@@ -70,9 +72,22 @@ class LogPanels:
         return cols, w
 
 
+@functools.lru_cache(maxsize=None)
 def _gl(n):
     x, w = np.polynomial.legendre.leggauss(n)
     return x, w
+
+
+_ZEROS = {}
+
+
+def _jn_zeros(order, count):
+    """First count positive zeros of J_order (computed once, grown on demand)."""
+    z = _ZEROS.get(order)
+    if z is None or z.size < count:
+        z = special.jn_zeros(order, max(count, 2 * (0 if z is None else z.size), 64))
+        _ZEROS[order] = z
+    return z[:count]
 
 
 def _averaged_limit(S, levels=14):
@@ -85,7 +100,7 @@ def _averaged_limit(S, levels=14):
     return T[-1]
 
 
-def transform_weights(lp, rho, lam_a, lam_lo, lam_asym, ntail=30, n_gl=16, order=0):
+def transform_weights(lp, rho, lam_a, lam_lo, lam_asym, ntail=30, n_gl=16, order=0, n_gl0=12):
     """Weights over the samples of lp (LogPanels in lambda) such that
       main @ g  = int over [lam_lo, lambda_K] of J_order(lambda rho) g
       tail[k] @ g = integral over the k-th panel after lambda_K,
@@ -94,7 +109,7 @@ def transform_weights(lp, rho, lam_a, lam_lo, lam_asym, ntail=30, n_gl=16, order
     ncols = lp.size
     jn = special.j0 if order == 0 else special.j1
     K = int(np.ceil(lam_asym * rho / np.pi)) + 1
-    zeros = special.jn_zeros(order, K + ntail + 1) / rho
+    zeros = _jn_zeros(order, K + ntail + 1) / rho
     l1 = zeros[0]
     # geometric subpanels of [lam_lo, l1], with lam_a as a breakpoint
     brk = [l1]
@@ -102,7 +117,7 @@ def transform_weights(lp, rho, lam_a, lam_lo, lam_asym, ntail=30, n_gl=16, order
         brk.append(brk[-1] / 2.0)
     brk.append(lam_lo)
     brk = sorted(set(brk + ([lam_a] if lam_lo < lam_a < l1 else [])))
-    xg, wg = _gl(12)
+    xg, wg = _gl(n_gl0)
     pa = np.array(brk[:-1])[:, None]
     pb = np.array(brk[1:])[:, None]
     nod0 = (0.5 * (pa + pb) + 0.5 * (pb - pa) * xg[None, :]).ravel()
@@ -130,16 +145,18 @@ def transform_weights(lp, rho, lam_a, lam_lo, lam_asym, ntail=30, n_gl=16, order
         np.add.at(corr, c2.ravel(), (w0[sel][:, None] * i2).ravel())
     # tail panels
     tail = np.zeros((ntail, ncols))
-    for k in range(ntail):
-        a, b = zeros[K - 1 + k], zeros[K + k]
-        nd = 0.5 * (a + b) + 0.5 * (b - a) * xg2
-        ww = 0.5 * (b - a) * wg2 * jn(nd * rho)
-        c3, i3 = lp.interp_rows(nd)
-        np.add.at(tail[k], c3.ravel(), (ww[:, None] * i3).ravel())
+    a = zeros[K - 1:K - 1 + ntail][:, None]
+    b = zeros[K:K + ntail][:, None]
+    nd = 0.5 * (a + b) + 0.5 * (b - a) * xg2[None, :]          # [ntail, n_gl]
+    ww = 0.5 * (b - a) * wg2[None, :] * jn(nd * rho)
+    c3, i3 = lp.interp_rows(nd.ravel())
+    rows = np.repeat(np.arange(ntail), xg2.size)
+    np.add.at(tail, (np.repeat(rows, i3.shape[1]), c3.ravel()), (ww.ravel()[:, None] * i3).ravel())
     return main, tail, corr
 
 
-def hankel_on_grid(G, lp, rhos, reg, lam_a, lam_lo, lam_asym, ntail=30, order=0):
+def hankel_on_grid(G, lp, rhos, reg, lam_a, lam_lo, lam_asym, ntail=30, order=0,
+                   n_gl=16, n_gl0=12, levels=14):
     """h[rho, f] = int J_order(lambda rho) G[lambda, f] dlambda, with the
     regularisation (order 0 only) applied to the functions where reg[f] is
     True.  G holds the samples of g on lp's nodes, shape [lp.size, F]."""
@@ -149,12 +166,13 @@ def hankel_on_grid(G, lp, rhos, reg, lam_a, lam_lo, lam_asym, ntail=30, order=0)
     if order != 0:
         reg = np.zeros(G.shape[1], bool)
     for ir, rho in enumerate(rhos):
-        main, tail, corr = transform_weights(lp, rho, lam_a, lam_lo, lam_asym, ntail, order=order)
+        main, tail, corr = transform_weights(lp, rho, lam_a, lam_lo, lam_asym, ntail, n_gl=n_gl,
+                                             order=order, n_gl0=n_gl0)
         if corr_val is None:
             corr_val = corr @ G
         s0 = main @ G
         s0 = s0 - np.where(reg, corr_val, 0.0)
         parts = tail @ G
         S = s0[None, :] + np.cumsum(parts, axis=0)
-        out[ir] = _averaged_limit(S)
+        out[ir] = _averaged_limit(S, levels)
     return out

@@ -27,6 +27,8 @@ is computed on its own, so the lemmas can be tested on the result.
 """
 from __future__ import annotations
 
+import functools
+
 import numpy as np
 
 from . import hankel, vertical
@@ -36,6 +38,7 @@ from .fundamental import MU0
 W0, WX, WY, WXY, WXX, WYY = range(6)
 
 
+@functools.lru_cache(maxsize=None)
 def _gl(n):
     return np.polynomial.legendre.leggauss(n)
 
@@ -135,13 +138,33 @@ def area_rule(kind, dx, dy, hx, hy, n_sing=24, n_reg=14):
     return rho, W
 
 
-def line_rule(kind, dx, dy, hx, hy, n=24):
+def _graded_toward(a, b, n, ratio=0.15, depth=1e-13):
+    """Gauss-Legendre nodes and weights on [a, b] (either order) for an
+    integrand with a logarithmic singularity at a: pieces whose lengths shrink
+    geometrically toward a (ratio per piece) down to depth * |b - a|, n
+    points each, and a last piece with a quadratically graded rule."""
+    xs, ws = _gl(n)
+    L = b - a
+    t_hi = 1.0
+    nodes, wts = [], []
+    while t_hi > depth:
+        t_lo = t_hi * ratio
+        nodes.append(a + L * (0.5 * (t_lo + t_hi) + 0.5 * (t_hi - t_lo) * xs))
+        wts.append(0.5 * (t_hi - t_lo) * abs(L) * ws)
+        t_hi = t_lo
+    s = 0.5 * (xs + 1.0)
+    nodes.append(a + L * t_hi * s ** 2)
+    wts.append(abs(L) * t_hi * 0.5 * ws * 2 * s)
+    return np.concatenate(nodes), np.concatenate(wts)
+
+
+def line_rule(kind, dx, dy, hx, hy, n=16):
     """Rule for -d_xx phi (kind WXX) or -d_yy phi (kind WYY): the measure
     -(delta(u + h) - 2 delta(u) + delta(u - h)) times the triangle in the
-    other direction."""
+    other direction.  On the line through the singular point (rho = 0, where
+    the radial function has a logarithmic singularity) the pieces next to it
+    are graded geometrically."""
     xs, ws = _gl(n)
-    s = 0.5 * (xs + 1.0)
-    wsn = 0.5 * ws
     rhos, wts = [], []
     for c, wc in ((-1, -1.0), (0, 2.0), (1, -1.0)):
         if kind == WXX:
@@ -154,11 +177,9 @@ def line_rule(kind, dx, dy, hx, hy, n=24):
             singular_a = abs(off) < 1e-12 * h_fix and abs(a - d_run) < 1e-12 * h_run
             singular_b = abs(off) < 1e-12 * h_fix and abs(b - d_run) < 1e-12 * h_run
             if singular_a:
-                v = a + (b - a) * s ** 2
-                wv = (b - a) * wsn * 2 * s
+                v, wv = _graded_toward(a, b, n)
             elif singular_b:
-                v = b - (b - a) * s ** 2
-                wv = (b - a) * wsn * 2 * s
+                v, wv = _graded_toward(b, a, n)
             else:
                 v = 0.5 * (a + b) + 0.5 * (b - a) * xs
                 wv = 0.5 * (b - a) * ws
@@ -168,9 +189,17 @@ def line_rule(kind, dx, dy, hx, hy, n=24):
     return np.concatenate(rhos), np.concatenate(wts)
 
 
-def build_tables(model, freq=None, n_lam_panel=16, rho_min_rel=1e-7, lam_asym_rel=40.0):
+QUAD = dict(lam_width=0.5, lam_n=16, rho_width=0.5, rho_n=12, rho_min_rel=1e-13,
+            lam_asym_rel=40.0, ntail=30, n_gl=16, n_gl0=12, levels=14,
+            n_sing=32, n_reg=20, n_line=16)
+
+
+def build_tables(model, freq=None, quad=None):
     """B for every signed offset: array [2Ny-1][2Nx-1][3][3][Nz][Nz] with
-    index [i + Ny - 1, j + Nx - 1] for y-offset i and x-offset j."""
+    index [i + Ny - 1, j + Nx - 1] for y-offset i and x-offset j.  quad
+    overrides entries of QUAD (panel widths and orders of every quadrature,
+    for convergence checks)."""
+    q = dict(QUAD, **(quad or {}))
     f = model["freq"] if freq is None else freq
     nx, ny, nz = model["nx"], model["ny"], model["nz"]
     hx, hy = model["hx"], model["hy"]
@@ -178,32 +207,33 @@ def build_tables(model, freq=None, n_lam_panel=16, rho_min_rel=1e-7, lam_asym_re
     d, sig = model["d"], model["sigma"]
     hmin = float(np.min(np.diff(ze)))
     href = min(hx, hy)
-    rho_min = rho_min_rel * href
+    rho_min = q["rho_min_rel"] * href
     rho_max = 1.05 * np.hypot((nx + 1) * hx, (ny + 1) * hy)
-    lam_asym = lam_asym_rel / hmin
+    lam_asym = q["lam_asym_rel"] / hmin
     lam_lo = 1e-9 / max(rho_max, ze[-1])
     lam_a = 1e-3 / max(rho_max, ze[-1])
-    ntail = 30
+    ntail = q["ntail"]
     lam_hi = 1.1 * (lam_asym + (ntail + 3) * np.pi / rho_min)
-    lp = hankel.LogPanels(lam_lo * 0.5, lam_hi, 0.5, n_lam_panel)
+    lp = hankel.LogPanels(lam_lo * 0.5, lam_hi, q["lam_width"], q["lam_n"])
     K = vertical.kernel_functions(lp.x, d, sig, f, ze)          # [nl, 5, nz, nz]
     lam = lp.x[:, None, None, None]
     G = (K * lam).reshape(lp.size, -1)                          # g = f(lambda) lambda
     reg = np.zeros((5, nz, nz), bool)
     reg[1] = True
     reg = reg.reshape(-1)
-    rp = hankel.LogPanels(rho_min, rho_max, 0.5, 12)
-    H = hankel.hankel_on_grid(G, lp, rp.x, reg, lam_a, lam_lo, lam_asym, ntail)  # [nrho, F]
+    rp = hankel.LogPanels(rho_min, rho_max, q["rho_width"], q["rho_n"])
+    H = hankel.hankel_on_grid(G, lp, rp.x, reg, lam_a, lam_lo, lam_asym, ntail,
+                              n_gl=q["n_gl"], n_gl0=q["n_gl0"], levels=q["levels"])  # [nrho, F]
     # weighted quadratures, folded onto the radial grid
     offs = [(i, j) for i in range(-ny + 1, ny) for j in range(-nx + 1, nx)]
     rows = []
     for (i, j) in offs:
         dx, dy = j * hx, i * hy
         for kind in (W0, WX, WY, WXY):
-            rho, w = area_rule(kind, dx, dy, hx, hy)
+            rho, w = area_rule(kind, dx, dy, hx, hy, q["n_sing"], q["n_reg"])
             rows.append((rho, w))
         for kind in (WXX, WYY):
-            rho, w = line_rule(kind, dx, dy, hx, hy)
+            rho, w = line_rule(kind, dx, dy, hx, hy, q["n_line"])
             rows.append((rho, w))
     M = np.zeros((len(rows), rp.size))
     for r, (rho, w) in enumerate(rows):

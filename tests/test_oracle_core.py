@@ -160,6 +160,25 @@ def test_transpose_mode_is_bilinear_adjoint():
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
 
 
+@pytest.mark.parametrize("mode", ["A", "AT", "B"])
+def test_direct_apply_equals_paper_system_matrix(mode):
+    """The O(N^2) apply in the factorised form S + R1 B R2 against the dense
+    matrix written as the paper's system, I - K Gamma (Sect. 2.2), its
+    transpose, and B itself: a swapped R1/R2 or a dropped term fails."""
+    m = _small_model()
+    rng = np.random.default_rng(11)
+    t = gs.random_packed_table(rng, m["nx"], m["ny"], m["nz"], scale=1e3)
+    B = dense.dense_from_packed(t, m)
+    d = dense.cie_diagonals(m)
+    x = gs.random_vector(rng, 2, m["nz"], m["ny"], m["nx"])
+    M = {"A": dense.system_matrix_from_K(B, d), "B": B}.get(mode)
+    if mode == "AT":
+        M = dense.system_matrix_from_K(B, d).T
+    ref = (x.reshape(2, -1) @ M.T).reshape(x.shape)
+    got = dense.apply_direct(B, d, x, mode)
+    assert np.linalg.norm(got - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
 # ---------------------------------------------------------------- normal field
 
 def test_half_space_impedance_closed_form():

@@ -1,7 +1,10 @@
 """Pins of the oracle's fundamental functions (Appendix B problem) and of its
 Galerkin tables (Sect. 3.1, Appendix A) against what the mathematics fixes:
-the whole-space closed form, the whole-space sum rule, the jump and interface
-conditions, reciprocity and the storage symmetries of Lemma 1 and Lemma 2."""
+the whole-space closed form (separated pairs by tensor quadrature of the
+closed-form tensor; self and touching pairs by the face-face form of the
+second derivatives, whose integrator is itself pinned by closed forms), the
+whole-space sum rule, the jump and interface conditions, reciprocity, the
+storage symmetries of Lemma 1 and Lemma 2 and quadrature doubling."""
 import numpy as np
 import pytest
 
@@ -103,6 +106,92 @@ def test_tables_whole_space_closed_form(ws_tables):
     assert _ws_errors(B, m) <= 1e-9
 
 
+def test_singular_integrator_closed_forms():
+    # The integrator behind the self and touching whole-space pairs, on the
+    # static kernel 1/R: two coincident unit squares (coplanar faces) and two
+    # coincident unit cubes, whose mean inverse distances have closed forms.
+    s2, s3 = np.sqrt(2.0), np.sqrt(3.0)
+    square = (4.0 / 3.0) * (1.0 - s2) + 4.0 * np.log(1.0 + s2)
+    cube = 2.0 * ((1.0 + s2 - 2.0 * s3) / 5.0 - np.pi / 3.0 + np.log((1.0 + s2) * (2.0 + s3)))
+    ax = wholespace._trap_axis(0.0, 1.0, 0.0, 1.0)
+    inv = lambda R: 1.0 / R + 0j                                   # noqa: E731
+    assert abs(wholespace._singular_integral(inv, [ax, ax], 0.0, 12) - square) <= 1e-13 * square
+    assert abs(wholespace._singular_integral(inv, [ax, ax, ax], 0.0, 12) - cube) <= 1e-13 * cube
+
+
+_PAIRS = [((0, 0, 0), (0, 0, 0)), ((1, 0, 0), (0, 0, 0)), ((0, 1, 0), (0, 0, 0)),
+          ((1, 1, 0), (0, 0, 0)), ((0, 0, 1), (0, 0, 0)), ((1, 0, 1), (0, 0, 0)),
+          ((-1, 1, 1), (0, 0, 0)), ((2, 0, 1), (0, 0, 0))]
+
+
+def _box(m, ix, iy, iz):
+    ze = m["z_edges"]
+    return ([ix * m["hx"], iy * m["hy"], ze[iz]], [(ix + 1) * m["hx"], (iy + 1) * m["hy"], ze[iz + 1]])
+
+
+@pytest.mark.parametrize("freq", [1.0, 300.0])
+def test_whole_space_pair_reference_identities(freq):
+    # Trace identity: sum_a int int d_a d_a g = int int (-k^2 g - delta), so
+    # trace B = 2 i w mu0 int int g - |n cap m| / sigma; it ties the face
+    # integrals to the volume integral, two different quadratures.  A
+    # separated pair must equal the tensor rule over the closed-form tensor.
+    m = _ws_model()
+    sig = m["sigma"][0].real
+    w = 2 * np.pi * freq
+    for (cn, cm) in _PAIRS:
+        lo_n, hi_n = _box(m, *cn)
+        lo_m, hi_m = _box(m, *cm)
+        B, I0, _ = wholespace.cell_pair_any(lo_n, hi_n, lo_m, hi_m, sig, freq, q=16)
+        ov = np.prod(np.clip(np.minimum(hi_n, hi_m) - np.maximum(lo_n, lo_m), 0, None))
+        tr = 2j * w * wholespace.MU0 * I0 - ov / sig
+        assert abs(np.trace(B) - tr) <= 1e-12 * np.abs(B).max()
+        if cn == (2, 0, 1):
+            ref = wholespace.cell_pair(lo_n, hi_n, lo_m, hi_m, sig, freq, q=10)
+            assert np.abs(B - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+def _touching_errors(B, m, freq=None):
+    """Worst |B - reference| / max|reference| over every self and touching
+    pair (lateral offsets -1..1, all depth pairs), all nine components."""
+    ny, nx = m["ny"], m["nx"]
+    f = m["freq"] if freq is None else freq
+    worst = 0.0
+    for i in (-1, 0, 1):
+        for j in (-1, 0, 1):
+            for iz in range(m["nz"]):
+                for jz in range(m["nz"]):
+                    lo_n, hi_n = _box(m, j, i, iz)
+                    lo_m, hi_m = _box(m, 0, 0, jz)
+                    ref, _, _ = wholespace.cell_pair_any(lo_n, hi_n, lo_m, hi_m,
+                                                         m["sigma"][0].real, f, q=12)
+                    got = B[i + ny - 1, j + nx - 1, :, :, iz, jz]
+                    worst = max(worst, np.abs(got - ref).max() / np.abs(ref).max())
+    return worst
+
+
+def test_tables_whole_space_self_and_touching(ws_tables):
+    # every component of every self and touching pair, one by one
+    m, B = ws_tables
+    assert _touching_errors(B, m) <= 1e-9          # seen 4.6e-11
+
+
+def test_tables_planted_xy_weight_error_fails_touching_pin(monkeypatch):
+    # Planted mistake: 5% too much weight in the d_x d_y phi rule of the self
+    # and touching offsets.  The sum rule cannot see it (the xy terms are odd
+    # in x and y and cancel over a symmetric window); the per-pair pin must.
+    orig = tables.area_rule
+
+    def planted(kind, dx, dy, hx, hy, n_sing=24, n_reg=14):
+        rho, w = orig(kind, dx, dy, hx, hy, n_sing, n_reg)
+        if kind == tables.WXY and abs(dx) <= hx * (1 + 1e-9) and abs(dy) <= hy * (1 + 1e-9):
+            w = 1.05 * w
+        return rho, w
+
+    monkeypatch.setattr(tables, "area_rule", planted)
+    m = _ws_model()
+    assert _touching_errors(tables.build_tables(m), m) > 1e-4
+
+
 def test_tables_other_v3_reading_fails_whole_space(monkeypatch):
     # Planted mistake: keep the 2 delta term in the vertical integral behind
     # V3 (the reading that differentiates outside the z* integral).  The
@@ -193,6 +282,21 @@ def test_tables_lemma1_and_reciprocity(layered_tables):
     # reciprocity of the full matrix: B[(a, iz), (b, jz)](D) = B[(b, jz), (a, iz)](-D)
     Bm = B[::-1, ::-1]
     assert np.abs(B - np.transpose(Bm, (0, 1, 3, 2, 5, 4))).max() <= 1e-11 * scale
+
+
+def test_tables_quadrature_doubling(layered_tables):
+    # Layered earth under insulating air: halving every panel width (lambda,
+    # rho) and raising every order (Hankel panels, tail length, vertex, area
+    # and line rules) changes no coefficient by more than 1e-10 of the
+    # largest of its component.
+    m, B = layered_tables
+    q2 = dict(lam_width=0.25, rho_width=0.25, ntail=40, n_gl=24, n_gl0=16,
+              n_sing=48, n_reg=30, n_line=24)
+    B2 = tables.build_tables(m, quad=q2)
+    for a in range(3):
+        for b in range(3):
+            mx = np.abs(B2[:, :, a, b]).max()
+            assert np.abs(B[:, :, a, b] - B2[:, :, a, b]).max() <= 1e-10 * mx, (a, b)
 
 
 @pytest.mark.parametrize("which", ["layered", "contrast"])
