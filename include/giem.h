@@ -271,7 +271,7 @@ int giem_solve(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
  * giem_solve_batch -- giem_solve for nf frequencies of one model at once.
  * The operators of one model at several frequencies share sigma_a and the
  * diagonal scalings of Sect. 3.1 and differ only in their tables, so the
- * nf x nrhs systems run GMRES (Sect. 3.4) in lockstep: one host
+ * nf x nrhs systems run GMRES (Sect. 3.3, item (ii)) in lockstep: one host
  * synchronisation per Arnoldi step for all of them, applies grouped per
  * frequency.  Each system follows its own Krylov process, so the results are
  * those of nf separate giem_solve calls up to rounding.
@@ -291,8 +291,11 @@ int giem_solve_batch(giem_handle *t, int32_t nf, const int32_t *ifreqs, const vo
 
 /*
  * giem_adjoint -- gradient of J = sum_r Re( sum_n g_r[n] . E_r[n] ) with
- * respect to log sigma_a of every cell for real conductivities (the
- * sensitivity is obtained from one solve with A^T; B = B^T by reciprocity).
+ * respect to log sigma_a of every cell for real conductivities, from one
+ * solve with A^T = S + R2 B R1.  B = B^T for the full 3N x 3N matrix: Lemma 1
+ * (Sect. 3.1: yx = xy, zx = -xz^T, zy = -yz^T at a fixed lateral offset)
+ * with the mirror parities of Lemma 2, which is the reciprocity
+ * G(M, M0) = G(M0, M)^T of the Green's tensor of Appendix A.
  *   adj_src: device c128 [nrhs][3][Nz][Ny][Nx], g above;
  *   E_fwd:   device c128 [nrhs][3][Nz][Ny][Nx], the forward solution E;
  *   grad_log_sigma: device double [Nz][Ny][Nx], accumulated (+=).
@@ -312,18 +315,19 @@ int giem_adjoint(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrh
  * earth side when the air is insulating (there sigma E_z + j_z = 0).
  *   sigma_a: device c128 [Nz][Ny][Nx];
  *   E_cells: device c128 [nrhs][3][Nz][Ny][Nx] (E = U / a, as from giem_solve);
- *   rec_xy:  host [nrec][2] receiver positions (x, y) in m; every receiver
- *            must lie above the centre of a cell of the grid;
+ *   rec_xyz: host [nrec][3] receiver positions (x, y, z) in m, z positive
+ *            down; every receiver must lie on the earth's surface (z = d[0])
+ *            above the centre of a cell of the grid;
  *   E_rec, H_rec: device c128 [nrhs][nrec][3] outputs.
  * E^N, H^N (1 V/m plane wave) are added for RHS 0 (x polarisation) and RHS 1
  * (y polarisation); further RHS get the anomalous fields only.  The cell
  * integrals for every receiver offset are computed on the first call for a
  * frequency and kept on the handle.  Synchronises the stream.
- * Errors: EINVAL, EDOMAIN (receiver not above a cell centre, or the grid does
- * not start at the surface d[0]), ENOMEM, EHIP.
+ * Errors: EINVAL, EDOMAIN (receiver off the surface or not above a cell
+ * centre, or the grid does not start at the surface d[0]), ENOMEM, EHIP.
  */
 int giem_fields(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
-                const void *E_cells, int32_t nrec, const double *rec_xy, void *E_rec,
+                const void *E_cells, int32_t nrec, const double *rec_xyz, void *E_rec,
                 void *H_rec, void *stream);
 
 /*
@@ -368,7 +372,7 @@ int giem_impedance_adjoint(int32_t nrec, const void *E_rec, const void *H_rec, c
  * Errors: EINVAL, EDOMAIN, ENOMEM, EHIP.
  */
 int giem_fields_adjoint(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
-                        const void *E_cells, int32_t nrec, const double *rec_xy, const void *wE,
+                        const void *E_cells, int32_t nrec, const double *rec_xyz, const void *wE,
                         const void *wH, void *adj_src, void *grad_log_sigma, void *stream);
 
 void giem_free(giem_handle *t);

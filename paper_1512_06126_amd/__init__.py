@@ -301,16 +301,24 @@ class Handle:
         d["rc"] = rc
         return d
 
-    def fields(self, sigma_a, E_cells, rec_xy, E_rec, H_rec, ifreq=0, stream=None):
-        rec = np.ascontiguousarray(rec_xy, dtype=np.float64)
+    def receivers(self, rec):
+        """Receiver positions as host float64 [nrec][3]; (x, y) pairs are
+        placed on the earth's surface z = d[0] of the handle's model."""
+        rec = np.asarray(rec, dtype=np.float64)
+        if rec.ndim == 2 and rec.shape[1] == 2:
+            rec = np.concatenate([rec, np.full((rec.shape[0], 1), float(self.model["d"][0]))], 1)
+        return np.ascontiguousarray(rec.reshape(-1, 3))
+
+    def fields(self, sigma_a, E_cells, rec_xyz, E_rec, H_rec, ifreq=0, stream=None):
+        rec = self.receivers(rec_xyz)
         _check(_lib.giem_fields(self._p, ifreq, _ptr(sigma_a), E_cells.shape[0], _ptr(E_cells),
                                 rec.shape[0], rec.ctypes.data, _ptr(E_rec), _ptr(H_rec),
                                 _stream(stream)))
         return E_rec, H_rec
 
-    def fields_adjoint(self, sigma_a, E_cells, rec_xy, wE, wH, adj_src, grad, ifreq=0,
+    def fields_adjoint(self, sigma_a, E_cells, rec_xyz, wE, wH, adj_src, grad, ifreq=0,
                        stream=None):
-        rec = np.ascontiguousarray(rec_xy, dtype=np.float64).reshape(-1, 2)
+        rec = self.receivers(rec_xyz)
         _check(_lib.giem_fields_adjoint(self._p, ifreq, _ptr(sigma_a), E_cells.shape[0],
                                         _ptr(E_cells), rec.shape[0], rec.ctypes.data, _ptr(wE),
                                         _ptr(wH), _ptr(adj_src), _ptr(grad), _stream(stream)))

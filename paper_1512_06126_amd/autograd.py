@@ -63,15 +63,16 @@ class _ImpedanceFn(torch.autograd.Function):
         return grad, None, None, None, None
 
 
-def impedance_tensor(handle, log_sigma, rec_xy, ifreqs=None, tol=1e-10, adj_tol=None,
+def impedance_tensor(handle, log_sigma, rec_xyz, ifreqs=None, tol=1e-10, adj_tol=None,
                      restart=30, max_iter=4000):
     """Z [nfreq][nrec][2][2] (complex128, on log_sigma's device) for the
     anomaly conductivity exp(log_sigma) ([Nz][Ny][Nx], float64), receivers
-    rec_xy [nrec][2] above cell centres and the handle's frequencies ifreqs
+    rec_xyz [nrec][3] (or (x, y) pairs [nrec][2], placed on the surface) above
+    cell centres and the handle's frequencies ifreqs
     (all by default).  Differentiable with respect to log_sigma."""
     if ifreqs is None:
         ifreqs = list(range(len(handle.freqs)))
-    rec = np.ascontiguousarray(rec_xy, dtype=np.float64).reshape(-1, 2)
+    rec = handle.receivers(rec_xyz)
     opts = dict(tol=tol, adj_tol=tol if adj_tol is None else adj_tol, restart=restart,
                 max_iter=max_iter)
     return _ImpedanceFn.apply(log_sigma, handle, rec, list(ifreqs), opts)

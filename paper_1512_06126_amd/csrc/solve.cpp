@@ -838,19 +838,25 @@ int giem_adjoint(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrh
 
 namespace giem {
 
-// Lattice indices of receivers that lie above cell centres; EDOMAIN otherwise
-// or when the anomaly grid does not start at the surface d[0].
-static int receiver_indices(const giem_handle *t, int nrec, const double *rec_xy,
+// Lattice indices of receivers rec_xyz [nrec][3] that lie on the earth's
+// surface (z = d[0]) above cell centres; EDOMAIN otherwise or when the anomaly
+// grid does not start at the surface d[0].
+static int receiver_indices(const giem_handle *t, int nrec, const double *rec_xyz,
                             std::vector<int> &idx, const char *who) {
-  if (std::fabs(t->z_edges[0] - t->d[0]) > 1e-9 * (t->z_edges[t->nz] - t->z_edges[0])) {
+  const double zscale = t->z_edges[t->nz] - t->z_edges[0];
+  if (std::fabs(t->z_edges[0] - t->d[0]) > 1e-9 * zscale) {
     set_error(std::string(who) + ": the anomaly grid must start at the earth's surface d[0]");
     return GIEM_EDOMAIN;
   }
   idx.assign(2 * (size_t)nrec, 0);
   for (int q = 0; q < nrec; ++q) {
-    const double fx = (rec_xy[2 * q] - t->x0) / t->hx - 0.5;
-    const double fy = (rec_xy[2 * q + 1] - t->y0) / t->hy - 0.5;
+    const double fx = (rec_xyz[3 * q] - t->x0) / t->hx - 0.5;
+    const double fy = (rec_xyz[3 * q + 1] - t->y0) / t->hy - 0.5;
     const double ix = std::round(fx), iy = std::round(fy);
+    if (!(std::fabs(rec_xyz[3 * q + 2] - t->d[0]) <= 1e-9 * zscale)) {
+      set_error(std::string(who) + ": receivers must lie on the earth's surface z = d[0]");
+      return GIEM_EDOMAIN;
+    }
     if (!(std::fabs(fx - ix) <= 1e-9) || !(std::fabs(fy - iy) <= 1e-9) || ix < 0 ||
         ix >= t->nx || iy < 0 || iy >= t->ny) {
       set_error(std::string(who) + ": receivers must lie above cell centres of the grid");
@@ -879,17 +885,17 @@ struct DevCopy {
 }  // namespace giem
 
 extern "C" int giem_fields(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
-                           const void *E_cells, int32_t nrec, const double *rec_xy, void *E_rec,
+                           const void *E_cells, int32_t nrec, const double *rec_xyz, void *E_rec,
                            void *H_rec, void *stream) {
   using namespace giem;
   if (!t || ifreq < 0 || ifreq >= (int)t->f.size() || !sigma_a || nrhs < 1 || !E_cells ||
-      nrec < 0 || (nrec > 0 && (!rec_xy || !E_rec || !H_rec))) {
+      nrec < 0 || (nrec > 0 && (!rec_xyz || !E_rec || !H_rec))) {
     set_error("giem_fields: bad argument");
     return GIEM_EINVAL;
   }
   if (nrec == 0) return GIEM_OK;
   std::vector<int> idx;
-  GIEM_TRY(receiver_indices(t, nrec, rec_xy, idx, "giem_fields"));
+  GIEM_TRY(receiver_indices(t, nrec, rec_xyz, idx, "giem_fields"));
   hipStream_t s = static_cast<hipStream_t>(stream);
   FreqTables &ft = t->f[ifreq];
   if (!ft.rec_kernel) GIEM_TRY(compute_receiver_kernels(t, ifreq, &ft.rec_kernel, s));
@@ -921,16 +927,16 @@ extern "C" int giem_fields(giem_handle *t, int32_t ifreq, const void *sigma_a, i
 
 extern "C" int giem_fields_adjoint(giem_handle *t, int32_t ifreq, const void *sigma_a,
                                    int32_t nrhs, const void *E_cells, int32_t nrec,
-                                   const double *rec_xy, const void *wE, const void *wH,
+                                   const double *rec_xyz, const void *wE, const void *wH,
                                    void *adj_src, void *grad_log_sigma, void *stream) {
   using namespace giem;
   if (!t || ifreq < 0 || ifreq >= (int)t->f.size() || !sigma_a || nrhs < 1 || !E_cells ||
-      nrec < 0 || (nrec > 0 && (!rec_xy || !wE || !wH)) || !adj_src || !grad_log_sigma) {
+      nrec < 0 || (nrec > 0 && (!rec_xyz || !wE || !wH)) || !adj_src || !grad_log_sigma) {
     set_error("giem_fields_adjoint: bad argument");
     return GIEM_EINVAL;
   }
   std::vector<int> idx;
-  if (nrec > 0) GIEM_TRY(receiver_indices(t, nrec, rec_xy, idx, "giem_fields_adjoint"));
+  if (nrec > 0) GIEM_TRY(receiver_indices(t, nrec, rec_xyz, idx, "giem_fields_adjoint"));
   hipStream_t s = static_cast<hipStream_t>(stream);
   GIEM_TRY(check_sigma_a(t, sigma_a, s));
   FreqTables &ft = t->f[ifreq];

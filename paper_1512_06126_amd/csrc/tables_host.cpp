@@ -96,17 +96,42 @@ Rule gauss_legendre(int n) {
   return r;
 }
 
+// Double-exponential (tanh-sinh) rule on [0, 1] for integrands with an
+// integrable singularity at 0 (here ln x, or x ln x): x = 1 / (1 + e^{-pi
+// sinh t}) on the equispaced t = k h, |t| <= t_max, weight h dx/dt.  The
+// nodes crowd towards both ends double-exponentially, which resolves the
+// logarithm without any knowledge of its coefficient.
+Rule tanh_sinh01(double h, double t_max) {
+  Rule r;
+  const int m = (int)std::floor(t_max / h);
+  for (int k = -m; k <= m; ++k) {
+    const double tk = k * h;
+    const double e = std::exp(-kPi * std::sinh(tk));
+    const double x = 1.0 / (1.0 + e);
+    const double w = h * kPi * std::cosh(tk) * x * (e / (1.0 + e));
+    if (x <= 0.0 || w <= 0.0) continue;
+    r.x.push_back(x);
+    r.w.push_back(w);
+  }
+  return r;
+}
+
 // Chebyshev-Lobatto panels of equal width in u = ln x; barycentric
 // interpolation inside a panel.
 struct LogGrid {
   std::vector<double> edges, node, bw, x;
   int n = 0;
-  void init(double lo, double hi, double width, int npp) {
+  // panels of equal width in ln x on [lo, hi]; with lead < lo one more,
+  // wider panel [lead, lo] in front (for functions that are nearly linear in
+  // ln x there)
+  void init(double lo, double hi, double width, int npp, double lead = 0.0) {
     n = npp;
     const double u0 = std::log(lo), u1 = std::log(hi);
     const int np = std::max(1, (int)std::ceil((u1 - u0) / width));
-    edges.resize(np + 1);
-    for (int i = 0; i <= np; ++i) edges[i] = u0 + (u1 - u0) * i / np;
+    const int extra = (lead > 0.0 && lead < lo) ? 1 : 0;
+    edges.resize(np + 1 + extra);
+    if (extra) edges[0] = std::log(lead);
+    for (int i = 0; i <= np; ++i) edges[i + extra] = u0 + (u1 - u0) * i / np;
     node.resize(n);
     bw.resize(n);
     for (int j = 0; j < n; ++j) {
@@ -114,8 +139,9 @@ struct LogGrid {
       bw[j] = (j & 1) ? -1.0 : 1.0;
       if (j == 0 || j == n - 1) bw[j] *= 0.5;
     }
-    x.resize((size_t)np * n);
-    for (int p = 0; p < np; ++p)
+    const int npan = np + extra;
+    x.resize((size_t)npan * n);
+    for (int p = 0; p < npan; ++p)
       for (int j = 0; j < n; ++j)
         x[(size_t)p * n + j] =
             std::exp(0.5 * (edges[p] + edges[p + 1]) + 0.5 * (edges[p + 1] - edges[p]) * node[j]);
@@ -226,7 +252,13 @@ Grids make_grids(const giem_handle *t) {
   double hmin = 1e300;
   for (int l = 0; l < t->nz; ++l) hmin = std::min(hmin, t->z_edges[l + 1] - t->z_edges[l]);
   const double href = std::min(t->hx, t->hy);
-  g.rho_min = 1e-7 * href;
+  // The radial functions grow like ln(1 / rho) at rho -> 0 and the line and
+  // vertex rules evaluate them down to rho ~ 1e-12 h: below that the
+  // clamped remainder is of relative size 1e-12.  Between rho_min and
+  // 1e-9 h they contribute at most ~1e-9 of a coefficient, so one panel
+  // (12 nodes over a factor 1000 in rho) resolves them well enough even where
+  // they grow like 1 / rho (faces of touching cells).
+  g.rho_min = 1e-12 * href;
   const double rho_max = 1.05 * std::hypot((t->nx + 1) * t->hx, (t->ny + 1) * t->hy);
   const double zmax = t->z_edges[t->nz];
   const double scale = std::max(rho_max, zmax);
@@ -235,7 +267,7 @@ Grids make_grids(const giem_handle *t) {
   g.lam_a = 1e-3 / scale;
   const double lam_hi = 1.1 * (g.lam_asym + (g.ntail + 3) * kPi / g.rho_min);
   g.lam.init(0.5 * g.lam_lo, lam_hi, 0.5, 16);
-  g.rho.init(g.rho_min, rho_max, 0.5, 12);
+  g.rho.init(1e-9 * href, rho_max, 0.5, 12, g.rho_min);
   return g;
 }
 
@@ -326,6 +358,13 @@ inline double weight_fn(int kind, double u, double v, double su, double sv, doub
   }
 }
 
+// radial variable of the two triangles at a singular vertex (integrand
+// r h(r ...), h ~ ln r) and the singular ends of the line rules
+const Rule &radial_rule() {
+  static const Rule r = tanh_sinh01(1.0 / 8.0, 3.75);
+  return r;
+}
+
 // int over the quadrant [x0,x1]x[y0,y1] of weight * h(|D - r'|); the
 // integrand is singular only when D is a vertex of the quadrant.
 void quadrant_rule(int kind, double dx, double dy, double x0, double x1, double y0, double y1,
@@ -347,13 +386,13 @@ void quadrant_rule(int kind, double dx, double dy, double x0, double x1, double 
     const double ox = vx[1 - (sing >> 1)], oy = vy[1 - (sing & 1)];
     const double ax[2] = {ox, px}, ay[2] = {py, oy};  // the two adjacent corners
     const int n = (int)gs.x.size();
+    const Rule &rad = radial_rule();
     for (int tri = 0; tri < 2; ++tri) {
       const double e1x = ax[tri] - px, e1y = ay[tri] - py;
       const double e2x = ox - ax[tri], e2y = oy - ay[tri];
       const double det = std::fabs(e1x * e2y - e1y * e2x);
-      for (int i = 0; i < n; ++i) {
-        const double s = 0.5 * (gs.x[i] + 1.0), ws = 0.5 * gs.w[i];
-        const double r = s * s, wr = ws * 2.0 * s;
+      for (size_t i = 0; i < rad.x.size(); ++i) {
+        const double r = rad.x[i], wr = rad.w[i];
         for (int j = 0; j < n; ++j) {
           const double tt = 0.5 * (gs.x[j] + 1.0), wt = 0.5 * gs.w[j];
           const double u = px + r * (e1x + tt * e2x), v = py + r * (e1y + tt * e2y);
@@ -410,19 +449,18 @@ void line_rule(int kind, double dx, double dy, double hx, double hy, const Rule 
       const bool on_line = std::fabs(off) < 1e-12 * hfix;
       const bool sa = on_line && std::fabs(a - drun) < 1e-12 * hrun;
       const bool sb = on_line && std::fabs(b - drun) < 1e-12 * hrun;
-      for (int i = 0; i < n; ++i) {
-        double v, wv;
-        const double s = 0.5 * (gl.x[i] + 1.0), ws = 0.5 * gl.w[i];
-        if (sa) {
-          v = a + (b - a) * s * s;
-          wv = (b - a) * ws * 2.0 * s;
-        } else if (sb) {
-          v = b - (b - a) * s * s;
-          wv = (b - a) * ws * 2.0 * s;
-        } else {
-          v = 0.5 * (a + b) + 0.5 * (b - a) * gl.x[i];
-          wv = 0.5 * (b - a) * gl.w[i];
+      if (sa || sb) {
+        // logarithmic singularity at the end a (sa) or b (sb)
+        const Rule &de = radial_rule();
+        for (size_t i = 0; i < de.x.size(); ++i) {
+          const double v = sa ? a + (b - a) * de.x[i] : b - (b - a) * de.x[i];
+          out.add(std::hypot(off, drun - v), wc * (b - a) * de.w[i] * (hrun - std::fabs(v)));
         }
+        continue;
+      }
+      for (int i = 0; i < n; ++i) {
+        const double v = 0.5 * (a + b) + 0.5 * (b - a) * gl.x[i];
+        const double wv = 0.5 * (b - a) * gl.w[i];
         out.add(std::hypot(off, drun - v), wc * wv * (hrun - std::fabs(v)));
       }
     }

@@ -15,6 +15,22 @@ def rel_err(a, b):
     return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
 
 
+def component_errors(a, b, axes, floor=1e-3):
+    """Relative 2-norm error of every slice of a against b that fixes the
+    indices along axes (for example the RHS and the field component), each
+    relative to the larger of that slice's norm and floor times the norm of
+    all of b: small components (E_z, cross-polarised parts) are checked on
+    their own scale instead of hiding under the large ones."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    axes = tuple(ax % b.ndim for ax in axes)
+    rest = tuple(ax for ax in range(b.ndim) if ax not in axes)
+    num = np.sqrt(np.sum(np.abs(a - b) ** 2, axis=rest))
+    den = np.sqrt(np.sum(np.abs(b) ** 2, axis=rest))
+    den = np.maximum(den, floor * np.linalg.norm(b.ravel()))
+    return float(np.max(num / np.maximum(den, 1e-300)))
+
+
 def random_model(nx, ny, nz, seed, contrast=2.0, freq=1.0):
     """A layered model whose cells sit in two earth layers, random sigma_a."""
     rng = np.random.default_rng(seed)

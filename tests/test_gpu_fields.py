@@ -5,7 +5,7 @@ import pytest
 
 import giem_synth as gs
 from oracle import dense, fields, normal_field
-from tests.gpu_util import rel_err, to_dev
+from tests.gpu_util import component_errors, rel_err, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -37,8 +37,13 @@ def test_fields_match_oracle(lib):
     e_ref, h_ref = fields.fields_at(m, E, rec)
     ee = rel_err(Er.cpu().numpy(), e_ref)
     eh = rel_err(Hr.cpu().numpy(), h_ref)
-    print(f"fields vs oracle: E {ee:.2e}  H {eh:.2e}", flush=True)
+    # per RHS and field component ([nrhs][nrec][3])
+    ce = component_errors(Er.cpu().numpy(), e_ref, (0, 2))
+    ch = component_errors(Hr.cpu().numpy(), h_ref, (0, 2))
+    print(f"fields vs oracle: E {ee:.2e}  H {eh:.2e}  per component E {ce:.2e}  H {ch:.2e}",
+          flush=True)
     assert ee <= 1e-9 and eh <= 1e-9
+    assert ce <= 1e-8 and ch <= 1e-8
 
 
 def test_fields_after_solve_match_oracle(lib):
@@ -64,8 +69,12 @@ def test_fields_after_solve_match_oracle(lib):
     e_ref, h_ref = fields.fields_at(m, Eref, rec)
     ee = rel_err(Er.cpu().numpy(), e_ref)
     eh = rel_err(Hr.cpu().numpy(), h_ref)
-    print(f"fields after solve: E {ee:.2e}  H {eh:.2e}", flush=True)
+    ce = component_errors(Er.cpu().numpy(), e_ref, (0, 2))
+    ch = component_errors(Hr.cpu().numpy(), h_ref, (0, 2))
+    print(f"fields after solve: E {ee:.2e}  H {eh:.2e}  per component E {ce:.2e}  H {ch:.2e}",
+          flush=True)
     assert ee <= 1e-9 and eh <= 1e-9
+    assert ce <= 1e-8 and ch <= 1e-8
     # impedance from both polarisations
     Z = fields.impedance(Er.cpu().numpy(), Hr.cpu().numpy())
     Zr = fields.impedance(e_ref, h_ref)
@@ -81,4 +90,10 @@ def test_fields_reject_receivers_off_centres(lib):
     with pytest.raises(lib.GiemError) as ex:
         h.fields(to_dev(m["sigma_a"]), E, np.array([[10.0, 60.0]]), Er, Er.clone())
     assert ex.value.code == lib.GIEM_EDOMAIN
+    # above a cell centre but below the surface
+    with pytest.raises(lib.GiemError) as ex:
+        h.fields(to_dev(m["sigma_a"]), E, np.array([[50.0, 60.0, 20.0]]), Er, Er.clone())
+    assert ex.value.code == lib.GIEM_EDOMAIN
+    # the same receiver on the surface, given as (x, y, z)
+    h.fields(to_dev(m["sigma_a"]), E, np.array([[50.0, 60.0, 0.0]]), Er, Er.clone())
     h.close()
