@@ -171,14 +171,42 @@ def config_batched():
     return models, freqs
 
 
-def config_large(seed=7, freq=10.0):
-    """A grid of the size of the paper's scalability workload (Sect. 4: cubes
-    of 25 m, 118 layers of cells; 175 x 224 columns here, since 2 x 176 has
-    the prime factor 11): three-layer earth, seven blocks with conductivity
-    factors up to 3.3e4."""
-    return config_layered(175, 224, 118, 25.0, 25.0, 25.0, seed, freq, n_earth_layers=3,
-                          n_boxes=7, side_xy=(10, 60), side_z=(8, 40),
-                          max_log_contrast=float(np.log10(3.3e4)), interface_step=25.0)
+# Blocks of the paper's benchmark model (Sect. 4, Table commemi_table): opposite
+# corners (x1, y1, z1), (x2, y2, z2) in km and conductivity in S/m.
+COMMEMI3D3_BLOCKS = [
+    (0.0, 2.4, 0.05, 3.0, 2.8, 0.30, 0.0033),
+    (0.0, 1.8, 0.05, 3.0, 2.4, 0.45, 0.033),
+    (0.0, 1.4, 0.05, 3.0, 1.8, 0.30, 0.1),
+    (0.0, 0.8, 0.05, 3.0, 1.4, 0.45, 0.033),
+    (0.0, 0.4, 0.05, 3.0, 0.8, 0.30, 0.0033),
+    (3.4, 2.8, 0.20, 4.4, 4.8, 1.00, 10.0),
+    (1.4, 0.0, 1.00, 2.4, 5.6, 3.00, 3.3333),
+]
+
+
+def config_commemi3d3(freq=1.0, h=25.0):
+    """The paper's benchmark model (Sect. 4): air | 0-1 km 1e-3 S/m | 1-7.5 km
+    1e-4 S/m | half-space 0.1 S/m, the seven blocks of COMMEMI3D3_BLOCKS, on
+    cubes of h metres covering x in [0, 4.4] km, y in [0, 5.6] km and
+    z in [0.05, 3] km (176 x 224 x 118 cells for h = 25 m, as in the paper's
+    scalability runs).  Cells outside the blocks carry the background."""
+    nx, ny = int(round(4400.0 / h)), int(round(5600.0 / h))
+    nz = int(round(2950.0 / h))
+    z_edges = 50.0 + h * np.arange(nz + 1)
+    d = np.array([0.0, 1000.0, 7500.0])
+    sigma = np.array([0.0, 1e-3, 1e-4, 0.1], dtype=np.complex128)
+    m = make_model(nx, ny, nz, h, h, z_edges, d, sigma, freq)
+    sa = m["sigma_a"].copy()
+    boxes = []
+    for (x1, y1, z1, x2, y2, z2, sg) in COMMEMI3D3_BLOCKS:
+        ix = (int(round(1000.0 * x1 / h)), int(round(1000.0 * x2 / h)))
+        iy = (int(round(1000.0 * y1 / h)), int(round(1000.0 * y2 / h)))
+        iz = (int(round((1000.0 * z1 - 50.0) / h)), int(round((1000.0 * z2 - 50.0) / h)))
+        sa[iz[0]:iz[1], iy[0]:iy[1], ix[0]:ix[1]] = sg
+        boxes.append((ix[0], ix[1], iy[0], iy[1], iz[0], iz[1], sg))
+    m["sigma_a"] = sa
+    m["boxes"] = boxes
+    return m
 
 
 def config_gradient(seed=5):

@@ -35,7 +35,7 @@ static bool factor_ok(int L, FftDesc &d) {
   d.L = L;
   d.nf = 0;
   int m = L;
-  const int radices[] = {16, 8, 4, 2, 3, 5, 7};
+  const int radices[] = {16, 8, 4, 2, 3, 5, 7, 11};
   for (int r : radices) {
     while (m % r == 0) {
       if (d.nf >= kMaxFactors) return false;
@@ -49,7 +49,7 @@ static bool factor_ok(int L, FftDesc &d) {
 static int make_plan(int L, FftPlan &p) {
   if (!factor_ok(L, p.d)) {
     set_error("transform length " + std::to_string(L) +
-              " must factor into 2, 3, 5 and 7 (Nx and Ny must be 7-smooth)");
+              " must factor into 2, 3, 5, 7 and 11 (Nx and Ny must be 11-smooth)");
     return GIEM_EINVAL;
   }
   std::vector<c128> t64(L);

@@ -66,7 +66,7 @@ constexpr int kMaxFactors = 24;
 struct FftDesc {
   int L;                  // transform length
   int nf;                 // number of radix stages
-  int fac[kMaxFactors];   // radices in stage order (16, 8, 4, 2, 3, 5, 7)
+  int fac[kMaxFactors];   // radices in stage order (16, 8, 4, 2, 3, 5, 7, 11)
 };
 
 // Per-RHS vector pointers of one apply (the basis vectors of GMRES are not

@@ -11,7 +11,7 @@
 // frequency point as one contiguous run and the FFT passes move G adjacent
 // planes (128-byte runs) per frequency point.
 //
-// FFTs are mixed-radix (16, 8, 4, 2, 3, 5, 7) Stockham passes done in LDS,
+// FFTs are mixed-radix (16, 8, 4, 2, 3, 5, 7, 11) Stockham passes done in LDS,
 // G sequences per workgroup; radix 16 and 8 are nested length-4 transforms in
 // registers, so a 256-point transform takes two passes through LDS.  Twiddles
 // between passes come from a per-length table.
@@ -220,7 +220,8 @@ __device__ void fft_lds(cplx<T> *buf, int G, int ld, const FftDesc &fd,
         case 2: fft_pass<T, 2, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
         case 3: fft_pass<T, 3, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
         case 5: fft_pass<T, 5, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
-        default: fft_pass<T, 7, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
+        case 7: fft_pass<T, 7, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
+        default: fft_pass<T, 11, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
       }
     }
     ns *= p;

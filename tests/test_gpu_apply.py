@@ -9,10 +9,10 @@ from tests.gpu_util import random_model, rel_err, to_dev
 
 pytestmark = pytest.mark.gpu
 
-# (nx, ny, nz, nrhs): single-cell and single-row edge cases, ragged 7-smooth
-# sizes whose padded lengths need radices 3, 5 and 7, the 16 x 16 x 4 grid.
+# (nx, ny, nz, nrhs): single-cell and single-row edge cases, ragged 11-smooth
+# sizes whose padded lengths need radices 3, 5, 7 and 11, the 16 x 16 x 4 grid.
 SHAPES = [(1, 1, 1, 1), (1, 5, 2, 1), (6, 1, 3, 2), (4, 3, 2, 3), (15, 7, 3, 2),
-          (10, 14, 2, 1), (16, 16, 4, 2), (9, 12, 5, 1)]
+          (10, 14, 2, 1), (16, 16, 4, 2), (9, 12, 5, 1), (11, 22, 2, 2), (33, 4, 3, 1)]
 
 
 def _case(nx, ny, nz, seed):
@@ -119,7 +119,7 @@ def test_apply_argument_errors_leave_output_untouched(lib):
 
 
 def test_rejects_non_smooth_sizes_and_bad_models(lib):
-    m, t, _ = _case(11, 4, 2, 5)
+    m, t, _ = _case(13, 4, 2, 5)
     with pytest.raises(lib.GiemError):
         lib.tables_import(m, [m["freq"]], t[None])
     m2, t2, _ = _case(4, 4, 2, 6)
@@ -177,7 +177,7 @@ def test_apply_full_size_sampled(lib, full_case, mode, prec, tol, nbuf):
     assert err <= tol, err
 
 
-@pytest.mark.parametrize("nx,ny,nz,nrhs", [(15, 7, 3, 2), (16, 16, 4, 2), (48, 40, 2, 1)])
+@pytest.mark.parametrize("nx,ny,nz,nrhs", [(15, 7, 3, 2), (16, 16, 4, 2), (48, 40, 2, 1), (11, 22, 2, 2)])
 def test_every_fft_shape_matches_dense(lib, nx, ny, nz, nrhs):
     # every (sequences, threads) launch shape of the four FFT passes gives the
     # dense product; giem_tune then keeps one of them per pass
