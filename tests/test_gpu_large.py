@@ -1,11 +1,12 @@
-"""A grid of the size of the paper's scalability workload on one GPU: 175 x
-224 x 118 cubes of 25 m (4.6 M cells, 13.9 M unknowns per right-hand side,
-two plane-wave sources), seven blocks of contrast up to 3.3e4, tables from
-giem_tables (35 GB of FP64 spectra plus a complex64 copy).  Only internal
-checks are possible at this size:
+"""The paper's benchmark model on one GPU (Sect. 4, Table commemi_table):
+176 x 224 x 118 cubes of 25 m from z = 50 m (4.65 M cells, 14 M unknowns per
+right-hand side, two plane-wave sources at 1 Hz), seven blocks of contrast up
+to 3.3e4, tables from giem_tables (35 GB of FP64 spectra plus a complex64
+copy).  Only internal checks are possible at this size:
   - the FP64 apply at sampled cells against the oracle's direct sum on the
-    exported table (gather block-product kernel, 350- and 448-point FFTs);
-  - the precision form against the FP64 solve (both to 1e-8);
+    exported table (gather block-product kernel, 352-point transforms with a
+    radix-11 pass, 448-point transforms);
+  - the precision form against the FP64 solve (both GMRES(60) to 1e-7);
   - sigma_a = sigma_b (A = I) returns the normal field in one Arnoldi step."""
 import time
 
@@ -21,7 +22,7 @@ pytestmark = pytest.mark.gpu
 
 def test_large_grid(lib):
     import torch
-    m = gs.config_large()
+    m = gs.config_commemi3d3()
     nx, ny, nz = m["nx"], m["ny"], m["nz"]
     t0 = time.perf_counter()
     h = lib.tables(m, [m["freq"]], flags=lib.TABLES_C64)
@@ -45,22 +46,32 @@ def test_large_grid(lib):
     print(f"  sampled FP64 apply vs oracle: {ea:.2e}", flush=True)
     assert ea <= 1e-10
 
-    # precision form against FP64
+    # precision form against FP64, GMRES(60) to 1e-7 (contrast 3.3e4: about
+    # 1,800 steps); solved in chunks of warm-started calls so that every
+    # chunk reports its residual
     shape = (2, 3, nz, ny, nx)
+
+    def chunked(prec, E):
+        done, t = 0, time.perf_counter()
+        while True:
+            st = h.solve(sa, E, tol=1e-7, restart=60, max_iter=600, precision=prec,
+                         warm_start=1 if done else 0, max_outer=40)
+            done += st["iters"]
+            print(f"    prec {prec}: {done} steps, residual {st['rel_residual']:.2e}, "
+                  f"{time.perf_counter() - t:.1f} s", flush=True)
+            if st["converged"] or done >= 6000:
+                return st, done, time.perf_counter() - t
+
     E64 = torch.zeros(shape, dtype=torch.complex128, device="cuda")
-    t1 = time.perf_counter()
-    s64 = h.solve(sa, E64, tol=1e-8, max_iter=8000)
-    t2 = time.perf_counter()
+    s64, n64, t64 = chunked(lib.FP64, E64)
     E32 = torch.zeros_like(E64)
-    s32 = h.solve(sa, E32, tol=1e-8, max_iter=8000, precision=lib.FP32, max_outer=60)
-    t3 = time.perf_counter()
+    s32, n32, t32 = chunked(lib.FP32, E32)
     assert s64["converged"] == 1 and s32["converged"] == 1, (s64, s32)
     errs = [float(torch.linalg.vector_norm(E32[p] - E64[p]) / torch.linalg.vector_norm(E64[p]))
             for p in range(2)]
-    print(f"  FP64 to 1e-8: {s64['iters']} it {t2 - t1:.1f} s; FP32-refined: {s32['iters']} it "
-          f"{s32['outer_iters']} outer {t3 - t2:.1f} s; difference {errs[0]:.1e} {errs[1]:.1e}",
-          flush=True)
-    assert max(errs) <= 1e-6
+    print(f"  FP64 to 1e-7: {n64} steps {t64:.1f} s; FP32-refined: {n32} inner steps "
+          f"{t32:.1f} s; difference {errs[0]:.1e} {errs[1]:.1e}", flush=True)
+    assert max(errs) <= 1e-5
     del E32
 
     # no anomaly: the normal field
