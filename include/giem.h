@@ -96,6 +96,9 @@ typedef struct {
   int32_t max_outer;   /* GIEM_FP32: limit on refinement steps                */
   int32_t weighted_ip; /* nonzero: volume-weighted L2 inner product (Sect. 2.1) */
   int32_t warm_start;  /* nonzero: E_cells holds the initial guess on entry    */
+  int32_t graph;       /* nonzero: each restart cycle runs as one captured HIP
+                          graph with the Arnoldi step on the device (one host
+                          wait per cycle); giem_solve_multi always does      */
 } giem_solve_opts;
 
 typedef struct {
@@ -287,6 +290,40 @@ int giem_solve(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
  */
 int giem_solve_batch(giem_handle *t, int32_t nf, const int32_t *ifreqs, const void *sigma_a,
                      int32_t nrhs, const void *const *rhs, void *const *E_cells,
+                     const giem_solve_opts *opts, giem_solve_stats *stats, void *stream);
+
+/*
+ * giem_solve_multi -- the systems of several models (handles, grids of any
+ * size) at several frequencies each, solved together: Sect. 3.3 item (ii)
+ * GMRES for every (model, frequency, right-hand side) system, each restart
+ * cycle of m Arnoldi steps recorded once as a HIP graph and replayed.  Inside
+ * a cycle nothing returns to the host: the applies, both Gram-Schmidt passes
+ * (the second one gated on the device by the same cancellation test as
+ * giem_solve), the Hessenberg column, the Givens rotation and the residual
+ * estimate run on the device, and the kernels of different models run on
+ * separate branches of the graph.  The host waits once per cycle (Krylov
+ * solution update, true residual, convergence).  A system that converges
+ * inside a cycle keeps its Krylov length at that step.  With GIEM_FP32 the
+ * FP64 residual refinement runs on the host and every inner solve is such a
+ * cycle of complex64 graphs.
+ *   groups:  host [ngroups]; group g solves handle t (each handle in one
+ *            group) at its frequency indices ifreqs[nf] with its sigma_a,
+ *            right-hand sides rhs[nf] (or NULL / NULL entries: plane waves,
+ *            nrhs <= 2) into E_cells[nf] (as giem_solve_batch);
+ *   stats:   host [sum of nf] in group order, or NULL.
+ * At most 96 systems in total; every handle on the current device.  Errors
+ * and ENOCONV as giem_solve.
+ */
+typedef struct {
+  giem_handle *t;
+  int32_t nf;
+  const int32_t *ifreqs;      /* host [nf]                                    */
+  const void *sigma_a;        /* device c128 [Nz][Ny][Nx] of this model       */
+  const void *const *rhs;     /* host [nf] device pointers, or NULL           */
+  void *const *E_cells;       /* host [nf] device pointers [nrhs][3][N] c128  */
+} giem_solve_group;
+
+int giem_solve_multi(int32_t ngroups, const giem_solve_group *groups, int32_t nrhs,
                      const giem_solve_opts *opts, giem_solve_stats *stats, void *stream);
 
 /*

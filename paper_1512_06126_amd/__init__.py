@@ -44,7 +44,14 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int32),
-                ("weighted_ip", ctypes.c_int32), ("warm_start", ctypes.c_int32)]
+                ("weighted_ip", ctypes.c_int32), ("warm_start", ctypes.c_int32),
+                ("graph", ctypes.c_int32)]
+
+
+class SolveGroup(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_void_p), ("nf", ctypes.c_int32), ("ifreqs", ctypes.c_void_p),
+                ("sigma_a", ctypes.c_void_p), ("rhs", ctypes.c_void_p),
+                ("E_cells", ctypes.c_void_p)]
 
 
 class SolveStats(ctypes.Structure):
@@ -78,6 +85,7 @@ def load():
         "giem_apply_timed": [P, I32, P, I32, P, P, U32, U32, P, P],
         "giem_apply_batch": [P, I32, P, P, I32, P, P, U32, U32, P],
         "giem_solve": [P, I32, P, I32, P, P, P, P, P],
+        "giem_solve_multi": [I32, P, I32, P, P, P],
         "giem_solve_batch": [P, I32, P, P, I32, P, P, P, P, P],
         "giem_adjoint": [P, I32, P, I32, P, P, P, P, P, P],
         "giem_fields": [P, I32, P, I32, P, I32, P, P, P, P],
@@ -104,7 +112,7 @@ def load():
 
 def exported_symbols():
     return ["giem_tables", "giem_tables_import", "giem_tables_export", "giem_tables_bytes",
-            "giem_apply", "giem_apply_timed", "giem_apply_batch", "giem_tune", "giem_set_fft_shape", "giem_set_block_buffers", "giem_profile", "giem_profile_read", "giem_solve", "giem_solve_batch",
+            "giem_apply", "giem_apply_timed", "giem_apply_batch", "giem_tune", "giem_set_fft_shape", "giem_set_block_buffers", "giem_profile", "giem_profile_read", "giem_solve", "giem_solve_batch", "giem_solve_multi",
             "giem_adjoint", "giem_fields", "giem_fields_adjoint", "giem_impedance",
             "giem_impedance_adjoint", "giem_free", "giem_last_error"]
 
@@ -245,10 +253,10 @@ class Handle:
 
     def solve(self, sigma_a, E_out, rhs=None, tol=1e-6, restart=30, max_iter=2000,
               precision=FP64, inner_tol=1e-3, max_outer=20, weighted_ip=0, warm_start=0,
-              ifreq=0, stream=None):
+              ifreq=0, stream=None, graph=0):
         o = SolveOpts(tol=tol, restart=restart, max_iter=max_iter, precision=precision,
                       inner_tol=inner_tol, max_outer=max_outer, weighted_ip=weighted_ip,
-                      warm_start=warm_start)
+                      warm_start=warm_start, graph=graph)
         st = SolveStats()
         nrhs = E_out.shape[0]
         rp = _ptr(rhs) if rhs is not None else ctypes.c_void_p(0)
@@ -261,7 +269,7 @@ class Handle:
 
     def solve_batch(self, sigma_a, E_outs, ifreqs=None, rhs=None, tol=1e-6, restart=30,
                     max_iter=2000, precision=FP64, inner_tol=1e-3, max_outer=20, weighted_ip=0,
-                    warm_start=0, stream=None):
+                    warm_start=0, stream=None, graph=0):
         """Solve at several frequencies at once: E_outs[f] receives the
         solution at frequency ifreqs[f] (all frequencies by default); rhs is
         None (plane waves) or a list of tensors.  Returns one stats dict per
@@ -276,7 +284,7 @@ class Handle:
             rp = (ctypes.c_void_p * nf)(*[(r.data_ptr() if r is not None else None) for r in rhs])
         o = SolveOpts(tol=tol, restart=restart, max_iter=max_iter, precision=precision,
                       inner_tol=inner_tol, max_outer=max_outer, weighted_ip=weighted_ip,
-                      warm_start=warm_start)
+                      warm_start=warm_start, graph=graph)
         st = (SolveStats * nf)()
         rc = _lib.giem_solve_batch(self._p, nf, fi, _ptr(sigma_a), E_outs[0].shape[0], rp, ep,
                                    ctypes.byref(o), st, _stream(stream))
@@ -323,6 +331,46 @@ class Handle:
                                         _ptr(E_cells), rec.shape[0], rec.ctypes.data, _ptr(wE),
                                         _ptr(wH), _ptr(adj_src), _ptr(grad), _stream(stream)))
         return adj_src, grad
+
+
+def solve_multi(groups, tol=1e-6, restart=30, max_iter=2000, precision=FP64, inner_tol=1e-3,
+                max_outer=20, weighted_ip=0, warm_start=0, stream=None):
+    """giem_solve_multi: groups is a list of (handle, sigma_a, E_outs, ifreqs,
+    rhs) tuples (ifreqs None: all of the handle's frequencies; rhs None: plane
+    waves, else a list of tensors); every E_outs[f] has the same number of
+    right-hand sides.  Returns one stats dict per (group, frequency)."""
+    load()
+    keep = []
+    arr = (SolveGroup * len(groups))()
+    nrhs = None
+    total = 0
+    for g, (h, sa, E_outs, ifreqs, rhs) in enumerate(groups):
+        nf = len(E_outs)
+        if ifreqs is None:
+            ifreqs = list(range(nf))
+        fi = (ctypes.c_int32 * nf)(*ifreqs)
+        ep = (ctypes.c_void_p * nf)(*[e.data_ptr() for e in E_outs])
+        rp = None
+        if rhs is not None:
+            rp = (ctypes.c_void_p * nf)(*[(r.data_ptr() if r is not None else None) for r in rhs])
+        keep += [fi, ep, rp]
+        arr[g] = SolveGroup(t=h._p, nf=nf, ifreqs=ctypes.cast(fi, ctypes.c_void_p),
+                            sigma_a=sa.data_ptr(), rhs=ctypes.cast(rp, ctypes.c_void_p) if rp else None,
+                            E_cells=ctypes.cast(ep, ctypes.c_void_p))
+        nrhs = E_outs[0].shape[0]
+        total += nf
+    o = SolveOpts(tol=tol, restart=restart, max_iter=max_iter, precision=precision,
+                  inner_tol=inner_tol, max_outer=max_outer, weighted_ip=weighted_ip,
+                  warm_start=warm_start, graph=1)
+    st = (SolveStats * total)()
+    rc = _lib.giem_solve_multi(len(groups), arr, nrhs, ctypes.byref(o), st, _stream(stream))
+    _check(rc, allow_noconv=True)
+    out = []
+    for k in range(total):
+        d = st[k].as_dict()
+        d["rc"] = rc
+        out.append(d)
+    return out
 
 
 def impedance(E_rec, H_rec, Z, stream=None):

@@ -85,19 +85,46 @@ using DotArgs = DotArgsT<c128>;
 using DotArgs32 = DotArgsT<c64>;
 int dot_partials_per_rhs();
 // partial sums of conj-weighted dots <w, V_i> (i < nb) and ||w||^2 into
-// part[r][block][nb + 1]; then reduced into out[r][nb + 1].
+// part[r][block][nb + 1]; then reduced into out[r][nb + 1].  With a gate,
+// system r is skipped (zeros out) unless gate[gate_off + r] is set.
 hipError_t launch_dots(const DotArgs &a, int nrhs, int nb, size_t n, int nz, int plane,
-                       const double *wlev, c128 *part, c128 *out, hipStream_t s);
+                       const double *wlev, c128 *part, c128 *out, hipStream_t s,
+                       const int *gate = nullptr, int gate_off = 0);
 hipError_t launch_dots(const DotArgs32 &a, int nrhs, int nb, size_t n, int nz, int plane,
-                       const double *wlev, c128 *part, c128 *out, hipStream_t s);
+                       const double *wlev, c128 *part, c128 *out, hipStream_t s,
+                       const int *gate = nullptr, int gate_off = 0);
 // w -= sum_i f[r][i] h[r][i] V_i (f = hscale[r * sstride + i], or 1 when
-// hscale is null), and ||w||^2 reduced into nrm[r] (real in .x)
+// hscale is null), and ||w||^2 reduced into nrm[r] (real in .x); gated as
+// launch_dots (a skipped system keeps w and gets nrm 0)
 hipError_t launch_update(const DotArgs &a, int nrhs, int nb, size_t n, int nz, int plane,
                          const double *wlev, const c128 *h, int hstride, const double *hscale,
-                         int sstride, c128 *part, c128 *nrm, hipStream_t s);
+                         int sstride, c128 *part, c128 *nrm, hipStream_t s,
+                         const int *gate = nullptr, int gate_off = 0);
 hipError_t launch_update(const DotArgs32 &a, int nrhs, int nb, size_t n, int nz, int plane,
                          const double *wlev, const c128 *h, int hstride, const double *hscale,
-                         int sstride, c128 *part, c128 *nrm, hipStream_t s);
+                         int sstride, c128 *part, c128 *nrm, hipStream_t s,
+                         const int *gate = nullptr, int gate_off = 0);
+// Device-side Arnoldi state of the systems of one graph-captured GMRES
+// cycle (index q): raw projections of both Gram-Schmidt passes (each handle's
+// systems in a region of their own, (m + 2) entries per system, laid out at
+// stride j + 2 in step j), squared norms after each pass, the second-pass gates, the
+// squared basis norms and their inverses at stride kArnStride, the rotated
+// Hessenberg matrix [(m + 1) m], rotations [m], residual vector [m + 1], and
+// per system the tolerance times |b|, convergence flag and Krylov length.
+constexpr int kArnStride = 65;
+struct ArnoldiState {
+  c128 *h1, *h2, *nrm1, *nrm2;
+  int *gate;
+  double *vn2, *scale;
+  c128 *H, *cs, *sn, *g;
+  double *tolb;
+  int *conv, *jlen;
+};
+hipError_t launch_gs_gate(int nq, const c128 *h1, int hstride, const c128 *nrm1, int *gate,
+                          double drop, hipStream_t s);
+// h1c, h2c: the raw projections of system q0 (the next at stride j + 2)
+hipError_t launch_arnoldi_tail(const ArnoldiState &st, const c128 *h1c, const c128 *h2c, int q0,
+                               int nq, int j, int m, hipStream_t s);
 // dst[r] = src[r] * scal[r] (complex scalars from the host)
 hipError_t launch_scale(c128 *const *dst, const c128 *const *src, const c128 *scal, int nrhs,
                         size_t n, hipStream_t s);

@@ -58,11 +58,19 @@ constexpr int kSlots = 8;
 template <typename VT, int SLOTS, bool P2>
 __global__ void __launch_bounds__(256)
 k_dots(DotArgsT<VT> a, int nb, size_t n, int nz, int plane, const double *__restrict__ wlev,
-       c128 *__restrict__ part) {
+       c128 *__restrict__ part, const int *__restrict__ gate, int gate_off) {
   constexpr int kSlots = SLOTS;
   __shared__ double red[8];
   const int r = blockIdx.y;
   const int s0 = blockIdx.z * kSlots;
+  if (gate && !gate[gate_off + r]) {
+    // pass not wanted for this system: zero partials, nothing read
+    if (threadIdx.x == 0)
+      for (int q = 0; q < kSlots; ++q)
+        if (s0 + q <= nb)
+          part[((size_t)r * (nb + 1) + s0 + q) * gridDim.x + blockIdx.x] = mk<double>(0.0, 0.0);
+    return;
+  }
   const VT *w = a.w[r];
   const VT *V = a.basis[r];
   double accr[kSlots], acci[kSlots];
@@ -152,25 +160,27 @@ static bool pairs_ok(const DotArgsT<VT> &a, int nrhs, size_t n) {
 template <typename VT>
 static hipError_t launch_dots_t(const DotArgsT<VT> &a, int nrhs, int nb, size_t n, int nz,
                                 int plane, const double *wlev, c128 *part, c128 *out,
-                                hipStream_t s) {
+                                hipStream_t s, const int *gate, int gate_off) {
   const int nslots = nb + 1;
   const dim3 grid(kRedBlocks, nrhs, (nslots + kSlots - 1) / kSlots);
   if (pairs_ok(a, nrhs, n))
-    k_dots<VT, kSlots, true><<<grid, 256, 0, s>>>(a, nb, n, nz, plane, wlev, part);
+    k_dots<VT, kSlots, true><<<grid, 256, 0, s>>>(a, nb, n, nz, plane, wlev, part, gate, gate_off);
   else
-    k_dots<VT, kSlots, false><<<grid, 256, 0, s>>>(a, nb, n, nz, plane, wlev, part);
+    k_dots<VT, kSlots, false><<<grid, 256, 0, s>>>(a, nb, n, nz, plane, wlev, part, gate, gate_off);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_reduce<<<dim3(nslots, nrhs), 256, 0, s>>>(part, kRedBlocks, nslots, out);
   return hipGetLastError();
 }
 hipError_t launch_dots(const DotArgs &a, int nrhs, int nb, size_t n, int nz, int plane,
-                       const double *wlev, c128 *part, c128 *out, hipStream_t s) {
-  return launch_dots_t(a, nrhs, nb, n, nz, plane, wlev, part, out, s);
+                       const double *wlev, c128 *part, c128 *out, hipStream_t s, const int *gate,
+                       int gate_off) {
+  return launch_dots_t(a, nrhs, nb, n, nz, plane, wlev, part, out, s, gate, gate_off);
 }
 hipError_t launch_dots(const DotArgs32 &a, int nrhs, int nb, size_t n, int nz, int plane,
-                       const double *wlev, c128 *part, c128 *out, hipStream_t s) {
-  return launch_dots_t(a, nrhs, nb, n, nz, plane, wlev, part, out, s);
+                       const double *wlev, c128 *part, c128 *out, hipStream_t s, const int *gate,
+                       int gate_off) {
+  return launch_dots_t(a, nrhs, nb, n, nz, plane, wlev, part, out, s, gate, gate_off);
 }
 
 // w -= sum_{i < nb} h[r][i] V_i ; partial ||w||^2 into part[r][0][block]
@@ -178,10 +188,14 @@ template <typename VT, bool P2>
 __global__ void __launch_bounds__(256)
 k_update(DotArgsT<VT> a, int nb, size_t n, int nz, int plane, const double *__restrict__ wlev,
          const c128 *__restrict__ h, int hstride, const double *__restrict__ hscale,
-         int sstride, c128 *__restrict__ part) {
+         int sstride, c128 *__restrict__ part, const int *__restrict__ gate, int gate_off) {
   __shared__ double red[8];
   __shared__ c128 hs[64];
   const int r = blockIdx.y;
+  if (gate && !gate[gate_off + r]) {
+    if (threadIdx.x == 0) part[(size_t)r * gridDim.x + blockIdx.x] = mk<double>(0.0, 0.0);
+    return;
+  }
   VT *w = const_cast<VT *>(a.w[r]);
   const VT *V = a.basis[r];
   for (int i = threadIdx.x; i < nb; i += blockDim.x) {
@@ -233,15 +247,15 @@ template <typename VT>
 static hipError_t launch_update_t(const DotArgsT<VT> &a, int nrhs, int nb, size_t n, int nz,
                                   int plane, const double *wlev, const c128 *h, int hstride,
                                   const double *hscale, int sstride, c128 *part, c128 *nrm,
-                                  hipStream_t s) {
+                                  hipStream_t s, const int *gate, int gate_off) {
   if (nb > 64) return hipErrorInvalidValue;
   dim3 grid(kRedBlocks, nrhs);
   if (pairs_ok(a, nrhs, n))
     k_update<VT, true><<<grid, 256, 0, s>>>(a, nb, n, nz, plane, wlev, h, hstride, hscale,
-                                             sstride, part);
+                                             sstride, part, gate, gate_off);
   else
     k_update<VT, false><<<grid, 256, 0, s>>>(a, nb, n, nz, plane, wlev, h, hstride, hscale,
-                                              sstride, part);
+                                              sstride, part, gate, gate_off);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_reduce<<<dim3(1, nrhs), 256, 0, s>>>(part, kRedBlocks, 1, nrm);
@@ -249,15 +263,17 @@ static hipError_t launch_update_t(const DotArgsT<VT> &a, int nrhs, int nb, size_
 }
 hipError_t launch_update(const DotArgs &a, int nrhs, int nb, size_t n, int nz, int plane,
                          const double *wlev, const c128 *h, int hstride, const double *hscale,
-                         int sstride, c128 *part, c128 *nrm, hipStream_t s) {
+                         int sstride, c128 *part, c128 *nrm, hipStream_t s, const int *gate,
+                         int gate_off) {
   return launch_update_t(a, nrhs, nb, n, nz, plane, wlev, h, hstride, hscale, sstride, part, nrm,
-                         s);
+                         s, gate, gate_off);
 }
 hipError_t launch_update(const DotArgs32 &a, int nrhs, int nb, size_t n, int nz, int plane,
                          const double *wlev, const c128 *h, int hstride, const double *hscale,
-                         int sstride, c128 *part, c128 *nrm, hipStream_t s) {
+                         int sstride, c128 *part, c128 *nrm, hipStream_t s, const int *gate,
+                         int gate_off) {
   return launch_update_t(a, nrhs, nb, n, nz, plane, wlev, h, hstride, hscale, sstride, part, nrm,
-                         s);
+                         s, gate, gate_off);
 }
 
 template <typename VT>
@@ -420,6 +436,99 @@ hipError_t launch_div_cells(c128 *out, const c128 *u, const c128 *acell, int nrh
 hipError_t launch_mul_cells(c128 *out, const c128 *u, const c128 *acell, int nrhs, size_t ncell,
                             hipStream_t s) {
   k_cellop<<<1024, 256, 0, s>>>(out, u, acell, ncell, (size_t)nrhs * 3 * ncell, 0);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- device-side Arnoldi
+// For GMRES cycles captured in a HIP graph (no host round trip per step):
+// the decision for the second Gram-Schmidt pass, and the Hessenberg column,
+// Givens rotation and residual estimate of step j, all on the device.
+
+// gate[q] = 1 when the projection removed more than 1 - drop of the squared
+// norm (||w'||^2 < drop ||w||^2), i.e. the pass is to be repeated
+__global__ void k_gs_gate(int nq, const c128 *__restrict__ h1, int hstride,
+                          const c128 *__restrict__ nrm1, int *__restrict__ gate, double drop) {
+  const int q = threadIdx.x;
+  if (q < nq) gate[q] = nrm1[q].x < drop * h1[(size_t)q * hstride + hstride - 1].x ? 1 : 0;
+}
+
+hipError_t launch_gs_gate(int nq, const c128 *h1, int hstride, const c128 *nrm1, int *gate,
+                          double drop, hipStream_t s) {
+  if (nq > 64) return hipErrorInvalidValue;
+  k_gs_gate<<<1, 64, 0, s>>>(nq, h1, hstride, nrm1, gate, drop);
+  return hipGetLastError();
+}
+
+__device__ __forceinline__ c128 cconj(c128 a) { return mk<double>(a.x, -a.y); }
+__device__ __forceinline__ double cabs2(c128 a) { return hypot(a.x, a.y); }
+__device__ __forceinline__ c128 cscal(c128 a, double f) { return mk<double>(a.x * f, a.y * f); }
+
+// Step j of the Arnoldi process of systems q0 .. q0 + nq - 1 (one thread
+// each).  The basis is kept unnormalised (vn2[i] = |V_i|^2); h1c (and h2c
+// after a second pass, gate[q] set) hold <V_i, w> for i <= j of system q0 + t
+// at offset t (j + 2); nrm1 and nrm2 the squared norm of the projected w after
+// each pass.
+__global__ void k_arnoldi_tail(ArnoldiState st, const c128 *__restrict__ h1c,
+                               const c128 *__restrict__ h2c, int q0, int nq, int j, int m) {
+  const int q = q0 + (int)threadIdx.x;
+  if ((int)threadIdx.x >= nq) return;
+  const int hs = j + 2;
+  const c128 *h1 = h1c + (size_t)threadIdx.x * hs;
+  const c128 *h2 = h2c + (size_t)threadIdx.x * hs;
+  const bool two = st.gate[q] != 0;
+  double *vn2 = st.vn2 + (size_t)q * kArnStride;
+  double *scl = st.scale + (size_t)q * kArnStride;
+  c128 *H = st.H + (size_t)q * (m + 1) * m;
+  c128 *cs = st.cs + (size_t)q * m;
+  c128 *sn = st.sn + (size_t)q * m;
+  c128 *g = st.g + (size_t)q * (m + 1);
+  const double nw = fmax(two ? st.nrm2[q].x : st.nrm1[q].x, 0.0);
+  const double vj = sqrt(vn2[j]);
+  for (int i = 0; i <= j; ++i) {
+    c128 hv = h1[i];
+    if (two) hv = cadd(hv, h2[i]);
+    const double d = sqrt(vn2[i]) * vj;
+    H[(size_t)i * m + j] = d > 0.0 ? cscal(hv, 1.0 / d) : mk<double>(0.0, 0.0);
+  }
+  const double wn = sqrt(nw);
+  const double hn = vj > 0.0 ? wn / vj : 0.0;
+  vn2[j + 1] = nw;
+  scl[j + 1] = nw > 0.0 ? 1.0 / nw : 0.0;
+  c128 hj1 = mk<double>(hn, 0.0);
+  for (int i = 0; i < j; ++i) {  // earlier rotations
+    const c128 a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
+    H[(size_t)i * m + j] = cadd(cmul(cs[i], a), cmul(sn[i], b));
+    H[(size_t)(i + 1) * m + j] = csub(cmul(cs[i], b), cmul(cconj(sn[i]), a));
+  }
+  const c128 a = H[(size_t)j * m + j];
+  const double an = cabs2(a), bn = cabs2(hj1);
+  const double rr = hypot(an, bn);
+  c128 c, sv;
+  if (an == 0.0) {
+    c = mk<double>(0.0, 0.0);
+    sv = mk<double>(1.0, 0.0);
+  } else {
+    c = mk<double>(an / rr, 0.0);
+    sv = cscal(cmul(cscal(a, 1.0 / an), cconj(hj1)), 1.0 / rr);
+  }
+  cs[j] = c;
+  sn[j] = sv;
+  H[(size_t)j * m + j] = cadd(cmul(c, a), cmul(sv, hj1));
+  H[(size_t)(j + 1) * m + j] = mk<double>(0.0, 0.0);
+  const c128 gj = g[j];
+  g[j + 1] = cscal(cmul(cconj(sv), gj), -1.0);
+  g[j] = cmul(c, gj);
+  const double est = cabs2(g[j + 1]);
+  if (!st.conv[q] && (est <= st.tolb[q] || hn == 0.0)) {
+    st.conv[q] = 1;
+    st.jlen[q] = j + 1;
+  }
+}
+
+hipError_t launch_arnoldi_tail(const ArnoldiState &st, const c128 *h1c, const c128 *h2c, int q0,
+                               int nq, int j, int m, hipStream_t s) {
+  if (nq > 64) return hipErrorInvalidValue;
+  k_arnoldi_tail<<<1, 64, 0, s>>>(st, h1c, h2c, q0, nq, j, m);
   return hipGetLastError();
 }
 

@@ -12,6 +12,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 
 #include "handle.h"
 
@@ -513,6 +514,423 @@ static int gmres(giem_handle *t, const std::vector<int> &fq, int nrhs, const VT 
   return GIEM_OK;
 }
 
+// ------------------------------------------------------------ graph-captured GMRES
+// The same GMRES(m) for systems of several handles (models of different grid
+// size) and frequencies, with each restart cycle of L <= m Arnoldi steps
+// recorded once as a HIP graph and replayed: the applies, both Gram-Schmidt
+// passes (the second gated on the device), the Hessenberg column, the Givens
+// rotation and the residual estimate all run on the device, so the host waits
+// once per cycle instead of once per step.  Every system runs the whole
+// cycle; one that converges (or breaks down) inside it records its Krylov
+// length and its later steps are not used.  The systems of one handle form a
+// contiguous range and get a branch (stream) of their own inside the graph,
+// so the kernels of different models overlap.
+
+template <typename VT>
+struct GSys {
+  giem_handle *t;
+  int fq;        // frequency index of the handle
+  const VT *b;
+  VT *x;
+};
+
+struct GraphExecs {
+  std::map<std::vector<int>, hipGraphExec_t> exec;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> events;
+  ~GraphExecs() {
+    for (auto &e : exec) hipGraphExecDestroy(e.second);
+    for (hipStream_t b : streams) hipStreamDestroy(b);
+    for (hipEvent_t e : events) hipEventDestroy(e);
+  }
+};
+
+// largest number of vectors apply_sys puts into one launch for these systems
+static int apply_sys_max_vectors(const giem_handle *t, const std::vector<int> &fq,
+                                 const std::vector<int> &sys) {
+  std::map<int, int> per_f;
+  for (int q : sys) per_f[fq[q]]++;
+  const size_t per_vec = (size_t)2 * 4 * t->nx * t->ny * 3 * t->nz * sizeof(c128);
+  const size_t budget = (size_t)8 << 30;
+  int best = 0;
+  std::map<int, int> chunks;  // chunk size -> count
+  for (auto &kv : per_f)
+    for (int left = kv.second; left > 0; left -= kMaxRhs) chunks[std::min(left, kMaxRhs)]++;
+  for (auto &kv : chunks) {
+    const int R = kv.first;
+    const int cap_vec = std::max(R, (int)std::min<size_t>(kMaxVec, budget / per_vec));
+    const int cap_f = std::max(1, std::min(kMaxFreqBatch, cap_vec / R));
+    best = std::max(best, R * std::min(cap_f, kv.second));
+  }
+  return best;
+}
+
+template <typename VT>
+static int gmres_graph(std::vector<GSys<VT>> &sys, const GmresParams &gp, hipStream_t s,
+                       GmresResult &res) {
+  const int ns = (int)sys.size();
+  const int m = gp.m;
+  if (ns < 1 || ns > kMaxSys || m < 1 || m > 64) {
+    set_error("graph GMRES: 1 to 96 systems and 1 <= restart <= 64");
+    return GIEM_EINVAL;
+  }
+  // handle blocks [hb[k], hb[k + 1])
+  std::vector<int> hb{0};
+  for (int q = 1; q < ns; ++q)
+    if (sys[q].t != sys[q - 1].t) hb.push_back(q);
+  hb.push_back(ns);
+  const int nblk = (int)hb.size() - 1;
+  std::vector<int> blk_of(ns);
+  for (int k = 0; k < nblk; ++k)
+    for (int q = hb[k]; q < hb[k + 1]; ++q) blk_of[q] = k;
+  for (int k = 0; k < nblk; ++k) {
+    giem_handle *t = sys[hb[k]].t;
+    for (int q = hb[k + 1]; q < ns; ++q)
+      if (sys[q].t == t) {
+        set_error("graph GMRES: the systems of one handle must be contiguous");
+        return GIEM_EINVAL;
+      }
+    GIEM_TRY(ensure_basis(t, hb[k + 1] - hb[k], m));
+  }
+  auto V = [&](int q, int i) -> VT * {
+    const giem_handle *t = sys[q].t;
+    return static_cast<VT *>(t->basis) + ((size_t)(q - hb[blk_of[q]]) * (m + 1) + i) * t->nvec();
+  };
+  auto wlev_of = [&](const giem_handle *t) {
+    return gp.weighted ? static_cast<const double *>(t->vol_lev) : nullptr;
+  };
+  // per-system frequency list and per-block local views for apply_sys
+  std::vector<std::vector<int>> bfq(nblk);
+  for (int k = 0; k < nblk; ++k)
+    for (int q = hb[k]; q < hb[k + 1]; ++q) bfq[k].push_back(sys[q].fq);
+  // apply y_q = A x_q for the systems qs of block k (local indices q - hb[k])
+  auto apply_block = [&](int k, const std::vector<int> &qs, const std::vector<const VT *> &in,
+                         const std::vector<VT *> &out, hipStream_t st) -> int {
+    std::vector<int> loc;
+    for (int q : qs) loc.push_back(q - hb[k]);
+    return apply_sys(sys[hb[k]].t, bfq[k], loc, in, out, gp.mode, gp.prec, st);
+  };
+  // spectra workspace sized before any capture (no allocation inside a graph)
+  for (int k = 0; k < nblk; ++k) {
+    std::vector<int> loc;
+    for (int q = hb[k]; q < hb[k + 1]; ++q) loc.push_back(q - hb[k]);
+    GIEM_TRY(ensure_spec_ws(sys[hb[k]].t, apply_sys_max_vectors(sys[hb[k]].t, bfq[k], loc),
+                            (int)gp.prec));
+  }
+  // device Arnoldi state, indexed by the position c in the cycle's list
+  const size_t nH = (size_t)(m + 1) * m;
+  const size_t b_h = (size_t)ns * (m + 2) * sizeof(c128), b_n = (size_t)ns * sizeof(c128);
+  const size_t b_v = (size_t)ns * kArnStride * sizeof(double);
+  const size_t b_H = (size_t)ns * nH * sizeof(c128), b_r = (size_t)ns * m * sizeof(c128);
+  const size_t b_g = (size_t)ns * (m + 1) * sizeof(c128), b_i = (size_t)ns * sizeof(int);
+  const size_t b_d = (size_t)ns * sizeof(double);
+  const size_t total = 2 * b_h + 2 * b_n + 2 * b_v + b_H + 2 * b_r + b_g + b_d + 3 * b_i + 256 * 16;
+  struct Dev {
+    void *p = nullptr;
+    ~Dev() {
+      if (p) hipFree(p);
+    }
+  } dev;
+  GIEM_HIP(hipMalloc(&dev.p, total), "hipMalloc Arnoldi state");
+  char *cur = static_cast<char *>(dev.p);
+  auto take = [&](size_t bytes) {
+    char *r = cur;
+    cur += (bytes + 255) & ~(size_t)255;
+    return r;
+  };
+  ArnoldiState st;
+  st.h1 = reinterpret_cast<c128 *>(take(b_h));
+  st.h2 = reinterpret_cast<c128 *>(take(b_h));
+  st.nrm1 = reinterpret_cast<c128 *>(take(b_n));
+  st.nrm2 = reinterpret_cast<c128 *>(take(b_n));
+  st.vn2 = reinterpret_cast<double *>(take(b_v));
+  st.scale = reinterpret_cast<double *>(take(b_v));
+  st.H = reinterpret_cast<c128 *>(take(b_H));
+  st.cs = reinterpret_cast<c128 *>(take(b_r));
+  st.sn = reinterpret_cast<c128 *>(take(b_r));
+  st.g = reinterpret_cast<c128 *>(take(b_g));
+  st.tolb = reinterpret_cast<double *>(take(b_d));
+  st.gate = reinterpret_cast<int *>(take(b_i));
+  st.conv = reinterpret_cast<int *>(take(b_i));
+  st.jlen = reinterpret_cast<int *>(take(b_i));
+  // norms of b
+  std::vector<double> normb(ns), beta(ns);
+  for (int k = 0; k < nblk; ++k) {
+    std::vector<const VT *> bp;
+    for (int q = hb[k]; q < hb[k + 1]; ++q) bp.push_back(sys[q].b);
+    std::vector<double> nb_;
+    GIEM_TRY(norms_of(sys[hb[k]].t, bp.data(), (int)bp.size(), wlev_of(sys[hb[k]].t), s, nb_));
+    for (int q = hb[k]; q < hb[k + 1]; ++q) normb[q] = nb_[q - hb[k]];
+  }
+  res.relres.assign(ns, 0.0);
+  res.iters = 0;
+  res.restarts = 0;
+  std::vector<int> done(ns, 0);
+  for (int q = 0; q < ns; ++q)
+    if (normb[q] == 0.0) {
+      GIEM_HIP(hipMemsetAsync(sys[q].x, 0, sys[q].t->nvec() * sizeof(VT), s), "zero x");
+      done[q] = 1;
+    }
+  GraphExecs gx;
+  for (int k = 0; k < nblk; ++k) {
+    hipStream_t b;
+    GIEM_HIP(hipStreamCreateWithFlags(&b, hipStreamNonBlocking), "hipStreamCreate");
+    gx.streams.push_back(b);
+    hipEvent_t e;
+    GIEM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+    gx.events.push_back(e);
+  }
+  hipEvent_t fork_ev;
+  GIEM_HIP(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming), "hipEventCreate");
+  gx.events.push_back(fork_ev);
+  // graphs are recorded on a stream of their own (the caller's stream may be
+  // the legacy default stream, which cannot be captured) and launched on s
+  hipStream_t cap;
+  GIEM_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "hipStreamCreate");
+  gx.streams.push_back(cap);
+  bool x_zero = gp.x_zero;
+  int iters = 0;
+  std::vector<c128> hostbuf;
+  while (true) {
+    std::vector<int> act;
+    for (int q = 0; q < ns; ++q)
+      if (!done[q]) act.push_back(q);
+    if (act.empty()) break;
+    // r0 = b - A x into V(q, 0) (eager)
+    for (int k = 0; k < nblk; ++k) {
+      std::vector<int> qs;
+      for (int q : act)
+        if (blk_of[q] == k) qs.push_back(q);
+      if (qs.empty()) continue;
+      if (x_zero) {
+        for (int q : qs) {
+          const size_t n = sys[q].t->nvec();
+          GIEM_HIP(hipMemcpyAsync(V(q, 0), sys[q].b, n * sizeof(VT), hipMemcpyDeviceToDevice, s), "copy b");
+          GIEM_HIP(hipMemsetAsync(sys[q].x, 0, n * sizeof(VT), s), "zero x");
+        }
+      } else {
+        std::vector<const VT *> in;
+        std::vector<VT *> out;
+        for (int q : qs) {
+          in.push_back(sys[q].x);
+          out.push_back(V(q, 0));
+        }
+        GIEM_TRY(apply_block(k, qs, in, out, s));
+        for (int q : qs)
+          GIEM_HIP(launch_axpby(V(q, 0), sys[q].b, V(q, 0), mk<double>(1, 0), mk<double>(-1, 0),
+                                sys[q].t->nvec(), s),
+                   "axpby");
+      }
+      std::vector<const VT *> rp;
+      for (int q : qs) rp.push_back(V(q, 0));
+      std::vector<double> bt;
+      GIEM_TRY(norms_of(sys[qs[0]].t, rp.data(), (int)qs.size(), wlev_of(sys[qs[0]].t), s, bt));
+      for (size_t i = 0; i < qs.size(); ++i) beta[qs[i]] = bt[i];
+    }
+    x_zero = false;
+    std::vector<int> cyc;
+    for (int q : act) {
+      res.relres[q] = beta[q] / normb[q];
+      if (beta[q] <= gp.tol * normb[q]) {
+        done[q] = 1;
+        continue;
+      }
+      if (iters < gp.max_iter) cyc.push_back(q);
+    }
+    if (cyc.empty()) break;
+    const int L = std::min(m, gp.max_iter - iters);
+    const int nc = (int)cyc.size();
+    // per-cycle initial state (host image, one upload per array)
+    {
+      std::vector<double> vn2((size_t)ns * kArnStride, 0.0), scl((size_t)ns * kArnStride, 0.0);
+      std::vector<c128> g((size_t)ns * (m + 1), mk<double>(0, 0));
+      std::vector<double> tolb(ns, 0.0);
+      std::vector<int> zi(ns, 0);
+      for (int c = 0; c < nc; ++c) {
+        const int q = cyc[c];
+        vn2[(size_t)c * kArnStride] = beta[q] * beta[q];
+        scl[(size_t)c * kArnStride] = 1.0 / (beta[q] * beta[q]);
+        g[(size_t)c * (m + 1)] = mk<double>(beta[q], 0.0);
+        tolb[c] = gp.tol * normb[q];
+      }
+      GIEM_HIP(hipMemcpyAsync(st.vn2, vn2.data(), vn2.size() * sizeof(double), hipMemcpyHostToDevice, s), "state");
+      GIEM_HIP(hipMemcpyAsync(st.scale, scl.data(), scl.size() * sizeof(double), hipMemcpyHostToDevice, s), "state");
+      GIEM_HIP(hipMemcpyAsync(st.g, g.data(), g.size() * sizeof(c128), hipMemcpyHostToDevice, s), "state");
+      GIEM_HIP(hipMemcpyAsync(st.tolb, tolb.data(), tolb.size() * sizeof(double), hipMemcpyHostToDevice, s), "state");
+      GIEM_HIP(hipMemcpyAsync(st.conv, zi.data(), zi.size() * sizeof(int), hipMemcpyHostToDevice, s), "state");
+      GIEM_HIP(hipMemcpyAsync(st.jlen, zi.data(), zi.size() * sizeof(int), hipMemcpyHostToDevice, s), "state");
+      // the host images must outlive the copies
+      GIEM_HIP(hipStreamSynchronize(s), "sync");
+    }
+    std::vector<int> key = cyc;
+    key.push_back(-L);
+    auto it = gx.exec.find(key);
+    if (it == gx.exec.end()) {
+      // record one cycle: a branch per handle block, forked from s
+      std::vector<bool> prof_was(nblk);
+      for (int k = 0; k < nblk; ++k) {
+        prof_was[k] = sys[hb[k]].t->prof;
+        sys[hb[k]].t->prof = false;
+      }
+      int rc = check_hip(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "begin capture");
+      if (rc == GIEM_OK) rc = check_hip(hipEventRecord(fork_ev, cap), "fork");
+      for (int k = 0; k < nblk && rc == GIEM_OK; ++k) {
+        std::vector<int> cs_;  // cycle positions of this block's systems
+        for (int c = 0; c < nc; ++c)
+          if (blk_of[cyc[c]] == k) cs_.push_back(c);
+        if (cs_.empty()) continue;
+        hipStream_t bs = gx.streams[k];
+        giem_handle *t = sys[hb[k]].t;
+        const size_t n = t->nvec();
+        const int plane = t->nx * t->ny;
+        c128 *part = static_cast<c128 *>(t->red_part);
+        rc = check_hip(hipStreamWaitEvent(bs, fork_ev, 0), "fork wait");
+        for (int j = 0; j < L && rc == GIEM_OK; ++j) {
+          std::vector<int> qs;
+          std::vector<const VT *> in;
+          std::vector<VT *> out;
+          for (int c : cs_) {
+            qs.push_back(cyc[c]);
+            in.push_back(V(cyc[c], j));
+            out.push_back(V(cyc[c], j + 1));
+          }
+          rc = apply_block(k, qs, in, out, bs);
+          const int nb = j + 1;
+          for (size_t i0 = 0; i0 < cs_.size() && rc == GIEM_OK; i0 += kMaxRhs) {
+            const int nq = (int)std::min<size_t>(kMaxRhs, cs_.size() - i0);
+            const int c0 = cs_[i0];  // positions of one block are consecutive
+            DotArgsT<VT> da{};
+            for (int i = 0; i < nq; ++i) {
+              da.w[i] = V(cyc[c0 + i], j + 1);
+              da.basis[i] = V(cyc[c0 + i], 0);
+            }
+            // the projections of a block live in its own region (the
+            // branches of different blocks run at different steps j)
+            const size_t hoff = (size_t)cs_[0] * (m + 2) + i0 * (size_t)(nb + 1);
+            c128 *h1 = st.h1 + hoff, *h2 = st.h2 + hoff;
+            double *sc = st.scale + (size_t)c0 * kArnStride;
+            const double *wl = wlev_of(t);
+            rc = check_hip(launch_dots(da, nq, nb, n, t->nz, plane, wl, part, h1, bs), "dots");
+            if (rc == GIEM_OK)
+              rc = check_hip(launch_update(da, nq, nb, n, t->nz, plane, wl, h1, nb + 1, sc,
+                                           kArnStride, part, st.nrm1 + c0, bs),
+                             "update");
+            if (rc == GIEM_OK)
+              rc = check_hip(launch_gs_gate(nq, h1, nb + 1, st.nrm1 + c0, st.gate + c0,
+                                            kReorthDrop, bs),
+                             "gate");
+            if (rc == GIEM_OK)
+              rc = check_hip(launch_dots(da, nq, nb, n, t->nz, plane, wl, part, h2, bs, st.gate, c0),
+                             "dots (second pass)");
+            if (rc == GIEM_OK)
+              rc = check_hip(launch_update(da, nq, nb, n, t->nz, plane, wl, h2, nb + 1, sc,
+                                           kArnStride, part, st.nrm2 + c0, bs, st.gate, c0),
+                             "update (second pass)");
+            if (rc == GIEM_OK)
+              rc = check_hip(launch_arnoldi_tail(st, h1, h2, c0, nq, j, m, bs), "Arnoldi tail");
+          }
+        }
+        if (rc == GIEM_OK) rc = check_hip(hipEventRecord(gx.events[k], bs), "join");
+        if (rc == GIEM_OK) rc = check_hip(hipStreamWaitEvent(cap, gx.events[k], 0), "join wait");
+      }
+      hipGraph_t graph = nullptr;
+      const int rc_end = check_hip(hipStreamEndCapture(cap, &graph), "end capture");
+      for (int k = 0; k < nblk; ++k) sys[hb[k]].t->prof = prof_was[k];
+      if (rc == GIEM_OK) rc = rc_end;
+      hipGraphExec_t exec = nullptr;
+      if (rc == GIEM_OK)
+        rc = check_hip(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "instantiate graph");
+      if (graph) hipGraphDestroy(graph);
+      if (rc != GIEM_OK) return rc;
+      it = gx.exec.emplace(key, exec).first;
+    }
+    GIEM_HIP(hipGraphLaunch(it->second, s), "launch graph");
+    iters += L;
+    ++res.restarts;
+    // read back the cycle's small state, solve R y = g on the host
+    std::vector<c128> H((size_t)nc * nH), g((size_t)nc * (m + 1));
+    std::vector<double> vn2((size_t)nc * kArnStride);
+    std::vector<int> conv(nc), jlen(nc);
+    GIEM_HIP(hipMemcpyAsync(H.data(), st.H, H.size() * sizeof(c128), hipMemcpyDeviceToHost, s), "read H");
+    GIEM_HIP(hipMemcpyAsync(g.data(), st.g, g.size() * sizeof(c128), hipMemcpyDeviceToHost, s), "read g");
+    GIEM_HIP(hipMemcpyAsync(vn2.data(), st.vn2, vn2.size() * sizeof(double), hipMemcpyDeviceToHost, s), "read norms");
+    GIEM_HIP(hipMemcpyAsync(conv.data(), st.conv, nc * sizeof(int), hipMemcpyDeviceToHost, s), "read flags");
+    GIEM_HIP(hipMemcpyAsync(jlen.data(), st.jlen, nc * sizeof(int), hipMemcpyDeviceToHost, s), "read lengths");
+    GIEM_HIP(hipStreamSynchronize(s), "sync");
+    std::vector<c128> yall((size_t)nc * 64, mk<double>(0, 0));
+    std::vector<int> klen(nc, 0);
+    for (int c = 0; c < nc; ++c) {
+      int k = conv[c] ? jlen[c] : L;
+      const c128 *Hc = H.data() + (size_t)c * nH;
+      const c128 *gc = g.data() + (size_t)c * (m + 1);
+      for (int i = 0; i < k; ++i)
+        if (Hc[(size_t)i * m + i].x == 0.0 && Hc[(size_t)i * m + i].y == 0.0) {
+          k = i;
+          break;
+        }
+      std::vector<cd> y(k);
+      for (int i = k - 1; i >= 0; --i) {
+        cd acc(gc[i].x, gc[i].y);
+        for (int l = i + 1; l < k; ++l)
+          acc -= cd(Hc[(size_t)i * m + l].x, Hc[(size_t)i * m + l].y) * y[l];
+        y[i] = acc / cd(Hc[(size_t)i * m + i].x, Hc[(size_t)i * m + i].y);
+      }
+      for (int i = 0; i < k; ++i) {
+        const cd yi = y[i] / std::sqrt(vn2[(size_t)c * kArnStride + i]);
+        yall[(size_t)c * 64 + i] = mk<double>(yi.real(), yi.imag());
+      }
+      klen[c] = k;
+    }
+    c128 *ydev = static_cast<c128 *>(sys[0].t->coef_dev);  // [kMaxSys][65]
+    GIEM_HIP(hipMemcpyAsync(ydev, yall.data(), (size_t)nc * 64 * sizeof(c128), hipMemcpyHostToDevice, s),
+             "copy y");
+    for (int c = 0; c < nc; ++c) {
+      if (klen[c] == 0) continue;
+      const int q = cyc[c];
+      LinArgsT<VT> la{};
+      la.x[0] = sys[q].x;
+      la.basis[0] = V(q, 0);
+      GIEM_HIP(launch_lincomb(la, 1, klen[c], sys[q].t->nvec(), ydev + (size_t)c * 64, 64, s), "lincomb");
+    }
+    GIEM_HIP(hipStreamSynchronize(s), "sync");
+    if (iters >= gp.max_iter) {
+      // final true residual for the report
+      for (int k = 0; k < nblk; ++k) {
+        std::vector<int> qs;
+        for (int q = hb[k]; q < hb[k + 1]; ++q)
+          if (!done[q]) qs.push_back(q);
+        if (qs.empty()) continue;
+        std::vector<const VT *> in;
+        std::vector<VT *> out;
+        for (int q : qs) {
+          in.push_back(sys[q].x);
+          out.push_back(V(q, 0));
+        }
+        GIEM_TRY(apply_block(k, qs, in, out, s));
+        std::vector<const VT *> rp;
+        for (int q : qs) {
+          GIEM_HIP(launch_axpby(V(q, 0), sys[q].b, V(q, 0), mk<double>(1, 0), mk<double>(-1, 0),
+                                sys[q].t->nvec(), s),
+                   "axpby");
+          rp.push_back(V(q, 0));
+        }
+        std::vector<double> rn;
+        GIEM_TRY(norms_of(sys[qs[0]].t, rp.data(), (int)qs.size(), wlev_of(sys[qs[0]].t), s, rn));
+        for (size_t i = 0; i < qs.size(); ++i) {
+          res.relres[qs[i]] = rn[i] / normb[qs[i]];
+          if (rn[i] <= gp.tol * normb[qs[i]]) done[qs[i]] = 1;
+        }
+      }
+      break;
+    }
+  }
+  res.iters = iters;
+  res.converged = true;
+  for (int q = 0; q < ns; ++q)
+    if (!done[q]) res.converged = false;
+  return GIEM_OK;
+}
+
 // ------------------------------------------------------------ solve entry
 static int check_sigma_a(giem_handle *t, const void *sigma_a, hipStream_t s) {
   std::vector<c128> h(t->ncell());
@@ -531,6 +949,42 @@ static int check_sigma_a(giem_handle *t, const void *sigma_a, hipStream_t s) {
   }
   return GIEM_OK;
 }
+
+// b of every system (f, r) into bv [nf][nrhs][n]: the caller's rhs[f], or the
+// plane-wave source U^0 = sqrt(Re sigma_b) <E^N> (x then y polarisation)
+static int prepare_rhs(giem_handle *t, int nf, const int *ifreqs, int nrhs,
+                       const void *const *rhs, c128 *bv, hipStream_t s) {
+  const size_t n = t->nvec();
+  for (int f = 0; f < nf; ++f) {
+    c128 *bf = bv + (size_t)f * nrhs * n;
+    if (rhs && rhs[f]) {
+      GIEM_HIP(hipMemcpyAsync(bf, rhs[f], (size_t)nrhs * n * sizeof(c128), hipMemcpyDeviceToDevice, s),
+               "copy rhs");
+    } else {
+      std::vector<cd> en, hs;
+      plane_wave_levels(t, t->f[ifreqs[f]].freq, en, hs);
+      std::vector<c128> enc(t->nz);
+      for (int k = 0; k < t->nz; ++k) enc[k] = mk<double>(en[k].real(), en[k].imag());
+      // stage per-level E^N in the small coefficient buffer
+      if ((size_t)t->nz > (size_t)kMaxSys * 65) {
+        set_error("Nz too large");
+        return GIEM_EINVAL;
+      }
+      GIEM_HIP(hipMemcpyAsync(t->coef_dev, enc.data(), t->nz * sizeof(c128), hipMemcpyHostToDevice, s),
+               "copy EN");
+      for (int r = 0; r < nrhs; ++r)
+        GIEM_HIP(launch_plane_wave_rhs(static_cast<c128 *>(t->coef_dev),
+                                       static_cast<double *>(t->sroot_lev), t->nx, t->ny, t->nz, r,
+                                       bf + (size_t)r * n, s),
+                 "plane wave");
+      GIEM_HIP(hipStreamSynchronize(s), "sync");
+    }
+  }
+  return GIEM_OK;
+}
+
+static int solve_groups_impl(int ng, const giem_solve_group *gr, int nrhs,
+                             const giem_solve_opts *o, giem_solve_stats *st, hipStream_t s);
 
 // Solve for nf frequencies of the handle at once (nf = 1 for giem_solve).
 // System (f, r) = frequency ifreqs[f], right-hand side r; all systems share
@@ -570,6 +1024,10 @@ static int solve_batch_impl(giem_handle *t, int nf, const int *ifreqs, const voi
     set_error("giem_solve: bad options (tol > 0, 1 <= restart <= 64, max_iter >= 1)");
     return GIEM_EINVAL;
   }
+  if (o->graph && mode == MODE_A) {
+    const giem_solve_group G{t, nf, ifreqs, sigma_a, rhs, E_cells};
+    return solve_groups_impl(1, &G, nrhs, o, st, s);
+  }
   GIEM_TRY(check_sigma_a(t, sigma_a, s));
   GIEM_TRY(compute_diagonals(t, static_cast<const c128 *>(sigma_a), s));
   const size_t n = t->nvec(), nc = t->ncell();
@@ -580,31 +1038,7 @@ static int solve_batch_impl(giem_handle *t, int nf, const int *ifreqs, const voi
   c128 *bv = ws, *uv = ws + (size_t)ns * n, *dv = ws + (size_t)2 * ns * n;
   c128 *cv = ws + (size_t)3 * ns * n;
   const c128 *acell = static_cast<const c128 *>(t->diag) + 3 * nc;
-  for (int f = 0; f < nf; ++f) {
-    c128 *bf = bv + (size_t)f * nrhs * n;
-    if (rhs && rhs[f]) {
-      GIEM_HIP(hipMemcpyAsync(bf, rhs[f], (size_t)nrhs * n * sizeof(c128), hipMemcpyDeviceToDevice, s),
-               "copy rhs");
-    } else {
-      std::vector<cd> en, hs;
-      plane_wave_levels(t, t->f[ifreqs[f]].freq, en, hs);
-      std::vector<c128> enc(t->nz);
-      for (int k = 0; k < t->nz; ++k) enc[k] = mk<double>(en[k].real(), en[k].imag());
-      // stage per-level E^N in the small coefficient buffer
-      if ((size_t)t->nz > (size_t)kMaxSys * 65) {
-        set_error("Nz too large");
-        return GIEM_EINVAL;
-      }
-      GIEM_HIP(hipMemcpyAsync(t->coef_dev, enc.data(), t->nz * sizeof(c128), hipMemcpyHostToDevice, s),
-               "copy EN");
-      for (int r = 0; r < nrhs; ++r)
-        GIEM_HIP(launch_plane_wave_rhs(static_cast<c128 *>(t->coef_dev),
-                                       static_cast<double *>(t->sroot_lev), t->nx, t->ny, t->nz, r,
-                                       bf + (size_t)r * n, s),
-                 "plane wave");
-      GIEM_HIP(hipStreamSynchronize(s), "sync");
-    }
-  }
+  GIEM_TRY(prepare_rhs(t, nf, ifreqs, nrhs, rhs, bv, s));
   const bool warm = o->warm_start != 0;
   if (warm)
     for (int f = 0; f < nf; ++f)
@@ -730,6 +1164,222 @@ static int solve_batch_impl(giem_handle *t, int nf, const int *ifreqs, const voi
   return rc;
 }
 
+// Solve the systems of several handles (models) and frequencies together
+// with graph-captured GMRES cycles (gmres_graph).  Group g is handle t_g at
+// frequencies ifreqs_g with its own sigma_a; system (g, f, r).  Outputs and
+// stats as solve_batch_impl, stats ordered group by group.
+static int solve_groups_impl(int ng, const giem_solve_group *gr, int nrhs,
+                             const giem_solve_opts *o, giem_solve_stats *st, hipStream_t s) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (ng < 1 || !gr || nrhs < 1 || nrhs > kMaxRhs || !o) {
+    set_error("giem_solve_multi: bad argument");
+    return GIEM_EINVAL;
+  }
+  if (!(o->tol > 0) || o->restart < 1 || o->restart > 64 || o->max_iter < 1 ||
+      (o->precision != PREC_FP64 && o->precision != PREC_FP32)) {
+    set_error("giem_solve_multi: bad options (tol > 0, 1 <= restart <= 64, max_iter >= 1)");
+    return GIEM_EINVAL;
+  }
+  int total = 0;
+  for (int g = 0; g < ng; ++g) {
+    const giem_solve_group &G = gr[g];
+    if (!G.t || G.nf < 1 || !G.ifreqs || !G.sigma_a || !G.E_cells) {
+      set_error("giem_solve_multi: bad group");
+      return GIEM_EINVAL;
+    }
+    for (int h = 0; h < g; ++h)
+      if (gr[h].t == G.t) {
+        set_error("giem_solve_multi: a handle may appear in one group only");
+        return GIEM_EINVAL;
+      }
+    if (G.t->device != gr[0].t->device) {
+      set_error("giem_solve_multi: every handle must live on the same device");
+      return GIEM_EINVAL;
+    }
+    for (int f = 0; f < G.nf; ++f) {
+      if (G.ifreqs[f] < 0 || G.ifreqs[f] >= (int)G.t->f.size() || !G.E_cells[f]) {
+        set_error("giem_solve_multi: bad frequency index or output");
+        return GIEM_EINVAL;
+      }
+      if (!(G.rhs && G.rhs[f]) && nrhs > 2) {
+        set_error("giem_solve_multi: the plane-wave source has two polarisations (nrhs <= 2)");
+        return GIEM_EINVAL;
+      }
+      if (o->precision == PREC_FP32 && !G.t->f[G.ifreqs[f]].spec32) {
+        set_error("giem_solve_multi: the FP32 form needs tables built with GIEM_TABLES_C64");
+        return GIEM_EINVAL;
+      }
+    }
+    total += G.nf * nrhs;
+  }
+  if (total > kMaxSys) {
+    set_error("giem_solve_multi: more than " + std::to_string(kMaxSys) + " systems");
+    return GIEM_EINVAL;
+  }
+  const bool warm = o->warm_start != 0;
+  // per group: diagonals, b, u; systems in group-major order
+  std::vector<GSys<c128>> sys;
+  std::vector<c128 *> dres, corr;  // FP64 residual and complex64 scratch per system
+  for (int g = 0; g < ng; ++g) {
+    const giem_solve_group &G = gr[g];
+    giem_handle *t = G.t;
+    GIEM_TRY(check_sigma_a(t, G.sigma_a, s));
+    GIEM_TRY(compute_diagonals(t, static_cast<const c128 *>(G.sigma_a), s));
+    const size_t n = t->nvec(), nc = t->ncell();
+    const int nsg = G.nf * nrhs;
+    GIEM_TRY(ensure_vec_ws(t, (size_t)4 * nsg));
+    c128 *ws = static_cast<c128 *>(t->vec_ws);
+    c128 *bv = ws, *uv = ws + (size_t)nsg * n;
+    std::vector<int> fi(G.ifreqs, G.ifreqs + G.nf);
+    GIEM_TRY(prepare_rhs(t, G.nf, fi.data(), nrhs, G.rhs, bv, s));
+    const c128 *acell = static_cast<const c128 *>(t->diag) + 3 * nc;
+    if (warm)
+      for (int f = 0; f < G.nf; ++f)
+        GIEM_HIP(launch_mul_cells(uv + (size_t)f * nrhs * n, static_cast<const c128 *>(G.E_cells[f]),
+                                  acell, nrhs, nc, s),
+                 "U = a E");
+    for (int q = 0; q < nsg; ++q) {
+      sys.push_back(GSys<c128>{t, G.ifreqs[q / nrhs], bv + (size_t)q * n, uv + (size_t)q * n});
+      dres.push_back(ws + (size_t)(2 * nsg + q) * n);
+      corr.push_back(ws + (size_t)(3 * nsg + q) * n);
+    }
+  }
+  const int ns = (int)sys.size();
+  GmresParams gp;
+  gp.tol = o->tol;
+  gp.m = o->restart;
+  gp.max_iter = o->max_iter;
+  gp.weighted = o->weighted_ip;
+  gp.mode = MODE_A;
+  int iters_total = 0, outer_total = 0;
+  std::vector<double> relres(ns, 0.0);
+  std::vector<char> sys_conv(ns, 0);
+  if (o->precision == PREC_FP64) {
+    gp.prec = PREC_FP64;
+    gp.x_zero = !warm;
+    GmresResult res;
+    GIEM_TRY(gmres_graph(sys, gp, s, res));
+    iters_total = res.iters;
+    outer_total = res.restarts;
+    for (int q = 0; q < ns; ++q) {
+      relres[q] = res.relres[q];
+      sys_conv[q] = res.relres[q] <= o->tol;
+    }
+  } else {
+    // refinement: r = b - A64 u (FP64, eager), inner graph GMRES in complex64
+    std::vector<double> normb(ns), rn(ns);
+    auto norms_all = [&](const std::vector<const c128 *> &v, std::vector<double> &out) -> int {
+      for (int q0 = 0; q0 < ns;) {
+        int q1 = q0;
+        while (q1 < ns && sys[q1].t == sys[q0].t) ++q1;
+        std::vector<double> part;
+        const double *wl = o->weighted_ip ? static_cast<const double *>(sys[q0].t->vol_lev) : nullptr;
+        GIEM_TRY(norms_of(sys[q0].t, v.data() + q0, q1 - q0, wl, s, part));
+        for (int q = q0; q < q1; ++q) out[q] = part[q - q0];
+        q0 = q1;
+      }
+      return GIEM_OK;
+    };
+    {
+      std::vector<const c128 *> bp;
+      for (auto &x : sys) bp.push_back(x.b);
+      GIEM_TRY(norms_all(bp, normb));
+    }
+    if (!warm)
+      for (auto &x : sys) GIEM_HIP(hipMemsetAsync(x.x, 0, x.t->nvec() * sizeof(c128), s), "zero");
+    const int max_outer = o->max_outer > 0 ? o->max_outer : 20;
+    const double itol = o->inner_tol > 0 ? o->inner_tol : 1e-3;
+    int outer = 0, inner_total = 0;
+    for (outer = 0; outer <= max_outer; ++outer) {
+      for (int q0 = 0; q0 < ns;) {
+        int q1 = q0;
+        while (q1 < ns && sys[q1].t == sys[q0].t) ++q1;
+        std::vector<int> fq, loc;
+        std::vector<const c128 *> in;
+        std::vector<c128 *> out;
+        for (int q = q0; q < q1; ++q) {
+          fq.push_back(sys[q].fq);
+          loc.push_back(q - q0);
+          in.push_back(sys[q].x);
+          out.push_back(dres[q]);
+        }
+        GIEM_TRY(apply_sys(sys[q0].t, fq, loc, in, out, MODE_A, PREC_FP64, s));
+        for (int q = q0; q < q1; ++q)
+          GIEM_HIP(launch_axpby(dres[q], sys[q].b, dres[q], mk<double>(1, 0), mk<double>(-1, 0),
+                                sys[q].t->nvec(), s),
+                   "axpby");
+        q0 = q1;
+      }
+      {
+        std::vector<const c128 *> dp(dres.begin(), dres.end());
+        GIEM_TRY(norms_all(dp, rn));
+      }
+      std::vector<int> act;
+      for (int q = 0; q < ns; ++q) {
+        relres[q] = normb[q] > 0 ? rn[q] / normb[q] : 0.0;
+        sys_conv[q] = relres[q] <= o->tol;
+        if (!sys_conv[q]) act.push_back(q);
+      }
+      if (act.empty() || outer == max_outer || inner_total >= o->max_iter) break;
+      std::vector<GSys<c64>> isys;
+      for (int q : act) {
+        c64 *r32 = reinterpret_cast<c64 *>(corr[q]);
+        c64 *dst[1] = {r32};
+        const c128 *src[1] = {dres[q]};
+        const c128 one = mk<double>(1, 0);
+        GIEM_HIP(launch_scale(dst, src, &one, 1, sys[q].t->nvec(), s), "r -> complex64");
+        isys.push_back(GSys<c64>{sys[q].t, sys[q].fq, r32, r32 + sys[q].t->nvec()});
+      }
+      GmresParams ip = gp;
+      ip.prec = PREC_FP32;
+      ip.tol = itol;
+      ip.x_zero = true;
+      ip.max_iter = std::max(1, o->max_iter - inner_total);
+      GmresResult res;
+      GIEM_TRY(gmres_graph(isys, ip, s, res));
+      inner_total += res.iters;
+      for (size_t k = 0; k < act.size(); ++k)
+        GIEM_HIP(launch_axpby(sys[act[k]].x, sys[act[k]].x, isys[k].x, mk<double>(1, 0),
+                              mk<double>(1, 0), sys[act[k]].t->nvec(), s),
+                 "u += d");
+    }
+    iters_total = inner_total;
+    outer_total = outer;
+  }
+  // E = U / a, stats per (group, frequency)
+  for (int g = 0, q = 0; g < ng; ++g) {
+    const giem_solve_group &G = gr[g];
+    const size_t nc = G.t->ncell();
+    const c128 *acell = static_cast<const c128 *>(G.t->diag) + 3 * nc;
+    for (int f = 0; f < G.nf; ++f, q += nrhs)
+      GIEM_HIP(launch_div_cells(static_cast<c128 *>(G.E_cells[f]), sys[q].x, acell, nrhs, nc, s),
+               "E = U / a");
+  }
+  GIEM_HIP(hipStreamSynchronize(s), "sync");
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  bool all_conv = true;
+  for (int g = 0, q = 0, k = 0; g < ng; ++g)
+    for (int f = 0; f < gr[g].nf; ++f, ++k) {
+      giem_solve_stats lst{};
+      lst.iters = iters_total;
+      lst.outer_iters = outer_total;
+      lst.converged = 1;
+      lst.rel_residual = 0.0;
+      lst.ms = ms;
+      for (int r = 0; r < nrhs; ++r, ++q) {
+        lst.rel_residual = std::max(lst.rel_residual, relres[q]);
+        if (!sys_conv[q]) lst.converged = 0;
+      }
+      if (!lst.converged) all_conv = false;
+      if (st) st[k] = lst;
+    }
+  if (!all_conv) {
+    set_error("GMRES reached the iteration limit before the tolerance");
+    return GIEM_ENOCONV;
+  }
+  return GIEM_OK;
+}
+
 static int solve_impl(giem_handle *t, int ifreq, const void *sigma_a, int nrhs, const void *rhs,
                       void *E_cells, const giem_solve_opts *o, giem_solve_stats *st,
                       hipStream_t s, unsigned mode) {
@@ -825,6 +1475,11 @@ int giem_solve_batch(giem_handle *t, int32_t nf, const int32_t *ifreqs, const vo
   std::vector<int> fi(ifreqs, ifreqs + nf);
   return solve_batch_impl(t, nf, fi.data(), sigma_a, nrhs, rhs, E_cells, opts, stats,
                           static_cast<hipStream_t>(stream), MODE_A);
+}
+
+int giem_solve_multi(int32_t ngroups, const giem_solve_group *groups, int32_t nrhs,
+                     const giem_solve_opts *opts, giem_solve_stats *stats, void *stream) {
+  return solve_groups_impl(ngroups, groups, nrhs, opts, stats, static_cast<hipStream_t>(stream));
 }
 
 int giem_adjoint(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,

@@ -3,10 +3,9 @@
     points): the FP64 apply at sampled cells against the oracle's direct sum
     on the exported table, and the precision form (complex64 operator and
     Krylov basis, FP64 refinement) against an FP64 solve at 1e-12;
-  - three models of uneven size, 64 x 64 x 16, 96 x 96 x 24 (padded length
-    192 needs a radix-3 pass) and 128 x 128 x 32, each at twelve frequencies
-    1e-3 .. 10 Hz: the precision form against the FP64 solve at every
-    frequency.
+  - the lockstep solver of several frequencies of one model against the
+    oracle and against separate solves (the three-model, twelve-frequency
+    set is in test_gpu_graph.py).
 The precision form runs to 1e-9 so that its error, not the tolerance of the
 comparison, is measured; the bar is 1e-6 relative per polarisation."""
 import time
@@ -65,28 +64,6 @@ def test_precision_256(lib):
           f"{s64['ms']:.0f} ms, FP32-refined {s32['iters']} inner / {s32['outer_iters']} outer "
           f"{s32['ms']:.0f} ms", flush=True)
     assert max(errs) <= 1e-6
-
-
-@pytest.mark.parametrize("which", [0, 1, 2])
-def test_batched_models_and_frequencies(lib, which):
-    models, freqs = gs.config_batched()
-    m = models[which]
-    nx, ny, nz = m["nx"], m["ny"], m["nz"]
-    t0 = time.perf_counter()
-    h = lib.tables(m, freqs, flags=lib.TABLES_C64)
-    sa = to_dev(m["sigma_a"])
-    h.tune(sa)
-    print(f"{nx}x{ny}x{nz}: tables for {len(freqs)} frequencies + tuning "
-          f"{time.perf_counter() - t0:.1f} s", flush=True)
-    worst = 0.0
-    for q in range(len(freqs)):
-        errs, s64, s32 = _pair(lib, h, sa, (3, nz, ny, nx), q)
-        worst = max(worst, max(errs))
-        print(f"  f = {freqs[q]:.4g} Hz: err {max(errs):.2e}, FP64 {s64['iters']} it "
-              f"{s64['ms']:.0f} ms, FP32-refined {s32['iters']} it {s32['ms']:.0f} ms", flush=True)
-        assert max(errs) <= 1e-6, (freqs[q], errs)
-    h.close()
-    print(f"  worst {worst:.2e}", flush=True)
 
 
 def test_batched_solve_matches_oracle(lib):
