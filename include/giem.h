@@ -163,6 +163,24 @@ int giem_apply(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
                const void *x, void *y, uint32_t mode, uint32_t prec, void *stream);
 
 /*
+ * giem_apply_noalloc -- giem_apply for callers that cannot allocate device
+ * memory during the call (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, kernels and results as
+ * giem_apply; the two spectra buffers of the three steps live in a fixed
+ * 64 MiB device array of the library instead of the handle's workspace, so
+ * the call makes no hipMalloc, hipFree or other allocation (the handle and its
+ * tables come from giem_tables as before).  Limit: 2 x 4 Nx Ny x 3 Nz x nrhs
+ * complex (16 bytes in GIEM_FP64, 8 in GIEM_FP32) must fit in 64 MiB, e.g.
+ * 64 x 64 x 16 with 2 right-hand sides in FP64; larger calls return EINVAL
+ * before any kernel runs.  The array is one per device and shared by every
+ * call on it, so calls that overlap in time on one device race (issue them on
+ * one stream, or serialise them).  The handle's device must be current.
+ * Never synchronises the stream.  Errors: EINVAL, EDOMAIN, EHIP.
+ */
+int giem_apply_noalloc(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
+                       const void *x, void *y, uint32_t mode, uint32_t prec, void *stream);
+
+/*
  * giem_apply_batch -- giem_apply for several frequencies of the handle at
  * once, one launch per kernel for all of them: y[f][r] = op_{ifreqs[f]}
  * x[f][r].  The frequencies share sigma_a (the diagonal scalings of

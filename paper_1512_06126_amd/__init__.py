@@ -82,6 +82,7 @@ def load():
         "giem_tables_export": [P, I32, P],
         "giem_tables_bytes": [P, P, P],
         "giem_apply": [P, I32, P, I32, P, P, U32, U32, P],
+        "giem_apply_noalloc": [P, I32, P, I32, P, P, U32, U32, P],
         "giem_apply_timed": [P, I32, P, I32, P, P, U32, U32, P, P],
         "giem_apply_batch": [P, I32, P, P, I32, P, P, U32, U32, P],
         "giem_solve": [P, I32, P, I32, P, P, P, P, P],
@@ -112,7 +113,7 @@ def load():
 
 def exported_symbols():
     return ["giem_tables", "giem_tables_import", "giem_tables_export", "giem_tables_bytes",
-            "giem_apply", "giem_apply_timed", "giem_apply_batch", "giem_tune", "giem_set_fft_shape", "giem_set_block_buffers", "giem_profile", "giem_profile_read", "giem_solve", "giem_solve_batch", "giem_solve_multi",
+            "giem_apply", "giem_apply_noalloc", "giem_apply_timed", "giem_apply_batch", "giem_tune", "giem_set_fft_shape", "giem_set_block_buffers", "giem_profile", "giem_profile_read", "giem_solve", "giem_solve_batch", "giem_solve_multi",
             "giem_adjoint", "giem_fields", "giem_fields_adjoint", "giem_impedance",
             "giem_impedance_adjoint", "giem_free", "giem_last_error"]
 
@@ -185,6 +186,15 @@ class Handle:
         sa = _ptr(sigma_a) if sigma_a is not None else ctypes.c_void_p(0)
         _check(_lib.giem_apply(self._p, ifreq, sa, nrhs, _ptr(x), _ptr(y), mode, prec,
                                _stream(stream)))
+        return y
+
+    def apply_noalloc(self, x, y, sigma_a=None, mode=MODE_A, prec=FP64, ifreq=0, stream=None):
+        """giem_apply_noalloc: the same apply with its spectra in the library's
+        fixed device array (no allocation during the call)."""
+        nrhs = x.shape[0]
+        sa = _ptr(sigma_a) if sigma_a is not None else ctypes.c_void_p(0)
+        _check(_lib.giem_apply_noalloc(self._p, ifreq, sa, nrhs, _ptr(x), _ptr(y), mode, prec,
+                                       _stream(stream)))
         return y
 
     def apply_batch(self, x, y, sigma_a=None, ifreqs=None, mode=MODE_A, prec=FP64, stream=None):

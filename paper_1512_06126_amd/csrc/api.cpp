@@ -77,6 +77,35 @@ static int make_cs(int n, void **out) {
   return GIEM_OK;
 }
 
+// Spectra workspace of giem_apply_noalloc: a fixed device array that every
+// call on a device shares (the device holds it until the process ends).  In
+// host code `scratch` is only a host-side stand-in for the symbol; its device
+// address is looked up once per device (init_scratch, from the library's
+// init call) and only that address is passed to kernels.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static void *g_scratch_dev[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+static int init_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) {
+    set_error("device index out of range for the no-allocation workspace");
+    return GIEM_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[device]) return GIEM_OK;
+  void *ptr = nullptr;
+  GIEM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+  g_scratch_dev[device] = ptr;
+  return GIEM_OK;
+}
+
+static size_t spec_ws_need(const giem_handle *t, int nvec, unsigned prec) {
+  const size_t c = prec == PREC_FP32 ? sizeof(c64) : sizeof(c128);
+  return (size_t)2 * 4 * t->nx * t->ny * 3 * t->nz * nvec * c;
+}
+
 int ensure_spec_ws(giem_handle *t, int nrhs, int prec) {
   (void)prec;
   // two spectra buffers: the block product reads one and writes the other
@@ -124,10 +153,12 @@ static void fft_shape(const giem_handle *t, unsigned prec, int G[4], int NT[4]) 
   }
 }
 
+// ws: spectra workspace of at least spec_ws_need() bytes supplied by the
+// caller, or null for the handle's own (grown here when too small).
 template <typename VT>
 static int apply_core_t(giem_handle *t, int nf, const int *ifreqs, int nrhs,
                         const VecPtrsT<VT> &p, unsigned mode, unsigned prec, hipStream_t s,
-                        double *stage_ms) {
+                        double *stage_ms, void *ws = nullptr) {
   const int nx = t->nx, ny = t->ny, nz = t->nz;
   if (nf < 1 || nf > kMaxFreqBatch || nrhs < 1 || nrhs > kMaxRhs || nf * nrhs > kMaxVec) {
     set_error("apply: too many frequencies or vectors in one batched apply");
@@ -147,7 +178,7 @@ static int apply_core_t(giem_handle *t, int nf, const int *ifreqs, int nrhs,
     }
   }
   const int nv = nf * nrhs;  // vectors of this apply, frequency-major
-  GIEM_TRY(ensure_spec_ws(t, nv, prec));
+  if (!ws) GIEM_TRY(ensure_spec_ws(t, nv, prec));
   const c128 *dg = static_cast<const c128 *>(t->diag);
   const size_t n = t->ncell();
   const c128 *S = dg, *R1 = dg + n, *R2 = dg + 2 * n;
@@ -175,7 +206,7 @@ static int apply_core_t(giem_handle *t, int nf, const int *ifreqs, int nrhs,
   if (stage_ms) {
     for (int i = 0; i < 6; ++i) GIEM_HIP(hipEventCreate(&own[i]), "hipEventCreate");
     ev = own;
-  } else if (t->prof) {
+  } else if (t->prof && !ws) {
     const size_t need = t->prof_stage < 0 ? 6 : 2;
     while (t->prof_ev.size() < t->prof_used + need) {
       // timing only: no system-scope fence (a full L2 write-back) when the
@@ -202,8 +233,8 @@ static int apply_core_t(giem_handle *t, int nf, const int *ifreqs, int nrhs,
     return GIEM_OK;
   };
   const size_t cbytes = prec == PREC_FP32 ? sizeof(c64) : sizeof(c128);
-  void *spa = t->spec_ws;
-  void *spb = static_cast<char *>(t->spec_ws) + (size_t)4 * nx * ny * rp * cbytes;
+  void *spa = ws ? ws : t->spec_ws;
+  void *spb = static_cast<char *>(spa) + (size_t)4 * nx * ny * rp * cbytes;
   GIEM_TRY(mark(0));
   GIEM_HIP(launch_fft_x_fwd(prec, p, r2, spa, nx, ny, nz, rp, G[0], NT[0], t->px.d, twx, s),
            "x-FFT");
@@ -357,6 +388,13 @@ static int create_handle(const giem_model *m, int nfreq, const double *freq, uin
   for (int k = 0; k <= m->nlay; ++k) t->sigma.emplace_back(m->sigma_b[2 * k], m->sigma_b[2 * k + 1]);
   t->flags = flags;
   hipGetDevice(&t->device);
+  {
+    const int rc = init_scratch(t->device);
+    if (rc != GIEM_OK) {
+      delete t;
+      return rc;
+    }
+  }
   // layer of every cell; no cell may straddle an interface
   for (int k = 0; k < t->nz; ++k) {
     const double a = t->z_edges[k], b = t->z_edges[k + 1];
@@ -594,6 +632,41 @@ static int apply_entry(giem_handle *t, int32_t ifreq, const void *sigma_a, int32
 int giem_apply(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs, const void *x,
                void *y, uint32_t mode, uint32_t prec, void *stream) {
   return apply_entry(t, ifreq, sigma_a, nrhs, x, y, mode, prec, stream, nullptr);
+}
+
+int giem_apply_noalloc(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
+                       const void *x, void *y, uint32_t mode, uint32_t prec, void *stream) {
+  if (!t || ifreq < 0 || ifreq >= (int)t->f.size() || nrhs < 1 || nrhs > kMaxRhs || !x || !y ||
+      mode > MODE_B || prec > PREC_FP32 || (mode != MODE_B && !sigma_a)) {
+    set_error("giem_apply_noalloc: bad argument");
+    return GIEM_EINVAL;
+  }
+  const size_t need = spec_ws_need(t, nrhs, prec);
+  if (need > kScratchBytes) {
+    set_error("giem_apply_noalloc: spectra of " + std::to_string(need) +
+              " bytes exceed the fixed workspace of " + std::to_string(kScratchBytes) + " bytes");
+    return GIEM_EINVAL;
+  }
+  int dev = -1;
+  GIEM_HIP(hipGetDevice(&dev), "hipGetDevice");
+  if (dev != t->device || !g_scratch_dev[dev]) {
+    set_error("giem_apply_noalloc: the handle's device must be current");
+    return GIEM_EINVAL;
+  }
+  const size_t nbytes = (size_t)nrhs * t->nvec() * sizeof(c128);
+  const char *xa = static_cast<const char *>(x), *ya = static_cast<const char *>(y);
+  if (xa < ya + nbytes && ya < xa + nbytes) {
+    set_error("giem_apply_noalloc: x and y overlap");
+    return GIEM_EINVAL;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (mode != MODE_B) GIEM_TRY(compute_diagonals(t, static_cast<const c128 *>(sigma_a), s));
+  VecPtrs p{};
+  for (int r = 0; r < nrhs; ++r) {
+    p.in[r] = static_cast<const c128 *>(x) + r * t->nvec();
+    p.out[r] = static_cast<c128 *>(y) + r * t->nvec();
+  }
+  return apply_core_t(t, 1, &ifreq, nrhs, p, mode, prec, s, nullptr, g_scratch_dev[dev]);
 }
 
 int giem_apply_batch(giem_handle *t, int32_t nf, const int32_t *ifreqs, const void *sigma_a,
