@@ -92,7 +92,9 @@ typedef struct {
   int32_t restart;     /* Krylov dimension m of GMRES(m), 1..64               */
   int32_t max_iter;    /* limit on operator applies of the (inner) GMRES      */
   int32_t precision;   /* GIEM_FP64 or GIEM_FP32                              */
-  double inner_tol;    /* GIEM_FP32: relative tolerance of each inner solve    */
+  double inner_tol;    /* GIEM_FP32: relative tolerance of each inner solve
+                          (default 1e-3); looser where a looser one already
+                          meets tol (the last refinement step)            */
   int32_t max_outer;   /* GIEM_FP32: limit on refinement steps                */
   int32_t weighted_ip; /* nonzero: volume-weighted L2 inner product (Sect. 2.1) */
   int32_t warm_start;  /* nonzero: E_cells holds the initial guess on entry    */
@@ -101,12 +103,22 @@ typedef struct {
                           wait per cycle); giem_solve_multi always does      */
 } giem_solve_opts;
 
+#define GIEM_HISTORY 64
 typedef struct {
   int32_t iters;       /* operator applies in GMRES (all RHS, max over RHS)    */
   int32_t outer_iters; /* refinement steps (GIEM_FP32), else restarts          */
   int32_t converged;   /* 1 if every RHS met tol                              */
   double rel_residual; /* max over RHS of the final true ||b - A x|| / ||b||   */
   double ms;           /* wall time of the call, ms                           */
+  int32_t n_history;   /* entries of history                                  */
+  double history[GIEM_HISTORY];
+                       /* the true ||b - A x|| / ||b|| (max over the RHS, one
+                          that stopped earlier counting with its final
+                          value) at the start of every restart cycle
+                          (GIEM_FP64) or after every refinement step
+                          (GIEM_FP32), the last entry being the final one;
+                          with more than GIEM_HISTORY entries the first
+                          GIEM_HISTORY - 1 and the last are kept              */
 } giem_solve_stats;
 
 /*
@@ -244,7 +256,8 @@ int giem_tune(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs, 
    of the same grid.  shape: host int32 [4][2], (sequences per workgroup,
    threads per workgroup) for x forward, y forward, y inverse, x inverse;
    threads must be 256 or 512 and the pass must fit the local data share and
-   at most 16 elements per thread.  NULL restores the built-in choice.
+   at most 16 elements per thread.  NULL restores the built-in choice.  Every
+   shape gives the same result bits.
    Errors: EINVAL (nothing is changed). */
 int giem_set_fft_shape(giem_handle *t, uint32_t prec, const int32_t *shape);
 

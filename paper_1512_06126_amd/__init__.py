@@ -54,13 +54,19 @@ class SolveGroup(ctypes.Structure):
                 ("E_cells", ctypes.c_void_p)]
 
 
+HISTORY = 64
+
+
 class SolveStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("outer_iters", ctypes.c_int32),
                 ("converged", ctypes.c_int32), ("rel_residual", ctypes.c_double),
-                ("ms", ctypes.c_double)]
+                ("ms", ctypes.c_double), ("n_history", ctypes.c_int32),
+                ("history", ctypes.c_double * HISTORY)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("n_history", "history")}
+        d["history"] = [self.history[i] for i in range(self.n_history)]
+        return d
 
 
 def load():

@@ -20,6 +20,11 @@ const std::string &get_error() { return g_last_error; }
 
 int check_hip(hipError_t e, const char *what) {
   if (e == hipSuccess) return GIEM_OK;
+  // the error is reported through the return code: take it out of the
+  // runtime's last-error slot, or the next launch check (hipGetLastError
+  // after a kernel launch) would report it again, e.g. after a failed
+  // hipMalloc
+  (void)hipGetLastError();
   set_error(std::string(what) + ": " + hipGetErrorString(e));
   return e == hipErrorOutOfMemory ? GIEM_ENOMEM : GIEM_EHIP;
 }

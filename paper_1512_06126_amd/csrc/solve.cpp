@@ -113,10 +113,47 @@ struct GmresParams {
   bool x_zero = true;
 };
 
+// Relative tolerance of one inner solve of the precision form: the inner
+// tolerance itol, relaxed where less is enough, i.e. where a correction that
+// reduces the residual of every unconverged system q by the factor
+// 0.5 tol |b_q| / |r_q| already meets the outer tolerance (in practice the
+// last refinement step, which would otherwise solve its correction far past
+// the outer tolerance).  The outer loop still checks the true FP64 residual.
+static double inner_tolerance(double itol, double tol, const std::vector<int> &act,
+                              const std::vector<double> &normb, const std::vector<double> &rn) {
+  double need = 0.5;
+  for (int q : act)
+    if (rn[q] > 0) need = std::min(need, 0.5 * tol * normb[q] / rn[q]);
+  return std::max(itol, need);
+}
+
+// Residual history of one frequency's right-hand sides q0 .. q0 + nq - 1 into
+// the stats: entry k is the largest k-th recorded residual among them, a
+// system that stopped earlier counting with its final residual (so the last
+// entry is the largest final residual); beyond GIEM_HISTORY entries the
+// first GIEM_HISTORY - 1 and the last are kept.
+static void fill_history(giem_solve_stats &st, const std::vector<std::vector<double>> &hist,
+                         int q0, int nq) {
+  size_t len = 0;
+  for (int q = q0; q < q0 + nq; ++q) len = std::max(len, hist[q].size());
+  auto at = [&](size_t k) {
+    double v = 0.0;
+    for (int q = q0; q < q0 + nq; ++q)
+      if (!hist[q].empty()) v = std::max(v, hist[q][std::min(k, hist[q].size() - 1)]);
+    return v;
+  };
+  st.n_history = (int32_t)std::min<size_t>(len, GIEM_HISTORY);
+  for (int k = 0; k < st.n_history; ++k)
+    st.history[k] = (len > GIEM_HISTORY && k == GIEM_HISTORY - 1) ? at(len - 1) : at(k);
+}
+
 struct GmresResult {
   int iters = 0;      // operator applies inside Arnoldi (max over RHS)
   int restarts = 0;
   std::vector<double> relres;  // final true residual / ||b||
+  // per system: the true residual / ||b|| at the start of every restart
+  // cycle, the last one being the final residual
+  std::vector<std::vector<double>> hist;
   bool converged = false;
 };
 
@@ -264,6 +301,7 @@ static int gmres(giem_handle *t, const std::vector<int> &fq, int nrhs, const VT 
   std::vector<double> normb;
   GIEM_TRY(norms_of(t, b, nrhs, wlev, s, normb));
   res.relres.assign(nrhs, 0.0);
+  res.hist.assign(nrhs, {});
   res.iters = 0;
   res.restarts = 0;
   std::vector<int> done(nrhs, 0);
@@ -326,6 +364,7 @@ static int gmres(giem_handle *t, const std::vector<int> &fq, int nrhs, const VT 
     for (size_t q = 0; q < act.size(); ++q) {
       const int r = act[q];
       res.relres[r] = beta[q] / normb[r];
+      res.hist[r].push_back(res.relres[r]);
       if (beta[q] <= gp.tol * normb[r]) {
         done[r] = 1;
         continue;
@@ -501,6 +540,7 @@ static int gmres(giem_handle *t, const std::vector<int> &fq, int nrhs, const VT 
         GIEM_TRY(norms_of(t, rp.data(), (int)left.size(), wlev, s, rn));
         for (size_t q = 0; q < left.size(); ++q) {
           res.relres[left[q]] = rn[q] / normb[left[q]];
+          res.hist[left[q]].push_back(res.relres[left[q]]);
           if (rn[q] <= gp.tol * normb[left[q]]) done[left[q]] = 1;
         }
       }
@@ -663,6 +703,7 @@ static int gmres_graph(std::vector<GSys<VT>> &sys, const GmresParams &gp, hipStr
     for (int q = hb[k]; q < hb[k + 1]; ++q) normb[q] = nb_[q - hb[k]];
   }
   res.relres.assign(ns, 0.0);
+  res.hist.assign(ns, {});
   res.iters = 0;
   res.restarts = 0;
   std::vector<int> done(ns, 0);
@@ -731,6 +772,7 @@ static int gmres_graph(std::vector<GSys<VT>> &sys, const GmresParams &gp, hipStr
     std::vector<int> cyc;
     for (int q : act) {
       res.relres[q] = beta[q] / normb[q];
+      res.hist[q].push_back(res.relres[q]);
       if (beta[q] <= gp.tol * normb[q]) {
         done[q] = 1;
         continue;
@@ -918,6 +960,7 @@ static int gmres_graph(std::vector<GSys<VT>> &sys, const GmresParams &gp, hipStr
         GIEM_TRY(norms_of(sys[qs[0]].t, rp.data(), (int)qs.size(), wlev_of(sys[qs[0]].t), s, rn));
         for (size_t i = 0; i < qs.size(); ++i) {
           res.relres[qs[i]] = rn[i] / normb[qs[i]];
+          res.hist[qs[i]].push_back(res.relres[qs[i]]);
           if (rn[i] <= gp.tol * normb[qs[i]]) done[qs[i]] = 1;
         }
       }
@@ -1063,6 +1106,7 @@ static int solve_batch_impl(giem_handle *t, int nf, const int *ifreqs, const voi
   int rc = GIEM_OK;
   int iters_total = 0, outer_total = 0;
   std::vector<double> relres(ns, 0.0);
+  std::vector<std::vector<double>> hist(ns);
   std::vector<char> sys_conv(ns, 0);
   if (o->precision == PREC_FP64) {
     gp.prec = PREC_FP64;
@@ -1073,6 +1117,7 @@ static int solve_batch_impl(giem_handle *t, int nf, const int *ifreqs, const voi
     outer_total = gr.restarts;
     for (int q = 0; q < ns; ++q) {
       relres[q] = gr.relres[q];
+      hist[q] = gr.hist[q];
       sys_conv[q] = gr.relres[q] <= o->tol;
     }
   } else {
@@ -1098,6 +1143,7 @@ static int solve_batch_impl(giem_handle *t, int nf, const int *ifreqs, const voi
       act.clear();
       for (int q = 0; q < ns; ++q) {
         relres[q] = normb[q] > 0 ? rn[q] / normb[q] : 0.0;
+        hist[q].push_back(relres[q]);
         sys_conv[q] = relres[q] <= o->tol;
         if (!sys_conv[q]) act.push_back(q);
       }
@@ -1121,7 +1167,7 @@ static int solve_batch_impl(giem_handle *t, int nf, const int *ifreqs, const voi
       }
       GmresParams ip = gp;
       ip.prec = PREC_FP32;
-      ip.tol = itol;
+      ip.tol = inner_tolerance(itol, o->tol, act, normb, rn);
       ip.x_zero = true;
       ip.max_iter = std::max(1, o->max_iter - inner_total);
       GmresResult gr;
@@ -1153,6 +1199,7 @@ static int solve_batch_impl(giem_handle *t, int nf, const int *ifreqs, const voi
       lst.rel_residual = std::max(lst.rel_residual, relres[q]);
       if (!sys_conv[q]) lst.converged = 0;
     }
+    fill_history(lst, hist, f * nrhs, nrhs);
     if (!lst.converged) all_conv = false;
     lst.ms = ms;
     if (st) st[f] = lst;
@@ -1253,6 +1300,7 @@ static int solve_groups_impl(int ng, const giem_solve_group *gr, int nrhs,
   gp.mode = MODE_A;
   int iters_total = 0, outer_total = 0;
   std::vector<double> relres(ns, 0.0);
+  std::vector<std::vector<double>> hist(ns);
   std::vector<char> sys_conv(ns, 0);
   if (o->precision == PREC_FP64) {
     gp.prec = PREC_FP64;
@@ -1263,6 +1311,7 @@ static int solve_groups_impl(int ng, const giem_solve_group *gr, int nrhs,
     outer_total = res.restarts;
     for (int q = 0; q < ns; ++q) {
       relres[q] = res.relres[q];
+      hist[q] = res.hist[q];
       sys_conv[q] = res.relres[q] <= o->tol;
     }
   } else {
@@ -1317,6 +1366,7 @@ static int solve_groups_impl(int ng, const giem_solve_group *gr, int nrhs,
       std::vector<int> act;
       for (int q = 0; q < ns; ++q) {
         relres[q] = normb[q] > 0 ? rn[q] / normb[q] : 0.0;
+        hist[q].push_back(relres[q]);
         sys_conv[q] = relres[q] <= o->tol;
         if (!sys_conv[q]) act.push_back(q);
       }
@@ -1332,7 +1382,7 @@ static int solve_groups_impl(int ng, const giem_solve_group *gr, int nrhs,
       }
       GmresParams ip = gp;
       ip.prec = PREC_FP32;
-      ip.tol = itol;
+      ip.tol = inner_tolerance(itol, o->tol, act, normb, rn);
       ip.x_zero = true;
       ip.max_iter = std::max(1, o->max_iter - inner_total);
       GmresResult res;
@@ -1366,6 +1416,7 @@ static int solve_groups_impl(int ng, const giem_solve_group *gr, int nrhs,
       lst.converged = 1;
       lst.rel_residual = 0.0;
       lst.ms = ms;
+      fill_history(lst, hist, q, nrhs);
       for (int r = 0; r < nrhs; ++r, ++q) {
         lst.rel_residual = std::max(lst.rel_residual, relres[q]);
         if (!sys_conv[q]) lst.converged = 0;
@@ -1444,6 +1495,7 @@ static int adjoint_impl(giem_handle *t, int ifreq, const void *sigma_a, int nrhs
     st->outer_iters = gr.restarts;
     st->converged = gr.converged;
     st->rel_residual = *std::max_element(gr.relres.begin(), gr.relres.end());
+    fill_history(*st, gr.hist, 0, nrhs);
     st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   if (!gr.converged) {

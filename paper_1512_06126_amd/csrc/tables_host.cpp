@@ -924,6 +924,7 @@ int compute_tables(giem_handle *t, hipStream_t s) {
       dM.alloc(Mt.size() * 8) != hipSuccess || dG.alloc(nl * ncolc * 16) != hipSuccess ||
       dH.alloc(nr * ncolc * 16) != hipSuccess || dc0.alloc(noff * 2 * T * 16) != hipSuccess ||
       dc1.alloc(3 * noff * T * 16) != hipSuccess || dc2.alloc(2 * noff * nz2 * 16) != hipSuccess) {
+    (void)hipGetLastError();  // reported here, not by the next launch check
     set_error("giem_tables: out of device memory");
     return GIEM_ENOMEM;
   }
@@ -1015,6 +1016,7 @@ int compute_receiver_kernels(giem_handle *t, int ifreq, void **out, hipStream_t 
       dH.alloc(nr * nf * 16) != hipSuccess || dC.alloc((size_t)R_COUNT * noff * nf * 16) != hipSuccess ||
       hipMalloc(&dK, noff * nz * 18 * sizeof(c128)) != hipSuccess) {
     if (dK) hipFree(dK);
+    (void)hipGetLastError();  // reported here, not by the next launch check
     set_error("giem_fields: out of device memory for the receiver kernels");
     return GIEM_ENOMEM;
   }

@@ -200,6 +200,36 @@ def test_iteration_limit_reports_noconv(lib):
     h.close()
 
 
+def test_residual_history(lib):
+    # giem_solve_stats.history: the true residual at the start of every
+    # restart cycle (FP64; from x = 0 the first is 1) or after every
+    # refinement step (precision form), the last equal to rel_residual; with
+    # restarts the true residual of GMRES does not grow
+    import torch
+    nx, ny, nz = 8, 6, 3
+    m, t, rng = _conditioned_case(nx, ny, nz, 15)
+    h = lib.tables_import(m, [m["freq"]], t[None], flags=lib.TABLES_C64)
+    sa = to_dev(m["sigma_a"])
+    rhs = to_dev(gs.random_vector(rng, 2, nz, ny, nx))
+    E = torch.empty((2, 3, nz, ny, nx), dtype=torch.complex128, device="cuda")
+    st = h.solve(sa, E, rhs=rhs, tol=1e-12, restart=4, max_iter=3000)
+    hist = st["history"]
+    print(f"FP64 GMRES(4): {st['outer_iters']} cycles, history {len(hist)} entries "
+          f"{hist[0]:.2e} .. {hist[-1]:.2e}", flush=True)
+    assert st["converged"] == 1
+    assert len(hist) == min(st["outer_iters"] + 1, 64)
+    assert abs(hist[0] - 1.0) <= 1e-12
+    assert hist[-1] == st["rel_residual"] and hist[-1] <= 1e-12
+    assert all(b <= a * (1 + 1e-9) for a, b in zip(hist, hist[1:]))
+    st = h.solve(sa, E, rhs=rhs, tol=1e-12, precision=lib.FP32, inner_tol=1e-3)
+    hist = st["history"]
+    print(f"precision form: {st['outer_iters']} refinement steps, history {hist}", flush=True)
+    assert st["converged"] == 1 and len(hist) == st["outer_iters"] + 1
+    assert hist[-1] == st["rel_residual"] and hist[-1] <= 1e-12
+    assert all(b < a for a, b in zip(hist, hist[1:]))
+    h.close()
+
+
 def test_invalid_sigma_rejected(lib):
     import torch
     nx, ny, nz = 4, 3, 2
