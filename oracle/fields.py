@@ -1,4 +1,5 @@
-"""Electric and magnetic fields at surface receivers from the cell fields
+"""Electric and magnetic fields at receivers from the cell fields, and the
+right-hand side of dipole sources
 (Sect. 2.2, the representation of the anomalous fields through G^E and G^H
 integrated over the cells; Appendix A for the tensors).  Test infrastructure.
 
@@ -233,9 +234,54 @@ def surface_normal_fields(model, freq=None):
     return EN, HN
 
 
-def fields_at(model, E_cells, rec_xy, sigma_a=None, freq=None, z0=0.0):
-    """e, h at receivers (x, y) [nrec, 2] for E_cells [R][3][Nz][Ny][Nx]
-    (RHS 0 / 1 = x / y polarisation of the plane-wave source): [R][nrec][3]."""
+def normal_fields_at(model, z0=0.0, freq=None):
+    """E^N and H^N at depth z0 in the earth for the x and the y polarisation
+    of the unit-surface-field plane wave: arrays [2][3].  Faraday's law
+    (curl E = i w mu0 H) for a field E_x(z): H_y = dE_x/dz / (i w mu0); for
+    E_y(z): H_x = -dE_y/dz / (i w mu0)."""
+    f = model["freq"] if freq is None else freq
+    if z0 == model["d"][0]:
+        return surface_normal_fields(model, f)      # E = 1 there by definition
+    pw = LayeredPlaneWave(model["d"], model["sigma"], f)
+    e = pw.E(z0)
+    hy = pw.dE(z0) / (1j * pw.omega * MU0)
+    EN = np.array([[e, 0, 0], [0, e, 0]], complex)
+    HN = np.array([[0, hy, 0], [-hy, 0, 0]], complex)
+    return EN, HN
+
+
+def dipole_source(model, src_xy, moments, freq=None, z0=0.0):
+    """Right-hand side U0 = sqrt(Re sigma_b) <E^0>_n of the scaled system for
+    electric dipoles of moments p_s [nsrc, 3] (A m) at points (x, y, z0)
+    (Sect. 2.1: the external current J_ext = p delta(r - r_s); Sect. 2.2: the
+    source enters only through the normal field E^0 averaged over each cell).
+    The normal field of a dipole is E^0(r) = G^E(r, r_s) p; by reciprocity of
+    the layered medium (Appendix A: G^E(r, r') = G^E(r', r)^T),
+      int_{cell n} E^0 = [int_{cell n} G^E(r_s, r) dr]^T p = KE(r_s <- n)^T p,
+    the receiver kernel of a receiver at the source point, transposed.
+    Array [nsrc, 3, nz, ny, nx]."""
+    nx, ny, nz = model["nx"], model["ny"], model["nz"]
+    hx, hy = model["hx"], model["hy"]
+    x0, y0 = model.get("x0", 0.0), model.get("y0", 0.0)
+    ze = np.asarray(model["z_edges"], float)
+    cx = x0 + (np.arange(nx) + 0.5) * hx
+    cy = y0 + (np.arange(ny) + 0.5) * hy
+    src_xy = np.atleast_2d(np.asarray(src_xy, float))
+    moments = np.atleast_2d(np.asarray(moments, complex))
+    offs = np.array([(xs - cxx, ys - cyy) for (xs, ys) in src_xy for cyy in cy for cxx in cx])
+    KE, _ = receiver_kernels(model, offs, freq, z0)
+    KE = KE.reshape(len(src_xy), ny, nx, nz, 3, 3)
+    vol = hx * hy * np.diff(ze)                                    # [nz]
+    sb = np.asarray(model["sigma"], complex)[model["layer_of_cell"]]
+    e0 = np.einsum("syxzrc,sr->sczyx", KE, moments) / vol[None, None, :, None, None]
+    return np.sqrt(sb.real)[None, None, :, None, None] * e0
+
+
+def fields_at(model, E_cells, rec_xy, sigma_a=None, freq=None, z0=0.0, normal=True):
+    """e, h at receivers (x, y, z0) [nrec, 2] for E_cells [R][3][Nz][Ny][Nx]
+    (RHS 0 / 1 = x / y polarisation of the plane-wave source, whose normal
+    fields at z0 are added when normal is set; else, or for further RHS, the
+    anomalous fields only): [R][nrec][3]."""
     sa = model["sigma_a"] if sigma_a is None else sigma_a
     nx, ny, nz = model["nx"], model["ny"], model["nz"]
     hx, hy = model["hx"], model["hy"]
@@ -247,14 +293,14 @@ def fields_at(model, E_cells, rec_xy, sigma_a=None, freq=None, z0=0.0):
     cy = y0 + (np.arange(ny) + 0.5) * hy
     rec_xy = np.atleast_2d(np.asarray(rec_xy, float))
     R = E_cells.shape[0]
-    EN, HN = surface_normal_fields(model, freq)
+    EN, HN = normal_fields_at(model, z0, freq)
     offs = np.array([(xr - cxx, yr - cyy) for (xr, yr) in rec_xy for cyy in cy for cxx in cx])
     KE, KH = receiver_kernels(model, offs, freq, z0)
     KE = KE.reshape(len(rec_xy), ny, nx, nz, 3, 3)
     KH = KH.reshape(len(rec_xy), ny, nx, nz, 3, 3)
     e = np.einsum("qyxzab,rbzyx->rqa", KE, cur)
     h = np.einsum("qyxzab,rbzyx->rqa", KH, cur)
-    n = min(R, 2)
+    n = min(R, 2) if normal else 0
     e[:n] += EN[:n, None, :]
     h[:n] += HN[:n, None, :]
     return e, h
