@@ -373,9 +373,10 @@ int giem_adjoint(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrh
                  const giem_solve_opts *opts, giem_solve_stats *stats, void *stream);
 
 /*
- * giem_fields -- electric and magnetic fields at receivers on the earth's
- * surface from the cell field (Sect. 2.2, the representation of the fields
- * through G^E and G^H integrated over the cells; Appendix A):
+ * giem_fields -- electric and magnetic fields at receivers in the earth
+ * above the anomaly grid from the cell field (Sect. 2.2, the representation
+ * of the fields through G^E and G^H integrated over the cells, which holds
+ * for any observation point; Appendix A):
  *   e(r) = E^N(r) + sum_n (sa_n - sb_n) [int_{cell n} G^E(r, M0) dM0] E_n,
  *   h(r) = H^N(r) + sum_n (sa_n - sb_n) [int_{cell n} G^H(r, M0) dM0] E_n,
  * with G^H = curl G^E / (i w mu0).  The horizontal E and all of H are
@@ -384,19 +385,54 @@ int giem_adjoint(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrh
  *   sigma_a: device c128 [Nz][Ny][Nx];
  *   E_cells: device c128 [nrhs][3][Nz][Ny][Nx] (E = U / a, as from giem_solve);
  *   rec_xyz: host [nrec][3] receiver positions (x, y, z) in m, z positive
- *            down; every receiver must lie on the earth's surface (z = d[0])
- *            above the centre of a cell of the grid;
+ *            down; all receivers of a call at one depth z0 with
+ *            d[0] <= z0 <= z_edges[0] (the earth's surface, any depth in
+ *            the earth above the grid, or the top face of the grid's first
+ *            cells), each above the centre of a cell of the grid;
  *   E_rec, H_rec: device c128 [nrhs][nrec][3] outputs.
- * E^N, H^N (1 V/m plane wave) are added for RHS 0 (x polarisation) and RHS 1
- * (y polarisation); further RHS get the anomalous fields only.  The cell
- * integrals for every receiver offset are computed on the first call for a
- * frequency and kept on the handle.  Synchronises the stream.
- * Errors: EINVAL, EDOMAIN (receiver off the surface or not above a cell
- * centre, or the grid does not start at the surface d[0]), ENOMEM, EHIP.
+ * E^N, H^N at depth z0 of the plane wave of 1 V/m at the surface are added
+ * for RHS 0 (x polarisation) and RHS 1 (y polarisation); further RHS get the
+ * anomalous fields only (giem_fields_anomalous: none added, for any source).
+ * The cell integrals for every receiver offset are computed on the first
+ * call for a frequency and depth and kept on the handle.  Synchronises the
+ * stream.  Errors: EINVAL, EDOMAIN (receivers not at one depth in that range
+ * or not above cell centres), ENOMEM, EHIP.
  */
 int giem_fields(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
                 const void *E_cells, int32_t nrec, const double *rec_xyz, void *E_rec,
                 void *H_rec, void *stream);
+
+/*
+ * giem_fields_anomalous -- giem_fields without the plane-wave normal fields:
+ * e - E^N and h - H^N of every RHS (Sect. 2.2), for solves whose source is
+ * not the plane wave (giem_dipole_source).  Same arguments and errors.
+ */
+int giem_fields_anomalous(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
+                          const void *E_cells, int32_t nrec, const double *rec_xyz, void *E_rec,
+                          void *H_rec, void *stream);
+
+/*
+ * giem_dipole_source -- right-hand side of electric dipole sources (Sect.
+ * 2.1: an external current J_ext = p delta(r - r_s); Sect. 2.2: the source
+ * enters the scaled system only through the cell averages of its normal
+ * field, U0_n = sqrt(Re sigma_b) <E^0>_n).  By reciprocity of the layered
+ * background (Appendix A: G^E(r, r') = G^E(r', r)^T) the cell integral of
+ * the dipole's normal field is the transposed receiver kernel of a receiver
+ * at the source point: int_{cell n} E^0 = [int_{cell n} G^E(r_s, M0) dM0]^T p.
+ *   src_xyz: host [nsrc][3] source positions, 1 <= nsrc <= 8, with the
+ *            constraints of giem_fields' receivers (one depth z0 with
+ *            d[0] <= z0 <= z_edges[0], above cell centres);
+ *   moments: host c128 [nsrc][3] dipole moments p (A m);
+ *   rhs:     device c128 [nsrc][3][Nz][Ny][Nx] output, one right-hand side
+ *            per source, to be passed as giem_solve's rhs; the solve gives
+ *            the total cell field, and at receivers giem_fields_anomalous
+ *            gives the anomalous part (the dipole's own normal field at the
+ *            receivers is not computed).
+ * Shares the receiver kernels of giem_fields (built on first use for the
+ * depth).  Synchronises the stream.  Errors: EINVAL, EDOMAIN, ENOMEM, EHIP.
+ */
+int giem_dipole_source(giem_handle *t, int32_t ifreq, int32_t nsrc, const double *src_xyz,
+                       const double *moments, void *rhs, void *stream);
 
 /*
  * giem_impedance -- impedance tensor at every receiver from the fields of the

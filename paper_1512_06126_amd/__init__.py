@@ -97,6 +97,8 @@ def load():
         "giem_adjoint": [P, I32, P, I32, P, P, P, P, P, P],
         "giem_fields": [P, I32, P, I32, P, I32, P, P, P, P],
         "giem_fields_adjoint": [P, I32, P, I32, P, I32, P, P, P, P, P, P],
+        "giem_fields_anomalous": [P, I32, P, I32, P, I32, P, P, P, P],
+        "giem_dipole_source": [P, I32, I32, P, P, P, P],
         "giem_impedance": [I32, P, P, P, P],
         "giem_impedance_adjoint": [I32, P, P, P, P, P, P],
         "giem_profile": [P, I32],
@@ -120,7 +122,8 @@ def load():
 def exported_symbols():
     return ["giem_tables", "giem_tables_import", "giem_tables_export", "giem_tables_bytes",
             "giem_apply", "giem_apply_noalloc", "giem_apply_timed", "giem_apply_batch", "giem_tune", "giem_set_fft_shape", "giem_set_block_buffers", "giem_profile", "giem_profile_read", "giem_solve", "giem_solve_batch", "giem_solve_multi",
-            "giem_adjoint", "giem_fields", "giem_fields_adjoint", "giem_impedance",
+            "giem_adjoint", "giem_fields", "giem_fields_anomalous", "giem_fields_adjoint",
+            "giem_dipole_source", "giem_impedance",
             "giem_impedance_adjoint", "giem_free", "giem_last_error"]
 
 
@@ -326,19 +329,33 @@ class Handle:
         return d
 
     def receivers(self, rec):
-        """Receiver positions as host float64 [nrec][3]; (x, y) pairs are
-        placed on the earth's surface z = d[0] of the handle's model."""
+        """Receiver (or source) positions as host float64 [nrec][3]; (x, y)
+        pairs are placed on the earth's surface z = d[0] of the handle's model."""
         rec = np.asarray(rec, dtype=np.float64)
         if rec.ndim == 2 and rec.shape[1] == 2:
             rec = np.concatenate([rec, np.full((rec.shape[0], 1), float(self.model["d"][0]))], 1)
         return np.ascontiguousarray(rec.reshape(-1, 3))
 
-    def fields(self, sigma_a, E_cells, rec_xyz, E_rec, H_rec, ifreq=0, stream=None):
+    def fields(self, sigma_a, E_cells, rec_xyz, E_rec, H_rec, ifreq=0, stream=None,
+               anomalous=False):
+        """giem_fields (plane-wave normal fields added for RHS 0 and 1), or
+        giem_fields_anomalous (the anomalous fields only, for any source)."""
         rec = self.receivers(rec_xyz)
-        _check(_lib.giem_fields(self._p, ifreq, _ptr(sigma_a), E_cells.shape[0], _ptr(E_cells),
-                                rec.shape[0], rec.ctypes.data, _ptr(E_rec), _ptr(H_rec),
-                                _stream(stream)))
+        fn = _lib.giem_fields_anomalous if anomalous else _lib.giem_fields
+        _check(fn(self._p, ifreq, _ptr(sigma_a), E_cells.shape[0], _ptr(E_cells), rec.shape[0],
+                  rec.ctypes.data, _ptr(E_rec), _ptr(H_rec), _stream(stream)))
         return E_rec, H_rec
+
+    def dipole_source(self, src_xyz, moments, rhs, ifreq=0, stream=None):
+        """giem_dipole_source: rhs [nsrc][3][Nz][Ny][Nx] (complex128, on the
+        device) receives the right-hand side of electric dipoles of moments
+        [nsrc][3] (A m) at src_xyz [nsrc][3] (or (x, y) on the surface), to be
+        passed to solve(rhs=...)."""
+        src = self.receivers(src_xyz)
+        mom = np.ascontiguousarray(np.asarray(moments, dtype=np.complex128).reshape(-1, 3))
+        _check(_lib.giem_dipole_source(self._p, ifreq, src.shape[0], src.ctypes.data,
+                                       mom.ctypes.data, _ptr(rhs), _stream(stream)))
+        return rhs
 
     def fields_adjoint(self, sigma_a, E_cells, rec_xyz, wE, wH, adj_src, grad, ifreq=0,
                        stream=None):

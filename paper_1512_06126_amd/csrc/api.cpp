@@ -523,7 +523,7 @@ void giem_free(giem_handle *t) {
     if (ft.spatial) hipFree(ft.spatial);
     if (ft.spec64) hipFree(ft.spec64);
     if (ft.spec32) hipFree(ft.spec32);
-    if (ft.rec_kernel) hipFree(ft.rec_kernel);
+    for (auto &rk : ft.rec_kernels) hipFree(rk.second);
   }
   void *dev[] = {t->px.tw64, t->px.tw32, t->py.tw64, t->py.tw32, t->cs_x, t->cs_y, t->bplan,
                  t->sb_lev, t->vol_lev, t->sroot_lev, t->diag, t->spec_ws, t->red_part,

@@ -3,6 +3,7 @@
 
 #include <complex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/giem.h"
@@ -26,7 +27,9 @@ struct FreqTables {
   void *spec64 = nullptr;      // c128 [(Ny+1)(Nx+1)][E] packed spectra
   void *spec32 = nullptr;      // c64 copy (GIEM_TABLES_C64)
   void *spatial = nullptr;     // c128 [Ny][Nx][E] packed spatial table (device)
-  void *rec_kernel = nullptr;  // receiver kernels (giem_fields), built on first use
+  // receiver kernels (giem_fields, giem_dipole_source) per receiver depth,
+  // built on first use
+  std::vector<std::pair<double, void *>> rec_kernels;
 };
 
 struct SolveWork;
@@ -115,6 +118,6 @@ int plane_wave_levels(const giem_handle *t, double freq, std::vector<cd> &en_lev
 // packed spatial tables of every frequency of the handle (t->f[q].spatial, device)
 int compute_tables(giem_handle *t, hipStream_t s);
 // receiver kernels of frequency ifreq (device, owned by the caller)
-int compute_receiver_kernels(giem_handle *t, int ifreq, void **out, hipStream_t s);
+int compute_receiver_kernels(giem_handle *t, int ifreq, double z0, void **out, hipStream_t s);
 
 }  // namespace giem

@@ -72,6 +72,11 @@ hipError_t launch_fields_adjoint(const c128 *K, const c128 *E, const c128 *sa, c
                                  const int *rec, int nrec, int nrhs, int nx, int ny, int nz,
                                  const c128 *wE, const c128 *wH, c128 *g, double *grad,
                                  hipStream_t s);
+// U0 of unit-free dipole moments p [nsrc][3] at lattice points src [nsrc][2]
+// from the receiver kernels K of their depth: out [nsrc][3][N]
+hipError_t launch_dipole_rhs(const c128 *K, const int *src, const c128 *p, int nsrc, int nx,
+                             int ny, int nz, const double *sroot_lev, const double *vol_lev,
+                             c128 *out, hipStream_t s);
 
 // Krylov vector kernels (kernels_vec.hip); vectors of n = 3 Nz Ny Nx complex.
 // Krylov vectors are complex128, or complex64 in the inner solve of the

@@ -344,6 +344,47 @@ hipError_t launch_fields_adjoint(const c128 *K, const c128 *E, const c128 *sa, c
   return hipGetLastError();
 }
 
+// Right-hand side of electric dipoles on the receiver lattice (Sect. 2.1,
+// the external current of a point source; Sect. 2.2, the source enters
+// through the cell averages of its normal field): by reciprocity of the
+// layered medium, G^E(r, r_s) = G^E(r_s, r)^T, so
+//   U0[s][c][n] = sqrt(Re sb_n) / V_n sum_a KE(r_s <- n)[a][c] p_s[a],
+// with KE the receiver kernel of a receiver at the source point.  One
+// thread per (cell, source); neighbouring threads take neighbouring cells.
+__global__ void __launch_bounds__(256)
+k_dipole_rhs(const c128 *__restrict__ K, const int *__restrict__ src, const c128 *__restrict__ p,
+             int nsrc, int nx, int ny, int nz, const double *__restrict__ sroot_lev,
+             const double *__restrict__ vol_lev, c128 *__restrict__ out) {
+  const size_t plane = (size_t)nx * ny, N = plane * nz;
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int sidx = blockIdx.y;
+  if (t >= N || sidx >= nsrc) return;
+  const int iz = (int)(t / plane);
+  const size_t rem = t - (size_t)iz * plane;
+  const int iy = (int)(rem / nx), ix = (int)(rem - (size_t)iy * nx);
+  const int is = src[2 * sidx], js = src[2 * sidx + 1];
+  const size_t off = (size_t)(js - iy + ny - 1) * (2 * nx - 1) + (is - ix + nx - 1);
+  const c128 *k = K + (off * nz + iz) * 18;
+  const c128 *ps = p + (size_t)sidx * 3;
+  const double f = sroot_lev[iz] / vol_lev[iz];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    c128 acc = mk<double>(0.0, 0.0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) cfma(acc, k[3 * a + c], ps[a]);
+    out[((size_t)sidx * 3 + c) * N + t] = cscale(acc, f);
+  }
+}
+
+hipError_t launch_dipole_rhs(const c128 *K, const int *src, const c128 *p, int nsrc, int nx,
+                             int ny, int nz, const double *sroot_lev, const double *vol_lev,
+                             c128 *out, hipStream_t s) {
+  const size_t N = (size_t)nx * ny * nz;
+  hipLaunchKernelGGL(k_dipole_rhs, dim3((unsigned)((N + 255) / 256), (unsigned)nsrc), dim3(256), 0,
+                     s, K, src, p, nsrc, nx, ny, nz, sroot_lev, vol_lev, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_assemble_rec(const c128 *c, c128 *out, int noff, int nz, double omega_mu0,
                                hipStream_t s) {
   const int64_t total = (int64_t)noff * nz;

@@ -75,6 +75,19 @@ struct PlaneWave {
     while (m < nl && d[m] <= z) ++m;
     return m;
   }
+  // E and dE/dz at depth z in the earth (z >= d[0])
+  cd value(double z, cd *dz) const {
+    const int m = layer(z);
+    const cd ik = cd(0, 1) * k[m];
+    if (m == nl) {
+      const cd e = a[m] * std::exp(ik * (z - d[m - 1]));
+      *dz = ik * e;
+      return e;
+    }
+    const cd up = std::exp(ik * (z - d[m])), dn = std::exp(-ik * (z - d[m]));
+    *dz = ik * a[m] * (up - r[m] * dn);
+    return a[m] * (up + r[m] * dn);
+  }
   // mean of E over [z1, z2] inside one earth layer
   cd average(double z1, double z2) const {
     const int m = layer(0.5 * (z1 + z2));
@@ -1545,33 +1558,54 @@ int giem_adjoint(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrh
 
 namespace giem {
 
-// Lattice indices of receivers rec_xyz [nrec][3] that lie on the earth's
-// surface (z = d[0]) above cell centres; EDOMAIN otherwise or when the anomaly
-// grid does not start at the surface d[0].
+// Lattice indices of receivers (or dipole sources) rec_xyz [nrec][3] above
+// cell centres at one common depth z0 in the earth, d[0] <= z0 <= the top of
+// the grid (on the first cells' top face, or above the grid); EDOMAIN
+// otherwise.
 static int receiver_indices(const giem_handle *t, int nrec, const double *rec_xyz,
-                            std::vector<int> &idx, const char *who) {
-  const double zscale = t->z_edges[t->nz] - t->z_edges[0];
-  if (std::fabs(t->z_edges[0] - t->d[0]) > 1e-9 * zscale) {
-    set_error(std::string(who) + ": the anomaly grid must start at the earth's surface d[0]");
+                            std::vector<int> &idx, double &z0, const char *who) {
+  const double zscale = std::max(t->z_edges[t->nz] - t->d[0], t->z_edges[t->nz] - t->z_edges[0]);
+  const double tol = 1e-9 * zscale;
+  idx.assign(2 * (size_t)nrec, 0);
+  z0 = nrec > 0 ? rec_xyz[2] : t->z_edges[0];
+  if (!(z0 >= t->d[0] - tol && z0 <= t->z_edges[0] + tol)) {
+    set_error(std::string(who) + ": points must lie in the earth at or above the top of the "
+              "anomaly grid (d[0] <= z <= top of the grid)");
     return GIEM_EDOMAIN;
   }
-  idx.assign(2 * (size_t)nrec, 0);
+  if (std::fabs(z0 - t->z_edges[0]) <= tol) z0 = t->z_edges[0];
+  if (std::fabs(z0 - t->d[0]) <= tol) z0 = t->d[0];
   for (int q = 0; q < nrec; ++q) {
     const double fx = (rec_xyz[3 * q] - t->x0) / t->hx - 0.5;
     const double fy = (rec_xyz[3 * q + 1] - t->y0) / t->hy - 0.5;
     const double ix = std::round(fx), iy = std::round(fy);
-    if (!(std::fabs(rec_xyz[3 * q + 2] - t->d[0]) <= 1e-9 * zscale)) {
-      set_error(std::string(who) + ": receivers must lie on the earth's surface z = d[0]");
+    if (!(std::fabs(rec_xyz[3 * q + 2] - z0) <= tol)) {
+      set_error(std::string(who) + ": all points of one call must lie at one depth");
       return GIEM_EDOMAIN;
     }
     if (!(std::fabs(fx - ix) <= 1e-9) || !(std::fabs(fy - iy) <= 1e-9) || ix < 0 ||
         ix >= t->nx || iy < 0 || iy >= t->ny) {
-      set_error(std::string(who) + ": receivers must lie above cell centres of the grid");
+      set_error(std::string(who) + ": points must lie above cell centres of the grid");
       return GIEM_EDOMAIN;
     }
     idx[2 * q] = (int)ix;
     idx[2 * q + 1] = (int)iy;
   }
+  return GIEM_OK;
+}
+
+// Receiver kernels of frequency ifreq at depth z0, built on first use.
+static int receiver_kernel(giem_handle *t, int ifreq, double z0, hipStream_t s, const c128 **K) {
+  FreqTables &ft = t->f[ifreq];
+  for (auto &rk : ft.rec_kernels)
+    if (rk.first == z0) {
+      *K = static_cast<const c128 *>(rk.second);
+      return GIEM_OK;
+    }
+  void *k = nullptr;
+  GIEM_TRY(compute_receiver_kernels(t, ifreq, z0, &k, s));
+  ft.rec_kernels.emplace_back(z0, k);
+  *K = static_cast<const c128 *>(k);
   return GIEM_OK;
 }
 
@@ -1589,46 +1623,98 @@ struct DevCopy {
   }
 };
 
-}  // namespace giem
-
-extern "C" int giem_fields(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
-                           const void *E_cells, int32_t nrec, const double *rec_xyz, void *E_rec,
-                           void *H_rec, void *stream) {
-  using namespace giem;
+static int fields_impl(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
+                       const void *E_cells, int32_t nrec, const double *rec_xyz, void *E_rec,
+                       void *H_rec, void *stream, bool normal, const char *who) {
   if (!t || ifreq < 0 || ifreq >= (int)t->f.size() || !sigma_a || nrhs < 1 || !E_cells ||
       nrec < 0 || (nrec > 0 && (!rec_xyz || !E_rec || !H_rec))) {
-    set_error("giem_fields: bad argument");
+    set_error(std::string(who) + ": bad argument");
     return GIEM_EINVAL;
   }
   if (nrec == 0) return GIEM_OK;
   std::vector<int> idx;
-  GIEM_TRY(receiver_indices(t, nrec, rec_xyz, idx, "giem_fields"));
+  double z0 = 0.0;
+  GIEM_TRY(receiver_indices(t, nrec, rec_xyz, idx, z0, who));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  FreqTables &ft = t->f[ifreq];
-  if (!ft.rec_kernel) GIEM_TRY(compute_receiver_kernels(t, ifreq, &ft.rec_kernel, s));
-  // normal fields at the surface: RHS 0 x polarisation, RHS 1 y polarisation
-  std::vector<cd> en_lev, hsurf;
-  GIEM_TRY(plane_wave_levels(t, ft.freq, en_lev, hsurf));
-  const cd hy = hsurf[0];
+  const c128 *K = nullptr;
+  GIEM_TRY(receiver_kernel(t, ifreq, z0, s, &K));
+  // normal fields at the receivers' depth: RHS 0 x polarisation, RHS 1 y
+  // polarisation of the unit-surface-field plane wave (H from Faraday's law)
   std::vector<c128> nf((size_t)nrhs * 6, mk<double>(0.0, 0.0));
-  if (nrhs >= 1) {
-    nf[0] = mk<double>(1.0, 0.0);
-    nf[4] = mk<double>(hy.real(), hy.imag());
-  }
-  if (nrhs >= 2) {
-    nf[6 + 1] = mk<double>(1.0, 0.0);
-    nf[6 + 3] = mk<double>(-hy.real(), -hy.imag());
+  if (normal) {
+    PlaneWave pw(t->d, t->sigma, t->f[ifreq].freq);
+    cd e = 1.0, hy = 1.0 / pw.Zs, de;
+    if (z0 != t->d[0]) {
+      e = pw.value(z0, &de);
+      hy = de / cd(0.0, pw.omega * kMu0);
+    }
+    if (nrhs >= 1) {
+      nf[0] = mk<double>(e.real(), e.imag());
+      nf[4] = mk<double>(hy.real(), hy.imag());
+    }
+    if (nrhs >= 2) {
+      nf[6 + 1] = mk<double>(e.real(), e.imag());
+      nf[6 + 3] = mk<double>(-hy.real(), -hy.imag());
+    }
   }
   DevCopy drec, dnf;
   GIEM_TRY(drec.put(idx.data(), idx.size() * sizeof(int), s, "receivers"));
   GIEM_TRY(dnf.put(nf.data(), nf.size() * sizeof(c128), s, "normal fields"));
-  GIEM_HIP(launch_fields(static_cast<const c128 *>(ft.rec_kernel), static_cast<const c128 *>(E_cells),
+  GIEM_HIP(launch_fields(K, static_cast<const c128 *>(E_cells),
                          static_cast<const c128 *>(sigma_a), static_cast<const c128 *>(t->sb_lev),
                          static_cast<const int *>(drec.p), nrec, nrhs, t->nx, t->ny, t->nz,
                          static_cast<const c128 *>(dnf.p), static_cast<c128 *>(E_rec),
                          static_cast<c128 *>(H_rec), s),
            "fields kernel");
   GIEM_HIP(hipStreamSynchronize(s), "fields");
+  return GIEM_OK;
+}
+
+}  // namespace giem
+
+extern "C" int giem_fields(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
+                           const void *E_cells, int32_t nrec, const double *rec_xyz, void *E_rec,
+                           void *H_rec, void *stream) {
+  return giem::fields_impl(t, ifreq, sigma_a, nrhs, E_cells, nrec, rec_xyz, E_rec, H_rec, stream,
+                           true, "giem_fields");
+}
+
+extern "C" int giem_fields_anomalous(giem_handle *t, int32_t ifreq, const void *sigma_a,
+                                     int32_t nrhs, const void *E_cells, int32_t nrec,
+                                     const double *rec_xyz, void *E_rec, void *H_rec,
+                                     void *stream) {
+  return giem::fields_impl(t, ifreq, sigma_a, nrhs, E_cells, nrec, rec_xyz, E_rec, H_rec, stream,
+                           false, "giem_fields_anomalous");
+}
+
+extern "C" int giem_dipole_source(giem_handle *t, int32_t ifreq, int32_t nsrc,
+                                  const double *src_xyz, const double *moments, void *rhs,
+                                  void *stream) {
+  using namespace giem;
+  if (!t || ifreq < 0 || ifreq >= (int)t->f.size() || nsrc < 1 || nsrc > kMaxRhs || !src_xyz ||
+      !moments || !rhs) {
+    set_error("giem_dipole_source: bad argument (1 .. 8 sources)");
+    return GIEM_EINVAL;
+  }
+  for (int q = 0; q < 6 * nsrc; ++q)
+    if (!std::isfinite(moments[q])) {
+      set_error("giem_dipole_source: moments must be finite");
+      return GIEM_EINVAL;
+    }
+  std::vector<int> idx;
+  double z0 = 0.0;
+  GIEM_TRY(receiver_indices(t, nsrc, src_xyz, idx, z0, "giem_dipole_source"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const c128 *K = nullptr;
+  GIEM_TRY(receiver_kernel(t, ifreq, z0, s, &K));
+  DevCopy dsrc, dmom;
+  GIEM_TRY(dsrc.put(idx.data(), idx.size() * sizeof(int), s, "sources"));
+  GIEM_TRY(dmom.put(moments, (size_t)nsrc * 3 * sizeof(c128), s, "moments"));
+  GIEM_HIP(launch_dipole_rhs(K, static_cast<const int *>(dsrc.p), static_cast<const c128 *>(dmom.p),
+                             nsrc, t->nx, t->ny, t->nz, static_cast<const double *>(t->sroot_lev),
+                             static_cast<const double *>(t->vol_lev), static_cast<c128 *>(rhs), s),
+           "dipole source kernel");
+  GIEM_HIP(hipStreamSynchronize(s), "dipole source");
   return GIEM_OK;
 }
 
@@ -1643,14 +1729,15 @@ extern "C" int giem_fields_adjoint(giem_handle *t, int32_t ifreq, const void *si
     return GIEM_EINVAL;
   }
   std::vector<int> idx;
-  if (nrec > 0) GIEM_TRY(receiver_indices(t, nrec, rec_xyz, idx, "giem_fields_adjoint"));
+  double z0 = 0.0;
+  if (nrec > 0) GIEM_TRY(receiver_indices(t, nrec, rec_xyz, idx, z0, "giem_fields_adjoint"));
   hipStream_t s = static_cast<hipStream_t>(stream);
   GIEM_TRY(check_sigma_a(t, sigma_a, s));
-  FreqTables &ft = t->f[ifreq];
-  if (nrec > 0 && !ft.rec_kernel) GIEM_TRY(compute_receiver_kernels(t, ifreq, &ft.rec_kernel, s));
+  const c128 *K = nullptr;
+  if (nrec > 0) GIEM_TRY(receiver_kernel(t, ifreq, z0, s, &K));
   DevCopy drec;
   if (nrec > 0) GIEM_TRY(drec.put(idx.data(), idx.size() * sizeof(int), s, "receivers"));
-  GIEM_HIP(launch_fields_adjoint(static_cast<const c128 *>(ft.rec_kernel),
+  GIEM_HIP(launch_fields_adjoint(K,
                                  static_cast<const c128 *>(E_cells),
                                  static_cast<const c128 *>(sigma_a),
                                  static_cast<const c128 *>(t->sb_lev),

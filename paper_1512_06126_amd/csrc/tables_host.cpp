@@ -665,6 +665,35 @@ struct Vertical {
   int nz;
   std::vector<int> lay;          // layer of each cell
   std::vector<double> ta, tb;    // local coordinates of the cell edges
+  // point observer (receiver kernels) at depth z0 in the earth, at or above
+  // the top of the grid: the gap [z0, top of the grid] split at interfaces
+  // into pieces (layer, local top, local bottom); empty when z0 is the top
+  double z0 = 0.0;
+  int lay_obs = 1;
+  std::vector<int> gap_lay;
+  std::vector<double> gap_ta, gap_tb;
+  void set_observer(double z) {
+    z0 = z;
+    gap_lay.clear();
+    gap_ta.clear();
+    gap_tb.clear();
+    const double top = t->z_edges[0];
+    auto layer_at = [&](double zz) {  // layer holding depth zz from below
+      int n = 1;
+      while (n < t->nlay && t->d[n] <= zz) ++n;
+      return n;
+    };
+    lay_obs = z0 < top ? layer_at(z0) : lay.empty() ? 1 : lay[0];
+    double a = z0;
+    while (a < top) {
+      const int n = layer_at(a);
+      const double b = (n < t->nlay) ? std::min(top, t->d[n]) : top;
+      gap_lay.push_back(n);
+      gap_ta.push_back(a - t->d[n - 1]);
+      gap_tb.push_back(b - t->d[n - 1]);
+      a = b;
+    }
+  }
   void init(const giem_handle *h, double freq) {
     t = h;
     nz = h->nz;
@@ -679,6 +708,7 @@ struct Vertical {
       ta[l] = h->z_edges[l] - top;
       tb[l] = h->z_edges[l + 1] - top;
     }
+    set_observer(h->z_edges[0]);
   }
 
   // per-cell factors of both kinds (k = 0: gamma = 1, k = 1: gamma = sigma)
@@ -689,7 +719,12 @@ struct Vertical {
     cx GDd;     // d/dz of U(z, bottom) - U(z, top) at the top edge (regular part)
   };
 
-  void factors(double lam, std::vector<Cell> (&cell)[2]) const {
+  // eta and the downward coefficients p of every layer (kind 0 and 1)
+  struct LayerFns {
+    std::vector<cx> eta, p[2];
+  };
+
+  void factors(double lam, std::vector<Cell> (&cell)[2], LayerFns *lf = nullptr) const {
     const int nl = t->nlay;
     const int nlayers = nl + 1;
     std::vector<cx> eta(nlayers);
@@ -717,6 +752,11 @@ struct Vertical {
         const cx a = g(n + 1) * eta[n] * (1.0 + Qp), b = g(n) * eta[n + 1] * (1.0 - Qp);
         q[k][n] = (a - b) / (a + b);
       }
+    }
+    if (lf) {
+      lf->eta = eta;
+      lf->p[0] = p[0];
+      lf->p[1] = p[1];
     }
     for (int k = 0; k < 2; ++k) {
       cell[k].resize(nz);
@@ -827,8 +867,9 @@ struct Vertical {
     }
   }
 
-  // Point observer at the top of the first cell (the earth's surface), on
-  // the earth side; the eight lambda-functions of every source level jz,
+  // Point observer at depth z0 (set_observer): at the top of the first cell
+  // (on the earth side), or above the grid inside the earth; the eight
+  // lambda-functions of every source level jz,
   // written as out[f * nz + jz]:
   //   0 lambda A1, 1 lambda A2, 2 lambda dA1, 3 lambda A4 / s, 4 lambda A5 / s,
   //   5 lambda A6 / s, 6 P / lambda, 7 Q / lambda   (s: surface layer)
@@ -839,23 +880,59 @@ struct Vertical {
   // the observer the z0-dependence is the product of the top-to-bottom
   // ratios of the cells above it; the cell the observer sits on uses the
   // derivative at its own top edge.
-  // large-lambda limit of lambda^2 A2 - 2 for the observer's own cell: every
-  // eta tends to lambda, so p_1 -> (s0 - s1) / (s0 + s1) and lambda^2 A2 ->
-  // 1 + p_1
+  // large-lambda limit of lambda^2 A2 - 2 for the observer on the top face
+  // of its own cell: every eta tends to lambda, so lambda^2 A2 -> 1 + p with
+  // p -> (s0 - s1) / (s0 + s1) when an interface lies at that face (s0 the
+  // layer above, e.g. the air at the surface) and p -> 0 when the cell's
+  // layer continues above it (a grid below the top of its layer)
   cx a6_inf() const {
-    const cx s0 = t->sigma[0], s1 = t->sigma[lay[0]];
+    const int n = lay[0];
+    const cx s1 = t->sigma[n];
+    const double top = t->z_edges[0], dn = t->d[n - 1];
+    const bool interface = std::fabs(top - dn) <= 1e-9 * (t->z_edges[nz] - top);
+    const cx s0 = interface ? t->sigma[n - 1] : s1;
     return (s0 - s1) / (s0 + s1) - 1.0;
   }
 
   void point_row(double lam, cx *out) const {
     std::vector<Cell> cell[2];
-    factors(lam, cell);
+    LayerFns lf;
+    factors(lam, cell, &lf);
     const cx iwm(0.0, omega * kMu0);
-    const cx so = t->sigma[lay[0]];
+    const cx so = t->sigma[lay_obs];
     cx R[2] = {1.0, 1.0}, Rd[2] = {0.0, 0.0};
+    const bool gap = !gap_lay.empty();
+    if (gap) {
+      // observer above the grid: U(z0, z*) = F(z0) G(z*) / W for every source
+      // cell, so each cell's functions at the top of the grid are carried up
+      // by F(z0) / F(top) (and F'(z0) / F(top) for the derivatives), the
+      // product of the ratios F(a) / F(b) over the pieces of the gap (F is
+      // continuous across interfaces; in a layer F(t) = e^{eta t} + p
+      // e^{-eta t} from the layer's top)
+      for (int k = 0; k < 2; ++k) {
+        for (size_t i = 0; i < gap_lay.size(); ++i) {
+          const int n = gap_lay[i];
+          const cx e = lf.eta[n], P = lf.p[k][n];
+          const double a = gap_ta[i], b = gap_tb[i];
+          const cx eh = std::exp(-e * (b - a));
+          const cx fa = 1.0 + P * std::exp(-2.0 * e * a), fb = 1.0 + P * std::exp(-2.0 * e * b);
+          const cx th = eh * fa / fb;
+          if (i == 0) Rd[k] = e * eh * (1.0 - P * std::exp(-2.0 * e * a)) / fb;
+          else Rd[k] *= th;
+          R[k] *= th;
+        }
+      }
+    }
     for (int jz = 0; jz < nz; ++jz) {
       cx A1, A2, dA1, A4, A5, A3;
-      if (jz == 0) {
+      if (gap) {
+        A1 = R[0] * cell[0][jz].GI;
+        A2 = R[1] * cell[1][jz].GI;
+        dA1 = Rd[0] * cell[0][jz].GI;
+        A4 = Rd[1] * cell[1][jz].GI;
+        A5 = R[1] * cell[1][jz].GD;
+        A3 = Rd[1] * cell[1][jz].GD;
+      } else if (jz == 0) {
         A1 = cell[0][0].GI;
         A2 = cell[1][0].GI;
         dA1 = cell[0][0].GId;
@@ -873,7 +950,7 @@ struct Vertical {
       // the observer's own cell: A6 tends to the constant a6_inf, whose
       // transform is a delta at the observer; it is taken out here and added
       // exactly to the own cell's G_zz (see compute_receiver_kernels)
-      const cx A6 = lam * lam * A2 - (jz == 0 ? 2.0 + a6_inf() : 0.0);
+      const cx A6 = lam * lam * A2 - ((jz == 0 && !gap) ? 2.0 + a6_inf() : 0.0);
       const cx Pv = -iwm * A1 + A3 / so;
       const cx Qv = dA1 + A5;
       out[0 * nz + jz] = lam * A1;
@@ -886,7 +963,7 @@ struct Vertical {
       out[7 * nz + jz] = Qv / lam;
       // ratios from the observer to the top of the next cell
       for (int k = 0; k < 2; ++k) {
-        Rd[k] = (jz == 0) ? cell[k][0].thetad : Rd[k] * cell[k][jz].theta;
+        Rd[k] = (jz == 0 && !gap) ? cell[k][0].thetad : Rd[k] * cell[k][jz].theta;
         R[k] *= cell[k][jz].theta;
       }
     }
@@ -972,12 +1049,12 @@ int compute_tables(giem_handle *t, hipStream_t s) {
   return GIEM_OK;
 }
 
-// Receiver kernels of every frequency: for receivers above cell centres at
+// Receiver kernels of one frequency: for receivers above cell centres at
 // lateral offset (di hx, dj hy) from a source cell of level jz, the cell
 // integrals of G^E and G^H, out[((dj + Ny - 1)(2 Nx - 1) + di + Nx - 1) nz +
-// jz][18] (E row-major, then H).  Receivers are at the earth's surface, the
-// top of the first cell.
-int compute_receiver_kernels(giem_handle *t, int ifreq, void **out, hipStream_t s) {
+// jz][18] (E row-major, then H).  Receivers are at depth z0 in the earth,
+// d[0] <= z0 <= top of the grid (the top itself: on the first cell's face).
+int compute_receiver_kernels(giem_handle *t, int ifreq, double z0, void **out, hipStream_t s) {
   const int nx = t->nx, ny = t->ny, nz = t->nz;
   const int nxo = 2 * nx - 1, nyo = 2 * ny - 1;
   const size_t noff = (size_t)nxo * nyo;
@@ -1007,6 +1084,8 @@ int compute_receiver_kernels(giem_handle *t, int ifreq, void **out, hipStream_t 
   }
   Vertical v;
   v.init(t, t->f[ifreq].freq);
+  v.set_observer(z0);
+  const bool touching = v.gap_lay.empty();
   std::vector<cx> G(nl * nf);
   parallel_for((int)nl, [&](int l) { v.point_row(g.lam.x[l], G.data() + (size_t)l * nf); });
   DevBuf dW, dWr, dM, dG, dH, dC;
@@ -1041,7 +1120,7 @@ int compute_receiver_kernels(giem_handle *t, int ifreq, void **out, hipStream_t 
                 "receiver kernel assembly") ||
       check_hip(hipStreamSynchronize(s), "receiver kernels"))
     rc = GIEM_EHIP;
-  if (rc == GIEM_OK) {
+  if (rc == GIEM_OK && touching) {
     // delta part of G_zz for the own cell (offset 0, level 0): the constant
     // a6_inf / s transforms to 2 pi a6_inf / s times the footprint's
     // indicator, i.e. a6_inf / (2 s) after the 1 / 4pi

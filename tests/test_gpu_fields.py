@@ -90,7 +90,7 @@ def test_fields_reject_receivers_off_centres(lib):
     with pytest.raises(lib.GiemError) as ex:
         h.fields(to_dev(m["sigma_a"]), E, np.array([[10.0, 60.0]]), Er, Er.clone())
     assert ex.value.code == lib.GIEM_EDOMAIN
-    # above a cell centre but below the surface
+    # above a cell centre but inside the grid (which starts at the surface)
     with pytest.raises(lib.GiemError) as ex:
         h.fields(to_dev(m["sigma_a"]), E, np.array([[50.0, 60.0, 20.0]]), Er, Er.clone())
     assert ex.value.code == lib.GIEM_EDOMAIN
