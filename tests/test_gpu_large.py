@@ -7,7 +7,11 @@ copy).  Only internal checks are possible at this size:
     exported table (gather block-product kernel, 352-point transforms with a
     radix-11 pass, 448-point transforms);
   - the precision form against the FP64 solve (both GMRES(60) to 1e-7);
-  - sigma_a = sigma_b (A = I) returns the normal field in one Arnoldi step."""
+  - sigma_a = sigma_b (A = I) returns the normal field in one Arnoldi step,
+    and the impedance at the surface (over the grid, which starts at 50 m)
+    is then the 1-D surface impedance of the background;
+  - apparent resistivity and phase along a surface profile across the blocks
+    (the quantity of the paper's maps), finite and positive."""
 import time
 
 import numpy as np
@@ -15,6 +19,7 @@ import pytest
 
 import giem_synth as gs
 from oracle import dense, normal_field, packed
+from oracle.fundamental import MU0
 from tests.gpu_util import rel_err, to_dev
 
 pytestmark = pytest.mark.gpu
@@ -74,6 +79,25 @@ def test_large_grid(lib):
     assert max(errs) <= 1e-5
     del E32
 
+    # surface profile across the blocks at y = 2.8 km: Z and rho_a, phase
+    w = 2 * np.pi * m["freq"]
+    sites = np.array([[(ix + 0.5) * m["hx"], (ny // 2 + 0.5) * m["hy"], 0.0]
+                      for ix in range(10, nx, 20)])
+    t1 = time.perf_counter()
+    Er = torch.empty((2, len(sites), 3), dtype=torch.complex128, device="cuda")
+    Hr = torch.empty_like(Er)
+    h.fields(sa, E64, sites, Er, Hr)
+    Z = torch.empty((len(sites), 2, 2), dtype=torch.complex128, device="cuda")
+    lib.impedance(Er, Hr, Z)
+    torch.cuda.synchronize()
+    z = Z.cpu().numpy()
+    rho = np.abs(z[:, 0, 1]) ** 2 / (w * MU0)
+    phase = np.degrees(np.angle(z[:, 0, 1]))
+    print(f"  surface profile (receiver kernels + fields {time.perf_counter() - t1:.1f} s): "
+          + ", ".join(f"{x / 1e3:.2f} km {r:.0f} ohm m {p:.0f} deg"
+                      for x, r, p in zip(sites[:, 0], rho, phase)), flush=True)
+    assert np.isfinite(z).all() and (rho > 0).all()
+
     # no anomaly: the normal field
     sb = m["sigma"][m["layer_of_cell"]][:, None, None] * np.ones(m["sigma_a"].shape)
     E64.zero_()
@@ -81,4 +105,12 @@ def test_large_grid(lib):
     en = normal_field.normal_field_cells(m)
     assert st["iters"] <= 1   # A = I: one Arnoldi step from x = 0
     assert rel_err(E64.cpu().numpy(), en) <= 1e-12
+    sb_d = to_dev(sb)
+    h.fields(sb_d, E64, sites, Er, Hr)
+    lib.impedance(Er, Hr, Z)
+    torch.cuda.synchronize()
+    zs = normal_field.LayeredPlaneWave(m["d"], m["sigma"], m["freq"]).Zs
+    z = Z.cpu().numpy()
+    assert np.abs(z[:, 0, 1] - zs).max() <= 1e-10 * abs(zs)
+    assert np.abs(z[:, 1, 0] + zs).max() <= 1e-10 * abs(zs)
     h.close()
