@@ -128,6 +128,7 @@ def counter_summary(dirs):
         alg[f"k_fft_x_fwd<{T}"] = b["fft_x"]
         alg[f"k_fft_y<{T}"] = (b["fft_y"] + b["ifft_y"]) / 2   # forward and inverse alike
         alg[f"k_block_pipe<{T}"] = alg[f"k_block_pipe1<{T}"] = b["block_product"]
+        alg[f"k_block_dbl<{T}"] = b["block_product"]
         alg[f"k_fft_x_inv<{T}"] = b["ifft_x"]
     gs_alg = {"k_dots": (sum(j + 2 for j in range(30)) * vec, 0),
               "k_update": (sum(j + 2 for j in range(30)) * vec, 30 * vec)}
@@ -313,9 +314,10 @@ def main():
     ap.add_argument("--counter-summary", nargs="+", metavar="DIR",
                     help="print the markdown summary of rocprofv3 --pmc runs of --counter-run "
                          "(their output directories) and exit")
-    ap.add_argument("--block-buffers", type=int, default=2,
-                    help="block-product variant in --counter-run (1 or 2 prefetch sets, 3 = two "
-                         "workgroups per CU; giem_tune chooses 2 for FP64 on this workload)")
+    ap.add_argument("--block-buffers", type=int, default=4,
+                    help="FP64 block-product variant in --counter-run (1 or 2 prefetch sets, 3 = "
+                         "two workgroups per CU, 4 = the next row staged into a second LDS "
+                         "buffer; giem_tune chooses 4 for FP64 on this workload)")
     args = ap.parse_args()
     if args.counter_summary:
         print(counter_summary(args.counter_summary))

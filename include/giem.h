@@ -267,8 +267,11 @@ int giem_set_fft_shape(giem_handle *t, uint32_t prec, const int32_t *shape);
    while a point is staged into local memory), 3 = two workgroups per CU,
    each wavefront doing a whole 16-row contraction (one workgroup's matrix
    products overlap the other's staging; where two do not fit the local data
-   share, 1 is used), 0 for the built-in choice (1).  Results agree to
-   rounding whichever variant runs.  Errors: EINVAL. */
+   share, 1 is used), 4 = the row of the next point written from registers
+   into a second local-memory buffer during the current point's matrix
+   products (Nz <= 32 and at most 2 right-hand sides in FP64, else 2 is
+   used), 0 for the built-in choice (1).  Results agree to rounding whichever
+   variant runs.  Errors: EINVAL. */
 int giem_set_block_buffers(giem_handle *t, uint32_t prec, int32_t nbuf);
 
 /* giem_profile_read -- wait for the last recorded apply and report what was

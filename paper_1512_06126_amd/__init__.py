@@ -250,7 +250,8 @@ class Handle:
 
     def set_block_buffers(self, prec, nbuf):
         """Variant of the block product: 1 or 2 prefetch sets in one
-        workgroup per CU, 3 = two workgroups per CU (0 = built-in, 1)."""
+        workgroup per CU, 3 = two workgroups per CU, 4 = the next point's row
+        staged into a second LDS buffer during the current point (0 = built-in, 1)."""
         _check(_lib.giem_set_block_buffers(self._p, prec, nbuf))
 
     def profile(self, enable=True, stage=None):

@@ -247,7 +247,7 @@ static int apply_core_t(giem_handle *t, int nf, const int *ifreqs, int nrhs,
   GIEM_HIP(launch_fft_y(prec, spa, 2 * nx, ny, rp, G[1], NT[1], t->py.d, twy, 0, s), "y-FFT");
   GIEM_TRY(mark(2));
   const int bv = t->block_nbuf[prec == PREC_FP32 ? 1 : 0];
-  const int nbuf = (bv == 2 || bv == 3) ? bv : 1;
+  const int nbuf = (bv >= 2 && bv <= 4) ? bv : 1;
   GIEM_HIP(launch_block(prec, tabs, nf, spa, spb, static_cast<const unsigned *>(t->bplan), nx,
                         ny, nz, nrhs, nbuf, s),
            "block product");
@@ -768,6 +768,7 @@ int giem_tune(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs, 
     cands.push_back({0, 0, 1});
     cands.push_back({0, 0, 2});
     if (block_two_per_cu(t->nz, nrhs, (int)prec)) cands.push_back({0, 0, 3});
+    if (block_dbl_supported(t->nz, nrhs, (int)prec)) cands.push_back({0, 0, 4});
     std::vector<std::array<double, 5>> med(cands.size());
     for (auto &m : med) m.fill(1e30);
     for (int round = 0; round < 2; ++round)
@@ -827,7 +828,7 @@ int giem_tune(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs, 
         chosen[(pi * 5 + k) * 2 + 1] = NT[k];
       }
       const int bv = t->block_nbuf[pi];
-      chosen[(pi * 5 + 4) * 2] = (bv == 2 || bv == 3) ? bv : 1;
+      chosen[(pi * 5 + 4) * 2] = (bv >= 2 && bv <= 4) ? bv : 1;
       chosen[(pi * 5 + 4) * 2 + 1] = 0;
     }
   }
@@ -860,8 +861,8 @@ int giem_set_fft_shape(giem_handle *t, uint32_t prec, const int32_t *shape) {
 }
 
 int giem_set_block_buffers(giem_handle *t, uint32_t prec, int32_t nbuf) {
-  if (!t || prec > PREC_FP32 || nbuf < 0 || nbuf > 3) {
-    set_error("giem_set_block_buffers: bad argument (0, 1, 2 or 3)");
+  if (!t || prec > PREC_FP32 || nbuf < 0 || nbuf > 4) {
+    set_error("giem_set_block_buffers: bad argument (0 to 4)");
     return GIEM_EINVAL;
   }
   t->block_nbuf[prec == PREC_FP32 ? 1 : 0] = nbuf;

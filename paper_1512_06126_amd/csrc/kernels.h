@@ -37,12 +37,15 @@ hipError_t launch_fft_x_inv(int prec, const VecPtrs32 &ptrs, const c128 *sd, con
 // record of the spectra holds nf R vectors, frequency f's at f R .. f R + R - 1.
 // nbuf: variant of the pipelined kernel: 1 or 2 register sets of prefetched
 // points (one workgroup per CU), 3: two workgroups per CU with one set each
-// (falls back to 1 where it does not fit, see block_two_per_cu)
+// (falls back to 1 where it does not fit, see block_two_per_cu), 4: the row of
+// the next point staged into a second LDS buffer during the current point's
+// MFMAs (falls back to 2, see block_dbl_supported)
 hipError_t launch_block(int prec, const TabSet &tabs, int nf, const void *sin, void *sout,
                         const unsigned *plan, int nx, int ny, int nz, int R, int nbuf,
                         hipStream_t s);
 std::vector<unsigned> block_plan(int nz);
 bool block_two_per_cu(int nz, int R, int prec);
+bool block_dbl_supported(int nz, int R, int prec);
 
 // table set-up (kernels_setup.hip)
 hipError_t launch_spectral_x(const c128 *spatial, c128 *tmp, const c128 *cs_x, int nx, int ny,

@@ -701,6 +701,212 @@ k_block_pipe(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict__
   }
 }
 
+// Double-buffered variant: the packed rows of two points live in LDS.  While
+// the wavefronts run the MFMAs of point p from one buffer, they write point
+// p + 1's row (loaded into registers during point p - 1) into the other one
+// and then issue the loads of point p + 2's row into the same registers, one
+// slot per k-step; the input vectors of point p + 1 are loaded at the start
+// of point p and staged after the barrier that starts point p + 1.  So the
+// staging of the row is off the path between two points' MFMAs, and a row's
+// loads have a whole point to arrive.  Needs two rows, the B rows and the
+// reduction buffer in LDS (FP64: Nz <= 32 with R <= 2).
+template <typename T, int NS, bool MF>
+__global__ void __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(3, 3)))
+k_block_dbl(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict__ sout, int nx,
+            int ny, int nz, int R, int nct, int nf) {
+  typedef Mfma<T> M;
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  constexpr int HS = NS / 2;  // k-steps per half
+  constexpr int kpad = 4 * NS;
+  static_assert(HS >= kStageRegs, "one row slot per k-step of the first half");
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int E = 2 * nz * (2 * nz + 1);
+  const int Es = E + 2 * nz;  // padded rows of the full blocks; entry Es is zero
+  const int QS = Es + 2;      // entries per row buffer
+  const int p3 = 3 * nz, tri = nz * (nz + 1) / 2;
+  const int nrt = (p3 + 15) >> 4;
+  v2 *Qb = reinterpret_cast<v2 *>(lds_raw);            // [2][QS]
+  T *Bs = reinterpret_cast<T *>(Qb + 2 * QS);           // [nct][kpad][16]
+  T *Red = Bs + (size_t)nct * kpad * 16;                // [nrt][4][64] partial sums
+  const int npts = (nx + 1) * (ny + 1);
+  const int ntask = MF ? nf * npts : npts;
+  const int rtot = MF ? nf * R : R;
+  const v2 *tab0 = reinterpret_cast<const v2 *>(tabs.tab[0]);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int kk0 = lane >> 4, j = lane & 15, part = j >> 3;
+  const int rt = wave % nrt, kh = wave / nrt;  // output tile, contraction half
+  const unsigned bmask = part ? 0u : 0x80000000u;
+  unsigned aoff[(HS + 1) / 2];
+  {
+    const int row = rt * 16 + (lane & 15);
+    const bool rowok = row < p3;
+    const int a = rowok ? row / nz : 0, iz = rowok ? row - a * nz : 0;
+#pragma unroll
+    for (int u = 0; u < HS; ++u) {
+      const int c = 4 * (kh * HS + u) + kk0;
+      unsigned w = (unsigned)Es;
+      if (rowok && c < p3) {
+        const int b = c / nz, jz = c - b * nz;
+        bool neg;
+        w = (unsigned)staged_index(a, iz, b, jz, nz, tri, neg) | (neg ? 0x8000u : 0u);
+      }
+      if (u & 1)
+        aoff[u >> 1] |= w << 16;
+      else
+        aoff[u >> 1] = w;
+    }
+  }
+  if (tid == 0) {
+    Qb[Es] = v2{(T)0, (T)0};
+    Qb[QS + Es] = v2{(T)0, (T)0};
+  }
+  const int nxe = nct * 8 * kpad;  // input-vector elements (c, v)
+  int tdst[kStageRegs];
+#pragma unroll
+  for (int u = 0; u < kStageRegs; ++u) {
+    const int e = tid + u * nthr;
+    tdst[u] = e < E ? staged_of_packed(e, nz, tri) : -1;
+  }
+  int xv_[kXRegs], xc_[kXRegs], xmi_[kXRegs], xr_[kXRegs], xb_[kXRegs], xdst_[kXRegs];
+#pragma unroll
+  for (int u = 0; u < kXRegs; ++u) {
+    const int idx = u * nthr + tid;
+    const int v = idx < nxe ? idx / kpad : 1 << 20, c = idx < nxe ? idx - v * kpad : 0;
+    xv_[u] = v;
+    xc_[u] = c < p3 ? c : 0;
+    xmi_[u] = idx < nxe ? v / R : 0;
+    xr_[u] = idx < nxe ? v - (v / R) * R : 0;
+    xb_[u] = c < p3 ? c / nz : 3;  // 3: padding row
+    xdst_[u] = idx < nxe ? ((v >> 3) * kpad + c) * 16 + (v & 7) : -1;
+  }
+  auto row_of = [&](int task_) __attribute__((always_inline)) {
+    const int f_ = MF ? task_ / npts : 0, rep_ = task_ - f_ * npts;
+    return (MF ? reinterpret_cast<const v2 *>(tabs.tab[f_]) : tab0) + (size_t)rep_ * E;
+  };
+  v2 pre[kStageRegs];
+  cplx<T> xpre[kXRegs];
+  unsigned xneg = 0, xval = 0;  // mirror sign / presence of each prefetched input element
+  auto load_x = [&](int task_) __attribute__((always_inline)) {
+    const int f_ = MF ? task_ / npts : 0, rep_ = task_ - f_ * npts;
+    const MirrorSet mm = mirror_set(rep_, nx, ny);
+    const int V = mm.n * R;
+    xneg = 0;
+    xval = 0;
+#pragma unroll
+    for (int u = 0; u < kXRegs; ++u) {
+      const bool ok = xv_[u] < V && xb_[u] < 3;
+      int pt;
+      bool fx, fy;
+      mirror_of(mm, ok ? xmi_[u] : 0, nx, ny, pt, fx, fy);
+      xpre[u] = sin[((size_t)pt * rtot + f_ * R + (ok ? xr_[u] : 0)) * p3 + xc_[u]];
+      if (ok && ((xb_[u] == 0 && fx) || (xb_[u] == 1 && fy))) xneg |= 1u << u;
+      if (ok) xval |= 1u << u;
+    }
+  };
+  int task = blockIdx.x;
+  // prologue: the first point's row into buffer 0, its input vectors and the
+  // second point's row into registers
+  {
+    const v2 *src = row_of(task);
+#pragma unroll
+    for (int u = 0; u < kStageRegs; ++u)
+      if (tdst[u] >= 0) pre[u] = src[tid + u * nthr];
+#pragma unroll
+    for (int u = 0; u < kStageRegs; ++u)
+      if (tdst[u] >= 0) Qb[tdst[u]] = pre[u];
+    load_x(task);
+    const int t1 = task + (int)gridDim.x;
+    const v2 *src1 = row_of(t1 < ntask ? t1 : task);
+#pragma unroll
+    for (int u = 0; u < kStageRegs; ++u)
+      if (tdst[u] >= 0) pre[u] = src1[tid + u * nthr];
+  }
+  int cur = 0;
+  for (; task < ntask; task += gridDim.x) {
+    const int f = MF ? task / npts : 0, rep = task - f * npts;
+    // every wavefront is done with the previous point (its MFMAs, Bs, Red),
+    // and this point's row, written during the previous point, is complete
+    lds_barrier();
+#pragma unroll
+    for (int u = 0; u < kXRegs; ++u) {
+      if (xdst_[u] >= 0) {
+        T *brow = Bs + xdst_[u];
+        const unsigned sm = ((xneg >> u) & 1u) ? 0x80000000u : 0u;
+        const bool ok = (xval >> u) & 1u;
+        brow[0] = ok ? flip_sign(xpre[u].x, sm) : (T)0;
+        brow[8] = ok ? flip_sign(xpre[u].y, sm) : (T)0;
+      }
+    }
+    const MirrorSet m = mirror_set(rep, nx, ny);
+    const int V = m.n * R;
+    const int ntk = task + (int)gridDim.x, ntk2 = ntk + (int)gridDim.x;
+    const bool more = ntk < ntask;
+    // the next point's input vectors (staged at its start) and the address of
+    // the row two points ahead (clamped past the last point)
+    load_x(more ? ntk : task);
+    const v2 *src2 = row_of(ntk2 < ntask ? ntk2 : (more ? ntk : task));
+    const v2 *Qv = Qb + cur * QS;
+    v2 *Qn = Qb + (cur ^ 1) * QS;
+    lds_barrier();
+    for (int ct = 0; ct * 8 < V; ++ct) {
+      typename M::acc_t accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+      const int kb = kh * HS * 4 + kk0;  // first B row of this half
+      const T *b1p = Bs + ((size_t)ct * kpad + kb) * 16 + j;
+      const T *b2p = Bs + ((size_t)ct * kpad + kb) * 16 + (j ^ 8);
+#pragma unroll
+      for (int u = 0; u < HS; ++u) {
+        const unsigned w = (u & 1) ? (aoff[u >> 1] >> 16) : (aoff[u >> 1] & 0xffffu);
+        const v2 q = Qv[w & 0x7fffu];
+        const unsigned qm = (w & 0x8000u) << 16;
+        const T b1 = b1p[u * 64];
+        const T b2 = flip_sign(b2p[u * 64], bmask);
+        accr = M::mma(flip_sign(q.x, qm), b1, accr);
+        acci = M::mma(flip_sign(q.y, qm), b2, acci);
+        if (ct == 0 && more && u < kStageRegs && tdst[u] >= 0) {
+          // slot u: the next point's entry into the other buffer (its reads
+          // by the previous point's MFMAs ended before the barriers above),
+          // then the load of the entry two points ahead into the freed
+          // register; one slot per k-step, so that the writes drain behind
+          // the MFMAs
+          Qn[tdst[u]] = pre[u];
+          pre[u] = src2[tid + u * nthr];
+        }
+        // keep each k-step's LDS traffic next to its MFMAs: hoisting it all
+        // ahead, on top of the row loads in flight, would exceed the
+        // registers of three wavefronts per SIMD
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (kh == 1) {
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) Red[(rt * 4 + qq) * 64 + lane] = accr[qq] + acci[qq];
+      }
+      lds_barrier();
+      if (kh == 0) {
+        const int v = ct * 8 + (j & 7);
+        if (v < V) {
+          const int mi = v / R, r = v - mi * R;
+          int pt;
+          bool fx, fy;
+          mirror_of(m, mi, nx, ny, pt, fx, fy);
+          T *ob = reinterpret_cast<T *>(sout + ((size_t)pt * rtot + f * R + r) * p3);
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq) {
+            const int orow = rt * 16 + M::row(lane, qq);
+            if (orow < p3) {
+              const int oa = orow / nz;
+              const T sg = ((oa == 0 && fx) || (oa == 1 && fy)) ? (T)-1 : (T)1;
+              ob[2 * orow + part] = sg * (accr[qq] + acci[qq] + Red[(rt * 4 + qq) * 64 + lane]);
+            }
+          }
+        }
+      }
+      lds_barrier();  // Red is reused by the next column tile
+    }
+    cur ^= 1;
+  }
+}
+
 static int lds_nct(int R) { return (4 * R + 7) / 8; }
 
 // k-steps rounded up to a multiple of 4 (the compiled variants)
@@ -717,6 +923,12 @@ static size_t lds_bytes_t(int nz, int R, size_t csize, int ks) {
 
 static const size_t kLdsLimit = 160 * 1024;
 
+// the double-buffered kernel: a second staged row on top of the KS = 2 layout
+static size_t lds_bytes_dbl(int nz, int R, size_t csize) {
+  const size_t Es = 2 * (size_t)nz * (2 * nz + 1) + 2 * nz;
+  return lds_bytes_t(nz, R, csize, 2) + (Es + 2) * csize;
+}
+
 // ks wavefronts (contraction parts) per 16-row tile
 static int lds_waves(int nz, int ks) { return ks * ((3 * nz + 15) / 16); }
 
@@ -731,6 +943,11 @@ static bool lds_fits(int nz, int R, size_t csize, int ks) {
   return lds_bytes_t(nz, R, csize, ks) <= lim && lds_ns(nz) / ks <= kMaxHalfSteps * (3 - ks) &&
          nthr <= 768 && E <= (long long)sr * nthr && nxe <= (long long)kXRegs * nthr &&
          E + 2 * nz + 1 < 0x8000;
+}
+
+static bool dbl_fits(int nz, int R, size_t csize) {
+  return lds_fits(nz, R, csize, 2) && lds_bytes_dbl(nz, R, csize) <= kLdsLimit &&
+         lds_ns(nz) / 2 >= kStageRegs && lds_nct(R) == 1;
 }
 
 #define GIEM_BLOCK_VARIANTS(X, T) \
@@ -756,6 +973,12 @@ hipError_t set_block_lds_limits() {
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);  \
   if (e == hipSuccess)                                                                     \
     e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_block_pipe<T, NS, 2, true>),   \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);  \
+  if (e == hipSuccess && NS / 2 >= kStageRegs)                                             \
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_block_dbl<T, (NS >= 12 ? NS : 12), false>), \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);  \
+  if (e == hipSuccess && NS / 2 >= kStageRegs)                                             \
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_block_dbl<T, (NS >= 12 ? NS : 12), true>), \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
   GIEM_BLOCK_VARIANTS(GIEM_SET_ATTR, double)
   GIEM_BLOCK_VARIANTS(GIEM_SET_ATTR, float)
@@ -784,9 +1007,10 @@ static hipError_t launch_block_t(const TabSet &tabs, int nf, const void *sin, vo
   const bool off32 = 4LL * nx * ny * nf * R * 3 * nz < (1LL << 31);
   const size_t cs = sizeof(cplx<T>);
   if (nbuf == 3 && !lds_fits(nz, R, cs, 1)) nbuf = 1;
+  if (nbuf == 4 && !dbl_fits(nz, R, cs)) nbuf = 2;
   const int ks = nbuf == 3 ? 1 : 2;
   if (lds_fits(nz, R, cs, ks) && off32) {
-    const size_t lds = lds_bytes_t(nz, R, cs, ks);
+    const size_t lds = nbuf == 4 ? lds_bytes_dbl(nz, R, cs) : lds_bytes_t(nz, R, cs, ks);
     const int nthr = 64 * lds_waves(nz, ks);
     // persistent grid: one workgroup per CU (two for ks = 1); more
     // workgroups per CU at small Nz measured slower (a larger tail round)
@@ -794,7 +1018,11 @@ static hipError_t launch_block_t(const TabSet &tabs, int nf, const void *sin, vo
     const long long grid = ntask < cap ? ntask : cap;
     const int ns = lds_ns(nz);
 #define GIEM_LAUNCH_MF(TT, NS, MF)                                                        \
-  if (nbuf == 2)                                                                          \
+  if (nbuf == 4)                                                                          \
+    k_block_dbl<TT, (NS >= 12 ? NS : 12), MF><<<(unsigned)grid, nthr, lds, s>>>(           \
+        tabs, static_cast<const cplx<TT> *>(sin), static_cast<cplx<TT> *>(sout), nx, ny,   \
+        nz, R, lds_nct(R), nf);                                                           \
+  else if (nbuf == 2)                                                                     \
     k_block_pipe<TT, NS, 2, MF><<<(unsigned)grid, nthr, lds, s>>>(                         \
         tabs, static_cast<const cplx<TT> *>(sin), static_cast<cplx<TT> *>(sout), nx, ny,   \
         nz, R, lds_nct(R), nf);                                                           \
@@ -831,6 +1059,10 @@ static hipError_t launch_block_t(const TabSet &tabs, int nf, const void *sin, vo
 
 bool block_two_per_cu(int nz, int R, int prec) {
   return lds_fits(nz, R, prec == PREC_FP32 ? sizeof(c64) : sizeof(c128), 1);
+}
+
+bool block_dbl_supported(int nz, int R, int prec) {
+  return dbl_fits(nz, R, prec == PREC_FP32 ? sizeof(c64) : sizeof(c128));
 }
 
 hipError_t launch_block(int prec, const TabSet &tabs, int nf, const void *sin, void *sout,

@@ -150,7 +150,7 @@ def full_case():
     return m, t, x, qnn, cells
 
 
-@pytest.mark.parametrize("nbuf", [1, 2, 3])
+@pytest.mark.parametrize("nbuf", [1, 2, 3, 4])
 @pytest.mark.parametrize("mode,prec,tol", [("A", 0, 1e-10), ("B", 0, 1e-10), ("AT", 0, 1e-10),
                                            ("B", 1, 1e-4)])
 def test_apply_full_size_sampled(lib, full_case, mode, prec, tol, nbuf):
@@ -209,7 +209,7 @@ def test_every_fft_shape_matches_dense(lib, nx, ny, nz, nrhs):
                 first[(g, nt)] = yd.clone()
                 tried += 1
         h.set_fft_shape(prec, None)
-        for nbuf in (3, 2, 1):
+        for nbuf in (4, 3, 2, 1):
             h.set_block_buffers(prec, nbuf)
             h.apply(xd, yd, sa, mode=lib.MODE_A, prec=prec)
             torch.cuda.synchronize()
@@ -245,7 +245,7 @@ def test_block_product_every_rhs_count_at_deepest_grids(lib, nz):
         xd = to_dev(x[:nrhs])
         yd = torch.empty_like(xd)
         for prec, tol in ((lib.FP64, 1e-10), (lib.FP32, 2e-5)):
-            for nbuf in (1, 2, 3):
+            for nbuf in (1, 2, 3, 4):
                 h.set_block_buffers(prec, nbuf)
                 h.apply(xd, yd, sa, mode=lib.MODE_A, prec=prec)
                 torch.cuda.synchronize()

@@ -69,7 +69,7 @@ def test_apply_batch_equals_separate(lib, prec):
     x = np.stack([gs.random_vector(rng, nrhs, nz, ny, nx) for _ in ifreqs])
     xd = to_dev(x)
     sa = to_dev(m["sigma_a"])
-    for nbuf in (1, 2, 3):
+    for nbuf in (1, 2, 3, 4):
         h.set_block_buffers(p, nbuf)
         for mode in (lib.MODE_A, lib.MODE_AT, lib.MODE_B):
             yb = torch.empty_like(xd)
