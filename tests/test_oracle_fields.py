@@ -85,10 +85,12 @@ def test_half_space_impedance():
     assert abs(Z[0, 1] - zc) <= 1e-12 * abs(zc) and abs(Z[1, 0] + zc) <= 1e-12 * abs(zc)
 
 
-def test_receiver_kernels_whole_space_at_depth():
+@pytest.mark.parametrize("z0", [25.0, 170.0])
+def test_receiver_kernels_whole_space_at_depth(z0):
     # receivers inside the earth above the anomaly grid (z0 = 25 m, grid from
-    # 50 m): the cell integrals of G^E and G^H against the closed form
-    sig, f, z0 = 0.02, 3.0, 25.0
+    # 50 m to 140 m) and below it (170 m): the cell integrals of G^E and G^H
+    # against the closed form
+    sig, f = 0.02, 3.0
     m = dict(nx=3, ny=3, nz=2, hx=100.0, hy=120.0, z_edges=np.array([50.0, 90.0, 140.0]),
              d=np.array([0.0]), sigma=np.array([sig, sig], complex), freq=f)
     offs = np.array([[0.0, 0.0], [100.0, 0.0], [0.0, 120.0], [230.0, -70.0]])
@@ -97,7 +99,7 @@ def test_receiver_kernels_whole_space_at_depth():
         for jz in range(2):
             lo = [-50.0, -60.0, m["z_edges"][jz]]
             hi = [50.0, 60.0, m["z_edges"][jz + 1]]
-            # 25 m above a 100 m face the closed form's Gauss rule needs 48
+            # 25-30 m from a 100 m face the closed form's Gauss rule needs 48
             # points per axis to reach 1e-12
             E, H = wholespace.point_box([dx, dy, z0], lo, hi, sig, f, q=48)
             assert np.abs(KE[k, jz] - E).max() <= 1e-8 * np.abs(E).max()
@@ -147,14 +149,15 @@ def _dipole_response(m, B, src, comps, rec, z0, transpose=True):
     return e[:, 0]
 
 
-@pytest.mark.parametrize("z0,comps", [(25.0, (0, 1, 2)), (0.0, (0, 1))])
+@pytest.mark.parametrize("z0,comps", [(25.0, (0, 1, 2)), (0.0, (0, 1)), (170.0, (0, 1, 2))])
 def test_dipole_source_reciprocity(z0, comps):
     # the anomalous response of the discretised problem is reciprocal:
     # E^a_i(A; unit dipole j at B) = E^a_j(B; unit dipole i at A), for sources
     # and receivers on the lattice above the grid (z0 = 25 m over a grid from
     # 50 m: every component; at the surface of an insulating air the vertical
-    # ones are earth-side values and only the horizontal ones are compared);
-    # the untransposed kernel breaks it
+    # ones are earth-side values and only the horizontal ones are compared;
+    # z0 = 170 m below the grid, in the second layer: every component); the
+    # untransposed kernel breaks it
     from oracle import tables
     rng = np.random.default_rng(77)
     nx, ny, nz = 3, 3, 2
