@@ -377,7 +377,7 @@ int giem_adjoint(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrh
 
 /*
  * giem_fields -- electric and magnetic fields at receivers in the earth
- * above the anomaly grid from the cell field (Sect. 2.2, the representation
+ * above or below the anomaly grid from the cell field (Sect. 2.2, the representation
  * of the fields through G^E and G^H integrated over the cells, which holds
  * for any observation point; Appendix A):
  *   e(r) = E^N(r) + sum_n (sa_n - sb_n) [int_{cell n} G^E(r, M0) dM0] E_n,
@@ -391,15 +391,16 @@ int giem_adjoint(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrh
  *            down; all receivers of a call at one depth z0 with
  *            d[0] <= z0 <= z_edges[0] (the earth's surface, any depth in
  *            the earth above the grid, or the top face of the grid's first
- *            cells), each above the centre of a cell of the grid;
+ *            cells) or z0 > z_edges[Nz] (below the grid), each above or
+ *            below the centre of a cell of the grid;
  *   E_rec, H_rec: device c128 [nrhs][nrec][3] outputs.
  * E^N, H^N at depth z0 of the plane wave of 1 V/m at the surface are added
  * for RHS 0 (x polarisation) and RHS 1 (y polarisation); further RHS get the
  * anomalous fields only (giem_fields_anomalous: none added, for any source).
  * The cell integrals for every receiver offset are computed on the first
  * call for a frequency and depth and kept on the handle.  Synchronises the
- * stream.  Errors: EINVAL, EDOMAIN (receivers not at one depth in that range
- * or not above cell centres), ENOMEM, EHIP.
+ * stream.  Errors: EINVAL, EDOMAIN (receivers not at one depth in those
+ * ranges or not over cell centres), ENOMEM, EHIP.
  */
 int giem_fields(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrhs,
                 const void *E_cells, int32_t nrec, const double *rec_xyz, void *E_rec,
@@ -423,8 +424,8 @@ int giem_fields_anomalous(giem_handle *t, int32_t ifreq, const void *sigma_a, in
  * the dipole's normal field is the transposed receiver kernel of a receiver
  * at the source point: int_{cell n} E^0 = [int_{cell n} G^E(r_s, M0) dM0]^T p.
  *   src_xyz: host [nsrc][3] source positions, 1 <= nsrc <= 8, with the
- *            constraints of giem_fields' receivers (one depth z0 with
- *            d[0] <= z0 <= z_edges[0], above cell centres);
+ *            constraints of giem_fields' receivers (one depth z0 above
+ *            or below the grid, over or under cell centres);
  *   moments: host c128 [nsrc][3] dipole moments p (A m);
  *   rhs:     device c128 [nsrc][3][Nz][Ny][Nx] output, one right-hand side
  *            per source, to be passed as giem_solve's rhs; the solve gives

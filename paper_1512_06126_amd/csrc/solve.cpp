@@ -1559,18 +1559,20 @@ int giem_adjoint(giem_handle *t, int32_t ifreq, const void *sigma_a, int32_t nrh
 namespace giem {
 
 // Lattice indices of receivers (or dipole sources) rec_xyz [nrec][3] above
-// cell centres at one common depth z0 in the earth, d[0] <= z0 <= the top of
-// the grid (on the first cells' top face, or above the grid); EDOMAIN
-// otherwise.
+// (or below) cell centres at one common depth z0 in the earth, d[0] <= z0 <=
+// the top of the grid (on the first cells' top face, or above the grid), or
+// z0 below the grid's bottom; EDOMAIN otherwise.
 static int receiver_indices(const giem_handle *t, int nrec, const double *rec_xyz,
                             std::vector<int> &idx, double &z0, const char *who) {
   const double zscale = std::max(t->z_edges[t->nz] - t->d[0], t->z_edges[t->nz] - t->z_edges[0]);
   const double tol = 1e-9 * zscale;
   idx.assign(2 * (size_t)nrec, 0);
   z0 = nrec > 0 ? rec_xyz[2] : t->z_edges[0];
-  if (!(z0 >= t->d[0] - tol && z0 <= t->z_edges[0] + tol)) {
+  const bool above = z0 >= t->d[0] - tol && z0 <= t->z_edges[0] + tol;
+  const bool below = z0 > t->z_edges[t->nz] + tol;
+  if (!above && !below) {
     set_error(std::string(who) + ": points must lie in the earth at or above the top of the "
-              "anomaly grid (d[0] <= z <= top of the grid)");
+              "anomaly grid (d[0] <= z <= top of the grid) or below its bottom");
     return GIEM_EDOMAIN;
   }
   if (std::fabs(z0 - t->z_edges[0]) <= tol) z0 = t->z_edges[0];

@@ -668,8 +668,10 @@ struct Vertical {
   // point observer (receiver kernels) at depth z0 in the earth, at or above
   // the top of the grid: the gap [z0, top of the grid] split at interfaces
   // into pieces (layer, local top, local bottom); empty when z0 is the top
+  // (or below the grid: the gap [bottom of the grid, z0])
   double z0 = 0.0;
   int lay_obs = 1;
+  bool below = false;
   std::vector<int> gap_lay;
   std::vector<double> gap_ta, gap_tb;
   void set_observer(double z) {
@@ -677,17 +679,19 @@ struct Vertical {
     gap_lay.clear();
     gap_ta.clear();
     gap_tb.clear();
-    const double top = t->z_edges[0];
+    const double top = t->z_edges[0], bot = t->z_edges[nz];
     auto layer_at = [&](double zz) {  // layer holding depth zz from below
       int n = 1;
       while (n < t->nlay && t->d[n] <= zz) ++n;
       return n;
     };
-    lay_obs = z0 < top ? layer_at(z0) : lay.empty() ? 1 : lay[0];
-    double a = z0;
-    while (a < top) {
+    below = z0 > bot;
+    lay_obs = (z0 < top || below) ? layer_at(z0) : lay.empty() ? 1 : lay[0];
+    double a = below ? bot : z0;
+    const double end = below ? z0 : top;
+    while (a < end) {
       const int n = layer_at(a);
-      const double b = (n < t->nlay) ? std::min(top, t->d[n]) : top;
+      const double b = (n < t->nlay) ? std::min(end, t->d[n]) : end;
       gap_lay.push_back(n);
       gap_ta.push_back(a - t->d[n - 1]);
       gap_tb.push_back(b - t->d[n - 1]);
@@ -721,7 +725,8 @@ struct Vertical {
 
   // eta and the downward coefficients p of every layer (kind 0 and 1)
   struct LayerFns {
-    std::vector<cx> eta, p[2];
+    std::vector<cx> eta, p[2], q[2];
+    std::vector<double> L;
   };
 
   void factors(double lam, std::vector<Cell> (&cell)[2], LayerFns *lf = nullptr) const {
@@ -755,8 +760,11 @@ struct Vertical {
     }
     if (lf) {
       lf->eta = eta;
-      lf->p[0] = p[0];
-      lf->p[1] = p[1];
+      lf->L = L;
+      for (int k = 0; k < 2; ++k) {
+        lf->p[k] = p[k];
+        lf->q[k] = q[k];
+      }
     }
     for (int k = 0; k < 2; ++k) {
       cell[k].resize(nz);
@@ -901,6 +909,55 @@ struct Vertical {
     const cx iwm(0.0, omega * kMu0);
     const cx so = t->sigma[lay_obs];
     cx R[2] = {1.0, 1.0}, Rd[2] = {0.0, 0.0};
+    if (below) {
+      // observer below the grid, source cell above it: U(z0, z*) = F(z*)
+      // G(z0) / (eta D) of the observer's layer (for the sigma kind times
+      // sigma_obs / sigma_source, the reciprocity sigma_s U(z, z*) =
+      // sigma_r U(z*, z)).  With Rb = F(bottom of the cell) / F(z0), the
+      // product of the ratios F(a) / F(b) over the cells below it and the
+      // gap, int_cell U(z0, z*) dz* = FI Rb U0 and U(z0, bottom) - U(z0,
+      // top) = FD Rb U0, with U0 = F(z0) G(z0) / (eta D) (and F(z0) G'(z0)
+      // / (eta D) for the z0-derivatives) in the observer's layer.
+      const int n0 = lay_obs;
+      const double t0 = z0 - t->d[n0 - 1];
+      const bool half = !std::isfinite(lf.L[n0]);
+      cx U0[2], U0d[2], Rb[2] = {1.0, 1.0};
+      for (int k = 0; k < 2; ++k) {
+        const cx e = lf.eta[n0], P = lf.p[k][n0], Q = lf.q[k][n0];
+        const cx fa0 = 1.0 + P * std::exp(-2.0 * e * t0);
+        const cx qq = half ? cx(0.0) : Q * std::exp(-2.0 * e * (lf.L[n0] - t0));
+        const cx D = half ? cx(1.0) : 1.0 - P * Q * std::exp(-2.0 * e * lf.L[n0]);
+        U0[k] = fa0 * (1.0 + qq) / (e * D);
+        U0d[k] = -fa0 * (1.0 - qq) / D;
+        for (size_t i = 0; i < gap_lay.size(); ++i) {
+          const int n = gap_lay[i];
+          const cx en = lf.eta[n], Pn = lf.p[k][n];
+          const double a = gap_ta[i], b = gap_tb[i];
+          Rb[k] *= std::exp(-en * (b - a)) * (1.0 + Pn * std::exp(-2.0 * en * a)) /
+                   (1.0 + Pn * std::exp(-2.0 * en * b));
+        }
+      }
+      for (int jz = nz - 1; jz >= 0; --jz) {
+        const cx ss = so / t->sigma[lay[jz]];  // sigma_obs / sigma_source
+        const cx A1 = cell[0][jz].FI * Rb[0] * U0[0];
+        const cx dA1 = cell[0][jz].FI * Rb[0] * U0d[0];
+        const cx A2 = ss * cell[1][jz].FI * Rb[1] * U0[1];
+        const cx A4 = ss * cell[1][jz].FI * Rb[1] * U0d[1];
+        const cx A5 = ss * cell[1][jz].FD * Rb[1] * U0[1];
+        const cx A3 = ss * cell[1][jz].FD * Rb[1] * U0d[1];
+        const cx A6 = lam * lam * A2;
+        out[0 * nz + jz] = lam * A1;
+        out[1 * nz + jz] = lam * A2;
+        out[2 * nz + jz] = lam * dA1;
+        out[3 * nz + jz] = lam * A4 / so;
+        out[4 * nz + jz] = lam * A5 / so;
+        out[5 * nz + jz] = lam * A6 / so;
+        out[6 * nz + jz] = (-iwm * A1 + A3 / so) / lam;
+        out[7 * nz + jz] = (dA1 + A5) / lam;
+        for (int k = 0; k < 2; ++k) Rb[k] *= cell[k][jz].theta;
+      }
+      return;
+    }
     const bool gap = !gap_lay.empty();
     if (gap) {
       // observer above the grid: U(z0, z*) = F(z0) G(z*) / W for every source
@@ -1053,7 +1110,8 @@ int compute_tables(giem_handle *t, hipStream_t s) {
 // lateral offset (di hx, dj hy) from a source cell of level jz, the cell
 // integrals of G^E and G^H, out[((dj + Ny - 1)(2 Nx - 1) + di + Nx - 1) nz +
 // jz][18] (E row-major, then H).  Receivers are at depth z0 in the earth,
-// d[0] <= z0 <= top of the grid (the top itself: on the first cell's face).
+// d[0] <= z0 <= top of the grid (the top itself: on the first cell's face),
+// or below the grid (z0 > its bottom).
 int compute_receiver_kernels(giem_handle *t, int ifreq, double z0, void **out, hipStream_t s) {
   const int nx = t->nx, ny = t->ny, nz = t->nz;
   const int nxo = 2 * nx - 1, nyo = 2 * ny - 1;

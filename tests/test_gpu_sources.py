@@ -1,4 +1,4 @@
-"""Receivers in the earth above the anomaly grid and electric dipole sources
+"""Receivers in the earth above or below the anomaly grid and electric dipole sources
 (Sect. 2.1, an external current as the source; Sect. 2.2, the field
 representation through the cell integrals of G^E and G^H; Appendix A, the
 reciprocity G^E(r, r') = G^E(r', r)^T), through the C ABI: against the
@@ -28,10 +28,11 @@ def _lattice(m):
                      for iy in range(m["ny"]) for ix in range(m["nx"])])
 
 
-@pytest.mark.parametrize("z0", [0.0, 25.0, 50.0])
+@pytest.mark.parametrize("z0", [0.0, 25.0, 50.0, 170.0])
 def test_fields_at_depth_match_oracle(lib, z0):
-    # the surface above a buried grid, a depth between them, and the grid's
-    # top face; normal fields of the plane wave at z0 included
+    # the surface above a buried grid, a depth between them, the grid's top
+    # face, and 30 m below the grid; normal fields of the plane wave at z0
+    # included
     import torch
     m, rng = _buried(31)
     nx, ny, nz = m["nx"], m["ny"], m["nz"]
@@ -58,7 +59,7 @@ def test_fields_at_depth_match_oracle(lib, z0):
     assert ce <= 1e-8 and ch <= 1e-8 and ca <= 1e-8
 
 
-@pytest.mark.parametrize("z0", [0.0, 25.0])
+@pytest.mark.parametrize("z0", [0.0, 25.0, 170.0])
 def test_dipole_source_matches_oracle(lib, z0):
     import torch
     m, rng = _buried(32)
@@ -78,13 +79,14 @@ def test_dipole_source_matches_oracle(lib, z0):
     assert err <= 1e-9 and ce <= 1e-8
 
 
-def test_dipole_source_reciprocity(lib):
+@pytest.mark.parametrize("z0", [25.0, 170.0])
+def test_dipole_source_reciprocity(lib, z0):
     # solve with dipole sources at A and at B (unit moments along x, y, z),
     # anomalous fields at the other point: E^a_i(A; j at B) = E^a_j(B; i at A)
+    # (above the grid and below it)
     import torch
     m, rng = _buried(33, nx=8, ny=6, freq=2.0)
     nx, ny, nz = m["nx"], m["ny"], m["nz"]
-    z0 = 25.0
     A = np.array([[150.0, 180.0, z0]])
     B = np.array([[650.0, 540.0, z0]])
     h = lib.tables(m, [m["freq"]])
@@ -120,6 +122,7 @@ def test_receivers_and_sources_rejected_outside_the_supported_set(lib):
     Er = torch.empty((1, 2, 3), dtype=torch.complex128, device="cuda")
     for bad in ([[50.0, 60.0, 0.0], [150.0, 60.0, 10.0]],     # two depths
                 [[50.0, 60.0, 70.0], [150.0, 60.0, 70.0]],     # inside the grid
+                [[50.0, 60.0, 140.0], [150.0, 60.0, 140.0]],   # on its bottom face
                 [[50.0, 60.0, -5.0], [150.0, 60.0, -5.0]]):    # in the air
         with pytest.raises(lib.GiemError) as ex:
             h.fields(sa, E, np.array(bad), Er, Er.clone())
