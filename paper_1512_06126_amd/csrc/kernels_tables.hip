@@ -2,9 +2,13 @@
 // Appendix A horizontal integrals): a real FP64 GEMM used for
 //   (1) the lambda -> rho Hankel contraction  H = W G   (W geometry only),
 //   (2) the rho -> offset spatial contraction B_k = M_k H (M_k geometry only),
-// and the kernel that forms the nine tensor components from the contracted
-// blocks and writes the packed storage of Sect. 3.1.
+// the kernel that forms the nine tensor components from the contracted
+// blocks and writes the packed storage of Sect. 3.1, and the lambda functions
+// of the vertical integrals (Appendix B), one lambda node per thread for the
+// layer recursions, one cell per thread for the cell factors and one depth
+// level per thread for the rows of the products over the cells between.
 #include "kernels.h"
+#include "vertical.h"
 
 namespace giem {
 
@@ -318,7 +322,60 @@ k_fields_adjoint(const c128 *__restrict__ K, const c128 *__restrict__ E,
   grad[n] += gsum;
 }
 
+// p/q recursions of every lambda node: eta, L, p, q of lambda l at l (nlay + 1)
+// (p and q: both kinds, 2 (nlay + 1) per node)
+__global__ __launch_bounds__(256) void k_vert_layers(vert::Model m, const double *__restrict__ lam,
+                                                     int nl, vert::zc *eta, double *L,
+                                                     vert::zc *p, vert::zc *q) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= nl) return;
+  const int nlayers = m.nlay + 1;
+  vert::layer_fns(lam[l], m, eta + (size_t)l * nlayers, L + (size_t)l * nlayers,
+                  p + (size_t)2 * l * nlayers, q + (size_t)2 * l * nlayers);
+}
+
+// factors of cell c, kind k, lambda l at cells[(l 2 + k) nz + c]
+__global__ __launch_bounds__(256) void k_vert_cells(vert::Model m, int nl,
+                                                    const vert::zc *__restrict__ eta,
+                                                    const double *__restrict__ L,
+                                                    const vert::zc *__restrict__ p,
+                                                    const vert::zc *__restrict__ q,
+                                                    vert::Cell *cells) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)nl * 2 * m.nz) return;
+  const int l = (int)(idx / (2 * m.nz)), k = (int)(idx / m.nz) % 2, c = (int)(idx % m.nz);
+  const int nlayers = m.nlay + 1;
+  vert::cell_factors(c, k, m, eta + (size_t)l * nlayers, L + (size_t)l * nlayers,
+                     p + (size_t)2 * l * nlayers, q + (size_t)2 * l * nlayers, cells[idx]);
+}
+
+// row i of the lambda functions of node l into G[l][ncolc]
+__global__ __launch_bounds__(256) void k_vert_rows(vert::Model m, const double *__restrict__ lam,
+                                                   int nl, const vert::Cell *__restrict__ cells,
+                                                   vert::zc *G, int ncolc) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)nl * m.nz) return;
+  const int l = (int)(idx / m.nz), i = (int)(idx % m.nz);
+  const vert::Cell *c0 = cells + (size_t)l * 2 * m.nz;
+  vert::table_row(i, lam[l], m, c0, c0 + m.nz, G + (size_t)l * ncolc);
+}
+
 }  // namespace
+
+hipError_t launch_vertical_rows(const vert::Model &m, const double *lam, int nl, vert::zc *eta,
+                                double *L, vert::zc *p, vert::zc *q, vert::Cell *cells,
+                                vert::zc *G, int ncolc, hipStream_t s) {
+  if (nl <= 0 || m.nz <= 0) return hipSuccess;
+  const int64_t ncell = (int64_t)nl * 2 * m.nz, nrow = (int64_t)nl * m.nz;
+  if ((ncell + 255) / 256 > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_vert_layers, dim3((nl + 255) / 256), dim3(256), 0, s, m, lam, nl, eta, L, p,
+                     q);
+  hipLaunchKernelGGL(k_vert_cells, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, s, m, nl,
+                     eta, L, p, q, cells);
+  hipLaunchKernelGGL(k_vert_rows, dim3((unsigned)((nrow + 255) / 256)), dim3(256), 0, s, m, lam,
+                     nl, cells, G, ncolc);
+  return hipGetLastError();
+}
 
 hipError_t launch_impedance(const c128 *E, const c128 *H, int nrec, c128 *Z, hipStream_t s) {
   if (nrec <= 0) return hipSuccess;

@@ -44,6 +44,7 @@
 #include <vector>
 
 #include "handle.h"
+#include "vertical.h"
 
 namespace giem {
 
@@ -53,6 +54,9 @@ hipError_t launch_assemble(const c128 *c0, const c128 *c1, const c128 *c2, c128 
                            int ny, int nz, double omega_mu0, hipStream_t s);
 hipError_t launch_assemble_rec(const c128 *c, c128 *out, int noff, int nz, double omega_mu0,
                                hipStream_t s);
+hipError_t launch_vertical_rows(const vert::Model &m, const double *lam, int nl, vert::zc *eta,
+                                double *L, vert::zc *p, vert::zc *q, vert::Cell *cells,
+                                vert::zc *G, int ncolc, hipStream_t s);
 
 namespace {
 
@@ -619,52 +623,22 @@ static void receiver_rule(int kind, double dx, double dy, double hx, double hy, 
 // ----------------------------------------------------- vertical functions
 typedef std::complex<double> cx;
 
-// Functions of x = eta h (Re x >= 0) that cancel for small |x|, by their
-// power series there:
-//   eps(x) = (1 - e^-x) / x       = sum_m (-x)^m / (m+1)!
-//   phi(x) = (x - 1 + e^-x) / x^2 = sum_m (-x)^m / (m+2)!
-//   psi(x) = (e^x - 1 - x) / x^2  = sum_m   x^m / (m+2)!
-inline cx series(cx x, int shift, bool alternate) {
-  cx s = 0.0, term = 1.0;
-  double fact = 1.0;
-  for (int q = 2; q <= shift; ++q) fact *= q;
-  for (int m = 0; m < 24; ++m) {
-    s += term / fact;
-    term *= alternate ? -x : x;
-    fact *= (m + 1 + shift);
-  }
-  return s;
-}
-inline cx f_eps(cx x) { return std::abs(x) < 0.5 ? series(x, 1, true) : (1.0 - std::exp(-x)) / x; }
-inline cx f_phi(cx x) {
-  return std::abs(x) < 0.5 ? series(x, 2, true) : (x - 1.0 + std::exp(-x)) / (x * x);
-}
-// damp psi(x) and damp (e^x - 1) with damp = e^{-2 eta L}, L >= h (no
-// overflow for large x: damp e^x = e^{x - 2 eta L})
-inline cx f_psi_damped(cx x, cx damp, cx e_x_damped) {
-  if (std::abs(x) < 0.5) return damp * series(x, 2, false);
-  return (e_x_damped - damp * (1.0 + x)) / (x * x);
-}
-inline cx f_expm1_damped(cx x, cx damp, cx e_x_damped) {
-  if (std::abs(x) < 0.5) return damp * x * series(x, 1, false);
-  return e_x_damped - damp;
-}
-
 struct Layering {
   int nlay;                   // number of interfaces
   std::vector<double> d;      // [nlay]
   std::vector<cx> sigma;      // [nlay + 1]
 };
 
-// Per-lambda vertical functions written into the four column groups of one
-// row of G: [P / lambda (T) | lambda A1 (T) | lambda A6 / sigma (T) |
-// lambda A4 / sigma (nz^2)].
+// The layered model seen from the depth cells (and from a point observer for
+// the receiver kernels), with the per-lambda cell factors of the vertical
+// functions.
 struct Vertical {
   const giem_handle *t;
   double omega;
   int nz;
   std::vector<int> lay;          // layer of each cell
   std::vector<double> ta, tb;    // local coordinates of the cell edges
+  std::vector<vert::zc> sig;     // layer conductivities [nlay + 1]
   // point observer (receiver kernels) at depth z0 in the earth, at or above
   // the top of the grid: the gap [z0, top of the grid] split at interfaces
   // into pieces (layer, local top, local bottom); empty when z0 is the top
@@ -705,6 +679,8 @@ struct Vertical {
     lay.resize(nz);
     ta.resize(nz);
     tb.resize(nz);
+    sig.resize(h->sigma.size());
+    for (size_t n = 0; n < sig.size(); ++n) sig[n] = vert::Z(h->sigma[n].real(), h->sigma[n].imag());
     for (int l = 0; l < nz; ++l) {
       const int n = h->layer_of_cell[l];
       lay[l] = n;
@@ -729,148 +705,58 @@ struct Vertical {
     std::vector<double> L;
   };
 
+  // the layered model in the form of the shared vertical functions
+  vert::Model model() const {
+    vert::Model m;
+    m.nz = nz;
+    m.nlay = t->nlay;
+    m.omega_mu0 = omega * kMu0;
+    m.sigma = sig.data();
+    m.d = t->d.data();
+    m.lay = lay.data();
+    m.ta = ta.data();
+    m.tb = tb.data();
+    return m;
+  }
+
   void factors(double lam, std::vector<Cell> (&cell)[2], LayerFns *lf = nullptr) const {
-    const int nl = t->nlay;
-    const int nlayers = nl + 1;
-    std::vector<cx> eta(nlayers);
+    const int nlayers = t->nlay + 1;
+    const vert::Model m = model();
+    std::vector<vert::zc> eta(nlayers), p(2 * nlayers), q(2 * nlayers);
     std::vector<double> L(nlayers);
-    for (int n = 0; n < nlayers; ++n) {
-      cx e = std::sqrt(cx(lam * lam, 0.0) - cx(0.0, omega * kMu0) * t->sigma[n]);
-      if (e.real() < 0) e = -e;
-      eta[n] = e;
-      L[n] = (n >= 1 && n < nl) ? t->d[n] - t->d[n - 1] : INFINITY;
-    }
-    std::vector<cx> p[2], q[2];
-    for (int k = 0; k < 2; ++k) {
-      p[k].assign(nlayers, 0.0);
-      q[k].assign(nlayers, 0.0);
-      auto g = [&](int n) { return k == 0 ? cx(1.0) : t->sigma[n]; };
-      // downward: p_n from the admittance of everything above layer n
-      for (int n = 1; n < nlayers; ++n) {
-        const cx Pm = (n - 1 >= 1) ? p[k][n - 1] * std::exp(-2.0 * eta[n - 1] * L[n - 1]) : 0.0;
-        const cx a = g(n - 1) * (1.0 + Pm) * eta[n], b = g(n) * eta[n - 1] * (1.0 - Pm);
-        p[k][n] = (a - b) / (a + b);
-      }
-      // upward: q_n from the admittance of everything below layer n
-      for (int n = nlayers - 2; n >= 1; --n) {
-        const cx Qp = (n + 1 < nl) ? q[k][n + 1] * std::exp(-2.0 * eta[n + 1] * L[n + 1]) : 0.0;
-        const cx a = g(n + 1) * eta[n] * (1.0 + Qp), b = g(n) * eta[n + 1] * (1.0 - Qp);
-        q[k][n] = (a - b) / (a + b);
-      }
-    }
+    vert::layer_fns(lam, m, eta.data(), L.data(), p.data(), q.data());
+    auto C = [](vert::zc z) { return cx(z.x, z.y); };
     if (lf) {
-      lf->eta = eta;
+      lf->eta.resize(nlayers);
       lf->L = L;
+      for (int n = 0; n < nlayers; ++n) lf->eta[n] = C(eta[n]);
       for (int k = 0; k < 2; ++k) {
-        lf->p[k] = p[k];
-        lf->q[k] = q[k];
+        lf->p[k].resize(nlayers);
+        lf->q[k].resize(nlayers);
+        for (int n = 0; n < nlayers; ++n) {
+          lf->p[k][n] = C(p[k * nlayers + n]);
+          lf->q[k][n] = C(q[k * nlayers + n]);
+        }
       }
     }
     for (int k = 0; k < 2; ++k) {
       cell[k].resize(nz);
       for (int l = 0; l < nz; ++l) {
-        const int n = lay[l];
-        const cx e = eta[n];
-        const double h = tb[l] - ta[l];
-        const cx P = p[k][n], Q = q[k][n];
-        const bool half = !std::isfinite(L[n]);
-        const cx eh = std::exp(-e * h);
-        const cx x = e * h;
-        const cx E1 = h * f_eps(x);
-        const cx ea = std::exp(-2.0 * e * ta[l]), eb = std::exp(-2.0 * e * tb[l]);
-        const cx fa = 1.0 + P * ea, fb = 1.0 + P * eb;
-        const cx fta = 1.0 - P * ea;  // F'(t_a) / (eta e^{eta t_a})
-        const cx qa = half ? cx(0.0) : Q * std::exp(-2.0 * e * (L[n] - ta[l]));
-        const cx qb = half ? cx(0.0) : Q * std::exp(-2.0 * e * (L[n] - tb[l]));
-        const cx ga = 1.0 + qa, gb = 1.0 + qb;
-        const cx damp = half ? cx(0.0) : std::exp(-2.0 * e * L[n]);
-        const cx pqd = P * Q * damp;
-        const cx D = 1.0 - pqd;
-        Cell &c = cell[k][l];
-        c.theta = eh * fa / fb;
-        c.thetad = e * eh * fta / fb;
-        c.FI = E1 * (1.0 + P * std::exp(-e * (ta[l] + tb[l]))) / fb;
-        c.FD = 1.0 - c.theta;
-        const cx qm = half ? cx(0.0) : Q * std::exp(-e * (2.0 * L[n] - ta[l] - tb[l]));
-        c.GI = fa * E1 * (1.0 + qm) / (e * D);
-        c.GD = fa * (eh * gb - ga) / (e * D);
-        c.GId = fta * E1 * (1.0 + qm) / D;
-        c.GDd = fta * (eh * gb - ga) / D;
-        // same cell
-        const cx Sp = ea * E1 * E1;
-        const cx Sq = half ? cx(0.0) : std::exp(-2.0 * e * (L[n] - tb[l])) * E1 * E1;
-        const cx psi = half ? cx(0.0) : f_psi_damped(x, damp, std::exp(x - 2.0 * e * L[n]));
-        const cx phix = f_phi(x);
-        c.diagA = (2.0 * h * h * phix + P * Sp + Q * Sq + P * Q * 2.0 * h * h * psi) / (e * D);
-        c.diagA4 = E1 * E1 * (qb - P * ea) / D;
-        {
-          // U(b,b) + U(a,a) - 2 U(a,b) - 2h, with the free part written
-          // stably: (2/(eta D))(1 - e^{-x}) - 2h = 2h (pqd - x phi(x)) / D
-          const cx em = std::exp(-e * ta[l]) - std::exp(-e * tb[l]);
-          const cx qq = half ? cx(0.0)
-                             : std::exp(-e * (L[n] - tb[l])) - std::exp(-e * (L[n] - ta[l]));
-          const cx pq_term =
-              half ? cx(0.0) : -2.0 * P * Q * f_expm1_damped(x, damp, std::exp(x - 2.0 * e * L[n]));
-          c.diagA3 = 2.0 * h * (pqd - x * phix) / D + (P * em * em + Q * qq * qq + pq_term) / (e * D);
-        }
-        {
-          // lambda^2 A2 - 2h = eta^2 A2 - 2h + k^2 A2 (stable for large lambda)
-          const cx ep = f_eps(x);
-          const cx kk2 = cx(0.0, omega * kMu0) * t->sigma[n];
-          const cx eta2A2m2h =
-              (2.0 * h * (pqd - ep) + e * (P * Sp + Q * Sq + P * Q * 2.0 * h * h * psi)) / D;
-          c.diagA6 = eta2A2m2h + kk2 * c.diagA;
-        }
-      }
-    }
-  }
-
-  void row(double lam, cx *out) const {
-    const int T = nz * (nz + 1) / 2;
-    std::vector<Cell> cell[2];
-    factors(lam, cell);
-    const cx iwm(0.0, omega * kMu0);
-    const double lam2 = lam * lam;
-    // upper pairs iz <= jz: P / lambda, lambda A1, lambda A6 / sigma
-    int u = 0;
-    for (int i = 0; i < nz; ++i) {
-      const cx si = t->sigma[lay[i]];
-      cx R1 = 1.0, Rs = 1.0;  // products of theta over cells strictly between
-      for (int j = i; j < nz; ++j) {
-        cx A1, A2, A3;
-        if (j == i) {
-          A1 = cell[0][i].diagA;
-          A2 = cell[1][i].diagA;
-          A3 = cell[1][i].diagA3;
-        } else {
-          if (j > i + 1) {
-            R1 *= cell[0][j - 1].theta;
-            Rs *= cell[1][j - 1].theta;
-          }
-          A1 = cell[0][i].FI * R1 * cell[0][j].GI;
-          A2 = cell[1][i].FI * Rs * cell[1][j].GI;
-          A3 = cell[1][i].FD * Rs * cell[1][j].GD;
-        }
-        const cx Pv = -iwm * A1 + A3 / si;
-        out[u] = Pv / lam;
-        out[T + u] = lam * A1;
-        const cx A6 = (j == i) ? cell[1][i].diagA6 : lam2 * A2;
-        out[2 * T + u] = lam * A6 / si;
-        ++u;
-      }
-    }
-    // A4 / sigma_obs, full [iz][jz]
-    cx *a4 = out + 3 * T;
-    for (int i = 0; i < nz; ++i) {
-      const cx si = t->sigma[lay[i]];
-      a4[i * nz + i] = lam * cell[1][i].diagA4 / si;
-      cx R = 1.0;
-      for (int j = i + 1; j < nz; ++j) {
-        if (j > i + 1) R *= cell[1][j - 1].theta;
-        // observation i above source j
-        a4[i * nz + j] = lam * cell[1][i].FD * R * cell[1][j].GI / si;
-        // observation j below source i: (sigma_j / sigma_i) FI_i R GD_j / sigma_j
-        a4[j * nz + i] = lam * cell[1][i].FI * R * cell[1][j].GD / si;
+        vert::Cell c;
+        vert::cell_factors(l, k, m, eta.data(), L.data(), p.data(), q.data(), c);
+        Cell &o = cell[k][l];
+        o.theta = C(c.theta);
+        o.FI = C(c.FI);
+        o.FD = C(c.FD);
+        o.GI = C(c.GI);
+        o.GD = C(c.GD);
+        o.diagA = C(c.diagA);
+        o.diagA4 = C(c.diagA4);
+        o.diagA3 = C(c.diagA3);
+        o.diagA6 = C(c.diagA6);
+        o.thetad = C(c.thetad);
+        o.GId = C(c.GId);
+        o.GDd = C(c.GDd);
       }
     }
   }
@@ -1053,11 +939,35 @@ int compute_tables(giem_handle *t, hipStream_t s) {
   std::vector<double> Wt, Wt_reg, Mt;
   hankel_weights(g, Wt, Wt_reg);
   spatial_matrix(t, g, Mt);
-  DevBuf dW, dWr, dM, dG, dH, dc0, dc1, dc2;
+  // the layered model and the lambda nodes on the device: sigma [nlay + 1]
+  // (complex), d [nlay], ta, tb [nz], lambda [nl], then the cells' layers
+  // [nz] (int); workspace of the vertical functions: eta, p, q (complex) and
+  // L per node and layer, the cell factors of both kinds per node and cell
+  Vertical v;
+  v.init(t, t->f.empty() ? 0.0 : t->f[0].freq);
+  const int nlayers = t->nlay + 1;
+  const size_t nmod = 2 * (size_t)nlayers + t->nlay + 2 * (size_t)nz + nl;
+  std::vector<double> model(nmod);
+  {
+    double *o = model.data();
+    for (int n = 0; n < nlayers; ++n, o += 2) {
+      o[0] = v.sig[n].x;
+      o[1] = v.sig[n].y;
+    }
+    o = std::copy(t->d.begin(), t->d.end(), o);
+    o = std::copy(v.ta.begin(), v.ta.end(), o);
+    o = std::copy(v.tb.begin(), v.tb.end(), o);
+    std::copy(g.lam.x.begin(), g.lam.x.end(), o);
+  }
+  const size_t nws = nl * nlayers;  // (node, layer) pairs
+  DevBuf dW, dWr, dM, dG, dH, dc0, dc1, dc2, dmod, dlay, dws, dcell;
   if (dW.alloc(Wt.size() * 8) != hipSuccess || dWr.alloc(Wt_reg.size() * 8) != hipSuccess ||
       dM.alloc(Mt.size() * 8) != hipSuccess || dG.alloc(nl * ncolc * 16) != hipSuccess ||
       dH.alloc(nr * ncolc * 16) != hipSuccess || dc0.alloc(noff * 2 * T * 16) != hipSuccess ||
-      dc1.alloc(3 * noff * T * 16) != hipSuccess || dc2.alloc(2 * noff * nz2 * 16) != hipSuccess) {
+      dc1.alloc(3 * noff * T * 16) != hipSuccess || dc2.alloc(2 * noff * nz2 * 16) != hipSuccess ||
+      dmod.alloc(nmod * 8) != hipSuccess || dlay.alloc((size_t)nz * sizeof(int)) != hipSuccess ||
+      dws.alloc(nws * (5 * sizeof(vert::zc) + sizeof(double))) != hipSuccess ||
+      dcell.alloc(nl * 2 * nz * sizeof(vert::Cell)) != hipSuccess) {
     (void)hipGetLastError();  // reported here, not by the next launch check
     set_error("giem_tables: out of device memory");
     return GIEM_ENOMEM;
@@ -1067,15 +977,31 @@ int compute_tables(giem_handle *t, hipStream_t s) {
       check_hip(hipMemcpyAsync(dWr.p, Wt_reg.data(), Wt_reg.size() * 8, hipMemcpyHostToDevice, s),
                 "upload Hankel weights") ||
       check_hip(hipMemcpyAsync(dM.p, Mt.data(), Mt.size() * 8, hipMemcpyHostToDevice, s),
-                "upload spatial weights"))
+                "upload spatial weights") ||
+      check_hip(hipMemcpyAsync(dmod.p, model.data(), nmod * 8, hipMemcpyHostToDevice, s),
+                "upload layered model") ||
+      check_hip(hipMemcpyAsync(dlay.p, v.lay.data(), (size_t)nz * sizeof(int),
+                               hipMemcpyHostToDevice, s),
+                "upload layered model"))
     return GIEM_EHIP;
-  std::vector<cx> G(nl * ncolc);
+  vert::Model dm;
+  dm.nz = nz;
+  dm.nlay = t->nlay;
+  dm.sigma = reinterpret_cast<const vert::zc *>(dmod.d());
+  dm.d = dmod.d() + 2 * nlayers;
+  dm.ta = dm.d + t->nlay;
+  dm.tb = dm.ta + nz;
+  const double *dlam = dm.tb + nz;
+  dm.lay = static_cast<const int *>(dlay.p);
+  vert::zc *deta = static_cast<vert::zc *>(dws.p);
+  vert::zc *dp = deta + nws, *dq = dp + 2 * nws;
+  double *dL = reinterpret_cast<double *>(dq + 2 * nws);
   for (size_t q = 0; q < t->f.size(); ++q) {
-    Vertical v;
-    v.init(t, t->f[q].freq);
-    parallel_for((int)nl, [&](int l) { v.row(g.lam.x[l], G.data() + (size_t)l * ncolc); });
-    if (check_hip(hipMemcpyAsync(dG.p, G.data(), G.size() * 16, hipMemcpyHostToDevice, s),
-                  "upload vertical functions"))
+    dm.omega_mu0 = 2 * kPi * t->f[q].freq * kMu0;
+    if (check_hip(launch_vertical_rows(dm, dlam, (int)nl, deta, dL, dp, dq,
+                                       static_cast<vert::Cell *>(dcell.p),
+                                       static_cast<vert::zc *>(dG.p), ncolc, s),
+                  "vertical functions"))
       return GIEM_EHIP;
     const int64_t ldg = 2 * (int64_t)ncolc;  // doubles per row of G and H
     // H[:, P] = W_reg G[:, P];  H[:, rest] = W G[:, rest]
