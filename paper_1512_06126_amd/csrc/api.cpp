@@ -304,18 +304,27 @@ int apply_multi(giem_handle *t, int nf, const int *ifreqs, int nrhs, const VecPt
 int upload_spatial(giem_handle *t, hipStream_t s) {
   const int nx = t->nx, ny = t->ny, nz = t->nz, E = t->E();
   const size_t nsc = (size_t)(nx + 1) * (ny + 1) * E;
-  void *tmp = nullptr;
+  void *tmp = nullptr, *tm = nullptr;
   int rc = GIEM_OK;
+  const size_t ntx = 2 * (size_t)nx * (nx + 1), nty = 2 * (size_t)ny * (ny + 1);
   rc = check_hip(hipMalloc(&tmp, (size_t)ny * (nx + 1) * E * sizeof(c128)), "hipMalloc tmp");
+  if (rc == GIEM_OK) rc = check_hip(hipMalloc(&tm, (ntx + nty) * sizeof(double)), "hipMalloc tmp");
+  double *Tx = static_cast<double *>(tm), *Ty = Tx + ntx;
+  if (rc == GIEM_OK)
+    rc = check_hip(launch_parity_matrices(static_cast<const c128 *>(t->cs_x), nx, Tx, s),
+                   "transform matrices");
+  if (rc == GIEM_OK)
+    rc = check_hip(launch_parity_matrices(static_cast<const c128 *>(t->cs_y), ny, Ty, s),
+                   "transform matrices");
   for (size_t q = 0; rc == GIEM_OK && q < t->f.size(); ++q) {
     FreqTables &ft = t->f[q];
     if (rc == GIEM_OK) rc = check_hip(hipMalloc(&ft.spec64, nsc * sizeof(c128)), "hipMalloc spectra");
     if (rc == GIEM_OK)
       rc = check_hip(launch_spectral_x(static_cast<const c128 *>(ft.spatial), static_cast<c128 *>(tmp),
-                                       static_cast<c128 *>(t->cs_x), nx, ny, nz, s), "spectral x");
+                                       Tx, nx, ny, nz, s), "spectral x");
     if (rc == GIEM_OK)
-      rc = check_hip(launch_spectral_y(static_cast<c128 *>(tmp), static_cast<c128 *>(ft.spec64),
-                                       static_cast<c128 *>(t->cs_y), nx, ny, nz, s), "spectral y");
+      rc = check_hip(launch_spectral_y(static_cast<c128 *>(tmp), static_cast<c128 *>(ft.spec64), Ty,
+                                       nx, ny, nz, s), "spectral y");
     if (rc == GIEM_OK && (t->flags & GIEM_TABLES_C64)) {
       rc = check_hip(hipMalloc(&ft.spec32, nsc * sizeof(c64)), "hipMalloc c64 spectra");
       if (rc == GIEM_OK)
@@ -325,6 +334,7 @@ int upload_spatial(giem_handle *t, hipStream_t s) {
     if (rc == GIEM_OK) rc = check_hip(hipStreamSynchronize(s), "sync");
   }
   if (tmp) hipFree(tmp);
+  if (tm) hipFree(tm);
   return rc;
 }
 

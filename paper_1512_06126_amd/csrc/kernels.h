@@ -48,9 +48,12 @@ bool block_two_per_cu(int nz, int R, int prec);
 bool block_dbl_supported(int nz, int R, int prec);
 
 // table set-up (kernels_setup.hip)
-hipError_t launch_spectral_x(const c128 *spatial, c128 *tmp, const c128 *cs_x, int nx, int ny,
+// Tx, Ty: the even and odd transform matrices of each axis, 2 n (n + 1)
+// doubles from launch_parity_matrices
+hipError_t launch_parity_matrices(const c128 *cs, int n, double *T, hipStream_t s);
+hipError_t launch_spectral_x(const c128 *spatial, c128 *tmp, const double *Tx, int nx, int ny,
                              int nz, hipStream_t s);
-hipError_t launch_spectral_y(const c128 *tmp, c128 *spectral, const c128 *cs_y, int nx, int ny,
+hipError_t launch_spectral_y(const c128 *tmp, c128 *spectral, const double *Ty, int nx, int ny,
                              int nz, hipStream_t s);
 hipError_t launch_to_c64(const c128 *src, c64 *dst, size_t n, hipStream_t s);
 hipError_t launch_diagonals(const c128 *sigma_a, const c128 *sb_lev, const double *vol_lev,

@@ -21,10 +21,12 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // 32 (w & 1) as 2 x 2 tiles.  Operands come straight from global memory (the
 // workgroup's 64-wide panels are re-read from L2 by its waves): both reads
 // are coalesced, 16 consecutive doubles per quarter wave.
+// With krange, row tile t of C contracts only over [krange[2t], krange[2t+1])
+// (the rows of At outside it are zero in that tile's columns).
 __global__ __launch_bounds__(256) void k_gemm_tn(const double *__restrict__ At, int64_t lda,
                                                  const double *__restrict__ B, int64_t ldb,
                                                  double *__restrict__ C, int64_t ldc, int m, int n,
-                                                 int k) {
+                                                 int k, const int *__restrict__ krange) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int m0 = blockIdx.y * 64 + (w >> 1) * 32;
   const int n0 = blockIdx.x * 64 + (w & 1) * 32;
@@ -35,9 +37,14 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const double *__restrict__ At, 
   const int ra0 = m0 + li, ra1 = m0 + 16 + li;
   const int cb0 = n0 + li, cb1 = n0 + 16 + li;
   const bool va0 = ra0 < m, va1 = ra1 < m, vb0 = cb0 < n, vb1 = cb1 < n;
-  for (int k0 = 0; k0 < k; k0 += 4) {
+  int kb = 0, ke = k;
+  if (krange) {
+    kb = krange[2 * blockIdx.y];
+    ke = min(k, krange[2 * blockIdx.y + 1]);
+  }
+  for (int k0 = kb; k0 < ke; k0 += 4) {
     const int kk = k0 + lk;
-    const bool vk = kk < k;
+    const bool vk = kk < ke;
     const double *ar = At + (int64_t)kk * lda;
     const double *br = B + (int64_t)kk * ldb;
     const double a0 = (vk && va0) ? ar[ra0] : 0.0;
@@ -460,11 +467,11 @@ hipError_t launch_fields(const c128 *K, const c128 *E, const c128 *sa, const c12
 }
 
 hipError_t launch_gemm_tn(const double *At, int64_t lda, const double *B, int64_t ldb, double *C,
-                          int64_t ldc, int m, int n, int k, hipStream_t s) {
+                          int64_t ldc, int m, int n, int k, hipStream_t s, const int *krange) {
   if (m <= 0 || n <= 0) return hipSuccess;
   dim3 grid((n + 63) / 64, (m + 63) / 64);
   if (grid.y > 65535) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_gemm_tn, grid, dim3(256), 0, s, At, lda, B, ldb, C, ldc, m, n, k);
+  hipLaunchKernelGGL(k_gemm_tn, grid, dim3(256), 0, s, At, lda, B, ldb, C, ldc, m, n, k, krange);
   return hipGetLastError();
 }
 

@@ -49,7 +49,8 @@
 namespace giem {
 
 hipError_t launch_gemm_tn(const double *At, int64_t lda, const double *B, int64_t ldb, double *C,
-                          int64_t ldc, int m, int n, int k, hipStream_t s);
+                          int64_t ldc, int m, int n, int k, hipStream_t s,
+                          const int *krange = nullptr);
 hipError_t launch_assemble(const c128 *c0, const c128 *c1, const c128 *c2, c128 *out, int nx,
                            int ny, int nz, double omega_mu0, hipStream_t s);
 hipError_t launch_assemble_rec(const c128 *c, c128 *out, int noff, int nz, double omega_mu0,
@@ -472,10 +473,13 @@ void line_rule(int kind, double dx, double dy, double hx, double hy, const Rule 
 }
 
 // Spatial fold matrices Mt[rho][kind * noff + (i Nx + j)] for i, j >= 0.
-void spatial_matrix(const giem_handle *t, const Grids &g, std::vector<double> &Mt) {
+// Rows of Mt with a non-zero entry in column c lie in [kcol[2c], kcol[2c+1]).
+void spatial_matrix(const giem_handle *t, const Grids &g, std::vector<double> &Mt,
+                    std::vector<int> &kcol) {
   const int nx = t->nx, ny = t->ny;
   const size_t noff = (size_t)nx * ny, nr = g.rho.size(), ncol = K_COUNT * noff;
   Mt.assign(nr * ncol, 0.0);
+  kcol.resize(2 * ncol);
   const Rule gs = gauss_legendre(24), g14 = gauss_legendre(14), g8 = gauss_legendre(8);
   const Rule gline = gauss_legendre(24);
   parallel_for((int)noff, [&](int o) {
@@ -489,12 +493,39 @@ void spatial_matrix(const giem_handle *t, const Grids &g, std::vector<double> &M
       else
         area_rule(kind, dx, dy, t->hx, t->hy, gs, g14, g8, pts);
       const size_t col = kind * noff + o;
+      size_t lo = nr, hi = 0;
       for (size_t q = 0; q < pts.rho.size(); ++q) {
         const size_t c0 = g.rho.interp(std::max(pts.rho[q], g.rho_min), wi);
         for (int k = 0; k < g.rho.n; ++k) Mt[(c0 + k) * ncol + col] += pts.w[q] * wi[k];
+        lo = std::min(lo, c0);
+        hi = std::max(hi, c0 + g.rho.n);
       }
+      kcol[2 * col] = (int)lo;
+      kcol[2 * col + 1] = (int)hi;
     }
   });
+}
+
+// Contraction range of each 64-row tile of a GEMM over the columns col0 ..
+// col0 + m of a rule matrix: the union of its columns' row ranges, widened to
+// whole steps of 4 so that the tile's MFMAs visit the same 4-row groups as a
+// dense loop (the groups skipped hold only zeros: the result is unchanged)
+std::vector<int> tile_ranges(const std::vector<int> &kcol, size_t col0, int m) {
+  const int nt = (m + 63) / 64;
+  std::vector<int> r(2 * (size_t)nt);
+  for (int tile = 0; tile < nt; ++tile) {
+    int lo = 1 << 30, hi = 0;
+    for (int c = tile * 64; c < std::min(m, tile * 64 + 64); ++c) {
+      const int a = kcol[2 * (col0 + c)], b = kcol[2 * (col0 + c) + 1];
+      if (a >= b) continue;
+      lo = std::min(lo, a);
+      hi = std::max(hi, b);
+    }
+    if (lo >= hi) lo = hi = 0;
+    r[2 * tile] = lo / 4 * 4;
+    r[2 * tile + 1] = (hi + 3) / 4 * 4;
+  }
+  return r;
 }
 
 // ------------------------------------------- receiver (point) rules
@@ -937,8 +968,19 @@ int compute_tables(giem_handle *t, hipStream_t s) {
   const Grids g = make_grids(t);
   const size_t nl = g.lam.size(), nr = g.rho.size();
   std::vector<double> Wt, Wt_reg, Mt;
+  std::vector<int> kcol;
   hankel_weights(g, Wt, Wt_reg);
-  spatial_matrix(t, g, Mt);
+  spatial_matrix(t, g, Mt, kcol);
+  // contraction ranges of the three spatial GEMMs' row tiles
+  std::vector<int> kr = tile_ranges(kcol, 0, (int)noff);
+  const size_t kr1 = kr.size();
+  {
+    const std::vector<int> a = tile_ranges(kcol, K_XX * noff, (int)(3 * noff));
+    const std::vector<int> b = tile_ranges(kcol, K_X * noff, (int)(2 * noff));
+    kr.insert(kr.end(), a.begin(), a.end());
+    kr.insert(kr.end(), b.begin(), b.end());
+  }
+  const size_t kr2 = kr1 + 2 * ((3 * noff + 63) / 64);
   // the layered model and the lambda nodes on the device: sigma [nlay + 1]
   // (complex), d [nlay], ta, tb [nz], lambda [nl], then the cells' layers
   // [nz] (int); workspace of the vertical functions: eta, p, q (complex) and
@@ -960,14 +1002,15 @@ int compute_tables(giem_handle *t, hipStream_t s) {
     std::copy(g.lam.x.begin(), g.lam.x.end(), o);
   }
   const size_t nws = nl * nlayers;  // (node, layer) pairs
-  DevBuf dW, dWr, dM, dG, dH, dc0, dc1, dc2, dmod, dlay, dws, dcell;
+  DevBuf dW, dWr, dM, dG, dH, dc0, dc1, dc2, dmod, dlay, dws, dcell, dkr;
   if (dW.alloc(Wt.size() * 8) != hipSuccess || dWr.alloc(Wt_reg.size() * 8) != hipSuccess ||
       dM.alloc(Mt.size() * 8) != hipSuccess || dG.alloc(nl * ncolc * 16) != hipSuccess ||
       dH.alloc(nr * ncolc * 16) != hipSuccess || dc0.alloc(noff * 2 * T * 16) != hipSuccess ||
       dc1.alloc(3 * noff * T * 16) != hipSuccess || dc2.alloc(2 * noff * nz2 * 16) != hipSuccess ||
       dmod.alloc(nmod * 8) != hipSuccess || dlay.alloc((size_t)nz * sizeof(int)) != hipSuccess ||
       dws.alloc(nws * (5 * sizeof(vert::zc) + sizeof(double))) != hipSuccess ||
-      dcell.alloc(nl * 2 * nz * sizeof(vert::Cell)) != hipSuccess) {
+      dcell.alloc(nl * 2 * nz * sizeof(vert::Cell)) != hipSuccess ||
+      dkr.alloc(kr.size() * sizeof(int)) != hipSuccess) {
     (void)hipGetLastError();  // reported here, not by the next launch check
     set_error("giem_tables: out of device memory");
     return GIEM_ENOMEM;
@@ -982,8 +1025,11 @@ int compute_tables(giem_handle *t, hipStream_t s) {
                 "upload layered model") ||
       check_hip(hipMemcpyAsync(dlay.p, v.lay.data(), (size_t)nz * sizeof(int),
                                hipMemcpyHostToDevice, s),
-                "upload layered model"))
+                "upload layered model") ||
+      check_hip(hipMemcpyAsync(dkr.p, kr.data(), kr.size() * sizeof(int), hipMemcpyHostToDevice, s),
+                "upload contraction ranges"))
     return GIEM_EHIP;
+  const int *dkr0 = static_cast<const int *>(dkr.p);
   vert::Model dm;
   dm.nz = nz;
   dm.nlay = t->nlay;
@@ -1014,13 +1060,13 @@ int compute_tables(giem_handle *t, hipStream_t s) {
     const int64_t ldm = (int64_t)K_COUNT * noff;
     // c0 = M_W0 [A1 | A6];  c1 = M_{XX,YY,XY} P;  c2 = M_{X,Y} A4
     if (check_hip(launch_gemm_tn(dM.d(), ldm, dH.d() + 2 * T, ldg, dc0.d(), 4 * T, (int)noff, 4 * T,
-                                 (int)nr, s),
+                                 (int)nr, s, dkr0),
                   "spatial contraction") ||
         check_hip(launch_gemm_tn(dM.d() + K_XX * noff, ldm, dH.d(), ldg, dc1.d(), 2 * T,
-                                 (int)(3 * noff), 2 * T, (int)nr, s),
+                                 (int)(3 * noff), 2 * T, (int)nr, s, dkr0 + kr1),
                   "spatial contraction") ||
         check_hip(launch_gemm_tn(dM.d() + K_X * noff, ldm, dH.d() + 6 * T, ldg, dc2.d(), 2 * nz2,
-                                 (int)(2 * noff), 2 * nz2, (int)nr, s),
+                                 (int)(2 * noff), 2 * nz2, (int)nr, s, dkr0 + kr2),
                   "spatial contraction") ||
         check_hip(hipMalloc(&t->f[q].spatial, noff * t->E() * 16), "hipMalloc spatial table") ||
         check_hip(launch_assemble(dc0.c(), dc1.c(), dc2.c(), static_cast<c128 *>(t->f[q].spatial),
@@ -1046,6 +1092,7 @@ int compute_receiver_kernels(giem_handle *t, int ifreq, double z0, void **out, h
   const Grids g = make_grids(t);
   const size_t nl = g.lam.size(), nr = g.rho.size();
   std::vector<double> Wt, Wt_reg, Mt(nr * R_COUNT * noff, 0.0);
+  std::vector<int> kcol(2 * R_COUNT * noff);
   hankel_weights(g, Wt, Wt_reg);
   {
     const Rule gs = gauss_legendre(24), g14 = gauss_legendre(14), g8 = gauss_legendre(8);
@@ -1058,11 +1105,16 @@ int compute_receiver_kernels(giem_handle *t, int ifreq, double z0, void **out, h
         RulePtsD pts;
         receiver_rule(kind, di * t->hx, dj * t->hy, t->hx, t->hy, gs, g14, g8, gl, pts);
         const size_t col = kind * noff + o;
+        size_t lo = nr, hi = 0;
         for (size_t q = 0; q < pts.rho.size(); ++q) {
           const double r = std::max(pts.rho[q], g.rho_min);
           const size_t c0 = pts.deriv[q] ? g.rho.interp_deriv(r, wi) : g.rho.interp(r, wi);
           for (int k = 0; k < g.rho.n; ++k) Mt[(c0 + k) * ncol + col] += pts.w[q] * wi[k];
+          lo = std::min(lo, c0);
+          hi = std::max(hi, c0 + g.rho.n);
         }
+        kcol[2 * col] = (int)lo;
+        kcol[2 * col + 1] = (int)hi;
       }
     });
   }
@@ -1072,11 +1124,13 @@ int compute_receiver_kernels(giem_handle *t, int ifreq, double z0, void **out, h
   const bool touching = v.gap_lay.empty();
   std::vector<cx> G(nl * nf);
   parallel_for((int)nl, [&](int l) { v.point_row(g.lam.x[l], G.data() + (size_t)l * nf); });
-  DevBuf dW, dWr, dM, dG, dH, dC;
+  const std::vector<int> kr = tile_ranges(kcol, 0, (int)(R_COUNT * noff));
+  DevBuf dW, dWr, dM, dG, dH, dC, dkr;
   void *dK = nullptr;
   if (dW.alloc(Wt.size() * 8) != hipSuccess || dWr.alloc(Wt_reg.size() * 8) != hipSuccess ||
       dM.alloc(Mt.size() * 8) != hipSuccess || dG.alloc(G.size() * 16) != hipSuccess ||
       dH.alloc(nr * nf * 16) != hipSuccess || dC.alloc((size_t)R_COUNT * noff * nf * 16) != hipSuccess ||
+      dkr.alloc(kr.size() * sizeof(int)) != hipSuccess ||
       hipMalloc(&dK, noff * nz * 18 * sizeof(c128)) != hipSuccess) {
     if (dK) hipFree(dK);
     (void)hipGetLastError();  // reported here, not by the next launch check
@@ -1090,6 +1144,8 @@ int compute_receiver_kernels(giem_handle *t, int ifreq, double z0, void **out, h
       check_hip(hipMemcpyAsync(dWr.p, Wt_reg.data(), Wt_reg.size() * 8, hipMemcpyHostToDevice, s), "upload") ||
       check_hip(hipMemcpyAsync(dM.p, Mt.data(), Mt.size() * 8, hipMemcpyHostToDevice, s), "upload") ||
       check_hip(hipMemcpyAsync(dG.p, G.data(), G.size() * 16, hipMemcpyHostToDevice, s), "upload") ||
+      check_hip(hipMemcpyAsync(dkr.p, kr.data(), kr.size() * sizeof(int), hipMemcpyHostToDevice, s),
+                "upload") ||
       // plain functions 0..5, regularised 6..7
       check_hip(launch_gemm_tn(dW.d(), nr, dG.d(), ldg, dH.d(), ldg, (int)nr, 2 * 6 * nz, (int)nl, s),
                 "receiver Hankel contraction") ||
@@ -1097,7 +1153,7 @@ int compute_receiver_kernels(giem_handle *t, int ifreq, double z0, void **out, h
                                (int)nr, 2 * 2 * nz, (int)nl, s),
                 "receiver Hankel contraction") ||
       check_hip(launch_gemm_tn(dM.d(), ldm, dH.d(), ldg, dC.d(), ldg, (int)(R_COUNT * noff), 2 * nf,
-                               (int)nr, s),
+                               (int)nr, s, static_cast<const int *>(dkr.p)),
                 "receiver spatial contraction") ||
       check_hip(launch_assemble_rec(dC.c(), static_cast<c128 *>(dK), (int)noff, nz,
                                     2 * kPi * t->f[ifreq].freq * kMu0, s),
