@@ -318,6 +318,9 @@ def main():
                     help="FP64 block-product variant in --counter-run (1 or 2 prefetch sets, 3 = "
                          "two workgroups per CU, 4 = the next row staged into a second LDS "
                          "buffer; giem_tune chooses 4 for FP64 on this workload)")
+    ap.add_argument("--table-build", action="store_true",
+                    help="only time giem_tables for the benchmark model of Sect. 4 on "
+                         "176x224x118 cells of 25 m, for one and for two frequencies, and exit")
     args = ap.parse_args()
     if args.counter_summary:
         print(counter_summary(args.counter_summary))
@@ -334,6 +337,19 @@ def main():
     g.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+
+    if args.table_build:
+        m = gs.config_commemi3d3()
+        for nf in (1, 2):
+            freqs = m["freq"] * 2.0 ** np.arange(nf)
+            t0 = time.perf_counter()
+            h = g.tables(m, freqs)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            h.close()
+            print(f"giem_tables, {m['nx']}x{m['ny']}x{m['nz']} cells, {nf} frequencies: "
+                  f"{dt:.2f} s", flush=True)
+        return
 
     model = gs.config_128x128x32()
     nx, ny, nz = model["nx"], model["ny"], model["nz"]
