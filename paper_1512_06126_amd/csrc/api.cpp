@@ -71,17 +71,6 @@ static int make_plan(int L, FftPlan &p) {
   return GIEM_OK;
 }
 
-static int make_cs(int n, void **out) {
-  std::vector<c128> cs(2 * n);
-  for (int a = 0; a < 2 * n; ++a) {
-    long double th = 3.141592653589793238462643383279503L * (long double)a / (long double)n;
-    cs[a] = mk<double>((double)cosl(th), (double)sinl(th));
-  }
-  GIEM_HIP(hipMalloc(out, cs.size() * sizeof(c128)), "hipMalloc cs");
-  GIEM_HIP(hipMemcpy(*out, cs.data(), cs.size() * sizeof(c128), hipMemcpyHostToDevice), "copy cs");
-  return GIEM_OK;
-}
-
 // Spectra workspace of giem_apply_noalloc: a fixed device array that every
 // call on a device shares (the device holds it until the process ends).  In
 // host code `scratch` is only a host-side stand-in for the symbol; its device
@@ -304,27 +293,25 @@ int apply_multi(giem_handle *t, int nf, const int *ifreqs, int nrhs, const VecPt
 int upload_spatial(giem_handle *t, hipStream_t s) {
   const int nx = t->nx, ny = t->ny, nz = t->nz, E = t->E();
   const size_t nsc = (size_t)(nx + 1) * (ny + 1) * E;
-  void *tmp = nullptr, *tm = nullptr;
+  void *tmp = nullptr;
   int rc = GIEM_OK;
-  const size_t ntx = 2 * (size_t)nx * (nx + 1), nty = 2 * (size_t)ny * (ny + 1);
   rc = check_hip(hipMalloc(&tmp, (size_t)ny * (nx + 1) * E * sizeof(c128)), "hipMalloc tmp");
-  if (rc == GIEM_OK) rc = check_hip(hipMalloc(&tm, (ntx + nty) * sizeof(double)), "hipMalloc tmp");
-  double *Tx = static_cast<double *>(tm), *Ty = Tx + ntx;
-  if (rc == GIEM_OK)
-    rc = check_hip(launch_parity_matrices(static_cast<const c128 *>(t->cs_x), nx, Tx, s),
-                   "transform matrices");
-  if (rc == GIEM_OK)
-    rc = check_hip(launch_parity_matrices(static_cast<const c128 *>(t->cs_y), ny, Ty, s),
-                   "transform matrices");
+  const int64_t row = (int64_t)(nx + 1) * E;
   for (size_t q = 0; rc == GIEM_OK && q < t->f.size(); ++q) {
     FreqTables &ft = t->f[q];
     if (rc == GIEM_OK) rc = check_hip(hipMalloc(&ft.spec64, nsc * sizeof(c128)), "hipMalloc spectra");
+    // along x: tmp[i][K][e] from spatial[i][j][e]; along y: spectra[Ky][K][e]
+    // from tmp[i][K][e] (the FFT passes of the apply at lengths 2 Nx, 2 Ny)
     if (rc == GIEM_OK)
-      rc = check_hip(launch_spectral_x(static_cast<const c128 *>(ft.spatial), static_cast<c128 *>(tmp),
-                                       Tx, nx, ny, nz, s), "spectral x");
+      rc = check_hip(launch_parity_fft(static_cast<const c128 *>(ft.spatial), E, (int64_t)nx * E, ny,
+                                       static_cast<c128 *>(tmp), E, row, nx, E, nz, 0, t->px.d,
+                                       t->px.tw64, s),
+                     "spectral x");
     if (rc == GIEM_OK)
-      rc = check_hip(launch_spectral_y(static_cast<c128 *>(tmp), static_cast<c128 *>(ft.spec64), Ty,
-                                       nx, ny, nz, s), "spectral y");
+      rc = check_hip(launch_parity_fft(static_cast<const c128 *>(tmp), row, E, nx + 1,
+                                       static_cast<c128 *>(ft.spec64), row, E, ny, E, nz, 1, t->py.d,
+                                       t->py.tw64, s),
+                     "spectral y");
     if (rc == GIEM_OK && (t->flags & GIEM_TABLES_C64)) {
       rc = check_hip(hipMalloc(&ft.spec32, nsc * sizeof(c64)), "hipMalloc c64 spectra");
       if (rc == GIEM_OK)
@@ -334,7 +321,6 @@ int upload_spatial(giem_handle *t, hipStream_t s) {
     if (rc == GIEM_OK) rc = check_hip(hipStreamSynchronize(s), "sync");
   }
   if (tmp) hipFree(tmp);
-  if (tm) hipFree(tm);
   return rc;
 }
 
@@ -484,8 +470,6 @@ static int finish_handle(giem_handle *t, hipStream_t s) {
   recall_tuned(t);
   GIEM_TRY(make_plan(2 * t->nx, t->px));
   GIEM_TRY(make_plan(2 * t->ny, t->py));
-  GIEM_TRY(make_cs(t->nx, &t->cs_x));
-  GIEM_TRY(make_cs(t->ny, &t->cs_y));
   {
     const std::vector<unsigned> plan = block_plan(nz);
     GIEM_HIP(hipMalloc(&t->bplan, plan.size() * sizeof(unsigned)), "hipMalloc plan");
@@ -535,7 +519,7 @@ void giem_free(giem_handle *t) {
     if (ft.spec32) hipFree(ft.spec32);
     for (auto &rk : ft.rec_kernels) hipFree(rk.second);
   }
-  void *dev[] = {t->px.tw64, t->px.tw32, t->py.tw64, t->py.tw32, t->cs_x, t->cs_y, t->bplan,
+  void *dev[] = {t->px.tw64, t->px.tw32, t->py.tw64, t->py.tw32, t->bplan,
                  t->sb_lev, t->vol_lev, t->sroot_lev, t->diag, t->spec_ws, t->red_part,
                  t->red_out, t->coef_dev, t->basis, t->vec_ws, t->gs_scale_dev};
   for (void *p : dev)

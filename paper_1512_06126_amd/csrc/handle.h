@@ -46,7 +46,6 @@ struct giem_handle {
   int device = 0;
   std::vector<giem::FreqTables> f;
   giem::FftPlan px, py;            // lengths 2 Nx, 2 Ny
-  void *cs_x = nullptr, *cs_y = nullptr;  // (cos, sin)(pi a / N), a < 2N
   void *bplan = nullptr;                  // gather plan of the block product
   // per-level device data
   void *sb_lev = nullptr;    // c128 [nz]

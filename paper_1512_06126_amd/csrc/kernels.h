@@ -48,13 +48,12 @@ bool block_two_per_cu(int nz, int R, int prec);
 bool block_dbl_supported(int nz, int R, int prec);
 
 // table set-up (kernels_setup.hip)
-// Tx, Ty: the even and odd transform matrices of each axis, 2 n (n + 1)
-// doubles from launch_parity_matrices
-hipError_t launch_parity_matrices(const c128 *cs, int n, double *T, hipStream_t s);
-hipError_t launch_spectral_x(const c128 *spatial, c128 *tmp, const double *Tx, int nx, int ny,
-                             int nz, hipStream_t s);
-hipError_t launch_spectral_y(const c128 *tmp, c128 *spectral, const double *Ty, int nx, int ny,
-                             int nz, hipStream_t s);
+// even/odd transform of the packed table along axis 0 (x) or 1 (y): nbatch
+// lines, element j of line b at in + b sb + j sj, K at out + b ob + K sk
+// (c128 units), n elements per line, transforms of length fd.L = 2 n
+hipError_t launch_parity_fft(const c128 *in, int64_t sj, int64_t sb, int nbatch, c128 *out,
+                             int64_t sk, int64_t ob, int n, int E, int nz, int axis,
+                             const FftDesc &fd, const void *tw, hipStream_t s);
 hipError_t launch_to_c64(const c128 *src, c64 *dst, size_t n, hipStream_t s);
 hipError_t launch_diagonals(const c128 *sigma_a, const c128 *sb_lev, const double *vol_lev,
                             int nx, int ny, int nz, c128 *S, c128 *R1, c128 *R2, c128 *a,

@@ -404,6 +404,62 @@ k_fft_y(cplx<T> *__restrict__ spec, int nx2, int ny, int rp_total, int G, FftDes
   }
 }
 
+// ------------------------------------------------------- table spectra
+// Even/odd transform of the packed table along one axis (a0; the parities of
+// Lemma 2): for G consecutive packed entries e of one line, the length-2N
+// sequence s[j] = c(j) (j < N), s[N] = 0, s[2N - j] = +-c(j) (the parity of
+// e's class along the axis) goes through the FFT passes, and S[K], K <= N,
+// is kept: S[K] = c(0) + 2 sum_j cos(pi K j / N) c(j), or -2i sum_j
+// sin(pi K j / N) c(j) for the odd classes.  in: line b at in + b sb,
+// element j at + j sj (c128 units; the E entries contiguous); out likewise
+// with K.  Grid: (entry group, line).
+__device__ __forceinline__ bool entry_odd(int e, int nz, int axis) {
+  const int tri = nz * (nz + 1) / 2;
+  const int c = e < 4 * tri ? e / tri : (e < 4 * tri + nz * nz ? 4 : 5);
+  // xy is odd along both axes, xz along x, yz along y
+  return c == 1 || c == (axis == 0 ? 4 : 5);
+}
+
+template <typename T, int EPT, int NT, bool POW2>
+__global__ void __launch_bounds__(NT)
+k_parity_fft(const c128 *__restrict__ in, int64_t sj, int64_t sb, c128 *__restrict__ out,
+             int64_t sk, int64_t ob, int n, int E, int nz, int axis, int G, FftDesc fd,
+             const c128 *__restrict__ tw) {
+  extern __shared__ unsigned char smem_raw[];
+  c128 *buf = reinterpret_cast<c128 *>(smem_raw);
+  const int L = fd.L, ld = fft_ld(L);
+  const int e0 = blockIdx.x * G;
+  in += (int64_t)blockIdx.y * sb;
+  out += (int64_t)blockIdx.y * ob;
+  constexpr int EH = (EPT + 1) / 2;  // G n <= NT EPT / 2
+  c128 v[EH];
+#pragma unroll
+  for (int u = 0; u < EH; ++u) {
+    const int idx = threadIdx.x + u * NT;
+    const int j = idx / G, g = idx - j * G;
+    v[u] = mk<double>(0, 0);
+    if (j < n && e0 + g < E) v[u] = in[(int64_t)j * sj + e0 + g];
+  }
+#pragma unroll
+  for (int u = 0; u < EH; ++u) {
+    const int idx = threadIdx.x + u * NT;
+    const int j = idx / G, g = idx - j * G;
+    if (j < n) {
+      buf[g * ld + lds_pad(j)] = v[u];
+      if (j > 0) {
+        const bool odd = entry_odd(e0 + g, nz, axis);
+        buf[g * ld + lds_pad(L - j)] = odd ? mk<double>(-v[u].x, -v[u].y) : v[u];
+      }
+    }
+  }
+  for (int g = threadIdx.x; g < G; g += NT) buf[g * ld + lds_pad(n)] = mk<double>(0, 0);
+  fft_lds<T, EPT, POW2>(buf, G, ld, fd, tw, false);
+  for (int idx = threadIdx.x; idx < G * (n + 1); idx += NT) {
+    const int K = idx / G, g = idx - K * G;
+    if (e0 + g < E) out[(int64_t)K * sk + e0 + g] = buf[g * ld + lds_pad(K)];
+  }
+}
+
 // ---------------------------------------------------------------- launchers
 // Elements per thread of a pass over G sequences of length L with nthr
 // threads (0 if the configuration is not instantiated).  At most 16: the x
@@ -479,6 +535,33 @@ static hipError_t launch_fft_y_t(void *spec, int nx2, int ny, int rp_total, int 
   GIEM_FFT_DISPATCH(k_fft_y, sp, nx2, ny, rp_total, G, fd, twp, inverse);
   return hipGetLastError();
 }
+// the packed entries of each line in groups of 8 (128-byte runs), fewer
+// where a 2N-point transform of 8 sequences needs more than 16 elements per
+// thread
+hipError_t launch_parity_fft(const c128 *in, int64_t sj, int64_t sb, int nbatch, c128 *out,
+                             int64_t sk, int64_t ob, int n, int E, int nz, int axis,
+                             const FftDesc &fd, const void *tw, hipStream_t s) {
+  typedef double T;
+  if (fd.L != 2 * n || nbatch <= 0 || nbatch > 65535 || E <= 0) return hipErrorInvalidValue;
+  int G = 0, nthr = 0;
+  for (int nt : {256, 512}) {
+    for (int g : {8, 4, 2, 1})
+      if (fft_ept(g, fd.L, nt, PREC_FP64)) {
+        G = g;
+        break;
+      }
+    if (G) {
+      nthr = nt;
+      break;
+    }
+  }
+  if (!G) return hipErrorInvalidConfiguration;
+  dim3 grid((E + G - 1) / G, nbatch);
+  size_t lds = (size_t)G * fft_ld(fd.L) * sizeof(c128);
+  const c128 *twp = static_cast<const c128 *>(tw);
+  GIEM_FFT_DISPATCH(k_parity_fft, in, sj, sb, out, sk, ob, n, E, nz, axis, G, fd, twp);
+  return hipGetLastError();
+}
 #undef KX
 #undef GIEM_FFT_DISPATCH
 #undef GIEM_FFT_CASES
@@ -518,8 +601,22 @@ static hipError_t allow_lds_y() {
   return hipSuccess;
 }
 
+template <bool P2>
+static hipError_t allow_lds_parity() {
+  const void *ks[] = {(const void *)k_parity_fft<double, 4, 256, P2>, (const void *)k_parity_fft<double, 8, 256, P2>,
+                      (const void *)k_parity_fft<double, 16, 256, P2>, (const void *)k_parity_fft<double, 4, 512, P2>,
+                      (const void *)k_parity_fft<double, 8, 512, P2>, (const void *)k_parity_fft<double, 16, 512, P2>};
+  for (const void *k : ks) {
+    const hipError_t e = allow_lds(k);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t set_lds_limits() {
   hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = allow_lds_parity<true>();
+  if (e == hipSuccess) e = allow_lds_parity<false>();
   if (e == hipSuccess) e = allow_lds_x<double, true, c128>();
   if (e == hipSuccess) e = allow_lds_x<double, false, c128>();
   if (e == hipSuccess) e = allow_lds_x<float, true, c128>();

@@ -1,146 +1,10 @@
-// Set-up kernels: spectra of the packed table (Sect. 3.3: the stored
-// quantities are the discrete Fourier transforms Q~ of the blocks Q(i, j)),
-// the diagonals of A = S + R1 B R2 (Sect. 3.1) and the plane-wave right-hand
+// Set-up kernels: the complex64 copy of the spectra of the packed table
+// (the spectra themselves come from the FFT passes, kernels_apply.hip), the
+// diagonals of A = S + R1 B R2 (Sect. 3.1) and the plane-wave right-hand
 // side U^0 = sqrt(Re sb) <E^N> (Sect. 2.2).
 #include "kernels.h"
 
 namespace giem {
-
-// The zero-padded circulant of length 2N built from c(j), |j| < N, with
-// c(-j) = +-c(j) has the transform
-//   even:  c(0) + 2 sum_{j>=1} c(j) cos(pi K j / N)
-//   odd:       -2i sum_{j>=1} c(j) sin(pi K j / N)
-// for 0 <= K <= N (the other half follows from the same parity; Lemma 2
-// gives each class of the packed entries its parity in x and y).  Along one
-// axis this is a real (N + 1) x N matrix applied to every complex entry, so
-// each pass is a batch of FP64 MFMA products over the entries of one parity.
-
-typedef double d4 __attribute__((ext_vector_type(4)));
-
-// T[j][K] = 1 or 0 (j = 0) and 2 cos or 2 sin (pi K j / N) (j >= 1): the even
-// matrix at T, the odd one at T + N (N + 1)
-__global__ void k_parity_matrices(const c128 *__restrict__ cs, int n, double *__restrict__ T) {
-  const int np = n + 1;
-  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n * np;
-       idx += gridDim.x * blockDim.x) {
-    const int j = idx / np, K = idx % np;
-    const c128 t = cs[(int)(((long long)K * j) % (2 * n))];  // (cos, sin)(pi K j / n)
-    T[idx] = (j == 0) ? 1.0 : 2.0 * t.x;
-    T[(size_t)n * np + idx] = (j == 0) ? 0.0 : 2.0 * t.y;
-  }
-}
-
-// C[b][K][c] = sum_j T[j][K] B'[b][j][c] for K < m, j < k and the n doubles
-// c of a run of complex entries, with B' = B (even) or, for the odd
-// transform, B times -i: (x, y) -> (y, -x), i.e. column c reads column c ^ 1,
-// negated for the imaginary parts.  Workgroup: 4 waves, 64 x 64 outputs of
-// one batch entry b; wave w owns rows 32 (w >> 1), columns 32 (w & 1) as 2 x 2
-// 16x16x4 MFMA tiles.  The row tiles of a column panel are consecutive
-// workgroups, so the panel is read from HBM about once.
-template <bool ROT>
-__global__ __launch_bounds__(256) void k_parity_gemm(const double *__restrict__ T, int ldt,
-                                                     const double *__restrict__ B, int64_t ldb,
-                                                     int64_t sb, double *__restrict__ C,
-                                                     int64_t ldc, int64_t sc, int m, int n, int k) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int m0 = blockIdx.x * 64 + (w >> 1) * 32;
-  const int n0 = blockIdx.y * 64 + (w & 1) * 32;
-  B += (int64_t)blockIdx.z * sb;
-  C += (int64_t)blockIdx.z * sc;
-  const int li = lane & 15, lk = lane >> 4;
-  d4 acc[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-  const int ra0 = m0 + li, ra1 = m0 + 16 + li;
-  const int cb0 = n0 + li, cb1 = n0 + 16 + li;
-  const bool va0 = ra0 < m, va1 = ra1 < m, vb0 = cb0 < n, vb1 = cb1 < n;
-  // n is even, so c ^ 1 < n whenever c < n
-  const int sb0 = ROT ? (cb0 ^ 1) : cb0, sb1 = ROT ? (cb1 ^ 1) : cb1;
-  const double g0 = (ROT && (cb0 & 1)) ? -1.0 : 1.0, g1 = (ROT && (cb1 & 1)) ? -1.0 : 1.0;
-  for (int k0 = 0; k0 < k; k0 += 4) {
-    const int kk = k0 + lk;
-    const bool vk = kk < k;
-    const double *ar = T + (int64_t)kk * ldt;
-    const double *br = B + (int64_t)kk * ldb;
-    const double a0 = (vk && va0) ? ar[ra0] : 0.0;
-    const double a1 = (vk && va1) ? ar[ra1] : 0.0;
-    const double b0 = (vk && vb0) ? g0 * br[sb0] : 0.0;
-    const double b1 = (vk && vb1) ? g1 * br[sb1] : 0.0;
-    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-  }
-  // D[(lane >> 4) + 4 q][lane & 15] in register q
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) {
-      const int col = n0 + 16 * b + li;
-      if (col >= n) continue;
-      for (int q = 0; q < 4; ++q) {
-        const int row = m0 + 16 * a + lk + 4 * q;
-        if (row < m) C[(int64_t)row * ldc + col] = acc[a][b][q];
-      }
-    }
-}
-
-// One pass along the x or y axis (length n) over the runs of packed entries
-// with the same parity along it.  in/out: row
-// j (K) of batch entry b at in + b sb + j ldb (out + b sc + K ldc), in c128
-// units; E entries per row.
-hipError_t parity_pass(const c128 *in, int64_t ldb, int64_t sb, c128 *out, int64_t ldc, int64_t sc,
-                       int nbatch, const double *T, int n, int nz, bool x_axis, hipStream_t s) {
-  const int tri = nz * (nz + 1) / 2, nz2 = nz * nz;
-  // class runs: xx [0, tri), xy [tri, 2 tri), yy and zz [2 tri, 4 tri),
-  // xz [4 tri, 4 tri + nz2), yz [4 tri + nz2, E); xy is odd along both axes,
-  // xz only along x, yz only along y
-  const int lo[4] = {0, tri, 2 * tri, 4 * tri};
-  const int hi[4] = {tri, 2 * tri, 4 * tri, 4 * tri + 2 * nz2};
-  if (nbatch <= 0 || nbatch > 65535) return hipErrorInvalidValue;
-  const int np = n + 1;
-  const double *Te = T, *To = T + (size_t)n * np;
-  auto run = [&](int a, int b, bool odd) -> hipError_t {
-    if (b <= a) return hipSuccess;
-    const int nd = 2 * (b - a);
-    const dim3 grid((np + 63) / 64, (nd + 63) / 64, nbatch);
-    const double *Bp = reinterpret_cast<const double *>(in + a);
-    double *Cp = reinterpret_cast<double *>(out + a);
-    if (odd)
-      hipLaunchKernelGGL(k_parity_gemm<true>, grid, dim3(256), 0, s, To, np, Bp, 2 * ldb, 2 * sb, Cp,
-                         2 * ldc, 2 * sc, np, nd, n);
-    else
-      hipLaunchKernelGGL(k_parity_gemm<false>, grid, dim3(256), 0, s, Te, np, Bp, 2 * ldb, 2 * sb,
-                         Cp, 2 * ldc, 2 * sc, np, nd, n);
-    return hipGetLastError();
-  };
-  hipError_t e = hipSuccess;
-  // xx, xy, yy + zz
-  for (int r = 0; r < 3 && e == hipSuccess; ++r) e = run(lo[r], hi[r], r == 1);
-  // xz (odd along x) and yz (odd along y)
-  if (e == hipSuccess) e = run(lo[3], lo[3] + nz2, x_axis);
-  if (e == hipSuccess) e = run(lo[3] + nz2, hi[3], !x_axis);
-  return e;
-}
-
-hipError_t launch_parity_matrices(const c128 *cs, int n, double *T, hipStream_t s) {
-  hipLaunchKernelGGL(k_parity_matrices, dim3((n * (n + 1) + 255) / 256), dim3(256), 0, s, cs, n, T);
-  return hipGetLastError();
-}
-
-// tmp[i][K][e] = sum_j term_x(K, j) spatial[i][j][e],  0 <= K <= Nx
-hipError_t launch_spectral_x(const c128 *spatial, c128 *tmp, const double *Tx, int nx, int ny,
-                             int nz, hipStream_t s) {
-  const int64_t E = 2 * nz * (2 * nz + 1);
-  return parity_pass(spatial, E, (int64_t)nx * E, tmp, E, (int64_t)(nx + 1) * E, ny, Tx, nx, nz,
-                     true, s);
-}
-
-// spectral[Ky][K][e] = sum_i term_y(Ky, i) tmp[i][K][e],  0 <= Ky <= Ny
-hipError_t launch_spectral_y(const c128 *tmp, c128 *spectral, const double *Ty, int nx, int ny,
-                             int nz, hipStream_t s) {
-  const int64_t E = 2 * nz * (2 * nz + 1);
-  const int64_t row = (int64_t)(nx + 1) * E;
-  return parity_pass(tmp, row, E, spectral, row, E, nx + 1, Ty, ny, nz, false, s);
-}
 
 __global__ void k_to_c64(const c128 *__restrict__ src, c64 *__restrict__ dst, size_t n) {
   for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n;
