@@ -40,6 +40,8 @@ hipError_t launch_fft_x_inv(int prec, const VecPtrs32 &ptrs, const c128 *sd, con
 // (falls back to 1 where it does not fit, see block_two_per_cu), 4: the row of
 // the next point staged into a second LDS buffer during the current point's
 // MFMAs (falls back to 2, see block_dbl_supported)
+// Where the row does not fit LDS (Nz > 32 at R = 2) every nbuf takes the
+// band-pair kernel in FP32 and the gather kernel in FP64.
 hipError_t launch_block(int prec, const TabSet &tabs, int nf, const void *sin, void *sout,
                         const unsigned *plan, int nx, int ny, int nz, int R, int nbuf,
                         hipStream_t s);

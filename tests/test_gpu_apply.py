@@ -254,12 +254,19 @@ def test_block_product_every_rhs_count_at_deepest_grids(lib, nz):
     h.close()
 
 
-@pytest.mark.parametrize("nx,ny,nz,nrhs", [(4, 3, 40, 2), (3, 2, 32, 8), (2, 3, 33, 1)])
+@pytest.mark.parametrize("nx,ny,nz,nrhs", [(4, 3, 40, 2), (3, 2, 32, 8), (2, 3, 33, 1),
+                                            (2, 3, 47, 2), (3, 2, 64, 1), (2, 2, 40, 8),
+                                            (2, 2, 118, 2), (2, 3, 130, 2), (2, 2, 170, 8)])
 @pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 2e-5)])
-def test_apply_gather_block_product(lib, nx, ny, nz, nrhs, prec, tol):
+def test_apply_deep_block_product(lib, nx, ny, nz, nrhs, prec, tol):
     # shapes whose packed row and input fragments do not fit the pipelined
     # kernel (more than 32 layers, or 8 right-hand sides at 32 layers) take
-    # the gather kernel; same bar against the dense product
+    # the gather kernel in FP64 and the band-pair kernel in FP32: for the
+    # latter partial last bands (33, 47, 118, 130 levels),
+    # whole bands (64), up to 8 bands (three output tiles per wavefront) and
+    # 9 to 11 (six; 170 levels is the deepest grid a handle accepts), several
+    # vector groups (8 right-hand sides at up to four mirror points); same
+    # bar against the dense product
     import torch
     m, t, rng = _case(nx, ny, nz, 500 + nz + nrhs)
     h = lib.tables_import(m, [m["freq"]], t[None], flags=lib.TABLES_C64)
@@ -274,6 +281,18 @@ def test_apply_gather_block_product(lib, nx, ny, nz, nrhs, prec, tol):
     err = rel_err(yd.cpu().numpy(), ref)
     h.close()
     assert err <= tol, err
+
+
+def test_deepest_grid_limit(lib):
+    # 170 levels is the deepest grid: 171 is refused when the handle is made
+    import torch  # noqa: F401
+    for nz, ok in ((170, True), (171, False)):
+        m, t, _ = _case(1, 1, nz, 950 + nz)
+        if ok:
+            lib.tables_import(m, [m["freq"]], t[None]).close()
+        else:
+            with pytest.raises(lib.GiemError):
+                lib.tables_import(m, [m["freq"]], t[None])
 
 
 def test_profile_modes(lib):

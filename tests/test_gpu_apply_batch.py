@@ -4,7 +4,7 @@ spectra, the block product over (frequency, point) pairs):
   - against the oracle's dense product on each frequency's table;
   - bit for bit against separate giem_apply calls (every plane's transforms
     and every point's products do the same arithmetic in both);
-  - the gather block-product kernel (Nz > 32), the largest batch (32
+  - the block-product kernels for Nz > 32, the largest batch (32
     vectors), repeated and permuted frequency indices, modes A, A^T and B,
     FP64 and FP32;
   - argument errors."""
@@ -82,9 +82,9 @@ def test_apply_batch_equals_separate(lib, prec):
     h.close()
 
 
-def test_apply_batch_gather_kernel(lib):
-    # Nz = 33: the packed row no longer fits one workgroup's LDS, the block
-    # product gathers from global memory
+def test_apply_batch_deep_kernel(lib):
+    # Nz = 33: the packed row no longer fits one workgroup's LDS, the FP64
+    # block product gathers from global memory
     import torch
     nx, ny, nz, nrhs = 4, 3, 33, 2
     rng = np.random.default_rng(91)
@@ -109,6 +109,16 @@ def test_apply_batch_gather_kernel(lib):
         h.apply(xd[f], ys[f], sa, mode=lib.MODE_A, ifreq=q)
     torch.cuda.synchronize()
     assert torch.equal(yd, ys)
+    # FP32: the band-pair kernel over (frequency, point) tasks
+    h.apply_batch(xd, yd, sa, ifreqs=ifreqs, mode=lib.MODE_A, prec=lib.FP32)
+    for f, q in enumerate(ifreqs):
+        h.apply(xd[f], ys[f], sa, mode=lib.MODE_A, ifreq=q, prec=lib.FP32)
+    torch.cuda.synchronize()
+    assert torch.equal(yd, ys)
+    y = yd.cpu().numpy()
+    for f, q in enumerate(ifreqs):
+        ref = dense.apply_direct(dense.dense_from_packed(tabs[q], m), d, x[f], "A")
+        assert rel_err(y[f], ref) <= 2e-5
     h.close()
 
 

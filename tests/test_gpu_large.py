@@ -4,7 +4,7 @@ right-hand side, two plane-wave sources at 1 Hz), seven blocks of contrast up
 to 3.3e4, tables from giem_tables (35 GB of FP64 spectra plus a complex64
 copy).  Only internal checks are possible at this size:
   - the FP64 apply at sampled cells against the oracle's direct sum on the
-    exported table (gather block-product kernel, 352-point transforms with a
+    exported table (band-pair block-product kernel, 352-point transforms with a
     radix-11 pass, 448-point transforms);
   - the precision form against the FP64 solve (both GMRES(60) to 1e-7);
   - sigma_a = sigma_b (A = I) returns the normal field in one Arnoldi step,
