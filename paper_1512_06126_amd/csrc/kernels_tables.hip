@@ -367,7 +367,162 @@ __global__ __launch_bounds__(256) void k_vert_rows(vert::Model m, const double *
   vert::table_row(i, lam[l], m, c0, c0 + m.nz, G + (size_t)l * ncolc);
 }
 
+// Hankel weights (Sect. 3.1 horizontal integration, the lambda -> rho
+// transform h(rho) = int J0(lambda rho) g(lambda) dlambda): row rho of the
+// weight matrix sums, over the quadrature nodes of the lambda integral, the
+// node weight times J0(lambda rho) times the barycentric interpolation
+// weights of g at lambda on its panel of the logarithmic Chebyshev grid.
+// The nodes: [lambda_lo, z1 / rho] in halving subpanels (lambda_a as a
+// breakpoint), then the panels between consecutive zeros of J0 up to the
+// K-th, then the tail panels weighted by the averaged limit of the last
+// partial sums.  One thread per (rho, lambda panel) sums, in increasing
+// lambda, the nodes that fall into its panel, and writes that panel's 16
+// columns (plain and regularised: J0 - 1 below lambda_a).
+struct HankelArgs {
+  const double *zeros, *edges, *node, *bw, *rho, *g1x, *g1w, *g2x, *g2w, *beta;
+  int nzeros, npan, nr, ng1, ng2, nt;
+  double lam_lo, lam_a, lam_asym;
+};
+constexpr int kHankelN = 16;  // nodes per lambda panel
+constexpr double kPiD = 3.14159265358979323846;
+
+__device__ __forceinline__ void hankel_node(const HankelArgs &a, int p, double rho, double lam,
+                                            double w, double (&acc)[kHankelN],
+                                            double (&accr)[kHankelN]) {
+  const double u = log(lam);
+  // panel of lambda: last edge <= u (upper bound - 1), clamped
+  int lo = 0, hi = a.npan + 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a.edges[mid] > u) hi = mid;
+    else lo = mid + 1;
+  }
+  int pn = lo - 1;
+  pn = pn < 0 ? 0 : (pn > a.npan - 1 ? a.npan - 1 : pn);
+  if (pn != p) return;
+  const double e0 = a.edges[p], e1 = a.edges[p + 1];
+  const double sl = (2.0 * u - (e0 + e1)) / (e1 - e0);
+  double wi[kHankelN];
+  double tot = 0.0;
+  int hit = -1;
+#pragma unroll
+  for (int j = 0; j < kHankelN; ++j) {
+    const double d = sl - a.node[j];
+    if (fabs(d) < 1e-14) hit = j;
+    wi[j] = hit >= 0 ? 0.0 : a.bw[j] / d;
+    tot += wi[j];
+  }
+#pragma unroll
+  for (int j = 0; j < kHankelN; ++j) wi[j] = hit >= 0 ? (j == hit ? 1.0 : 0.0) : wi[j] / tot;
+  const double jv = j0(lam * rho);
+  const double jr = lam < a.lam_a ? jv - 1.0 : jv;
+#pragma unroll
+  for (int q = 0; q < kHankelN; ++q) {
+    acc[q] += w * jv * wi[q];
+    accr[q] += w * jr * wi[q];
+  }
+}
+
+__global__ __launch_bounds__(128) void k_hankel_weights(HankelArgs a, double *__restrict__ Wt,
+                                                        double *__restrict__ Wt_reg) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)a.nr * a.npan) return;
+  const int p = (int)(idx % a.npan), ir = (int)(idx / a.npan);
+  const double rho = a.rho[ir];
+  // the panel's lambda range, widened (the node filter is exact)
+  const double Llo = p == 0 ? 0.0 : exp(a.edges[p]) * (1.0 - 1e-9);
+  const double Lhi = p == a.npan - 1 ? INFINITY : exp(a.edges[p + 1]) * (1.0 + 1e-9);
+  double acc[kHankelN], accr[kHankelN];
+#pragma unroll
+  for (int q = 0; q < kHankelN; ++q) acc[q] = accr[q] = 0.0;
+  const double l1 = a.zeros[0] / rho;
+  if (Llo <= l1) {
+    // subpanels [lam_lo, l1 / 2^M], ..., [l1 / 2, l1] (exact halvings), the
+    // one holding lambda_a split there
+    int M = 0;
+    while (ldexp(l1, -M) / 2.0 > a.lam_lo) ++M;
+    for (int m = M; m >= 0; --m) {
+      const double a0 = m == M ? a.lam_lo : ldexp(l1, -(m + 1)), b0 = ldexp(l1, -m);
+      if (b0 < Llo || a0 > Lhi) continue;
+      const bool split = a.lam_a > a0 && a.lam_a < b0;
+      for (int piece = 0; piece < (split ? 2 : 1); ++piece) {
+        const double pa = split && piece == 1 ? a.lam_a : a0;
+        const double pb = split && piece == 0 ? a.lam_a : b0;
+        for (int q = 0; q < a.ng1; ++q) {
+          const double lam = 0.5 * (pa + pb) + 0.5 * (pb - pa) * a.g1x[q];
+          hankel_node(a, p, rho, lam, 0.5 * (pb - pa) * a.g1w[q], acc, accr);
+        }
+      }
+    }
+  }
+  // panels k = 1 .. K - 1 + nt between zeros k - 1 and k (the last nt the
+  // tail, weighted by beta)
+  const int K = (int)ceil(a.lam_asym * rho / kPiD) + 1;
+  const int klast = K - 1 + a.nt;
+  // first k with zeros[k] / rho >= Llo, last k with zeros[k - 1] / rho <= Lhi
+  int lo = 1, hi = klast + 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a.zeros[mid] / rho >= Llo) hi = mid;
+    else lo = mid + 1;
+  }
+  const int kmin = lo;
+  lo = kmin;
+  hi = klast + 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a.zeros[mid - 1] / rho <= Lhi) lo = mid + 1;
+    else hi = mid;
+  }
+  const int kmax = lo - 1;
+  for (int k = kmin; k <= kmax; ++k) {
+    const double za = a.zeros[k - 1] / rho, zb = a.zeros[k] / rho;
+    const double scale = k < K ? 1.0 : a.beta[k - K];
+    for (int q = 0; q < a.ng2; ++q) {
+      const double lam = 0.5 * (za + zb) + 0.5 * (zb - za) * a.g2x[q];
+      hankel_node(a, p, rho, lam, scale * 0.5 * (zb - za) * a.g2w[q], acc, accr);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kHankelN; ++q) {
+    Wt[(size_t)(p * kHankelN + q) * a.nr + ir] = acc[q];
+    Wt_reg[(size_t)(p * kHankelN + q) * a.nr + ir] = accr[q];
+  }
+}
+
 }  // namespace
+
+hipError_t launch_hankel_weights(const double *args, int nzeros, int npan, int nr, int ng1, int ng2,
+                                 int nt, double lam_lo, double lam_a, double lam_asym, double *Wt,
+                                 double *Wt_reg, hipStream_t s) {
+  // args: zeros [nzeros], edges [npan + 1], node [16], bw [16], rho [nr],
+  // g1x, g1w [ng1], g2x, g2w [ng2], beta [nt]
+  HankelArgs a;
+  a.zeros = args;
+  a.edges = a.zeros + nzeros;
+  a.node = a.edges + npan + 1;
+  a.bw = a.node + kHankelN;
+  a.rho = a.bw + kHankelN;
+  a.g1x = a.rho + nr;
+  a.g1w = a.g1x + ng1;
+  a.g2x = a.g1w + ng1;
+  a.g2w = a.g2x + ng2;
+  a.beta = a.g2w + ng2;
+  a.nzeros = nzeros;
+  a.npan = npan;
+  a.nr = nr;
+  a.ng1 = ng1;
+  a.ng2 = ng2;
+  a.nt = nt;
+  a.lam_lo = lam_lo;
+  a.lam_a = lam_a;
+  a.lam_asym = lam_asym;
+  const int64_t n = (int64_t)nr * npan;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hankel_weights, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, s, a, Wt,
+                     Wt_reg);
+  return hipGetLastError();
+}
 
 hipError_t launch_vertical_rows(const vert::Model &m, const double *lam, int nl, vert::zc *eta,
                                 double *L, vert::zc *p, vert::zc *q, vert::Cell *cells,

@@ -58,6 +58,9 @@ hipError_t launch_assemble_rec(const c128 *c, c128 *out, int noff, int nz, doubl
 hipError_t launch_vertical_rows(const vert::Model &m, const double *lam, int nl, vert::zc *eta,
                                 double *L, vert::zc *p, vert::zc *q, vert::Cell *cells,
                                 vert::zc *G, int ncolc, hipStream_t s);
+hipError_t launch_hankel_weights(const double *args, int nzeros, int npan, int nr, int ng1, int ng2,
+                                 int nt, double lam_lo, double lam_a, double lam_asym, double *Wt,
+                                 double *Wt_reg, hipStream_t s);
 
 namespace {
 
@@ -276,17 +279,33 @@ Grids make_grids(const giem_handle *t) {
   return g;
 }
 
+struct DevBuf {
+  void *p = nullptr;
+  ~DevBuf() {
+    if (p) hipFree(p);
+  }
+  hipError_t alloc(size_t bytes) { return hipMalloc(&p, bytes); }
+  double *d() { return static_cast<double *>(p); }
+  c128 *c() { return static_cast<c128 *>(p); }
+};
+
 // Hankel weights: rows Wt[lam][rho] (transposed for the GEMM) for the plain
-// transform and for the regularised one.
-void hankel_weights(const Grids &g, std::vector<double> &Wt, std::vector<double> &Wt_reg) {
-  const size_t nl = g.lam.size(), nr = g.rho.size();
-  Wt.assign(nl * nr, 0.0);
-  Wt_reg.assign(nl * nr, 0.0);
+// transform and for the regularised one, computed on the GPU
+// (launch_hankel_weights) from what is set up here: the zeros of J0 that the
+// panels need, the lambda grid, the rho nodes, the Gauss-Legendre rules of
+// the first and the main panels, and the tail weights beta_i, the averaged
+// limit of the last partial sums (binomial averaging over `levels` levels).
+int hankel_weights(const Grids &g, double *dWt, double *dWt_reg, hipStream_t s) {
+  const size_t nr = g.rho.size();
+  const int npan = (int)g.lam.edges.size() - 1;
+  if (g.lam.n != 16) {
+    set_error("giem_tables: the lambda grid must have 16 nodes per panel");
+    return GIEM_EINVAL;
+  }
   const double rho_max = g.rho.x.back();
   const int kmax = (int)std::ceil(g.lam_asym * rho_max / kPi) + 1;
   const std::vector<double> zeros = j0_zeros(kmax + g.ntail + 2);
   const Rule r1 = gauss_legendre(g.ngl_first), r2 = gauss_legendre(g.ngl_main);
-  // averaged limit of the last partial sums: weight of the tail panel i
   const int nt = g.ntail, lv = std::min(g.levels, nt - 1);
   std::vector<double> c(nt, 0.0), beta(nt, 0.0);
   {
@@ -299,48 +318,33 @@ void hankel_weights(const Grids &g, std::vector<double> &Wt, std::vector<double>
       beta[i] = acc;
     }
   }
-  parallel_for((int)nr, [&](int ir) {
-    const double rho = g.rho.x[ir];
-    std::vector<double> row(nl, 0.0), row_reg(nl, 0.0);
-    double wi[32];
-    auto add = [&](double lam, double w, bool reg_part) {
-      const double j = std::cyl_bessel_j(0.0, lam * rho);
-      const size_t c0 = g.lam.interp(lam, wi);
-      for (int q = 0; q < g.lam.n; ++q) {
-        row[c0 + q] += w * j * wi[q];
-        row_reg[c0 + q] += w * (reg_part ? j - 1.0 : j) * wi[q];
-      }
-    };
-    const int K = (int)std::ceil(g.lam_asym * rho / kPi) + 1;
-    const double l1 = zeros[0] / rho;
-    // [lam_lo, l1] in halving subpanels, with lam_a as a breakpoint
-    std::vector<double> brk{l1};
-    while (brk.back() / 2.0 > g.lam_lo) brk.push_back(brk.back() / 2.0);
-    brk.push_back(g.lam_lo);
-    if (g.lam_a > g.lam_lo && g.lam_a < l1) brk.push_back(g.lam_a);
-    std::sort(brk.begin(), brk.end());
-    brk.erase(std::unique(brk.begin(), brk.end()), brk.end());
-    for (size_t p = 0; p + 1 < brk.size(); ++p) {
-      const double a = brk[p], b = brk[p + 1];
-      for (int q = 0; q < g.ngl_first; ++q) {
-        const double lam = 0.5 * (a + b) + 0.5 * (b - a) * r1.x[q];
-        add(lam, 0.5 * (b - a) * r1.w[q], lam < g.lam_a);
-      }
-    }
-    // panels between consecutive zeros up to the K-th zero, then the tail
-    auto panel = [&](double a, double b, double scale) {
-      for (int q = 0; q < g.ngl_main; ++q) {
-        const double lam = 0.5 * (a + b) + 0.5 * (b - a) * r2.x[q];
-        add(lam, scale * 0.5 * (b - a) * r2.w[q], lam < g.lam_a);
-      }
-    };
-    for (int k = 1; k < K; ++k) panel(zeros[k - 1] / rho, zeros[k] / rho, 1.0);
-    for (int i = 0; i < nt; ++i) panel(zeros[K - 1 + i] / rho, zeros[K + i] / rho, beta[i]);
-    for (size_t l = 0; l < nl; ++l) {
-      Wt[l * nr + ir] = row[l];
-      Wt_reg[l * nr + ir] = row_reg[l];
-    }
-  });
+  std::vector<double> args;
+  auto put = [&](const std::vector<double> &v) { args.insert(args.end(), v.begin(), v.end()); };
+  put(zeros);
+  put(g.lam.edges);
+  put(g.lam.node);
+  put(g.lam.bw);
+  put(g.rho.x);
+  put(r1.x);
+  put(r1.w);
+  put(r2.x);
+  put(r2.w);
+  put(beta);
+  DevBuf dargs;
+  if (dargs.alloc(args.size() * 8) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("giem_tables: out of device memory");
+    return GIEM_ENOMEM;
+  }
+  if (check_hip(hipMemcpyAsync(dargs.p, args.data(), args.size() * 8, hipMemcpyHostToDevice, s),
+                "upload Hankel rules") ||
+      check_hip(launch_hankel_weights(dargs.d(), (int)zeros.size(), npan, (int)nr, (int)r1.x.size(),
+                                      (int)r2.x.size(), nt, g.lam_lo, g.lam_a, g.lam_asym, dWt,
+                                      dWt_reg, s),
+                "Hankel weights") ||
+      check_hip(hipStreamSynchronize(s), "Hankel weights"))  // before dargs is freed
+    return GIEM_EHIP;
+  return GIEM_OK;
 }
 
 // ----------------------------------------------------- horizontal rules
@@ -944,15 +948,6 @@ struct Vertical {
   }
 };
 
-struct DevBuf {
-  void *p = nullptr;
-  ~DevBuf() {
-    if (p) hipFree(p);
-  }
-  hipError_t alloc(size_t bytes) { return hipMalloc(&p, bytes); }
-  double *d() { return static_cast<double *>(p); }
-  c128 *c() { return static_cast<c128 *>(p); }
-};
 
 }  // namespace
 
@@ -967,9 +962,8 @@ int compute_tables(giem_handle *t, hipStream_t s) {
   }
   const Grids g = make_grids(t);
   const size_t nl = g.lam.size(), nr = g.rho.size();
-  std::vector<double> Wt, Wt_reg, Mt;
+  std::vector<double> Mt;
   std::vector<int> kcol;
-  hankel_weights(g, Wt, Wt_reg);
   spatial_matrix(t, g, Mt, kcol);
   // contraction ranges of the three spatial GEMMs' row tiles
   std::vector<int> kr = tile_ranges(kcol, 0, (int)noff);
@@ -1003,7 +997,7 @@ int compute_tables(giem_handle *t, hipStream_t s) {
   }
   const size_t nws = nl * nlayers;  // (node, layer) pairs
   DevBuf dW, dWr, dM, dG, dH, dc0, dc1, dc2, dmod, dlay, dws, dcell, dkr;
-  if (dW.alloc(Wt.size() * 8) != hipSuccess || dWr.alloc(Wt_reg.size() * 8) != hipSuccess ||
+  if (dW.alloc(nl * nr * 8) != hipSuccess || dWr.alloc(nl * nr * 8) != hipSuccess ||
       dM.alloc(Mt.size() * 8) != hipSuccess || dG.alloc(nl * ncolc * 16) != hipSuccess ||
       dH.alloc(nr * ncolc * 16) != hipSuccess || dc0.alloc(noff * 2 * T * 16) != hipSuccess ||
       dc1.alloc(3 * noff * T * 16) != hipSuccess || dc2.alloc(2 * noff * nz2 * 16) != hipSuccess ||
@@ -1015,11 +1009,11 @@ int compute_tables(giem_handle *t, hipStream_t s) {
     set_error("giem_tables: out of device memory");
     return GIEM_ENOMEM;
   }
-  if (check_hip(hipMemcpyAsync(dW.p, Wt.data(), Wt.size() * 8, hipMemcpyHostToDevice, s),
-                "upload Hankel weights") ||
-      check_hip(hipMemcpyAsync(dWr.p, Wt_reg.data(), Wt_reg.size() * 8, hipMemcpyHostToDevice, s),
-                "upload Hankel weights") ||
-      check_hip(hipMemcpyAsync(dM.p, Mt.data(), Mt.size() * 8, hipMemcpyHostToDevice, s),
+  {
+    const int rc = hankel_weights(g, dW.d(), dWr.d(), s);
+    if (rc != GIEM_OK) return rc;
+  }
+  if (check_hip(hipMemcpyAsync(dM.p, Mt.data(), Mt.size() * 8, hipMemcpyHostToDevice, s),
                 "upload spatial weights") ||
       check_hip(hipMemcpyAsync(dmod.p, model.data(), nmod * 8, hipMemcpyHostToDevice, s),
                 "upload layered model") ||
@@ -1091,9 +1085,8 @@ int compute_receiver_kernels(giem_handle *t, int ifreq, double z0, void **out, h
   const int nf = 8 * nz;  // complex functions per lambda
   const Grids g = make_grids(t);
   const size_t nl = g.lam.size(), nr = g.rho.size();
-  std::vector<double> Wt, Wt_reg, Mt(nr * R_COUNT * noff, 0.0);
+  std::vector<double> Mt(nr * R_COUNT * noff, 0.0);
   std::vector<int> kcol(2 * R_COUNT * noff);
-  hankel_weights(g, Wt, Wt_reg);
   {
     const Rule gs = gauss_legendre(24), g14 = gauss_legendre(14), g8 = gauss_legendre(8);
     const Rule gl = gauss_legendre(24);
@@ -1127,7 +1120,7 @@ int compute_receiver_kernels(giem_handle *t, int ifreq, double z0, void **out, h
   const std::vector<int> kr = tile_ranges(kcol, 0, (int)(R_COUNT * noff));
   DevBuf dW, dWr, dM, dG, dH, dC, dkr;
   void *dK = nullptr;
-  if (dW.alloc(Wt.size() * 8) != hipSuccess || dWr.alloc(Wt_reg.size() * 8) != hipSuccess ||
+  if (dW.alloc(nl * nr * 8) != hipSuccess || dWr.alloc(nl * nr * 8) != hipSuccess ||
       dM.alloc(Mt.size() * 8) != hipSuccess || dG.alloc(G.size() * 16) != hipSuccess ||
       dH.alloc(nr * nf * 16) != hipSuccess || dC.alloc((size_t)R_COUNT * noff * nf * 16) != hipSuccess ||
       dkr.alloc(kr.size() * sizeof(int)) != hipSuccess ||
@@ -1140,9 +1133,14 @@ int compute_receiver_kernels(giem_handle *t, int ifreq, double z0, void **out, h
   const int64_t ldg = 2 * (int64_t)nf;
   const int64_t ldm = (int64_t)R_COUNT * noff;
   int rc = GIEM_OK;
-  if (check_hip(hipMemcpyAsync(dW.p, Wt.data(), Wt.size() * 8, hipMemcpyHostToDevice, s), "upload") ||
-      check_hip(hipMemcpyAsync(dWr.p, Wt_reg.data(), Wt_reg.size() * 8, hipMemcpyHostToDevice, s), "upload") ||
-      check_hip(hipMemcpyAsync(dM.p, Mt.data(), Mt.size() * 8, hipMemcpyHostToDevice, s), "upload") ||
+  {
+    const int hrc = hankel_weights(g, dW.d(), dWr.d(), s);
+    if (hrc != GIEM_OK) {
+      hipFree(dK);
+      return hrc;
+    }
+  }
+  if (check_hip(hipMemcpyAsync(dM.p, Mt.data(), Mt.size() * 8, hipMemcpyHostToDevice, s), "upload") ||
       check_hip(hipMemcpyAsync(dG.p, G.data(), G.size() * 16, hipMemcpyHostToDevice, s), "upload") ||
       check_hip(hipMemcpyAsync(dkr.p, kr.data(), kr.size() * sizeof(int), hipMemcpyHostToDevice, s),
                 "upload") ||
