@@ -490,7 +490,234 @@ __global__ __launch_bounds__(128) void k_hankel_weights(HankelArgs a, double *__
   }
 }
 
+// Spatial fold matrix (Appendix A, the horizontal Galerkin integrals as
+// convolutions of the radial functions with the footprint autocorrelation
+// phi): column (kind, offset) holds, over the rho nodes, the quadrature
+// weights of int w_kind(u, v) h(|D - (u, v)|) du dv (kinds phi, d_x phi,
+// d_y phi, d_xy phi over the four quadrants of phi's support) or of the
+// line integrals of -d_xx phi and -d_yy phi, each weight spread over the
+// barycentric interpolation weights of h on its rho panel.  One thread per
+// column (the columns are disjoint): quadrants with the singular vertex at D
+// by two triangles with a graded radial variable (tanh-sinh), the others by
+// tensor Gauss-Legendre rules (14 points within 2 h of D, split in 2 x 2
+// within h / 2, 8 points beyond); lines by Gauss-Legendre pieces, the ends
+// at D by the radial rule.  Weights of one rho panel are summed in
+// registers and added to the column when the panel changes.
+struct FoldArgs {
+  const double *edges, *node, *bw;  // rho grid: npan + 1 edges, 12 nodes per panel
+  const double *gs_x, *gs_w, *g14_x, *g14_w, *g8_x, *g8_w, *rad_x, *rad_w;
+  int npan, nrad, nx, ny;
+  double hx, hy, rho_min;
+};
+constexpr int kFoldN = 12;
+enum { F_W0 = 0, F_XX, F_YY, F_XY, F_X, F_Y, F_COUNT };
+
+struct FoldAcc {
+  double acc[kFoldN];
+  int cur, lo, hi;
+};
+
+__device__ __forceinline__ void fold_flush(FoldAcc &f, double *Mt, int64_t ncol, int64_t col) {
+  if (f.cur < 0) return;
+#pragma unroll
+  for (int k = 0; k < kFoldN; ++k) {
+    Mt[(int64_t)(f.cur * kFoldN + k) * ncol + col] += f.acc[k];
+    f.acc[k] = 0.0;
+  }
+}
+
+__device__ __forceinline__ void fold_emit(const FoldArgs &a, FoldAcc &f, double r, double w,
+                                          double *Mt, int64_t ncol, int64_t col) {
+  const double u = log(r > a.rho_min ? r : a.rho_min);
+  int lo = 0, hi = a.npan + 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a.edges[mid] > u) hi = mid;
+    else lo = mid + 1;
+  }
+  int p = lo - 1;
+  p = p < 0 ? 0 : (p > a.npan - 1 ? a.npan - 1 : p);
+  if (p != f.cur) {
+    fold_flush(f, Mt, ncol, col);
+    f.cur = p;
+    f.lo = min(f.lo, p * kFoldN);
+    f.hi = max(f.hi, p * kFoldN + kFoldN);
+  }
+  const double e0 = a.edges[p], e1 = a.edges[p + 1];
+  const double sl = (2.0 * u - (e0 + e1)) / (e1 - e0);
+  double wi[kFoldN];
+  double tot = 0.0;
+  int hit = -1;
+#pragma unroll
+  for (int j = 0; j < kFoldN; ++j) {
+    const double d = sl - a.node[j];
+    if (fabs(d) < 1e-14) hit = j;
+    wi[j] = hit >= 0 ? 0.0 : a.bw[j] / d;
+    tot += wi[j];
+  }
+#pragma unroll
+  for (int j = 0; j < kFoldN; ++j)
+    f.acc[j] += w * (hit >= 0 ? (j == hit ? 1.0 : 0.0) : wi[j] / tot);
+}
+
+__device__ __forceinline__ double fold_weight(int kind, double u, double v, double su, double sv,
+                                              double hx, double hy) {
+  switch (kind) {
+    case F_W0: return (hx - fabs(u)) * (hy - fabs(v));
+    case F_X: return -su * (hy - fabs(v));
+    case F_Y: return -sv * (hx - fabs(u));
+    default: return -su * sv;  // F_XY
+  }
+}
+
+__global__ __launch_bounds__(128) void k_spatial_fold(FoldArgs a, double *__restrict__ Mt,
+                                                      int *__restrict__ kcol) {
+  const int64_t noff = (int64_t)a.nx * a.ny, ncol = F_COUNT * noff;
+  const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= ncol) return;
+  const int kind = (int)(col / noff), o = (int)(col - kind * noff);
+  const double dx = (o % a.nx) * a.hx, dy = (o / a.nx) * a.hy;
+  const double hx = a.hx, hy = a.hy;
+  FoldAcc f;
+  f.cur = -1;
+  f.lo = 1 << 30;
+  f.hi = 0;
+#pragma unroll
+  for (int k = 0; k < kFoldN; ++k) f.acc[k] = 0.0;
+  if (kind == F_XX || kind == F_YY) {
+    // -d_xx phi = -(delta(u + hx) - 2 delta(u) + delta(u - hx)) (hy - |v|)
+    // (and with x, y exchanged): three lines along the other axis
+    const double dfix = kind == F_XX ? dx : dy, drun = kind == F_XX ? dy : dx;
+    const double hfix = kind == F_XX ? hx : hy, hrun = kind == F_XX ? hy : hx;
+    for (int c = -1; c <= 1; ++c) {
+      const double wc = c == 0 ? 2.0 : -1.0;
+      const double off = dfix - c * hfix;
+      double cuts[4] = {-hrun, 0.0, hrun, 0.0};
+      int nc = 3;
+      if (drun > -hrun && drun < hrun && drun != 0.0) {
+        // insert drun in order
+        cuts[3] = hrun;
+        if (drun < 0.0) {
+          cuts[2] = 0.0;
+          cuts[1] = drun;
+        } else {
+          cuts[2] = drun;
+        }
+        nc = 4;
+      }
+      const bool on_line = fabs(off) < 1e-12 * hfix;
+      for (int pc = 0; pc + 1 < nc; ++pc) {
+        const double pa = cuts[pc], pb = cuts[pc + 1];
+        const bool sa = on_line && fabs(pa - drun) < 1e-12 * hrun;
+        const bool sb = on_line && fabs(pb - drun) < 1e-12 * hrun;
+        if (sa || sb) {
+          // logarithmic singularity at the end pa (sa) or pb (sb)
+          for (int i = 0; i < a.nrad; ++i) {
+            const double v = sa ? pa + (pb - pa) * a.rad_x[i] : pb - (pb - pa) * a.rad_x[i];
+            fold_emit(a, f, hypot(off, drun - v), wc * (pb - pa) * a.rad_w[i] * (hrun - fabs(v)),
+                      Mt, ncol, col);
+          }
+          continue;
+        }
+        for (int i = 0; i < 24; ++i) {
+          const double v = 0.5 * (pa + pb) + 0.5 * (pb - pa) * a.gs_x[i];
+          const double wv = 0.5 * (pb - pa) * a.gs_w[i];
+          fold_emit(a, f, hypot(off, drun - v), wc * wv * (hrun - fabs(v)), Mt, ncol, col);
+        }
+      }
+    }
+  } else {
+    for (int sx = -1; sx <= 1; sx += 2)
+      for (int sy = -1; sy <= 1; sy += 2) {
+        const double x0 = fmin(0.0, sx * hx), x1 = fmax(0.0, sx * hx);
+        const double y0 = fmin(0.0, sy * hy), y1 = fmax(0.0, sy * hy);
+        const double tx = 1e-9 * hx, ty = 1e-9 * hy;
+        int sing = -1;
+        const double vx[2] = {x0, x1}, vy[2] = {y0, y1};
+        for (int ia = 0; ia < 2; ++ia)
+          for (int ib = 0; ib < 2; ++ib)
+            if (fabs(vx[ia] - dx) < tx && fabs(vy[ib] - dy) < ty) sing = 2 * ia + ib;
+        if (sing >= 0) {
+          // two triangles from the singular vertex P, graded radial variable
+          const double px = vx[sing >> 1], py = vy[sing & 1];
+          const double ox = vx[1 - (sing >> 1)], oy = vy[1 - (sing & 1)];
+          for (int tri = 0; tri < 2; ++tri) {
+            const double cx = tri == 0 ? ox : px, cy = tri == 0 ? py : oy;  // adjacent corner
+            const double e1x = cx - px, e1y = cy - py;
+            const double e2x = ox - cx, e2y = oy - cy;
+            const double det = fabs(e1x * e2y - e1y * e2x);
+            for (int i = 0; i < a.nrad; ++i) {
+              const double r = a.rad_x[i], wr = a.rad_w[i];
+              for (int j = 0; j < 24; ++j) {
+                const double tt = 0.5 * (a.gs_x[j] + 1.0), wt = 0.5 * a.gs_w[j];
+                const double uu = px + r * (e1x + tt * e2x), vv = py + r * (e1y + tt * e2y);
+                fold_emit(a, f, hypot(dx - uu, dy - vv),
+                          wr * wt * r * det * fold_weight(kind, uu, vv, sx, sy, hx, hy), Mt, ncol,
+                          col);
+              }
+            }
+          }
+          continue;
+        }
+        const double ddx = fmax(fmax(x0 - dx, 0.0), dx - x1);
+        const double ddy = fmax(fmax(y0 - dy, 0.0), dy - y1);
+        const double dist = hypot(ddx, ddy), hm = fmin(hx, hy);
+        const bool near = dist < 2.0 * hm;
+        const double *rx = near ? a.g14_x : a.g8_x, *rw = near ? a.g14_w : a.g8_w;
+        const int n = near ? 14 : 8;
+        const int split = dist < 0.5 * hm ? 2 : 1;
+        for (int ia = 0; ia < split; ++ia)
+          for (int ib = 0; ib < split; ++ib) {
+            const double xa = x0 + (x1 - x0) * ia / split, xb = x0 + (x1 - x0) * (ia + 1) / split;
+            const double ya = y0 + (y1 - y0) * ib / split, yb = y0 + (y1 - y0) * (ib + 1) / split;
+            for (int i = 0; i < n; ++i)
+              for (int j = 0; j < n; ++j) {
+                const double uu = 0.5 * (xa + xb) + 0.5 * (xb - xa) * rx[i];
+                const double vv = 0.5 * (ya + yb) + 0.5 * (yb - ya) * rx[j];
+                fold_emit(a, f, hypot(dx - uu, dy - vv),
+                          0.25 * (xb - xa) * (yb - ya) * rw[i] * rw[j] *
+                              fold_weight(kind, uu, vv, sx, sy, hx, hy),
+                          Mt, ncol, col);
+              }
+          }
+      }
+  }
+  fold_flush(f, Mt, ncol, col);
+  kcol[2 * col] = f.lo < f.hi ? f.lo : 0;
+  kcol[2 * col + 1] = f.lo < f.hi ? f.hi : 0;
+}
+
 }  // namespace
+
+hipError_t launch_spatial_fold(const double *args, int npan, int nrad, int nx, int ny, double hx,
+                               double hy, double rho_min, double *Mt, int *kcol, hipStream_t s) {
+  // args: edges [npan + 1], node [12], bw [12], Gauss-Legendre 24, 14, 8 (x
+  // then w), radial rule [nrad] (x then w); Mt zeroed by the caller
+  FoldArgs a;
+  a.edges = args;
+  a.node = a.edges + npan + 1;
+  a.bw = a.node + kFoldN;
+  a.gs_x = a.bw + kFoldN;
+  a.gs_w = a.gs_x + 24;
+  a.g14_x = a.gs_w + 24;
+  a.g14_w = a.g14_x + 14;
+  a.g8_x = a.g14_w + 14;
+  a.g8_w = a.g8_x + 8;
+  a.rad_x = a.g8_w + 8;
+  a.rad_w = a.rad_x + nrad;
+  a.npan = npan;
+  a.nrad = nrad;
+  a.nx = nx;
+  a.ny = ny;
+  a.hx = hx;
+  a.hy = hy;
+  a.rho_min = rho_min;
+  const int64_t ncol = (int64_t)F_COUNT * nx * ny;
+  if (ncol <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_spatial_fold, dim3((unsigned)((ncol + 127) / 128)), dim3(128), 0, s, a, Mt,
+                     kcol);
+  return hipGetLastError();
+}
 
 hipError_t launch_hankel_weights(const double *args, int nzeros, int npan, int nr, int ng1, int ng2,
                                  int nt, double lam_lo, double lam_a, double lam_asym, double *Wt,

@@ -61,6 +61,8 @@ hipError_t launch_vertical_rows(const vert::Model &m, const double *lam, int nl,
 hipError_t launch_hankel_weights(const double *args, int nzeros, int npan, int nr, int ng1, int ng2,
                                  int nt, double lam_lo, double lam_a, double lam_asym, double *Wt,
                                  double *Wt_reg, hipStream_t s);
+hipError_t launch_spatial_fold(const double *args, int npan, int nrad, int nx, int ny, double hx,
+                               double hy, double rho_min, double *Mt, int *kcol, hipStream_t s);
 
 namespace {
 
@@ -350,23 +352,6 @@ int hankel_weights(const Grids &g, double *dWt, double *dWt_reg, hipStream_t s) 
 // ----------------------------------------------------- horizontal rules
 enum { K_W0 = 0, K_XX, K_YY, K_XY, K_X, K_Y, K_COUNT };
 
-struct RulePts {
-  std::vector<double> rho, w;
-  void add(double r, double wt) {
-    rho.push_back(r);
-    w.push_back(wt);
-  }
-};
-
-inline double weight_fn(int kind, double u, double v, double su, double sv, double hx, double hy) {
-  switch (kind) {
-    case K_W0: return (hx - std::fabs(u)) * (hy - std::fabs(v));
-    case K_X: return -su * (hy - std::fabs(v));
-    case K_Y: return -sv * (hx - std::fabs(u));
-    default: return -su * sv;  // K_XY
-  }
-}
-
 // radial variable of the two triangles at a singular vertex (integrand
 // r h(r ...), h ~ ln r) and the singular ends of the line rules
 const Rule &radial_rule() {
@@ -374,140 +359,51 @@ const Rule &radial_rule() {
   return r;
 }
 
-// int over the quadrant [x0,x1]x[y0,y1] of weight * h(|D - r'|); the
-// integrand is singular only when D is a vertex of the quadrant.
-void quadrant_rule(int kind, double dx, double dy, double x0, double x1, double y0, double y1,
-                   double su, double sv, double hx, double hy, const Rule &gs, const Rule &g14,
-                   const Rule &g8, RulePts &out) {
-  const double tx = 1e-9 * hx, ty = 1e-9 * hy;
-  int sing = -1;
-  const double vx[2] = {x0, x1}, vy[2] = {y0, y1};
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b)
-      if (std::fabs(vx[a] - dx) < tx && std::fabs(vy[b] - dy) < ty) sing = 2 * a + b;
-  auto emit = [&](double u, double v, double wq) {
-    const double wk = weight_fn(kind, u, v, su, sv, hx, hy);
-    out.add(std::hypot(dx - u, dy - v), wq * wk);
-  };
-  if (sing >= 0) {
-    // two triangles from the singular vertex P, radial variable r = s^2
-    const double px = vx[sing >> 1], py = vy[sing & 1];
-    const double ox = vx[1 - (sing >> 1)], oy = vy[1 - (sing & 1)];
-    const double ax[2] = {ox, px}, ay[2] = {py, oy};  // the two adjacent corners
-    const int n = (int)gs.x.size();
-    const Rule &rad = radial_rule();
-    for (int tri = 0; tri < 2; ++tri) {
-      const double e1x = ax[tri] - px, e1y = ay[tri] - py;
-      const double e2x = ox - ax[tri], e2y = oy - ay[tri];
-      const double det = std::fabs(e1x * e2y - e1y * e2x);
-      for (size_t i = 0; i < rad.x.size(); ++i) {
-        const double r = rad.x[i], wr = rad.w[i];
-        for (int j = 0; j < n; ++j) {
-          const double tt = 0.5 * (gs.x[j] + 1.0), wt = 0.5 * gs.w[j];
-          const double u = px + r * (e1x + tt * e2x), v = py + r * (e1y + tt * e2y);
-          emit(u, v, wr * wt * r * det);
-        }
-      }
-    }
-    return;
+// Spatial fold matrices Mt[rho][kind * noff + (i Nx + j)] for i, j >= 0,
+// built on the GPU (launch_spatial_fold) into dMt from the rho grid and the
+// quadrature rules set up here.  Rows of Mt with a non-zero entry in column c
+// lie in [kcol[2c], kcol[2c+1]) (copied back into kcol).
+int spatial_matrix(const giem_handle *t, const Grids &g, double *dMt, int *dkcol,
+                   std::vector<int> &kcol, hipStream_t s) {
+  const size_t noff = (size_t)t->nx * t->ny, nr = g.rho.size(), ncol = K_COUNT * noff;
+  if (g.rho.n != 12) {
+    set_error("giem_tables: the rho grid must have 12 nodes per panel");
+    return GIEM_EINVAL;
   }
-  const double ddx = std::max({x0 - dx, 0.0, dx - x1}), ddy = std::max({y0 - dy, 0.0, dy - y1});
-  const double dist = std::hypot(ddx, ddy), hm = std::min(hx, hy);
-  const Rule &rr = dist < 2.0 * hm ? g14 : g8;
-  const int split = dist < 0.5 * hm ? 2 : 1;
-  const int n = (int)rr.x.size();
-  for (int a = 0; a < split; ++a)
-    for (int b = 0; b < split; ++b) {
-      const double xa = x0 + (x1 - x0) * a / split, xb = x0 + (x1 - x0) * (a + 1) / split;
-      const double ya = y0 + (y1 - y0) * b / split, yb = y0 + (y1 - y0) * (b + 1) / split;
-      for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) {
-          const double u = 0.5 * (xa + xb) + 0.5 * (xb - xa) * rr.x[i];
-          const double v = 0.5 * (ya + yb) + 0.5 * (yb - ya) * rr.x[j];
-          emit(u, v, 0.25 * (xb - xa) * (yb - ya) * rr.w[i] * rr.w[j]);
-        }
-    }
-}
-
-void area_rule(int kind, double dx, double dy, double hx, double hy, const Rule &gs,
-               const Rule &g14, const Rule &g8, RulePts &out) {
-  for (int sx = -1; sx <= 1; sx += 2)
-    for (int sy = -1; sy <= 1; sy += 2) {
-      const double x0 = std::min(0.0, sx * hx), x1 = std::max(0.0, sx * hx);
-      const double y0 = std::min(0.0, sy * hy), y1 = std::max(0.0, sy * hy);
-      quadrant_rule(kind, dx, dy, x0, x1, y0, y1, sx, sy, hx, hy, gs, g14, g8, out);
-    }
-}
-
-// -d_xx phi = -(delta(u + hx) - 2 delta(u) + delta(u - hx)) (hy - |v|) and
-// the same with x and y exchanged: line integrals along v.
-void line_rule(int kind, double dx, double dy, double hx, double hy, const Rule &gl,
-               RulePts &out) {
-  const int n = (int)gl.x.size();
-  const double dfix = kind == K_XX ? dx : dy, drun = kind == K_XX ? dy : dx;
-  const double hfix = kind == K_XX ? hx : hy, hrun = kind == K_XX ? hy : hx;
-  for (int c = -1; c <= 1; ++c) {
-    const double wc = c == 0 ? 2.0 : -1.0;
-    const double off = dfix - c * hfix;
-    std::vector<double> cuts{-hrun, 0.0, hrun};
-    if (drun > -hrun && drun < hrun) cuts.push_back(drun);
-    std::sort(cuts.begin(), cuts.end());
-    cuts.erase(std::unique(cuts.begin(), cuts.end()), cuts.end());
-    for (size_t p = 0; p + 1 < cuts.size(); ++p) {
-      const double a = cuts[p], b = cuts[p + 1];
-      const bool on_line = std::fabs(off) < 1e-12 * hfix;
-      const bool sa = on_line && std::fabs(a - drun) < 1e-12 * hrun;
-      const bool sb = on_line && std::fabs(b - drun) < 1e-12 * hrun;
-      if (sa || sb) {
-        // logarithmic singularity at the end a (sa) or b (sb)
-        const Rule &de = radial_rule();
-        for (size_t i = 0; i < de.x.size(); ++i) {
-          const double v = sa ? a + (b - a) * de.x[i] : b - (b - a) * de.x[i];
-          out.add(std::hypot(off, drun - v), wc * (b - a) * de.w[i] * (hrun - std::fabs(v)));
-        }
-        continue;
-      }
-      for (int i = 0; i < n; ++i) {
-        const double v = 0.5 * (a + b) + 0.5 * (b - a) * gl.x[i];
-        const double wv = 0.5 * (b - a) * gl.w[i];
-        out.add(std::hypot(off, drun - v), wc * wv * (hrun - std::fabs(v)));
-      }
-    }
-  }
-}
-
-// Spatial fold matrices Mt[rho][kind * noff + (i Nx + j)] for i, j >= 0.
-// Rows of Mt with a non-zero entry in column c lie in [kcol[2c], kcol[2c+1]).
-void spatial_matrix(const giem_handle *t, const Grids &g, std::vector<double> &Mt,
-                    std::vector<int> &kcol) {
-  const int nx = t->nx, ny = t->ny;
-  const size_t noff = (size_t)nx * ny, nr = g.rho.size(), ncol = K_COUNT * noff;
-  Mt.assign(nr * ncol, 0.0);
-  kcol.resize(2 * ncol);
   const Rule gs = gauss_legendre(24), g14 = gauss_legendre(14), g8 = gauss_legendre(8);
-  const Rule gline = gauss_legendre(24);
-  parallel_for((int)noff, [&](int o) {
-    const int i = o / nx, j = o % nx;
-    const double dx = j * t->hx, dy = i * t->hy;
-    double wi[32];
-    for (int kind = 0; kind < K_COUNT; ++kind) {
-      RulePts pts;
-      if (kind == K_XX || kind == K_YY)
-        line_rule(kind, dx, dy, t->hx, t->hy, gline, pts);
-      else
-        area_rule(kind, dx, dy, t->hx, t->hy, gs, g14, g8, pts);
-      const size_t col = kind * noff + o;
-      size_t lo = nr, hi = 0;
-      for (size_t q = 0; q < pts.rho.size(); ++q) {
-        const size_t c0 = g.rho.interp(std::max(pts.rho[q], g.rho_min), wi);
-        for (int k = 0; k < g.rho.n; ++k) Mt[(c0 + k) * ncol + col] += pts.w[q] * wi[k];
-        lo = std::min(lo, c0);
-        hi = std::max(hi, c0 + g.rho.n);
-      }
-      kcol[2 * col] = (int)lo;
-      kcol[2 * col + 1] = (int)hi;
-    }
-  });
+  const Rule &rad = radial_rule();
+  std::vector<double> args;
+  auto put = [&](const std::vector<double> &v) { args.insert(args.end(), v.begin(), v.end()); };
+  put(g.rho.edges);
+  put(g.rho.node);
+  put(g.rho.bw);
+  put(gs.x);
+  put(gs.w);
+  put(g14.x);
+  put(g14.w);
+  put(g8.x);
+  put(g8.w);
+  put(rad.x);
+  put(rad.w);
+  DevBuf dargs;
+  if (dargs.alloc(args.size() * 8) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("giem_tables: out of device memory");
+    return GIEM_ENOMEM;
+  }
+  kcol.resize(2 * ncol);
+  if (check_hip(hipMemsetAsync(dMt, 0, nr * ncol * 8, s), "clear spatial weights") ||
+      check_hip(hipMemcpyAsync(dargs.p, args.data(), args.size() * 8, hipMemcpyHostToDevice, s),
+                "upload spatial rules") ||
+      check_hip(launch_spatial_fold(dargs.d(), (int)g.rho.edges.size() - 1, (int)rad.x.size(),
+                                    t->nx, t->ny, t->hx, t->hy, g.rho_min, dMt, dkcol, s),
+                "spatial weights") ||
+      check_hip(hipMemcpyAsync(kcol.data(), dkcol, kcol.size() * sizeof(int),
+                               hipMemcpyDeviceToHost, s),
+                "spatial weight ranges") ||
+      check_hip(hipStreamSynchronize(s), "spatial weights"))
+    return GIEM_EHIP;
+  return GIEM_OK;
 }
 
 // Contraction range of each 64-row tile of a GEMM over the columns col0 ..
@@ -962,19 +858,10 @@ int compute_tables(giem_handle *t, hipStream_t s) {
   }
   const Grids g = make_grids(t);
   const size_t nl = g.lam.size(), nr = g.rho.size();
-  std::vector<double> Mt;
-  std::vector<int> kcol;
-  spatial_matrix(t, g, Mt, kcol);
-  // contraction ranges of the three spatial GEMMs' row tiles
-  std::vector<int> kr = tile_ranges(kcol, 0, (int)noff);
-  const size_t kr1 = kr.size();
-  {
-    const std::vector<int> a = tile_ranges(kcol, K_XX * noff, (int)(3 * noff));
-    const std::vector<int> b = tile_ranges(kcol, K_X * noff, (int)(2 * noff));
-    kr.insert(kr.end(), a.begin(), a.end());
-    kr.insert(kr.end(), b.begin(), b.end());
-  }
-  const size_t kr2 = kr1 + 2 * ((3 * noff + 63) / 64);
+  // contraction ranges of the three spatial GEMMs' row tiles (filled below)
+  const size_t kr1 = 2 * ((noff + 63) / 64), kr2 = kr1 + 2 * ((3 * noff + 63) / 64);
+  const size_t nkr = kr2 + 2 * ((2 * noff + 63) / 64);
+  const size_t ncolm = (size_t)K_COUNT * noff;
   // the layered model and the lambda nodes on the device: sigma [nlay + 1]
   // (complex), d [nlay], ta, tb [nz], lambda [nl], then the cells' layers
   // [nz] (int); workspace of the vertical functions: eta, p, q (complex) and
@@ -996,26 +883,32 @@ int compute_tables(giem_handle *t, hipStream_t s) {
     std::copy(g.lam.x.begin(), g.lam.x.end(), o);
   }
   const size_t nws = nl * nlayers;  // (node, layer) pairs
-  DevBuf dW, dWr, dM, dG, dH, dc0, dc1, dc2, dmod, dlay, dws, dcell, dkr;
+  DevBuf dW, dWr, dM, dG, dH, dc0, dc1, dc2, dmod, dlay, dws, dcell, dkr, dkcol;
   if (dW.alloc(nl * nr * 8) != hipSuccess || dWr.alloc(nl * nr * 8) != hipSuccess ||
-      dM.alloc(Mt.size() * 8) != hipSuccess || dG.alloc(nl * ncolc * 16) != hipSuccess ||
+      dM.alloc(nr * ncolm * 8) != hipSuccess || dkcol.alloc(2 * ncolm * sizeof(int)) != hipSuccess ||
+      dG.alloc(nl * ncolc * 16) != hipSuccess ||
       dH.alloc(nr * ncolc * 16) != hipSuccess || dc0.alloc(noff * 2 * T * 16) != hipSuccess ||
       dc1.alloc(3 * noff * T * 16) != hipSuccess || dc2.alloc(2 * noff * nz2 * 16) != hipSuccess ||
       dmod.alloc(nmod * 8) != hipSuccess || dlay.alloc((size_t)nz * sizeof(int)) != hipSuccess ||
       dws.alloc(nws * (5 * sizeof(vert::zc) + sizeof(double))) != hipSuccess ||
       dcell.alloc(nl * 2 * nz * sizeof(vert::Cell)) != hipSuccess ||
-      dkr.alloc(kr.size() * sizeof(int)) != hipSuccess) {
+      dkr.alloc(nkr * sizeof(int)) != hipSuccess) {
     (void)hipGetLastError();  // reported here, not by the next launch check
     set_error("giem_tables: out of device memory");
     return GIEM_ENOMEM;
   }
+  std::vector<int> kcol, kr;
   {
-    const int rc = hankel_weights(g, dW.d(), dWr.d(), s);
+    int rc = hankel_weights(g, dW.d(), dWr.d(), s);
+    if (rc == GIEM_OK) rc = spatial_matrix(t, g, dM.d(), static_cast<int *>(dkcol.p), kcol, s);
     if (rc != GIEM_OK) return rc;
+    kr = tile_ranges(kcol, 0, (int)noff);
+    const std::vector<int> a = tile_ranges(kcol, K_XX * noff, (int)(3 * noff));
+    const std::vector<int> b = tile_ranges(kcol, K_X * noff, (int)(2 * noff));
+    kr.insert(kr.end(), a.begin(), a.end());
+    kr.insert(kr.end(), b.begin(), b.end());
   }
-  if (check_hip(hipMemcpyAsync(dM.p, Mt.data(), Mt.size() * 8, hipMemcpyHostToDevice, s),
-                "upload spatial weights") ||
-      check_hip(hipMemcpyAsync(dmod.p, model.data(), nmod * 8, hipMemcpyHostToDevice, s),
+  if (check_hip(hipMemcpyAsync(dmod.p, model.data(), nmod * 8, hipMemcpyHostToDevice, s),
                 "upload layered model") ||
       check_hip(hipMemcpyAsync(dlay.p, v.lay.data(), (size_t)nz * sizeof(int),
                                hipMemcpyHostToDevice, s),
