@@ -2,26 +2,30 @@
 // (Sect. 3.1; Appendix A for the Green's tensor, Appendix B for the vertical
 // integration, Appendix C for the horizontal integration).
 //
-// Structure of the computation, per frequency:
+// Structure of the computation (every step on the GPU; this file sets up
+// the grids, rules and the layered model and drives the kernels of
+// kernels_tables.hip), per frequency:
 //  1. vertical integrals over every pair of depth cells, for lambda on a
 //     logarithmic Chebyshev grid, from the p/q recursions of Appendix B and
 //     the factorisation of the fundamental function U_gamma into a solution
 //     F that satisfies the conditions above and G that satisfies those below
 //     (U(z, z*) ~ F(z_<) G(z_>)); every exponential is evaluated with a
-//     non-positive real part;
+//     non-positive real part (vertical.h);
 //  2. zero-order Hankel transforms h(rho) = int J0(lambda rho) g(lambda)
 //     dlambda of the five lambda functions, on a logarithmic Chebyshev grid
 //     in rho: a geometry-only weight matrix (Gauss-Legendre panels between
-//     the zeros of J0, tail summed by repeated averaging) contracted with the
-//     lambda samples on the GPU;
+//     the zeros of J0, tail summed by repeated averaging), built once per
+//     call and contracted with the lambda samples;
 //  3. horizontal Galerkin integration: the product of the two cells'
 //     footprints becomes their autocorrelation phi (a product of triangles),
 //     and the tensor components are convolutions of h with phi, d phi or
 //     d^2 phi, evaluated with quadrature rules whose nodes are graded towards
-//     the singular vertex (Duffy); folded onto the rho grid they form a
-//     second geometry-only matrix, contracted on the GPU;
+//     the singular vertex; folded onto the rho grid they form a second
+//     geometry-only matrix, built once per call and contracted;
 //  4. the nine components are formed and packed (upper triangles of xx, xy,
 //     yy, zz; full xz, yz).
+// The receiver kernels (compute_receiver_kernels) evaluate their lambda
+// functions and point rules on the host and contract them on the GPU.
 // The lambda-functions, with sigma_n the conductivity of the observation
 // cell and P = -i w mu0 A1 + A3 / sigma_n:
 //   A1 = int int U_1;  A3 = int int (d_z d_z* U_sigma - 2 delta) (regular
