@@ -23,6 +23,13 @@ MODELS = {
     "contrast_1e4": dict(nx=3, ny=2, nz=3, hx=100.0, hy=100.0,
                          z_edges=np.array([0.0, 50.0, 100.0, 150.0]), d=np.array([0.0, 50.0]),
                          sigma=np.array([0.0, 1e-4, 1.0], complex), freq=0.01),
+    # 240 offsets (several 64-column tiles of every spatial contraction and
+    # of the spatial fold), uneven cells, three earth layers under the air
+    # with interfaces between cells of the grid
+    "several_tiles": dict(nx=20, ny=12, nz=5, hx=90.0, hy=70.0,
+                          z_edges=np.array([0.0, 30.0, 70.0, 120.0, 180.0, 260.0]),
+                          d=np.array([0.0, 70.0, 180.0]),
+                          sigma=np.array([0.0, 0.05, 0.002, 0.3], complex), freq=3.0),
 }
 
 
