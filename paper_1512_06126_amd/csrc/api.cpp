@@ -237,8 +237,7 @@ static int apply_core_t(giem_handle *t, int nf, const int *ifreqs, int nrhs,
   GIEM_TRY(mark(2));
   const int bv = t->block_nbuf[prec == PREC_FP32 ? 1 : 0];
   const int nbuf = (bv >= 2 && bv <= 4) ? bv : 1;
-  GIEM_HIP(launch_block(prec, tabs, nf, spa, spb, static_cast<const unsigned *>(t->bplan), nx,
-                        ny, nz, nrhs, nbuf, s),
+  GIEM_HIP(launch_block(prec, tabs, nf, spa, spb, nx, ny, nz, nrhs, nbuf, s),
            "block product");
   GIEM_TRY(mark(3));
   GIEM_HIP(launch_fft_y(prec, spb, 2 * nx, ny, rp, G[2], NT[2], t->py.d, twy, 1, s),
@@ -470,12 +469,6 @@ static int finish_handle(giem_handle *t, hipStream_t s) {
   recall_tuned(t);
   GIEM_TRY(make_plan(2 * t->nx, t->px));
   GIEM_TRY(make_plan(2 * t->ny, t->py));
-  {
-    const std::vector<unsigned> plan = block_plan(nz);
-    GIEM_HIP(hipMalloc(&t->bplan, plan.size() * sizeof(unsigned)), "hipMalloc plan");
-    GIEM_HIP(hipMemcpy(t->bplan, plan.data(), plan.size() * sizeof(unsigned), hipMemcpyHostToDevice),
-             "copy plan");
-  }
   std::vector<c128> sb(nz);
   std::vector<double> vol(nz), sr(nz);
   for (int k = 0; k < nz; ++k) {
@@ -519,7 +512,7 @@ void giem_free(giem_handle *t) {
     if (ft.spec32) hipFree(ft.spec32);
     for (auto &rk : ft.rec_kernels) hipFree(rk.second);
   }
-  void *dev[] = {t->px.tw64, t->px.tw32, t->py.tw64, t->py.tw32, t->bplan,
+  void *dev[] = {t->px.tw64, t->px.tw32, t->py.tw64, t->py.tw32,
                  t->sb_lev, t->vol_lev, t->sroot_lev, t->diag, t->spec_ws, t->red_part,
                  t->red_out, t->coef_dev, t->basis, t->vec_ws, t->gs_scale_dev};
   for (void *p : dev)

@@ -46,7 +46,6 @@ struct giem_handle {
   int device = 0;
   std::vector<giem::FreqTables> f;
   giem::FftPlan px, py;            // lengths 2 Nx, 2 Ny
-  void *bplan = nullptr;           // gather plan of the FP64 block product (Nz > 32)
   // per-level device data
   void *sb_lev = nullptr;    // c128 [nz]
   void *vol_lev = nullptr;   // double [nz]

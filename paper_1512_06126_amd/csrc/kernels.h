@@ -32,7 +32,7 @@ hipError_t launch_fft_x_inv(int prec, const VecPtrs32 &ptrs, const c128 *sd, con
                             const void *spec, int nx, int ny, int nz, int rp_total, int G,
                             int nthr, const FftDesc &fd, const void *tw, double scale,
                             hipStream_t s);
-// out-of-place: sin and sout are two spectra buffers; plan from block_plan(nz).
+// out-of-place: sin and sout are two spectra buffers.
 // nf frequencies (tables tabs.tab[0..nf)) with R vectors each: a point's
 // record of the spectra holds nf R vectors, frequency f's at f R .. f R + R - 1.
 // nbuf: variant of the pipelined kernel: 1 or 2 register sets of prefetched
@@ -41,11 +41,9 @@ hipError_t launch_fft_x_inv(int prec, const VecPtrs32 &ptrs, const c128 *sd, con
 // the next point staged into a second LDS buffer during the current point's
 // MFMAs (falls back to 2, see block_dbl_supported)
 // Where the row does not fit LDS (Nz > 32 at R = 2) every nbuf takes the
-// band-pair kernel in FP32 and the gather kernel in FP64.
+// band-pair kernel.
 hipError_t launch_block(int prec, const TabSet &tabs, int nf, const void *sin, void *sout,
-                        const unsigned *plan, int nx, int ny, int nz, int R, int nbuf,
-                        hipStream_t s);
-std::vector<unsigned> block_plan(int nz);
+                        int nx, int ny, int nz, int R, int nbuf, hipStream_t s);
 bool block_two_per_cu(int nz, int R, int prec);
 bool block_dbl_supported(int nz, int R, int prec);
 

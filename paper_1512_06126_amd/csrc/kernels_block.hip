@@ -23,12 +23,10 @@
 // point's row is in flight into registers; 12 wavefronts (two per 16-row
 // tile, each half of the contraction) run the MFMAs from LDS.
 //
-// Rows and input vectors that outgrow LDS (Nz > 32 at R = 2): in FP32
-// k_block_band, one workgroup per point that stages the packed row by pairs
-// of 16-level bands, each entry once, and keeps the output tiles'
-// accumulators in its wavefronts; in FP64 k_block, one wavefront per (point,
-// 16-row tile), fragments gathered straight from global memory through a
-// host-built plan.
+// k_block_band (rows and input vectors that outgrow LDS: Nz > 32 at R = 2):
+// one workgroup per point stages the packed row by pairs of 16-level bands,
+// each entry once, and keeps the output tiles' accumulators in its
+// wavefronts.
 //
 // Several frequencies can share one launch: the spectra of all their vectors
 // are transformed together, a point's record holds nf R vectors (frequency
@@ -90,120 +88,8 @@ __device__ __forceinline__ void mirror_of(const MirrorSet &m, int mi, int nx, in
   pt = ky * 2 * nx + kx;
 }
 
-// Gather plan: for tile t, k-step s and lane l (row r = 16 t + l % 16,
-// column c = 4 s + l / 16) one word holds the packed offset of Q[r][c] (low
-// 24 bits), its sign (bit 24, Lemma 1 transposes), validity (bit 25) and the
-// component beta of column c (bits 26-27, for the mirror flips of X).  The
-// plan depends on Nz only and is shared by every frequency point.
-__host__ __device__ inline unsigned plan_word(int nz, int r, int c) {
-  const int tri = nz * (nz + 1) / 2, p3 = 3 * nz;
-  if (r >= p3 || c >= p3) return 0u;
-  const int a = r / nz, iz = r - a * nz, b = c / nz, jz = c - b * nz;
-  const int blk = a * 3 + b;
-  const bool trans = (blk == 6) || (blk == 7);
-  const bool full = (blk == 2) || (blk == 5) || trans;
-  const bool second = (blk == 5) || (blk == 7);
-  int idx;
-  if (full) {
-    const int row = trans ? jz : iz, col = trans ? iz : jz;
-    idx = 4 * tri + (second ? nz * nz : 0) + row * nz + col;
-  } else {
-    const int lo = iz < jz ? iz : jz, hi = iz < jz ? jz : iz;
-    const int base = (blk == 0) ? 0 : (blk == 4) ? 2 * tri : (blk == 8) ? 3 * tri : tri;
-    idx = base + lo * nz - (lo * (lo - 1)) / 2 + (hi - lo);
-  }
-  return (unsigned)idx | (trans ? (1u << 24) : 0u) | (1u << 25) | ((unsigned)b << 26);
-}
-
-// FP64 block product for rows too long for LDS: one wavefront per
-// (frequency, representative point, 16-row tile of the output); no LDS and
-// no barriers: the wave gathers its A fragments from the packed block and its
-// B fragments from the input spectra (with the mirror sign flips), and writes
-// its rows of the output spectra, which live in a second buffer.  (In FP64
-// the band-pair kernel below holds one workgroup per CU by its registers and
-// measured 18.8 against 17.6 ms for this one at 176 x 224 x 118.)
-template <typename T>
-__global__ void __launch_bounds__(512)
-k_block(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict__ sout,
-        const unsigned *__restrict__ plan, int nx, int ny, int nz, int R, int nf) {
-  typedef Mfma<T> M;
-  const int E = 2 * nz * (2 * nz + 1);
-  const int p3 = 3 * nz;
-  const int nsteps = (p3 + 3) >> 2;
-  const int ntiles = (p3 + 15) >> 4;
-  const int npts = (nx + 1) * (ny + 1);
-  const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);  // global wave
-  const int task = gw / ntiles, tile = gw - task * ntiles;
-  if (task >= nf * npts) return;  // whole wave exits together
-  const int f = task / npts, rep = task - f * npts;
-  const int rtot = nf * R;  // vectors per point record of the spectra
-  const int lane = threadIdx.x & 63;
-  const MirrorSet m = mirror_set(rep, nx, ny);
-  const int V = m.n * R;
-  const cplx<T> *tq = static_cast<const cplx<T> *>(tabs.tab[f]) + (size_t)rep * E;
-  const unsigned *pl = plan + (size_t)tile * nsteps * 64 + lane;
-  const int kk = lane >> 4;
-  const int j = lane & 15;
-  const int vloc = j & 7, part = j >> 3;
-  for (int vg = 0; vg < V; vg += 8) {
-    const int v = vg + vloc;
-    const bool vvalid = v < V;
-    int pt = 0;
-    bool fx = false, fy = false;
-    const int mi = vvalid ? v / R : 0, rr = vvalid ? v - mi * R : 0;
-    mirror_of(m, mi, nx, ny, pt, fx, fy);
-    const cplx<T> *xb = sin + ((size_t)pt * rtot + f * R + rr) * p3;
-    typename M::acc_t accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
-    constexpr int U = 8;  // k-steps whose operands are requested ahead
-    for (int s0 = 0; s0 < nsteps; s0 += U) {
-      cplx<T> q[U], x[U];
-      unsigned w[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) w[u] = (s0 + u < nsteps) ? pl[(s0 + u) * 64] : 0u;
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int c = 4 * (s0 + u) + kk;
-        const bool ok = (w[u] >> 25) & 1u;
-        q[u] = tq[ok ? (w[u] & 0xffffffu) : 0];
-        x[u] = xb[c < p3 ? c : 0];  // B[c][j] does not depend on the lane's A row
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const bool ok = (w[u] >> 25) & 1u;
-        const T qs_ = ((w[u] >> 24) & 1u) ? (T)-1 : (T)1;
-        const T qr = ok ? qs_ * q[u].x : (T)0;
-        const T qim = ok ? qs_ * q[u].y : (T)0;
-        const int cc = 4 * (s0 + u) + kk;
-        const unsigned cb = (unsigned)(cc / nz);
-        const bool xn = (cb == 0u && fx) || (cb == 1u && fy);
-        const bool xok = vvalid && cc < p3;
-        const T xs_ = xn ? (T)-1 : (T)1;
-        const T xr = xok ? xs_ * x[u].x : (T)0;
-        const T xi = xok ? xs_ * x[u].y : (T)0;
-        const T b1 = part ? xi : xr;
-        const T b2 = part ? xr : -xi;
-        accr = M::mma(qr, b1, accr);
-        acci = M::mma(qim, b2, acci);
-      }
-    }
-    if (vvalid) {
-      T *ob = reinterpret_cast<T *>(sout + ((size_t)pt * rtot + f * R + rr) * p3);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int row = tile * 16 + M::row(lane, q);
-        if (row < p3) {
-          const int a = row / nz;
-          const T sg = ((a == 0 && fx) || (a == 1 && fy)) ? (T)-1 : (T)1;
-          ob[2 * row + part] = sg * (accr[q] + acci[q]);
-        }
-      }
-    }
-  }
-}
-
-
-// FP32 block product for rows too long for LDS (Nz > 32 at R = 2): one
-// workgroup of 8 wavefronts per (frequency, representative point).  The 3Nz x 3Nz
+// Block product for rows too long for LDS (Nz > 32 at R = 2): one workgroup
+// per (frequency, representative point), 8 wavefronts in FP32, 16 in FP64.  The 3Nz x 3Nz
 // matrix is visited by pairs (I, J), I <= J, of 16-level bands: the
 // workgroup stages every packed entry with one level in band I and the other
 // in band J into LDS (the I-rows, J-columns tile of the four symmetric
@@ -211,7 +97,7 @@ k_block(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict__ sout
 // entry once per point, with 128-byte and longer runs, and applies it to the
 // output bands I and J: yx = xy, and the symmetric blocks' (J, I) tiles are
 // the transposes; zx = -xz^T, zy = -yz^T (Lemma 1).  Output tile (alpha,
-// band) belongs to wavefront (3 band + alpha) mod 8, which keeps its
+// band) belongs to wavefront (3 band + alpha) mod NW, which keeps its
 // accumulators over all pairs (the six tiles of a pair fall on different
 // wavefronts where they can).  The next pair's entries are loaded into
 // registers while the current pair's MFMAs run.  Slots of the staged tiles:
@@ -246,17 +132,18 @@ __device__ __forceinline__ void band_next(int &I, int &J, int nb) {
   }
 }
 
-template <typename T>
-__device__ __forceinline__ void band_store(cplx<T> *buf, const cplx<T> (&pre)[4], int tid) {
+template <typename T, int NT, int NPRE>
+__device__ __forceinline__ void band_store(cplx<T> *buf, const cplx<T> (&pre)[NPRE], int tid) {
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int q = tid + 512 * u;
+  for (int u = 0; u < NPRE; ++u) {
+    const int q = tid + NT * u;
     buf[(q >> 8) * kBandSlot + ((q >> 4) & 15) * kBandLd + (q & 15)] = pre[u];
   }
 }
 
-template <typename T, int MAXT, int KB, int WPE>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE)))
+// NW wavefronts per workgroup, MAXT output tiles per wavefront
+template <typename T, int MAXT, int KB, int WPE, int NW>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_block_band(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict__ sout, int nx,
              int ny, int nz, int R, int nf) {
   typedef Mfma<T> M;
@@ -269,6 +156,7 @@ k_block_band(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict__
   const int npts = (nx + 1) * (ny + 1);
   const int f = blockIdx.x / npts, rep = blockIdx.x - f * npts;
   const int rtot = nf * R;
+  constexpr int NT = 64 * NW, NPRE = 2048 / NT;  // threads, staged entries per thread
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, kk = lane >> 4;
   const int vloc = li & 7, part = li >> 3;
@@ -278,7 +166,7 @@ k_block_band(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict__
   for (int vg = 0; vg < V; vg += 8) {
     __syncthreads();  // the previous vector group's reads of Xs are done
     // Xs[(beta nb 16 + jz) 8 + v]: levels jz in [Nz, 16 nb) hold zeros
-    for (int idx = tid; idx < 8 * 3 * nb * 16; idx += 512) {
+    for (int idx = tid; idx < 8 * 3 * nb * 16; idx += NT) {
       const int v = idx / (3 * nb * 16), cc = idx - v * (3 * nb * 16);
       const int b = cc / (nb * 16), jz = cc - b * (nb * 16), c = b * nz + jz;
       cplx<T> val = mk<T>(0, 0);
@@ -297,23 +185,23 @@ k_block_band(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict__
     for (int s = 0; s < MAXT; ++s) accr[s] = acci[s] = typename M::acc_t{0, 0, 0, 0};
     // the next pair's entries are loaded into registers during the current
     // pair's MFMAs
-    cplx<T> pre[4];
+    cplx<T> pre[NPRE];
     int I = 0, J = 0, Ip = 0, Jp = 0;  // current pair, last pair requested
 #pragma unroll
-    for (int u = 0; u < 4; ++u) pre[u] = band_entry(tq, tid + 512 * u, 0, 0, nz, tri);
+    for (int u = 0; u < NPRE; ++u) pre[u] = band_entry(tq, tid + NT * u, 0, 0, nz, tri);
     for (int p = 0; p < npairs; ++p) {
       __syncthreads();  // the previous pair's tiles are no longer read
-      band_store(Ts, pre, tid);
+      band_store<T, NT, NPRE>(Ts, pre, tid);
       if (p + 1 < npairs) {
         band_next(Ip, Jp, nb);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) pre[u] = band_entry(tq, tid + 512 * u, Ip, Jp, nz, tri);
+        for (int u = 0; u < NPRE; ++u) pre[u] = band_entry(tq, tid + NT * u, Ip, Jp, nz, tri);
       }
       __syncthreads();
       const cplx<T> *Tc = Ts;
 #pragma unroll
       for (int s = 0; s < MAXT; ++s) {
-        const int o = w + 8 * s;
+        const int o = w + NW * s;
         if (o >= 3 * nb) continue;
         const int band = o / 3, a = o - 3 * band;
 #pragma unroll 1
@@ -373,7 +261,7 @@ k_block_band(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict__
       T *ob = reinterpret_cast<T *>(sout + ((size_t)pt * rtot + f * R + rr) * p3);
 #pragma unroll
       for (int s = 0; s < MAXT; ++s) {
-        const int o = w + 8 * s;
+        const int o = w + NW * s;
         if (o >= 3 * nb) continue;
         const int band = o / 3, a = o - 3 * band;
         const T sgo = ((a == 0 && fx) || (a == 1 && fy)) ? (T)-1 : (T)1;
@@ -389,15 +277,16 @@ k_block_band(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict__
 
 // fragment batch and occupancy target per tile count: four wavefronts per
 // SIMD (two workgroups per CU) where the registers allow
-template <typename T, int MAXT>
+template <typename T, int MAXT, int NW>
 struct BandCfg {
   static constexpr int KB = 4;
-  static constexpr int WPE = MAXT == 3 ? 4 : 2;
+  // accumulator registers grow with MAXT and the element size
+  static constexpr int WPE = MAXT * (int)(sizeof(T) / 4) <= 4 ? 4 : 2;
 };
-template <typename T, int MAXT>
+template <typename T, int MAXT, int NW>
 static const void *band_kernel() {
   return reinterpret_cast<const void *>(
-      k_block_band<T, MAXT, BandCfg<T, MAXT>::KB, BandCfg<T, MAXT>::WPE>);
+      k_block_band<T, MAXT, BandCfg<T, MAXT, NW>::KB, BandCfg<T, MAXT, NW>::WPE, NW>);
 }
 
 static size_t lds_bytes_band(int nz, size_t csize) {
@@ -1190,7 +1079,8 @@ hipError_t set_block_lds_limits() {
   GIEM_BLOCK_VARIANTS(GIEM_SET_ATTR, double)
   GIEM_BLOCK_VARIANTS(GIEM_SET_ATTR, float)
 #undef GIEM_SET_ATTR
-  const void *band[] = {band_kernel<float, 3>(), band_kernel<float, 6>()};
+  const void *band[] = {band_kernel<float, 3, 8>(), band_kernel<float, 6, 8>(),
+                        band_kernel<double, 2, 16>(), band_kernel<double, 3, 16>()};
   for (const void *k : band)
     if (e == hipSuccess)
       e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
@@ -1199,20 +1089,9 @@ hipError_t set_block_lds_limits() {
 
 bool block_supported(int nz, int R) { return nz >= 1 && 2 * nz * (2 * nz + 1) < (1 << 24) && R >= 1 && R <= kMaxRhs; }
 
-std::vector<unsigned> block_plan(int nz) {
-  const int p3 = 3 * nz, nsteps = (p3 + 3) / 4, ntiles = (p3 + 15) / 16;
-  std::vector<unsigned> w((size_t)ntiles * nsteps * 64);
-  for (int t = 0; t < ntiles; ++t)
-    for (int st = 0; st < nsteps; ++st)
-      for (int l = 0; l < 64; ++l)
-        w[((size_t)t * nsteps + st) * 64 + l] = plan_word(nz, 16 * t + (l & 15), 4 * st + (l >> 4));
-  return w;
-}
-
 template <typename T>
 static hipError_t launch_block_t(const TabSet &tabs, int nf, const void *sin, void *sout,
-                                 const unsigned *plan, int nx, int ny, int nz, int R, int nbuf,
-                                 hipStream_t s) {
+                                 int nx, int ny, int nz, int R, int nbuf, hipStream_t s) {
   const long long ntask = (long long)nf * (nx + 1) * (ny + 1);
   // the pipelined kernels form spectra element offsets in 32-bit integers
   const bool off32 = 4LL * nx * ny * nf * R * 3 * nz < (1LL << 31);
@@ -1258,31 +1137,30 @@ static hipError_t launch_block_t(const TabSet &tabs, int nf, const void *sin, vo
 #undef GIEM_LAUNCH
 #undef GIEM_LAUNCH_MF
   }
-  // rows too long for LDS: in FP32 the band-pair kernel (up to 6 output
-  // tiles per wavefront: Nz <= 256; the handle refuses Nz > 170), in FP64
-  // the gather kernel
+  // rows too long for LDS: the band-pair kernel (FP32: 8 wavefronts, 3 or 6
+  // output tiles each; FP64: 16 wavefronts, 2 or 3 tiles each, its
+  // accumulators being twice as wide): Nz <= 256, the handle refuses Nz > 170
+  const int nb = (nz + 15) / 16;
+  if (3 * nb > 48 || lds_bytes_band(nz, cs) > kLdsLimit || ntask > 0x7fffffffLL)
+    return hipErrorInvalidValue;
+  const size_t lds = lds_bytes_band(nz, cs);
+  const cplx<T> *si = static_cast<const cplx<T> *>(sin);
+  cplx<T> *so = static_cast<cplx<T> *>(sout);
   if constexpr (sizeof(T) == 4) {
-    const int nb = (nz + 15) / 16;
-    if (3 * nb <= 48 && lds_bytes_band(nz, cs) <= kLdsLimit && ntask <= 0x7fffffffLL) {
-      const size_t lds = lds_bytes_band(nz, cs);
-      if (3 * nb <= 24)
-        k_block_band<T, 3, BandCfg<T, 3>::KB, BandCfg<T, 3>::WPE><<<(unsigned)ntask, 512, lds, s>>>(
-            tabs, static_cast<const cplx<T> *>(sin), static_cast<cplx<T> *>(sout), nx, ny, nz, R,
-            nf);
-      else
-        k_block_band<T, 6, BandCfg<T, 6>::KB, BandCfg<T, 6>::WPE><<<(unsigned)ntask, 512, lds, s>>>(
-            tabs, static_cast<const cplx<T> *>(sin), static_cast<cplx<T> *>(sout), nx, ny, nz, R,
-            nf);
-      return hipGetLastError();
-    }
+    if (3 * nb <= 24)
+      k_block_band<T, 3, BandCfg<T, 3, 8>::KB, BandCfg<T, 3, 8>::WPE, 8>
+          <<<(unsigned)ntask, 512, lds, s>>>(tabs, si, so, nx, ny, nz, R, nf);
+    else
+      k_block_band<T, 6, BandCfg<T, 6, 8>::KB, BandCfg<T, 6, 8>::WPE, 8>
+          <<<(unsigned)ntask, 512, lds, s>>>(tabs, si, so, nx, ny, nz, R, nf);
+  } else {
+    if (3 * nb <= 32)
+      k_block_band<T, 2, BandCfg<T, 2, 16>::KB, BandCfg<T, 2, 16>::WPE, 16>
+          <<<(unsigned)ntask, 1024, lds, s>>>(tabs, si, so, nx, ny, nz, R, nf);
+    else
+      k_block_band<T, 3, BandCfg<T, 3, 16>::KB, BandCfg<T, 3, 16>::WPE, 16>
+          <<<(unsigned)ntask, 1024, lds, s>>>(tabs, si, so, nx, ny, nz, R, nf);
   }
-  const int ntiles = (3 * nz + 15) / 16;
-  const long long waves = ntask * ntiles;
-  const int per_block = 4;
-  const long long grid = (waves + per_block - 1) / per_block;
-  k_block<T><<<(unsigned)grid, 64 * per_block, 0, s>>>(tabs, static_cast<const cplx<T> *>(sin),
-                                                      static_cast<cplx<T> *>(sout), plan, nx, ny,
-                                                      nz, R, nf);
   return hipGetLastError();
 }
 
@@ -1295,12 +1173,10 @@ bool block_dbl_supported(int nz, int R, int prec) {
 }
 
 hipError_t launch_block(int prec, const TabSet &tabs, int nf, const void *sin, void *sout,
-                        const unsigned *plan, int nx, int ny, int nz, int R, int nbuf,
-                        hipStream_t s) {
+                        int nx, int ny, int nz, int R, int nbuf, hipStream_t s) {
   if (nf < 1 || nf > kMaxFreqBatch) return hipErrorInvalidValue;
-  return prec == PREC_FP32
-             ? launch_block_t<float>(tabs, nf, sin, sout, plan, nx, ny, nz, R, nbuf, s)
-             : launch_block_t<double>(tabs, nf, sin, sout, plan, nx, ny, nz, R, nbuf, s);
+  return prec == PREC_FP32 ? launch_block_t<float>(tabs, nf, sin, sout, nx, ny, nz, R, nbuf, s)
+                           : launch_block_t<double>(tabs, nf, sin, sout, nx, ny, nz, R, nbuf, s);
 }
 
 }  // namespace giem

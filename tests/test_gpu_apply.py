@@ -261,10 +261,10 @@ def test_block_product_every_rhs_count_at_deepest_grids(lib, nz):
 def test_apply_deep_block_product(lib, nx, ny, nz, nrhs, prec, tol):
     # shapes whose packed row and input fragments do not fit the pipelined
     # kernel (more than 32 layers, or 8 right-hand sides at 32 layers) take
-    # the gather kernel in FP64 and the band-pair kernel in FP32: for the
-    # latter partial last bands (33, 47, 118, 130 levels),
-    # whole bands (64), up to 8 bands (three output tiles per wavefront) and
-    # 9 to 11 (six; 170 levels is the deepest grid a handle accepts), several
+    # the band-pair kernel: partial last bands (33, 47, 118, 130 levels),
+    # whole bands (64), the two tile counts per wavefront of each precision
+    # (FP32: three up to 8 bands, six from 9; FP64: two up to 10 bands,
+    # three at 11; 170 levels is the deepest grid a handle accepts), several
     # vector groups (8 right-hand sides at up to four mirror points); same
     # bar against the dense product
     import torch

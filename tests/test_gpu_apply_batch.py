@@ -83,8 +83,8 @@ def test_apply_batch_equals_separate(lib, prec):
 
 
 def test_apply_batch_deep_kernel(lib):
-    # Nz = 33: the packed row no longer fits one workgroup's LDS, the FP64
-    # block product gathers from global memory
+    # Nz = 33: the packed row no longer fits one workgroup's LDS, the block
+    # product stages it by pairs of level bands
     import torch
     nx, ny, nz, nrhs = 4, 3, 33, 2
     rng = np.random.default_rng(91)
@@ -109,7 +109,7 @@ def test_apply_batch_deep_kernel(lib):
         h.apply(xd[f], ys[f], sa, mode=lib.MODE_A, ifreq=q)
     torch.cuda.synchronize()
     assert torch.equal(yd, ys)
-    # FP32: the band-pair kernel over (frequency, point) tasks
+    # FP32 as well
     h.apply_batch(xd, yd, sa, ifreqs=ifreqs, mode=lib.MODE_A, prec=lib.FP32)
     for f, q in enumerate(ifreqs):
         h.apply(xd[f], ys[f], sa, mode=lib.MODE_A, ifreq=q, prec=lib.FP32)
