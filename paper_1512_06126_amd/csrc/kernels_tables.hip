@@ -527,8 +527,10 @@ __device__ __forceinline__ void fold_flush(FoldAcc &f, double *Mt, int64_t ncol,
 }
 
 __device__ __forceinline__ void fold_emit(const FoldArgs &a, FoldAcc &f, double r, double w,
-                                          double *Mt, int64_t ncol, int64_t col) {
-  const double u = log(r > a.rho_min ? r : a.rho_min);
+                                          double *Mt, int64_t ncol, int64_t col,
+                                          bool deriv = false) {
+  const double xq = r > a.rho_min ? r : a.rho_min;
+  const double u = log(xq);
   int lo = 0, hi = a.npan + 1;
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
@@ -545,6 +547,41 @@ __device__ __forceinline__ void fold_emit(const FoldArgs &a, FoldAcc &f, double 
   }
   const double e0 = a.edges[p], e1 = a.edges[p + 1];
   const double sl = (2.0 * u - (e0 + e1)) / (e1 - e0);
+  if (deriv) {
+    // d/d rho of the panel's interpolating polynomial in ln rho
+    const double scale = 2.0 / (e1 - e0) / xq;
+    int hit = -1;
+#pragma unroll
+    for (int j = 0; j < kFoldN; ++j)
+      if (fabs(sl - a.node[j]) < 1e-14) hit = j;
+    if (hit >= 0) {
+      // row of the barycentric differentiation matrix
+      double diag = 0.0;
+#pragma unroll
+      for (int j = 0; j < kFoldN; ++j) {
+        if (j == hit) continue;
+        const double dj = (a.bw[j] / a.bw[hit]) / (a.node[hit] - a.node[j]);
+        diag -= dj;
+        f.acc[j] += w * (dj * scale);
+      }
+      f.acc[hit] += w * (diag * scale);
+    } else {
+      double D = 0.0, Dd = 0.0;
+#pragma unroll
+      for (int j = 0; j < kFoldN; ++j) {
+        const double d = sl - a.node[j];
+        D += a.bw[j] / d;
+        Dd += -a.bw[j] / (d * d);
+      }
+#pragma unroll
+      for (int j = 0; j < kFoldN; ++j) {
+        const double d = sl - a.node[j];
+        const double aj = a.bw[j] / d, adj = -a.bw[j] / (d * d);
+        f.acc[j] += w * ((adj / D - aj * Dd / (D * D)) * scale);
+      }
+    }
+    return;
+  }
   double wi[kFoldN];
   double tot = 0.0;
   int hit = -1;
@@ -687,7 +724,159 @@ __global__ __launch_bounds__(128) void k_spatial_fold(FoldArgs a, double *__rest
   kcol[2 * col + 1] = f.lo < f.hi ? f.hi : 0;
 }
 
+// Receiver rule matrix: a receiver above the centre of a cell at lateral
+// offset (dx, dy) from the centre of the source cell sees the footprint B =
+// [-hx/2, hx/2] x [-hy/2, hy/2]; column (kind, offset) holds the weights of
+// int_B h(|D - r'|) (kind 0; B split at the receiver's projection, the
+// pieces with D at a vertex by two triangles with r = s^2 grading, the
+// others by tensor Gauss-Legendre rules), of the face measures of d_x B and
+// d_y B against h (kinds 1, 2), and of the same faces against -dh/dx or
+// -dh/dy (kinds 3, 4, 5: derivative weights of h on its rho panel).  One
+// thread per column; offsets (di, dj) with |di| < Nx, |dj| < Ny.
+enum { RF_B0 = 0, RF_BX, RF_BY, RF_BXX, RF_BYY, RF_BXY, RF_COUNT };
+
+__device__ void rec_box(const FoldArgs &a, FoldAcc &f, double dx, double dy, double x0, double x1,
+                        double y0, double y1, double h, double *Mt, int64_t ncol, int64_t col) {
+  const double tol = 1e-9 * h;
+  int sing = -1;
+  const double vx[2] = {x0, x1}, vy[2] = {y0, y1};
+  for (int ia = 0; ia < 2; ++ia)
+    for (int ib = 0; ib < 2; ++ib)
+      if (fabs(vx[ia] - dx) < tol && fabs(vy[ib] - dy) < tol) sing = 2 * ia + ib;
+  if (sing >= 0) {
+    const double px = vx[sing >> 1], py = vy[sing & 1];
+    const double ox = vx[1 - (sing >> 1)], oy = vy[1 - (sing & 1)];
+    for (int tri = 0; tri < 2; ++tri) {
+      const double cx = tri == 0 ? ox : px, cy = tri == 0 ? py : oy;
+      const double e1x = cx - px, e1y = cy - py;
+      const double e2x = ox - cx, e2y = oy - cy;
+      const double det = fabs(e1x * e2y - e1y * e2x);
+      for (int i = 0; i < 24; ++i) {
+        const double sv = 0.5 * (a.gs_x[i] + 1.0), ws = 0.5 * a.gs_w[i];
+        const double r = sv * sv, wr = ws * 2.0 * sv;
+        for (int j = 0; j < 24; ++j) {
+          const double tt = 0.5 * (a.gs_x[j] + 1.0), wt = 0.5 * a.gs_w[j];
+          const double uu = px + r * (e1x + tt * e2x), vv = py + r * (e1y + tt * e2y);
+          fold_emit(a, f, hypot(dx - uu, dy - vv), wr * wt * r * det, Mt, ncol, col);
+        }
+      }
+    }
+    return;
+  }
+  const double dist = hypot(fmax(fmax(x0 - dx, 0.0), dx - x1), fmax(fmax(y0 - dy, 0.0), dy - y1));
+  const bool near = dist < 2.0 * h;
+  const double *rx = near ? a.g14_x : a.g8_x, *rw = near ? a.g14_w : a.g8_w;
+  const int n = near ? 14 : 8;
+  const int split = dist < 0.5 * h ? 3 : 1;
+  for (int ia = 0; ia < split; ++ia)
+    for (int ib = 0; ib < split; ++ib) {
+      const double xa = x0 + (x1 - x0) * ia / split, xb = x0 + (x1 - x0) * (ia + 1) / split;
+      const double ya = y0 + (y1 - y0) * ib / split, yb = y0 + (y1 - y0) * (ib + 1) / split;
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+          const double uu = 0.5 * (xa + xb) + 0.5 * (xb - xa) * rx[i];
+          const double vv = 0.5 * (ya + yb) + 0.5 * (yb - ya) * rx[j];
+          fold_emit(a, f, hypot(dx - uu, dy - vv), 0.25 * (xb - xa) * (yb - ya) * rw[i] * rw[j],
+                    Mt, ncol, col);
+        }
+    }
+}
+
+__global__ __launch_bounds__(128) void k_receiver_fold(FoldArgs a, double *__restrict__ Mt,
+                                                       int *__restrict__ kcol) {
+  const int nxo = 2 * a.nx - 1, nyo = 2 * a.ny - 1;
+  const int64_t noff = (int64_t)nxo * nyo, ncol = RF_COUNT * noff;
+  const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= ncol) return;
+  const int kind = (int)(col / noff), o = (int)(col - kind * noff);
+  const int dj = o / nxo - (a.ny - 1), di = o % nxo - (a.nx - 1);
+  const double hx = a.hx, hy = a.hy, dx = di * hx, dy = dj * hy;
+  FoldAcc f;
+  f.cur = -1;
+  f.lo = 1 << 30;
+  f.hi = 0;
+#pragma unroll
+  for (int k = 0; k < kFoldN; ++k) f.acc[k] = 0.0;
+  if (kind == RF_B0) {
+    // the footprint split at the receiver's projection
+    double xs[3] = {-hx / 2, hx / 2, hx / 2}, ys[3] = {-hy / 2, hy / 2, hy / 2};
+    int nxs = 2, nys = 2;
+    if (dx > -hx / 2 && dx < hx / 2) {
+      xs[1] = dx;
+      nxs = 3;
+    }
+    if (dy > -hy / 2 && dy < hy / 2) {
+      ys[1] = dy;
+      nys = 3;
+    }
+    for (int ia = 0; ia + 1 < nxs; ++ia)
+      for (int ib = 0; ib + 1 < nys; ++ib)
+        rec_box(a, f, dx, dy, xs[ia], xs[ia + 1], ys[ib], ys[ib + 1], fmin(hx, hy), Mt, ncol, col);
+  } else {
+    const bool xface = kind == RF_BX || kind == RF_BXX || kind == RF_BXY;
+    for (int side = 0; side < 2; ++side) {
+      const double sgn = side == 0 ? 1.0 : -1.0;
+      const double fpos = (side == 0 ? -0.5 : 0.5) * (xface ? hx : hy);
+      const double half = 0.5 * (xface ? hy : hx);
+      const double dn = xface ? dx : dy;  // normal coordinate of the receiver
+      const double dt = xface ? dy : dx;  // running coordinate
+      double cuts[3] = {-half, half, half};
+      int nc = 2;
+      if (dt > -half && dt < half) {
+        cuts[1] = dt;
+        nc = 3;
+      }
+      for (int piece = 0; piece + 1 < nc; ++piece) {
+        const double pa = cuts[piece], pb = cuts[piece + 1];
+        for (int i = 0; i < 24; ++i) {
+          const double tq = 0.5 * (pa + pb) + 0.5 * (pb - pa) * a.gs_x[i];
+          const double w = sgn * 0.5 * (pb - pa) * a.gs_w[i];
+          const double rho = hypot(dn - fpos, dt - tq);
+          if (kind == RF_BX || kind == RF_BY)
+            fold_emit(a, f, rho, w, Mt, ncol, col);
+          else if (kind == RF_BXX || kind == RF_BYY)
+            fold_emit(a, f, rho, -w * (dn - fpos) / rho, Mt, ncol, col, true);
+          else
+            fold_emit(a, f, rho, -w * (dt - tq) / rho, Mt, ncol, col, true);
+        }
+      }
+    }
+  }
+  fold_flush(f, Mt, ncol, col);
+  kcol[2 * col] = f.lo < f.hi ? f.lo : 0;
+  kcol[2 * col + 1] = f.lo < f.hi ? f.hi : 0;
+}
+
 }  // namespace
+
+hipError_t launch_receiver_fold(const double *args, int npan, int nrad, int nx, int ny, double hx,
+                                 double hy, double rho_min, double *Mt, int *kcol, hipStream_t s) {
+  // args as for launch_spatial_fold (the radial rule is not used)
+  FoldArgs a;
+  a.edges = args;
+  a.node = a.edges + npan + 1;
+  a.bw = a.node + kFoldN;
+  a.gs_x = a.bw + kFoldN;
+  a.gs_w = a.gs_x + 24;
+  a.g14_x = a.gs_w + 24;
+  a.g14_w = a.g14_x + 14;
+  a.g8_x = a.g14_w + 14;
+  a.g8_w = a.g8_x + 8;
+  a.rad_x = a.g8_w + 8;
+  a.rad_w = a.rad_x + nrad;
+  a.npan = npan;
+  a.nrad = nrad;
+  a.nx = nx;
+  a.ny = ny;
+  a.hx = hx;
+  a.hy = hy;
+  a.rho_min = rho_min;
+  const int64_t ncol = (int64_t)RF_COUNT * (2 * nx - 1) * (2 * ny - 1);
+  if (ncol <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_receiver_fold, dim3((unsigned)((ncol + 127) / 128)), dim3(128), 0, s, a, Mt,
+                     kcol);
+  return hipGetLastError();
+}
 
 hipError_t launch_spatial_fold(const double *args, int npan, int nrad, int nx, int ny, double hx,
                                double hy, double rho_min, double *Mt, int *kcol, hipStream_t s) {

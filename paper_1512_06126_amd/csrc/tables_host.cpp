@@ -67,6 +67,8 @@ hipError_t launch_hankel_weights(const double *args, int nzeros, int npan, int n
                                  double *Wt_reg, hipStream_t s);
 hipError_t launch_spatial_fold(const double *args, int npan, int nrad, int nx, int ny, double hx,
                                double hy, double rho_min, double *Mt, int *kcol, hipStream_t s);
+hipError_t launch_receiver_fold(const double *args, int npan, int nrad, int nx, int ny, double hx,
+                                double hy, double rho_min, double *Mt, int *kcol, hipStream_t s);
 
 namespace {
 
@@ -130,8 +132,8 @@ Rule tanh_sinh01(double h, double t_max) {
   return r;
 }
 
-// Chebyshev-Lobatto panels of equal width in u = ln x; barycentric
-// interpolation inside a panel.
+// Chebyshev-Lobatto panels of equal width in u = ln x (nodes, edges and
+// the barycentric weights of a panel).
 struct LogGrid {
   std::vector<double> edges, node, bw, x;
   int n = 0;
@@ -161,65 +163,8 @@ struct LogGrid {
             std::exp(0.5 * (edges[p] + edges[p + 1]) + 0.5 * (edges[p + 1] - edges[p]) * node[j]);
   }
   size_t size() const { return x.size(); }
-  // f(xq) ~ sum_j w[j] f(x[col0 + j]); returns col0
-  size_t interp(double xq, double *w) const {
-    const double u = std::log(xq);
-    const int np = (int)edges.size() - 1;
-    int p = (int)(std::upper_bound(edges.begin(), edges.end(), u) - edges.begin()) - 1;
-    p = std::min(std::max(p, 0), np - 1);
-    const double s = (2.0 * u - (edges[p] + edges[p + 1])) / (edges[p + 1] - edges[p]);
-    double tot = 0.0;
-    int hit = -1;
-    for (int j = 0; j < n; ++j) {
-      const double d = s - node[j];
-      if (std::fabs(d) < 1e-14) hit = j;
-      w[j] = hit >= 0 ? 0.0 : bw[j] / d;
-      tot += w[j];
-    }
-    if (hit >= 0) {
-      for (int j = 0; j < n; ++j) w[j] = (j == hit) ? 1.0 : 0.0;
-    } else {
-      for (int j = 0; j < n; ++j) w[j] /= tot;
-    }
-    return (size_t)p * n;
-  }
-  // d f / d x at xq: weights over the same n nodes (derivative of the panel's
-  // interpolating polynomial in u = ln x, divided by x)
-  size_t interp_deriv(double xq, double *w) const {
-    const double u = std::log(xq);
-    const int np = (int)edges.size() - 1;
-    int p = (int)(std::upper_bound(edges.begin(), edges.end(), u) - edges.begin()) - 1;
-    p = std::min(std::max(p, 0), np - 1);
-    const double width = edges[p + 1] - edges[p];
-    const double s = (2.0 * u - (edges[p] + edges[p + 1])) / width;
-    const double scale = 2.0 / width / xq;  // ds/du * du/dx
-    int hit = -1;
-    for (int j = 0; j < n; ++j)
-      if (std::fabs(s - node[j]) < 1e-14) hit = j;
-    if (hit >= 0) {
-      // row of the barycentric differentiation matrix
-      double diag = 0.0;
-      for (int j = 0; j < n; ++j) {
-        if (j == hit) continue;
-        w[j] = (bw[j] / bw[hit]) / (node[hit] - node[j]);
-        diag -= w[j];
-      }
-      w[hit] = diag;
-    } else {
-      double D = 0.0, Dd = 0.0;
-      double a[32], ad[32];
-      for (int j = 0; j < n; ++j) {
-        const double d = s - node[j];
-        a[j] = bw[j] / d;
-        ad[j] = -bw[j] / (d * d);
-        D += a[j];
-        Dd += ad[j];
-      }
-      for (int j = 0; j < n; ++j) w[j] = ad[j] / D - a[j] * Dd / (D * D);
-    }
-    for (int j = 0; j < n; ++j) w[j] *= scale;
-    return (size_t)p * n;
-  }
+  // (the barycentric interpolation on a panel, and its derivative, run in
+  // the rule-matrix kernels of kernels_tables.hip)
 };
 
 void parallel_for(int n, const std::function<void(int)> &f) {
@@ -363,17 +308,10 @@ const Rule &radial_rule() {
   return r;
 }
 
-// Spatial fold matrices Mt[rho][kind * noff + (i Nx + j)] for i, j >= 0,
-// built on the GPU (launch_spatial_fold) into dMt from the rho grid and the
-// quadrature rules set up here.  Rows of Mt with a non-zero entry in column c
-// lie in [kcol[2c], kcol[2c+1]) (copied back into kcol).
-int spatial_matrix(const giem_handle *t, const Grids &g, double *dMt, int *dkcol,
-                   std::vector<int> &kcol, hipStream_t s) {
-  const size_t noff = (size_t)t->nx * t->ny, nr = g.rho.size(), ncol = K_COUNT * noff;
-  if (g.rho.n != 12) {
-    set_error("giem_tables: the rho grid must have 12 nodes per panel");
-    return GIEM_EINVAL;
-  }
+// What the rule-matrix kernels read: the rho grid (edges, nodes and
+// barycentric weights of a panel), Gauss-Legendre rules of 24, 14 and 8
+// points and the radial (tanh-sinh) rule, nodes then weights.
+std::vector<double> fold_args(const Grids &g, int &nrad) {
   const Rule gs = gauss_legendre(24), g14 = gauss_legendre(14), g8 = gauss_legendre(8);
   const Rule &rad = radial_rule();
   std::vector<double> args;
@@ -389,6 +327,23 @@ int spatial_matrix(const giem_handle *t, const Grids &g, double *dMt, int *dkcol
   put(g8.w);
   put(rad.x);
   put(rad.w);
+  nrad = (int)rad.x.size();
+  return args;
+}
+
+// Spatial fold matrices Mt[rho][kind * noff + (i Nx + j)] for i, j >= 0,
+// built on the GPU (launch_spatial_fold) into dMt from the rho grid and the
+// quadrature rules set up here.  Rows of Mt with a non-zero entry in column c
+// lie in [kcol[2c], kcol[2c+1]) (copied back into kcol).
+int spatial_matrix(const giem_handle *t, const Grids &g, double *dMt, int *dkcol,
+                   std::vector<int> &kcol, hipStream_t s) {
+  const size_t noff = (size_t)t->nx * t->ny, nr = g.rho.size(), ncol = K_COUNT * noff;
+  if (g.rho.n != 12) {
+    set_error("giem_tables: the rho grid must have 12 nodes per panel");
+    return GIEM_EINVAL;
+  }
+  int nrad = 0;
+  const std::vector<double> args = fold_args(g, nrad);
   DevBuf dargs;
   if (dargs.alloc(args.size() * 8) != hipSuccess) {
     (void)hipGetLastError();
@@ -399,8 +354,8 @@ int spatial_matrix(const giem_handle *t, const Grids &g, double *dMt, int *dkcol
   if (check_hip(hipMemsetAsync(dMt, 0, nr * ncol * 8, s), "clear spatial weights") ||
       check_hip(hipMemcpyAsync(dargs.p, args.data(), args.size() * 8, hipMemcpyHostToDevice, s),
                 "upload spatial rules") ||
-      check_hip(launch_spatial_fold(dargs.d(), (int)g.rho.edges.size() - 1, (int)rad.x.size(),
-                                    t->nx, t->ny, t->hx, t->hy, g.rho_min, dMt, dkcol, s),
+      check_hip(launch_spatial_fold(dargs.d(), (int)g.rho.edges.size() - 1, nrad, t->nx, t->ny,
+                                    t->hx, t->hy, g.rho_min, dMt, dkcol, s),
                 "spatial weights") ||
       check_hip(hipMemcpyAsync(kcol.data(), dkcol, kcol.size() * sizeof(int),
                                hipMemcpyDeviceToHost, s),
@@ -440,120 +395,6 @@ std::vector<int> tile_ranges(const std::vector<int> &kcol, size_t col0, int m) {
 // with -1) and d_y B, and the kx^2, ky^2, kx ky terms the same faces against
 // -d h / d x or -d h / d y (derivative weights).
 enum { R_B0 = 0, R_BX, R_BY, R_BXX, R_BYY, R_BXY, R_COUNT };
-
-struct RulePtsD {
-  std::vector<double> rho, w;
-  std::vector<char> deriv;
-  void add(double r, double wt, bool d) {
-    rho.push_back(r);
-    w.push_back(wt);
-    deriv.push_back(d ? 1 : 0);
-  }
-};
-
-// int over [x0,x1] x [y0,y1] of h(|D - r'|); singular only at a vertex
-static void box_piece(double dx, double dy, double x0, double x1, double y0, double y1, double h,
-                      const Rule &gs, const Rule &g14, const Rule &g8, RulePtsD &out) {
-  const double tol = 1e-9 * h;
-  int sing = -1;
-  const double vx[2] = {x0, x1}, vy[2] = {y0, y1};
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b)
-      if (std::fabs(vx[a] - dx) < tol && std::fabs(vy[b] - dy) < tol) sing = 2 * a + b;
-  if (sing >= 0) {
-    const double px = vx[sing >> 1], py = vy[sing & 1];
-    const double ox = vx[1 - (sing >> 1)], oy = vy[1 - (sing & 1)];
-    const double ax[2] = {ox, px}, ay[2] = {py, oy};
-    const int n = (int)gs.x.size();
-    for (int tri = 0; tri < 2; ++tri) {
-      const double e1x = ax[tri] - px, e1y = ay[tri] - py;
-      const double e2x = ox - ax[tri], e2y = oy - ay[tri];
-      const double det = std::fabs(e1x * e2y - e1y * e2x);
-      for (int i = 0; i < n; ++i) {
-        const double sv = 0.5 * (gs.x[i] + 1.0), ws = 0.5 * gs.w[i];
-        const double r = sv * sv, wr = ws * 2.0 * sv;
-        for (int j = 0; j < n; ++j) {
-          const double tt = 0.5 * (gs.x[j] + 1.0), wt = 0.5 * gs.w[j];
-          const double u = px + r * (e1x + tt * e2x), v = py + r * (e1y + tt * e2y);
-          out.add(std::hypot(dx - u, dy - v), wr * wt * r * det, false);
-        }
-      }
-    }
-    return;
-  }
-  const double dist = std::hypot(std::max({x0 - dx, 0.0, dx - x1}), std::max({y0 - dy, 0.0, dy - y1}));
-  const Rule &rr = dist < 2.0 * h ? g14 : g8;
-  const int split = dist < 0.5 * h ? 3 : 1;
-  const int n = (int)rr.x.size();
-  for (int a = 0; a < split; ++a)
-    for (int b = 0; b < split; ++b) {
-      const double xa = x0 + (x1 - x0) * a / split, xb = x0 + (x1 - x0) * (a + 1) / split;
-      const double ya = y0 + (y1 - y0) * b / split, yb = y0 + (y1 - y0) * (b + 1) / split;
-      for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) {
-          const double u = 0.5 * (xa + xb) + 0.5 * (xb - xa) * rr.x[i];
-          const double v = 0.5 * (ya + yb) + 0.5 * (yb - ya) * rr.x[j];
-          out.add(std::hypot(dx - u, dy - v), 0.25 * (xb - xa) * (yb - ya) * rr.w[i] * rr.w[j],
-                  false);
-        }
-    }
-}
-
-static void receiver_rule(int kind, double dx, double dy, double hx, double hy, const Rule &gs,
-                          const Rule &g14, const Rule &g8, const Rule &gl, RulePtsD &out) {
-  if (kind == R_B0) {
-    // split the footprint at the receiver's projection
-    double xs[3] = {-hx / 2, 0, hx / 2}, ys[3] = {-hy / 2, 0, hy / 2};
-    int nxs = 2, nys = 2;
-    xs[1] = hx / 2;
-    ys[1] = hy / 2;
-    if (dx > -hx / 2 && dx < hx / 2) {
-      xs[1] = dx;
-      xs[2] = hx / 2;
-      nxs = 3;
-    }
-    if (dy > -hy / 2 && dy < hy / 2) {
-      ys[1] = dy;
-      ys[2] = hy / 2;
-      nys = 3;
-    }
-    for (int a = 0; a + 1 < nxs; ++a)
-      for (int b = 0; b + 1 < nys; ++b)
-        box_piece(dx, dy, xs[a], xs[a + 1], ys[b], ys[b + 1], std::min(hx, hy), gs, g14, g8, out);
-    return;
-  }
-  const bool xface = kind == R_BX || kind == R_BXX || kind == R_BXY;
-  const int n = (int)gl.x.size();
-  for (int side = 0; side < 2; ++side) {
-    const double sgn = side == 0 ? 1.0 : -1.0;
-    const double fpos = (side == 0 ? -0.5 : 0.5) * (xface ? hx : hy);
-    const double half = 0.5 * (xface ? hy : hx);
-    const double dn = xface ? dx : dy;  // normal coordinate of the receiver
-    const double dt = xface ? dy : dx;  // running coordinate
-    double cuts[3] = {-half, half, half};
-    int nc = 2;
-    if (dt > -half && dt < half) {
-      cuts[1] = dt;
-      cuts[2] = half;
-      nc = 3;
-    }
-    for (int piece = 0; piece + 1 < nc; ++piece) {
-      const double a = cuts[piece], b = cuts[piece + 1];
-      for (int i = 0; i < n; ++i) {
-        const double t = 0.5 * (a + b) + 0.5 * (b - a) * gl.x[i];
-        const double w = sgn * 0.5 * (b - a) * gl.w[i];
-        const double rho = std::hypot(dn - fpos, dt - t);
-        if (kind == R_BX || kind == R_BY) {
-          out.add(rho, w, false);
-        } else if (kind == R_BXX || kind == R_BYY) {
-          out.add(rho, -w * (dn - fpos) / rho, true);  // -dh/drho (normal) / rho
-        } else {
-          out.add(rho, -w * (dt - t) / rho, true);     // kx ky: running direction
-        }
-      }
-    }
-  }
-}
 
 // ----------------------------------------------------- vertical functions
 typedef std::complex<double> cx;
@@ -982,45 +823,20 @@ int compute_receiver_kernels(giem_handle *t, int ifreq, double z0, void **out, h
   const int nf = 8 * nz;  // complex functions per lambda
   const Grids g = make_grids(t);
   const size_t nl = g.lam.size(), nr = g.rho.size();
-  std::vector<double> Mt(nr * R_COUNT * noff, 0.0);
-  std::vector<int> kcol(2 * R_COUNT * noff);
-  {
-    const Rule gs = gauss_legendre(24), g14 = gauss_legendre(14), g8 = gauss_legendre(8);
-    const Rule gl = gauss_legendre(24);
-    const size_t ncol = R_COUNT * noff;
-    parallel_for((int)noff, [&](int o) {
-      const int dj = o / nxo - (ny - 1), di = o % nxo - (nx - 1);
-      double wi[32];
-      for (int kind = 0; kind < R_COUNT; ++kind) {
-        RulePtsD pts;
-        receiver_rule(kind, di * t->hx, dj * t->hy, t->hx, t->hy, gs, g14, g8, gl, pts);
-        const size_t col = kind * noff + o;
-        size_t lo = nr, hi = 0;
-        for (size_t q = 0; q < pts.rho.size(); ++q) {
-          const double r = std::max(pts.rho[q], g.rho_min);
-          const size_t c0 = pts.deriv[q] ? g.rho.interp_deriv(r, wi) : g.rho.interp(r, wi);
-          for (int k = 0; k < g.rho.n; ++k) Mt[(c0 + k) * ncol + col] += pts.w[q] * wi[k];
-          lo = std::min(lo, c0);
-          hi = std::max(hi, c0 + g.rho.n);
-        }
-        kcol[2 * col] = (int)lo;
-        kcol[2 * col + 1] = (int)hi;
-      }
-    });
-  }
   Vertical v;
   v.init(t, t->f[ifreq].freq);
   v.set_observer(z0);
   const bool touching = v.gap_lay.empty();
   std::vector<cx> G(nl * nf);
   parallel_for((int)nl, [&](int l) { v.point_row(g.lam.x[l], G.data() + (size_t)l * nf); });
-  const std::vector<int> kr = tile_ranges(kcol, 0, (int)(R_COUNT * noff));
-  DevBuf dW, dWr, dM, dG, dH, dC, dkr;
+  const size_t ncolr = (size_t)R_COUNT * noff;
+  DevBuf dW, dWr, dM, dG, dH, dC, dkr, dkcol;
   void *dK = nullptr;
   if (dW.alloc(nl * nr * 8) != hipSuccess || dWr.alloc(nl * nr * 8) != hipSuccess ||
-      dM.alloc(Mt.size() * 8) != hipSuccess || dG.alloc(G.size() * 16) != hipSuccess ||
+      dM.alloc(nr * ncolr * 8) != hipSuccess || dkcol.alloc(2 * ncolr * sizeof(int)) != hipSuccess ||
+      dG.alloc(G.size() * 16) != hipSuccess ||
       dH.alloc(nr * nf * 16) != hipSuccess || dC.alloc((size_t)R_COUNT * noff * nf * 16) != hipSuccess ||
-      dkr.alloc(kr.size() * sizeof(int)) != hipSuccess ||
+      dkr.alloc(2 * ((ncolr + 63) / 64) * sizeof(int)) != hipSuccess ||
       hipMalloc(&dK, noff * nz * 18 * sizeof(c128)) != hipSuccess) {
     if (dK) hipFree(dK);
     (void)hipGetLastError();  // reported here, not by the next launch check
@@ -1030,15 +846,43 @@ int compute_receiver_kernels(giem_handle *t, int ifreq, double z0, void **out, h
   const int64_t ldg = 2 * (int64_t)nf;
   const int64_t ldm = (int64_t)R_COUNT * noff;
   int rc = GIEM_OK;
+  std::vector<int> kr;
   {
-    const int hrc = hankel_weights(g, dW.d(), dWr.d(), s);
+    int hrc = hankel_weights(g, dW.d(), dWr.d(), s);
+    if (hrc == GIEM_OK) {
+      // the receiver rule matrix on the GPU, its row ranges back for the
+      // contraction ranges
+      int nrad = 0;
+      const std::vector<double> args = fold_args(g, nrad);
+      std::vector<int> kcol(2 * ncolr);
+      DevBuf dargs;
+      if (dargs.alloc(args.size() * 8) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("giem_fields: out of device memory for the receiver kernels");
+        hrc = GIEM_ENOMEM;
+      } else if (check_hip(hipMemsetAsync(dM.p, 0, nr * ncolr * 8, s), "clear receiver weights") ||
+                 check_hip(hipMemcpyAsync(dargs.p, args.data(), args.size() * 8,
+                                          hipMemcpyHostToDevice, s),
+                           "upload receiver rules") ||
+                 check_hip(launch_receiver_fold(dargs.d(), (int)g.rho.edges.size() - 1, nrad, nx, ny,
+                                                t->hx, t->hy, g.rho_min, dM.d(),
+                                                static_cast<int *>(dkcol.p), s),
+                           "receiver weights") ||
+                 check_hip(hipMemcpyAsync(kcol.data(), dkcol.p, kcol.size() * sizeof(int),
+                                          hipMemcpyDeviceToHost, s),
+                           "receiver weight ranges") ||
+                 check_hip(hipStreamSynchronize(s), "receiver weights")) {
+        hrc = GIEM_EHIP;
+      } else {
+        kr = tile_ranges(kcol, 0, (int)ncolr);
+      }
+    }
     if (hrc != GIEM_OK) {
       hipFree(dK);
       return hrc;
     }
   }
-  if (check_hip(hipMemcpyAsync(dM.p, Mt.data(), Mt.size() * 8, hipMemcpyHostToDevice, s), "upload") ||
-      check_hip(hipMemcpyAsync(dG.p, G.data(), G.size() * 16, hipMemcpyHostToDevice, s), "upload") ||
+  if (check_hip(hipMemcpyAsync(dG.p, G.data(), G.size() * 16, hipMemcpyHostToDevice, s), "upload") ||
       check_hip(hipMemcpyAsync(dkr.p, kr.data(), kr.size() * sizeof(int), hipMemcpyHostToDevice, s),
                 "upload") ||
       // plain functions 0..5, regularised 6..7
