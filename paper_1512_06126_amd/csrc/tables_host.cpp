@@ -25,7 +25,8 @@
 //  4. the nine components are formed and packed (upper triangles of xx, xy,
 //     yy, zz; full xz, yz).
 // The receiver kernels (compute_receiver_kernels) evaluate their lambda
-// functions and point rules on the host and contract them on the GPU.
+// functions on the host (the same vertical.h); their rule matrix, Hankel
+// weights and contractions run on the GPU.
 // The lambda-functions, with sigma_n the conductivity of the observation
 // cell and P = -i w mu0 A1 + A3 / sigma_n:
 //   A1 = int int U_1;  A3 = int int (d_z d_z* U_sigma - 2 delta) (regular
