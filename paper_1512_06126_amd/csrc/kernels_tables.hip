@@ -356,6 +356,24 @@ __global__ __launch_bounds__(256) void k_vert_cells(vert::Model m, int nl,
                      p + (size_t)2 * l * nlayers, q + (size_t)2 * l * nlayers, cells[idx]);
 }
 
+// the point observer's lambda functions of node l into G[l][8 nz]
+__global__ __launch_bounds__(64) void k_vert_point(vert::Model m, vert::Observer ob,
+                                                   const double *__restrict__ lam, int nl,
+                                                   const vert::zc *__restrict__ eta,
+                                                   const double *__restrict__ L,
+                                                   const vert::zc *__restrict__ p,
+                                                   const vert::zc *__restrict__ q,
+                                                   const vert::Cell *__restrict__ cells,
+                                                   vert::zc *G) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= nl) return;
+  const int nlayers = m.nlay + 1;
+  const vert::Cell *c0 = cells + (size_t)l * 2 * m.nz;
+  vert::point_row(lam[l], m, ob, eta + (size_t)l * nlayers, L + (size_t)l * nlayers,
+                  p + (size_t)2 * l * nlayers, q + (size_t)2 * l * nlayers, c0, c0 + m.nz,
+                  G + (size_t)l * 8 * m.nz);
+}
+
 // row i of the lambda functions of node l into G[l][ncolc]
 __global__ __launch_bounds__(256) void k_vert_rows(vert::Model m, const double *__restrict__ lam,
                                                    int nl, const vert::Cell *__restrict__ cells,
@@ -937,6 +955,21 @@ hipError_t launch_hankel_weights(const double *args, int nzeros, int npan, int n
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_hankel_weights, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, s, a, Wt,
                      Wt_reg);
+  return hipGetLastError();
+}
+
+hipError_t launch_vertical_point(const vert::Model &m, const vert::Observer &ob, const double *lam,
+                                 int nl, vert::zc *eta, double *L, vert::zc *p, vert::zc *q,
+                                 vert::Cell *cells, vert::zc *G, hipStream_t s) {
+  if (nl <= 0 || m.nz <= 0) return hipSuccess;
+  const int64_t ncell = (int64_t)nl * 2 * m.nz;
+  if ((ncell + 255) / 256 > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_vert_layers, dim3((nl + 255) / 256), dim3(256), 0, s, m, lam, nl, eta, L, p,
+                     q);
+  hipLaunchKernelGGL(k_vert_cells, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, s, m, nl,
+                     eta, L, p, q, cells);
+  hipLaunchKernelGGL(k_vert_point, dim3((nl + 63) / 64), dim3(64), 0, s, m, ob, lam, nl, eta, L, p,
+                     q, cells, G);
   return hipGetLastError();
 }
 

@@ -44,8 +44,6 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
-#include <functional>
-#include <thread>
 #include <vector>
 
 #include "handle.h"
@@ -63,6 +61,9 @@ hipError_t launch_assemble_rec(const c128 *c, c128 *out, int noff, int nz, doubl
 hipError_t launch_vertical_rows(const vert::Model &m, const double *lam, int nl, vert::zc *eta,
                                 double *L, vert::zc *p, vert::zc *q, vert::Cell *cells,
                                 vert::zc *G, int ncolc, hipStream_t s);
+hipError_t launch_vertical_point(const vert::Model &m, const vert::Observer &ob, const double *lam,
+                                 int nl, vert::zc *eta, double *L, vert::zc *p, vert::zc *q,
+                                 vert::Cell *cells, vert::zc *G, hipStream_t s);
 hipError_t launch_hankel_weights(const double *args, int nzeros, int npan, int nr, int ng1, int ng2,
                                  int nt, double lam_lo, double lam_a, double lam_asym, double *Wt,
                                  double *Wt_reg, hipStream_t s);
@@ -168,21 +169,6 @@ struct LogGrid {
   // the rule-matrix kernels of kernels_tables.hip)
 };
 
-void parallel_for(int n, const std::function<void(int)> &f) {
-  int nt = (int)std::thread::hardware_concurrency();
-  nt = std::max(1, std::min(nt, 32));
-  nt = std::min(nt, n);
-  if (nt <= 1) {
-    for (int i = 0; i < n; ++i) f(i);
-    return;
-  }
-  std::vector<std::thread> th;
-  for (int t = 0; t < nt; ++t)
-    th.emplace_back([&, t] {
-      for (int i = t; i < n; i += nt) f(i);
-    });
-  for (auto &x : th) x.join();
-}
 
 // ------------------------------------------------------------ Bessel zeros
 std::vector<double> j0_zeros(int count) {
@@ -407,11 +393,11 @@ struct Layering {
 };
 
 // The layered model seen from the depth cells (and from a point observer for
-// the receiver kernels), with the per-lambda cell factors of the vertical
-// functions.
+// the receiver kernels): each cell's layer and local edge depths, the point
+// observer's layer and gap pieces; the vertical functions themselves are
+// computed on the GPU from these (vertical.h).
 struct Vertical {
   const giem_handle *t;
-  double omega;
   int nz;
   std::vector<int> lay;          // layer of each cell
   std::vector<double> ta, tb;    // local coordinates of the cell edges
@@ -449,10 +435,9 @@ struct Vertical {
       a = b;
     }
   }
-  void init(const giem_handle *h, double freq) {
+  void init(const giem_handle *h) {
     t = h;
     nz = h->nz;
-    omega = 2 * kPi * freq;
     lay.resize(nz);
     ta.resize(nz);
     tb.resize(nz);
@@ -468,89 +453,6 @@ struct Vertical {
     set_observer(h->z_edges[0]);
   }
 
-  // per-cell factors of both kinds (k = 0: gamma = 1, k = 1: gamma = sigma)
-  struct Cell {
-    cx theta, FI, FD, GI, GD, diagA, diagA4, diagA3, diagA6;
-    cx thetad;  // F'(top) / F(bottom): the top cell's ratio differentiated at its top
-    cx GId;     // d/dz of int_cell U(z, z*) dz* at the cell's top edge
-    cx GDd;     // d/dz of U(z, bottom) - U(z, top) at the top edge (regular part)
-  };
-
-  // eta and the downward coefficients p of every layer (kind 0 and 1)
-  struct LayerFns {
-    std::vector<cx> eta, p[2], q[2];
-    std::vector<double> L;
-  };
-
-  // the layered model in the form of the shared vertical functions
-  vert::Model model() const {
-    vert::Model m;
-    m.nz = nz;
-    m.nlay = t->nlay;
-    m.omega_mu0 = omega * kMu0;
-    m.sigma = sig.data();
-    m.d = t->d.data();
-    m.lay = lay.data();
-    m.ta = ta.data();
-    m.tb = tb.data();
-    return m;
-  }
-
-  void factors(double lam, std::vector<Cell> (&cell)[2], LayerFns *lf = nullptr) const {
-    const int nlayers = t->nlay + 1;
-    const vert::Model m = model();
-    std::vector<vert::zc> eta(nlayers), p(2 * nlayers), q(2 * nlayers);
-    std::vector<double> L(nlayers);
-    vert::layer_fns(lam, m, eta.data(), L.data(), p.data(), q.data());
-    auto C = [](vert::zc z) { return cx(z.x, z.y); };
-    if (lf) {
-      lf->eta.resize(nlayers);
-      lf->L = L;
-      for (int n = 0; n < nlayers; ++n) lf->eta[n] = C(eta[n]);
-      for (int k = 0; k < 2; ++k) {
-        lf->p[k].resize(nlayers);
-        lf->q[k].resize(nlayers);
-        for (int n = 0; n < nlayers; ++n) {
-          lf->p[k][n] = C(p[k * nlayers + n]);
-          lf->q[k][n] = C(q[k * nlayers + n]);
-        }
-      }
-    }
-    for (int k = 0; k < 2; ++k) {
-      cell[k].resize(nz);
-      for (int l = 0; l < nz; ++l) {
-        vert::Cell c;
-        vert::cell_factors(l, k, m, eta.data(), L.data(), p.data(), q.data(), c);
-        Cell &o = cell[k][l];
-        o.theta = C(c.theta);
-        o.FI = C(c.FI);
-        o.FD = C(c.FD);
-        o.GI = C(c.GI);
-        o.GD = C(c.GD);
-        o.diagA = C(c.diagA);
-        o.diagA4 = C(c.diagA4);
-        o.diagA3 = C(c.diagA3);
-        o.diagA6 = C(c.diagA6);
-        o.thetad = C(c.thetad);
-        o.GId = C(c.GId);
-        o.GDd = C(c.GDd);
-      }
-    }
-  }
-
-  // Point observer at depth z0 (set_observer): at the top of the first cell
-  // (on the earth side), or above the grid inside the earth; the eight
-  // lambda-functions of every source level jz,
-  // written as out[f * nz + jz]:
-  //   0 lambda A1, 1 lambda A2, 2 lambda dA1, 3 lambda A4 / s, 4 lambda A5 / s,
-  //   5 lambda A6 / s, 6 P / lambda, 7 Q / lambda   (s: surface layer)
-  // with A1 = int U_1, A2 = int U_s, dA1 = d/dz A1, A4 = d/dz A2,
-  // A5 = U_s(z, bottom) - U_s(z, top), A3 = d/dz A5 (regular part),
-  // A6 = lambda^2 A2 - 2 [observer in the cell], P = -i w mu0 A1 + A3 / s,
-  // Q = dA1 + A5.  U(z0, z*) = F(z0) G(z*) / ..., so for the cell jz below
-  // the observer the z0-dependence is the product of the top-to-bottom
-  // ratios of the cells above it; the cell the observer sits on uses the
-  // derivative at its own top edge.
   // large-lambda limit of lambda^2 A2 - 2 for the observer on the top face
   // of its own cell: every eta tends to lambda, so lambda^2 A2 -> 1 + p with
   // p -> (s0 - s1) / (s0 + s1) when an interface lies at that face (s0 the
@@ -564,132 +466,85 @@ struct Vertical {
     const cx s0 = interface ? t->sigma[n - 1] : s1;
     return (s0 - s1) / (s0 + s1) - 1.0;
   }
-
-  void point_row(double lam, cx *out) const {
-    std::vector<Cell> cell[2];
-    LayerFns lf;
-    factors(lam, cell, &lf);
-    const cx iwm(0.0, omega * kMu0);
-    const cx so = t->sigma[lay_obs];
-    cx R[2] = {1.0, 1.0}, Rd[2] = {0.0, 0.0};
-    if (below) {
-      // observer below the grid, source cell above it: U(z0, z*) = F(z*)
-      // G(z0) / (eta D) of the observer's layer (for the sigma kind times
-      // sigma_obs / sigma_source, the reciprocity sigma_s U(z, z*) =
-      // sigma_r U(z*, z)).  With Rb = F(bottom of the cell) / F(z0), the
-      // product of the ratios F(a) / F(b) over the cells below it and the
-      // gap, int_cell U(z0, z*) dz* = FI Rb U0 and U(z0, bottom) - U(z0,
-      // top) = FD Rb U0, with U0 = F(z0) G(z0) / (eta D) (and F(z0) G'(z0)
-      // / (eta D) for the z0-derivatives) in the observer's layer.
-      const int n0 = lay_obs;
-      const double t0 = z0 - t->d[n0 - 1];
-      const bool half = !std::isfinite(lf.L[n0]);
-      cx U0[2], U0d[2], Rb[2] = {1.0, 1.0};
-      for (int k = 0; k < 2; ++k) {
-        const cx e = lf.eta[n0], P = lf.p[k][n0], Q = lf.q[k][n0];
-        const cx fa0 = 1.0 + P * std::exp(-2.0 * e * t0);
-        const cx qq = half ? cx(0.0) : Q * std::exp(-2.0 * e * (lf.L[n0] - t0));
-        const cx D = half ? cx(1.0) : 1.0 - P * Q * std::exp(-2.0 * e * lf.L[n0]);
-        U0[k] = fa0 * (1.0 + qq) / (e * D);
-        U0d[k] = -fa0 * (1.0 - qq) / D;
-        for (size_t i = 0; i < gap_lay.size(); ++i) {
-          const int n = gap_lay[i];
-          const cx en = lf.eta[n], Pn = lf.p[k][n];
-          const double a = gap_ta[i], b = gap_tb[i];
-          Rb[k] *= std::exp(-en * (b - a)) * (1.0 + Pn * std::exp(-2.0 * en * a)) /
-                   (1.0 + Pn * std::exp(-2.0 * en * b));
-        }
-      }
-      for (int jz = nz - 1; jz >= 0; --jz) {
-        const cx ss = so / t->sigma[lay[jz]];  // sigma_obs / sigma_source
-        const cx A1 = cell[0][jz].FI * Rb[0] * U0[0];
-        const cx dA1 = cell[0][jz].FI * Rb[0] * U0d[0];
-        const cx A2 = ss * cell[1][jz].FI * Rb[1] * U0[1];
-        const cx A4 = ss * cell[1][jz].FI * Rb[1] * U0d[1];
-        const cx A5 = ss * cell[1][jz].FD * Rb[1] * U0[1];
-        const cx A3 = ss * cell[1][jz].FD * Rb[1] * U0d[1];
-        const cx A6 = lam * lam * A2;
-        out[0 * nz + jz] = lam * A1;
-        out[1 * nz + jz] = lam * A2;
-        out[2 * nz + jz] = lam * dA1;
-        out[3 * nz + jz] = lam * A4 / so;
-        out[4 * nz + jz] = lam * A5 / so;
-        out[5 * nz + jz] = lam * A6 / so;
-        out[6 * nz + jz] = (-iwm * A1 + A3 / so) / lam;
-        out[7 * nz + jz] = (dA1 + A5) / lam;
-        for (int k = 0; k < 2; ++k) Rb[k] *= cell[k][jz].theta;
-      }
-      return;
-    }
-    const bool gap = !gap_lay.empty();
-    if (gap) {
-      // observer above the grid: U(z0, z*) = F(z0) G(z*) / W for every source
-      // cell, so each cell's functions at the top of the grid are carried up
-      // by F(z0) / F(top) (and F'(z0) / F(top) for the derivatives), the
-      // product of the ratios F(a) / F(b) over the pieces of the gap (F is
-      // continuous across interfaces; in a layer F(t) = e^{eta t} + p
-      // e^{-eta t} from the layer's top)
-      for (int k = 0; k < 2; ++k) {
-        for (size_t i = 0; i < gap_lay.size(); ++i) {
-          const int n = gap_lay[i];
-          const cx e = lf.eta[n], P = lf.p[k][n];
-          const double a = gap_ta[i], b = gap_tb[i];
-          const cx eh = std::exp(-e * (b - a));
-          const cx fa = 1.0 + P * std::exp(-2.0 * e * a), fb = 1.0 + P * std::exp(-2.0 * e * b);
-          const cx th = eh * fa / fb;
-          if (i == 0) Rd[k] = e * eh * (1.0 - P * std::exp(-2.0 * e * a)) / fb;
-          else Rd[k] *= th;
-          R[k] *= th;
-        }
-      }
-    }
-    for (int jz = 0; jz < nz; ++jz) {
-      cx A1, A2, dA1, A4, A5, A3;
-      if (gap) {
-        A1 = R[0] * cell[0][jz].GI;
-        A2 = R[1] * cell[1][jz].GI;
-        dA1 = Rd[0] * cell[0][jz].GI;
-        A4 = Rd[1] * cell[1][jz].GI;
-        A5 = R[1] * cell[1][jz].GD;
-        A3 = Rd[1] * cell[1][jz].GD;
-      } else if (jz == 0) {
-        A1 = cell[0][0].GI;
-        A2 = cell[1][0].GI;
-        dA1 = cell[0][0].GId;
-        A4 = cell[1][0].GId;
-        A5 = cell[1][0].GD;
-        A3 = cell[1][0].GDd;
-      } else {
-        A1 = R[0] * cell[0][jz].GI;
-        A2 = R[1] * cell[1][jz].GI;
-        dA1 = Rd[0] * cell[0][jz].GI;
-        A4 = Rd[1] * cell[1][jz].GI;
-        A5 = R[1] * cell[1][jz].GD;
-        A3 = Rd[1] * cell[1][jz].GD;
-      }
-      // the observer's own cell: A6 tends to the constant a6_inf, whose
-      // transform is a delta at the observer; it is taken out here and added
-      // exactly to the own cell's G_zz (see compute_receiver_kernels)
-      const cx A6 = lam * lam * A2 - ((jz == 0 && !gap) ? 2.0 + a6_inf() : 0.0);
-      const cx Pv = -iwm * A1 + A3 / so;
-      const cx Qv = dA1 + A5;
-      out[0 * nz + jz] = lam * A1;
-      out[1 * nz + jz] = lam * A2;
-      out[2 * nz + jz] = lam * dA1;
-      out[3 * nz + jz] = lam * A4 / so;
-      out[4 * nz + jz] = lam * A5 / so;
-      out[5 * nz + jz] = lam * A6 / so;
-      out[6 * nz + jz] = Pv / lam;
-      out[7 * nz + jz] = Qv / lam;
-      // ratios from the observer to the top of the next cell
-      for (int k = 0; k < 2; ++k) {
-        Rd[k] = (jz == 0 && !gap) ? cell[k][0].thetad : Rd[k] * cell[k][jz].theta;
-        R[k] *= cell[k][jz].theta;
-      }
-    }
-  }
 };
 
+
+}  // namespace
+
+namespace {
+
+// The layered model, the lambda nodes and the workspace of the vertical
+// functions on the device: sigma [nlay + 1] (complex), d [nlay], ta, tb [nz],
+// lambda [nl], then the cells' layers [nz] and, for a point observer, its
+// gap pieces (layer; local top and bottom); eta, p, q (complex) and L per
+// node and layer, and the cell factors of both kinds per node and cell.
+struct VertDev {
+  DevBuf mod, ilay, ws, cell;
+  std::vector<double> hmod;  // kept until the uploads have run
+  std::vector<int> hlay;
+  vert::Model m{};
+  vert::Observer ob{};
+  const double *lam = nullptr;
+  vert::zc *eta = nullptr, *p = nullptr, *q = nullptr;
+  double *L = nullptr;
+  vert::Cell *cells = nullptr;
+
+  int init(const giem_handle *t, const Vertical &v, const std::vector<double> &lamx,
+           hipStream_t s) {
+    const int nz = t->nz, nlayers = t->nlay + 1, ngap = (int)v.gap_lay.size();
+    const size_t nl = lamx.size();
+    hmod.clear();
+    for (int n = 0; n < nlayers; ++n) {
+      hmod.push_back(v.sig[n].x);
+      hmod.push_back(v.sig[n].y);
+    }
+    hmod.insert(hmod.end(), t->d.begin(), t->d.end());
+    hmod.insert(hmod.end(), v.ta.begin(), v.ta.end());
+    hmod.insert(hmod.end(), v.tb.begin(), v.tb.end());
+    hmod.insert(hmod.end(), lamx.begin(), lamx.end());
+    hmod.insert(hmod.end(), v.gap_ta.begin(), v.gap_ta.end());
+    hmod.insert(hmod.end(), v.gap_tb.begin(), v.gap_tb.end());
+    hlay = v.lay;
+    hlay.insert(hlay.end(), v.gap_lay.begin(), v.gap_lay.end());
+    const size_t nws = nl * nlayers;  // (node, layer) pairs
+    if (mod.alloc(hmod.size() * 8) != hipSuccess || ilay.alloc(hlay.size() * sizeof(int)) != hipSuccess ||
+        ws.alloc(nws * (5 * sizeof(vert::zc) + sizeof(double))) != hipSuccess ||
+        cell.alloc(nl * 2 * nz * sizeof(vert::Cell)) != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("out of device memory for the vertical functions");
+      return GIEM_ENOMEM;
+    }
+    if (check_hip(hipMemcpyAsync(mod.p, hmod.data(), hmod.size() * 8, hipMemcpyHostToDevice, s),
+                  "upload layered model") ||
+        check_hip(hipMemcpyAsync(ilay.p, hlay.data(), hlay.size() * sizeof(int),
+                                 hipMemcpyHostToDevice, s),
+                  "upload layered model"))
+      return GIEM_EHIP;
+    m.nz = nz;
+    m.nlay = t->nlay;
+    m.sigma = reinterpret_cast<const vert::zc *>(mod.d());
+    m.d = mod.d() + 2 * nlayers;
+    m.ta = m.d + t->nlay;
+    m.tb = m.ta + nz;
+    lam = m.tb + nz;
+    m.lay = static_cast<const int *>(ilay.p);
+    ob.z0 = v.z0;
+    ob.lay_obs = v.lay_obs;
+    ob.below = v.below;
+    ob.ngap = ngap;
+    ob.gap_ta = lam + nl;
+    ob.gap_tb = ob.gap_ta + ngap;
+    ob.gap_lay = m.lay + nz;
+    const vert::zc a6 = vert::Z(v.a6_inf().real(), v.a6_inf().imag());
+    ob.a6 = a6;
+    eta = static_cast<vert::zc *>(ws.p);
+    p = eta + nws;
+    q = p + 2 * nws;
+    L = reinterpret_cast<double *>(q + 2 * nws);
+    cells = static_cast<vert::Cell *>(cell.p);
+    return GIEM_OK;
+  }
+};
 
 }  // namespace
 
@@ -708,36 +563,14 @@ int compute_tables(giem_handle *t, hipStream_t s) {
   const size_t kr1 = 2 * ((noff + 63) / 64), kr2 = kr1 + 2 * ((3 * noff + 63) / 64);
   const size_t nkr = kr2 + 2 * ((2 * noff + 63) / 64);
   const size_t ncolm = (size_t)K_COUNT * noff;
-  // the layered model and the lambda nodes on the device: sigma [nlay + 1]
-  // (complex), d [nlay], ta, tb [nz], lambda [nl], then the cells' layers
-  // [nz] (int); workspace of the vertical functions: eta, p, q (complex) and
-  // L per node and layer, the cell factors of both kinds per node and cell
   Vertical v;
-  v.init(t, t->f.empty() ? 0.0 : t->f[0].freq);
-  const int nlayers = t->nlay + 1;
-  const size_t nmod = 2 * (size_t)nlayers + t->nlay + 2 * (size_t)nz + nl;
-  std::vector<double> model(nmod);
-  {
-    double *o = model.data();
-    for (int n = 0; n < nlayers; ++n, o += 2) {
-      o[0] = v.sig[n].x;
-      o[1] = v.sig[n].y;
-    }
-    o = std::copy(t->d.begin(), t->d.end(), o);
-    o = std::copy(v.ta.begin(), v.ta.end(), o);
-    o = std::copy(v.tb.begin(), v.tb.end(), o);
-    std::copy(g.lam.x.begin(), g.lam.x.end(), o);
-  }
-  const size_t nws = nl * nlayers;  // (node, layer) pairs
-  DevBuf dW, dWr, dM, dG, dH, dc0, dc1, dc2, dmod, dlay, dws, dcell, dkr, dkcol;
+  v.init(t);
+  DevBuf dW, dWr, dM, dG, dH, dc0, dc1, dc2, dkr, dkcol;
   if (dW.alloc(nl * nr * 8) != hipSuccess || dWr.alloc(nl * nr * 8) != hipSuccess ||
       dM.alloc(nr * ncolm * 8) != hipSuccess || dkcol.alloc(2 * ncolm * sizeof(int)) != hipSuccess ||
       dG.alloc(nl * ncolc * 16) != hipSuccess ||
       dH.alloc(nr * ncolc * 16) != hipSuccess || dc0.alloc(noff * 2 * T * 16) != hipSuccess ||
       dc1.alloc(3 * noff * T * 16) != hipSuccess || dc2.alloc(2 * noff * nz2 * 16) != hipSuccess ||
-      dmod.alloc(nmod * 8) != hipSuccess || dlay.alloc((size_t)nz * sizeof(int)) != hipSuccess ||
-      dws.alloc(nws * (5 * sizeof(vert::zc) + sizeof(double))) != hipSuccess ||
-      dcell.alloc(nl * 2 * nz * sizeof(vert::Cell)) != hipSuccess ||
       dkr.alloc(nkr * sizeof(int)) != hipSuccess) {
     (void)hipGetLastError();  // reported here, not by the next launch check
     set_error("giem_tables: out of device memory");
@@ -754,31 +587,18 @@ int compute_tables(giem_handle *t, hipStream_t s) {
     kr.insert(kr.end(), a.begin(), a.end());
     kr.insert(kr.end(), b.begin(), b.end());
   }
-  if (check_hip(hipMemcpyAsync(dmod.p, model.data(), nmod * 8, hipMemcpyHostToDevice, s),
-                "upload layered model") ||
-      check_hip(hipMemcpyAsync(dlay.p, v.lay.data(), (size_t)nz * sizeof(int),
-                               hipMemcpyHostToDevice, s),
-                "upload layered model") ||
-      check_hip(hipMemcpyAsync(dkr.p, kr.data(), kr.size() * sizeof(int), hipMemcpyHostToDevice, s),
+  VertDev vd;
+  {
+    const int rc = vd.init(t, v, g.lam.x, s);
+    if (rc != GIEM_OK) return rc;
+  }
+  if (check_hip(hipMemcpyAsync(dkr.p, kr.data(), kr.size() * sizeof(int), hipMemcpyHostToDevice, s),
                 "upload contraction ranges"))
     return GIEM_EHIP;
   const int *dkr0 = static_cast<const int *>(dkr.p);
-  vert::Model dm;
-  dm.nz = nz;
-  dm.nlay = t->nlay;
-  dm.sigma = reinterpret_cast<const vert::zc *>(dmod.d());
-  dm.d = dmod.d() + 2 * nlayers;
-  dm.ta = dm.d + t->nlay;
-  dm.tb = dm.ta + nz;
-  const double *dlam = dm.tb + nz;
-  dm.lay = static_cast<const int *>(dlay.p);
-  vert::zc *deta = static_cast<vert::zc *>(dws.p);
-  vert::zc *dp = deta + nws, *dq = dp + 2 * nws;
-  double *dL = reinterpret_cast<double *>(dq + 2 * nws);
   for (size_t q = 0; q < t->f.size(); ++q) {
-    dm.omega_mu0 = 2 * kPi * t->f[q].freq * kMu0;
-    if (check_hip(launch_vertical_rows(dm, dlam, (int)nl, deta, dL, dp, dq,
-                                       static_cast<vert::Cell *>(dcell.p),
+    vd.m.omega_mu0 = 2 * kPi * t->f[q].freq * kMu0;
+    if (check_hip(launch_vertical_rows(vd.m, vd.lam, (int)nl, vd.eta, vd.L, vd.p, vd.q, vd.cells,
                                        static_cast<vert::zc *>(dG.p), ncolc, s),
                   "vertical functions"))
       return GIEM_EHIP;
@@ -825,17 +645,15 @@ int compute_receiver_kernels(giem_handle *t, int ifreq, double z0, void **out, h
   const Grids g = make_grids(t);
   const size_t nl = g.lam.size(), nr = g.rho.size();
   Vertical v;
-  v.init(t, t->f[ifreq].freq);
+  v.init(t);
   v.set_observer(z0);
-  const bool touching = v.gap_lay.empty();
-  std::vector<cx> G(nl * nf);
-  parallel_for((int)nl, [&](int l) { v.point_row(g.lam.x[l], G.data() + (size_t)l * nf); });
+  const bool touching = v.gap_lay.empty() && !v.below;
   const size_t ncolr = (size_t)R_COUNT * noff;
   DevBuf dW, dWr, dM, dG, dH, dC, dkr, dkcol;
   void *dK = nullptr;
   if (dW.alloc(nl * nr * 8) != hipSuccess || dWr.alloc(nl * nr * 8) != hipSuccess ||
       dM.alloc(nr * ncolr * 8) != hipSuccess || dkcol.alloc(2 * ncolr * sizeof(int)) != hipSuccess ||
-      dG.alloc(G.size() * 16) != hipSuccess ||
+      dG.alloc(nl * nf * 16) != hipSuccess ||
       dH.alloc(nr * nf * 16) != hipSuccess || dC.alloc((size_t)R_COUNT * noff * nf * 16) != hipSuccess ||
       dkr.alloc(2 * ((ncolr + 63) / 64) * sizeof(int)) != hipSuccess ||
       hipMalloc(&dK, noff * nz * 18 * sizeof(c128)) != hipSuccess) {
@@ -883,7 +701,19 @@ int compute_receiver_kernels(giem_handle *t, int ifreq, double z0, void **out, h
       return hrc;
     }
   }
-  if (check_hip(hipMemcpyAsync(dG.p, G.data(), G.size() * 16, hipMemcpyHostToDevice, s), "upload") ||
+  // the observer's lambda functions on the GPU
+  VertDev vd;
+  {
+    const int vrc = vd.init(t, v, g.lam.x, s);
+    if (vrc != GIEM_OK) {
+      hipFree(dK);
+      return vrc;
+    }
+    vd.m.omega_mu0 = 2 * kPi * t->f[ifreq].freq * kMu0;
+  }
+  if (check_hip(launch_vertical_point(vd.m, vd.ob, vd.lam, (int)nl, vd.eta, vd.L, vd.p, vd.q,
+                                      vd.cells, static_cast<vert::zc *>(dG.p), s),
+                "receiver vertical functions") ||
       check_hip(hipMemcpyAsync(dkr.p, kr.data(), kr.size() * sizeof(int), hipMemcpyHostToDevice, s),
                 "upload") ||
       // plain functions 0..5, regularised 6..7

@@ -252,5 +252,139 @@ __host__ __device__ inline void table_row(int i, double lam, const Model &m, con
   }
 }
 
+// A point observer at depth z0 in the earth (receiver kernels), at or above
+// the top of the grid, or below its bottom: the layer holding it, and the
+// gap between it and the grid split at interfaces into pieces (layer, local
+// top, local bottom), empty when z0 is the top of the grid; a6 the
+// large-lambda limit of lambda^2 A2 - 2 for the observer on its own cell's
+// top face.
+struct Observer {
+  double z0;
+  int lay_obs, ngap;
+  bool below;
+  const int *gap_lay;
+  const double *gap_ta, *gap_tb;
+  zc a6;
+};
+
+// The eight lambda functions of every source level jz for a point observer,
+// out[f nz + jz]:
+//   0 lambda A1, 1 lambda A2, 2 lambda dA1, 3 lambda A4 / s, 4 lambda A5 / s,
+//   5 lambda A6 / s, 6 P / lambda, 7 Q / lambda   (s: the observer's layer)
+// with A1 = int U_1, A2 = int U_s, dA1 = d/dz A1, A4 = d/dz A2,
+// A5 = U_s(z, bottom) - U_s(z, top), A3 = d/dz A5 (regular part),
+// A6 = lambda^2 A2 - 2 [observer in the cell], P = -i w mu0 A1 + A3 / s,
+// Q = dA1 + A5.  Above the grid U(z0, z*) = F(z0) G(z*) / (eta D): each
+// cell's functions at the top of the grid are carried up by F(z0) / F(top)
+// (F'(z0) / F(top) for the derivatives), the product of the ratios
+// F(a) / F(b) over the pieces of the gap and the cells above; the cell the
+// observer touches uses the derivative at its own top edge.  Below the grid
+// U(z0, z*) = F(z*) G(z0) / (eta D) in the observer's layer (times
+// sigma_obs / sigma_source for the sigma kind: sigma_s U(z, z*) = sigma_r
+// U(z*, z)), with the ratios F(bottom of the cell) / F(z0) over the cells
+// below and the gap.  eta, L, p, q: from layer_fns; c0, c1: the cells'
+// factors of both kinds.
+__host__ __device__ inline void point_row(double lam, const Model &m, const Observer &ob,
+                                          const zc *eta, const double *L, const zc *p,
+                                          const zc *q, const Cell *c0, const Cell *c1, zc *out) {
+  const int nz = m.nz, nlayers = m.nlay + 1;
+  const Cell *cell[2] = {c0, c1};
+  const zc iwm = Z(0.0, m.omega_mu0);
+  const zc so = m.sigma[ob.lay_obs];
+  if (ob.below) {
+    const int n0 = ob.lay_obs;
+    const double t0 = ob.z0 - m.d[n0 - 1];
+    const bool half = !(L[n0] < kFinite);
+    zc U0[2], U0d[2], Rb[2] = {Z(1.0), Z(1.0)};
+    for (int k = 0; k < 2; ++k) {
+      const zc e = eta[n0], P = p[k * nlayers + n0], Q = q[k * nlayers + n0];
+      const zc fa0 = 1.0 + P * zexp(-2.0 * e * t0);
+      const zc qq = half ? Z(0.0) : Q * zexp(-2.0 * e * (L[n0] - t0));
+      const zc D = half ? Z(1.0) : 1.0 - P * Q * zexp(-2.0 * e * L[n0]);
+      U0[k] = fa0 * (1.0 + qq) / (e * D);
+      U0d[k] = -1.0 * (fa0 * (1.0 - qq) / D);
+      for (int i = 0; i < ob.ngap; ++i) {
+        const int n = ob.gap_lay[i];
+        const zc en = eta[n], Pn = p[k * nlayers + n];
+        const double a = ob.gap_ta[i], b = ob.gap_tb[i];
+        Rb[k] = Rb[k] * (zexp(-en * (b - a)) * (1.0 + Pn * zexp(-2.0 * en * a)) /
+                         (1.0 + Pn * zexp(-2.0 * en * b)));
+      }
+    }
+    for (int jz = nz - 1; jz >= 0; --jz) {
+      const zc ss = so / m.sigma[m.lay[jz]];  // sigma_obs / sigma_source
+      const zc A1 = c0[jz].FI * Rb[0] * U0[0];
+      const zc dA1 = c0[jz].FI * Rb[0] * U0d[0];
+      const zc A2 = ss * c1[jz].FI * Rb[1] * U0[1];
+      const zc A4 = ss * c1[jz].FI * Rb[1] * U0d[1];
+      const zc A5 = ss * c1[jz].FD * Rb[1] * U0[1];
+      const zc A3 = ss * c1[jz].FD * Rb[1] * U0d[1];
+      const zc A6 = lam * lam * A2;
+      out[0 * nz + jz] = lam * A1;
+      out[1 * nz + jz] = lam * A2;
+      out[2 * nz + jz] = lam * dA1;
+      out[3 * nz + jz] = lam * A4 / so;
+      out[4 * nz + jz] = lam * A5 / so;
+      out[5 * nz + jz] = lam * A6 / so;
+      out[6 * nz + jz] = ((-iwm) * A1 + A3 / so) / lam;
+      out[7 * nz + jz] = (dA1 + A5) / lam;
+      for (int k = 0; k < 2; ++k) Rb[k] = Rb[k] * cell[k][jz].theta;
+    }
+    return;
+  }
+  const bool gap = ob.ngap > 0;
+  zc R[2] = {Z(1.0), Z(1.0)}, Rd[2] = {Z(0.0), Z(0.0)};
+  if (gap) {
+    for (int k = 0; k < 2; ++k) {
+      for (int i = 0; i < ob.ngap; ++i) {
+        const int n = ob.gap_lay[i];
+        const zc e = eta[n], P = p[k * nlayers + n];
+        const double a = ob.gap_ta[i], b = ob.gap_tb[i];
+        const zc eh = zexp(-e * (b - a));
+        const zc fa = 1.0 + P * zexp(-2.0 * e * a), fb = 1.0 + P * zexp(-2.0 * e * b);
+        const zc th = eh * fa / fb;
+        if (i == 0) Rd[k] = e * eh * (1.0 - P * zexp(-2.0 * e * a)) / fb;
+        else Rd[k] = Rd[k] * th;
+        R[k] = R[k] * th;
+      }
+    }
+  }
+  for (int jz = 0; jz < nz; ++jz) {
+    zc A1, A2, dA1, A4, A5, A3;
+    if (!gap && jz == 0) {
+      A1 = c0[0].GI;
+      A2 = c1[0].GI;
+      dA1 = c0[0].GId;
+      A4 = c1[0].GId;
+      A5 = c1[0].GD;
+      A3 = c1[0].GDd;
+    } else {
+      A1 = R[0] * c0[jz].GI;
+      A2 = R[1] * c1[jz].GI;
+      dA1 = Rd[0] * c0[jz].GI;
+      A4 = Rd[1] * c1[jz].GI;
+      A5 = R[1] * c1[jz].GD;
+      A3 = Rd[1] * c1[jz].GD;
+    }
+    // the observer's own cell: A6 tends to the constant a6, whose transform
+    // is a delta at the observer; it is taken out here and added exactly to
+    // the own cell's G_zz
+    const zc A6 = lam * lam * A2 - ((jz == 0 && !gap) ? 2.0 + ob.a6 : Z(0.0));
+    out[0 * nz + jz] = lam * A1;
+    out[1 * nz + jz] = lam * A2;
+    out[2 * nz + jz] = lam * dA1;
+    out[3 * nz + jz] = lam * A4 / so;
+    out[4 * nz + jz] = lam * A5 / so;
+    out[5 * nz + jz] = lam * A6 / so;
+    out[6 * nz + jz] = ((-iwm) * A1 + A3 / so) / lam;
+    out[7 * nz + jz] = (dA1 + A5) / lam;
+    // ratios from the observer to the top of the next cell
+    for (int k = 0; k < 2; ++k) {
+      Rd[k] = (jz == 0 && !gap) ? cell[k][0].thetad : Rd[k] * cell[k][jz].theta;
+      R[k] = R[k] * cell[k][jz].theta;
+    }
+  }
+}
+
 }  // namespace vert
 }  // namespace giem
