@@ -270,8 +270,11 @@ int giem_set_fft_shape(giem_handle *t, uint32_t prec, const int32_t *shape);
    share, 1 is used), 4 = the row of the next point written from registers
    into a second local-memory buffer during the current point's matrix
    products (Nz <= 32 and at most 2 right-hand sides in FP64, else 2 is
-   used), 0 for the built-in choice (1).  Results agree to rounding whichever
-   variant runs.  Errors: EINVAL. */
+   used), 0 for the built-in choice (1).  Where a point's packed row and
+   input vectors do not fit the local data share (Nz > 32 at 2 right-hand
+   sides) every variant runs the band-pair kernel, which stages the row by
+   pairs of 16-level bands.  Results agree to rounding whichever variant
+   runs.  Errors: EINVAL. */
 int giem_set_block_buffers(giem_handle *t, uint32_t prec, int32_t nbuf);
 
 /* giem_profile_read -- wait for the last recorded apply and report what was
