@@ -393,9 +393,9 @@ __global__ __launch_bounds__(256) void k_vert_rows(vert::Model m, const double *
 // The nodes: [lambda_lo, z1 / rho] in halving subpanels (lambda_a as a
 // breakpoint), then the panels between consecutive zeros of J0 up to the
 // K-th, then the tail panels weighted by the averaged limit of the last
-// partial sums.  One thread per (rho, lambda panel) sums, in increasing
-// lambda, the nodes that fall into its panel, and writes that panel's 16
-// columns (plain and regularised: J0 - 1 below lambda_a).
+// partial sums.  One wavefront per (rho, lambda panel) sums the nodes that
+// fall into its panel and writes that panel's 16 columns (plain and
+// regularised: J0 - 1 below lambda_a).
 struct HankelArgs {
   const double *zeros, *edges, *node, *bw, *rho, *g1x, *g1w, *g2x, *g2w, *beta;
   int nzeros, npan, nr, ng1, ng2, nt;
@@ -441,10 +441,15 @@ __device__ __forceinline__ void hankel_node(const HankelArgs &a, int p, double r
   }
 }
 
-__global__ __launch_bounds__(128) void k_hankel_weights(HankelArgs a, double *__restrict__ Wt,
+// One wavefront per (rho, lambda panel): its lanes take the subpanels and
+// the zero panels in turn and the wavefront sums their partial columns with
+// a fixed butterfly (the large rho nodes' high panels hold tens of
+// thousands of quadrature nodes, the low ones a few).
+__global__ __launch_bounds__(256) void k_hankel_weights(HankelArgs a, double *__restrict__ Wt,
                                                         double *__restrict__ Wt_reg) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)a.nr * a.npan) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t idx = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (idx >= (int64_t)a.nr * a.npan) return;  // whole wavefront
   const int p = (int)(idx % a.npan), ir = (int)(idx / a.npan);
   const double rho = a.rho[ir];
   // the panel's lambda range, widened (the node filter is exact)
@@ -459,7 +464,7 @@ __global__ __launch_bounds__(128) void k_hankel_weights(HankelArgs a, double *__
     // one holding lambda_a split there
     int M = 0;
     while (ldexp(l1, -M) / 2.0 > a.lam_lo) ++M;
-    for (int m = M; m >= 0; --m) {
+    for (int m = M - lane; m >= 0; m -= 64) {
       const double a0 = m == M ? a.lam_lo : ldexp(l1, -(m + 1)), b0 = ldexp(l1, -m);
       if (b0 < Llo || a0 > Lhi) continue;
       const bool split = a.lam_a > a0 && a.lam_a < b0;
@@ -493,7 +498,7 @@ __global__ __launch_bounds__(128) void k_hankel_weights(HankelArgs a, double *__
     else hi = mid;
   }
   const int kmax = lo - 1;
-  for (int k = kmin; k <= kmax; ++k) {
+  for (int k = kmin + lane; k <= kmax; k += 64) {
     const double za = a.zeros[k - 1] / rho, zb = a.zeros[k] / rho;
     const double scale = k < K ? 1.0 : a.beta[k - K];
     for (int q = 0; q < a.ng2; ++q) {
@@ -503,8 +508,18 @@ __global__ __launch_bounds__(128) void k_hankel_weights(HankelArgs a, double *__
   }
 #pragma unroll
   for (int q = 0; q < kHankelN; ++q) {
-    Wt[(size_t)(p * kHankelN + q) * a.nr + ir] = acc[q];
-    Wt_reg[(size_t)(p * kHankelN + q) * a.nr + ir] = accr[q];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      acc[q] += __shfl_xor(acc[q], off, 64);
+      accr[q] += __shfl_xor(accr[q], off, 64);
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < kHankelN; ++q) {
+      Wt[(size_t)(p * kHankelN + q) * a.nr + ir] = acc[q];
+      Wt_reg[(size_t)(p * kHankelN + q) * a.nr + ir] = accr[q];
+    }
   }
 }
 
@@ -951,9 +966,9 @@ hipError_t launch_hankel_weights(const double *args, int nzeros, int npan, int n
   a.lam_lo = lam_lo;
   a.lam_a = lam_a;
   a.lam_asym = lam_asym;
-  const int64_t n = (int64_t)nr * npan;
+  const int64_t n = (int64_t)nr * npan;  // one wavefront each, four per workgroup
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_hankel_weights, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, s, a, Wt,
+  hipLaunchKernelGGL(k_hankel_weights, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, a, Wt,
                      Wt_reg);
   return hipGetLastError();
 }
