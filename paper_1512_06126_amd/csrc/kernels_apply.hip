@@ -362,12 +362,14 @@ k_fft_x_inv(VecPtrsT<VT> ptrs, const c128 *__restrict__ sdiag, const c128 *__res
 // ---------------------------------------------------------------- y passes
 // Forward (rows y >= Ny are zero, output all 2 Ny rows) or inverse (read all
 // 2 Ny rows, write rows < Ny) FFT along y, in place.  Grid: (Kx, plane group).
-// At most 128 VGPRs (four wavefronts per SIMD): the FP64 pass then fits four
-// 256-thread workgroups of 8 planes, or two of 512 threads and 16 planes,
-// per CU instead of three and one (no spills; 73 -> 69-71 us at 128 x 128 x
-// 32 for the best shape, every result bit unchanged).
+// Power-of-two lengths: at most 128 VGPRs (four wavefronts per SIMD): the
+// FP64 pass then fits four 256-thread workgroups of 8 planes, or two of 512
+// threads and 16 planes, per CU instead of three and one (73 -> 69-71 us at
+// 128 x 128 x 32 for the best shape, every result bit unchanged).  The
+// mixed-radix kernels (lengths with factors 3, 5, 7, 11) keep their
+// registers: capped at 128 they spill hundreds of bytes per lane.
 template <typename T, int EPT, int NT, bool POW2>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(POW2 ? 4 : 1)))
 k_fft_y(cplx<T> *__restrict__ spec, int nx2, int ny, int rp_total, int G, FftDesc fd,
         const cplx<T> *__restrict__ tw, int inverse) {
   extern __shared__ unsigned char smem_raw[];
