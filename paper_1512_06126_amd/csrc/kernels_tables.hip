@@ -3,10 +3,14 @@
 //   (1) the lambda -> rho Hankel contraction  H = W G   (W geometry only),
 //   (2) the rho -> offset spatial contraction B_k = M_k H (M_k geometry only),
 // the kernel that forms the nine tensor components from the contracted
-// blocks and writes the packed storage of Sect. 3.1, and the lambda functions
-// of the vertical integrals (Appendix B), one lambda node per thread for the
-// layer recursions, one cell per thread for the cell factors and one depth
-// level per thread for the rows of the products over the cells between.
+// blocks and writes the packed storage of Sect. 3.1, the lambda functions
+// of the vertical integrals (Appendix B: one lambda node per thread for the
+// layer recursions, one cell per thread for the cell factors, one depth
+// level per thread for the rows of the products over the cells between, one
+// lambda node per thread for a point observer's row), the two geometry-only
+// rule matrices (Hankel weights; spatial fold, and its receiver form), and
+// the receiver-side kernels (fields at receivers, impedance, dipole
+// right-hand sides and the adjoint sums).
 #include "kernels.h"
 #include "vertical.h"
 
