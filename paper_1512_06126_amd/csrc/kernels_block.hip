@@ -137,7 +137,8 @@ __device__ __forceinline__ void band_store(cplx<T> *buf, const cplx<T> (&pre)[NP
 #pragma unroll
   for (int u = 0; u < NPRE; ++u) {
     const int q = tid + NT * u;
-    buf[(q >> 8) * kBandSlot + ((q >> 4) & 15) * kBandLd + (q & 15)] = pre[u];
+    if (NT * NPRE == 2048 || q < 2048)
+      buf[(q >> 8) * kBandSlot + ((q >> 4) & 15) * kBandLd + (q & 15)] = pre[u];
   }
 }
 
@@ -156,7 +157,8 @@ k_block_band(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict__
   const int npts = (nx + 1) * (ny + 1);
   const int f = blockIdx.x / npts, rep = blockIdx.x - f * npts;
   const int rtot = nf * R;
-  constexpr int NT = 64 * NW, NPRE = 2048 / NT;  // threads, staged entries per thread
+  // threads, staged entries per thread (8 slots of 16 x 16)
+  constexpr int NT = 64 * NW, NPRE = (2048 + NT - 1) / NT;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, kk = lane >> 4;
   const int vloc = li & 7, part = li >> 3;
@@ -188,14 +190,16 @@ k_block_band(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict__
     cplx<T> pre[NPRE];
     int I = 0, J = 0, Ip = 0, Jp = 0;  // current pair, last pair requested
 #pragma unroll
-    for (int u = 0; u < NPRE; ++u) pre[u] = band_entry(tq, tid + NT * u, 0, 0, nz, tri);
+    for (int u = 0; u < NPRE; ++u)
+      pre[u] = tid + NT * u < 2048 ? band_entry(tq, tid + NT * u, 0, 0, nz, tri) : mk<T>(0, 0);
     for (int p = 0; p < npairs; ++p) {
       __syncthreads();  // the previous pair's tiles are no longer read
       band_store<T, NT, NPRE>(Ts, pre, tid);
       if (p + 1 < npairs) {
         band_next(Ip, Jp, nb);
 #pragma unroll
-        for (int u = 0; u < NPRE; ++u) pre[u] = band_entry(tq, tid + NT * u, Ip, Jp, nz, tri);
+        for (int u = 0; u < NPRE; ++u)
+          pre[u] = tid + NT * u < 2048 ? band_entry(tq, tid + NT * u, Ip, Jp, nz, tri) : mk<T>(0, 0);
       }
       __syncthreads();
       const cplx<T> *Tc = Ts;
@@ -275,18 +279,14 @@ k_block_band(TabSet tabs, const cplx<T> *__restrict__ sin, cplx<T> *__restrict__
   }
 }
 
-// fragment batch and occupancy target per tile count: four wavefronts per
-// SIMD (two workgroups per CU) where the registers allow
-template <typename T, int MAXT, int NW>
-struct BandCfg {
-  static constexpr int KB = 4;
-  // accumulator registers grow with MAXT and the element size
-  static constexpr int WPE = MAXT * (int)(sizeof(T) / 4) <= 4 ? 4 : 2;
-};
-template <typename T, int MAXT, int NW>
+// The variants launched: (T, output tiles per wavefront, fragment batch,
+// wavefronts per SIMD, wavefronts per workgroup).  FP32: 8 wavefronts of 3
+// tiles up to 8 bands (two workgroups per CU), 16 of 3 beyond; FP64: 16 of 2
+// up to 10 bands (four wavefronts per SIMD), 12 of 3 at 11 (170 VGPRs, three
+// per SIMD)
+template <typename T, int MAXT, int KB, int WPE, int NW>
 static const void *band_kernel() {
-  return reinterpret_cast<const void *>(
-      k_block_band<T, MAXT, BandCfg<T, MAXT, NW>::KB, BandCfg<T, MAXT, NW>::WPE, NW>);
+  return reinterpret_cast<const void *>(k_block_band<T, MAXT, KB, WPE, NW>);
 }
 
 static size_t lds_bytes_band(int nz, size_t csize) {
@@ -1079,8 +1079,8 @@ hipError_t set_block_lds_limits() {
   GIEM_BLOCK_VARIANTS(GIEM_SET_ATTR, double)
   GIEM_BLOCK_VARIANTS(GIEM_SET_ATTR, float)
 #undef GIEM_SET_ATTR
-  const void *band[] = {band_kernel<float, 3, 8>(), band_kernel<float, 6, 8>(),
-                        band_kernel<double, 2, 16>(), band_kernel<double, 3, 16>()};
+  const void *band[] = {band_kernel<float, 3, 4, 4, 8>(), band_kernel<float, 3, 4, 4, 16>(),
+                        band_kernel<double, 2, 4, 4, 16>(), band_kernel<double, 3, 4, 3, 12>()};
   for (const void *k : band)
     if (e == hipSuccess)
       e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
@@ -1148,18 +1148,17 @@ static hipError_t launch_block_t(const TabSet &tabs, int nf, const void *sin, vo
   cplx<T> *so = static_cast<cplx<T> *>(sout);
   if constexpr (sizeof(T) == 4) {
     if (3 * nb <= 24)
-      k_block_band<T, 3, BandCfg<T, 3, 8>::KB, BandCfg<T, 3, 8>::WPE, 8>
-          <<<(unsigned)ntask, 512, lds, s>>>(tabs, si, so, nx, ny, nz, R, nf);
+      k_block_band<T, 3, 4, 4, 8><<<(unsigned)ntask, 512, lds, s>>>(tabs, si, so, nx, ny, nz, R, nf);
     else
-      k_block_band<T, 6, BandCfg<T, 6, 8>::KB, BandCfg<T, 6, 8>::WPE, 8>
-          <<<(unsigned)ntask, 512, lds, s>>>(tabs, si, so, nx, ny, nz, R, nf);
+      k_block_band<T, 3, 4, 4, 16><<<(unsigned)ntask, 1024, lds, s>>>(tabs, si, so, nx, ny, nz, R,
+                                                                      nf);
   } else {
     if (3 * nb <= 32)
-      k_block_band<T, 2, BandCfg<T, 2, 16>::KB, BandCfg<T, 2, 16>::WPE, 16>
-          <<<(unsigned)ntask, 1024, lds, s>>>(tabs, si, so, nx, ny, nz, R, nf);
+      k_block_band<T, 2, 4, 4, 16><<<(unsigned)ntask, 1024, lds, s>>>(tabs, si, so, nx, ny, nz, R,
+                                                                      nf);
     else
-      k_block_band<T, 3, BandCfg<T, 3, 16>::KB, BandCfg<T, 3, 16>::WPE, 16>
-          <<<(unsigned)ntask, 1024, lds, s>>>(tabs, si, so, nx, ny, nz, R, nf);
+      k_block_band<T, 3, 4, 3, 12><<<(unsigned)ntask, 768, lds, s>>>(tabs, si, so, nx, ny, nz, R,
+                                                                    nf);
   }
   return hipGetLastError();
 }
