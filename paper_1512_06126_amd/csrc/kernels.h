@@ -47,13 +47,15 @@ hipError_t launch_block(int prec, const TabSet &tabs, int nf, const void *sin, v
 bool block_two_per_cu(int nz, int R, int prec);
 bool block_dbl_supported(int nz, int R, int prec);
 
-// table set-up (kernels_setup.hip)
 // even/odd transform of the packed table along axis 0 (x) or 1 (y): nbatch
 // lines, element j of line b at in + b sb + j sj, K at out + b ob + K sk
 // (c128 units), n elements per line, transforms of length fd.L = 2 n
+// (kernels_apply.hip, on the FFT passes of the apply)
 hipError_t launch_parity_fft(const c128 *in, int64_t sj, int64_t sb, int nbatch, c128 *out,
                              int64_t sk, int64_t ob, int n, int E, int nz, int axis,
                              const FftDesc &fd, const void *tw, hipStream_t s);
+
+// table set-up (kernels_setup.hip)
 hipError_t launch_to_c64(const c128 *src, c64 *dst, size_t n, hipStream_t s);
 hipError_t launch_diagonals(const c128 *sigma_a, const c128 *sb_lev, const double *vol_lev,
                             int nx, int ny, int nz, c128 *S, c128 *R1, c128 *R2, c128 *a,
@@ -61,6 +63,7 @@ hipError_t launch_diagonals(const c128 *sigma_a, const c128 *sb_lev, const doubl
 hipError_t launch_plane_wave_rhs(const c128 *en_lev, const double *sroot_lev, int nx, int ny,
                                  int nz, int pol, c128 *out, hipStream_t s);
 
+// gradient of the adjoint misfit (kernels_setup.hip)
 hipError_t launch_adjoint_grad(const c128 *sigma_a, const c128 *sb_lev, const c128 *acell,
                                const c128 *g, const c128 *E, const c128 *lam, const c128 *w,
                                int nrhs, int nx, int ny, int nz, double *grad, hipStream_t s);

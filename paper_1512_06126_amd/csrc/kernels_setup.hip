@@ -1,7 +1,8 @@
 // Set-up kernels: the complex64 copy of the spectra of the packed table
 // (the spectra themselves come from the FFT passes, kernels_apply.hip), the
-// diagonals of A = S + R1 B R2 (Sect. 3.1) and the plane-wave right-hand
-// side U^0 = sqrt(Re sb) <E^N> (Sect. 2.2).
+// diagonals of A = S + R1 B R2 (Sect. 3.1), the plane-wave right-hand
+// side U^0 = sqrt(Re sb) <E^N> (Sect. 2.2) and the per-cell gradient of a
+// misfit from the forward and adjoint fields.
 #include "kernels.h"
 
 namespace giem {
