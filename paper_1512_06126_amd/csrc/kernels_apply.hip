@@ -231,8 +231,13 @@ __device__ void fft_lds(cplx<T> *buf, int G, int ld, const FftDesc &fd,
 // ---------------------------------------------------------------- x passes
 // Step 1, x pass: u -> R2 u (or u), zero-pad to 2 Nx, forward FFT along x.
 // Grid: (y, plane group).  Output rows y < Ny of the spectra buffer.
+// Power-of-two lengths: at most 128 VGPRs (four wavefronts per SIMD).  In
+// FP64 that spills 16-28 bytes per lane and the pass is still faster (54 ->
+// 51.5 us at 128 x 128 x 32 with 8 planes on 256 threads); the inverse pass,
+// which holds its epilogue's loads as well, spills up to 168 bytes under the
+// same cap and keeps its registers.
 template <typename T, int EPT, int NT, bool POW2, typename VT>
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(POW2 ? 4 : 1)))
 k_fft_x_fwd(VecPtrsT<VT> ptrs, const c128 *__restrict__ r2, cplx<T> *__restrict__ spec, int nx,
             int ny, int nz, int rp_total, int G, FftDesc fd, const cplx<T> *__restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
