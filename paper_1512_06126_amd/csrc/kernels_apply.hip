@@ -139,18 +139,18 @@ __device__ __forceinline__ void small_dft(cplx<T> (&v)[P], bool inv,
 // (k = j mod ns) and writes y[(j / ns) ns P + k + q ns]; after all passes the
 // sequence is in natural order.  Inputs are staged in registers so the pass
 // works in place.
-// REMAT: the thread index is made opaque to the compiler at every pass, so
-// that the LDS addresses derived from it (the same in every pass of one
-// radix) are recomputed per pass rather than held in registers across the
-// whole transform.  The power-of-two apply passes take it: in FP64 they drop
-// from 128-140 to 88-98 VGPRs with no spill (five wavefronts per SIMD).
-template <typename T, int P, int EPT, bool REMAT = false>
+// The thread index is made opaque to the compiler at every pass, so that the
+// LDS addresses derived from it (the same in every pass of one radix) are
+// recomputed per pass rather than held in registers across the whole
+// transform: in FP64 the power-of-two passes drop from 128-140 to 88-98
+// VGPRs and the mixed-radix ones from 184-235 to 103-144, none spilling.
+template <typename T, int P, int EPT>
 __device__ __forceinline__ void fft_pass(cplx<T> *buf, int G, int ld, int L, int ns,
                                          const cplx<T> *__restrict__ tw, bool inv) {
   constexpr int MB = (EPT + P - 1) / P;
   const int nthr = blockDim.x;
   int tid = threadIdx.x;
-  if constexpr (REMAT) asm volatile("" : "+v"(tid));
+  asm volatile("" : "+v"(tid));
   const int lp = L / P;
   const int nb = G * lp;
   cplx<T> v[MB][P];
@@ -205,7 +205,7 @@ __device__ __forceinline__ void fft_pass(cplx<T> *buf, int G, int ld, int L, int
 // All passes of one transform.  POW2 instantiations (lengths 2^k) carry
 // only the radix 16, 8, 4 and 2 passes: register allocation takes the
 // largest path of the switch, and the odd-radix passes would cost occupancy.
-template <typename T, int EPT, bool POW2, bool REMAT = false>
+template <typename T, int EPT, bool POW2>
 __device__ void fft_lds(cplx<T> *buf, int G, int ld, const FftDesc &fd,
                         const cplx<T> *__restrict__ tw, bool inv) {
   __syncthreads();
@@ -214,21 +214,21 @@ __device__ void fft_lds(cplx<T> *buf, int G, int ld, const FftDesc &fd,
     const int p = fd.fac[s];
     if constexpr (POW2) {
       switch (p) {
-        case 16: fft_pass<T, 16, EPT, REMAT>(buf, G, ld, fd.L, ns, tw, inv); break;
-        case 8: fft_pass<T, 8, EPT, REMAT>(buf, G, ld, fd.L, ns, tw, inv); break;
-        case 4: fft_pass<T, 4, EPT, REMAT>(buf, G, ld, fd.L, ns, tw, inv); break;
-        default: fft_pass<T, 2, EPT, REMAT>(buf, G, ld, fd.L, ns, tw, inv); break;
+        case 16: fft_pass<T, 16, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
+        case 8: fft_pass<T, 8, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
+        case 4: fft_pass<T, 4, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
+        default: fft_pass<T, 2, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
       }
     } else {
       switch (p) {
-        case 16: fft_pass<T, 16, EPT, REMAT>(buf, G, ld, fd.L, ns, tw, inv); break;
-        case 8: fft_pass<T, 8, EPT, REMAT>(buf, G, ld, fd.L, ns, tw, inv); break;
-        case 4: fft_pass<T, 4, EPT, REMAT>(buf, G, ld, fd.L, ns, tw, inv); break;
-        case 2: fft_pass<T, 2, EPT, REMAT>(buf, G, ld, fd.L, ns, tw, inv); break;
-        case 3: fft_pass<T, 3, EPT, REMAT>(buf, G, ld, fd.L, ns, tw, inv); break;
-        case 5: fft_pass<T, 5, EPT, REMAT>(buf, G, ld, fd.L, ns, tw, inv); break;
-        case 7: fft_pass<T, 7, EPT, REMAT>(buf, G, ld, fd.L, ns, tw, inv); break;
-        default: fft_pass<T, 11, EPT, REMAT>(buf, G, ld, fd.L, ns, tw, inv); break;
+        case 16: fft_pass<T, 16, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
+        case 8: fft_pass<T, 8, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
+        case 4: fft_pass<T, 4, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
+        case 2: fft_pass<T, 2, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
+        case 3: fft_pass<T, 3, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
+        case 5: fft_pass<T, 5, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
+        case 7: fft_pass<T, 7, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
+        default: fft_pass<T, 11, EPT>(buf, G, ld, fd.L, ns, tw, inv); break;
       }
     }
     ns *= p;
@@ -238,9 +238,10 @@ __device__ void fft_lds(cplx<T> *buf, int G, int ld, const FftDesc &fd,
 // ---------------------------------------------------------------- x passes
 // Step 1, x pass: u -> R2 u (or u), zero-pad to 2 Nx, forward FFT along x.
 // Grid: (y, plane group).  Output rows y < Ny of the spectra buffer.
-// Power-of-two lengths recompute the transform's LDS addresses per pass
-// (REMAT; 98 VGPRs in FP64, 54 -> 48.5 us at 128 x 128 x 32 with 8 planes on
-// 256 threads; the floor of four wavefronts per SIMD no longer binds).
+// With the transform's LDS addresses recomputed per pass (fft_pass) the
+// FP64 kernel takes 98 VGPRs for power-of-two lengths (54 -> 48.5 us at
+// 128 x 128 x 32 with 8 planes on 256 threads; the floor of four
+// wavefronts per SIMD no longer binds).
 template <typename T, int EPT, int NT, bool POW2, typename VT>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(POW2 ? 4 : 1)))
 k_fft_x_fwd(VecPtrsT<VT> ptrs, const c128 *__restrict__ r2, cplx<T> *__restrict__ spec, int nx,
@@ -283,7 +284,7 @@ k_fft_x_fwd(VecPtrsT<VT> ptrs, const c128 *__restrict__ r2, cplx<T> *__restrict_
       buf[g * ld + lds_pad(xx)] = ccast<T>(cmul(va[u], vs[u]));
     }
   }
-  fft_lds<T, EPT, POW2, POW2>(buf, G, ld, fd, tw, false);
+  fft_lds<T, EPT, POW2>(buf, G, ld, fd, tw, false);
   for (int e = threadIdx.x; e < G * L; e += blockDim.x) {
     const int K = e / G, g = e - K * G;
     const int rp = rp0 + g;
@@ -294,8 +295,8 @@ k_fft_x_fwd(VecPtrsT<VT> ptrs, const c128 *__restrict__ r2, cplx<T> *__restrict_
 // Step 3, x pass: inverse FFT along x, keep x < Nx, scale by 1/(4 Nx Ny) and
 // finish the operator: y = S u + R1 (B R2 u)  (mode A, with R1/R2 swapped for
 // A^T), or y = B u (mode B: s == nullptr, r1 == nullptr).
-// Power-of-two lengths recompute the transform's LDS addresses per pass
-// (REMAT; 96 VGPRs in FP64, 63.7 -> 57.5 us at 128 x 128 x 32).
+// With the transform's LDS addresses recomputed per pass: 96 VGPRs in FP64
+// for power-of-two lengths (63.7 -> 57.5 us at 128 x 128 x 32).
 template <typename T, int EPT, int NT, bool POW2, typename VT>
 __global__ void __launch_bounds__(NT)
 k_fft_x_inv(VecPtrsT<VT> ptrs, const c128 *__restrict__ sdiag, const c128 *__restrict__ r1,
@@ -327,7 +328,7 @@ k_fft_x_inv(VecPtrsT<VT> ptrs, const c128 *__restrict__ sdiag, const c128 *__res
       }
     }
   }
-  fft_lds<T, EPT, POW2, POW2>(buf, G, ld, fd, tw, true);
+  fft_lds<T, EPT, POW2>(buf, G, ld, fd, tw, true);
   // epilogue: the diagonal terms are loaded after the transform, so that
   // they do not hold registers across it; every load of a thread is issued
   // before any of them is used (from a clamped address where an output is
@@ -376,10 +377,9 @@ k_fft_x_inv(VecPtrsT<VT> ptrs, const c128 *__restrict__ sdiag, const c128 *__res
 // 2 Ny rows, write rows < Ny) FFT along y, in place.  Grid: (Kx, plane group).
 // Power-of-two lengths: at least four wavefronts per SIMD (73 -> 69-71 us at
 // 128 x 128 x 32 for the best shape, every result bit unchanged), now met
-// without a cap by recomputing the LDS addresses per pass (REMAT, 88 VGPRs
-// in FP64).  The mixed-radix kernels (lengths with factors 3, 5, 7, 11) hold
-// their addresses and keep their registers: capped at 128 they spill
-// hundreds of bytes per lane.
+// without a cap by recomputing the LDS addresses per pass (88 VGPRs in
+// FP64).  The mixed-radix kernels (lengths with factors 3, 5, 7, 11) carry
+// no floor (103 VGPRs in FP64 at 8 elements per thread).
 template <typename T, int EPT, int NT, bool POW2>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(POW2 ? 4 : 1)))
 k_fft_y(cplx<T> *__restrict__ spec, int nx2, int ny, int rp_total, int G, FftDesc fd,
@@ -410,7 +410,7 @@ k_fft_y(cplx<T> *__restrict__ spec, int nx2, int ny, int rp_total, int G, FftDes
       }
     }
   }
-  fft_lds<T, EPT, POW2, POW2>(buf, G, ld, fd, tw, inverse != 0);
+  fft_lds<T, EPT, POW2>(buf, G, ld, fd, tw, inverse != 0);
   for (int e = threadIdx.x; e < G * nout; e += blockDim.x) {
     const int yy = e / G, g = e - yy * G;
     const int rp = rp0 + g;
